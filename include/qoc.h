@@ -1,0 +1,188 @@
+/*
+ * qoc.h - C ABI of libqoc: cost and exact gradient of piecewise-constant
+ * quantum optimal control on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Leung, Abdelhafez, Koch, Schuster, "Speedup for quantum optimal
+ * control from automatic differentiation based on graphics processing
+ * units", arXiv:1612.04929.
+ *
+ * The problem statement follows the paper's Sec. II and Table I:
+ *   H_j   = H_0 + sum_k u_{k,j} H_k                      (eq. 1)
+ *   U_j   = exp(-i H_j dt)                                (eq. 3), hbar = 1
+ *   psi_{j+1}^s = U_j psi_j^s, j = 0..N-1, s = 0..S-1     (eqs. 2, 4)
+ *   z     = (1/S) sum_s <T_s|psi_N^s>,  C_fid = 1 - |z|^2 (composite state
+ *           infidelity, Sec. II.A; equals the gate infidelity C1 when the
+ *           S = d columns of the identity are propagated)
+ *   c_j   = (1/S) sum_s sum_m w_m |psi_j^s[m]|^2, j = 1..N  (Table I, C5)
+ *   C_amp = sum u^2 (C3),  C_var = sum_k sum_{j>=1} (u_{k,j}-u_{k,j-1})^2 (C4)
+ *   C     = a_fid C_fid + a_pen sum_j c_j + a_amp C_amp + a_var C_var
+ * Each U_j is evaluated by a truncated Taylor series of order p with n
+ * scaling-and-squaring steps, with one global (p, n) (Sec. III, eq. 6),
+ * and the gradient dC/du_{k,j} is the exact derivative of that evaluation
+ * (reverse accumulation through the Taylor and squaring recurrences, in
+ * place of the first-order formula of eq. 7).
+ *
+ * Conventions for every entry point
+ *  - Complex numbers crossing the ABI are interleaved (re, im) doubles.
+ *  - Matrices are row-major d x d; H_k is stored [k][row][col].
+ *  - States are stored state-major: component m of state s at [s*d + m].
+ *  - Controls are stored u[k*N + j] (control k, step j); the gradient uses
+ *    the same layout.
+ *  - The caller owns every pointer it passes.  qoc_create copies all
+ *    problem data, so the caller may free it after the call returns.
+ *    Outputs are caller-allocated.  The handle owns all device memory.
+ *  - Errors are reported by the returned status only; no exception or
+ *    abort crosses the ABI.  On error, outputs are left untouched and
+ *    qoc_last_error() describes the cause (thread-local string).
+ *  - A handle is not thread-safe; distinct handles may be used from
+ *    distinct threads.
+ */
+#ifndef QOC_H
+#define QOC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qoc_handle qoc_handle;
+
+typedef enum {
+  QOC_OK = 0,
+  QOC_ERR_ARG = -1,            /* null pointer or invalid scalar argument   */
+  QOC_ERR_SHAPE = -2,          /* d, M, N, S out of range or inconsistent   */
+  QOC_ERR_NOT_HERMITIAN = -3,  /* H_0 or some H_k fails the Hermitian check */
+  QOC_ERR_NONFINITE = -4,      /* NaN/Inf in an input                       */
+  QOC_ERR_NOMEM = -5,          /* device or host allocation failed          */
+  QOC_ERR_DEVICE = -6,         /* HIP runtime error or no usable device     */
+  QOC_ERR_UNSUPPORTED = -7     /* valid request this build does not handle  */
+} qoc_status;
+
+/* Precision of the matrix-product chains (Taylor, squaring, adjoint). */
+enum { QOC_FP64 = 0, QOC_FP32 = 1, QOC_BF16X3 = 2 };
+
+/* Fidelity mode: coherent |(1/S) sum_s <T_s|psi_N^s>|^2 (phase-sensitive,
+ * equals the gate fidelity on a full basis) or incoherent
+ * (1/S) sum_s |<T_s|psi_N^s>|^2 (mean of the per-state fidelity C2). */
+enum { QOC_FID_COHERENT = 0, QOC_FID_INCOHERENT = 1 };
+
+/* Bits of *flags_out. */
+enum { QOC_WARN_DRIFT = 1 };
+
+typedef struct {
+  int d;                    /* Hilbert-space dimension, 1 <= d <= 4096     */
+  int M;                    /* number of control Hamiltonians, 0 <= M <= 64 */
+  int N;                    /* number of time steps, N >= 1                 */
+  int S;                    /* propagated columns, 1 <= S <= d              */
+  double dt;                /* step length (> 0), same time unit as 1/H     */
+  const double *H0;         /* d*d complex, Hermitian                       */
+  const double *Hk;         /* M*d*d complex, each Hermitian (NULL if M=0)  */
+  const double *psi0;       /* S*d complex initial states                   */
+  const double *psiT;       /* S*d complex target states (zero outside the
+                               target subspace: the projector P_S of the
+                               composite infidelity is implicit)            */
+  const double *penalty_w;  /* d real weights >= 0 of forbidden levels, or
+                               NULL (no per-step penalty)                   */
+  double alpha_fid, alpha_amp, alpha_var, alpha_pen;   /* cost weights      */
+  int fid_mode;             /* QOC_FID_COHERENT or QOC_FID_INCOHERENT       */
+  int precision;            /* QOC_FP32 (default), QOC_FP64 or QOC_BF16X3   */
+  int checkpoint_every;     /* state checkpoint interval L of the blocked
+                               sweeps; 0 = power of two nearest sqrt(N);
+                               otherwise rounded up to a power of two       */
+  double taylor_tol;        /* truncation tolerance tau of the (p, n) rule;
+                               0 = 1e-10 (FP32, BF16X3) or 1e-15 (FP64)     */
+  int taylor_p, taylor_n;   /* both >= 1 (p >= 2): fixed global (p, n) and
+                               no per-call host synchronisation; otherwise
+                               (p, n) is chosen per call from theta_max     */
+  double drift_warn;        /* threshold of QOC_WARN_DRIFT; 0 = 1e-4        */
+  int device;               /* HIP device ordinal                           */
+} qoc_problem_desc;
+
+/* Diagnostics of the most recent forward / cost_grad call on a handle. */
+typedef struct {
+  int p, n;                 /* Taylor order and squaring count used          */
+  double theta_max;         /* max_j ||dt H_j||_1, evaluated in FP64         */
+  double norm_drift;        /* max_{j,s} | ||psi_{j+1}^s||^2 - ||psi_j^s||^2 |
+                               (FP64), the unitarity drift seen by the
+                               propagated columns                           */
+  int block_len;            /* checkpoint interval L actually used           */
+  int n_blocks;             /* ceil(N / L)                                   */
+  int d_pad;                /* device padding of d (multiple of 16)          */
+  size_t device_bytes;      /* device memory held by the handle              */
+} qoc_info;
+
+/* Create a handle: validates and copies the problem to device memory.
+ * Checks: shapes; S <= d; finite inputs; dt > 0; Hermiticity of H_0 and
+ * every H_k with ||H - H^dagger||_max <= 1e-12 * max(1, ||H||_max);
+ * penalty weights >= 0.  Paper: Sec. II (problem statement), Table I. */
+qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out);
+
+/* Forward pass only (Sec. II, eqs. 1-4; Table I).  u: M*N host doubles.
+ * Outputs (host, each may be NULL): *cost_fid = C_fid; step_penalty[j-1] =
+ * c_j for j = 1..N; psiN: S*d complex final states; *flags_out: warning
+ * bits.  Blocks until the results are on the host. */
+qoc_status qoc_forward(qoc_handle *h, const double *u, double *cost_fid,
+                       double *step_penalty, double *psiN, int *flags_out);
+
+/* Cost and exact gradient (Sec. II.B reverse accumulation; Table I costs).
+ * u, grad: M*N host doubles (grad may be NULL only if M == 0).
+ * *cost = C (weighted total), *cost_fid = C_fid, step_penalty[j-1] = c_j
+ * (or NULL), *flags_out warning bits (or NULL).  Blocks until done. */
+qoc_status qoc_cost_grad(qoc_handle *h, const double *u, double *cost,
+                         double *cost_fid, double *step_penalty, double *grad,
+                         int *flags_out);
+
+/* Device-resident variant of qoc_cost_grad for callers that keep u and the
+ * outputs in HBM (e.g. a torch.autograd.Function).  u_dev: M*N doubles on
+ * the handle's device; out_dev: 2 + N doubles written as
+ * [C, C_fid, c_1, ..., c_N]; grad_dev: M*N doubles.  Work is enqueued on
+ * `stream` (a hipStream_t; NULL = the default stream).  When (p, n) is not
+ * fixed in the descriptor the call synchronises `stream` once to read
+ * theta_max back; with a fixed (p, n) it is fully asynchronous. */
+qoc_status qoc_cost_grad_device(qoc_handle *h, const double *u_dev,
+                                double *out_dev, double *grad_dev, void *stream);
+
+/* Batched variant: B independent handles (uneven d, N, M allowed), each
+ * with its own device u / out / grad pointers as in qoc_cost_grad_device,
+ * enqueued on one stream. */
+qoc_status qoc_cost_grad_batched(int B, qoc_handle *const *hs,
+                                 const double *const *u_dev,
+                                 double *const *out_dev,
+                                 double *const *grad_dev, void *stream);
+
+/* Diagnostics of the last call (see qoc_info). */
+qoc_status qoc_get_info(const qoc_handle *h, qoc_info *info);
+
+/* Per-phase device timing for measurement: when enabled, each phase of a
+ * call is bracketed with HIP events on the stream it runs on.
+ * qoc_profile_read returns, per phase, the summed event time in
+ * milliseconds and the number of calls timed (arrays of QOC_PHASE_COUNT),
+ * synchronising outstanding events; reset != 0 clears the counters. */
+enum {
+  QOC_PHASE_NORM = 0,       /* FP64 step norms and theta_max               */
+  QOC_PHASE_EXPM = 1,       /* Taylor + squaring chains, all steps          */
+  QOC_PHASE_BLOCKPROD = 2,  /* block products of the two-level sweep        */
+  QOC_PHASE_FORWARD = 3,    /* forward sweeps, penalties, fidelity           */
+  QOC_PHASE_BACKWARD = 4,   /* costate sweeps                               */
+  QOC_PHASE_ADJOINT = 5,    /* per-step exact derivative + gradient          */
+  QOC_PHASE_COUNT = 6
+};
+qoc_status qoc_profile_enable(qoc_handle *h, int on);
+qoc_status qoc_profile_read(qoc_handle *h, double *ms, long long *calls,
+                            int reset);
+
+/* The (p, n) rule on the host: fewest products G = p-1+n with
+ * 2^n (theta/2^n)^(p+1)/(p+1)! e^(theta/2^n) <= tol, ties to smaller n,
+ * p >= 2 (Sec. III: global conservative truncation and scaling). */
+qoc_status qoc_taylor_select(double theta, double tol, int *p, int *n);
+
+void qoc_destroy(qoc_handle *h);
+const char *qoc_status_string(qoc_status s);
+const char *qoc_last_error(void);
+const char *qoc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QOC_H */
