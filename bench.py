@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Throughput of one cost + exact-gradient evaluation (the whole hot path)
+on one MI355X, in time-steps per second, on a seeded synthetic workload.
+
+A "step" of this benchmark is one qoc_cost_grad_device call over the whole
+control array: norms and (p, n), all N step exponentials, block products,
+forward sweeps with penalties and fidelity, costate sweeps, and the exact
+per-step derivative contracted into dC/du.  Inputs are resident in HBM
+before the timed region.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--config c2|c3|c4|c1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cost+grad time-steps/sec vs plain FP64 GPU path at |ΔF|≤1e-6, d=16–512"
+PEAK = {"fp32": {"mfma": 157.3e12, "alu": 157.3e12 / 2}, "fp64": {"mfma": 78.6e12, "alu": 78.6e12}}
+HBM_PEAK = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_work(prob, info, phase, calls, precision):
+    """(bound, algorithmic units per launch) for one timed kernel phase.
+
+    Complex d x d x d product = 8 d^3 real flops; streaming one step
+    propagator D_j = 8 d^2 bytes (FP32 planar).  True d, not the padding.
+    """
+    d, N, M, S = prob.d, prob.N, prob.M, prob.S
+    p, n, L = info["p"], info["n"], info["block_len"]
+    esz = 8 if precision == "fp64" else 4
+    if phase == "taylor":
+        return "mfma", N * 8.0 * d ** 3
+    if phase == "blockprod":
+        total = (N - info["n_blocks"]) * 8.0 * d ** 3
+        return "mfma", total / max(calls, 1)
+    if phase in ("fwd_replay", "bwd_pairs"):
+        return "hbm", N * 2.0 * d * d * esz
+    if phase in ("fwd_blocks", "bwd_blocks"):
+        return "hbm", info["n_blocks"] * 2.0 * d * d * esz
+    if phase == "adjoint":
+        f, r = 0.0, S
+        for _ in range(n):
+            f += 2 * 8.0 * d * d * min(r, d)
+            r = min(2 * r, d)
+        f += 2 * (p - 1) * 8.0 * d * d * r + 8.0 * d * d * p * r + 8.0 * d * d * M
+        return "mfma", N * f
+    if phase == "norm":
+        return "alu", N * d * d * (M + 1) * 4.0
+    if phase == "assemble":
+        return "hbm", N * 2.0 * d * d * esz * 2
+    return "hbm", 0.0
+
+
+def fp64_torch_path(prob, dev, reps=2):
+    """Plain FP64 GPU path: complex128 torch, batched matrix_exp, a
+    sequential product loop and autograd (exact Frechet derivatives)."""
+    import numpy as np
+    import torch
+    c128 = torch.complex128
+    H0 = torch.tensor(prob.H0, dtype=c128, device=dev)
+    Hk = torch.tensor(prob.Hk, dtype=c128, device=dev)
+    psi0 = torch.tensor(prob.psi0.T.copy(), dtype=c128, device=dev)      # d x S
+    psiT = torch.tensor(prob.psiT.T.copy(), dtype=c128, device=dev)
+    w = torch.tensor(prob.w if prob.w is not None else np.zeros(prob.d), dtype=torch.float64,
+                     device=dev)
+    S = prob.S
+
+    def run(u_np):
+        u = torch.tensor(u_np, dtype=torch.float64, device=dev, requires_grad=True)
+        H = H0 + torch.tensordot(u.to(c128).t().contiguous(), Hk, dims=1)
+        U = torch.linalg.matrix_exp((-1j * prob.dt) * H)
+        psi = psi0
+        pen = torch.zeros((), dtype=torch.float64, device=dev)
+        for j in range(prob.N):
+            psi = U[j] @ psi
+            if prob.w is not None:
+                pen = pen + (w[:, None] * (psi.real ** 2 + psi.imag ** 2)).sum() / S
+        ov = (psiT.conj() * psi).sum(dim=0)
+        F = (ov.sum() / S).abs() ** 2 if prob.fid_mode == "coherent" else (ov.abs() ** 2).sum() / S
+        C = prob.alpha_fid * (1 - F) + prob.alpha_pen * pen + prob.alpha_amp * (u ** 2).sum()
+        if prob.N > 1:
+            C = C + prob.alpha_var * ((u[:, 1:] - u[:, :-1]) ** 2).sum()
+        C.backward()
+        return float(C.detach()), float(F.detach()), u.grad.detach().cpu().numpy()
+
+    run(prob.u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        C, F, g = run(prob.u)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return dict(value=prob.N / dt, unit="time-steps/s", ms_per_step=dt * 1e3, reps=reps,
+                F=F, grad=g)
+
+
+def cpu_baseline(prob, seconds):
+    """The FP64 oracle as it stands, on the host cores, on a bounded sample."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    # size the sample so that one call takes a few seconds at most
+    probe = prob.with_steps(min(prob.N, 50))
+    t0 = time.perf_counter()
+    oracle.cost_grad(probe)
+    per_step = (time.perf_counter() - t0) / probe.N
+    n_sample = int(max(1, min(prob.N, (seconds / 3.0) / max(per_step, 1e-9))))
+    sample = prob.with_steps(n_sample)
+    runs, steps, t0 = 0, 0, time.perf_counter()
+    ref = None
+    while True:
+        ref = oracle.cost_grad(sample)
+        runs += 1
+        steps += sample.N
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=steps / el, unit="time-steps/s", cores=int(cores), kind="oracle",
+                sample=f"{runs} x oracle.cost_grad on the first {n_sample} of {prob.N} steps "
+                       f"of {prob.name} ({el:.1f} s)"), (sample, ref)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-torch-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the time-sharded design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1612_04929_amd import qoc
+
+    dev = torch.device("cuda:0")
+    prob = workloads.make_config(args.config)
+    log(f"[bench] {prob.name}: d={prob.d} M={prob.M} N={prob.N} S={prob.S} "
+        f"precision={args.precision}")
+    h = qoc.Problem(prob, precision=args.precision, device=0)
+    u = torch.from_numpy(np.ascontiguousarray(prob.u)).to(dev)
+    out = torch.zeros(2 + prob.N, dtype=torch.float64, device=dev)
+    grad = torch.zeros(max(1, prob.M * prob.N), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def step():
+        h.cost_grad_device(u.data_ptr(), out.data_ptr(), grad.data_ptr(), stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.profile_enable(True)
+    h.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = h.profile_read(reset=True)
+    h.profile_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = prob.N / (ms / 1e3)
+    info = h.info()
+    C_gpu = float(out[0].item())
+    Cfid_gpu = float(out[1].item())
+    g_gpu = grad[: prob.M * prob.N].cpu().numpy().reshape(prob.M, prob.N)
+    log(f"[bench] {args.steps} steps: {ms:.3f} ms/step, {value:.4g} time-steps/s, info={info}")
+
+    kernels = {}
+    for ph, (tms, calls) in prof.items():
+        if calls:
+            kernels[ph] = dict(total_ms=tms / args.steps, launches=calls // args.steps,
+                               avg_launch_ms=tms / calls)
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    bound, units = algorithmic_work(prob, info, dom, kernels[dom]["launches"] * args.steps,
+                                    args.precision)
+    avg_s = kernels[dom]["avg_launch_ms"] / 1e3
+    if bound == "hbm":
+        achieved, peak, unit = units / avg_s / 1e9, HBM_PEAK / 1e9, "GB/s"
+    else:
+        achieved, peak, unit = units / avg_s / 1e12, PEAK[args.precision][bound] / 1e12, "TFLOP/s"
+    roofline = dict(kernel=dom, bound=bound, achieved=achieved, peak=peak, unit=unit,
+                    frac=achieved / peak, traffic=None)
+    for k, v in kernels.items():
+        b, un = algorithmic_work(prob, info, k, v["launches"] * args.steps, args.precision)
+        s = v["avg_launch_ms"] / 1e3
+        v["bound"] = b
+        if b == "hbm":
+            v["achieved_GBps"] = un / s / 1e9 if s > 0 else None
+        else:
+            v["achieved_TFLOPs"] = un / s / 1e12 if s > 0 else None
+
+    res = dict(metric=METRIC, value=value, unit="time-steps/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype=args.precision, data="synthetic (seeded generators)",
+               config=dict(workload=prob.name, d=prob.d, M=prob.M, N=prob.N, S=prob.S,
+                           dt=prob.dt, precision=args.precision, taylor_p=info["p"],
+                           taylor_n=info["n"], checkpoint_every=info["block_len"]),
+               roofline=roofline)
+    if not args.no_cpu_baseline:
+        cb, (sample, ref) = cpu_baseline(prob, args.cpu_seconds)
+        res["cpu_baseline"] = cb
+        if sample.N == prob.N:
+            gref = ref["grad"]
+            res["accuracy_vs_oracle"] = dict(
+                dF=abs((1 - Cfid_gpu) - ref["F"]), dC=abs(C_gpu - ref["C"]),
+                grad_rel=float(np.linalg.norm(g_gpu - gref) / np.linalg.norm(gref)))
+    if not args.no_torch_baseline:
+        tb = fp64_torch_path(prob, dev)
+        g64 = tb.pop("grad")
+        tb["dF_vs_this"] = abs(tb.pop("F") - (1 - Cfid_gpu))
+        tb["grad_rel_vs_this"] = float(np.linalg.norm(g64 - g_gpu) / np.linalg.norm(g64))
+        res["fp64_gpu_path"] = tb
+        res["speedup_vs_fp64_gpu_path"] = value / tb["value"]
+    res["kernels"] = kernels
+    res["diagnostics"] = dict(theta_max=info["theta_max"], norm_drift=info["norm_drift"],
+                              n_blocks=info["n_blocks"], d_pad=info["d_pad"],
+                              device_bytes=info["device_bytes"])
+    h.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

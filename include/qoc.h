@@ -71,7 +71,7 @@ enum { QOC_FID_COHERENT = 0, QOC_FID_INCOHERENT = 1 };
 enum { QOC_WARN_DRIFT = 1 };
 
 typedef struct {
-  int d;                    /* Hilbert-space dimension, 1 <= d <= 4096     */
+  int d;                    /* Hilbert-space dimension, 1 <= d <= 1024     */
   int M;                    /* number of control Hamiltonians, 0 <= M <= 64 */
   int N;                    /* number of time steps, N >= 1                 */
   int S;                    /* propagated columns, 1 <= S <= d              */
@@ -92,9 +92,10 @@ typedef struct {
                                otherwise rounded up to a power of two       */
   double taylor_tol;        /* truncation tolerance tau of the (p, n) rule;
                                0 = 1e-10 (FP32, BF16X3) or 1e-15 (FP64)     */
-  int taylor_p, taylor_n;   /* both >= 1 (p >= 2): fixed global (p, n) and
-                               no per-call host synchronisation; otherwise
-                               (p, n) is chosen per call from theta_max     */
+  int taylor_p, taylor_n;   /* taylor_p >= 2 and taylor_n >= 0: fixed global
+                               (p, n), no per-call host synchronisation;
+                               taylor_p == 0: (p, n) chosen per call from
+                               theta_max; anything else is QOC_ERR_ARG      */
   double drift_warn;        /* threshold of QOC_WARN_DRIFT; 0 = 1e-4        */
   int device;               /* HIP device ordinal                           */
 } qoc_problem_desc;
@@ -154,19 +155,26 @@ qoc_status qoc_cost_grad_batched(int B, qoc_handle *const *hs,
 /* Diagnostics of the last call (see qoc_info). */
 qoc_status qoc_get_info(const qoc_handle *h, qoc_info *info);
 
-/* Per-phase device timing for measurement: when enabled, each phase of a
- * call is bracketed with HIP events on the stream it runs on.
- * qoc_profile_read returns, per phase, the summed event time in
- * milliseconds and the number of calls timed (arrays of QOC_PHASE_COUNT),
- * synchronising outstanding events; reset != 0 clears the counters. */
+/* Per-kernel device timing for measurement: when enabled, every kernel
+ * launch of a call is bracketed with HIP events on the stream it runs on
+ * (the events are resolved lazily, so enabling this adds no host
+ * synchronisation).  qoc_profile_read synchronises the outstanding events
+ * and returns, per phase, the summed event time in milliseconds and the
+ * number of launches timed (arrays of QOC_PHASE_COUNT); reset != 0 clears
+ * the counters. */
 enum {
-  QOC_PHASE_NORM = 0,       /* FP64 step norms and theta_max               */
-  QOC_PHASE_EXPM = 1,       /* Taylor + squaring chains, all steps          */
-  QOC_PHASE_BLOCKPROD = 2,  /* block products of the two-level sweep        */
-  QOC_PHASE_FORWARD = 3,    /* forward sweeps, penalties, fidelity           */
-  QOC_PHASE_BACKWARD = 4,   /* costate sweeps                               */
-  QOC_PHASE_ADJOINT = 5,    /* per-step exact derivative + gradient          */
-  QOC_PHASE_COUNT = 6
+  QOC_PHASE_NORM = 0,        /* FP64 step norms, theta_max                   */
+  QOC_PHASE_ASSEMBLE = 1,    /* X_j = -i dt/2^n H_j and the first Horner term */
+  QOC_PHASE_TAYLOR = 2,      /* one batched complex product of the Taylor /
+                                squaring chain over all N steps (per launch) */
+  QOC_PHASE_BLOCKPROD = 3,   /* one level of the block-product tree          */
+  QOC_PHASE_FWD_BLOCKS = 4,  /* sequential checkpoint sweep over blocks      */
+  QOC_PHASE_FWD_REPLAY = 5,  /* in-block replay, penalties, block costates   */
+  QOC_PHASE_COST = 6,        /* FP64 fidelity overlap and cost terms         */
+  QOC_PHASE_BWD_BLOCKS = 7,  /* sequential costate sweep over blocks         */
+  QOC_PHASE_BWD_PAIRS = 8,   /* in-block costates lambda_{j+1}               */
+  QOC_PHASE_ADJOINT = 9,     /* per-step exact derivative + gradient         */
+  QOC_PHASE_COUNT = 10
 };
 qoc_status qoc_profile_enable(qoc_handle *h, int on);
 qoc_status qoc_profile_read(qoc_handle *h, double *ms, long long *calls,

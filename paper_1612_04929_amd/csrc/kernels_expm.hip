@@ -1,0 +1,183 @@
+// Step exponentials by truncated Taylor series with scaling and squaring
+// (Sec. III, eq. 6), all N steps independent, in the "D-form":
+//   X   = -i (dt / 2^n) H_j
+//   Q_p = I + X/p,  Q_k = I + (1/k) X Q_{k+1}   (k = p-1 .. 2)   Horner
+//   D^(0) = X Q_2 = T_p(X) - I
+//   D^(i+1) = 2 D^(i) + D^(i) D^(i)            ((I + D)^2 = I + 2D + D^2)
+//   U_j = I + D^(n)
+// Keeping D = U - I instead of U avoids the systematic FP32 truncation of
+// adding a small update to the identity at every step.
+#include "qoc_device.h"
+#include "qoc_kernels.h"
+
+namespace qoc {
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_assemble(const T *__restrict__ Hf,
+                                                  const double *__restrict__ u, int dp, int M,
+                                                  int N, T s, T inv_p, T *__restrict__ X,
+                                                  T *__restrict__ Q) {
+  const long plane = (long)dp * dp;
+  const long total = (long)N * plane;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const long j = e / plane, rc = e - j * plane;
+    T hr = Hf[rc], hi = Hf[plane + rc];
+    for (int k = 0; k < M; ++k) {
+      const T c = (T)u[(long)k * N + j];
+      hr += c * Hf[(long)(k + 1) * 2 * plane + rc];
+      hi += c * Hf[(long)(k + 1) * 2 * plane + plane + rc];
+    }
+    // -i s (hr + i hi) = s hi - i s hr
+    const T xr = s * hi, xi = -s * hr;
+    T *Xj = X + j * 2 * plane;
+    Xj[rc] = xr;
+    Xj[plane + rc] = xi;
+    if (Q) {
+      const int r = (int)(rc / dp), c = (int)(rc - (long)r * dp);
+      T *Qj = Q + j * 2 * plane;
+      Qj[rc] = (r == c ? (T)1 : (T)0) + xr * inv_p;
+      Qj[plane + rc] = xi * inv_p;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_store(const StageArgs<T> &a, long j, int row, int col,
+                                            T accr, T acci) {
+  const long plane = (long)a.dp * a.dp;
+  const long o = (long)row * a.dp + col;
+  T vr = a.alpha * accr, vi = a.alpha * acci;
+  if (a.betaA != (T)0) {
+    const T *Aj = a.A + j * a.strideA;
+    vr += a.betaA * Aj[o];
+    vi += a.betaA * Aj[plane + o];
+  }
+  if (a.betaB != (T)0) {
+    const T *Bj = a.B + j * a.strideB;
+    vr += a.betaB * Bj[o];
+    vi += a.betaB * Bj[plane + o];
+  }
+  if (row == col) vr += a.gamma;
+  T *Cj = a.C + j * a.strideC;
+  Cj[o] = vr;
+  Cj[plane + o] = vi;
+}
+
+// dp a multiple of 16: one wavefront per 16x16 output tile, operands read
+// straight from L1/L2 (small matrices: the whole matrix is a few tiles).
+template <typename T, int OPA>
+__global__ __launch_bounds__(256) void k_stage16(StageArgs<T> a) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t1 = a.dp >> 4;
+  const long tiles = (long)t1 * t1;
+  const long gt = (long)blockIdx.x * 4 + w;
+  if (gt >= (long)a.nmat * tiles) return;  // wave-uniform, no barriers below
+  const long j = gt / tiles;
+  const int t = (int)(gt - j * tiles);
+  const int r0 = (t / t1) * 16, c0 = (t % t1) * 16;
+  const long plane = (long)a.dp * a.dp;
+  CView<const T> A = cview<const T>(a.A + j * a.strideA, plane, a.dp);
+  CView<const T> B = cview<const T>(a.B + j * a.strideB, plane, a.dp);
+  v4<T> cr = vzero<T>(), ci = vzero<T>();
+  wave_cgemm16<T, OPA, 0>(A, B, r0, c0, a.dp, cr, ci);
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    stage_store(a, j, r0 + 4 * (lane >> 4) + v, c0 + (lane & 15), cr[v], ci[v]);
+}
+
+// dp a multiple of 64: one workgroup per 64x64 output tile, LDS-staged,
+// XCD-aware block order (all tiles of one step on one XCD's L2).
+template <typename T, int OPA>
+__global__ __launch_bounds__(256) void k_stage64(StageArgs<T> a, long padded) {
+  __shared__ T lds[T64_LDS_ELEMS];
+  const int t1 = a.dp >> 6;
+  const long tiles = (long)t1 * t1;
+  const long logical = xcd_logical_block(blockIdx.x, padded);
+  if (logical >= (long)a.nmat * tiles) return;  // block-uniform
+  const long j = logical / tiles;
+  const int t = (int)(logical - j * tiles);
+  const int r0 = (t / t1) * 64, c0 = (t % t1) * 64;
+  const long plane = (long)a.dp * a.dp;
+  CView<const T> A = cview<const T>(a.A + j * a.strideA, plane, a.dp);
+  CView<const T> B = cview<const T>(a.B + j * a.strideB, plane, a.dp);
+  v4<T> acc[2][2][2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      acc[m][n][0] = vzero<T>();
+      acc[m][n][1] = vzero<T>();
+    }
+  wg_cgemm64<T, OPA>(A, B, r0, c0, a.dp, lds, acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        stage_store(a, j, r0 + wr + 16 * m + 4 * (lane >> 4) + v, c0 + wc + 16 * n + (lane & 15),
+                    acc[m][n][0][v], acc[m][n][1][v]);
+}
+
+template <typename T>
+hipError_t launch_assemble(const T *Hf, const double *u, int dp, int M, int N, T s, T inv_p,
+                           T *X, T *Q, hipStream_t st) {
+  const long total = (long)N * dp * dp;
+  long blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_assemble<T>, dim3((unsigned)blocks), dim3(256), 0, st, Hf, u, dp, M, N, s,
+                     inv_p, X, Q);
+  return hipGetLastError();
+}
+
+template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hipStream_t st) {
+  if (a.nmat <= 0) return hipSuccess;
+  if (a.dp % 64 == 0) {
+    const long t1 = a.dp / 64;
+    const long total = (long)a.nmat * t1 * t1;
+    const long padded = (total + 7) / 8 * 8;
+    if (opa)
+      hipLaunchKernelGGL((k_stage64<T, 1>), dim3((unsigned)padded), dim3(256), 0, st, a, padded);
+    else
+      hipLaunchKernelGGL((k_stage64<T, 0>), dim3((unsigned)padded), dim3(256), 0, st, a, padded);
+  } else {
+    const long t1 = a.dp / 16;
+    const long total = (long)a.nmat * t1 * t1;
+    const long blocks = (total + 3) / 4;
+    if (opa)
+      hipLaunchKernelGGL((k_stage16<T, 1>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_stage16<T, 0>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T> __global__ void k_fill(T *p, long n, T v) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T> hipError_t launch_fill(T *p, long n, T v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  long blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+template hipError_t launch_assemble<float>(const float *, const double *, int, int, int, float,
+                                           float, float *, float *, hipStream_t);
+template hipError_t launch_assemble<double>(const double *, const double *, int, int, int, double,
+                                            double, double *, double *, hipStream_t);
+template hipError_t launch_stage<float>(int, const StageArgs<float> &, hipStream_t);
+template hipError_t launch_stage<double>(int, const StageArgs<double> &, hipStream_t);
+template hipError_t launch_fill<float>(float *, long, float, hipStream_t);
+template hipError_t launch_fill<double>(double *, long, double, hipStream_t);
+template hipError_t launch_fill<unsigned long long>(unsigned long long *, long, unsigned long long,
+                                                    hipStream_t);
+
+}  // namespace qoc

@@ -1,0 +1,396 @@
+// Forward and costate sweeps as a blocked two-level scan.
+//
+// The product of propagators (Sec. II, eqs. 2-4) is inherently sequential
+// over time steps.  Instead of N dependent matrix-vector steps on one
+// compute unit, the steps are cut into nb blocks of L (a power of two near
+// sqrt(N)):
+//   F2  sequential over blocks: psi_{(b+1)L} = (I + E_b) psi_{bL} with the
+//       block product E_b = U_{bL+L-1} ... U_{bL} - I (state checkpoints);
+//   F3  parallel over blocks and columns: replay psi_j inside each block
+//       from its checkpoint, per-step penalties c_j (Table I, C5), and the
+//       block-local penalty costate mu_b;
+//   cost: fidelity overlap in FP64 and the final costate lambda_N;
+//   B2  sequential over blocks: lambda_{bL} = (I + E_b)^H lambda_{(b+1)L} + mu_b;
+//   B3  parallel over blocks and columns: lambda_{j+1} for every step, the
+//       cotangent partner of psi_j for the per-step derivative.
+// Columns (states) propagate independently, so every sweep runs one
+// workgroup per column (F2, B2) or per (block, column) (F3, B3).
+// All updates are in D-form: y = x + D x.
+#include "qoc_device.h"
+#include "qoc_kernels.h"
+
+namespace qoc {
+
+// y = x + D x, D row-major planar (dp x dp) in global memory, x and y in
+// LDS.  One wavefront per output row, lanes along the row (coalesced).
+template <typename T>
+__device__ __forceinline__ void mv_plus(const T *__restrict__ Dr, const T *__restrict__ Di,
+                                        int dp, const T *xr, const T *xi, T *yr, T *yi) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int m = w; m < dp; m += nw) {
+    T sr = 0, si = 0;
+    for (int k = lane; k < dp; k += 64) {
+      const T dr = Dr[(long)m * dp + k], di = Di[(long)m * dp + k];
+      sr += dr * xr[k] - di * xi[k];
+      si += dr * xi[k] + di * xr[k];
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) {
+      yr[m] = xr[m] + sr;
+      yi[m] = xi[m] + si;
+    }
+  }
+}
+
+// y = x + D^H x (+ add), one thread per output row, coalesced along D's rows.
+template <typename T>
+__device__ __forceinline__ void mv_plus_adj(const T *__restrict__ Dr, const T *__restrict__ Di,
+                                            int dp, const T *xr, const T *xi, T *yr, T *yi,
+                                            const T *addr, const T *addi) {
+  for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+    T sr = 0, si = 0;
+    for (int k = 0; k < dp; ++k) {
+      const T dr = Dr[(long)k * dp + m], di = -Di[(long)k * dp + m];
+      sr += dr * xr[k] - di * xi[k];
+      si += dr * xi[k] + di * xr[k];
+    }
+    T vr = xr[m] + sr, vi = xi[m] + si;
+    if (addr) {
+      vr += addr[m];
+      vi += addi[m];
+    }
+    yr[m] = vr;
+    yi[m] = vi;
+  }
+}
+
+// Block-wide FP64 sum (256 threads).
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  return s;
+}
+
+template <typename T> __device__ __forceinline__ const T *set_re(const T *base, int S, int dp, int s) {
+  return base + (long)s * dp;
+}
+template <typename T> __device__ __forceinline__ const T *set_im(const T *base, int S, int dp, int s) {
+  return base + (long)S * dp + (long)s * dp;
+}
+template <typename T> __device__ __forceinline__ T *set_rew(T *base, int S, int dp, int s) {
+  return base + (long)s * dp;
+}
+template <typename T> __device__ __forceinline__ T *set_imw(T *base, int S, int dp, int s) {
+  return base + (long)S * dp + (long)s * dp;
+}
+
+// ------------------------------------------------------------------ F2
+template <typename T> __global__ __launch_bounds__(256) void k_fwd_blocks(SweepArgs<T> a) {
+  extern __shared__ unsigned char shraw[];
+  T *buf = (T *)shraw;
+  const int dp = a.dp, S = a.S, s = blockIdx.x;
+  const long set = 2L * S * dp, mat = 2L * dp * dp;
+  T *xr = buf, *xi = buf + dp, *yr = buf + 2 * dp, *yi = buf + 3 * dp;
+  for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+    xr[m] = set_re(a.psi0, S, dp, s)[m];
+    xi[m] = set_im(a.psi0, S, dp, s)[m];
+    set_rew(a.ckpt, S, dp, s)[m] = xr[m];
+    set_imw(a.ckpt, S, dp, s)[m] = xi[m];
+  }
+  __syncthreads();
+  for (int b = 0; b < a.nb; ++b) {
+    const T *E = a.E + (long)b * mat;
+    mv_plus(E, E + (long)dp * dp, dp, xr, xi, yr, yi);
+    __syncthreads();
+    T *c = a.ckpt + (long)(b + 1) * set;
+    for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+      set_rew(c, S, dp, s)[m] = yr[m];
+      set_imw(c, S, dp, s)[m] = yi[m];
+    }
+    T *tr = xr, *ti = xi;
+    xr = yr; xi = yi; yr = tr; yi = ti;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ F3
+template <typename T> __global__ __launch_bounds__(256) void k_fwd_replay(SweepArgs<T> a) {
+  extern __shared__ unsigned char shraw[];
+  T *buf = (T *)shraw;
+  __shared__ double red[4];
+  const int dp = a.dp, S = a.S;
+  const int b = blockIdx.x / S, s = blockIdx.x - (blockIdx.x / S) * S;
+  const long set = 2L * S * dp, mat = 2L * dp * dp;
+  const int start = b * a.L, end = min(a.N, start + a.L);
+  T *xr = buf, *xi = buf + dp, *yr = buf + 2 * dp, *yi = buf + 3 * dp;
+  const T *c = a.ckpt + (long)b * set;
+  double pen = 0.0, nrm = 0.0;
+  for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+    const T vr = set_re(c, S, dp, s)[m], vi = set_im(c, S, dp, s)[m];
+    xr[m] = vr; xi[m] = vi;
+    set_rew(a.psi_buf + (long)start * set, S, dp, s)[m] = vr;
+    set_imw(a.psi_buf + (long)start * set, S, dp, s)[m] = vi;
+    const double q = (double)vr * vr + (double)vi * vi;
+    nrm += q;
+    if (a.w64) pen += a.w64[m] * q;
+  }
+  nrm = block_sum(nrm, red);
+  if (a.w64) {
+    pen = block_sum(pen, red);
+    if (start >= 1 && threadIdx.x == 0) a.c_part[(long)start * S + s] = pen;
+  }
+  double drift = 0.0;
+  __syncthreads();
+  for (int j = start; j < end; ++j) {
+    const T *D = a.D + (long)j * mat;
+    mv_plus(D, D + (long)dp * dp, dp, xr, xi, yr, yi);
+    __syncthreads();
+    const bool store = (j + 1 < end) || (j + 1 == a.N);
+    double p2 = 0.0, n2 = 0.0;
+    for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+      const T vr = yr[m], vi = yi[m];
+      if (store) {
+        set_rew(a.psi_buf + (long)(j + 1) * set, S, dp, s)[m] = vr;
+        set_imw(a.psi_buf + (long)(j + 1) * set, S, dp, s)[m] = vi;
+      }
+      const double q = (double)vr * vr + (double)vi * vi;
+      n2 += q;
+      if (a.w64) p2 += a.w64[m] * q;
+    }
+    n2 = block_sum(n2, red);
+    if (a.w64) {
+      p2 = block_sum(p2, red);
+      if (store && threadIdx.x == 0) a.c_part[(long)(j + 1) * S + s] = p2;
+    }
+    drift = fmax(drift, fabs(n2 - nrm));
+    nrm = n2;
+    T *tr = xr, *ti = xi;
+    xr = yr; xi = yi; yr = tr; yi = ti;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    atomicMax(a.drift_bits, (unsigned long long)__double_as_longlong(drift));
+  if (!a.pw) return;  // block-uniform
+  // block-local penalty costate from zero at the block end:
+  // mu <- mu + D_j^H mu + pw o psi_j   (penalty only for j >= 1)
+  T *mr = xr, *mi = xi, *nr = yr, *ni = yi;
+  T *pr = buf + 4 * dp, *pi = buf + 5 * dp;
+  for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+    mr[m] = 0;
+    mi[m] = 0;
+  }
+  __syncthreads();
+  for (int j = end - 1; j >= start; --j) {
+    const T *ps = a.psi_buf + (long)j * set;
+    for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+      const T wgt = (j >= 1) ? a.pw[m] : (T)0;
+      pr[m] = wgt * set_re(ps, S, dp, s)[m];
+      pi[m] = wgt * set_im(ps, S, dp, s)[m];
+    }
+    __syncthreads();
+    const T *D = a.D + (long)j * mat;
+    mv_plus_adj(D, D + (long)dp * dp, dp, mr, mi, nr, ni, pr, pi);
+    __syncthreads();
+    T *tr = mr, *ti = mi;
+    mr = nr; mi = ni; nr = tr; ni = ti;
+  }
+  T *mu = a.mu + (long)b * set;
+  for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+    set_rew(mu, S, dp, s)[m] = mr[m];
+    set_imw(mu, S, dp, s)[m] = mi[m];
+  }
+}
+
+// ------------------------------------------------------------------ cost
+// FP64: overlaps, fidelity, per-step penalties, regularisers, total cost,
+// and the final costate lambda_N (rounded to the chain precision).
+template <typename T> __global__ __launch_bounds__(256) void k_cost(SweepArgs<T> a) {
+  __shared__ double red[4];
+  const int dp = a.dp, d = a.d, S = a.S, N = a.N, M = a.M;
+  const long set = 2L * S * dp;
+  const T *psiN = a.psi_buf + (long)N * set;
+  double zr = 0.0, zi = 0.0, Finc = 0.0;
+  for (int s = 0; s < S; ++s) {
+    double pr = 0.0, pi = 0.0;
+    for (int m = threadIdx.x; m < d; m += blockDim.x) {
+      const double tr = a.psiT64[((long)s * d + m) * 2], ti = a.psiT64[((long)s * d + m) * 2 + 1];
+      const double xr = (double)set_re(psiN, S, dp, s)[m], xi = (double)set_im(psiN, S, dp, s)[m];
+      pr += tr * xr + ti * xi;  // conj(T) psi
+      pi += tr * xi - ti * xr;
+    }
+    pr = block_sum(pr, red);
+    pi = block_sum(pi, red);
+    zr += pr;
+    zi += pi;
+    Finc += pr * pr + pi * pi;
+    if (threadIdx.x == 0) {
+      a.zinfo[3 + 2 * s] = pr;
+      a.zinfo[4 + 2 * s] = pi;
+    }
+  }
+  zr /= S;
+  zi /= S;
+  const double F = (a.fid_mode == 0) ? (zr * zr + zi * zi) : Finc / S;
+  double cpen = 0.0;
+  for (int j = 1 + threadIdx.x; j <= N; j += blockDim.x) {
+    double cj = 0.0;
+    if (a.w64)
+      for (int s = 0; s < S; ++s) cj += a.c_part[(long)j * S + s];
+    cj /= S;
+    a.out[2 + j - 1] = cj;
+    cpen += cj;
+  }
+  cpen = block_sum(cpen, red);
+  double camp = 0.0, cvar = 0.0;
+  for (long e = threadIdx.x; e < (long)M * N; e += blockDim.x) {
+    const double x = a.u[e];
+    camp += x * x;
+    const long j = e % N;
+    if (j >= 1) {
+      const double dx = x - a.u[e - 1];
+      cvar += dx * dx;
+    }
+  }
+  camp = block_sum(camp, red);
+  cvar = block_sum(cvar, red);
+  const double Cfid = 1.0 - F;
+  if (threadIdx.x == 0) {
+    a.out[0] = a.alpha_fid * Cfid + a.alpha_pen * cpen + a.alpha_amp * camp + a.alpha_var * cvar;
+    a.out[1] = Cfid;
+    a.zinfo[0] = zr;
+    a.zinfo[1] = zi;
+    a.zinfo[2] = F;
+  }
+  __syncthreads();
+  // lambda_N^s = -a_fid coef_s T_s + pw o psi_N^s, coef = z/S or o_s/S
+  T *lamN = a.lam_ckpt + (long)a.nb * set;
+  for (int s = 0; s < S; ++s) {
+    double cr, ci;
+    if (a.fid_mode == 0) {
+      cr = zr / S;
+      ci = zi / S;
+    } else {
+      cr = a.zinfo[3 + 2 * s] / S;
+      ci = a.zinfo[4 + 2 * s] / S;
+    }
+    for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+      double tr = 0.0, ti = 0.0;
+      if (m < d) {
+        tr = a.psiT64[((long)s * d + m) * 2];
+        ti = a.psiT64[((long)s * d + m) * 2 + 1];
+      }
+      double lr = -a.alpha_fid * (cr * tr - ci * ti);
+      double li = -a.alpha_fid * (cr * ti + ci * tr);
+      if (a.pw) {
+        lr += (double)a.pw[m] * (double)set_re(psiN, S, dp, s)[m];
+        li += (double)a.pw[m] * (double)set_im(psiN, S, dp, s)[m];
+      }
+      set_rew(lamN, S, dp, s)[m] = (T)lr;
+      set_imw(lamN, S, dp, s)[m] = (T)li;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ B2
+template <typename T> __global__ __launch_bounds__(256) void k_bwd_blocks(SweepArgs<T> a) {
+  extern __shared__ unsigned char shraw[];
+  T *buf = (T *)shraw;
+  const int dp = a.dp, S = a.S, s = blockIdx.x;
+  const long set = 2L * S * dp, mat = 2L * dp * dp;
+  T *xr = buf, *xi = buf + dp, *yr = buf + 2 * dp, *yi = buf + 3 * dp;
+  const T *lN = a.lam_ckpt + (long)a.nb * set;
+  for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+    xr[m] = set_re(lN, S, dp, s)[m];
+    xi[m] = set_im(lN, S, dp, s)[m];
+  }
+  __syncthreads();
+  for (int b = a.nb - 1; b >= 1; --b) {
+    const T *E = a.E + (long)b * mat;
+    const T *mur = a.mu ? set_re(a.mu + (long)b * set, S, dp, s) : nullptr;
+    const T *mui = a.mu ? set_im(a.mu + (long)b * set, S, dp, s) : nullptr;
+    mv_plus_adj(E, E + (long)dp * dp, dp, xr, xi, yr, yi, mur, mui);
+    __syncthreads();
+    T *c = a.lam_ckpt + (long)b * set;
+    for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+      set_rew(c, S, dp, s)[m] = yr[m];
+      set_imw(c, S, dp, s)[m] = yi[m];
+    }
+    T *tr = xr, *ti = xi;
+    xr = yr; xi = yi; yr = tr; yi = ti;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ B3
+template <typename T> __global__ __launch_bounds__(256) void k_bwd_pairs(SweepArgs<T> a) {
+  extern __shared__ unsigned char shraw[];
+  T *buf = (T *)shraw;
+  const int dp = a.dp, S = a.S;
+  const int b = blockIdx.x / S, s = blockIdx.x - (blockIdx.x / S) * S;
+  const long set = 2L * S * dp, mat = 2L * dp * dp;
+  const int start = b * a.L, end = min(a.N, start + a.L);
+  T *xr = buf, *xi = buf + dp, *yr = buf + 2 * dp, *yi = buf + 3 * dp;
+  T *pr = buf + 4 * dp, *pi = buf + 5 * dp;
+  const T *c = a.lam_ckpt + (long)(b + 1) * set;
+  for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+    xr[m] = set_re(c, S, dp, s)[m];
+    xi[m] = set_im(c, S, dp, s)[m];
+  }
+  __syncthreads();
+  for (int j = end - 1; j >= start; --j) {
+    T *lb = a.lam_buf + (long)j * set;
+    const T *ps = a.psi_buf + (long)j * set;
+    for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+      set_rew(lb, S, dp, s)[m] = xr[m];
+      set_imw(lb, S, dp, s)[m] = xi[m];
+      const T wgt = (a.pw && j >= 1) ? a.pw[m] : (T)0;
+      pr[m] = wgt * set_re(ps, S, dp, s)[m];
+      pi[m] = wgt * set_im(ps, S, dp, s)[m];
+    }
+    if (j == start) break;  // lambda_start belongs to the previous block
+    __syncthreads();
+    const T *D = a.D + (long)j * mat;
+    mv_plus_adj(D, D + (long)dp * dp, dp, xr, xi, yr, yi, pr, pi);
+    __syncthreads();
+    T *tr = xr, *ti = xi;
+    xr = yr; xi = yi; yr = tr; yi = ti;
+  }
+}
+
+template <typename T> hipError_t launch_fwd_blocks(const SweepArgs<T> &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_fwd_blocks<T>, dim3(a.S), dim3(256), 4 * a.dp * sizeof(T), st, a);
+  return hipGetLastError();
+}
+template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_fwd_replay<T>, dim3(a.nb * a.S), dim3(256), 6 * a.dp * sizeof(T), st, a);
+  return hipGetLastError();
+}
+template <typename T> hipError_t launch_cost(const SweepArgs<T> &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_cost<T>, dim3(1), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+template <typename T> hipError_t launch_bwd_blocks(const SweepArgs<T> &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_bwd_blocks<T>, dim3(a.S), dim3(256), 4 * a.dp * sizeof(T), st, a);
+  return hipGetLastError();
+}
+template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_bwd_pairs<T>, dim3(a.nb * a.S), dim3(256), 6 * a.dp * sizeof(T), st, a);
+  return hipGetLastError();
+}
+
+#define QOC_INST(T)                                                                   \
+  template hipError_t launch_fwd_blocks<T>(const SweepArgs<T> &, hipStream_t);       \
+  template hipError_t launch_fwd_replay<T>(const SweepArgs<T> &, hipStream_t);       \
+  template hipError_t launch_cost<T>(const SweepArgs<T> &, hipStream_t);             \
+  template hipError_t launch_bwd_blocks<T>(const SweepArgs<T> &, hipStream_t);       \
+  template hipError_t launch_bwd_pairs<T>(const SweepArgs<T> &, hipStream_t);
+QOC_INST(float)
+QOC_INST(double)
+#undef QOC_INST
+
+}  // namespace qoc

@@ -1,0 +1,779 @@
+// libqoc host side: C ABI, validation, device memory and the launch plan of
+// one cost (+ gradient) evaluation.  See include/qoc.h for the contract.
+#include "../../include/qoc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qoc_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+qoc_status fail(qoc_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess)                                                          \
+      return fail(QOC_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// (p, n) reading of the paper's "conservative global choice" (Sec. III):
+// fewest products p-1+n such that the Taylor remainder bound, amplified by
+// the 2^n squarings, is at most tol.
+double taylor_bound(double theta, int p, int n) {
+  const double x = std::ldexp(theta, -n);
+  double f = 1.0;
+  for (int k = 2; k <= p + 1; ++k) f *= k;
+  return std::ldexp(1.0, n) * std::pow(x, p + 1) / f * std::exp(x);
+}
+
+bool taylor_select(double theta, double tol, int *p_out, int *n_out) {
+  int bestG = -1, bp = 0, bn = 0;
+  for (int n = 0; n < 60; ++n) {
+    for (int p = 2; p <= 30; ++p) {
+      if (taylor_bound(theta, p, n) <= tol) {
+        const int G = p - 1 + n;
+        if (bestG < 0 || G < bestG) {
+          bestG = G;
+          bp = p;
+          bn = n;
+        }
+        break;
+      }
+    }
+  }
+  if (bestG < 0) return false;
+  *p_out = bp;
+  *n_out = bn;
+  return true;
+}
+
+int pow2_at_least(long v) {
+  int l = 1;
+  while (l < v) l <<= 1;
+  return l;
+}
+
+}  // namespace
+
+struct qoc_handle {
+  // problem
+  int d = 0, dp = 0, M = 0, N = 0, S = 0, prec = QOC_FP32, fid_mode = 0;
+  double dt = 0, a_fid = 0, a_amp = 0, a_var = 0, a_pen = 0, tol = 0, drift_warn = 0;
+  bool has_pen = false;
+  int fixed_p = 0, fixed_n = 0;
+  int L = 1, nb = 1, device = 0;
+  size_t esize = 4;  // sizeof(T) of the chain precision
+  hipStream_t stream = nullptr;
+  // device buffers (chain precision T unless noted)
+  void *Hf = nullptr;         // (M+1) x 2 dp^2
+  double *H64 = nullptr;      // (M+1) x d^2 complex interleaved
+  double *u_dev = nullptr;    // M x N
+  double *out_dev = nullptr;  // 2 + N
+  double *grad_dev = nullptr; // M x N
+  void *psi0 = nullptr;       // state set [2][S][dp]
+  double *psiT64 = nullptr;   // S x d complex interleaved
+  double *w64 = nullptr;      // dp
+  void *pw = nullptr;         // dp, a_pen / S * w
+  void *X = nullptr, *Qa = nullptr, *Qb = nullptr;  // N x 2 dp^2 each
+  void *Dlev = nullptr;       // levels x N x 2 dp^2
+  int levels_alloc = 0;
+  void *ckpt = nullptr, *lam_ckpt = nullptr, *mu = nullptr;  // (nb+1) sets
+  void *psi_buf = nullptr, *lam_buf = nullptr;                // N+1, N sets
+  double *c_part = nullptr;   // (N+1) x S
+  unsigned long long *bits = nullptr;  // [theta, drift]
+  double *zinfo = nullptr;    // 3 + 2S
+  void *adj = nullptr;
+  long adj_elems_alloc = 0;   // total elements
+  int adj_blocks = 0;
+  // pinned host staging
+  double *h_u = nullptr, *h_out = nullptr, *h_grad = nullptr;
+  size_t bytes = 0;
+  // diagnostics
+  int last_p = 0, last_n = 0;
+  double last_theta = 0, last_drift = 0;
+  // profiling
+  bool prof = false;
+  double prof_ms[QOC_PHASE_COUNT] = {0};
+  long long prof_calls[QOC_PHASE_COUNT] = {0};
+  struct Pending {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = 0;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+  }
+  ~DeviceGuard() {
+    if (ok) (void)hipSetDevice(prev);
+  }
+};
+
+qoc_status dalloc(qoc_handle *h, void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(QOC_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                   hipGetErrorString(e));
+  }
+  h->bytes += bytes;
+  return QOC_OK;
+}
+
+void dfree(qoc_handle *h, void **p, size_t bytes) {
+  if (*p) {
+    (void)hipFree(*p);
+    h->bytes -= std::min(h->bytes, bytes);
+  }
+  *p = nullptr;
+}
+
+void release(qoc_handle *h) {
+  void **ptrs[] = {&h->Hf, (void **)&h->H64, (void **)&h->u_dev, (void **)&h->out_dev,
+                   (void **)&h->grad_dev, &h->psi0, (void **)&h->psiT64, (void **)&h->w64,
+                   &h->pw, &h->X, &h->Qa, &h->Qb, &h->Dlev, &h->ckpt, &h->lam_ckpt, &h->mu,
+                   &h->psi_buf, &h->lam_buf, (void **)&h->c_part, (void **)&h->bits,
+                   (void **)&h->zinfo, &h->adj};
+  for (void **p : ptrs)
+    if (*p) {
+      (void)hipFree(*p);
+      *p = nullptr;
+    }
+  if (h->h_u) (void)hipHostFree(h->h_u);
+  if (h->h_out) (void)hipHostFree(h->h_out);
+  if (h->h_grad) (void)hipHostFree(h->h_grad);
+  h->h_u = h->h_out = h->h_grad = nullptr;
+  for (auto &pe : h->pending) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  h->pending.clear();
+  for (auto e : h->event_pool) (void)hipEventDestroy(e);
+  h->event_pool.clear();
+  if (h->stream) (void)hipStreamDestroy(h->stream);
+  h->stream = nullptr;
+  h->bytes = 0;
+}
+
+bool all_finite(const double *p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// ||H - H^dagger||_max <= 1e-12 max(1, ||H||_max), H d x d interleaved
+bool hermitian(const double *H, int d) {
+  double mx = 0.0, dev = 0.0;
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c < d; ++c) {
+      const double ar = H[2 * ((size_t)r * d + c)], ai = H[2 * ((size_t)r * d + c) + 1];
+      const double br = H[2 * ((size_t)c * d + r)], bi = -H[2 * ((size_t)c * d + r) + 1];
+      mx = std::max(mx, std::hypot(ar, ai));
+      dev = std::max(dev, std::hypot(ar - br, ai - bi));
+    }
+  return dev <= 1e-12 * std::max(1.0, mx);
+}
+
+// ------------------------------------------------------------------ timing
+hipEvent_t pool_event(qoc_handle *h) {
+  if (!h->event_pool.empty()) {
+    hipEvent_t e = h->event_pool.back();
+    h->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct PhaseTimer {
+  qoc_handle *h;
+  int phase;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  PhaseTimer(qoc_handle *h_, int ph, hipStream_t s) : h(h_), phase(ph), st(s) {
+    if (h->prof) {
+      a = pool_event(h);
+      if (a) (void)hipEventRecord(a, st);
+    }
+  }
+  void done() {
+    if (h->prof && a) {
+      hipEvent_t b = pool_event(h);
+      if (b) {
+        (void)hipEventRecord(b, st);
+        h->pending.push_back({phase, a, b});
+      }
+      a = nullptr;
+    }
+  }
+  ~PhaseTimer() { done(); }
+};
+
+qoc_status drain_pending(qoc_handle *h) {
+  for (auto &pe : h->pending) {
+    HIP_TRY(hipEventSynchronize(pe.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, pe.a, pe.b));
+    h->prof_ms[pe.phase] += ms;
+    h->prof_calls[pe.phase] += 1;
+    h->event_pool.push_back(pe.a);
+    h->event_pool.push_back(pe.b);
+  }
+  h->pending.clear();
+  return QOC_OK;
+}
+
+// ------------------------------------------------------------------ buffers
+template <typename T> qoc_status ensure_levels(qoc_handle *h, int levels) {
+  if (levels <= h->levels_alloc) return QOC_OK;
+  const size_t mat = 2 * (size_t)h->dp * h->dp;
+  dfree(h, &h->Dlev, (size_t)h->levels_alloc * h->N * mat * sizeof(T));
+  h->levels_alloc = 0;
+  qoc_status s = dalloc(h, &h->Dlev, (size_t)levels * h->N * mat * sizeof(T));
+  if (s) return s;
+  h->levels_alloc = levels;
+  return QOC_OK;
+}
+
+template <typename T> qoc_status ensure_adjoint(qoc_handle *h, int p, int Rcap) {
+  const long per = qoc::adjoint_scratch_elems<T>(h->dp, p, Rcap);
+  const long total = per * (long)h->adj_blocks;
+  if (total <= h->adj_elems_alloc) return QOC_OK;
+  dfree(h, &h->adj, (size_t)h->adj_elems_alloc * sizeof(T));
+  h->adj_elems_alloc = 0;
+  qoc_status s = dalloc(h, &h->adj, (size_t)total * sizeof(T));
+  if (s) return s;
+  h->adj_elems_alloc = total;
+  return QOC_OK;
+}
+
+template <typename T>
+qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
+  const int d = h->d, dp = h->dp, M = h->M, N = h->N, S = h->S;
+  const size_t mat = 2 * (size_t)dp * dp, set = 2 * (size_t)S * dp;
+  qoc_status s;
+#define ALLOC(ptr, bytes)                                        \
+  if ((s = dalloc(h, (void **)&(ptr), (bytes))) != QOC_OK) return s;
+  ALLOC(h->Hf, (M + 1) * mat * sizeof(T));
+  ALLOC(h->H64, (size_t)(M + 1) * d * d * 2 * sizeof(double));
+  ALLOC(h->u_dev, (size_t)std::max(1, M * N) * sizeof(double));
+  ALLOC(h->out_dev, (size_t)(2 + N) * sizeof(double));
+  ALLOC(h->grad_dev, (size_t)std::max(1, M * N) * sizeof(double));
+  ALLOC(h->psi0, set * sizeof(T));
+  ALLOC(h->psiT64, (size_t)S * d * 2 * sizeof(double));
+  if (h->has_pen) {
+    ALLOC(h->w64, (size_t)dp * sizeof(double));
+    ALLOC(h->pw, (size_t)dp * sizeof(T));
+  }
+  ALLOC(h->X, (size_t)N * mat * sizeof(T));
+  ALLOC(h->Qa, (size_t)N * mat * sizeof(T));
+  ALLOC(h->Qb, (size_t)N * mat * sizeof(T));
+  ALLOC(h->ckpt, (size_t)(h->nb + 1) * set * sizeof(T));
+  ALLOC(h->lam_ckpt, (size_t)(h->nb + 1) * set * sizeof(T));
+  if (h->has_pen) ALLOC(h->mu, (size_t)h->nb * set * sizeof(T));
+  ALLOC(h->psi_buf, (size_t)(N + 1) * set * sizeof(T));
+  ALLOC(h->lam_buf, (size_t)N * set * sizeof(T));
+  ALLOC(h->c_part, (size_t)(N + 1) * S * sizeof(double));
+  ALLOC(h->bits, 2 * sizeof(unsigned long long));
+  ALLOC(h->zinfo, (size_t)(3 + 2 * S) * sizeof(double));
+#undef ALLOC
+  if (hipHostMalloc((void **)&h->h_u, (size_t)std::max(1, M * N) * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void **)&h->h_out, (size_t)(2 + N + 2 * S * d) * sizeof(double)) !=
+          hipSuccess ||
+      hipHostMalloc((void **)&h->h_grad, (size_t)std::max(1, M * N) * sizeof(double)) !=
+          hipSuccess)
+    return fail(QOC_ERR_NOMEM, "pinned host staging allocation failed");
+
+  // upload problem data (padded planar copies in the chain precision)
+  std::vector<T> hf((M + 1) * mat, (T)0);
+  for (int k = 0; k <= M; ++k) {
+    const double *src = (k == 0) ? desc->H0 : desc->Hk + (size_t)(k - 1) * d * d * 2;
+    T *re = hf.data() + k * mat, *im = re + (size_t)dp * dp;
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < d; ++c) {
+        re[(size_t)r * dp + c] = (T)src[2 * ((size_t)r * d + c)];
+        im[(size_t)r * dp + c] = (T)src[2 * ((size_t)r * d + c) + 1];
+      }
+  }
+  HIP_TRY(hipMemcpy(h->Hf, hf.data(), hf.size() * sizeof(T), hipMemcpyHostToDevice));
+  std::vector<double> h64((size_t)(M + 1) * d * d * 2);
+  std::memcpy(h64.data(), desc->H0, (size_t)d * d * 2 * sizeof(double));
+  if (M) std::memcpy(h64.data() + (size_t)d * d * 2, desc->Hk, (size_t)M * d * d * 2 * sizeof(double));
+  HIP_TRY(hipMemcpy(h->H64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice));
+  std::vector<T> ps(set, (T)0);
+  for (int s2 = 0; s2 < S; ++s2)
+    for (int m = 0; m < d; ++m) {
+      ps[(size_t)s2 * dp + m] = (T)desc->psi0[2 * ((size_t)s2 * d + m)];
+      ps[(size_t)S * dp + (size_t)s2 * dp + m] = (T)desc->psi0[2 * ((size_t)s2 * d + m) + 1];
+    }
+  HIP_TRY(hipMemcpy(h->psi0, ps.data(), set * sizeof(T), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->psiT64, desc->psiT, (size_t)S * d * 2 * sizeof(double),
+                    hipMemcpyHostToDevice));
+  if (h->has_pen) {
+    std::vector<double> w(dp, 0.0);
+    std::vector<T> pw(dp, (T)0);
+    for (int m = 0; m < d; ++m) {
+      w[m] = desc->penalty_w[m];
+      pw[m] = (T)(h->a_pen / S * desc->penalty_w[m]);
+    }
+    HIP_TRY(hipMemcpy(h->w64, w.data(), dp * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->pw, pw.data(), dp * sizeof(T), hipMemcpyHostToDevice));
+  }
+  return QOC_OK;
+}
+
+// ------------------------------------------------------------------ pipeline
+template <typename T>
+qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad_dev,
+               hipStream_t st, bool want_grad) {
+  const int dp = h->dp, N = h->N, M = h->M, S = h->S;
+  const long mat = 2L * dp * dp;
+  int p, n;
+  // ---- (p, n): fixed, or from theta_max (FP64 norms on the device)
+  {
+    HIP_TRY(qoc::launch_fill<unsigned long long>(h->bits, 2, 0ull, st));
+    PhaseTimer tm(h, QOC_PHASE_NORM, st);
+    HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, st));
+    tm.done();
+    if (h->fixed_p >= 2) {
+      p = h->fixed_p;
+      n = h->fixed_n;
+    } else {
+      unsigned long long tb = 0;
+      HIP_TRY(hipMemcpyAsync(&tb, h->bits, sizeof(tb), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      double theta;
+      std::memcpy(&theta, &tb, sizeof(theta));
+      h->last_theta = theta;
+      if (!std::isfinite(theta)) return fail(QOC_ERR_NONFINITE, "non-finite step norm");
+      if (!taylor_select(theta, h->tol, &p, &n))
+        return fail(QOC_ERR_UNSUPPORTED, "no (p, n) meets the tolerance for theta_max = " +
+                                             std::to_string(theta));
+    }
+  }
+  const int Rraw = (long)S << std::min(n, 30) > dp ? dp : (S << n);
+  const int Rcap = (Rraw + 15) & ~15;
+  qoc_status s = ensure_levels<T>(h, n + 1);
+  if (s) return s;
+  if (want_grad && (s = ensure_adjoint<T>(h, p, std::min(Rcap, dp))) != QOC_OK) return s;
+  h->last_p = p;
+  h->last_n = n;
+  T *X = (T *)h->X, *Qa = (T *)h->Qa, *Qb = (T *)h->Qb, *Dl = (T *)h->Dlev;
+  const long lev = (long)N * mat;
+  // ---- step exponentials: Horner in D-form, then squarings
+  {
+    const double sc = std::ldexp(h->dt, -n);
+    {
+      PhaseTimer tm(h, QOC_PHASE_ASSEMBLE, st);
+      HIP_TRY(qoc::launch_assemble<T>((const T *)h->Hf, u_dev, dp, M, N, (T)sc, (T)(1.0 / p), X,
+                                      Qa, st));
+    }
+    T *cur = Qa, *nxt = Qb;
+    for (int k = p - 1; k >= 2; --k) {
+      qoc::StageArgs<T> a{X, mat, cur, mat, nxt, mat, N, dp, (T)(1.0 / k), (T)0, (T)0, (T)1};
+      PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
+      HIP_TRY(qoc::launch_stage<T>(0, a, st));
+      std::swap(cur, nxt);
+    }
+    {
+      qoc::StageArgs<T> a{X, mat, cur, mat, Dl, mat, N, dp, (T)1, (T)0, (T)0, (T)0};
+      PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
+      HIP_TRY(qoc::launch_stage<T>(0, a, st));
+    }
+    for (int i = 0; i < n; ++i) {
+      qoc::StageArgs<T> a{Dl + i * lev, mat, Dl + i * lev, mat, Dl + (i + 1) * lev, mat, N, dp,
+                          (T)1, (T)0, (T)2, (T)0};
+      PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
+      HIP_TRY(qoc::launch_stage<T>(0, a, st));
+    }
+  }
+  const T *D = Dl + (long)n * lev;
+  // ---- block products E_b (pairwise tree, D-form: C = A + B + A B)
+  const T *E = D;
+  {
+    long cnt = N;
+    const T *in = D;
+    T *outb = Qa;
+    for (int span = 2; span <= h->L; span <<= 1) {
+      const long pairs = cnt / 2;
+      qoc::StageArgs<T> a{in + mat, 2 * mat, in, 2 * mat, outb, mat, (int)pairs, dp,
+                          (T)1, (T)1, (T)1, (T)0};
+      PhaseTimer tm(h, QOC_PHASE_BLOCKPROD, st);
+      HIP_TRY(qoc::launch_stage<T>(0, a, st));
+      tm.done();
+      if (cnt & 1)
+        HIP_TRY(hipMemcpyAsync(outb + pairs * mat, in + (cnt - 1) * mat, mat * sizeof(T),
+                               hipMemcpyDeviceToDevice, st));
+      cnt = (cnt + 1) / 2;
+      in = outb;
+      outb = (outb == Qa) ? Qb : Qa;
+    }
+    E = in;
+  }
+  qoc::SweepArgs<T> sw{};
+  sw.N = N; sw.L = h->L; sw.nb = h->nb; sw.dp = dp; sw.d = h->d; sw.S = S; sw.M = M;
+  sw.D = D; sw.E = E; sw.psi0 = (const T *)h->psi0; sw.ckpt = (T *)h->ckpt;
+  sw.psi_buf = (T *)h->psi_buf; sw.lam_ckpt = (T *)h->lam_ckpt; sw.mu = (T *)h->mu;
+  sw.lam_buf = (T *)h->lam_buf; sw.w64 = h->w64; sw.pw = (const T *)h->pw;
+  sw.c_part = h->c_part; sw.drift_bits = h->bits + 1; sw.psiT64 = h->psiT64; sw.u = u_dev;
+  sw.alpha_fid = h->a_fid; sw.alpha_pen = h->a_pen; sw.alpha_amp = h->a_amp;
+  sw.alpha_var = h->a_var; sw.fid_mode = h->fid_mode; sw.out = out_dev; sw.zinfo = h->zinfo;
+  {
+    PhaseTimer tm(h, QOC_PHASE_FWD_BLOCKS, st);
+    HIP_TRY(qoc::launch_fwd_blocks<T>(sw, st));
+  }
+  {
+    PhaseTimer tm(h, QOC_PHASE_FWD_REPLAY, st);
+    HIP_TRY(qoc::launch_fwd_replay<T>(sw, st));
+  }
+  {
+    PhaseTimer tm(h, QOC_PHASE_COST, st);
+    HIP_TRY(qoc::launch_cost<T>(sw, st));
+  }
+  if (!want_grad) return QOC_OK;
+  {
+    PhaseTimer tm(h, QOC_PHASE_BWD_BLOCKS, st);
+    HIP_TRY(qoc::launch_bwd_blocks<T>(sw, st));
+  }
+  {
+    PhaseTimer tm(h, QOC_PHASE_BWD_PAIRS, st);
+    HIP_TRY(qoc::launch_bwd_pairs<T>(sw, st));
+  }
+  if (M > 0) {
+    PhaseTimer tm(h, QOC_PHASE_ADJOINT, st);
+    qoc::AdjointArgs<T> ad{};
+    ad.N = N; ad.dp = dp; ad.M = M; ad.S = S; ad.p = p; ad.n = n;
+    ad.Rcap = std::min(Rcap, dp); ad.nblocks = h->adj_blocks;
+    ad.X = X; ad.Dlev = Dl; ad.lam_buf = (const T *)h->lam_buf; ad.psi_buf = (const T *)h->psi_buf;
+    ad.Hf = (const T *)h->Hf; ad.u = u_dev; ad.s_scale = std::ldexp(h->dt, -n);
+    ad.alpha_amp = h->a_amp; ad.alpha_var = h->a_var; ad.scratch = (T *)h->adj;
+    ad.scratch_elems = qoc::adjoint_scratch_elems<T>(dp, p, ad.Rcap); ad.grad = grad_dev;
+    HIP_TRY(qoc::launch_adjoint<T>(ad, st));
+  }
+  return QOC_OK;
+}
+
+qoc_status run_any(qoc_handle *h, const double *u_dev, double *out_dev, double *grad_dev,
+                   hipStream_t st, bool want_grad) {
+  if (h->prec == QOC_FP64) return run<double>(h, u_dev, out_dev, grad_dev, st, want_grad);
+  return run<float>(h, u_dev, out_dev, grad_dev, st, want_grad);
+}
+
+qoc_status finish_diag(qoc_handle *h, hipStream_t st, int *flags) {
+  unsigned long long b[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(b, h->bits, sizeof(b), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double th, dr;
+  std::memcpy(&th, &b[0], 8);
+  std::memcpy(&dr, &b[1], 8);
+  h->last_theta = th;
+  h->last_drift = dr;
+  if (flags) *flags = (dr > h->drift_warn) ? QOC_WARN_DRIFT : 0;
+  if (h->prof) return drain_pending(h);
+  return QOC_OK;
+}
+
+qoc_status check_u(qoc_handle *h, const double *u) {
+  if (h->M > 0 && !u) return fail(QOC_ERR_ARG, "u is NULL");
+  if (h->M > 0 && !all_finite(u, (size_t)h->M * h->N))
+    return fail(QOC_ERR_NONFINITE, "u contains NaN or Inf");
+  return QOC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qoc_version(void) { return "libqoc 0.1 (gfx950)"; }
+
+const char *qoc_last_error(void) { return g_err.c_str(); }
+
+const char *qoc_status_string(qoc_status s) {
+  switch (s) {
+    case QOC_OK: return "ok";
+    case QOC_ERR_ARG: return "invalid argument";
+    case QOC_ERR_SHAPE: return "invalid shape";
+    case QOC_ERR_NOT_HERMITIAN: return "Hamiltonian not Hermitian";
+    case QOC_ERR_NONFINITE: return "non-finite input";
+    case QOC_ERR_NOMEM: return "out of memory";
+    case QOC_ERR_DEVICE: return "device error";
+    case QOC_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+qoc_status qoc_taylor_select(double theta, double tol, int *p, int *n) {
+  if (!p || !n) return fail(QOC_ERR_ARG, "null output pointer");
+  if (!(theta >= 0.0) || !std::isfinite(theta) || !(tol > 0.0))
+    return fail(QOC_ERR_ARG, "theta must be finite and >= 0, tol > 0");
+  if (!taylor_select(theta, tol, p, n)) return fail(QOC_ERR_UNSUPPORTED, "no (p, n) meets tol");
+  return QOC_OK;
+}
+
+qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
+  if (!out) return fail(QOC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(QOC_ERR_ARG, "desc is NULL");
+  const qoc_problem_desc &D = *desc;
+  if (D.d < 1 || D.d > 1024) return fail(QOC_ERR_SHAPE, "d must be in [1, 1024]");
+  if (D.M < 0 || D.M > 64) return fail(QOC_ERR_SHAPE, "M must be in [0, 64]");
+  if (D.N < 1 || D.N > (1 << 22)) return fail(QOC_ERR_SHAPE, "N must be in [1, 2^22]");
+  if (D.S < 1 || D.S > D.d) return fail(QOC_ERR_SHAPE, "S must be in [1, d]");
+  if (!(D.dt > 0.0) || !std::isfinite(D.dt)) return fail(QOC_ERR_ARG, "dt must be finite and > 0");
+  if (!D.H0 || !D.psi0 || !D.psiT || (D.M > 0 && !D.Hk))
+    return fail(QOC_ERR_ARG, "H0, Hk (M > 0), psi0 and psiT must be non-NULL");
+  if (D.fid_mode != QOC_FID_COHERENT && D.fid_mode != QOC_FID_INCOHERENT)
+    return fail(QOC_ERR_ARG, "fid_mode must be QOC_FID_COHERENT or QOC_FID_INCOHERENT");
+  if (D.precision != QOC_FP32 && D.precision != QOC_FP64 && D.precision != QOC_BF16X3)
+    return fail(QOC_ERR_ARG, "precision must be QOC_FP32, QOC_FP64 or QOC_BF16X3");
+  if (D.precision == QOC_BF16X3)
+    return fail(QOC_ERR_UNSUPPORTED, "QOC_BF16X3 is not available in this build");
+  if (D.checkpoint_every < 0) return fail(QOC_ERR_ARG, "checkpoint_every must be >= 0");
+  if (!(D.taylor_tol >= 0.0) || !std::isfinite(D.taylor_tol))
+    return fail(QOC_ERR_ARG, "taylor_tol must be finite and >= 0");
+  if (!(D.taylor_p == 0 || (D.taylor_p >= 2 && D.taylor_p <= 64 && D.taylor_n >= 0 &&
+                            D.taylor_n <= 60)))
+    return fail(QOC_ERR_ARG, "taylor_p must be 0 (automatic) or in [2, 64] with taylor_n in [0, 60]");
+  if (!(D.drift_warn >= 0.0)) return fail(QOC_ERR_ARG, "drift_warn must be >= 0");
+  const double alphas[4] = {D.alpha_fid, D.alpha_amp, D.alpha_var, D.alpha_pen};
+  if (!all_finite(alphas, 4)) return fail(QOC_ERR_NONFINITE, "cost weights must be finite");
+  const size_t dd = (size_t)D.d * D.d * 2;
+  if (!all_finite(D.H0, dd) || (D.M > 0 && !all_finite(D.Hk, dd * D.M)))
+    return fail(QOC_ERR_NONFINITE, "Hamiltonian contains NaN or Inf");
+  if (!all_finite(D.psi0, (size_t)D.S * D.d * 2) || !all_finite(D.psiT, (size_t)D.S * D.d * 2))
+    return fail(QOC_ERR_NONFINITE, "states contain NaN or Inf");
+  if (D.penalty_w) {
+    if (!all_finite(D.penalty_w, D.d)) return fail(QOC_ERR_NONFINITE, "penalty_w has NaN or Inf");
+    for (int m = 0; m < D.d; ++m)
+      if (D.penalty_w[m] < 0.0) return fail(QOC_ERR_ARG, "penalty_w must be >= 0");
+  }
+  if (!hermitian(D.H0, D.d)) return fail(QOC_ERR_NOT_HERMITIAN, "H0 is not Hermitian");
+  for (int k = 0; k < D.M; ++k)
+    if (!hermitian(D.Hk + dd * k, D.d))
+      return fail(QOC_ERR_NOT_HERMITIAN, "H_" + std::to_string(k + 1) + " is not Hermitian");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(QOC_ERR_DEVICE, "no HIP device available");
+  }
+  if (D.device < 0 || D.device >= ndev) return fail(QOC_ERR_ARG, "device ordinal out of range");
+
+  qoc_handle *h = new (std::nothrow) qoc_handle();
+  if (!h) return fail(QOC_ERR_NOMEM, "host allocation failed");
+  h->d = D.d;
+  h->dp = (D.d + 15) / 16 * 16;
+  h->M = D.M;
+  h->N = D.N;
+  h->S = D.S;
+  h->dt = D.dt;
+  h->prec = D.precision;
+  h->esize = (D.precision == QOC_FP64) ? 8 : 4;
+  h->fid_mode = D.fid_mode;
+  h->a_fid = D.alpha_fid;
+  h->a_amp = D.alpha_amp;
+  h->a_var = D.alpha_var;
+  h->a_pen = D.alpha_pen;
+  h->has_pen = D.penalty_w != nullptr;
+  h->tol = D.taylor_tol > 0 ? D.taylor_tol : (D.precision == QOC_FP64 ? 1e-15 : 1e-10);
+  h->drift_warn = D.drift_warn > 0 ? D.drift_warn : 1e-4;
+  h->fixed_p = D.taylor_p;
+  h->fixed_n = D.taylor_n;
+  h->device = D.device;
+  if (D.checkpoint_every > 0) {
+    h->L = pow2_at_least(D.checkpoint_every);
+  } else {
+    const double r = std::sqrt((double)D.N);
+    int l = 1;
+    while (l * 2 <= r) l <<= 1;                   // l <= sqrt(N) < 2l
+    h->L = (r / l > (2.0 * l) / r) ? 2 * l : l;   // nearer in ratio
+  }
+  h->nb = (int)((D.N + h->L - 1) / h->L);
+  h->adj_blocks = std::min(D.N, 1024);
+  DeviceGuard g(h->device);
+  if (!g.ok) {
+    delete h;
+    return fail(QOC_ERR_DEVICE, "hipSetDevice failed");
+  }
+  if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete h;
+    return fail(QOC_ERR_DEVICE, "hipStreamCreate failed");
+  }
+  qoc_status s = (h->prec == QOC_FP64) ? alloc_all<double>(h, desc) : alloc_all<float>(h, desc);
+  if (s != QOC_OK) {
+    std::string msg = g_err;
+    release(h);
+    delete h;
+    return fail(s, msg);
+  }
+  *out = h;
+  return QOC_OK;
+}
+
+void qoc_destroy(qoc_handle *h) {
+  if (!h) return;
+  DeviceGuard g(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  release(h);
+  delete h;
+}
+
+qoc_status qoc_forward(qoc_handle *h, const double *u, double *cost_fid, double *step_penalty,
+                       double *psiN, int *flags_out) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  qoc_status s = check_u(h, u);
+  if (s) return s;
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(QOC_ERR_DEVICE, "hipSetDevice failed");
+  hipStream_t st = h->stream;
+  const size_t mn = (size_t)h->M * h->N;
+  if (mn) {
+    std::memcpy(h->h_u, u, mn * sizeof(double));
+    HIP_TRY(hipMemcpyAsync(h->u_dev, h->h_u, mn * sizeof(double), hipMemcpyHostToDevice, st));
+  }
+  if ((s = run_any(h, h->u_dev, h->out_dev, h->grad_dev, st, false)) != QOC_OK) return s;
+  HIP_TRY(hipMemcpyAsync(h->h_out, h->out_dev, (2 + h->N) * sizeof(double),
+                         hipMemcpyDeviceToHost, st));
+  // final states: psi_buf[N] (padded planar, chain precision)
+  const size_t set = 2 * (size_t)h->S * h->dp;
+  std::vector<unsigned char> tmp(set * h->esize);
+  HIP_TRY(hipMemcpyAsync(tmp.data(), (unsigned char *)h->psi_buf + (size_t)h->N * set * h->esize,
+                         set * h->esize, hipMemcpyDeviceToHost, st));
+  int flags = 0;
+  if ((s = finish_diag(h, st, &flags)) != QOC_OK) return s;
+  if (cost_fid) *cost_fid = h->h_out[1];
+  if (step_penalty) std::memcpy(step_penalty, h->h_out + 2, h->N * sizeof(double));
+  if (psiN) {
+    for (int s2 = 0; s2 < h->S; ++s2)
+      for (int m = 0; m < h->d; ++m) {
+        const size_t ir = (size_t)s2 * h->dp + m, ii = (size_t)h->S * h->dp + ir;
+        double vr, vi;
+        if (h->esize == 8) {
+          vr = ((double *)tmp.data())[ir];
+          vi = ((double *)tmp.data())[ii];
+        } else {
+          vr = ((float *)tmp.data())[ir];
+          vi = ((float *)tmp.data())[ii];
+        }
+        psiN[2 * ((size_t)s2 * h->d + m)] = vr;
+        psiN[2 * ((size_t)s2 * h->d + m) + 1] = vi;
+      }
+  }
+  if (flags_out) *flags_out = flags;
+  return QOC_OK;
+}
+
+qoc_status qoc_cost_grad(qoc_handle *h, const double *u, double *cost, double *cost_fid,
+                         double *step_penalty, double *grad, int *flags_out) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  if (h->M > 0 && !grad) return fail(QOC_ERR_ARG, "grad is NULL");
+  qoc_status s = check_u(h, u);
+  if (s) return s;
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(QOC_ERR_DEVICE, "hipSetDevice failed");
+  hipStream_t st = h->stream;
+  const size_t mn = (size_t)h->M * h->N;
+  if (mn) {
+    std::memcpy(h->h_u, u, mn * sizeof(double));
+    HIP_TRY(hipMemcpyAsync(h->u_dev, h->h_u, mn * sizeof(double), hipMemcpyHostToDevice, st));
+  }
+  if ((s = run_any(h, h->u_dev, h->out_dev, h->grad_dev, st, true)) != QOC_OK) return s;
+  HIP_TRY(hipMemcpyAsync(h->h_out, h->out_dev, (2 + h->N) * sizeof(double),
+                         hipMemcpyDeviceToHost, st));
+  if (mn)
+    HIP_TRY(hipMemcpyAsync(h->h_grad, h->grad_dev, mn * sizeof(double), hipMemcpyDeviceToHost, st));
+  int flags = 0;
+  if ((s = finish_diag(h, st, &flags)) != QOC_OK) return s;
+  if (cost) *cost = h->h_out[0];
+  if (cost_fid) *cost_fid = h->h_out[1];
+  if (step_penalty) std::memcpy(step_penalty, h->h_out + 2, h->N * sizeof(double));
+  if (mn) std::memcpy(grad, h->h_grad, mn * sizeof(double));
+  if (flags_out) *flags_out = flags;
+  return QOC_OK;
+}
+
+qoc_status qoc_cost_grad_device(qoc_handle *h, const double *u_dev, double *out_dev,
+                                double *grad_dev, void *stream) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  if ((h->M > 0 && (!u_dev || !grad_dev)) || !out_dev)
+    return fail(QOC_ERR_ARG, "u_dev, out_dev and grad_dev must be non-NULL");
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(QOC_ERR_DEVICE, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)stream;
+  return run_any(h, h->M > 0 ? u_dev : h->u_dev, out_dev, grad_dev, st, true);
+}
+
+qoc_status qoc_cost_grad_batched(int B, qoc_handle *const *hs, const double *const *u_dev,
+                                 double *const *out_dev, double *const *grad_dev, void *stream) {
+  if (B < 0 || (B > 0 && (!hs || !u_dev || !out_dev || !grad_dev)))
+    return fail(QOC_ERR_ARG, "invalid batch arrays");
+  for (int b = 0; b < B; ++b) {
+    if (!hs[b]) return fail(QOC_ERR_ARG, "null handle in batch");
+    if (hs[b]->device != hs[0]->device) return fail(QOC_ERR_ARG, "batch spans several devices");
+  }
+  for (int b = 0; b < B; ++b) {
+    qoc_status s = qoc_cost_grad_device(hs[b], u_dev[b], out_dev[b], grad_dev[b], stream);
+    if (s) return s;
+  }
+  return QOC_OK;
+}
+
+qoc_status qoc_get_info(const qoc_handle *h, qoc_info *info) {
+  if (!h || !info) return fail(QOC_ERR_ARG, "null argument");
+  info->p = h->last_p;
+  info->n = h->last_n;
+  info->theta_max = h->last_theta;
+  info->norm_drift = h->last_drift;
+  info->block_len = h->L;
+  info->n_blocks = h->nb;
+  info->d_pad = h->dp;
+  info->device_bytes = h->bytes;
+  return QOC_OK;
+}
+
+qoc_status qoc_profile_enable(qoc_handle *h, int on) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  h->prof = on != 0;
+  return QOC_OK;
+}
+
+qoc_status qoc_profile_read(qoc_handle *h, double *ms, long long *calls, int reset) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  DeviceGuard g(h->device);
+  qoc_status s = drain_pending(h);
+  if (s) return s;
+  for (int i = 0; i < QOC_PHASE_COUNT; ++i) {
+    if (ms) ms[i] = h->prof_ms[i];
+    if (calls) calls[i] = h->prof_calls[i];
+    if (reset) {
+      h->prof_ms[i] = 0;
+      h->prof_calls[i] = 0;
+    }
+  }
+  return QOC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+// Device-side building blocks shared by the libqoc kernels (gfx950 / CDNA4).
+//
+// Complex matrices are stored planar: a real plane and an imaginary plane,
+// each row-major.  A complex product is four real MFMA products
+//   Re(AB) = Ar Br - Ai Bi,   Im(AB) = Ar Bi + Ai Br,
+// i.e. the real block form of the paper's complex-to-real isomorphism
+// (Sec. III, eq. 8) applied to one operand only, without materialising the
+// redundant 2d x 2d block matrix.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qoc {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct V4T;
+template <> struct V4T<float> { typedef f32x4 type; };
+template <> struct V4T<double> { typedef f64x4 type; };
+template <typename T> using v4 = typename V4T<T>::type;
+
+// D(16x16) += A(16x4) B(4x16).  Operand layout: lane l holds A[l%16][l/16]
+// and B[l/16][l%16]; result register v of lane l is D[4*(l/16)+v][l%16].
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma4(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __device__ __forceinline__ v4<T> vzero() {
+  v4<T> z;
+  z[0] = 0; z[1] = 0; z[2] = 0; z[3] = 0;
+  return z;
+}
+
+// Planar complex matrix view: element (r, c) at re[r*ld + c], im[r*ld + c].
+template <typename T> struct CView {
+  T *re, *im;
+  int ld;
+};
+
+template <typename T>
+__device__ __forceinline__ CView<T> cview(T *base, long plane, int ld) {
+  CView<T> v;
+  v.re = base;
+  v.im = base + plane;
+  v.ld = ld;
+  return v;
+}
+
+// One wavefront accumulates the 16x16 complex tile (r0, c0) of
+// op(A) * op(B) over an inner dimension K (multiple of 4), reading operands
+// straight from global memory (L1/L2 resident).  OPA / OPB: 0 = as stored,
+// 1 = conjugate transpose.  cr, ci: real / imaginary accumulators.
+template <typename T, int OPA, int OPB>
+__device__ __forceinline__ void wave_cgemm16(CView<const T> A, CView<const T> B, int r0,
+                                             int c0, int K, v4<T> &cr, v4<T> &ci) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
+  for (int k = 0; k < K; k += 4) {
+    T ar, ai, br, bi;
+    if (OPA == 0) {
+      const long o = (long)(r0 + i) * A.ld + (k + kk);
+      ar = A.re[o]; ai = A.im[o];
+    } else {
+      const long o = (long)(k + kk) * A.ld + (r0 + i);
+      ar = A.re[o]; ai = -A.im[o];
+    }
+    if (OPB == 0) {
+      const long o = (long)(k + kk) * B.ld + (c0 + i);
+      br = B.re[o]; bi = B.im[o];
+    } else {
+      const long o = (long)(c0 + i) * B.ld + (k + kk);
+      br = B.re[o]; bi = -B.im[o];
+    }
+    cr = mfma4(ar, br, cr);
+    cr = mfma4(-ai, bi, cr);
+    ci = mfma4(ar, bi, ci);
+    ci = mfma4(ai, br, ci);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup (256 threads, 4 waves) LDS-tiled 64x64 complex tile of
+// C = op(A) * B, with op(A) = A or A^H and B as stored.  The inner
+// dimension runs in chunks of BK = 16 staged in LDS in k-major layout
+// (row stride 64 + 16 elements, which keeps the 16-lane fragment reads of
+// each half-wave on distinct banks).  Wave w owns the 32x32 sub-tile
+// (32*(w>>1), 32*(w&1)) as 2x2 MFMA tiles.
+// ---------------------------------------------------------------------------
+constexpr int T64_BK = 16;
+constexpr int T64_LD = 64 + 16;
+// LDS elements of T needed by wg_cgemm64: A and B chunks, re and im planes.
+constexpr int T64_LDS_ELEMS = 4 * T64_BK * T64_LD;
+
+template <typename T, int OPA>
+__device__ __forceinline__ void wg_cgemm64(CView<const T> A, CView<const T> B, int r0, int c0,
+                                           int K, T *lds, v4<T> (&acc)[2][2][2]) {
+  T *Asr = lds;
+  T *Asi = Asr + T64_BK * T64_LD;
+  T *Bsr = Asi + T64_BK * T64_LD;
+  T *Bsi = Bsr + T64_BK * T64_LD;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  for (int k0 = 0; k0 < K; k0 += T64_BK) {
+    // stage op(A)[r0:r0+64, k0:k0+16] as As[k][r]
+    if (OPA == 0) {
+      const int r = t >> 2, kq = (t & 3) * 4;
+      const long o = (long)(r0 + r) * A.ld + k0 + kq;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Asr[(kq + q) * T64_LD + r] = A.re[o + q];
+        Asi[(kq + q) * T64_LD + r] = A.im[o + q];
+      }
+    } else {
+      const int k = t >> 4, rq = (t & 15) * 4;
+      const long o = (long)(k0 + k) * A.ld + r0 + rq;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Asr[k * T64_LD + rq + q] = A.re[o + q];
+        Asi[k * T64_LD + rq + q] = -A.im[o + q];
+      }
+    }
+    {
+      const int k = t >> 4, cq = (t & 15) * 4;
+      const long o = (long)(k0 + k) * B.ld + c0 + cq;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Bsr[k * T64_LD + cq + q] = B.re[o + q];
+        Bsi[k * T64_LD + cq + q] = B.im[o + q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < T64_BK; k4 += 4) {
+      T ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        ar[m] = Asr[(k4 + kk) * T64_LD + wr + 16 * m + i];
+        ai[m] = Asi[(k4 + kk) * T64_LD + wr + 16 * m + i];
+        br[m] = Bsr[(k4 + kk) * T64_LD + wc + 16 * m + i];
+        bi[m] = Bsi[(k4 + kk) * T64_LD + wc + 16 * m + i];
+      }
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          acc[m][n][0] = mfma4(ar[m], br[n], acc[m][n][0]);
+          acc[m][n][0] = mfma4(-ai[m], bi[n], acc[m][n][0]);
+          acc[m][n][1] = mfma4(ar[m], bi[n], acc[m][n][1]);
+          acc[m][n][1] = mfma4(ai[m], br[n], acc[m][n][1]);
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// Blocks of a 1-D launch are dispatched round-robin over the 8 XCDs of an
+// MI355X.  Re-map the block index so that consecutive logical blocks (the
+// tiles of one matrix, which share operand panels) land on the same XCD
+// and hence the same L2.  `padded` is the launch size, a multiple of 8.
+__device__ __forceinline__ long xcd_logical_block(long b, long padded) {
+  const long per = padded >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+// Wave-wide sum (64 lanes) with cross-lane shuffles.
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T> __device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+}  // namespace qoc

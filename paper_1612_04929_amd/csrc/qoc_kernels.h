@@ -1,0 +1,86 @@
+// Host-side launchers of the libqoc HIP kernels (implemented in the *.hip
+// files of this directory, instantiated for float and double).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace qoc {
+
+// Batched complex product with a fused epilogue, one matrix per step:
+//   C_j = alpha * op(A_j) * B_j + betaA * A_j + betaB * B_j + gamma * I
+// Matrices are dp x dp planar (re plane, then im plane), matrix j of a
+// stack at base + j * stride.  op(A) = A (opa = 0) or A^H (opa = 1).
+template <typename T> struct StageArgs {
+  const T *A;
+  long strideA;
+  const T *B;
+  long strideB;
+  T *C;
+  long strideC;
+  int nmat, dp;
+  T alpha, betaA, betaB, gamma;
+};
+
+// X_j = -i s (H_0 + sum_k u_{k,j} H_k) for all steps and, when Q is not
+// null, Q_j = I + X_j / p (the innermost Horner factor).
+template <typename T>
+hipError_t launch_assemble(const T *Hf, const double *u, int dp, int M, int N, T s, T inv_p,
+                           T *X, T *Q, hipStream_t st);
+
+template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hipStream_t st);
+
+// theta_max = max_j ||dt H_j||_1 in FP64 (atomic max on the bit pattern).
+hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, double dt,
+                       unsigned long long *theta_bits, hipStream_t st);
+
+template <typename T> hipError_t launch_fill(T *p, long n, T v, hipStream_t st);
+
+// Blocked two-level sweep.  State sets are [2][S][dp] (re plane of S
+// states, then im plane).  Block b covers steps [b*L, min(N, (b+1)*L)).
+template <typename T> struct SweepArgs {
+  int N, L, nb, dp, d, S, M;
+  const T *D;          // N x (2 dp^2): D_j = U_j - I
+  const T *E;          // nb x (2 dp^2): block products minus identity
+  const T *psi0;       // one state set
+  T *ckpt;             // (nb+1) state sets: psi at block starts
+  T *psi_buf;          // (N+1) state sets: psi_j
+  T *lam_ckpt;         // (nb+1) state sets: lambda at block starts
+  T *mu;               // nb state sets: block-local penalty costates
+  T *lam_buf;          // N state sets: lambda_{j+1} for step j
+  const double *w64;   // dp penalty weights (FP64) or null
+  const T *pw;         // dp scaled weights a_pen / S * w or null
+  double *c_part;      // (N+1) x S per-column penalty sums
+  unsigned long long *drift_bits;
+  // cost
+  const double *psiT64;  // S x d interleaved complex targets
+  const double *u;       // M x N controls (FP64)
+  double alpha_fid, alpha_pen, alpha_amp, alpha_var;
+  int fid_mode;
+  double *out;          // [C, C_fid, c_1..c_N]
+  double *zinfo;        // [Re z, Im z, F]
+};
+template <typename T> hipError_t launch_fwd_blocks(const SweepArgs<T> &a, hipStream_t st);
+template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStream_t st);
+template <typename T> hipError_t launch_cost(const SweepArgs<T> &a, hipStream_t st);
+template <typename T> hipError_t launch_bwd_blocks(const SweepArgs<T> &a, hipStream_t st);
+template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStream_t st);
+
+// Exact per-step derivative of the Taylor + squaring evaluation, contracted
+// with the control Hamiltonians (see kernels_adjoint.hip).
+template <typename T> struct AdjointArgs {
+  int N, dp, M, S, p, n, Rcap, nblocks;
+  const T *X;          // N x 2 dp^2
+  const T *Dlev;       // (n+1) x N x 2 dp^2: D^(i)_j, level-major
+  const T *lam_buf;    // N state sets
+  const T *psi_buf;    // (N+1) state sets
+  const T *Hf;         // (M+1) x 2 dp^2 (index 0 = H_0)
+  const double *u;     // M x N
+  double s_scale;      // dt / 2^n
+  double alpha_amp, alpha_var;
+  T *scratch;          // nblocks x scratch_elems
+  long scratch_elems;
+  double *grad;        // M x N
+};
+template <typename T> long adjoint_scratch_elems(int dp, int p, int Rcap);
+template <typename T> hipError_t launch_adjoint(const AdjointArgs<T> &a, hipStream_t st);
+
+}  // namespace qoc

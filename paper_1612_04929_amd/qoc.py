@@ -1,0 +1,217 @@
+"""Python binding of libqoc (ctypes; argument marshalling only).
+
+Every step of the cost and gradient runs in the HIP kernels of
+``libqoc.so``; this module converts arrays to the C-ABI layout declared in
+``include/qoc.h`` and raises :class:`QocError` on any non-zero status.
+There is no fallback: if the shared library is missing or fails to load,
+``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqoc.so")
+
+QOC_FP64, QOC_FP32, QOC_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": QOC_FP64, "fp32": QOC_FP32, "bf16x3": QOC_BF16X3}
+QOC_FID_COHERENT, QOC_FID_INCOHERENT = 0, 1
+QOC_WARN_DRIFT = 1
+PHASES = ["norm", "assemble", "taylor", "blockprod", "fwd_blocks", "fwd_replay", "cost",
+          "bwd_blocks", "bwd_pairs", "adjoint"]
+STATUS = {0: "QOC_OK", -1: "QOC_ERR_ARG", -2: "QOC_ERR_SHAPE", -3: "QOC_ERR_NOT_HERMITIAN",
+          -4: "QOC_ERR_NONFINITE", -5: "QOC_ERR_NOMEM", -6: "QOC_ERR_DEVICE",
+          -7: "QOC_ERR_UNSUPPORTED"}
+EXPORTS = ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
+           "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
+           "qoc_profile_read", "qoc_taylor_select", "qoc_destroy", "qoc_status_string",
+           "qoc_last_error", "qoc_version"]
+
+_dp = C.POINTER(C.c_double)
+
+
+class Desc(C.Structure):
+    _fields_ = [("d", C.c_int), ("M", C.c_int), ("N", C.c_int), ("S", C.c_int),
+                ("dt", C.c_double), ("H0", _dp), ("Hk", _dp), ("psi0", _dp), ("psiT", _dp),
+                ("penalty_w", _dp), ("alpha_fid", C.c_double), ("alpha_amp", C.c_double),
+                ("alpha_var", C.c_double), ("alpha_pen", C.c_double), ("fid_mode", C.c_int),
+                ("precision", C.c_int), ("checkpoint_every", C.c_int),
+                ("taylor_tol", C.c_double), ("taylor_p", C.c_int), ("taylor_n", C.c_int),
+                ("drift_warn", C.c_double), ("device", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("p", C.c_int), ("n", C.c_int), ("theta_max", C.c_double),
+                ("norm_drift", C.c_double), ("block_len", C.c_int), ("n_blocks", C.c_int),
+                ("d_pad", C.c_int), ("device_bytes", C.c_size_t)]
+
+
+class QocError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libqoc.so (raises if it is missing: there is no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing; build it with "
+                          "`python -m paper_1612_04929_amd.build`")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.qoc_create.argtypes = [C.POINTER(Desc), C.POINTER(vp)]
+    lib.qoc_forward.argtypes = [vp, _dp, _dp, _dp, _dp, C.POINTER(C.c_int)]
+    lib.qoc_cost_grad.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, C.POINTER(C.c_int)]
+    lib.qoc_cost_grad_device.argtypes = [vp, vp, vp, vp, vp]
+    lib.qoc_cost_grad_batched.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp),
+                                          C.POINTER(vp), C.POINTER(vp), vp]
+    lib.qoc_get_info.argtypes = [vp, C.POINTER(Info)]
+    lib.qoc_profile_enable.argtypes = [vp, C.c_int]
+    lib.qoc_profile_read.argtypes = [vp, _dp, C.POINTER(C.c_longlong), C.c_int]
+    lib.qoc_taylor_select.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int)]
+    lib.qoc_destroy.argtypes = [vp]
+    lib.qoc_destroy.restype = None
+    for f in ["qoc_status_string", "qoc_last_error", "qoc_version"]:
+        getattr(lib, f).restype = C.c_char_p
+    lib.qoc_status_string.argtypes = [C.c_int]
+    for f in ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
+              "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
+              "qoc_profile_read", "qoc_taylor_select"]:
+        getattr(lib, f).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != 0:
+        raise QocError(st, load().qoc_last_error().decode())
+
+
+def _cplx(a, shape):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128).reshape(shape))
+    return a, a.view(np.float64).ctypes.data_as(_dp)
+
+
+def taylor_select(theta: float, tol: float):
+    p, n = C.c_int(), C.c_int()
+    _check(load().qoc_taylor_select(float(theta), float(tol), C.byref(p), C.byref(n)))
+    return p.value, n.value
+
+
+def version() -> str:
+    return load().qoc_version().decode()
+
+
+class Problem:
+    """A handle on one optimal-control problem resident on the GPU.
+
+    ``prob`` is any object with the attributes d, M, N, S, dt, H0 (d x d),
+    Hk (M x d x d), psi0 / psiT (S x d, row s = state s), w (d or None),
+    alpha_fid / alpha_pen / alpha_amp / alpha_var and fid_mode.
+    """
+
+    def __init__(self, prob, precision="fp32", checkpoint_every=0, taylor_tol=0.0,
+                 taylor_pn=None, drift_warn=0.0, device=0):
+        lib = load()
+        self.d, self.M, self.N, self.S = int(prob.d), int(prob.M), int(prob.N), int(prob.S)
+        keep = []
+        H0, pH0 = _cplx(prob.H0, (self.d, self.d))
+        Hk, pHk = _cplx(prob.Hk if self.M else np.zeros((1, self.d, self.d)),
+                        (max(self.M, 1), self.d, self.d))
+        p0, pp0 = _cplx(prob.psi0, (self.S, self.d))
+        pT, ppT = _cplx(prob.psiT, (self.S, self.d))
+        keep += [H0, Hk, p0, pT]
+        pw = None
+        if getattr(prob, "w", None) is not None:
+            w = np.ascontiguousarray(np.asarray(prob.w, dtype=np.float64).reshape(self.d))
+            keep.append(w)
+            pw = w.ctypes.data_as(_dp)
+        mode = getattr(prob, "fid_mode", "coherent")
+        fid = {"coherent": 0, "incoherent": 1}.get(mode, mode)
+        tp, tn = (0, 0) if taylor_pn is None else (int(taylor_pn[0]), int(taylor_pn[1]))
+        desc = Desc(self.d, self.M, self.N, self.S, float(prob.dt), pH0,
+                    pHk if self.M else None, pp0, ppT, pw, float(prob.alpha_fid),
+                    float(prob.alpha_amp), float(prob.alpha_var), float(prob.alpha_pen),
+                    int(fid), PRECISIONS.get(precision, precision), int(checkpoint_every),
+                    float(taylor_tol), tp, tn, float(drift_warn), int(device))
+        self._h = C.c_void_p()
+        _check(lib.qoc_create(C.byref(desc), C.byref(self._h)))
+        self.precision = precision
+
+    # -- host-array calls -------------------------------------------------
+    def _u(self, u):
+        u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(self.M, self.N))
+        return u, u.ctypes.data_as(_dp)
+
+    def forward(self, u):
+        u, pu = self._u(u)
+        cf = C.c_double()
+        c = np.zeros(self.N)
+        psiN = np.zeros((self.S, self.d), dtype=np.complex128)
+        flags = C.c_int()
+        _check(load().qoc_forward(self._h, pu, C.byref(cf), c.ctypes.data_as(_dp),
+                                  psiN.view(np.float64).ctypes.data_as(_dp), C.byref(flags)))
+        return dict(C_fid=cf.value, c=c, psiN=psiN, flags=flags.value, **self.info())
+
+    def cost_grad(self, u):
+        u, pu = self._u(u)
+        cc, cf = C.c_double(), C.c_double()
+        c = np.zeros(self.N)
+        g = np.zeros((max(self.M, 1), self.N))
+        flags = C.c_int()
+        _check(load().qoc_cost_grad(self._h, pu, C.byref(cc), C.byref(cf),
+                                    c.ctypes.data_as(_dp), g.ctypes.data_as(_dp),
+                                    C.byref(flags)))
+        return dict(C=cc.value, C_fid=cf.value, c=c, grad=g[: self.M], flags=flags.value,
+                    **self.info())
+
+    # -- device-pointer call (e.g. torch tensors) ---------------------------
+    def cost_grad_device(self, u_ptr: int, out_ptr: int, grad_ptr: int, stream: int = 0):
+        _check(load().qoc_cost_grad_device(self._h, C.c_void_p(u_ptr), C.c_void_p(out_ptr),
+                                           C.c_void_p(grad_ptr), C.c_void_p(stream)))
+
+    def info(self):
+        inf = Info()
+        _check(load().qoc_get_info(self._h, C.byref(inf)))
+        return dict(p=inf.p, n=inf.n, theta_max=inf.theta_max, norm_drift=inf.norm_drift,
+                    block_len=inf.block_len, n_blocks=inf.n_blocks, d_pad=inf.d_pad,
+                    device_bytes=inf.device_bytes)
+
+    def profile_enable(self, on=True):
+        _check(load().qoc_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self, reset=False):
+        ms = (C.c_double * len(PHASES))()
+        calls = (C.c_longlong * len(PHASES))()
+        _check(load().qoc_profile_read(self._h, ms, calls, 1 if reset else 0))
+        return {ph: (ms[i], calls[i]) for i, ph in enumerate(PHASES)}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().qoc_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cost_grad_batched(problems, u_ptrs, out_ptrs, grad_ptrs, stream: int = 0):
+    """One call over several handles (device pointers, one stream)."""
+    B = len(problems)
+    arr = lambda xs: (C.c_void_p * max(B, 1))(*[C.c_void_p(int(x)) for x in xs])
+    hs = (C.c_void_p * max(B, 1))(*[p._h for p in problems])
+    _check(load().qoc_cost_grad_batched(B, hs, arr(u_ptrs), arr(out_ptrs), arr(grad_ptrs),
+                                        C.c_void_p(stream)))

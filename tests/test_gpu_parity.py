@@ -1,0 +1,172 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (FP32 chains): |F_gpu - F_oracle| <= 1e-6 and gradient relative
+l2 error <= 1e-4 (the accuracy targets of the FP32 path).  FP64 chains:
+|dF| <= 1e-11, gradient relative error <= 1e-9.  Per-step penalties and
+the total cost are compared against bounds derived in the design notes from
+FP32 state rounding: |dc_j| <= 2e-6 * max(1, max|c|) and
+|dC| <= 1e-6 * (1 + |C|) + a_pen * N * 2e-6.
+
+Every case prints its name, shape and the achieved errors (flushed) before
+and after the GPU call.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_1612_04929_amd import qoc
+
+pytestmark = pytest.mark.gpu
+
+REPORT = os.environ.get("QOC_PARITY_REPORT")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def compare(name, prob, precision="fp32", oracle_out=None, **kw):
+    say(f"[parity] {name}: d={prob.d} M={prob.M} N={prob.N} S={prob.S} prec={precision}")
+    ref = oracle_out if oracle_out is not None else oracle.cost_grad(prob)
+    h = qoc.Problem(prob, precision=precision, **kw)
+    out = h.cost_grad(prob.u)
+    fwd = h.forward(prob.u)
+    h.close()
+    errs = dict(
+        dF=abs((1 - out["C_fid"]) - ref["F"]),
+        dC=abs(out["C"] - ref["C"]),
+        dc=float(np.max(np.abs(out["c"] - ref["c"]))) if prob.N else 0.0,
+        grad_rel=rel(out["grad"], ref["grad"]) if prob.M else 0.0,
+        psiN=float(np.max(np.abs(fwd["psiN"] - ref["psiN"]))),
+        dF_fwd=abs((1 - fwd["C_fid"]) - ref["F"]),
+        p=out["p"], n=out["n"], theta=out["theta_max"], theta_ref=ref["theta_max"],
+        drift=out["norm_drift"], L=out["block_len"], nb=out["n_blocks"])
+    say(f"[parity] {name}: " + json.dumps({k: (float(v) if isinstance(v, (float, np.floating)) else v)
+                                           for k, v in errs.items()}))
+    if REPORT:
+        with open(REPORT, "a") as f:
+            f.write(json.dumps({"case": name, "precision": precision, **{
+                k: (float(v) if isinstance(v, (float, np.floating)) else v)
+                for k, v in errs.items()}}) + "\n")
+    return out, ref, errs
+
+
+def check(prob, errs, precision="fp32"):
+    if precision == "fp64":
+        tF, tG, tc = 1e-11, 1e-9, 1e-11
+    else:
+        tF, tG, tc = 1e-6, 1e-4, 2e-6
+    assert errs["dF"] <= tF, errs
+    assert errs["dF_fwd"] <= tF, errs
+    if prob.M:
+        assert errs["grad_rel"] <= tG, errs
+    pen = prob.w is not None
+    if pen:
+        assert errs["dc"] <= tc, errs
+    budget = prob.alpha_fid * tF + (prob.alpha_pen * prob.N * tc if pen else 0.0) + 1e-9
+    assert errs["dC"] <= budget, errs
+    # the GPU chooses (p, n) from its own FP64 theta_max by the same rule
+    assert abs(errs["theta"] - errs["theta_ref"]) <= 1e-12 * max(1.0, errs["theta_ref"]), errs
+
+
+def test_config1_qubit_x_gate():
+    p = workloads.config1()
+    out, ref, e = compare("c1", p)
+    check(p, e)
+    assert (e["p"], e["n"]) == oracle.taylor_select(ref["theta_max"], 1e-10)
+
+
+def test_config2_transmon_cnot_full():
+    p = workloads.config2()
+    out, ref, e = compare("c2", p)
+    check(p, e)
+    assert (e["p"], e["n"]) == oracle.taylor_select(ref["theta_max"], 1e-10)
+
+
+@pytest.mark.parametrize("d,S,N,mode", [
+    (5, 1, 37, "coherent"),        # ragged d (pad 16), ragged N
+    (5, 5, 40, "coherent"),        # full unitary: rank compression in the adjoint
+    (20, 3, 100, "incoherent"),    # pad 32, incoherent fidelity
+    (64, 2, 70, "coherent"),       # 64-tiled product kernels
+    (70, 4, 33, "coherent"),       # pad 80, 16-tiled kernels on a non-64 multiple
+    (3, 2, 1, "coherent"),         # a single step
+])
+def test_random_problems(d, S, N, mode):
+    rng = np.random.default_rng(100 + d + N)
+    p = workloads.random_problem(rng, d=d, M=3, N=N, S=S, dt=0.2, scale=2.0, fid_mode=mode)
+    out, ref, e = compare(f"rand_d{d}_S{S}_N{N}_{mode}", p)
+    check(p, e)
+
+
+@pytest.mark.parametrize("L", [1, 2, 8, 64])
+def test_checkpoint_interval_does_not_change_results(L):
+    rng = np.random.default_rng(7)
+    p = workloads.random_problem(rng, d=12, M=2, N=50, S=2, dt=0.3, scale=1.5)
+    out, ref, e = compare(f"ckpt_L{L}", p, checkpoint_every=L)
+    check(p, e)
+    assert e["L"] == L
+
+
+def test_fixed_taylor_parameters():
+    p = workloads.config2().with_steps(400)
+    out, ref, e = compare("c2_fixed_pn", p, taylor_pn=(12, 2))
+    check(p, e)
+    assert (e["p"], e["n"]) == (12, 2)
+
+
+def test_no_controls_and_no_penalty():
+    rng = np.random.default_rng(11)
+    p = workloads.random_problem(rng, d=6, M=0, N=20, S=2, with_penalty=False)
+    out, ref, e = compare("rand_M0", p)
+    check(p, e)
+
+
+def test_fp64_chains_match_oracle_tightly():
+    p = workloads.config2().with_steps(500)
+    out, ref, e = compare("c2_fp64", p, precision="fp64")
+    check(p, e, precision="fp64")
+    rng = np.random.default_rng(12)
+    q = workloads.random_problem(rng, d=70, M=2, N=20, S=3, dt=0.3, scale=2.0)
+    out, ref, e = compare("rand_d70_fp64", q, precision="fp64")
+    check(q, e, precision="fp64")
+
+
+def test_config3_transmon_cavity_reduced_steps():
+    p = workloads.config3().with_steps(800)
+    out, ref, e = compare("c3_N800", p)
+    check(p, e)
+
+
+def test_config4_spin_chain_reduced_steps():
+    p = workloads.config4().with_steps(24)
+    out, ref, e = compare("c4_N24", p)
+    check(p, e)
+
+
+def test_directional_derivative_fp64_gpu():
+    """Central difference of the GPU cost along a random direction equals
+    <grad, v> (FP64 chains), at the full two-transmon size."""
+    p = workloads.config2()
+    h = qoc.Problem(p, precision="fp64", taylor_pn=(10, 2))
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(p.u.shape)
+    g = h.cost_grad(p.u)["grad"]
+    eps = 1e-5
+    cp = h.cost_grad(p.u + eps * v)["C"]
+    cm = h.cost_grad(p.u - eps * v)["C"]
+    fd = (cp - cm) / (2 * eps)
+    an = float(np.sum(g * v))
+    say(f"[parity] fd_direction: fd={fd!r} analytic={an!r}")
+    assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+    h.close()
