@@ -45,21 +45,34 @@ template <typename T> __device__ __forceinline__ CView<const T> cst(CView<T> v) 
   return o;
 }
 
+// A "group" of GW wavefronts works on one time step: GW = 4 (the whole
+// workgroup) for larger d, GW = 1 (each wavefront its own step) for small d
+// where a product has only a few 16x16 tiles.
+template <int GW> __device__ __forceinline__ void grp_sync() {
+  if (GW == 4) {
+    __syncthreads();
+  } else {
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // Out[:, 0:cols] = alpha op(Am) Bin[:, 0:cols] + addS * Add[:, 0:cols]
-// rows and cols multiples of 16, K = inner dimension.  Tiles over 4 waves.
-template <typename T, int OPA>
-__device__ __forceinline__ void wg_thin(CView<const T> Am, CView<const T> Bin, int K, int rows,
-                                        int cols, T alpha, CView<const T> Add, T addS,
-                                        CView<T> Out) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// rows and cols multiples of 16, K = inner dimension.  Tiles over the
+// group's GW waves.
+template <typename T, int OPA, int GW>
+__device__ __forceinline__ void grp_thin(CView<const T> Am, CView<const T> Bin, int K, int rows,
+                                         int cols, T alpha, CView<const T> Add, T addS,
+                                         CView<T> Out) {
+  const int gw = (threadIdx.x >> 6) % GW, lane = threadIdx.x & 63;
   const int tr = rows >> 4, tc = cols >> 4;
-  for (int t = w; t < tr * tc; t += 4) {
+  for (int t = gw; t < tr * tc; t += GW) {
     const int r0 = (t / tc) * 16, c0 = (t % tc) * 16;
     v4<T> cr = vzero<T>(), ci = vzero<T>();
     wave_cgemm16<T, OPA, 0>(Am, Bin, r0, c0, K, cr, ci);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int row = r0 + 4 * (lane >> 4) + v, col = c0 + (lane & 15);
+      const int row = r0 + acc_row<T>(lane, v), col = c0 + (lane & 15);
       T vr = alpha * cr[v], vi = alpha * ci[v];
       if (addS != (T)0) {
         vr += addS * Add.re[(long)row * Add.ld + col];
@@ -73,15 +86,19 @@ __device__ __forceinline__ void wg_thin(CView<const T> Am, CView<const T> Bin, i
 
 constexpr int ADJ_MCHUNK = 32;
 
-template <typename T> __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs<T> a) {
+template <typename T, int GW> __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs<T> a) {
   __shared__ double gsum[4][ADJ_MCHUNK];
+  constexpr int GS = 64 * GW;              // threads per group
+  constexpr int GPB = 4 / GW;              // groups per workgroup
   const int dp = a.dp, S = a.S, p = a.p, n = a.n, R = a.Rcap, M = a.M, N = a.N;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int gt = threadIdx.x % GS, gw = w % GW;
+  const long grp = (long)blockIdx.x * GPB + w / GW, ngrp = (long)gridDim.x * GPB;
   const long plane = (long)dp * dp, mat = 2 * plane, set = 2L * S * dp;
   const long thin = (long)dp * R;
   const int KK = p * R;
   const long big = (long)dp * KK;
-  T *base = a.scratch + (long)blockIdx.x * a.scratch_elems;
+  T *base = a.scratch + grp * a.scratch_elems;
   CView<T> A = cview<T>(base, thin, R);
   CView<T> B = cview<T>(base + 2 * thin, thin, R);
   CView<T> T1 = cview<T>(base + 4 * thin, thin, R);
@@ -93,29 +110,29 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint(AdjointAr
   nullv.im = nullptr;
   nullv.ld = 0;
 
-  for (long j = blockIdx.x; j < N; j += gridDim.x) {
-    for (long e = tid; e < 8 * thin; e += 256) base[e] = (T)0;
-    __syncthreads();
+  for (long j = grp; j < N; j += ngrp) {
+    for (long e = gt; e < 8 * thin; e += GS) base[e] = (T)0;
+    grp_sync<GW>();
     const T *lam = a.lam_buf + j * set;
     const T *psi = a.psi_buf + j * set;
-    for (int e = tid; e < S * dp; e += 256) {
+    for (int e = gt; e < S * dp; e += GS) {
       const int s = e / dp, m = e - (e / dp) * dp;
       A.re[(long)m * R + s] = lam[(long)s * dp + m];
       A.im[(long)m * R + s] = lam[(long)S * dp + (long)s * dp + m];
       B.re[(long)m * R + s] = psi[(long)s * dp + m];
       B.im[(long)m * R + s] = psi[(long)S * dp + (long)s * dp + m];
     }
-    __syncthreads();
+    grp_sync<GW>();
     int r = S;
     // ---- squaring levels, top (n-1) to bottom (0)
     for (int i = n - 1; i >= 0; --i) {
       CView<const T> Dv = cview<const T>(a.Dlev + ((long)i * N + j) * mat, plane, dp);
       const int rr = (r + 15) & ~15;
-      wg_thin<T, 1>(Dv, cst(A), dp, dp, rr, (T)1, cst(A), (T)1, T1);  // A + D^H A
-      wg_thin<T, 0>(Dv, cst(B), dp, dp, rr, (T)1, cst(B), (T)1, T2);  // B + D B
-      __syncthreads();
+      grp_thin<T, 1, GW>(Dv, cst(A), dp, dp, rr, (T)1, cst(A), (T)1, T1);  // A + D^H A
+      grp_thin<T, 0, GW>(Dv, cst(B), dp, dp, rr, (T)1, cst(B), (T)1, T2);  // B + D B
+      grp_sync<GW>();
       if (2 * r <= dp) {
-        for (int e = tid; e < dp * r; e += 256) {
+        for (int e = gt; e < dp * r; e += GS) {
           const int m = e / r, c = e - (e / r) * r;
           const long o = (long)m * R + c;
           A.re[o + r] = T1.re[o];
@@ -126,54 +143,54 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint(AdjointAr
           B.re[o] = T2.re[o];
           B.im[o] = T2.im[o];
         }
-        __syncthreads();
+        grp_sync<GW>();
         r *= 2;
       } else {
         // full form: F = A (U B)^H + (U^H A) B^H, then A = F, B = I
         const int t1 = dp >> 4;
-        for (int t = w; t < t1 * t1; t += 4) {
+        for (int t = gw; t < t1 * t1; t += GW) {
           const int r0 = (t / t1) * 16, c0 = (t % t1) * 16;
           v4<T> cr = vzero<T>(), ci = vzero<T>();
           wave_cgemm16<T, 0, 1>(cst(A), cst(T2), r0, c0, rr, cr, ci);
           wave_cgemm16<T, 0, 1>(cst(T1), cst(B), r0, c0, rr, cr, ci);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int row = r0 + 4 * (lane >> 4) + v, col = c0 + (lane & 15);
+            const int row = r0 + acc_row<T>(lane, v), col = c0 + (lane & 15);
             Abig.re[(long)row * KK + col] = cr[v];
             Abig.im[(long)row * KK + col] = ci[v];
           }
         }
-        __syncthreads();
-        for (long e = tid; e < plane; e += 256) {
+        grp_sync<GW>();
+        for (long e = gt; e < plane; e += GS) {
           const int m = (int)(e / dp), c = (int)(e - (long)m * dp);
           A.re[(long)m * R + c] = Abig.re[(long)m * KK + c];
           A.im[(long)m * R + c] = Abig.im[(long)m * KK + c];
           B.re[(long)m * R + c] = (m == c) ? (T)1 : (T)0;
           B.im[(long)m * R + c] = (T)0;
         }
-        __syncthreads();
+        grp_sync<GW>();
         r = dp;
       }
     }
     // ---- Horner reverse: blocks of width rr packed in Abig / Vbig
     const int rr = (r + 15) & ~15;
     CView<const T> Xv = cview<const T>(a.X + j * mat, plane, dp);
-    for (int e = tid; e < dp * rr; e += 256) {
+    for (int e = gt; e < dp * rr; e += GS) {
       const int m = e / rr, c = e - (e / rr) * rr;
       Vbig.re[(long)m * KK + (p - 1) * rr + c] = B.re[(long)m * R + c];  // V_{p+1} = B
       Vbig.im[(long)m * KK + (p - 1) * rr + c] = B.im[(long)m * R + c];
       Abig.re[(long)m * KK + c] = A.re[(long)m * R + c];                 // At_1 = A
       Abig.im[(long)m * KK + c] = A.im[(long)m * R + c];
     }
-    __syncthreads();
+    grp_sync<GW>();
     for (int t = 0; t < p - 1; ++t) {
       const int kv = p - t;  // V_kv = B + (1/kv) X V_{kv+1}; V_k stored at block k-2
-      wg_thin<T, 0>(Xv, cst(sub(Vbig, (kv - 1) * rr)), dp, dp, rr, (T)(1.0 / kv), cst(B), (T)1,
-                    sub(Vbig, (kv - 2) * rr));
+      grp_thin<T, 0, GW>(Xv, cst(sub(Vbig, (kv - 1) * rr)), dp, dp, rr, (T)(1.0 / kv), cst(B),
+                         (T)1, sub(Vbig, (kv - 2) * rr));
       const int ka = t + 1;  // At_{ka+1} = X^H At_ka / (ka+1); At_k stored at block k-1
-      wg_thin<T, 1>(Xv, cst(sub(Abig, (ka - 1) * rr)), dp, dp, rr, (T)(1.0 / (ka + 1)), nullv,
-                    (T)0, sub(Abig, ka * rr));
-      __syncthreads();
+      grp_thin<T, 1, GW>(Xv, cst(sub(Abig, (ka - 1) * rr)), dp, dp, rr, (T)(1.0 / (ka + 1)),
+                         nullv, (T)0, sub(Abig, ka * rr));
+      grp_sync<GW>();
     }
     // ---- Xbar = Abig Vbig^H (inner p*rr) contracted with H_k
     const int Kin = p * rr;
@@ -184,13 +201,13 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint(AdjointAr
       double part[ADJ_MCHUNK];
 #pragma unroll
       for (int q = 0; q < ADJ_MCHUNK; ++q) part[q] = 0.0;
-      for (int t = w; t < t1 * t1; t += 4) {
+      for (int t = gw; t < t1 * t1; t += GW) {
         const int r0 = (t / t1) * 16, c0 = (t % t1) * 16;
         v4<T> cr = vzero<T>(), ci = vzero<T>();
         wave_cgemm16<T, 0, 1>(cst(Abig), cst(Vbig), r0, c0, Kin, cr, ci);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const long o = (long)(r0 + 4 * (lane >> 4) + v) * dp + c0 + (lane & 15);
+          const long o = (long)(r0 + acc_row<T>(lane, v)) * dp + c0 + (lane & 15);
           const double xr = (double)cr[v], xi = (double)ci[v];
 #pragma unroll
           for (int q = 0; q < ADJ_MCHUNK; ++q) {
@@ -201,34 +218,63 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint(AdjointAr
           }
         }
       }
+      if (GW == 1) {
 #pragma unroll
-      for (int q = 0; q < ADJ_MCHUNK; ++q) {
-        if (q < cnt) {
-          const double v = wave_sum(part[q]);
-          if (lane == 0) gsum[w][q] = v;
+        for (int q = 0; q < ADJ_MCHUNK; ++q) {
+          if (q < cnt) {
+            const double v = wave_sum(part[q]);
+            part[q] = v;
+          }
         }
+        if (lane < cnt) {
+          double g = 0.0;
+#pragma unroll
+          for (int q = 0; q < ADJ_MCHUNK; ++q)
+            if (q == lane) g = part[q];
+          const int k = k0 + lane;
+          const double *uk = a.u + (long)k * N;
+          double reg = 2.0 * a.alpha_amp * uk[j];
+          if (j >= 1) reg += 2.0 * a.alpha_var * (uk[j] - uk[j - 1]);
+          if (j <= N - 2) reg -= 2.0 * a.alpha_var * (uk[j + 1] - uk[j]);
+          a.grad[(long)k * N + j] = two_s * g + reg;
+        }
+        grp_sync<GW>();
+      } else {
+#pragma unroll
+        for (int q = 0; q < ADJ_MCHUNK; ++q) {
+          if (q < cnt) {
+            const double v = wave_sum(part[q]);
+            if (lane == 0) gsum[w][q] = v;
+          }
+        }
+        __syncthreads();
+        if (gt < cnt) {
+          const int k = k0 + gt;
+          const double g = gsum[0][gt] + gsum[1][gt] + gsum[2][gt] + gsum[3][gt];
+          const double *uk = a.u + (long)k * N;
+          double reg = 2.0 * a.alpha_amp * uk[j];
+          if (j >= 1) reg += 2.0 * a.alpha_var * (uk[j] - uk[j - 1]);
+          if (j <= N - 2) reg -= 2.0 * a.alpha_var * (uk[j + 1] - uk[j]);
+          a.grad[(long)k * N + j] = two_s * g + reg;
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      if (tid < cnt) {
-        const int k = k0 + tid;
-        const double g = gsum[0][tid] + gsum[1][tid] + gsum[2][tid] + gsum[3][tid];
-        const double *uk = a.u + (long)k * N;
-        double reg = 2.0 * a.alpha_amp * uk[j];
-        if (j >= 1) reg += 2.0 * a.alpha_var * (uk[j] - uk[j - 1]);
-        if (j <= N - 2) reg -= 2.0 * a.alpha_var * (uk[j + 1] - uk[j]);
-        a.grad[(long)k * N + j] = two_s * g + reg;
-      }
-      __syncthreads();
     }
-    if (M == 0) __syncthreads();
   }
 }
 
+template <typename T> int adjoint_groups_per_block(int dp) { return dp <= 32 ? 4 : 1; }
+
 template <typename T> hipError_t launch_adjoint(const AdjointArgs<T> &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_adjoint<T>, dim3(a.nblocks), dim3(256), 0, st, a);
+  if (adjoint_groups_per_block<T>(a.dp) == 4)
+    hipLaunchKernelGGL((k_adjoint<T, 1>), dim3(a.nblocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_adjoint<T, 4>), dim3(a.nblocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
+template int adjoint_groups_per_block<float>(int);
+template int adjoint_groups_per_block<double>(int);
 template long adjoint_scratch_elems<float>(int, int, int);
 template long adjoint_scratch_elems<double>(int, int, int);
 template hipError_t launch_adjoint<float>(const AdjointArgs<float> &, hipStream_t);

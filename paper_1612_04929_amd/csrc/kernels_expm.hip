@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_stage16(StageArgs<T> a) {
   wave_cgemm16<T, OPA, 0>(A, B, r0, c0, a.dp, cr, ci);
 #pragma unroll
   for (int v = 0; v < 4; ++v)
-    stage_store(a, j, r0 + 4 * (lane >> 4) + v, c0 + (lane & 15), cr[v], ci[v]);
+    stage_store(a, j, r0 + acc_row<T>(lane, v), c0 + (lane & 15), cr[v], ci[v]);
 }
 
 // dp a multiple of 64: one workgroup per 64x64 output tile, LDS-staged,
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_stage64(StageArgs<T> a, long padded) {
     for (int n = 0; n < 2; ++n)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        stage_store(a, j, r0 + wr + 16 * m + 4 * (lane >> 4) + v, c0 + wc + 16 * n + (lane & 15),
+        stage_store(a, j, r0 + wr + 16 * m + acc_row<T>(lane, v), c0 + wc + 16 * n + (lane & 15),
                     acc[m][n][0][v], acc[m][n][1][v]);
 }
 

@@ -7,8 +7,9 @@
 //   F2  sequential over blocks: psi_{(b+1)L} = (I + E_b) psi_{bL} with the
 //       block product E_b = U_{bL+L-1} ... U_{bL} - I (state checkpoints);
 //   F3  parallel over blocks and columns: replay psi_j inside each block
-//       from its checkpoint, per-step penalties c_j (Table I, C5), and the
-//       block-local penalty costate mu_b;
+//       from its checkpoint, and the block-local penalty costate mu_b
+//       (the per-step penalties c_j of Table I, C5, are then reduced in
+//       parallel over all steps by k_pen);
 //   cost: fidelity overlap in FP64 and the final costate lambda_N;
 //   B2  sequential over blocks: lambda_{bL} = (I + E_b)^H lambda_{(b+1)L} + mu_b;
 //   B3  parallel over blocks and columns: lambda_{j+1} for every step, the
@@ -122,59 +123,33 @@ template <typename T> __global__ __launch_bounds__(256) void k_fwd_blocks(SweepA
 template <typename T> __global__ __launch_bounds__(256) void k_fwd_replay(SweepArgs<T> a) {
   extern __shared__ unsigned char shraw[];
   T *buf = (T *)shraw;
-  __shared__ double red[4];
   const int dp = a.dp, S = a.S;
   const int b = blockIdx.x / S, s = blockIdx.x - (blockIdx.x / S) * S;
   const long set = 2L * S * dp, mat = 2L * dp * dp;
   const int start = b * a.L, end = min(a.N, start + a.L);
   T *xr = buf, *xi = buf + dp, *yr = buf + 2 * dp, *yi = buf + 3 * dp;
   const T *c = a.ckpt + (long)b * set;
-  double pen = 0.0, nrm = 0.0;
   for (int m = threadIdx.x; m < dp; m += blockDim.x) {
     const T vr = set_re(c, S, dp, s)[m], vi = set_im(c, S, dp, s)[m];
     xr[m] = vr; xi[m] = vi;
     set_rew(a.psi_buf + (long)start * set, S, dp, s)[m] = vr;
     set_imw(a.psi_buf + (long)start * set, S, dp, s)[m] = vi;
-    const double q = (double)vr * vr + (double)vi * vi;
-    nrm += q;
-    if (a.w64) pen += a.w64[m] * q;
   }
-  nrm = block_sum(nrm, red);
-  if (a.w64) {
-    pen = block_sum(pen, red);
-    if (start >= 1 && threadIdx.x == 0) a.c_part[(long)start * S + s] = pen;
-  }
-  double drift = 0.0;
   __syncthreads();
   for (int j = start; j < end; ++j) {
     const T *D = a.D + (long)j * mat;
     mv_plus(D, D + (long)dp * dp, dp, xr, xi, yr, yi);
     __syncthreads();
-    const bool store = (j + 1 < end) || (j + 1 == a.N);
-    double p2 = 0.0, n2 = 0.0;
-    for (int m = threadIdx.x; m < dp; m += blockDim.x) {
-      const T vr = yr[m], vi = yi[m];
-      if (store) {
-        set_rew(a.psi_buf + (long)(j + 1) * set, S, dp, s)[m] = vr;
-        set_imw(a.psi_buf + (long)(j + 1) * set, S, dp, s)[m] = vi;
+    if ((j + 1 < end) || (j + 1 == a.N)) {
+      for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+        set_rew(a.psi_buf + (long)(j + 1) * set, S, dp, s)[m] = yr[m];
+        set_imw(a.psi_buf + (long)(j + 1) * set, S, dp, s)[m] = yi[m];
       }
-      const double q = (double)vr * vr + (double)vi * vi;
-      n2 += q;
-      if (a.w64) p2 += a.w64[m] * q;
     }
-    n2 = block_sum(n2, red);
-    if (a.w64) {
-      p2 = block_sum(p2, red);
-      if (store && threadIdx.x == 0) a.c_part[(long)(j + 1) * S + s] = p2;
-    }
-    drift = fmax(drift, fabs(n2 - nrm));
-    nrm = n2;
     T *tr = xr, *ti = xi;
     xr = yr; xi = yi; yr = tr; yi = ti;
     __syncthreads();
   }
-  if (threadIdx.x == 0)
-    atomicMax(a.drift_bits, (unsigned long long)__double_as_longlong(drift));
   if (!a.pw) return;  // block-uniform
   // block-local penalty costate from zero at the block end:
   // mu <- mu + D_j^H mu + pw o psi_j   (penalty only for j >= 1)

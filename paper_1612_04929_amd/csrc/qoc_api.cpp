@@ -260,8 +260,10 @@ template <typename T> qoc_status ensure_levels(qoc_handle *h, int levels) {
 }
 
 template <typename T> qoc_status ensure_adjoint(qoc_handle *h, int p, int Rcap) {
+  const int gpb = qoc::adjoint_groups_per_block<T>(h->dp);
+  h->adj_blocks = std::min((h->N + gpb - 1) / gpb, 1024);
   const long per = qoc::adjoint_scratch_elems<T>(h->dp, p, Rcap);
-  const long total = per * (long)h->adj_blocks;
+  const long total = per * (long)h->adj_blocks * gpb;
   if (total <= h->adj_elems_alloc) return QOC_OK;
   dfree(h, &h->adj, (size_t)h->adj_elems_alloc * sizeof(T));
   h->adj_elems_alloc = 0;
@@ -442,26 +444,28 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   sw.c_part = h->c_part; sw.drift_bits = h->bits + 1; sw.psiT64 = h->psiT64; sw.u = u_dev;
   sw.alpha_fid = h->a_fid; sw.alpha_pen = h->a_pen; sw.alpha_amp = h->a_amp;
   sw.alpha_var = h->a_var; sw.fid_mode = h->fid_mode; sw.out = out_dev; sw.zinfo = h->zinfo;
+  const bool small = qoc::small_sweep_ok<T>(dp, S);
   {
     PhaseTimer tm(h, QOC_PHASE_FWD_BLOCKS, st);
-    HIP_TRY(qoc::launch_fwd_blocks<T>(sw, st));
+    HIP_TRY(small ? qoc::launch_small_sweep<T>(0, sw, st) : qoc::launch_fwd_blocks<T>(sw, st));
   }
   {
     PhaseTimer tm(h, QOC_PHASE_FWD_REPLAY, st);
-    HIP_TRY(qoc::launch_fwd_replay<T>(sw, st));
+    HIP_TRY(small ? qoc::launch_small_sweep<T>(1, sw, st) : qoc::launch_fwd_replay<T>(sw, st));
   }
   {
     PhaseTimer tm(h, QOC_PHASE_COST, st);
+    HIP_TRY(qoc::launch_pen<T>(sw, st));
     HIP_TRY(qoc::launch_cost<T>(sw, st));
   }
   if (!want_grad) return QOC_OK;
   {
     PhaseTimer tm(h, QOC_PHASE_BWD_BLOCKS, st);
-    HIP_TRY(qoc::launch_bwd_blocks<T>(sw, st));
+    HIP_TRY(small ? qoc::launch_small_sweep<T>(2, sw, st) : qoc::launch_bwd_blocks<T>(sw, st));
   }
   {
     PhaseTimer tm(h, QOC_PHASE_BWD_PAIRS, st);
-    HIP_TRY(qoc::launch_bwd_pairs<T>(sw, st));
+    HIP_TRY(small ? qoc::launch_small_sweep<T>(3, sw, st) : qoc::launch_bwd_pairs<T>(sw, st));
   }
   if (M > 0) {
     PhaseTimer tm(h, QOC_PHASE_ADJOINT, st);

@@ -21,12 +21,22 @@ template <> struct V4T<double> { typedef f64x4 type; };
 template <typename T> using v4 = typename V4T<T>::type;
 
 // D(16x16) += A(16x4) B(4x16).  Operand layout: lane l holds A[l%16][l/16]
-// and B[l/16][l%16]; result register v of lane l is D[4*(l/16)+v][l%16].
+// and B[l/16][l%16].  Result register v of lane l holds column l%16 and row
+// acc_row<T>(l, v): 4*(l/16)+v for the FP32 instruction, 4*v+(l/16) for the
+// FP64 one (checked on the device).
 __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ f64x4 mfma4(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int v);
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int v) {
+  return 4 * (lane >> 4) + v;
+}
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int v) {
+  return 4 * v + (lane >> 4);
 }
 
 template <typename T> __device__ __forceinline__ v4<T> vzero() {

@@ -63,6 +63,12 @@ template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStr
 template <typename T> hipError_t launch_cost(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_bwd_blocks(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStream_t st);
+// Small padded d (<= 64): all columns per workgroup, prefetched step matrices.
+// which: 0 = F2, 1 = F3, 2 = B2, 3 = B3.
+template <typename T> bool small_sweep_ok(int dp, int S);
+template <typename T> hipError_t launch_small_sweep(int which, const SweepArgs<T> &a, hipStream_t st);
+// Per-step penalties c_j (FP64) and the norm drift, parallel over (j, s).
+template <typename T> hipError_t launch_pen(const SweepArgs<T> &a, hipStream_t st);
 
 // Exact per-step derivative of the Taylor + squaring evaluation, contracted
 // with the control Hamiltonians (see kernels_adjoint.hip).
@@ -76,11 +82,13 @@ template <typename T> struct AdjointArgs {
   const double *u;     // M x N
   double s_scale;      // dt / 2^n
   double alpha_amp, alpha_var;
-  T *scratch;          // nblocks x scratch_elems
+  T *scratch;          // nblocks x groups_per_block x scratch_elems
   long scratch_elems;
   double *grad;        // M x N
 };
 template <typename T> long adjoint_scratch_elems(int dp, int p, int Rcap);
+// Time steps processed concurrently per workgroup (one per wave for small d).
+template <typename T> int adjoint_groups_per_block(int dp);
 template <typename T> hipError_t launch_adjoint(const AdjointArgs<T> &a, hipStream_t st);
 
 }  // namespace qoc
