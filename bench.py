@@ -29,7 +29,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_work(prob, info, phase, calls, precision):
+def algorithmic_work(prob, info, phase, calls, precision, steps_timed=1):
     """(bound, algorithmic units per launch) for one timed kernel phase.
 
     Complex d x d x d product = 8 d^3 real flops; streaming one step
@@ -39,7 +39,10 @@ def algorithmic_work(prob, info, phase, calls, precision):
     p, n, L = info["p"], info["n"], info["block_len"]
     esz = 8 if precision == "fp64" else 4
     if phase == "taylor":
-        return "mfma", N * 8.0 * d ** 3
+        # p - 1 + n complex products per step, spread over the launches
+        G = p - 1 + n
+        per_call = max(calls // max(steps_timed, 1), 1)
+        return "mfma", N * 8.0 * d ** 3 * G / per_call
     if phase == "blockprod":
         total = (N - info["n_blocks"]) * 8.0 * d ** 3
         return "mfma", total / max(calls, 1)
@@ -197,7 +200,7 @@ def main():
                                avg_launch_ms=tms / calls)
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     bound, units = algorithmic_work(prob, info, dom, kernels[dom]["launches"] * args.steps,
-                                    args.precision)
+                                    args.precision, args.steps)
     avg_s = kernels[dom]["avg_launch_ms"] / 1e3
     if bound == "hbm":
         achieved, peak, unit = units / avg_s / 1e9, HBM_PEAK / 1e9, "GB/s"
@@ -206,7 +209,8 @@ def main():
     roofline = dict(kernel=dom, bound=bound, achieved=achieved, peak=peak, unit=unit,
                     frac=achieved / peak, traffic=None)
     for k, v in kernels.items():
-        b, un = algorithmic_work(prob, info, k, v["launches"] * args.steps, args.precision)
+        b, un = algorithmic_work(prob, info, k, v["launches"] * args.steps, args.precision,
+                                 args.steps)
         s = v["avg_launch_ms"] / 1e3
         v["bound"] = b
         if b == "hbm":

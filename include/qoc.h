@@ -152,7 +152,8 @@ qoc_status qoc_cost_grad_batched(int B, qoc_handle *const *hs,
                                  double *const *out_dev,
                                  double *const *grad_dev, void *stream);
 
-/* Diagnostics of the last call (see qoc_info). */
+/* Diagnostics of the last call (see qoc_info).  Synchronises the handle's
+ * device to read the on-device diagnostics back. */
 qoc_status qoc_get_info(const qoc_handle *h, qoc_info *info);
 
 /* Per-kernel device timing for measurement: when enabled, every kernel

@@ -13,6 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libqoc.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["kernels_expm.hip", "kernels_norm.hip", "kernels_sweep.hip", "kernels_sweep_small.hip",
+           "kernels_expm_small.hip",
+           "kernels_sweep_wave.hip",
            "kernels_adjoint.hip", "qoc_api.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # packed FP32 VALU instructions stay disabled in all device code

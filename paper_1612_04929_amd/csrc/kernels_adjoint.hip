@@ -90,7 +90,9 @@ template <typename T, int GW> __global__ __launch_bounds__(256) void k_adjoint(A
   __shared__ double gsum[4][ADJ_MCHUNK];
   constexpr int GS = 64 * GW;              // threads per group
   constexpr int GPB = 4 / GW;              // groups per workgroup
-  const int dp = a.dp, S = a.S, p = a.p, n = a.n, R = a.Rcap, M = a.M, N = a.N;
+  const int dp = a.dp, S = a.S, R = a.Rcap, M = a.M, N = a.N;
+  const int p = a.pn ? a.pn[0] : a.p, n = a.pn ? a.pn[1] : a.n;
+  const double s_scale = a.pn ? a.sc[0] : a.s_scale;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gt = threadIdx.x % GS, gw = w % GW;
   const long grp = (long)blockIdx.x * GPB + w / GW, ngrp = (long)gridDim.x * GPB;
@@ -126,7 +128,8 @@ template <typename T, int GW> __global__ __launch_bounds__(256) void k_adjoint(A
     int r = S;
     // ---- squaring levels, top (n-1) to bottom (0)
     for (int i = n - 1; i >= 0; --i) {
-      CView<const T> Dv = cview<const T>(a.Dlev + ((long)i * N + j) * mat, plane, dp);
+      const long slot = a.pn ? (long)(n - i) : (long)i;
+      CView<const T> Dv = cview<const T>(a.Dlev + (slot * N + j) * mat, plane, dp);
       const int rr = (r + 15) & ~15;
       grp_thin<T, 1, GW>(Dv, cst(A), dp, dp, rr, (T)1, cst(A), (T)1, T1);  // A + D^H A
       grp_thin<T, 0, GW>(Dv, cst(B), dp, dp, rr, (T)1, cst(B), (T)1, T2);  // B + D B
@@ -195,7 +198,7 @@ template <typename T, int GW> __global__ __launch_bounds__(256) void k_adjoint(A
     // ---- Xbar = Abig Vbig^H (inner p*rr) contracted with H_k
     const int Kin = p * rr;
     const int t1 = dp >> 4;
-    const double two_s = 2.0 * a.s_scale;
+    const double two_s = 2.0 * s_scale;
     for (int k0 = 0; k0 < M; k0 += ADJ_MCHUNK) {
       const int cnt = min(ADJ_MCHUNK, M - k0);
       double part[ADJ_MCHUNK];

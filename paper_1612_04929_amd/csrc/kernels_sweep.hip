@@ -211,26 +211,14 @@ template <typename T> __global__ __launch_bounds__(256) void k_cost(SweepArgs<T>
   zr /= S;
   zi /= S;
   const double F = (a.fid_mode == 0) ? (zr * zr + zi * zi) : Finc / S;
-  double cpen = 0.0;
-  for (int j = 1 + threadIdx.x; j <= N; j += blockDim.x) {
-    double cj = 0.0;
-    if (a.w64)
-      for (int s = 0; s < S; ++s) cj += a.c_part[(long)j * S + s];
-    cj /= S;
-    a.out[2 + j - 1] = cj;
-    cpen += cj;
+  // per-step penalties were written to out[2..] by k_pen, with partial sums
+  double cpen = 0.0, camp = 0.0, cvar = 0.0;
+  for (int q = threadIdx.x; q < a.npart; q += blockDim.x) {
+    cpen += a.part[q];
+    camp += a.part[a.npart + q];
+    cvar += a.part[2 * a.npart + q];
   }
   cpen = block_sum(cpen, red);
-  double camp = 0.0, cvar = 0.0;
-  for (long e = threadIdx.x; e < (long)M * N; e += blockDim.x) {
-    const double x = a.u[e];
-    camp += x * x;
-    const long j = e % N;
-    if (j >= 1) {
-      const double dx = x - a.u[e - 1];
-      cvar += dx * dx;
-    }
-  }
   camp = block_sum(camp, red);
   cvar = block_sum(cvar, red);
   const double Cfid = 1.0 - F;

@@ -1,11 +1,11 @@
 // Latency-oriented sweeps for small Hilbert spaces (padded d <= 64).
 //
 // Same blocked two-level scan as kernels_sweep.hip (F2 / F3 / B2 / B3), but
-// each workgroup carries all S columns at once and the step matrix is
-// staged through LDS with a one-step register prefetch: the global loads of
-// D_{j+1} are issued before the product with D_j, so the HBM latency is
-// off the sequential critical path.  For the costate sweeps the matrix is
-// stored transposed in LDS, so both directions read rows.
+// each workgroup carries all S columns at once and the step matrices are
+// staged through LDS from a register ring that is PD steps ahead: the global
+// loads for step j + PD are issued before the product of step j, so HBM
+// latency is off the sequential critical path.  For the costate sweeps the
+// matrix is stored transposed in LDS, so both directions read rows.
 //
 // Per step: y = x + op(D) x (+ add) for the S columns, op = identity or ^H.
 // Thread t handles output o = t / KC (o = s * DP + m) and the k-chunk
@@ -17,7 +17,9 @@
 namespace qoc {
 
 template <typename T, int DP> struct SmallPlan {
-  static constexpr int PF = (2 * DP * DP + 255) / 256;  // prefetched elements per thread
+  static constexpr int PF = (2 * DP * DP + 255) / 256;  // step-matrix elements per thread
+  static constexpr int PA = 4;                          // state-set elements per thread
+  static constexpr int PD = DP <= 16 ? 8 : (DP <= 32 ? 4 : 2);  // prefetch depth (steps)
   int S, OUT, KC, CH;
   __device__ void init(int S_) {
     S = S_;
@@ -31,41 +33,39 @@ template <typename T, int DP> struct SmallPlan {
   }
 };
 
-template <typename T, int DP>
-__device__ __forceinline__ void sm_prefetch(const T *__restrict__ g, T (&reg)[SmallPlan<T, DP>::PF]) {
+// Ring loads and stores are branch-free so that the compiler's wait counts
+// stay exact (a conditional load makes it wait for every load in flight).
+// Every load is in bounds because the device buffers carry kRingSlack
+// elements of padding and ring indices are clamped.
+template <typename T, int N>
+__device__ __forceinline__ void pf_load(const T *__restrict__ g, T (&reg)[N]) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < SmallPlan<T, DP>::PF; ++q) {
-    const int e = q * 256 + t;
-    reg[q] = (e < 2 * DP * DP) ? g[e] : (T)0;
-  }
+  for (int q = 0; q < N; ++q) reg[q] = g[q * 256 + t];
 }
 
-template <typename T, int DP, bool TRANS>
-__device__ __forceinline__ void sm_store(T *Ds, const T (&reg)[SmallPlan<T, DP>::PF]) {
+template <typename T, int DP, int N, bool TRANS>
+__device__ __forceinline__ void pf_store(T *dst, const T (&reg)[N]) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < SmallPlan<T, DP>::PF; ++q) {
+  for (int q = 0; q < N; ++q) {
     const int e = q * 256 + t;
-    if (e < 2 * DP * DP) {
-      if (TRANS) {
-        const int pl = e / (DP * DP), rem = e - pl * DP * DP;
-        const int r = rem / DP, c = rem - r * DP;
-        Ds[pl * DP * DP + c * DP + r] = reg[q];
-      } else {
-        Ds[e] = reg[q];
-      }
+    if (TRANS) {
+      const int pl = e / (DP * DP), rem = e - pl * DP * DP;
+      const int r = rem / DP, c = rem - r * DP;
+      dst[pl * DP * DP + c * DP + r] = reg[q];
+    } else {
+      dst[e] = reg[q];
     }
   }
 }
 
-// y = x + op(D) x + add, with op(D)[m][k] = Ds[m][k] (CONJ = false) or
-// conj(Ds[m][k]) where Ds holds D^T (CONJ = true).  add (optional) is
-// given per output as (ar, ai) from the caller's registers.
+// y = x + op(D) x (+ wl o add), op(D)[m][k] = Ds[m][k] (CONJ = false) or
+// conj(Ds[m][k]) with Ds holding D^T (CONJ = true); add is a state set in
+// LDS, wl per-level weights in LDS (null: unit weights).
 template <typename T, int DP, bool CONJ>
 __device__ __forceinline__ void sm_apply(const SmallPlan<T, DP> &P, const T *Ds, const T *x,
-                                         T *y, const T *addr_g, const T *addi_g,
-                                         const T *pw, bool use_add) {
+                                         T *y, const T *add, const T *wl) {
   const int t = threadIdx.x;
   const int SD = P.S * DP;
   const T *Dr = Ds, *Di = Ds + DP * DP;
@@ -91,9 +91,10 @@ __device__ __forceinline__ void sm_apply(const SmallPlan<T, DP> &P, const T *Ds,
     }
     if (o < P.OUT && kc == 0) {
       T vr = x[s * DP + m] + sr, vi = x[SD + s * DP + m] + si;
-      if (use_add) {
-        vr += pw[m] * addr_g[s * DP + m];
-        vi += pw[m] * addi_g[s * DP + m];
+      if (add) {
+        const T wgt = wl ? wl[m] : (T)1;
+        vr += wgt * add[s * DP + m];
+        vi += wgt * add[SD + s * DP + m];
       }
       y[s * DP + m] = vr;
       y[SD + s * DP + m] = vi;
@@ -101,140 +102,160 @@ __device__ __forceinline__ void sm_apply(const SmallPlan<T, DP> &P, const T *Ds,
   }
 }
 
+// These kernels always run 256 threads per workgroup.  The constant (and not
+// blockDim.x, which is read from the dispatch packet with a global load)
+// keeps the prefetch ring's loads in flight.
+constexpr int kThreads = 256;
+
 template <typename T>
 __device__ __forceinline__ void copy_set(T *dst, const T *src, int n) {
-  for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
+  for (int e = threadIdx.x; e < n; e += kThreads) dst[e] = src[e];
 }
+
+// Software pipeline over `count` steps: the step matrix (and, with AUX, one
+// state set) of step i + PD is loaded into registers while step i runs, so
+// global-memory latency stays off the sequential path.  step(i) must end
+// with a barrier after its last LDS read of Ds / As.  The barriers inside
+// the pipeline order LDS only (lds_barrier), so loads in flight stay in
+// flight; the global stores a step makes are read only by later kernels.
+template <typename T, int DP, bool TRANS, bool AUX, class DPtr, class APtr, class Step>
+__device__ __forceinline__ void sm_pipeline(int count, DPtr dptr, APtr aptr, T *Ds, T *As,
+                                            Step step) {
+  typedef SmallPlan<T, DP> P;
+  constexpr int PD = P::PD, PF = P::PF, PA = AUX ? P::PA : 1;
+  static_assert(PF * 256 == 2 * DP * DP, "step matrix must fill the ring slot exactly");
+  if (count <= 0) return;
+  T rd[PD][PF];
+  T ra[PD][PA];
+#pragma unroll
+  for (int q = 0; q < PD; ++q) {
+    const int i = q < count ? q : count - 1;
+    pf_load<T, PF>(dptr(i), rd[q]);
+    if (AUX) pf_load<T, PA>(aptr(i), ra[q]);
+  }
+  for (int i0 = 0; i0 < count; i0 += PD) {
+#pragma unroll
+    for (int q = 0; q < PD; ++q) {
+      const int i = i0 + q;
+      if (i < count) {
+        pf_store<T, DP, PF, TRANS>(Ds, rd[q]);
+        if (AUX) pf_store<T, DP, PA, false>(As, ra[q]);
+        lds_barrier();
+        const int nx = (i + PD < count) ? i + PD : count - 1;
+        pf_load<T, PF>(dptr(nx), rd[q]);
+        if (AUX) pf_load<T, PA>(aptr(nx), ra[q]);
+        step(i);
+      }
+    }
+  }
+}
+
+// LDS: Ds (2 DP^2) | x, y (2 S DP each) | As (4 * 256, one full ring slot)
+// | wl (DP)
+#define SM_SETUP                                                   \
+  extern __shared__ unsigned char shraw[];                         \
+  T *Ds = (T *)shraw;                                              \
+  const int set = 2 * a.S * DP;                                    \
+  T *x = Ds + 2 * DP * DP, *y = x + set, *As = y + set;            \
+  T *wl = As + 4 * 256;                                            \
+  SmallPlan<T, DP> P;                                              \
+  P.init(a.S);                                                     \
+  const long mat = 2L * DP * DP;                                   \
+  (void)mat;
 
 // ------------------------------------------------------------------ F2
 template <typename T, int DP> __global__ __launch_bounds__(256) void k_smF2(SweepArgs<T> a) {
-  extern __shared__ unsigned char shraw[];
-  T *Ds = (T *)shraw;
-  T *x = Ds + 2 * DP * DP, *y = x + 2 * a.S * DP;
-  SmallPlan<T, DP> P;
-  P.init(a.S);
-  const int set = 2 * a.S * DP;
-  const long mat = 2L * DP * DP;
-  T reg[SmallPlan<T, DP>::PF];
+  SM_SETUP
   copy_set(x, a.psi0, set);
   copy_set(a.ckpt, a.psi0, set);
-  sm_prefetch<T, DP>(a.E, reg);
-  for (int b = 0; b < a.nb; ++b) {
-    sm_store<T, DP, false>(Ds, reg);
-    __syncthreads();
-    if (b + 1 < a.nb) sm_prefetch<T, DP>(a.E + (b + 1) * mat, reg);
-    sm_apply<T, DP, false>(P, Ds, x, y, nullptr, nullptr, nullptr, false);
-    __syncthreads();
+  __syncthreads();
+  auto dptr = [&](int i) -> const T * { return a.E + i * mat; };
+  auto nop = [&](int) -> const T * { return nullptr; };
+  sm_pipeline<T, DP, false, false>(a.nb, dptr, nop, Ds, As, [&](int b) {
+    sm_apply<T, DP, false>(P, Ds, x, y, nullptr, nullptr);
+    lds_barrier();
     copy_set(a.ckpt + (long)(b + 1) * set, y, set);
     T *tmp = x; x = y; y = tmp;
-  }
+  });
 }
 
 // ------------------------------------------------------------------ F3
 template <typename T, int DP> __global__ __launch_bounds__(256) void k_smF3(SweepArgs<T> a) {
-  extern __shared__ unsigned char shraw[];
-  T *Ds = (T *)shraw;
-  T *x = Ds + 2 * DP * DP, *y = x + 2 * a.S * DP;
-  SmallPlan<T, DP> P;
-  P.init(a.S);
-  const int set = 2 * a.S * DP;
-  const long mat = 2L * DP * DP;
+  SM_SETUP
   const int b = blockIdx.x;
-  const int start = b * a.L, end = min(a.N, start + a.L);
-  T reg[SmallPlan<T, DP>::PF];
+  const int start = b * a.L, end = min(a.N, start + a.L), cnt = end - start;
   copy_set(x, a.ckpt + (long)b * set, set);
   copy_set(a.psi_buf + (long)start * set, a.ckpt + (long)b * set, set);
-  sm_prefetch<T, DP>(a.D + start * mat, reg);
-  for (int j = start; j < end; ++j) {
-    sm_store<T, DP, false>(Ds, reg);
-    __syncthreads();
-    if (j + 1 < end) sm_prefetch<T, DP>(a.D + (j + 1) * mat, reg);
-    sm_apply<T, DP, false>(P, Ds, x, y, nullptr, nullptr, nullptr, false);
-    __syncthreads();
+  if (a.pw) copy_set(wl, a.pw, DP);
+  __syncthreads();
+  auto fptr = [&](int i) -> const T * { return a.D + (start + i) * mat; };
+  auto nop = [&](int) -> const T * { return nullptr; };
+  sm_pipeline<T, DP, false, false>(cnt, fptr, nop, Ds, As, [&](int i) {
+    sm_apply<T, DP, false>(P, Ds, x, y, nullptr, nullptr);
+    lds_barrier();
+    const int j = start + i;
     if (j + 1 < end || j + 1 == a.N) copy_set(a.psi_buf + (long)(j + 1) * set, y, set);
     T *tmp = x; x = y; y = tmp;
-  }
+  });
   if (!a.pw) return;  // block-uniform
-  // block-local penalty costate from zero at the block end (states of this
-  // block were written above by this workgroup):
-  // mu <- mu + D_j^H mu + pw o psi_j   (penalty only for j >= 1)
-  for (int e = threadIdx.x; e < set; e += blockDim.x) x[e] = (T)0;
-  sm_prefetch<T, DP>(a.D + (end - 1) * mat, reg);
+  // block-local penalty costate from zero at the block end, over the states
+  // this workgroup just wrote:  mu <- mu + D_j^H mu + pw o psi_j  (j >= 1)
+  __syncthreads();  // last state copy-out done before x is reused
+  for (int e = threadIdx.x; e < set; e += kThreads) x[e] = (T)0;
   __syncthreads();
-  for (int j = end - 1; j >= start; --j) {
-    sm_store<T, DP, true>(Ds, reg);
-    __syncthreads();
-    if (j - 1 >= start) sm_prefetch<T, DP>(a.D + (j - 1) * mat, reg);
-    const T *ps = a.psi_buf + (long)j * set;
-    sm_apply<T, DP, true>(P, Ds, x, y, ps, ps + a.S * DP, a.pw, j >= 1);
-    __syncthreads();
+  auto bptr = [&](int i) -> const T * { return a.D + (end - 1 - i) * mat; };
+  auto pptr = [&](int i) -> const T * { return a.psi_buf + (long)(end - 1 - i) * set; };
+  sm_pipeline<T, DP, true, true>(cnt, bptr, pptr, Ds, As, [&](int i) {
+    const int j = end - 1 - i;
+    sm_apply<T, DP, true>(P, Ds, x, y, j >= 1 ? As : nullptr, wl);
+    lds_barrier();
     T *tmp = x; x = y; y = tmp;
-  }
+  });
   copy_set(a.mu + (long)b * set, x, set);
 }
 
 // ------------------------------------------------------------------ B2
 template <typename T, int DP> __global__ __launch_bounds__(256) void k_smB2(SweepArgs<T> a) {
-  extern __shared__ unsigned char shraw[];
-  T *Ds = (T *)shraw;
-  T *x = Ds + 2 * DP * DP, *y = x + 2 * a.S * DP;
-  SmallPlan<T, DP> P;
-  P.init(a.S);
-  const int set = 2 * a.S * DP;
-  const long mat = 2L * DP * DP;
-  T reg[SmallPlan<T, DP>::PF];
+  SM_SETUP
   copy_set(x, a.lam_ckpt + (long)a.nb * set, set);
-  if (a.nb >= 2) sm_prefetch<T, DP>(a.E + (a.nb - 1) * mat, reg);
-  for (int b = a.nb - 1; b >= 1; --b) {
-    sm_store<T, DP, true>(Ds, reg);
-    __syncthreads();
-    if (b - 1 >= 1) sm_prefetch<T, DP>(a.E + (b - 1) * mat, reg);
-    const T *mu = a.mu ? a.mu + (long)b * set : nullptr;
-    T *yy = y;
-    if (mu) {
-      // y = x + E^H x + mu : use the add path with unit weights via pw = null
-      sm_apply<T, DP, true>(P, Ds, x, yy, nullptr, nullptr, nullptr, false);
-      __syncthreads();
-      for (int e = threadIdx.x; e < set; e += blockDim.x) yy[e] += mu[e];
-    } else {
-      sm_apply<T, DP, true>(P, Ds, x, yy, nullptr, nullptr, nullptr, false);
-    }
-    __syncthreads();
-    copy_set(a.lam_ckpt + (long)b * set, yy, set);
+  __syncthreads();
+  // steps b = nb-1 .. 1:  lambda_{bL} = lambda + E_b^H lambda + mu_b
+  auto dptr = [&](int i) -> const T * { return a.E + (a.nb - 1 - i) * mat; };
+  auto mptr = [&](int i) -> const T * {
+    return a.mu ? a.mu + (long)(a.nb - 1 - i) * set : a.lam_ckpt;  // dummy when no penalty
+  };
+  sm_pipeline<T, DP, true, true>(a.nb - 1, dptr, mptr, Ds, As, [&](int i) {
+    sm_apply<T, DP, true>(P, Ds, x, y, a.mu ? As : nullptr, nullptr);
+    lds_barrier();
+    copy_set(a.lam_ckpt + (long)(a.nb - 1 - i) * set, y, set);
     T *tmp = x; x = y; y = tmp;
-  }
+  });
 }
 
 // ------------------------------------------------------------------ B3
 template <typename T, int DP> __global__ __launch_bounds__(256) void k_smB3(SweepArgs<T> a) {
-  extern __shared__ unsigned char shraw[];
-  T *Ds = (T *)shraw;
-  T *x = Ds + 2 * DP * DP, *y = x + 2 * a.S * DP;
-  SmallPlan<T, DP> P;
-  P.init(a.S);
-  const int set = 2 * a.S * DP;
-  const long mat = 2L * DP * DP;
+  SM_SETUP
   const int b = blockIdx.x;
   const int start = b * a.L, end = min(a.N, start + a.L);
-  T reg[SmallPlan<T, DP>::PF];
   copy_set(x, a.lam_ckpt + (long)(b + 1) * set, set);
-  if (end - 1 > start) sm_prefetch<T, DP>(a.D + (end - 1) * mat, reg);
+  if (a.pw) copy_set(wl, a.pw, DP);
   __syncthreads();
-  for (int j = end - 1; j >= start; --j) {
-    copy_set(a.lam_buf + (long)j * set, x, set);  // lambda_{j+1}
-    if (j == start) break;                        // block-uniform
-    sm_store<T, DP, true>(Ds, reg);
-    __syncthreads();
-    if (j - 1 > start) sm_prefetch<T, DP>(a.D + (j - 1) * mat, reg);
-    const T *ps = a.psi_buf + (long)j * set;
-    sm_apply<T, DP, true>(P, Ds, x, y, ps, ps + a.S * DP, a.pw, a.pw != nullptr && j >= 1);
-    __syncthreads();
+  // steps j = end-1 .. start+1: emit lambda_{j+1}, then
+  // lambda_j = lambda_{j+1} + D_j^H lambda_{j+1} + pw o psi_j
+  auto dptr = [&](int i) -> const T * { return a.D + (end - 1 - i) * mat; };
+  auto pptr = [&](int i) -> const T * { return a.psi_buf + (long)(end - 1 - i) * set; };
+  sm_pipeline<T, DP, true, true>(end - 1 - start, dptr, pptr, Ds, As, [&](int i) {
+    const int j = end - 1 - i;
+    copy_set(a.lam_buf + (long)j * set, x, set);
+    sm_apply<T, DP, true>(P, Ds, x, y, (a.pw && j >= 1) ? As : nullptr, wl);
+    lds_barrier();
     T *tmp = x; x = y; y = tmp;
-  }
+  });
+  copy_set(a.lam_buf + (long)start * set, x, set);
 }
 
 template <typename T, int DP> size_t sm_lds_bytes(int S) {
-  return sizeof(T) * (2 * DP * DP + 4 * (size_t)S * DP);
+  return sizeof(T) * (2 * DP * DP + 4 * (size_t)S * DP + 4 * 256 + DP);
 }
 
 template <typename T, int DP> hipError_t sm_launch(int which, const SweepArgs<T> &a, hipStream_t st) {
@@ -250,7 +271,8 @@ template <typename T, int DP> hipError_t sm_launch(int which, const SweepArgs<T>
 
 template <typename T> bool small_sweep_ok(int dp, int S) {
   if (dp > 64 || dp % 16) return false;
-  const size_t bytes = sizeof(T) * (2 * (size_t)dp * dp + 4 * (size_t)S * dp);
+  if (2 * S * dp > 4 * 256) return false;  // one state set per 4 elements per thread
+  const size_t bytes = sizeof(T) * (2 * (size_t)dp * dp + 4 * (size_t)S * dp + 4 * 256 + dp);
   return bytes <= 60 * 1024;
 }
 
@@ -265,45 +287,72 @@ template <typename T> hipError_t launch_small_sweep(int which, const SweepArgs<T
 }
 
 // ------------------------------------------------------------------ penalties
-// c_part[j][s] = sum_m w_m |psi_j^s[m]|^2 (FP64) for j = 1..N and the norm
-// drift max_{j,s} | ||psi_{j+1}^s||^2 - ||psi_j^s||^2 |, all in parallel.
+// One wavefront per step transition j -> j+1 (FP64): c_{j+1} =
+// (1/S) sum_s sum_m w_m |psi_{j+1}^s[m]|^2 written to out, the norm drift
+// max_{j,s} | ||psi_{j+1}^s||^2 - ||psi_j^s||^2 |, and per-workgroup partial
+// sums of the penalties and of the regularisers C3 (|u|^2) and C4 (control
+// variations) for the final reduction in k_cost (deterministic order).
 template <typename T> __global__ __launch_bounds__(256) void k_pen(SweepArgs<T> a) {
-  __shared__ double red[4];
-  const long pairs = (long)a.N * a.S;
-  const int dp = a.dp, S = a.S;
+  __shared__ double red[3][4];
+  __shared__ double dred[4];
+  const int dp = a.dp, S = a.S, N = a.N;
   const long set = 2L * S * dp;
-  double dmax = 0.0;
-  for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < pairs;
-       q += (long)gridDim.x * blockDim.x) {
-    const long j = q / S;            // step j -> j + 1
-    const int s = (int)(q - j * S);
-    const T *p0r = a.psi_buf + j * set + (long)s * dp, *p0i = p0r + (long)S * dp;
-    const T *p1r = a.psi_buf + (j + 1) * set + (long)s * dp, *p1i = p1r + (long)S * dp;
-    double n0 = 0.0, n1 = 0.0, pen = 0.0;
-    for (int m = 0; m < dp; ++m) {
-      const double ar = p0r[m], ai = p0i[m], br = p1r[m], bi = p1i[m];
-      const double q1 = br * br + bi * bi;
-      n0 += ar * ar + ai * ai;
-      n1 += q1;
-      if (a.w64) pen += a.w64[m] * q1;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double cpen = 0.0, dmax = 0.0;
+  for (long j = (long)blockIdx.x * 4 + w; j < N; j += (long)gridDim.x * 4) {
+    double csum = 0.0;
+    for (int s = 0; s < S; ++s) {
+      const T *p0r = a.psi_buf + j * set + (long)s * dp, *p0i = p0r + (long)S * dp;
+      const T *p1r = a.psi_buf + (j + 1) * set + (long)s * dp, *p1i = p1r + (long)S * dp;
+      double n0 = 0.0, n1 = 0.0, pen = 0.0;
+      for (int m = lane; m < dp; m += 64) {
+        const double ar = p0r[m], ai = p0i[m], br = p1r[m], bi = p1i[m];
+        const double q1 = br * br + bi * bi;
+        n0 += ar * ar + ai * ai;
+        n1 += q1;
+        if (a.w64) pen += a.w64[m] * q1;
+      }
+      n0 = wave_sum(n0);
+      n1 = wave_sum(n1);
+      if (a.w64) csum += wave_sum(pen);
+      dmax = fmax(dmax, fabs(n1 - n0));
     }
-    if (a.w64) a.c_part[(j + 1) * S + s] = pen;
-    dmax = fmax(dmax, fabs(n1 - n0));
+    const double cj = csum / S;
+    if (lane == 0) a.out[2 + j] = cj;
+    cpen += cj;
   }
+  double camp = 0.0, cvar = 0.0;
+  const long MN = (long)a.M * N;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < MN; e += (long)gridDim.x * 256) {
+    const double x = a.u[e];
+    camp += x * x;
+    if (e % N >= 1) {
+      const double dx = x - a.u[e - 1];
+      cvar += dx * dx;
+    }
+  }
+  camp = wave_sum(camp);
+  cvar = wave_sum(cvar);
   dmax = wave_max(dmax);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dmax;
+  if (lane == 0) {
+    red[0][w] = cpen;  // identical on all lanes of the wave
+    red[1][w] = camp;
+    red[2][w] = cvar;
+    dred[w] = dmax;
+  }
   __syncthreads();
+  if (threadIdx.x < 3) {
+    const int q = threadIdx.x;
+    a.part[q * gridDim.x + blockIdx.x] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
+  }
   if (threadIdx.x == 0) {
-    double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double m = fmax(fmax(dred[0], dred[1]), fmax(dred[2], dred[3]));
     atomicMax(a.drift_bits, (unsigned long long)__double_as_longlong(m));
   }
 }
 
 template <typename T> hipError_t launch_pen(const SweepArgs<T> &a, hipStream_t st) {
-  const long pairs = (long)a.N * a.S;
-  long blocks = (pairs + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_pen<T>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_pen<T>, dim3(a.npart), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -60,6 +60,11 @@ bool taylor_select(double theta, double tol, int *p_out, int *n_out) {
   return true;
 }
 
+// Capacity of the device-side (p, n) choice on the small-d path.
+constexpr int kSmallNCap = 16, kSmallPCap = 16;
+// Padding (elements) of the state buffers read by fixed-size prefetch slots.
+constexpr size_t kRingSlack = 1024;
+
 int pow2_at_least(long v) {
   int l = 1;
   while (l < v) l <<= 1;
@@ -92,9 +97,12 @@ struct qoc_handle {
   int levels_alloc = 0;
   void *ckpt = nullptr, *lam_ckpt = nullptr, *mu = nullptr;  // (nb+1) sets
   void *psi_buf = nullptr, *lam_buf = nullptr;                // N+1, N sets
-  double *c_part = nullptr;   // (N+1) x S
   unsigned long long *bits = nullptr;  // [theta, drift]
   double *zinfo = nullptr;    // 3 + 2S
+  double *part = nullptr;     // 3 x npart
+  int *pn_dev = nullptr;      // device-side (p, n, status)
+  double *sc_dev = nullptr;   // device-side (dt / 2^n, theta)
+  int npart = 1;
   void *adj = nullptr;
   long adj_elems_alloc = 0;   // total elements
   int adj_blocks = 0;
@@ -155,8 +163,9 @@ void release(qoc_handle *h) {
   void **ptrs[] = {&h->Hf, (void **)&h->H64, (void **)&h->u_dev, (void **)&h->out_dev,
                    (void **)&h->grad_dev, &h->psi0, (void **)&h->psiT64, (void **)&h->w64,
                    &h->pw, &h->X, &h->Qa, &h->Qb, &h->Dlev, &h->ckpt, &h->lam_ckpt, &h->mu,
-                   &h->psi_buf, &h->lam_buf, (void **)&h->c_part, (void **)&h->bits,
-                   (void **)&h->zinfo, &h->adj};
+                   &h->psi_buf, &h->lam_buf, (void **)&h->bits,
+                   (void **)&h->zinfo, (void **)&h->part, (void **)&h->pn_dev,
+                   (void **)&h->sc_dev, &h->adj};
   for (void **p : ptrs)
     if (*p) {
       (void)hipFree(*p);
@@ -294,14 +303,20 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   ALLOC(h->X, (size_t)N * mat * sizeof(T));
   ALLOC(h->Qa, (size_t)N * mat * sizeof(T));
   ALLOC(h->Qb, (size_t)N * mat * sizeof(T));
-  ALLOC(h->ckpt, (size_t)(h->nb + 1) * set * sizeof(T));
-  ALLOC(h->lam_ckpt, (size_t)(h->nb + 1) * set * sizeof(T));
-  if (h->has_pen) ALLOC(h->mu, (size_t)h->nb * set * sizeof(T));
-  ALLOC(h->psi_buf, (size_t)(N + 1) * set * sizeof(T));
-  ALLOC(h->lam_buf, (size_t)N * set * sizeof(T));
-  ALLOC(h->c_part, (size_t)(N + 1) * S * sizeof(double));
+  // state buffers carry kRingSlack elements of padding: the small-d sweeps
+  // load fixed-size ring slots that may run past the last state set
+  const size_t slack = kRingSlack;
+  ALLOC(h->ckpt, ((size_t)(h->nb + 1) * set + slack) * sizeof(T));
+  ALLOC(h->lam_ckpt, ((size_t)(h->nb + 1) * set + slack) * sizeof(T));
+  if (h->has_pen) ALLOC(h->mu, ((size_t)h->nb * set + slack) * sizeof(T));
+  ALLOC(h->psi_buf, ((size_t)(N + 1) * set + slack) * sizeof(T));
+  ALLOC(h->lam_buf, ((size_t)N * set + slack) * sizeof(T));
   ALLOC(h->bits, 2 * sizeof(unsigned long long));
   ALLOC(h->zinfo, (size_t)(3 + 2 * S) * sizeof(double));
+  h->npart = std::max(1, std::min(1024, (N + 3) / 4));
+  ALLOC(h->part, (size_t)3 * h->npart * sizeof(double));
+  ALLOC(h->pn_dev, 4 * sizeof(int));
+  ALLOC(h->sc_dev, 2 * sizeof(double));
 #undef ALLOC
   if (hipHostMalloc((void **)&h->h_u, (size_t)std::max(1, M * N) * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void **)&h->h_out, (size_t)(2 + N + 2 * S * d) * sizeof(double)) !=
@@ -354,13 +369,42 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
                hipStream_t st, bool want_grad) {
   const int dp = h->dp, N = h->N, M = h->M, S = h->S;
   const long mat = 2L * dp * dp;
-  int p, n;
-  // ---- (p, n): fixed, or from theta_max (FP64 norms on the device)
-  {
+  const long lev = (long)N * mat;
+  const bool small_path = qoc::small_expm_ok<T>(dp) && qoc::small_sweep_ok<T>(dp, S);
+  T *X = (T *)h->X, *Qa = (T *)h->Qa, *Qb = (T *)h->Qb;
+  const T *D = nullptr, *E = nullptr;
+  int p = 0, n = 0, Rcap_used = dp;
+  if (small_path) {
+    // ---- no host round trip: (p, n) chosen on the device, fused chains
+    const int n_cap = kSmallNCap, p_cap = kSmallPCap;
+    qoc_status s = ensure_levels<T>(h, n_cap + 1);
+    if (s) return s;
+    if (want_grad && (s = ensure_adjoint<T>(h, p_cap, dp)) != QOC_OK) return s;
     HIP_TRY(qoc::launch_fill<unsigned long long>(h->bits, 2, 0ull, st));
-    PhaseTimer tm(h, QOC_PHASE_NORM, st);
-    HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, st));
-    tm.done();
+    {
+      PhaseTimer tm(h, QOC_PHASE_NORM, st);
+      HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, st));
+      HIP_TRY(qoc::launch_select(h->bits, h->dt, h->tol, n_cap, p_cap, h->fixed_p, h->fixed_n,
+                                 h->pn_dev, h->sc_dev, st));
+    }
+    {
+      PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
+      HIP_TRY(qoc::launch_expm_small<T>((const T *)h->Hf, u_dev, dp, M, N, h->pn_dev, h->sc_dev,
+                                        X, (T *)h->Dlev, st));
+    }
+    D = (const T *)h->Dlev;  // slot 0 = D^(n)
+    {
+      PhaseTimer tm(h, QOC_PHASE_BLOCKPROD, st);
+      HIP_TRY(qoc::launch_blockprod_small<T>(D, dp, N, h->L, h->nb, Qa, st));
+    }
+    E = Qa;
+  } else {
+    // ---- (p, n): fixed, or from theta_max (FP64 norms on the device)
+    HIP_TRY(qoc::launch_fill<unsigned long long>(h->bits, 2, 0ull, st));
+    {
+      PhaseTimer tm(h, QOC_PHASE_NORM, st);
+      HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, st));
+    }
     if (h->fixed_p >= 2) {
       p = h->fixed_p;
       n = h->fixed_n;
@@ -376,18 +420,15 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
         return fail(QOC_ERR_UNSUPPORTED, "no (p, n) meets the tolerance for theta_max = " +
                                              std::to_string(theta));
     }
-  }
-  const int Rraw = (long)S << std::min(n, 30) > dp ? dp : (S << n);
-  const int Rcap = (Rraw + 15) & ~15;
-  qoc_status s = ensure_levels<T>(h, n + 1);
-  if (s) return s;
-  if (want_grad && (s = ensure_adjoint<T>(h, p, std::min(Rcap, dp))) != QOC_OK) return s;
-  h->last_p = p;
-  h->last_n = n;
-  T *X = (T *)h->X, *Qa = (T *)h->Qa, *Qb = (T *)h->Qb, *Dl = (T *)h->Dlev;
-  const long lev = (long)N * mat;
-  // ---- step exponentials: Horner in D-form, then squarings
-  {
+    const int Rraw = (long)S << std::min(n, 30) > dp ? dp : (S << n);
+    Rcap_used = std::min((Rraw + 15) & ~15, dp);
+    qoc_status s = ensure_levels<T>(h, n + 1);
+    if (s) return s;
+    if (want_grad && (s = ensure_adjoint<T>(h, p, Rcap_used)) != QOC_OK) return s;
+    h->last_p = p;
+    h->last_n = n;
+    T *Dl = (T *)h->Dlev;
+    // ---- step exponentials: Horner in D-form, then squarings
     const double sc = std::ldexp(h->dt, -n);
     {
       PhaseTimer tm(h, QOC_PHASE_ASSEMBLE, st);
@@ -412,11 +453,8 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
       PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
       HIP_TRY(qoc::launch_stage<T>(0, a, st));
     }
-  }
-  const T *D = Dl + (long)n * lev;
-  // ---- block products E_b (pairwise tree, D-form: C = A + B + A B)
-  const T *E = D;
-  {
+    D = Dl + (long)n * lev;
+    // ---- block products E_b (pairwise tree, D-form: C = A + B + A B)
     long cnt = N;
     const T *in = D;
     T *outb = Qa;
@@ -441,17 +479,31 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   sw.D = D; sw.E = E; sw.psi0 = (const T *)h->psi0; sw.ckpt = (T *)h->ckpt;
   sw.psi_buf = (T *)h->psi_buf; sw.lam_ckpt = (T *)h->lam_ckpt; sw.mu = (T *)h->mu;
   sw.lam_buf = (T *)h->lam_buf; sw.w64 = h->w64; sw.pw = (const T *)h->pw;
-  sw.c_part = h->c_part; sw.drift_bits = h->bits + 1; sw.psiT64 = h->psiT64; sw.u = u_dev;
+  sw.drift_bits = h->bits + 1; sw.psiT64 = h->psiT64; sw.u = u_dev;
   sw.alpha_fid = h->a_fid; sw.alpha_pen = h->a_pen; sw.alpha_amp = h->a_amp;
   sw.alpha_var = h->a_var; sw.fid_mode = h->fid_mode; sw.out = out_dev; sw.zinfo = h->zinfo;
-  const bool small = qoc::small_sweep_ok<T>(dp, S);
+  sw.part = h->part; sw.npart = h->npart;
+  // sweep kernels: one wavefront (S d_pad <= 64), one workgroup with a
+  // prefetch ring (d_pad <= 64), or the generic streaming kernels
+  const bool wave = qoc::wave_sweep_ok<T>(dp, S);
+  const bool small = !wave && qoc::small_sweep_ok<T>(dp, S);
+  auto sweep = [&](int which) -> hipError_t {
+    if (wave) return qoc::launch_wave_sweep<T>(which, sw, st);
+    if (small) return qoc::launch_small_sweep<T>(which, sw, st);
+    switch (which) {
+      case 0: return qoc::launch_fwd_blocks<T>(sw, st);
+      case 1: return qoc::launch_fwd_replay<T>(sw, st);
+      case 2: return qoc::launch_bwd_blocks<T>(sw, st);
+      default: return qoc::launch_bwd_pairs<T>(sw, st);
+    }
+  };
   {
     PhaseTimer tm(h, QOC_PHASE_FWD_BLOCKS, st);
-    HIP_TRY(small ? qoc::launch_small_sweep<T>(0, sw, st) : qoc::launch_fwd_blocks<T>(sw, st));
+    HIP_TRY(sweep(0));
   }
   {
     PhaseTimer tm(h, QOC_PHASE_FWD_REPLAY, st);
-    HIP_TRY(small ? qoc::launch_small_sweep<T>(1, sw, st) : qoc::launch_fwd_replay<T>(sw, st));
+    HIP_TRY(sweep(1));
   }
   {
     PhaseTimer tm(h, QOC_PHASE_COST, st);
@@ -461,21 +513,22 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   if (!want_grad) return QOC_OK;
   {
     PhaseTimer tm(h, QOC_PHASE_BWD_BLOCKS, st);
-    HIP_TRY(small ? qoc::launch_small_sweep<T>(2, sw, st) : qoc::launch_bwd_blocks<T>(sw, st));
+    HIP_TRY(sweep(2));
   }
   {
     PhaseTimer tm(h, QOC_PHASE_BWD_PAIRS, st);
-    HIP_TRY(small ? qoc::launch_small_sweep<T>(3, sw, st) : qoc::launch_bwd_pairs<T>(sw, st));
+    HIP_TRY(sweep(3));
   }
   if (M > 0) {
     PhaseTimer tm(h, QOC_PHASE_ADJOINT, st);
     qoc::AdjointArgs<T> ad{};
-    ad.N = N; ad.dp = dp; ad.M = M; ad.S = S; ad.p = p; ad.n = n;
-    ad.Rcap = std::min(Rcap, dp); ad.nblocks = h->adj_blocks;
-    ad.X = X; ad.Dlev = Dl; ad.lam_buf = (const T *)h->lam_buf; ad.psi_buf = (const T *)h->psi_buf;
+    ad.N = N; ad.dp = dp; ad.M = M; ad.S = S; ad.p = small_path ? kSmallPCap : p; ad.n = n;
+    ad.Rcap = Rcap_used; ad.nblocks = h->adj_blocks;
+    ad.pn = small_path ? h->pn_dev : nullptr; ad.sc = small_path ? h->sc_dev : nullptr;
+    ad.X = X; ad.Dlev = (const T *)h->Dlev; ad.lam_buf = (const T *)h->lam_buf; ad.psi_buf = (const T *)h->psi_buf;
     ad.Hf = (const T *)h->Hf; ad.u = u_dev; ad.s_scale = std::ldexp(h->dt, -n);
     ad.alpha_amp = h->a_amp; ad.alpha_var = h->a_var; ad.scratch = (T *)h->adj;
-    ad.scratch_elems = qoc::adjoint_scratch_elems<T>(dp, p, ad.Rcap); ad.grad = grad_dev;
+    ad.scratch_elems = qoc::adjoint_scratch_elems<T>(dp, ad.p, ad.Rcap); ad.grad = grad_dev;
     HIP_TRY(qoc::launch_adjoint<T>(ad, st));
   }
   return QOC_OK;
@@ -489,8 +542,19 @@ qoc_status run_any(qoc_handle *h, const double *u_dev, double *out_dev, double *
 
 qoc_status finish_diag(qoc_handle *h, hipStream_t st, int *flags) {
   unsigned long long b[2] = {0, 0};
+  int pn[3] = {0, 0, 0};
   HIP_TRY(hipMemcpyAsync(b, h->bits, sizeof(b), hipMemcpyDeviceToHost, st));
+  const bool small_path = h->prec == QOC_FP64
+                              ? (qoc::small_expm_ok<double>(h->dp) && qoc::small_sweep_ok<double>(h->dp, h->S))
+                              : (qoc::small_expm_ok<float>(h->dp) && qoc::small_sweep_ok<float>(h->dp, h->S));
+  if (small_path) HIP_TRY(hipMemcpyAsync(pn, h->pn_dev, sizeof(pn), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  if (small_path) {
+    h->last_p = pn[0];
+    h->last_n = pn[1];
+    if (pn[2]) return fail(QOC_ERR_UNSUPPORTED, "the (p, n) required by theta_max exceeds the "
+                                                "preallocated capacity of the small-d path");
+  }
   double th, dr;
   std::memcpy(&th, &b[0], 8);
   std::memcpy(&dr, &b[1], 8);
@@ -745,8 +809,34 @@ qoc_status qoc_cost_grad_batched(int B, qoc_handle *const *hs, const double *con
   return QOC_OK;
 }
 
-qoc_status qoc_get_info(const qoc_handle *h, qoc_info *info) {
-  if (!h || !info) return fail(QOC_ERR_ARG, "null argument");
+qoc_status qoc_get_info(const qoc_handle *hc, qoc_info *info) {
+  if (!hc || !info) return fail(QOC_ERR_ARG, "null argument");
+  qoc_handle *h = const_cast<qoc_handle *>(hc);
+  {
+    // refresh from the device (the device-pointer entry points do not read
+    // their diagnostics back)
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(QOC_ERR_DEVICE, "hipSetDevice failed");
+    HIP_TRY(hipDeviceSynchronize());
+    unsigned long long b[2] = {0, 0};
+    HIP_TRY(hipMemcpy(b, h->bits, sizeof(b), hipMemcpyDeviceToHost));
+    std::memcpy(&h->last_theta, &b[0], 8);
+    std::memcpy(&h->last_drift, &b[1], 8);
+    int pn[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpy(pn, h->pn_dev, sizeof(pn), hipMemcpyDeviceToHost));
+    if (pn[0] >= 2 && h->fixed_p == 0 && h->last_p == 0) {
+      h->last_p = pn[0];
+      h->last_n = pn[1];
+    }
+    const bool small_path =
+        h->prec == QOC_FP64
+            ? (qoc::small_expm_ok<double>(h->dp) && qoc::small_sweep_ok<double>(h->dp, h->S))
+            : (qoc::small_expm_ok<float>(h->dp) && qoc::small_sweep_ok<float>(h->dp, h->S));
+    if (small_path && pn[0] >= 2) {
+      h->last_p = pn[0];
+      h->last_n = pn[1];
+    }
+  }
   info->p = h->last_p;
   info->n = h->last_n;
   info->theta_max = h->last_theta;

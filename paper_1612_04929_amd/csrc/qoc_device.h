@@ -176,6 +176,19 @@ __device__ __forceinline__ long xcd_logical_block(long b, long padded) {
   return (b & 7) * per + (b >> 3);
 }
 
+// Workgroup barrier that orders LDS traffic only.  __syncthreads() also
+// waits for every outstanding global-memory operation of the wave (vmcnt
+// covers loads and stores on this architecture), which would drain a
+// register prefetch ring at every step.  Use only where no global-memory
+// visibility between the waves of the workgroup is needed.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  // s_waitcnt lgkmcnt(0), vmcnt and expcnt left at their maxima
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Wave-wide sum (64 lanes) with cross-lane shuffles.
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

@@ -34,6 +34,20 @@ hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, 
 
 template <typename T> hipError_t launch_fill(T *p, long n, T v, hipStream_t st);
 
+// Small padded d (16, 32; 48 in FP32): the whole Taylor + squaring chain of
+// a step in LDS, (p, n, dt/2^n) read from device memory (pn, sc).  Level
+// D^(i) is stored at slot n - i (slot 0 = the final D^(n)).
+template <typename T> bool small_expm_ok(int dp);
+template <typename T>
+hipError_t launch_expm_small(const T *Hf, const double *u, int dp, int M, int N, const int *pn,
+                             const double *sc, T *X, T *Dlev, hipStream_t st);
+template <typename T>
+hipError_t launch_blockprod_small(const T *D, int dp, int N, int L, int nb, T *E, hipStream_t st);
+// (p, n) from theta_max on the device: pn = {p, n, status}, sc = {dt/2^n, theta}.
+hipError_t launch_select(const unsigned long long *theta_bits, double dt, double tol, int n_cap,
+                         int p_cap, int fixed_p, int fixed_n, int *pn, double *sc,
+                         hipStream_t st);
+
 // Blocked two-level sweep.  State sets are [2][S][dp] (re plane of S
 // states, then im plane).  Block b covers steps [b*L, min(N, (b+1)*L)).
 template <typename T> struct SweepArgs {
@@ -48,7 +62,6 @@ template <typename T> struct SweepArgs {
   T *lam_buf;          // N state sets: lambda_{j+1} for step j
   const double *w64;   // dp penalty weights (FP64) or null
   const T *pw;         // dp scaled weights a_pen / S * w or null
-  double *c_part;      // (N+1) x S per-column penalty sums
   unsigned long long *drift_bits;
   // cost
   const double *psiT64;  // S x d interleaved complex targets
@@ -56,7 +69,9 @@ template <typename T> struct SweepArgs {
   double alpha_fid, alpha_pen, alpha_amp, alpha_var;
   int fid_mode;
   double *out;          // [C, C_fid, c_1..c_N]
-  double *zinfo;        // [Re z, Im z, F]
+  double *zinfo;        // [Re z, Im z, F, then Re/Im overlap of each column]
+  double *part;         // 3 x npart partial sums (penalties, |u|^2, variations)
+  int npart;            // workgroups of k_pen
 };
 template <typename T> hipError_t launch_fwd_blocks(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStream_t st);
@@ -67,6 +82,9 @@ template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStre
 // which: 0 = F2, 1 = F3, 2 = B2, 3 = B3.
 template <typename T> bool small_sweep_ok(int dp, int S);
 template <typename T> hipError_t launch_small_sweep(int which, const SweepArgs<T> &a, hipStream_t st);
+// One wavefront holding the whole state set (S * dp <= 64, dp = 16 or 32).
+template <typename T> bool wave_sweep_ok(int dp, int S);
+template <typename T> hipError_t launch_wave_sweep(int which, const SweepArgs<T> &a, hipStream_t st);
 // Per-step penalties c_j (FP64) and the norm drift, parallel over (j, s).
 template <typename T> hipError_t launch_pen(const SweepArgs<T> &a, hipStream_t st);
 
@@ -81,6 +99,8 @@ template <typename T> struct AdjointArgs {
   const T *Hf;         // (M+1) x 2 dp^2 (index 0 = H_0)
   const double *u;     // M x N
   double s_scale;      // dt / 2^n
+  const int *pn;       // if not null: p, n read from here (device-side choice),
+  const double *sc;    //   dt / 2^n from sc[0], and level i at slot n - i
   double alpha_amp, alpha_var;
   T *scratch;          // nblocks x groups_per_block x scratch_elems
   long scratch_elems;
