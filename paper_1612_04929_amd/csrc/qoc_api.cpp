@@ -379,7 +379,9 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     const int n_cap = kSmallNCap, p_cap = kSmallPCap;
     qoc_status s = ensure_levels<T>(h, n_cap + 1);
     if (s) return s;
-    if (want_grad && (s = ensure_adjoint<T>(h, p_cap, dp)) != QOC_OK) return s;
+    if (want_grad && !qoc::adjoint16_ok<T>(dp, p_cap) &&
+        (s = ensure_adjoint<T>(h, p_cap, dp)) != QOC_OK)
+      return s;
     HIP_TRY(qoc::launch_fill<unsigned long long>(h->bits, 2, 0ull, st));
     {
       PhaseTimer tm(h, QOC_PHASE_NORM, st);
@@ -529,7 +531,10 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     ad.Hf = (const T *)h->Hf; ad.u = u_dev; ad.s_scale = std::ldexp(h->dt, -n);
     ad.alpha_amp = h->a_amp; ad.alpha_var = h->a_var; ad.scratch = (T *)h->adj;
     ad.scratch_elems = qoc::adjoint_scratch_elems<T>(dp, ad.p, ad.Rcap); ad.grad = grad_dev;
-    HIP_TRY(qoc::launch_adjoint<T>(ad, st));
+    if (qoc::adjoint16_ok<T>(dp, ad.p))
+      HIP_TRY(qoc::launch_adjoint16<T>(ad, st));
+    else
+      HIP_TRY(qoc::launch_adjoint<T>(ad, st));
   }
   return QOC_OK;
 }

@@ -110,5 +110,9 @@ template <typename T> long adjoint_scratch_elems(int dp, int p, int Rcap);
 // Time steps processed concurrently per workgroup (one per wave for small d).
 template <typename T> int adjoint_groups_per_block(int dp);
 template <typename T> hipError_t launch_adjoint(const AdjointArgs<T> &a, hipStream_t st);
+// Register-resident variant for padded d = 16 (one wavefront per step, no
+// scratch); p_max bounds the Taylor order it may be asked to handle.
+template <typename T> bool adjoint16_ok(int dp, int p_max);
+template <typename T> hipError_t launch_adjoint16(const AdjointArgs<T> &a, hipStream_t st);
 
 }  // namespace qoc
