@@ -267,6 +267,7 @@ template <typename T, int GW> __global__ __launch_bounds__(256) void k_adjoint(A
 }
 
 template <typename T> int adjoint_groups_per_block(int dp) { return dp <= 32 ? 4 : 1; }
+// (the LDS-staged variant for dp >= 64 also runs one step per workgroup)
 
 template <typename T> hipError_t launch_adjoint(const AdjointArgs<T> &a, hipStream_t st) {
   if (adjoint_groups_per_block<T>(a.dp) == 4)

@@ -283,63 +283,6 @@ hipError_t launch_blockprod_small(const T *D, int dp, int N, int L, int nb, T *E
   return hipGetLastError();
 }
 
-// Device-side (p, n) choice from theta_max (same rule as the host's
-// qoc_taylor_select), so a call needs no host round trip.  Writes
-// pn = {p, n, status} and sc = {dt / 2^n, theta_max}; status 1 when the
-// required n or p exceeds the preallocated n_cap / p_cap or no pair meets tol.
-__global__ void k_select(const unsigned long long *theta_bits, double dt, double tol, int n_cap,
-                         int p_cap, int fixed_p, int fixed_n, int *pn, double *sc) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double theta = __longlong_as_double((long long)theta_bits[0]);
-  int bp = 0, bn = 0, bestG = -1;
-  if (fixed_p >= 2) {
-    bp = fixed_p;
-    bn = fixed_n;
-    bestG = 0;
-  } else {
-    for (int n = 0; n < 60; ++n) {
-      const double x = ldexp(theta, -n);
-      double f = 1.0, pw = x;  // pw = x^(p+1) for p = 0 start
-      for (int p = 1; p <= 30; ++p) {
-        f *= (p + 1);
-        pw *= x;
-        if (p >= 2 && ldexp(1.0, n) * pw / f * exp(x) <= tol) {
-          const int G = p - 1 + n;
-          if (bestG < 0 || G < bestG) {
-            bestG = G;
-            bp = p;
-            bn = n;
-          }
-          break;
-        }
-      }
-    }
-  }
-  int status = 0;
-  if (bestG < 0 || !(theta >= 0.0)) {
-    status = 1;
-    bp = 2;
-    bn = 0;
-  } else if (bn > n_cap || bp > p_cap) {
-    status = 1;
-    bn = min(bn, n_cap);
-    bp = min(bp, p_cap);
-  }
-  pn[0] = bp;
-  pn[1] = bn;
-  pn[2] = status;
-  sc[0] = ldexp(dt, -bn);
-  sc[1] = theta;
-}
-
-hipError_t launch_select(const unsigned long long *theta_bits, double dt, double tol, int n_cap,
-                         int p_cap, int fixed_p, int fixed_n, int *pn, double *sc,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, st, theta_bits, dt, tol, n_cap, p_cap,
-                     fixed_p, fixed_n, pn, sc);
-  return hipGetLastError();
-}
-
 template bool small_expm_ok<float>(int);
 template bool small_expm_ok<double>(int);
 template hipError_t launch_expm_small<float>(const float *, const double *, int, int, int,

@@ -22,47 +22,151 @@
 
 namespace qoc {
 
+// 16-byte vector of T (4 floats or 2 doubles) for wide global loads.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+  typedef float4 type;
+  static constexpr int n = 4;
+};
+template <> struct Vec16<double> {
+  typedef double2 type;
+  static constexpr int n = 2;
+};
+template <typename T> __device__ __forceinline__ T vget(const typename Vec16<T>::type &v, int q);
+template <> __device__ __forceinline__ float vget<float>(const float4 &v, int q) {
+  return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+}
+template <> __device__ __forceinline__ double vget<double>(const double2 &v, int q) {
+  return q == 0 ? v.x : v.y;
+}
+
 // y = x + D x, D row-major planar (dp x dp) in global memory, x and y in
-// LDS.  One wavefront per output row, lanes along the row (coalesced).
+// LDS.  Each wavefront takes 8 output rows at a time with the lanes along
+// the rows in 16-byte vectors (coalesced, 8 rows x 2 planes of loads in
+// flight), then reduces the 16 partial sums across the wavefront.  dp is a
+// multiple of 16; the matrices are 16-byte aligned.
 template <typename T>
 __device__ __forceinline__ void mv_plus(const T *__restrict__ Dr, const T *__restrict__ Di,
                                         int dp, const T *xr, const T *xi, T *yr, T *yi) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int m = w; m < dp; m += nw) {
-    T sr = 0, si = 0;
-    for (int k = lane; k < dp; k += 64) {
-      const T dr = Dr[(long)m * dp + k], di = Di[(long)m * dp + k];
-      sr += dr * xr[k] - di * xi[k];
-      si += dr * xi[k] + di * xr[k];
+  typedef typename Vec16<T>::type V;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int RB = 8;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = 4;
+  const int nv = dp / VN;
+  for (int m0 = w * RB; m0 < dp; m0 += nw * RB) {
+    T sr[RB], si[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      sr[q] = 0;
+      si[q] = 0;
     }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    if (lane == 0) {
-      yr[m] = xr[m] + sr;
-      yi[m] = xi[m] + si;
+    for (int kv = lane; kv < nv; kv += 64) {
+      const int k = kv * VN;
+      V dr[RB], di[RB];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        dr[q] = *reinterpret_cast<const V *>(Dr + (long)(m0 + q) * dp + k);
+        di[q] = *reinterpret_cast<const V *>(Di + (long)(m0 + q) * dp + k);
+      }
+#pragma unroll
+      for (int e = 0; e < VN; ++e) {
+        const T a = xr[k + e], b = xi[k + e];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+          const T vr = vget<T>(dr[q], e), vi = vget<T>(di[q], e);
+          sr[q] += vr * a - vi * b;
+          si[q] += vr * b + vi * a;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      sr[q] = wave_sum(sr[q]);
+      si[q] = wave_sum(si[q]);
+    }
+    if (lane < RB) {
+      T vr = 0, vi = 0;
+#pragma unroll
+      for (int q = 0; q < RB; ++q)
+        if (q == lane) {
+          vr = sr[q];
+          vi = si[q];
+        }
+      yr[m0 + lane] = xr[m0 + lane] + vr;
+      yi[m0 + lane] = xi[m0 + lane] + vi;
     }
   }
 }
 
-// y = x + D^H x (+ add), one thread per output row, coalesced along D's rows.
+// y = x + D^H x (+ add).  Thread t owns the VN consecutive output rows of
+// column group t % G (G = dp / VN) and the inner-dimension slice t / G of
+// the 256 / G slices; each reads 16-byte vectors of D's rows (coalesced
+// across the column groups).  Slice partial sums meet in LDS scratch `red`
+// (2 * 256 * VN elements) with one barrier.
 template <typename T>
 __device__ __forceinline__ void mv_plus_adj(const T *__restrict__ Dr, const T *__restrict__ Di,
                                             int dp, const T *xr, const T *xi, T *yr, T *yi,
-                                            const T *addr, const T *addi) {
-  for (int m = threadIdx.x; m < dp; m += blockDim.x) {
-    T sr = 0, si = 0;
-    for (int k = 0; k < dp; ++k) {
-      const T dr = Dr[(long)k * dp + m], di = -Di[(long)k * dp + m];
-      sr += dr * xr[k] - di * xi[k];
-      si += dr * xi[k] + di * xr[k];
+                                            const T *addr, const T *addi, T *red) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VN = Vec16<T>::n;
+  const int t = threadIdx.x;
+  const int G = dp / VN;                       // column groups
+  const int SL = G >= 256 ? 1 : 256 / G;       // inner-dimension slices
+  const int kper = (dp + SL - 1) / SL;
+  for (int g0 = 0; g0 < G; g0 += 256 / SL) {
+    const int cg = g0 + t % (256 / SL), sl = t / (256 / SL);
+    T sr[VN], si[VN];
+#pragma unroll
+    for (int e = 0; e < VN; ++e) {
+      sr[e] = 0;
+      si[e] = 0;
     }
-    T vr = xr[m] + sr, vi = xi[m] + si;
-    if (addr) {
-      vr += addr[m];
-      vi += addi[m];
+    if (cg < G && sl < SL) {
+      const int k0 = sl * kper, k1 = min(dp, k0 + kper);
+      for (int k = k0; k < k1; ++k) {
+        const V dr = *reinterpret_cast<const V *>(Dr + (long)k * dp + cg * VN);
+        const V di = *reinterpret_cast<const V *>(Di + (long)k * dp + cg * VN);
+        const T a = xr[k], b = xi[k];
+#pragma unroll
+        for (int e = 0; e < VN; ++e) {
+          const T vr = vget<T>(dr, e), vi = -vget<T>(di, e);
+          sr[e] += vr * a - vi * b;
+          si[e] += vr * b + vi * a;
+        }
+      }
     }
-    yr[m] = vr;
-    yi[m] = vi;
+    if (SL > 1) {
+#pragma unroll
+      for (int e = 0; e < VN; ++e) {
+        red[(2 * t) * VN + e] = sr[e];
+        red[(2 * t + 1) * VN + e] = si[e];
+      }
+      __syncthreads();
+      if (sl == 0 && cg < G) {
+        for (int s2 = 1; s2 < SL; ++s2) {
+          const int tt = t + s2 * (256 / SL);
+#pragma unroll
+          for (int e = 0; e < VN; ++e) {
+            sr[e] += red[(2 * tt) * VN + e];
+            si[e] += red[(2 * tt + 1) * VN + e];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (sl == 0 && cg < G) {
+#pragma unroll
+      for (int e = 0; e < VN; ++e) {
+        const int m = cg * VN + e;
+        T vr = xr[m] + sr[e], vi = xi[m] + si[e];
+        if (addr) {
+          vr += addr[m];
+          vi += addi[m];
+        }
+        yr[m] = vr;
+        yi[m] = vi;
+      }
+    }
   }
 }
 
@@ -169,7 +273,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_fwd_replay(SweepA
     }
     __syncthreads();
     const T *D = a.D + (long)j * mat;
-    mv_plus_adj(D, D + (long)dp * dp, dp, mr, mi, nr, ni, pr, pi);
+    mv_plus_adj(D, D + (long)dp * dp, dp, mr, mi, nr, ni, pr, pi, buf + 6 * dp);
     __syncthreads();
     T *tr = mr, *ti = mi;
     mr = nr; mi = ni; nr = tr; ni = ti;
@@ -276,7 +380,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_bwd_blocks(SweepA
     const T *E = a.E + (long)b * mat;
     const T *mur = a.mu ? set_re(a.mu + (long)b * set, S, dp, s) : nullptr;
     const T *mui = a.mu ? set_im(a.mu + (long)b * set, S, dp, s) : nullptr;
-    mv_plus_adj(E, E + (long)dp * dp, dp, xr, xi, yr, yi, mur, mui);
+    mv_plus_adj(E, E + (long)dp * dp, dp, xr, xi, yr, yi, mur, mui, buf + 6 * dp);
     __syncthreads();
     T *c = a.lam_ckpt + (long)b * set;
     for (int m = threadIdx.x; m < dp; m += blockDim.x) {
@@ -318,7 +422,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_bwd_pairs(SweepAr
     if (j == start) break;  // lambda_start belongs to the previous block
     __syncthreads();
     const T *D = a.D + (long)j * mat;
-    mv_plus_adj(D, D + (long)dp * dp, dp, xr, xi, yr, yi, pr, pi);
+    mv_plus_adj(D, D + (long)dp * dp, dp, xr, xi, yr, yi, pr, pi, buf + 6 * dp);
     __syncthreads();
     T *tr = xr, *ti = xi;
     xr = yr; xi = yi; yr = tr; yi = ti;
@@ -330,7 +434,7 @@ template <typename T> hipError_t launch_fwd_blocks(const SweepArgs<T> &a, hipStr
   return hipGetLastError();
 }
 template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_fwd_replay<T>, dim3(a.nb * a.S), dim3(256), 6 * a.dp * sizeof(T), st, a);
+  hipLaunchKernelGGL(k_fwd_replay<T>, dim3(a.nb * a.S), dim3(256), 6 * a.dp * sizeof(T) + 8192, st, a);
   return hipGetLastError();
 }
 template <typename T> hipError_t launch_cost(const SweepArgs<T> &a, hipStream_t st) {
@@ -338,11 +442,11 @@ template <typename T> hipError_t launch_cost(const SweepArgs<T> &a, hipStream_t 
   return hipGetLastError();
 }
 template <typename T> hipError_t launch_bwd_blocks(const SweepArgs<T> &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_bwd_blocks<T>, dim3(a.S), dim3(256), 4 * a.dp * sizeof(T), st, a);
+  hipLaunchKernelGGL(k_bwd_blocks<T>, dim3(a.S), dim3(256), 6 * a.dp * sizeof(T) + 8192, st, a);
   return hipGetLastError();
 }
 template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_bwd_pairs<T>, dim3(a.nb * a.S), dim3(256), 6 * a.dp * sizeof(T), st, a);
+  hipLaunchKernelGGL(k_bwd_pairs<T>, dim3(a.nb * a.S), dim3(256), 6 * a.dp * sizeof(T) + 8192, st, a);
   return hipGetLastError();
 }
 

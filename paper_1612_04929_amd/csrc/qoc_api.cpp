@@ -97,13 +97,15 @@ struct qoc_handle {
   int levels_alloc = 0;
   void *ckpt = nullptr, *lam_ckpt = nullptr, *mu = nullptr;  // (nb+1) sets
   void *psi_buf = nullptr, *lam_buf = nullptr;                // N+1, N sets
-  unsigned long long *bits = nullptr;  // [theta, drift]
+  unsigned long long *bits = nullptr;  // [theta, drift, norm ticket, pen ticket]
   double *zinfo = nullptr;    // 3 + 2S
   double *part = nullptr;     // 3 x npart
   int *pn_dev = nullptr;      // device-side (p, n, status)
   double *sc_dev = nullptr;   // device-side (dt / 2^n, theta)
   int npart = 1;
   void *adj = nullptr;
+  double *adj_part = nullptr;  // batched large-d adjoint partial sums
+  long adj_part_alloc = 0;
   long adj_elems_alloc = 0;   // total elements
   int adj_blocks = 0;
   // pinned host staging
@@ -165,7 +167,7 @@ void release(qoc_handle *h) {
                    &h->pw, &h->X, &h->Qa, &h->Qb, &h->Dlev, &h->ckpt, &h->lam_ckpt, &h->mu,
                    &h->psi_buf, &h->lam_buf, (void **)&h->bits,
                    (void **)&h->zinfo, (void **)&h->part, (void **)&h->pn_dev,
-                   (void **)&h->sc_dev, &h->adj};
+                   (void **)&h->sc_dev, &h->adj, (void **)&h->adj_part};
   for (void **p : ptrs)
     if (*p) {
       (void)hipFree(*p);
@@ -269,10 +271,24 @@ template <typename T> qoc_status ensure_levels(qoc_handle *h, int levels) {
 }
 
 template <typename T> qoc_status ensure_adjoint(qoc_handle *h, int p, int Rcap) {
-  const int gpb = qoc::adjoint_groups_per_block<T>(h->dp);
-  h->adj_blocks = std::min((h->N + gpb - 1) / gpb, 1024);
-  const long per = qoc::adjoint_scratch_elems<T>(h->dp, p, Rcap);
-  const long total = per * (long)h->adj_blocks * gpb;
+  long total;
+  if (qoc::adjoint_big_ok<T>(h->dp)) {
+    // batched large-d adjoint: scratch per step, partial sums per tile
+    total = qoc::adjoint_big_scratch_per_step<T>(h->dp, p, Rcap) * (long)h->N;
+    const long rp = (h->dp + 63) / 64;
+    const long parts = (long)h->N * rp * rp * std::max(h->M, 1);
+    if (parts > h->adj_part_alloc) {
+      dfree(h, (void **)&h->adj_part, (size_t)h->adj_part_alloc * sizeof(double));
+      h->adj_part_alloc = 0;
+      qoc_status s = dalloc(h, (void **)&h->adj_part, (size_t)parts * sizeof(double));
+      if (s) return s;
+      h->adj_part_alloc = parts;
+    }
+  } else {
+    const int gpb = qoc::adjoint_groups_per_block<T>(h->dp);
+    h->adj_blocks = std::min((h->N + gpb - 1) / gpb, 1024);
+    total = qoc::adjoint_scratch_elems<T>(h->dp, p, Rcap) * (long)h->adj_blocks * gpb;
+  }
   if (total <= h->adj_elems_alloc) return QOC_OK;
   dfree(h, &h->adj, (size_t)h->adj_elems_alloc * sizeof(T));
   h->adj_elems_alloc = 0;
@@ -311,7 +327,7 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   if (h->has_pen) ALLOC(h->mu, ((size_t)h->nb * set + slack) * sizeof(T));
   ALLOC(h->psi_buf, ((size_t)(N + 1) * set + slack) * sizeof(T));
   ALLOC(h->lam_buf, ((size_t)N * set + slack) * sizeof(T));
-  ALLOC(h->bits, 2 * sizeof(unsigned long long));
+  ALLOC(h->bits, 4 * sizeof(unsigned long long));  // theta, drift, tickets
   ALLOC(h->zinfo, (size_t)(3 + 2 * S) * sizeof(double));
   h->npart = std::max(1, std::min(1024, (N + 3) / 4));
   ALLOC(h->part, (size_t)3 * h->npart * sizeof(double));
@@ -382,12 +398,12 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     if (want_grad && !qoc::adjoint16_ok<T>(dp, p_cap) &&
         (s = ensure_adjoint<T>(h, p_cap, dp)) != QOC_OK)
       return s;
-    HIP_TRY(qoc::launch_fill<unsigned long long>(h->bits, 2, 0ull, st));
+    HIP_TRY(qoc::launch_fill<unsigned long long>(h->bits, 4, 0ull, st));
     {
       PhaseTimer tm(h, QOC_PHASE_NORM, st);
-      HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, st));
-      HIP_TRY(qoc::launch_select(h->bits, h->dt, h->tol, n_cap, p_cap, h->fixed_p, h->fixed_n,
-                                 h->pn_dev, h->sc_dev, st));
+      qoc::SelectArgs sel{h->pn_dev, h->sc_dev, (unsigned *)(h->bits + 2), h->tol, n_cap, p_cap,
+                          h->fixed_p, h->fixed_n};
+      HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, sel, st));
     }
     {
       PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
@@ -402,10 +418,11 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     E = Qa;
   } else {
     // ---- (p, n): fixed, or from theta_max (FP64 norms on the device)
-    HIP_TRY(qoc::launch_fill<unsigned long long>(h->bits, 2, 0ull, st));
+    HIP_TRY(qoc::launch_fill<unsigned long long>(h->bits, 4, 0ull, st));
     {
       PhaseTimer tm(h, QOC_PHASE_NORM, st);
-      HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, st));
+      qoc::SelectArgs sel{};
+      HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, sel, st));
     }
     if (h->fixed_p >= 2) {
       p = h->fixed_p;
@@ -531,8 +548,11 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     ad.Hf = (const T *)h->Hf; ad.u = u_dev; ad.s_scale = std::ldexp(h->dt, -n);
     ad.alpha_amp = h->a_amp; ad.alpha_var = h->a_var; ad.scratch = (T *)h->adj;
     ad.scratch_elems = qoc::adjoint_scratch_elems<T>(dp, ad.p, ad.Rcap); ad.grad = grad_dev;
+    ad.part = h->adj_part;
     if (qoc::adjoint16_ok<T>(dp, ad.p))
       HIP_TRY(qoc::launch_adjoint16<T>(ad, st));
+    else if (qoc::adjoint_big_ok<T>(dp))
+      HIP_TRY(qoc::launch_adjoint_big<T>(ad, st));
     else
       HIP_TRY(qoc::launch_adjoint<T>(ad, st));
   }

@@ -28,9 +28,20 @@ hipError_t launch_assemble(const T *Hf, const double *u, int dp, int M, int N, T
 
 template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hipStream_t st);
 
+// Device-side (p, n) choice made by the last workgroup of the norm kernel
+// (pn = null: no choice).  pn = {p, n, status}, sc = {dt / 2^n, theta};
+// status 1 when the pair exceeds n_cap / p_cap or none meets tol.  `ticket`
+// must be zero at launch.
+struct SelectArgs {
+  int *pn;
+  double *sc;
+  unsigned *ticket;
+  double tol;
+  int n_cap, p_cap, fixed_p, fixed_n;
+};
 // theta_max = max_j ||dt H_j||_1 in FP64 (atomic max on the bit pattern).
 hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, double dt,
-                       unsigned long long *theta_bits, hipStream_t st);
+                       unsigned long long *theta_bits, const SelectArgs &sel, hipStream_t st);
 
 template <typename T> hipError_t launch_fill(T *p, long n, T v, hipStream_t st);
 
@@ -43,10 +54,6 @@ hipError_t launch_expm_small(const T *Hf, const double *u, int dp, int M, int N,
                              const double *sc, T *X, T *Dlev, hipStream_t st);
 template <typename T>
 hipError_t launch_blockprod_small(const T *D, int dp, int N, int L, int nb, T *E, hipStream_t st);
-// (p, n) from theta_max on the device: pn = {p, n, status}, sc = {dt/2^n, theta}.
-hipError_t launch_select(const unsigned long long *theta_bits, double dt, double tol, int n_cap,
-                         int p_cap, int fixed_p, int fixed_n, int *pn, double *sc,
-                         hipStream_t st);
 
 // Blocked two-level sweep.  State sets are [2][S][dp] (re plane of S
 // states, then im plane).  Block b covers steps [b*L, min(N, (b+1)*L)).
@@ -105,6 +112,7 @@ template <typename T> struct AdjointArgs {
   T *scratch;          // nblocks x groups_per_block x scratch_elems
   long scratch_elems;
   double *grad;        // M x N
+  double *part;        // batched variant: N x tiles x M partial sums
 };
 template <typename T> long adjoint_scratch_elems(int dp, int p, int Rcap);
 // Time steps processed concurrently per workgroup (one per wave for small d).
@@ -113,6 +121,12 @@ template <typename T> hipError_t launch_adjoint(const AdjointArgs<T> &a, hipStre
 // Register-resident variant for padded d = 16 (one wavefront per step, no
 // scratch); p_max bounds the Taylor order it may be asked to handle.
 template <typename T> bool adjoint16_ok(int dp, int p_max);
+// Batched variant for padded d >= 64: one launch per stage of the reverse
+// recurrence over all N steps; scratch is per step (N x per_step elements)
+// and `part` holds N x tiles x M partial sums.  (p, n) must be host-known.
+template <typename T> bool adjoint_big_ok(int dp);
+template <typename T> long adjoint_big_scratch_per_step(int dp, int p, int Rcap);
+template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_adjoint16(const AdjointArgs<T> &a, hipStream_t st);
 
 }  // namespace qoc
