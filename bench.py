@@ -21,7 +21,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "cost+grad time-steps/sec vs plain FP64 GPU path at |ΔF|≤1e-6, d=16–512"
-PEAK = {"fp32": {"mfma": 157.3e12, "alu": 157.3e12 / 2}, "fp64": {"mfma": 78.6e12, "alu": 78.6e12}}
+# Dense MFMA peaks.  bf16x3 executes three bf16 products per FP32-equivalent
+# product, so its FP32-equivalent peak is the bf16 peak over 3.
+PEAK = {"fp32": {"mfma": 157.3e12, "alu": 157.3e12 / 2}, "fp64": {"mfma": 78.6e12, "alu": 78.6e12},
+        "bf16x3": {"mfma": 2.5e15 / 3, "alu": 157.3e12 / 2}}
+BF3_PHASES = ("taylor", "blockprod")  # phases that run bf16x3 products (padded d % 64 == 0)
 HBM_PEAK = 8.0e12
 
 
@@ -37,7 +41,7 @@ def algorithmic_work(prob, info, phase, calls, precision, steps_timed=1):
     """
     d, N, M, S = prob.d, prob.N, prob.M, prob.S
     p, n, L = info["p"], info["n"], info["block_len"]
-    esz = 8 if precision == "fp64" else 4
+    esz = 8 if precision == "fp64" else 4  # bf16x3 keeps FP32 storage
     if phase == "taylor":
         # p - 1 + n complex products per step, spread over the launches
         G = p - 1 + n
@@ -143,7 +147,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-torch-baseline", action="store_true")
@@ -202,10 +206,16 @@ def main():
     bound, units = algorithmic_work(prob, info, dom, kernels[dom]["launches"] * args.steps,
                                     args.precision, args.steps)
     avg_s = kernels[dom]["avg_launch_ms"] / 1e3
+    def peak_of(phase, b):
+        prec = args.precision
+        if prec == "bf16x3" and not (phase in BF3_PHASES and info["d_pad"] % 64 == 0):
+            prec = "fp32"
+        return PEAK[prec][b]
+
     if bound == "hbm":
         achieved, peak, unit = units / avg_s / 1e9, HBM_PEAK / 1e9, "GB/s"
     else:
-        achieved, peak, unit = units / avg_s / 1e12, PEAK[args.precision][bound] / 1e12, "TFLOP/s"
+        achieved, peak, unit = units / avg_s / 1e12, peak_of(dom, bound) / 1e12, "TFLOP/s"
     roofline = dict(kernel=dom, bound=bound, achieved=achieved, peak=peak, unit=unit,
                     frac=achieved / peak, traffic=None)
     for k, v in kernels.items():

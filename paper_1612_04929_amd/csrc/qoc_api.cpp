@@ -76,6 +76,7 @@ int pow2_at_least(long v) {
 struct qoc_handle {
   // problem
   int d = 0, dp = 0, M = 0, N = 0, S = 0, prec = QOC_FP32, fid_mode = 0;
+  int bf3 = 0;  // bf16x3 split products in the batched chains (padded d >= 64)
   double dt = 0, a_fid = 0, a_amp = 0, a_var = 0, a_pen = 0, tol = 0, drift_warn = 0;
   bool has_pen = false;
   int fixed_p = 0, fixed_n = 0;
@@ -456,19 +457,19 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     }
     T *cur = Qa, *nxt = Qb;
     for (int k = p - 1; k >= 2; --k) {
-      qoc::StageArgs<T> a{X, mat, cur, mat, nxt, mat, N, dp, (T)(1.0 / k), (T)0, (T)0, (T)1};
+      qoc::StageArgs<T> a{X, mat, cur, mat, nxt, mat, N, dp, (T)(1.0 / k), (T)0, (T)0, (T)1, h->bf3};
       PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
       HIP_TRY(qoc::launch_stage<T>(0, a, st));
       std::swap(cur, nxt);
     }
     {
-      qoc::StageArgs<T> a{X, mat, cur, mat, Dl, mat, N, dp, (T)1, (T)0, (T)0, (T)0};
+      qoc::StageArgs<T> a{X, mat, cur, mat, Dl, mat, N, dp, (T)1, (T)0, (T)0, (T)0, h->bf3};
       PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
       HIP_TRY(qoc::launch_stage<T>(0, a, st));
     }
     for (int i = 0; i < n; ++i) {
       qoc::StageArgs<T> a{Dl + i * lev, mat, Dl + i * lev, mat, Dl + (i + 1) * lev, mat, N, dp,
-                          (T)1, (T)0, (T)2, (T)0};
+                          (T)1, (T)0, (T)2, (T)0, h->bf3};
       PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
       HIP_TRY(qoc::launch_stage<T>(0, a, st));
     }
@@ -480,7 +481,7 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     for (int span = 2; span <= h->L; span <<= 1) {
       const long pairs = cnt / 2;
       qoc::StageArgs<T> a{in + mat, 2 * mat, in, 2 * mat, outb, mat, (int)pairs, dp,
-                          (T)1, (T)1, (T)1, (T)0};
+                          (T)1, (T)1, (T)1, (T)0, h->bf3};
       PhaseTimer tm(h, QOC_PHASE_BLOCKPROD, st);
       HIP_TRY(qoc::launch_stage<T>(0, a, st));
       tm.done();
@@ -643,8 +644,6 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
     return fail(QOC_ERR_ARG, "fid_mode must be QOC_FID_COHERENT or QOC_FID_INCOHERENT");
   if (D.precision != QOC_FP32 && D.precision != QOC_FP64 && D.precision != QOC_BF16X3)
     return fail(QOC_ERR_ARG, "precision must be QOC_FP32, QOC_FP64 or QOC_BF16X3");
-  if (D.precision == QOC_BF16X3)
-    return fail(QOC_ERR_UNSUPPORTED, "QOC_BF16X3 is not available in this build");
   if (D.checkpoint_every < 0) return fail(QOC_ERR_ARG, "checkpoint_every must be >= 0");
   if (!(D.taylor_tol >= 0.0) || !std::isfinite(D.taylor_tol))
     return fail(QOC_ERR_ARG, "taylor_tol must be finite and >= 0");
@@ -684,6 +683,7 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
   h->S = D.S;
   h->dt = D.dt;
   h->prec = D.precision;
+  h->bf3 = D.precision == QOC_BF16X3 ? 1 : 0;
   h->esize = (D.precision == QOC_FP64) ? 8 : 4;
   h->fid_mode = D.fid_mode;
   h->a_fid = D.alpha_fid;

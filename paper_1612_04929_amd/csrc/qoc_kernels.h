@@ -18,6 +18,7 @@ template <typename T> struct StageArgs {
   long strideC;
   int nmat, dp;
   T alpha, betaA, betaB, gamma;
+  int bf3;  // 1: bf16x3 split products (FP32 storage, padded d multiple of 64)
 };
 
 // X_j = -i s (H_0 + sum_k u_{k,j} H_k) for all steps and, when Q is not
