@@ -12,6 +12,7 @@
 // skipped, so any padded d (multiple of 16) works.
 #include "qoc_device.h"
 #include "qoc_kernels.h"
+#include "qoc_tile.h"
 
 namespace qoc {
 
@@ -96,75 +97,13 @@ __device__ __forceinline__ void wg_tile(CView<const T> A, CView<const T> B, int 
   }
 }
 
-// Out[:, 0:W] = alpha op(Am) Bin[:, 0:W] + addS Add[:, 0:W], rows = K = dp.
-template <typename T, int OPA, int TN>
-__device__ __forceinline__ void big_thin_tn(CView<const T> Am, CView<const T> Bin, int dp, int W,
-                                            T alpha, CView<const T> Add, T addS, CView<T> Out,
-                                            BigLds<T> &L) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int r0 = 0; r0 < dp; r0 += 64) {
-    for (int c0 = 0; c0 < W; c0 += TN) {
-      v4<T> cr[TN / 16], ci[TN / 16];
-#pragma unroll
-      for (int q = 0; q < TN / 16; ++q) {
-        cr[q] = vzero<T>();
-        ci[q] = vzero<T>();
-      }
-      wg_tile<T, OPA, 0, TN>(Am, Bin, r0, c0, dp, dp, L, cr, ci);
-      if (r0 + 16 * w < dp) {
-#pragma unroll
-        for (int q = 0; q < TN / 16; ++q)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = r0 + 16 * w + acc_row<T>(lane, v), col = c0 + 16 * q + (lane & 15);
-            T vr = alpha * cr[q][v], vi = alpha * ci[q][v];
-            if (addS != (T)0) {
-              vr += addS * Add.re[(long)row * Add.ld + col];
-              vi += addS * Add.im[(long)row * Add.ld + col];
-            }
-            Out.re[(long)row * Out.ld + col] = vr;
-            Out.im[(long)row * Out.ld + col] = vi;
-          }
-      }
-    }
-  }
-  __syncthreads();
-}
-
-template <typename T, int OPA>
-__device__ __forceinline__ void big_thin(CView<const T> Am, CView<const T> Bin, int dp, int W,
-                                         T alpha, CView<const T> Add, T addS, CView<T> Out,
-                                         BigLds<T> &L) {
-  if (W % 64 == 0)
-    big_thin_tn<T, OPA, 64>(Am, Bin, dp, W, alpha, Add, addS, Out, L);
-  else if (W % 32 == 0)
-    big_thin_tn<T, OPA, 32>(Am, Bin, dp, W, alpha, Add, addS, Out, L);
-  else
-    big_thin_tn<T, OPA, 16>(Am, Bin, dp, W, alpha, Add, addS, Out, L);
-}
-
-template <typename T> __device__ __forceinline__ CView<T> bsub(CView<T> v, int col0) {
-  CView<T> o;
-  o.re = v.re + col0;
-  o.im = v.im + col0;
-  o.ld = v.ld;
-  return o;
-}
-template <typename T> __device__ __forceinline__ CView<const T> bcst(CView<T> v) {
-  CView<const T> o;
-  o.re = v.re;
-  o.im = v.im;
-  o.ld = v.ld;
-  return o;
-}
-
-
 // Operand of a batched launch: element (r, c) of step j at
 // base + j * stride + r * ld + c (real plane) and + plane (imaginary plane).
 template <typename T> struct BOp {
   const T *base;
   long stride, plane;
   int ld;
+  int rr = 1 << 30, bmul = 1, boff = 0;  // inner-index block map (see TOp)
   __device__ __forceinline__ CView<const T> at(long j, int col0 = 0) const {
     CView<const T> v;
     v.re = base + j * stride + col0;
@@ -172,11 +111,24 @@ template <typename T> struct BOp {
     v.ld = ld;
     return v;
   }
+  __device__ __forceinline__ TOp<T> top(long j, int rows) const {
+    TOp<T> o;
+    o.re = base + j * stride;
+    o.im = o.re + plane;
+    o.ld = ld;
+    o.rows = rows;
+    o.rr = rr;
+    o.bmul = bmul;
+    o.boff = boff;
+    return o;
+  }
 };
 
 template <typename T> struct ThinBatch {
   BOp<T> A[2], B[2], Add[2], Out[2];
   T alpha[2], addS[2];
+  T alpha2[2];  // columns >= split: alpha2 * product, no addend
+  int split[2];
   int opa[2];
   int nhalf, N, dp, W;
 };
@@ -214,8 +166,10 @@ template <typename T, int TN> __global__ __launch_bounds__(256) void k_thin_batc
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = r0 + 16 * w + acc_row<T>(lane, v), col = c0 + 16 * q + (lane & 15);
-      T vr = a.alpha[h] * cr[q][v], vi = a.alpha[h] * ci[q][v];
-      if (a.addS[h] != (T)0) {
+      const bool first = col < a.split[h];
+      const T al = first ? a.alpha[h] : a.alpha2[h];
+      T vr = al * cr[q][v], vi = al * ci[q][v];
+      if (first && a.addS[h] != (T)0) {
         vr += a.addS[h] * Ad.re[(long)row * Ad.ld + col];
         vi += a.addS[h] * Ad.im[(long)row * Ad.ld + col];
       }
@@ -224,80 +178,192 @@ template <typename T, int TN> __global__ __launch_bounds__(256) void k_thin_batc
     }
 }
 
-template <typename T> struct XbarBatch {
-  BOp<T> Abig, Vbig;       // dp x KK blocks per step; inner dimension Kin
-  BOp<T> A2, B2;           // second accumulation (rank compression), or base null
-  const T *Hf;             // (M+1) x 2 dp^2
-  double *part;            // N x tiles x M partial sums (contract) ...
-  T *F;                    // ... or F output (compression, dp x ldF per step)
-  long Fstride, Fplane;
-  int ldF;
-  int N, dp, Kin, Kin2, M, contract;
+// Thin products on 64 x 64 tiles (chain precision or bf16x3): the
+// ThinBatch contract of k_thin_batch for widths of 64 and more.
+template <typename T, bool BF3>
+__global__ __launch_bounds__(256) void k_thin64(ThinBatch<T> a, long padded) {
+  __shared__ __align__(16) char lds[TILE64_LDS_BYTES];
+  const int rp = (a.dp + 63) / 64, cp = (a.W + 63) / 64;
+  const long per_step = (long)rp * cp, per_half = per_step * a.N;
+  const long logical = xcd_logical_block(blockIdx.x, padded);
+  if (logical >= per_half * a.nhalf) return;  // block-uniform
+  const int h = (int)(logical / per_half);
+  const long rem = logical - h * per_half;
+  const long j = rem / per_step;
+  const int t = (int)(rem - j * per_step);
+  const int r0 = (t / cp) * 64, c0 = (t % cp) * 64;
+  const TOp<T> A = a.A[h].top(j, a.dp);
+  const TOp<T> B = a.B[h].top(j, a.W);
+  v4<T> acc[2][2][2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      acc[m][n][0] = vzero<T>();
+      acc[m][n][1] = vzero<T>();
+    }
+  // op(A) = A (inner index along rows) or A^H (along columns, conjugated);
+  // B as stored (inner index down its columns)
+  if (a.opa[h])
+    tile64<T, BF3, false, true, false, false>(A, B, r0, c0, a.dp, lds, acc);
+  else
+    tile64<T, BF3, true, false, false, false>(A, B, r0, c0, a.dp, lds, acc);
+  CView<const T> Ad = a.Add[h].at(j);
+  T *ore = const_cast<T *>(a.Out[h].at(j).re), *oim = const_cast<T *>(a.Out[h].at(j).im);
+  const int old = a.Out[h].ld;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int r, c;
+        tile64_pos<T>(m, n, v, r, c);
+        const int row = r0 + r, col = c0 + c;
+        if (row < a.dp && col < a.W) {
+          const bool first = col < a.split[h];
+          const T al = first ? a.alpha[h] : a.alpha2[h];
+          T vr = al * acc[m][n][0][v], vi = al * acc[m][n][1][v];
+          if (first && a.addS[h] != (T)0) {
+            vr += a.addS[h] * Ad.re[(long)row * Ad.ld + col];
+            vi += a.addS[h] * Ad.im[(long)row * Ad.ld + col];
+          }
+          ore[(long)row * old + col] = vr;
+          oim[(long)row * old + col] = vi;
+        }
+      }
+}
+
+// Out_j = A1_j B1_j^H (+ A2_j B2_j^H) for every step j, on 64 x 64 tiles;
+// the inner dimension of each pair runs along the rows of both operands
+// (through their block maps).  Xbar = sum_k At_k V_{k+1}^H, and the
+// rank-compressed factor F = A T2^H + T1 B^H.
+template <typename T> struct XStore {
+  BOp<T> A1, B1, A2, B2;
+  int K1, K2;  // K2 = 0: one product
+  T *out;
+  long ostride, oplane;
+  int old;
+  int N, dp;
 };
 
-// Tile (r0, c0) of Abig_j Vbig_j^H (+ A2_j B2_j^H); either contracted with
-// every H_k (partial sums per tile) or stored.
-template <typename T> __global__ __launch_bounds__(256) void k_xbar_batch(XbarBatch<T> a, long padded) {
-  __shared__ BigLds<T> L;
-  __shared__ double red[4][32];
+template <typename T, bool BF3>
+__global__ __launch_bounds__(256) void k_xstore(XStore<T> a, long padded) {
+  __shared__ __align__(16) char lds[TILE64_LDS_BYTES];
   const int rp = (a.dp + 63) / 64;
   const long per_step = (long)rp * rp;
   const long logical = xcd_logical_block(blockIdx.x, padded);
-  if (logical >= per_step * a.N) return;
+  if (logical >= per_step * a.N) return;  // block-uniform
   const long j = logical / per_step;
   const int t = (int)(logical - j * per_step);
   const int r0 = (t / rp) * 64, c0 = (t % rp) * 64;
-  v4<T> cr[4], ci[4];
+  v4<T> acc[2][2][2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    cr[q] = vzero<T>();
-    ci[q] = vzero<T>();
-  }
-  wg_tile<T, 0, 1, 64>(a.Abig.at(j), a.Vbig.at(j), r0, c0, a.Kin, a.dp, L, cr, ci);
-  if (a.A2.base) wg_tile<T, 0, 1, 64>(a.A2.at(j), a.B2.at(j), r0, c0, a.Kin2, a.dp, L, cr, ci);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const bool on = r0 + 16 * w < a.dp;
-  const long plane = (long)a.dp * a.dp;
-  if (!a.contract) {
-    if (!on) return;
+  for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int n = 0; n < 2; ++n) {
+      acc[m][n][0] = vzero<T>();
+      acc[m][n][1] = vzero<T>();
+    }
+  tile64<T, BF3, true, false, true, true>(a.A1.top(j, a.dp), a.B1.top(j, a.dp), r0, c0, a.K1,
+                                          lds, acc);
+  if (a.K2 > 0)
+    tile64<T, BF3, true, false, true, true>(a.A2.top(j, a.dp), a.B2.top(j, a.dp), r0, c0, a.K2,
+                                            lds, acc);
+  T *o = a.out + j * a.ostride;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = r0 + 16 * w + acc_row<T>(lane, v), col = c0 + 16 * q + (lane & 15);
-        if (col < a.dp) {
-          a.F[j * a.Fstride + (long)row * a.ldF + col] = cr[q][v];
-          a.F[j * a.Fstride + a.Fplane + (long)row * a.ldF + col] = ci[q][v];
+        int r, c;
+        tile64_pos<T>(m, n, v, r, c);
+        const int row = r0 + r, col = c0 + c;
+        if (row < a.dp && col < a.dp) {
+          o[(long)row * a.old + col] = acc[m][n][0][v];
+          o[a.oplane + (long)row * a.old + col] = acc[m][n][1][v];
         }
       }
-    return;
-  }
-  for (int k0 = 0; k0 < a.M; k0 += 32) {
-    const int cnt = min(32, a.M - k0);
-    for (int q = 0; q < cnt; ++q) {
-      double part = 0.0;
-      if (on) {
-        const T *H = a.Hf + (long)(1 + k0 + q) * 2 * plane;
+}
+
+// g_{k,j} partials: sum over a slice of the dp^2 entries of
+// Re(Xbar_j) Im(H_k) - Im(Xbar_j) Re(H_k)   (= Im tr(Xbar_j^H H_k) in total)
+// as an MFMA product of the steps x entries panel of Xbar with the
+// entries x controls panel of H: a workgroup takes 64 steps (16 per wave)
+// and one slice of entries, so each H entry read serves 64 steps (the 4
+// waves read the same H addresses).  Each lane loads 4 consecutive entries
+// of its step (A operand) and of its control (B operand) and feeds them to
+// 4 MFMAs: the entry order inside the inner dimension is a consistent
+// permutation for both operands.  FP32 partial sums over a slice (chain
+// precision), FP64 across slices (k_adj_finish).
+template <typename T> struct GContract {
+  const T *xb;
+  long xstride, plane;
+  const T *Hf;  // (M+1) x 2 plane, control k at index k + 1
+  double *part;  // [N][nsl][M]
+  int N, M, nsl, slen;
+};
+
+template <typename T> __global__ __launch_bounds__(256) void k_gcontract(GContract<T> a) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int mi = lane & 15, g4 = 4 * (lane >> 4);
+  const int slice = blockIdx.x;
+  const long j0 = (long)blockIdx.y * 64 + 16 * w;
+  const long e0 = (long)slice * a.slen;
+  const long e1 = e0 + a.slen < a.plane ? e0 + a.slen : a.plane;
+  const long j = j0 + mi;
+  const bool jok = j < a.N;
+  const T *xr = a.xb + (jok ? j : 0) * a.xstride, *xi = xr + a.plane;
+  constexpr int MT = 4;  // 64 controls per pass
+  for (int kt0 = 0; kt0 < a.M; kt0 += 16 * MT) {
+    v4<T> acc[MT];
 #pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4)
+    for (int q = 0; q < MT; ++q) acc[q] = vzero<T>();
+    const T *hb[MT];
+    bool kok[MT];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = r0 + 16 * w + acc_row<T>(lane, v), col = c0 + 16 * q4 + (lane & 15);
-            if (col < a.dp) {
-              const long o = (long)row * a.dp + col;
-              part += (double)cr[q4][v] * (double)H[plane + o] - (double)ci[q4][v] * (double)H[o];
-            }
-          }
+    for (int q = 0; q < MT; ++q) {
+      const int k = kt0 + 16 * q + mi;
+      kok[q] = k < a.M;
+      hb[q] = a.Hf + (long)(kok[q] ? k + 1 : 0) * 2 * a.plane;
+    }
+    for (long e = e0; e < e1; e += 16) {
+      T ar[4], ai[4];
+      ld4(xr + e + g4, ar);
+      ld4(xi + e + g4, ai);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ar[i] = jok ? ar[i] : (T)0;
+        ai[i] = jok ? ai[i] : (T)0;
       }
-      part = wave_sum(part);
-      if (lane == 0) red[w][q] = part;
+#pragma unroll
+      for (int q = 0; q < MT; ++q) {
+        if (kt0 + 16 * q < a.M) {  // wave-uniform
+          T hr[4], hi[4];
+          ld4(hb[q] + e + g4, hr);
+          ld4(hb[q] + a.plane + e + g4, hi);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const T bi = kok[q] ? hi[i] : (T)0, br = kok[q] ? -hr[i] : (T)0;
+            acc[q] = mfma4(ar[i], bi, acc[q]);
+            acc[q] = mfma4(ai[i], br, acc[q]);
+          }
+        }
+      }
     }
-    __syncthreads();
-    if (threadIdx.x < cnt) {
-      const int q = threadIdx.x;
-      a.part[((long)j * per_step + t) * a.M + k0 + q] = red[0][q] + red[1][q] + red[2][q] + red[3][q];
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+      if (kt0 + 16 * q < a.M) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const long jj = j0 + acc_row<T>(lane, v);
+          const int kk = kt0 + 16 * q + mi;
+          if (jj < a.N && kk < a.M)
+            a.part[(jj * a.nsl + slice) * a.M + kk] = (double)acc[q][v];
+        }
+      }
     }
-    __syncthreads();
   }
 }
 
@@ -370,23 +436,26 @@ template <typename T> __global__ void k_adj_cat(AdjCat<T> a) {
 template <typename T> struct AdjHorn {
   T *scratch;
   long per, thin, big;
-  int N, dp, R, KK, rr, p;
+  int N, dp, R, KK2, rr;
 };
 
-// Vbig block p-1 = B (V_{p+1}), Abig block 0 = A (At_1), width rr
+// Horner panel P_0 = [V_{p+1} | At_1] = [B | A]: columns [0, rr) and [rr, 2 rr)
+// of the Big region (row stride KK2)
 template <typename T> __global__ void k_adj_horn_init(AdjHorn<T> a) {
-  const long total = (long)a.N * a.dp * a.rr;
+  const int w2 = 2 * a.rr;
+  const long total = (long)a.N * a.dp * w2;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
        e += (long)gridDim.x * blockDim.x) {
-    const long j = e / ((long)a.dp * a.rr);
-    const long rem = e - j * a.dp * a.rr;
-    const int m = (int)(rem / a.rr), c = (int)(rem - (long)m * a.rr);
+    const long j = e / ((long)a.dp * w2);
+    const long rem = e - j * a.dp * w2;
+    const int m = (int)(rem / w2), c = (int)(rem - (long)m * w2);
     T *base = a.scratch + j * a.per;
-    T *Abr = base + 8 * a.thin, *Abi = Abr + a.big, *Vbr = Abi + a.big, *Vbi = Vbr + a.big;
-    Vbr[(long)m * a.KK + (a.p - 1) * a.rr + c] = base[2 * a.thin + (long)m * a.R + c];
-    Vbi[(long)m * a.KK + (a.p - 1) * a.rr + c] = base[3 * a.thin + (long)m * a.R + c];
-    Abr[(long)m * a.KK + c] = base[(long)m * a.R + c];
-    Abi[(long)m * a.KK + c] = base[a.thin + (long)m * a.R + c];
+    T *Pr = base + 8 * a.thin, *Pi = Pr + a.big;
+    const bool vb = c < a.rr;
+    const T *src = base + (vb ? 2 * a.thin : 0);
+    const long o = (long)m * a.R + (vb ? c : c - a.rr);
+    Pr[(long)m * a.KK2 + c] = src[o];
+    Pi[(long)m * a.KK2 + c] = src[a.thin + o];
   }
 }
 
@@ -425,10 +494,28 @@ template <typename T> long adjoint_big_scratch_per_step(int dp, int p, int R) {
   return 2L * dp * (4L * R + 2L * p * R);
 }
 
+// Entry slices of the gradient contraction (at most 1024 entries each).
+long adjoint_big_slices(int dp) {
+  const long plane = (long)dp * dp;
+  return (plane + 1023) / 1024;
+}
+
 // Host plan of the batched large-d adjoint (p, n known on the host).
+//
+// Per-step scratch: A, B (dp x R) | T1, T2 (dp x R) | Big (dp x 2 p R).
+// The reverse squaring levels grow A, B by concatenation (rank r -> 2r) or
+// compress them to A = F, B = I once the rank would exceed dp.  The two
+// Horner chains share one product per stage: X is anti-Hermitian (built
+// from exactly Hermitian copies of the Hamiltonians), so X^H At = -X At
+// and the panel P_t = [V_{p+1-t} | At_{t+1}] advances as
+//   P_{t+1} = X P_t diag(1/(p-t), -1/(t+2)) + [B | 0],
+// every P_t kept side by side in Big.  Xbar = sum_k At_k V_{k+1}^H then runs
+// over the At and V column blocks of Big through block maps, is stored,
+// and is contracted with every H_k by k_gcontract.
 template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hipStream_t st) {
   const int dp = a.dp, N = a.N, S = a.S, R = a.Rcap, p = a.p, n = a.n, M = a.M;
-  const long thin = (long)dp * R, KK = (long)p * R, big = (long)dp * KK;
+  const bool bf3 = a.bf3 != 0;
+  const long thin = (long)dp * R, KK2 = 2L * p * R, big = (long)dp * KK2;
   const long per = adjoint_big_scratch_per_step<T>(dp, p, R);
   const long mat = 2L * dp * dp, lev = (long)N * mat;
   T *sc = a.scratch;
@@ -443,15 +530,32 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
     return o;
   };
   auto launch_thin = [&](ThinBatch<T> &tb) -> hipError_t {
-    const int TN = tb.W % 64 == 0 ? 64 : (tb.W % 32 == 0 ? 32 : 16);
+    if (tb.W >= 64) {
+      const long total = (long)tb.nhalf * N * ((dp + 63) / 64) * ((tb.W + 63) / 64);
+      const long padded = (total + 7) / 8 * 8;
+      if (bf3)
+        hipLaunchKernelGGL((k_thin64<T, true>), dim3((unsigned)padded), dim3(256), 0, st, tb,
+                           padded);
+      else
+        hipLaunchKernelGGL((k_thin64<T, false>), dim3((unsigned)padded), dim3(256), 0, st, tb,
+                           padded);
+      return hipGetLastError();
+    }
+    const int TN = tb.W % 32 == 0 ? 32 : 16;
     const long total = (long)tb.nhalf * N * ((dp + 63) / 64) * (tb.W / TN);
     const long padded = (total + 7) / 8 * 8;
-    if (TN == 64)
-      hipLaunchKernelGGL((k_thin_batch<T, 64>), dim3((unsigned)padded), dim3(256), 0, st, tb, padded);
-    else if (TN == 32)
+    if (TN == 32)
       hipLaunchKernelGGL((k_thin_batch<T, 32>), dim3((unsigned)padded), dim3(256), 0, st, tb, padded);
     else
       hipLaunchKernelGGL((k_thin_batch<T, 16>), dim3((unsigned)padded), dim3(256), 0, st, tb, padded);
+    return hipGetLastError();
+  };
+  auto launch_xstore = [&](XStore<T> &xs) -> hipError_t {
+    const long rp = (dp + 63) / 64, total = (long)N * rp * rp, padded = (total + 7) / 8 * 8;
+    if (bf3)
+      hipLaunchKernelGGL((k_xstore<T, true>), dim3((unsigned)padded), dim3(256), 0, st, xs, padded);
+    else
+      hipLaunchKernelGGL((k_xstore<T, false>), dim3((unsigned)padded), dim3(256), 0, st, xs, padded);
     return hipGetLastError();
   };
   const BOp<T> Ablk = blk(0, R, thin), Bblk = blk(2 * thin, R, thin);
@@ -463,67 +567,75 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
     const BOp<T> Dop{a.Dlev + slot * lev, mat, (long)dp * dp, dp};
     ThinBatch<T> tb{};
     tb.A[0] = Dop; tb.B[0] = Ablk; tb.Add[0] = Ablk; tb.Out[0] = T1blk;
-    tb.alpha[0] = (T)1; tb.addS[0] = (T)1; tb.opa[0] = 1;            // A + D^H A
+    tb.alpha[0] = (T)1; tb.addS[0] = (T)1; tb.opa[0] = 1; tb.split[0] = rr;   // A + D^H A
     tb.A[1] = Dop; tb.B[1] = Bblk; tb.Add[1] = Bblk; tb.Out[1] = T2blk;
-    tb.alpha[1] = (T)1; tb.addS[1] = (T)1; tb.opa[1] = 0;            // B + D B
+    tb.alpha[1] = (T)1; tb.addS[1] = (T)1; tb.opa[1] = 0; tb.split[1] = rr;   // B + D B
     tb.nhalf = 2; tb.N = N; tb.dp = dp; tb.W = rr;
     if ((e = launch_thin(tb)) != hipSuccess) return e;
     if (2 * r <= dp) {
-      AdjCat<T> c{sc, per, thin, big, N, dp, R, r, (int)KK, 0};
+      AdjCat<T> c{sc, per, thin, big, N, dp, R, r, (int)KK2, 0};
       hipLaunchKernelGGL(k_adj_cat<T>, dim3(grid_for((long)N * dp * r)), dim3(256), 0, st, c);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       r *= 2;
     } else {
-      // rank would exceed dp: F = A T2^H + T1 B^H (the Abig region is free
+      // rank would exceed dp: F = A T2^H + T1 B^H into the Big region (free
       // until the Horner stage), then A = F, B = I (here R = dp)
-      XbarBatch<T> xb{};
-      xb.Abig = Ablk; xb.Vbig = T2blk; xb.A2 = T1blk; xb.B2 = Bblk;
-      xb.N = N; xb.dp = dp; xb.Kin = rr; xb.Kin2 = rr; xb.contract = 0;
-      xb.F = sc + 8 * thin; xb.Fstride = per; xb.Fplane = big; xb.ldF = (int)KK;
-      const long rp = (dp + 63) / 64, total = (long)N * rp * rp, padded = (total + 7) / 8 * 8;
-      hipLaunchKernelGGL(k_xbar_batch<T>, dim3((unsigned)padded), dim3(256), 0, st, xb, padded);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      AdjCat<T> c{sc, per, thin, big, N, dp, R, dp, (int)KK, 1};
+      XStore<T> xs{};
+      xs.A1 = Ablk; xs.B1 = T2blk; xs.A2 = T1blk; xs.B2 = Bblk; xs.K1 = rr; xs.K2 = rr;
+      xs.out = sc + 8 * thin; xs.ostride = per; xs.oplane = big; xs.old = (int)KK2;
+      xs.N = N; xs.dp = dp;
+      if ((e = launch_xstore(xs)) != hipSuccess) return e;
+      AdjCat<T> c{sc, per, thin, big, N, dp, R, dp, (int)KK2, 1};
       hipLaunchKernelGGL(k_adj_cat<T>, dim3(grid_for((long)N * dp * dp)), dim3(256), 0, st, c);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       r = dp;
     }
   }
-  // ---- Horner reverse
+  // ---- Horner reverse: one product per stage over [V | At]
   const int rr = (r + 15) & ~15;
   {
-    AdjHorn<T> hi{sc, per, thin, big, N, dp, R, (int)KK, rr, p};
-    hipLaunchKernelGGL(k_adj_horn_init<T>, dim3(grid_for((long)N * dp * rr)), dim3(256), 0, st, hi);
+    AdjHorn<T> hi{sc, per, thin, big, N, dp, R, (int)KK2, rr};
+    hipLaunchKernelGGL(k_adj_horn_init<T>, dim3(grid_for((long)N * dp * 2 * rr)), dim3(256), 0,
+                       st, hi);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const BOp<T> Xop{a.X, mat, (long)dp * dp, dp};
   for (int t = 0; t < p - 1; ++t) {
-    const int kv = p - t, ka = t + 1;
     ThinBatch<T> tb{};
-    tb.A[0] = Xop; tb.B[0] = blk(8 * thin + 2 * big + (long)(kv - 1) * rr, (int)KK, big);
-    tb.Add[0] = Bblk; tb.Out[0] = blk(8 * thin + 2 * big + (long)(kv - 2) * rr, (int)KK, big);
-    tb.alpha[0] = (T)(1.0 / kv); tb.addS[0] = (T)1; tb.opa[0] = 0;   // V_kv
-    tb.A[1] = Xop; tb.B[1] = blk(8 * thin + (long)(ka - 1) * rr, (int)KK, big);
-    tb.Add[1] = Ablk; tb.Out[1] = blk(8 * thin + (long)ka * rr, (int)KK, big);
-    tb.alpha[1] = (T)(1.0 / (ka + 1)); tb.addS[1] = (T)0; tb.opa[1] = 1;  // At_{ka+1}
-    tb.nhalf = 2; tb.N = N; tb.dp = dp; tb.W = rr;
+    tb.A[0] = Xop; tb.opa[0] = 0;
+    tb.B[0] = blk(8 * thin + (long)(2 * t) * rr, (int)KK2, big);
+    tb.Out[0] = blk(8 * thin + (long)(2 * t + 2) * rr, (int)KK2, big);
+    tb.Add[0] = Bblk; tb.addS[0] = (T)1;
+    tb.alpha[0] = (T)(1.0 / (p - t));            // V_{p-t} = B + X V_{p+1-t} / (p-t)
+    tb.alpha2[0] = (T)(-1.0 / (t + 2));          // At_{t+2} = X^H At_{t+1} / (t+2)
+    tb.split[0] = rr;
+    tb.nhalf = 1; tb.N = N; tb.dp = dp; tb.W = 2 * rr;
     if ((e = launch_thin(tb)) != hipSuccess) return e;
   }
-  // ---- Xbar and contraction
-  const long rp = (dp + 63) / 64, tiles = rp * rp;
+  // ---- Xbar = sum_k At_k V_{k+1}^H, stored, then contracted with every H_k
   {
-    XbarBatch<T> xb{};
-    xb.Abig = blk(8 * thin, (int)KK, big);
-    xb.Vbig = blk(8 * thin + 2 * big, (int)KK, big);
-    xb.A2.base = nullptr;
-    xb.Hf = a.Hf; xb.part = a.part; xb.N = N; xb.dp = dp; xb.Kin = p * rr; xb.M = M;
-    xb.contract = 1;
-    const long total = (long)N * tiles, padded = (total + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_xbar_batch<T>, dim3((unsigned)padded), dim3(256), 0, st, xb, padded);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    XStore<T> xs{};
+    xs.A1 = blk(8 * thin, (int)KK2, big);
+    xs.A1.rr = rr; xs.A1.bmul = 2; xs.A1.boff = 1;           // At_{kb+1}: block 2 kb + 1
+    xs.B1 = blk(8 * thin, (int)KK2, big);
+    xs.B1.rr = rr; xs.B1.bmul = -2; xs.B1.boff = 2 * (p - 1);  // V_{kb+2}: block 2 (p-1-kb)
+    xs.K1 = p * rr; xs.K2 = 0;
+    xs.out = a.xbar; xs.ostride = mat; xs.oplane = (long)dp * dp; xs.old = dp;
+    xs.N = N; xs.dp = dp;
+    if ((e = launch_xstore(xs)) != hipSuccess) return e;
+  }
+  const long nsl = adjoint_big_slices(dp);
+  {
+    GContract<T> gc{a.xbar, mat, (long)dp * dp, a.Hf, a.part, N, M, (int)nsl,
+                    (int)std::min<long>(1024, (long)dp * dp)};
+    if (M > 0) {
+      dim3 grid((unsigned)nsl, (unsigned)((N + 63) / 64));
+      hipLaunchKernelGGL(k_gcontract<T>, grid, dim3(256), 0, st, gc);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   AdjFinish<T> f{a.part, a.u, a.grad, 2.0 * a.s_scale, a.alpha_amp, a.alpha_var, nullptr, N, M,
-                 (int)tiles};
+                 (int)nsl};
   hipLaunchKernelGGL(k_adj_finish<T>, dim3(grid_for((long)N * M)), dim3(256), 0, st, f);
   return hipGetLastError();
 }

@@ -9,35 +9,77 @@
 // adding a small update to the identity at every step.
 #include "qoc_device.h"
 #include "qoc_kernels.h"
+#include "qoc_tile.h"
 
 namespace qoc {
+
+// Block: 256 consecutive matrix entries (one per thread, coalesced) x
+// AS_STEPS steps; each Hamiltonian entry loaded feeds AS_STEPS steps, and
+// the control amplitudes are wave-uniform LDS broadcasts.
+constexpr int AS_STEPS = 16, AS_KC = 8;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_assemble(const T *__restrict__ Hf,
                                                   const double *__restrict__ u, int dp, int M,
                                                   int N, T s, T inv_p, T *__restrict__ X,
                                                   T *__restrict__ Q) {
+  extern __shared__ char as_smem[];
+  T *coef = (T *)as_smem;  // [AS_STEPS][M]
   const long plane = (long)dp * dp;
-  const long total = (long)N * plane;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-       e += (long)gridDim.x * blockDim.x) {
-    const long j = e / plane, rc = e - j * plane;
-    T hr = Hf[rc], hi = Hf[plane + rc];
-    for (int k = 0; k < M; ++k) {
-      const T c = (T)u[(long)k * N + j];
-      hr += c * Hf[(long)(k + 1) * 2 * plane + rc];
-      hi += c * Hf[(long)(k + 1) * 2 * plane + plane + rc];
+  const int t = threadIdx.x;
+  const int j0 = blockIdx.x * AS_STEPS;
+  const long rc = (long)blockIdx.y * 256 + t;
+  for (int e = t; e < AS_STEPS * M; e += 256) {
+    const int sj = e / M, k = e - sj * M;
+    coef[e] = (j0 + sj < N) ? (T)u[(long)k * N + j0 + sj] : (T)0;
+  }
+  __syncthreads();
+  if (rc >= plane) return;  // no barrier below
+  T hr[AS_STEPS], hi[AS_STEPS];
+  {
+    const T a = Hf[rc], b = Hf[plane + rc];
+#pragma unroll
+    for (int q = 0; q < AS_STEPS; ++q) {
+      hr[q] = a;
+      hi[q] = b;
     }
-    // -i s (hr + i hi) = s hi - i s hr
-    const T xr = s * hi, xi = -s * hr;
-    T *Xj = X + j * 2 * plane;
-    Xj[rc] = xr;
-    Xj[plane + rc] = xi;
-    if (Q) {
-      const int r = (int)(rc / dp), c = (int)(rc - (long)r * dp);
-      T *Qj = Q + j * 2 * plane;
-      Qj[rc] = (r == c ? (T)1 : (T)0) + xr * inv_p;
-      Qj[plane + rc] = xi * inv_p;
+  }
+  for (int k0 = 0; k0 < M; k0 += AS_KC) {
+    T kr[AS_KC], ki[AS_KC];
+#pragma unroll
+    for (int q = 0; q < AS_KC; ++q) {
+      const bool ok = k0 + q < M;
+      const T *Hk = Hf + (long)(ok ? k0 + q + 1 : 0) * 2 * plane;
+      kr[q] = ok ? Hk[rc] : (T)0;
+      ki[q] = ok ? Hk[plane + rc] : (T)0;
+    }
+#pragma unroll
+    for (int q = 0; q < AS_KC; ++q) {
+      if (k0 + q < M) {
+#pragma unroll
+        for (int sj = 0; sj < AS_STEPS; ++sj) {
+          const T c = coef[sj * M + k0 + q];
+          hr[sj] += c * kr[q];
+          hi[sj] += c * ki[q];
+        }
+      }
+    }
+  }
+  const int r = (int)(rc / dp), c = (int)(rc - (long)r * dp);
+#pragma unroll
+  for (int sj = 0; sj < AS_STEPS; ++sj) {
+    const long j = j0 + sj;
+    if (j < N) {
+      // -i s (hr + i hi) = s hi - i s hr
+      const T xr = s * hi[sj], xi = -s * hr[sj];
+      T *Xj = X + j * 2 * plane;
+      Xj[rc] = xr;
+      Xj[plane + rc] = xi;
+      if (Q) {
+        T *Qj = Q + j * 2 * plane;
+        Qj[rc] = (r == c ? (T)1 : (T)0) + xr * inv_p;
+        Qj[plane + rc] = xi * inv_p;
+      }
     }
   }
 }
@@ -122,114 +164,8 @@ __global__ __launch_bounds__(256) void k_stage64(StageArgs<T> a, long padded) {
                     acc[m][n][0][v], acc[m][n][1][v]);
 }
 
-// ---------------------------------------------------------------------------
-// bf16x3 split-precision variant of k_stage64 (FP32 storage, FP32
-// accumulation).  Each FP32 operand x is split on its way into LDS as
-// hi = RNE_bf16(x), lo = RNE_bf16(x - hi) (x - hi is exact in FP32), and
-// every real product is hi*hi + hi*lo + lo*hi on the bf16 16x16x32 MFMA;
-// the dropped lo*lo term and the split leave a relative error of a few
-// 2^-17 per product.  The inner dimension runs in chunks of 32 (one MFMA
-// K); LDS holds the chunk of op(A) as [plane][row][k] and of B as
-// [plane][col][k] (k contiguous, row stride 40 halves), planes re_hi,
-// re_lo, im_hi, im_lo, so each lane's operand is one 16-byte LDS read.
-// The next chunk's FP32 operands are loaded into registers while the
-// current one is multiplied.
-// ---------------------------------------------------------------------------
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int BF_BK = 32;
-constexpr int BF_LDK = BF_BK + 8;
-
-__device__ __forceinline__ f32x4 mfma_bf(bf16x8 a, bf16x8 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ bf16x8 bf_neg(bf16x8 v) {
-  u32x4 u = __builtin_bit_cast(u32x4, v);
-  u ^= 0x80008000u;
-  return __builtin_bit_cast(bf16x8, u);
-}
-
-// 8 FP32 values -> hi / lo bf16 parts.
-__device__ __forceinline__ void bf_split8(const float (&x)[8], bf16x8 &hi, bf16x8 &lo) {
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const __bf16 h = (__bf16)x[q];
-    hi[q] = h;
-    lo[q] = (__bf16)(x[q] - (float)h);
-  }
-}
-
-// LDS of one 64x64 output tile: 4 planes x 64 rows x BF_LDK for each operand.
-struct alignas(16) BfLds {
-  __bf16 a[4][64][BF_LDK];
-  __bf16 b[4][64][BF_LDK];
-};
-
-// FP32 staging registers of one thread for one chunk: 8 k of one row of
-// op(A) and 8 k of one column of B, real and imaginary parts.
-struct BfRegs {
-  float ar[8], ai[8], br[8], bi[8];
-};
-
-template <int OPA>
-__device__ __forceinline__ void bf_load(const StageArgs<float> &a, const float *Aj,
-                                        const float *Bj, long plane, int r0, int c0, int k0,
-                                        BfRegs &g) {
-  const int t = threadIdx.x;
-  const int dp = a.dp;
-  if (OPA == 0) {
-    // row r, k = 8 kq .. 8 kq + 7 of A (contiguous): two 16-byte loads per plane
-    const int r = t >> 2, kq = t & 3;
-    const long o = (long)(r0 + r) * dp + k0 + 8 * kq;
-    const float4 *pr = (const float4 *)(Aj + o), *pi = (const float4 *)(Aj + plane + o);
-    const float4 r0v = pr[0], r1v = pr[1], i0v = pi[0], i1v = pi[1];
-    g.ar[0] = r0v.x; g.ar[1] = r0v.y; g.ar[2] = r0v.z; g.ar[3] = r0v.w;
-    g.ar[4] = r1v.x; g.ar[5] = r1v.y; g.ar[6] = r1v.z; g.ar[7] = r1v.w;
-    g.ai[0] = i0v.x; g.ai[1] = i0v.y; g.ai[2] = i0v.z; g.ai[3] = i0v.w;
-    g.ai[4] = i1v.x; g.ai[5] = i1v.y; g.ai[6] = i1v.z; g.ai[7] = i1v.w;
-  } else {
-    // op(A)[r][k] = conj(A[k][r]): lanes along r are contiguous in memory
-    const int r = t & 63, kq = t >> 6;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const long o = (long)(k0 + 8 * kq + q) * dp + r0 + r;
-      g.ar[q] = Aj[o];
-      g.ai[q] = -Aj[plane + o];
-    }
-  }
-  {
-    const int c = t & 63, kq = t >> 6;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const long o = (long)(k0 + 8 * kq + q) * dp + c0 + c;
-      g.br[q] = Bj[o];
-      g.bi[q] = Bj[plane + o];
-    }
-  }
-}
-
-template <int OPA>
-__device__ __forceinline__ void bf_store(const BfRegs &g, BfLds &L) {
-  const int t = threadIdx.x;
-  const int ra = OPA == 0 ? (t >> 2) : (t & 63), ka = OPA == 0 ? (t & 3) : (t >> 6);
-  const int cb = t & 63, kb = t >> 6;
-  bf16x8 h, l;
-  bf_split8(g.ar, h, l);
-  *(bf16x8 *)&L.a[0][ra][8 * ka] = h;
-  *(bf16x8 *)&L.a[1][ra][8 * ka] = l;
-  bf_split8(g.ai, h, l);
-  *(bf16x8 *)&L.a[2][ra][8 * ka] = h;
-  *(bf16x8 *)&L.a[3][ra][8 * ka] = l;
-  bf_split8(g.br, h, l);
-  *(bf16x8 *)&L.b[0][cb][8 * kb] = h;
-  *(bf16x8 *)&L.b[1][cb][8 * kb] = l;
-  bf_split8(g.bi, h, l);
-  *(bf16x8 *)&L.b[2][cb][8 * kb] = h;
-  *(bf16x8 *)&L.b[3][cb][8 * kb] = l;
-}
-
+// bf16x3 variant of k_stage64 (FP32 storage; the split-product tile of
+// qoc_tile.h), same tiling, epilogue and block order.
 template <int OPA>
 __global__ __launch_bounds__(256) void k_stage64_bf3(StageArgs<float> a, long padded) {
   __shared__ BfLds L;
@@ -241,11 +177,8 @@ __global__ __launch_bounds__(256) void k_stage64_bf3(StageArgs<float> a, long pa
   const int t = (int)(logical - j * tiles);
   const int r0 = (t / t1) * 64, c0 = (t % t1) * 64;
   const long plane = (long)a.dp * a.dp;
-  const float *Aj = a.A + j * a.strideA;
-  const float *Bj = a.B + j * a.strideB;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = lane & 15, g8 = 8 * (lane >> 4);
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const TOp<float> A = make_top<float>(a.A + j * a.strideA, plane, a.dp, a.dp);
+  const TOp<float> B = make_top<float>(a.B + j * a.strideB, plane, a.dp, a.dp);
   f32x4 acc[2][2][2];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
@@ -254,64 +187,28 @@ __global__ __launch_bounds__(256) void k_stage64_bf3(StageArgs<float> a, long pa
       acc[m][n][0] = vzero<float>();
       acc[m][n][1] = vzero<float>();
     }
-  BfRegs g;
-  bf_load<OPA>(a, Aj, Bj, plane, r0, c0, 0, g);
-  for (int k0 = 0; k0 < a.dp; k0 += BF_BK) {
-    bf_store<OPA>(g, L);
-    __syncthreads();
-    if (k0 + BF_BK < a.dp) bf_load<OPA>(a, Aj, Bj, plane, r0, c0, k0 + BF_BK, g);
-    bf16x8 fa[2][4], fb[2][4], na[2][2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        fa[m][p] = *(const bf16x8 *)&L.a[p][wr + 16 * m + i][g8];
-        fb[m][p] = *(const bf16x8 *)&L.b[p][wc + 16 * m + i][g8];
-      }
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      na[m][0] = bf_neg(fa[m][2]);
-      na[m][1] = bf_neg(fa[m][3]);
-    }
-    // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br, each real product as
-    // hi*hi + hi*lo + lo*hi; consecutive MFMAs go to different accumulators
-#define BF3_TERM(dst, X, Y)                                                    \
-  _Pragma("unroll") for (int m = 0; m < 2; ++m)                                \
-  _Pragma("unroll") for (int n = 0; n < 2; ++n)                                \
-    acc[m][n][dst] = mfma_bf(X, Y, acc[m][n][dst]);
-    BF3_TERM(0, fa[m][0], fb[n][0])
-    BF3_TERM(1, fa[m][0], fb[n][2])
-    BF3_TERM(0, fa[m][0], fb[n][1])
-    BF3_TERM(1, fa[m][0], fb[n][3])
-    BF3_TERM(0, fa[m][1], fb[n][0])
-    BF3_TERM(1, fa[m][1], fb[n][2])
-    BF3_TERM(0, na[m][0], fb[n][2])
-    BF3_TERM(1, fa[m][2], fb[n][0])
-    BF3_TERM(0, na[m][0], fb[n][3])
-    BF3_TERM(1, fa[m][2], fb[n][1])
-    BF3_TERM(0, na[m][1], fb[n][2])
-    BF3_TERM(1, fa[m][3], fb[n][0])
-#undef BF3_TERM
-    __syncthreads();
-  }
+  // op(A) = A: inner index along rows of A; op(A) = A^H: along columns,
+  // conjugated; B as stored: inner index along columns of B
+  ctile64_bf3<OPA == 0, OPA == 1, false, false>(A, B, r0, c0, a.dp, L, acc);
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
     for (int n = 0; n < 2; ++n)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        stage_store(a, j, r0 + wr + 16 * m + acc_row<float>(lane, v),
-                    c0 + wc + 16 * n + (lane & 15), acc[m][n][0][v], acc[m][n][1][v]);
+      for (int v = 0; v < 4; ++v) {
+        int r, c;
+        tile64_pos<float>(m, n, v, r, c);
+        stage_store(a, j, r0 + r, c0 + c, acc[m][n][0][v], acc[m][n][1][v]);
+      }
 }
 
 template <typename T>
 hipError_t launch_assemble(const T *Hf, const double *u, int dp, int M, int N, T s, T inv_p,
                            T *X, T *Q, hipStream_t st) {
-  const long total = (long)N * dp * dp;
-  long blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_assemble<T>, dim3((unsigned)blocks), dim3(256), 0, st, Hf, u, dp, M, N, s,
-                     inv_p, X, Q);
+  const long plane = (long)dp * dp;
+  dim3 grid((unsigned)((N + AS_STEPS - 1) / AS_STEPS), (unsigned)((plane + 255) / 256));
+  const size_t shm = sizeof(T) * AS_STEPS * M;
+  hipLaunchKernelGGL(k_assemble<T>, grid, dim3(256), shm, st, Hf, u, dp, M, N, s, inv_p, X, Q);
   return hipGetLastError();
 }
 

@@ -3,15 +3,17 @@
 // The paper fixes one conservative truncation order p and squaring count n
 // for all steps instead of estimating each step's spectral radius
 // (Sec. III); this kernel supplies the global norm that choice is made
-// from.  Each workgroup covers 16 columns x 16 steps; the Hamiltonian
-// entries of a 2-row chunk are staged once in LDS and reused by all 16
-// steps, so H is read from L2 N/16 times instead of N times.
+// from, in FP64 from the FP64 copies of the Hamiltonians.
 #include "qoc_device.h"
 #include "qoc_kernels.h"
 
 namespace qoc {
 
-constexpr int NRM_COLS = 16, NRM_STEPS = 16, NRM_ROWS = 2;
+// Block: 64 columns (one per lane) x NRM_STEPS steps (NRM_SW per wave);
+// each Hamiltonian entry loaded feeds NRM_SW steps, and the 4 waves of a
+// block read the same entries (L1 hits).  NRM_KC control Hamiltonians are
+// held in registers at a time.
+constexpr int NRM_SW = 4, NRM_STEPS = 4 * NRM_SW, NRM_KC = 8;
 
 // (p, n) from theta by the rule of qoc_taylor_select, one wavefront, one
 // lane per squaring count n; returns {p, n, status} and dt / 2^n.
@@ -71,61 +73,75 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
                                               const double *__restrict__ u, int d, int M, int N,
                                               double dt, unsigned long long *theta_bits,
                                               SelectArgs sel) {
-  extern __shared__ double sh[];
-  // sh layout: coef[NRM_STEPS][M] then Hs[(M+1)][NRM_ROWS][NRM_COLS][2]
-  double *coef = sh;
-  double *Hs = sh + NRM_STEPS * M;
-  __shared__ double red[4];
-  const int t = threadIdx.x;
-  const int cc = t & (NRM_COLS - 1), jj = t >> 4;
-  const int c0 = blockIdx.y * NRM_COLS, j0 = blockIdx.x * NRM_STEPS;
-  const int col = c0 + cc, j = j0 + jj;
+  extern __shared__ double coef[];  // [NRM_STEPS][M] control amplitudes of the block's steps
+  __shared__ unsigned long long red[4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int col = blockIdx.y * 64 + lane;
+  const int j0 = blockIdx.x * NRM_STEPS;
   for (int e = t; e < NRM_STEPS * M; e += 256) {
     const int sj = e / M, k = e - sj * M;
     coef[e] = (j0 + sj < N) ? u[(long)k * N + j0 + sj] : 0.0;
   }
-  double acc = 0.0;
-  const int hs_elems = (M + 1) * NRM_ROWS * NRM_COLS;
-  for (int r0 = 0; r0 < d; r0 += NRM_ROWS) {
-    __syncthreads();
-    for (int e = t; e < hs_elems; e += 256) {
-      const int k = e / (NRM_ROWS * NRM_COLS);
-      const int rem = e - k * NRM_ROWS * NRM_COLS;
-      const int rr = rem / NRM_COLS, c = rem - rr * NRM_COLS;
-      const int row = r0 + rr, cl = c0 + c;
-      double vr = 0.0, vi = 0.0;
-      if (row < d && cl < d) {
-        const long o = ((long)k * d * d + (long)row * d + cl) * 2;
-        vr = H64[o];
-        vi = H64[o + 1];
+  __syncthreads();
+  // wave w: steps j0 + NRM_SW w .. + NRM_SW - 1 (coefficient reads are
+  // wave-uniform LDS broadcasts); lane: one column; rows streamed
+  const double *cw = coef + w * NRM_SW * M;
+  double nrm[NRM_SW];
+#pragma unroll
+  for (int s = 0; s < NRM_SW; ++s) nrm[s] = 0.0;
+  if (col < d) {
+    const long dd = (long)d * d;
+    for (int r = 0; r < d; ++r) {
+      const double2 h0 = *(const double2 *)(H64 + ((long)r * d + col) * 2);
+      double hr[NRM_SW], hi[NRM_SW];
+#pragma unroll
+      for (int s = 0; s < NRM_SW; ++s) {
+        hr[s] = h0.x;
+        hi[s] = h0.y;
       }
-      Hs[2 * e] = vr;
-      Hs[2 * e + 1] = vi;
-    }
-    __syncthreads();
-    if (col < d && j < N) {
-      for (int rr = 0; rr < NRM_ROWS; ++rr) {
-        const int e0 = rr * NRM_COLS + cc;
-        double hr = Hs[2 * e0], hi = Hs[2 * e0 + 1];
-        for (int k = 0; k < M; ++k) {
-          const double c = coef[jj * M + k];
-          const int e = (k + 1) * NRM_ROWS * NRM_COLS + e0;
-          hr += c * Hs[2 * e];
-          hi += c * Hs[2 * e + 1];
+      for (int k0 = 0; k0 < M; k0 += NRM_KC) {
+        double2 hk[NRM_KC];
+#pragma unroll
+        for (int q = 0; q < NRM_KC; ++q)
+          hk[q] = (k0 + q < M)
+                      ? *(const double2 *)(H64 + ((long)(k0 + q + 1) * dd + (long)r * d + col) * 2)
+                      : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < NRM_KC; ++q) {
+          if (k0 + q < M) {
+#pragma unroll
+            for (int s = 0; s < NRM_SW; ++s) {
+              const double c = cw[s * M + k0 + q];
+              hr[s] += c * hk[q].x;
+              hi[s] += c * hk[q].y;
+            }
+          }
         }
-        acc += sqrt(hr * hr + hi * hi);
       }
+#pragma unroll
+      for (int s = 0; s < NRM_SW; ++s) nrm[s] += sqrt(hr[s] * hr[s] + hi[s] * hi[s]);
     }
   }
-  double v = (col < d && j < N) ? dt * acc : 0.0;
+  // maximum as FP64 bit patterns (values are >= 0; a NaN maps to the
+  // largest pattern so that it reaches theta_max and is reported)
+  unsigned long long v = 0ull;
+#pragma unroll
+  for (int s = 0; s < NRM_SW; ++s) {
+    if (col < d && j0 + w * NRM_SW + s < N) {
+      const double x = dt * nrm[s];
+      const unsigned long long b =
+          (x != x) ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(x);
+      v = b > v ? b : v;
+    }
+  }
   v = wave_max(v);
   if ((t & 63) == 0) red[t >> 6] = v;
   __syncthreads();
   __shared__ int last;
   if (t == 0) {
-    double m = red[0];
+    unsigned long long m = red[0];
     for (int i = 1; i < 4; ++i) m = red[i] > m ? red[i] : m;
-    atomicMax(theta_bits, (unsigned long long)__double_as_longlong(m));
+    atomicMax(theta_bits, m);
     last = 0;
     if (sel.pn) {
       __threadfence();
@@ -144,9 +160,8 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
 
 hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, double dt,
                        unsigned long long *theta_bits, const SelectArgs &sel, hipStream_t st) {
-  dim3 grid((N + NRM_STEPS - 1) / NRM_STEPS, (d + NRM_COLS - 1) / NRM_COLS);
-  const size_t shm =
-      sizeof(double) * (NRM_STEPS * M + 2 * (M + 1) * NRM_ROWS * NRM_COLS);
+  dim3 grid((N + NRM_STEPS - 1) / NRM_STEPS, (d + 63) / 64);
+  const size_t shm = sizeof(double) * NRM_STEPS * M;
   hipLaunchKernelGGL(k_norm, grid, dim3(256), shm, st, H64, u, d, M, N, dt, theta_bits, sel);
   return hipGetLastError();
 }

@@ -113,7 +113,9 @@ template <typename T> struct AdjointArgs {
   T *scratch;          // nblocks x groups_per_block x scratch_elems
   long scratch_elems;
   double *grad;        // M x N
-  double *part;        // batched variant: N x tiles x M partial sums
+  double *part;        // batched variant: N x slices x M partial sums
+  T *xbar;             // batched variant: N x 2 dp^2 work space for Xbar_j
+  int bf3;             // batched variant: bf16x3 split products
 };
 template <typename T> long adjoint_scratch_elems(int dp, int p, int Rcap);
 // Time steps processed concurrently per workgroup (one per wave for small d).
@@ -123,10 +125,15 @@ template <typename T> hipError_t launch_adjoint(const AdjointArgs<T> &a, hipStre
 // scratch); p_max bounds the Taylor order it may be asked to handle.
 template <typename T> bool adjoint16_ok(int dp, int p_max);
 // Batched variant for padded d >= 64: one launch per stage of the reverse
-// recurrence over all N steps; scratch is per step (N x per_step elements)
-// and `part` holds N x tiles x M partial sums.  (p, n) must be host-known.
+// recurrence over all N steps; scratch is per step (N x per_step elements),
+// `xbar` holds N matrices and `part` N x slices x M partial sums.  The
+// control Hamiltonians must be exactly Hermitian (X^H = -X is used).
+// (p, n) must be host-known.
 template <typename T> bool adjoint_big_ok(int dp);
 template <typename T> long adjoint_big_scratch_per_step(int dp, int p, int Rcap);
+// Entry slices of the batched gradient contraction (partial sums per step
+// and control: N x slices x M doubles in `part`).
+long adjoint_big_slices(int dp);
 template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_adjoint16(const AdjointArgs<T> &a, hipStream_t st);
 

@@ -1,0 +1,302 @@
+// Operand-generic 64x64 complex tile products for the batched kernels
+// (Taylor / squaring stages, the per-step derivative), in the chain
+// precision (FP32 or FP64 MFMA) or as bf16x3 split products.
+//
+// A tile is C[i0:i0+64, j0:j0+64] += op(A)[i0:, 0:K] op(B)[0:K, j0:] where
+// an operand is described by a TOp: element (i, kk) of op(X), with i the
+// outer index (rows of op(A) / columns of op(B)) and kk the inner one.
+//   KC = true : memory is row-major over (i, col(kk)), element at
+//               i * ld + col(kk) (the inner index runs along a row)
+//   KC = false: element at col(kk) * ld + i
+//   CJ = true : complex conjugate
+// col(kk) maps the inner index to a memory column in blocks of rr,
+// col(kk) = (bmul * (kk / rr) + boff) * rr + kk % rr, so that a product can
+// run over non-adjacent column blocks of a stored panel.  Outer indices at
+// or beyond `rows` read as zero.
+//
+// Requirements (checked by the callers): ld, rr and K multiples of 16,
+// rows a multiple of 16, base pointers 16-byte aligned.
+#pragma once
+#include "qoc_device.h"
+
+namespace qoc {
+
+template <typename T> struct TOp {
+  const T *re, *im;
+  int ld, rows;
+  int rr, bmul, boff;
+  __device__ __forceinline__ int col(int kk) const {
+    const int b = kk / rr;
+    return (bmul * b + boff) * rr + (kk - b * rr);
+  }
+};
+
+template <typename T>
+__host__ __device__ inline TOp<T> make_top(const T *re, long plane, int ld, int rows) {
+  TOp<T> o;
+  o.re = re;
+  o.im = re + plane;
+  o.ld = ld;
+  o.rows = rows;
+  o.rr = 1 << 30;
+  o.bmul = 1;
+  o.boff = 0;
+  return o;
+}
+
+__device__ __forceinline__ void ld4(const float *p, float (&v)[4]) {
+  const float4 x = *(const float4 *)p;
+  v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+__device__ __forceinline__ void ld4(const double *p, double (&v)[4]) {
+  const double2 x = *(const double2 *)p, y = *(const double2 *)(p + 2);
+  v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+}
+
+// ---------------------------------------------------------------- FP32 / FP64
+// LDS: A and B chunks of 16 inner indices, k-major with row stride T64_LD
+// (the layout of wg_cgemm64), T64_LDS_ELEMS elements.
+
+template <typename T, bool KC, bool CJ>
+__device__ __forceinline__ void stage_op16(const TOp<T> &X, int i0, int k0, T *Sr, T *Si) {
+  const int t = threadIdx.x;
+  T vr[4], vi[4];
+  if (KC) {
+    const int i = t >> 2, kq = (t & 3) * 4;
+    const bool ok = i0 + i < X.rows;
+    const long o = ok ? (long)(i0 + i) * X.ld + X.col(k0 + kq) : 0;
+    ld4(X.re + o, vr);
+    ld4(X.im + o, vi);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Sr[(kq + q) * T64_LD + i] = ok ? vr[q] : (T)0;
+      Si[(kq + q) * T64_LD + i] = ok ? (CJ ? -vi[q] : vi[q]) : (T)0;
+    }
+  } else {
+    const int k = t >> 4, iq = (t & 15) * 4;
+    const bool ok = i0 + iq < X.rows;
+    const long o = ok ? (long)X.col(k0 + k) * X.ld + i0 + iq : 0;
+    ld4(X.re + o, vr);
+    ld4(X.im + o, vi);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Sr[k * T64_LD + iq + q] = ok ? vr[q] : (T)0;
+      Si[k * T64_LD + iq + q] = ok ? (CJ ? -vi[q] : vi[q]) : (T)0;
+    }
+  }
+}
+
+// acc[m][n][0/1] (re / im) of the 32x32 sub-tile (32 (w >> 1), 32 (w & 1))
+// of wave w, as 2 x 2 MFMA tiles.  All 256 threads must call.
+template <typename T, bool AKC, bool ACJ, bool BKC, bool BCJ>
+__device__ __forceinline__ void ctile64(const TOp<T> &A, const TOp<T> &B, int i0, int j0, int K,
+                                        T *lds, v4<T> (&acc)[2][2][2]) {
+  T *Asr = lds;
+  T *Asi = Asr + T64_BK * T64_LD;
+  T *Bsr = Asi + T64_BK * T64_LD;
+  T *Bsi = Bsr + T64_BK * T64_LD;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  for (int k0 = 0; k0 < K; k0 += T64_BK) {
+    stage_op16<T, AKC, ACJ>(A, i0, k0, Asr, Asi);
+    stage_op16<T, BKC, BCJ>(B, j0, k0, Bsr, Bsi);
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < T64_BK; k4 += 4) {
+      T ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        ar[m] = Asr[(k4 + kk) * T64_LD + wr + 16 * m + i];
+        ai[m] = Asi[(k4 + kk) * T64_LD + wr + 16 * m + i];
+        br[m] = Bsr[(k4 + kk) * T64_LD + wc + 16 * m + i];
+        bi[m] = Bsi[(k4 + kk) * T64_LD + wc + 16 * m + i];
+      }
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          acc[m][n][0] = mfma4(ar[m], br[n], acc[m][n][0]);
+          acc[m][n][0] = mfma4(-ai[m], bi[n], acc[m][n][0]);
+          acc[m][n][1] = mfma4(ar[m], bi[n], acc[m][n][1]);
+          acc[m][n][1] = mfma4(ai[m], br[n], acc[m][n][1]);
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- bf16x3
+// Each FP32 operand x is split on its way into LDS as hi = RNE_bf16(x),
+// lo = RNE_bf16(x - hi) (x - hi is exact in FP32), and every real product
+// is hi*hi + hi*lo + lo*hi on the bf16 16x16x32 MFMA with FP32
+// accumulation; the dropped lo*lo term and the two roundings leave a
+// relative error of a few 2^-18 per product.  The inner dimension runs in
+// chunks of 32 (one MFMA K; a ragged last chunk of 16 is zero-filled).
+// LDS holds each operand chunk as [plane][outer][k] (k contiguous, row
+// stride 40 halves), planes re_hi, re_lo, im_hi, im_lo, so each lane's
+// MFMA operand is one 16-byte LDS read.  The next chunk's FP32 values are
+// loaded into registers while the current chunk is multiplied.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BF_BK = 32;
+constexpr int BF_LDK = BF_BK + 8;
+
+__device__ __forceinline__ f32x4 mfma_bf(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 bf_neg(bf16x8 v) {
+  u32x4 u = __builtin_bit_cast(u32x4, v);
+  u ^= 0x80008000u;
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+__device__ __forceinline__ void bf_split8(const float (&x)[8], bf16x8 &hi, bf16x8 &lo) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const __bf16 h = (__bf16)x[q];
+    hi[q] = h;
+    lo[q] = (__bf16)(x[q] - (float)h);
+  }
+}
+
+struct alignas(16) BfLds {
+  __bf16 a[4][64][BF_LDK];
+  __bf16 b[4][64][BF_LDK];
+};
+
+// Thread -> (outer index, group of 8 inner indices) of a 64 x 32 chunk.
+template <bool KC> __device__ __forceinline__ void bf_slot(int t, int &i, int &kq) {
+  if (KC) {
+    i = t >> 2;
+    kq = t & 3;
+  } else {
+    i = t & 63;
+    kq = t >> 6;
+  }
+}
+
+template <bool KC, bool CJ>
+__device__ __forceinline__ void bf_load_op(const TOp<float> &X, int i0, int k0, int K,
+                                           float (&vr)[8], float (&vi)[8]) {
+  int i, kq;
+  bf_slot<KC>(threadIdx.x, i, kq);
+  const int kk = k0 + 8 * kq;
+  const bool ok = (i0 + i < X.rows) && (kk < K);
+  if (KC) {
+    const long o = ok ? (long)(i0 + i) * X.ld + X.col(kk) : 0;
+    const float4 *pr = (const float4 *)(X.re + o), *pi = (const float4 *)(X.im + o);
+    const float4 r0 = pr[0], r1 = pr[1], q0 = pi[0], q1 = pi[1];
+    vr[0] = r0.x; vr[1] = r0.y; vr[2] = r0.z; vr[3] = r0.w;
+    vr[4] = r1.x; vr[5] = r1.y; vr[6] = r1.z; vr[7] = r1.w;
+    vi[0] = q0.x; vi[1] = q0.y; vi[2] = q0.z; vi[3] = q0.w;
+    vi[4] = q1.x; vi[5] = q1.y; vi[6] = q1.z; vi[7] = q1.w;
+  } else {
+    const int c = ok ? X.col(kk) : 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const long o = ok ? (long)(c + q) * X.ld + i0 + i : 0;
+      vr[q] = X.re[o];
+      vi[q] = X.im[o];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    vr[q] = ok ? vr[q] : 0.0f;
+    vi[q] = ok ? (CJ ? -vi[q] : vi[q]) : 0.0f;
+  }
+}
+
+template <bool KC>
+__device__ __forceinline__ void bf_store_op(const float (&vr)[8], const float (&vi)[8],
+                                            __bf16 (&S)[4][64][BF_LDK]) {
+  int i, kq;
+  bf_slot<KC>(threadIdx.x, i, kq);
+  bf16x8 h, l;
+  bf_split8(vr, h, l);
+  *(bf16x8 *)&S[0][i][8 * kq] = h;
+  *(bf16x8 *)&S[1][i][8 * kq] = l;
+  bf_split8(vi, h, l);
+  *(bf16x8 *)&S[2][i][8 * kq] = h;
+  *(bf16x8 *)&S[3][i][8 * kq] = l;
+}
+
+template <bool AKC, bool ACJ, bool BKC, bool BCJ>
+__device__ __forceinline__ void ctile64_bf3(const TOp<float> &A, const TOp<float> &B, int i0,
+                                            int j0, int K, BfLds &L, f32x4 (&acc)[2][2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, g8 = 8 * (lane >> 4);
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  float ar[8], ai[8], br[8], bi[8];
+  bf_load_op<AKC, ACJ>(A, i0, 0, K, ar, ai);
+  bf_load_op<BKC, BCJ>(B, j0, 0, K, br, bi);
+  for (int k0 = 0; k0 < K; k0 += BF_BK) {
+    bf_store_op<AKC>(ar, ai, L.a);
+    bf_store_op<BKC>(br, bi, L.b);
+    __syncthreads();
+    if (k0 + BF_BK < K) {
+      bf_load_op<AKC, ACJ>(A, i0, k0 + BF_BK, K, ar, ai);
+      bf_load_op<BKC, BCJ>(B, j0, k0 + BF_BK, K, br, bi);
+    }
+    bf16x8 fa[2][4], fb[2][4], na[2][2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        fa[m][p] = *(const bf16x8 *)&L.a[p][wr + 16 * m + i][g8];
+        fb[m][p] = *(const bf16x8 *)&L.b[p][wc + 16 * m + i][g8];
+      }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      na[m][0] = bf_neg(fa[m][2]);
+      na[m][1] = bf_neg(fa[m][3]);
+    }
+    // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br, each real product as
+    // hi*hi + hi*lo + lo*hi; consecutive MFMAs go to different accumulators
+#define QOC_BF3_TERM(dst, X, Y)                                                \
+  _Pragma("unroll") for (int m = 0; m < 2; ++m)                                \
+  _Pragma("unroll") for (int n = 0; n < 2; ++n)                                \
+    acc[m][n][dst] = mfma_bf(X, Y, acc[m][n][dst]);
+    QOC_BF3_TERM(0, fa[m][0], fb[n][0])
+    QOC_BF3_TERM(1, fa[m][0], fb[n][2])
+    QOC_BF3_TERM(0, fa[m][0], fb[n][1])
+    QOC_BF3_TERM(1, fa[m][0], fb[n][3])
+    QOC_BF3_TERM(0, fa[m][1], fb[n][0])
+    QOC_BF3_TERM(1, fa[m][1], fb[n][2])
+    QOC_BF3_TERM(0, na[m][0], fb[n][2])
+    QOC_BF3_TERM(1, fa[m][2], fb[n][0])
+    QOC_BF3_TERM(0, na[m][0], fb[n][3])
+    QOC_BF3_TERM(1, fa[m][2], fb[n][1])
+    QOC_BF3_TERM(0, na[m][1], fb[n][2])
+    QOC_BF3_TERM(1, fa[m][3], fb[n][0])
+#undef QOC_BF3_TERM
+    __syncthreads();
+  }
+}
+
+// Dispatch: one 64x64 tile in the chain precision or as bf16x3 (float only).
+// lds must hold max(T64_LDS_ELEMS * sizeof(T), sizeof(BfLds)) bytes.
+template <typename T, bool BF3, bool AKC, bool ACJ, bool BKC, bool BCJ>
+__device__ __forceinline__ void tile64(const TOp<T> &A, const TOp<T> &B, int i0, int j0, int K,
+                                       void *lds, v4<T> (&acc)[2][2][2]) {
+  if constexpr (BF3 && sizeof(T) == 4)
+    ctile64_bf3<AKC, ACJ, BKC, BCJ>(A, B, i0, j0, K, *(BfLds *)lds, acc);
+  else
+    ctile64<T, AKC, ACJ, BKC, BCJ>(A, B, i0, j0, K, (T *)lds, acc);
+}
+
+constexpr int TILE64_LDS_BYTES =
+    (int)sizeof(BfLds) > T64_LDS_ELEMS * 8 ? (int)sizeof(BfLds) : T64_LDS_ELEMS * 8;
+
+// Row / column of element v of accumulator [m][n] of this lane in a 64x64 tile.
+template <typename T>
+__device__ __forceinline__ void tile64_pos(int m, int n, int v, int &r, int &c) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  r = (w >> 1) * 32 + 16 * m + acc_row<T>(lane, v);
+  c = (w & 1) * 32 + 16 * n + (lane & 15);
+}
+
+}  // namespace qoc

@@ -101,6 +101,8 @@ def test_config2_transmon_cnot_full():
     (64, 2, 70, "coherent"),       # 64-tiled product kernels
     (70, 4, 33, "coherent"),       # pad 80, 16-tiled kernels on a non-64 multiple
     (3, 2, 1, "coherent"),         # a single step
+    (64, 48, 20, "coherent"),      # batched adjoint: rank compression at the first level
+    (100, 3, 25, "incoherent"),    # batched adjoint on pad 112 (partial 64-tiles)
 ])
 def test_random_problems(d, S, N, mode):
     rng = np.random.default_rng(100 + d + N)
