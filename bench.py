@@ -8,7 +8,11 @@ forward sweeps with penalties and fidelity, costate sweeps, and the exact
 per-step derivative contracted into dC/du.  Inputs are resident in HBM
 before the timed region.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--config c2|c3|c4|c1]
+  python bench.py [--steps K] [--warmup W] [--config c2|c3|c4|c1|c5]
+
+c5 (256 uneven instances): a step is one optimizer iteration (every
+instance's cost + gradient and an Adam update), replayed from a HIP graph;
+value = sum of N_i over the median iteration time.
 """
 import argparse
 import json
@@ -141,6 +145,104 @@ def cpu_baseline(prob, seconds):
                        f"of {prob.name} ({el:.1f} s)"), (sample, ref)
 
 
+def batch_work(probs, batch):
+    """Algorithmic MFMA flops of one cost+grad over all instances (the
+    counting of algorithmic_work: Taylor/squaring products, block products
+    and the per-step derivative) and their sum over instances."""
+    tot = 0.0
+    for p, h in zip(probs, batch.handles):
+        inf = h.info()
+        d, N, M, S = p.d, p.N, p.M, p.S
+        pp, nn = inf["p"], inf["n"]
+        G = pp - 1 + nn
+        f = N * 8.0 * d ** 3 * G + (N - inf["n_blocks"]) * 8.0 * d ** 3
+        _, fa = algorithmic_work(p, inf, "adjoint", 1, "fp32")
+        tot += f + fa
+    return tot
+
+
+def bench_batch(args):
+    """Uneven batch: every instance's cost + gradient and an Adam update per
+    iteration; graph replays vs eager multi-stream vs per-instance calls."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1612_04929_amd.batch import Batch
+
+    dev = torch.device("cuda:0")
+    probs = workloads.config5()
+    log(f"[bench] c5: {len(probs)} instances, d {min(p.d for p in probs)}..{max(p.d for p in probs)}, "
+        f"sum N = {sum(p.N for p in probs)}, precision={args.precision}")
+    b = Batch(probs, precision=args.precision, streams=args.streams)
+    res_acc = {}
+    if not args.no_cpu_baseline:
+        import oracle
+        order = sorted(range(len(probs)), key=lambda i: probs[i].d ** 3 * probs[i].N)
+        sample = order[:: max(1, len(order) // 6)][:6]
+        worst_F, worst_g = 0.0, 0.0
+        for i in sample:
+            ref = oracle.cost_grad(probs[i])
+            g = b.grad[i][: probs[i].M * probs[i].N].cpu().numpy().reshape(probs[i].M, probs[i].N)
+            dF = abs((1 - float(b.out[i][1])) - ref["F"])
+            gr = float(np.linalg.norm(g - ref["grad"]) / max(np.linalg.norm(ref["grad"]), 1e-300))
+            worst_F, worst_g = max(worst_F, dF), max(worst_g, gr)
+        res_acc = dict(instances=[f"{probs[i].name} d={probs[i].d} N={probs[i].N}" for i in sample],
+                       max_dF=worst_F, max_grad_rel=worst_g)
+        log(f"[bench] c5 accuracy sample: {res_acc}")
+
+    def timed(fn, iters):
+        st = torch.cuda.current_stream(dev)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(iters)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, e in evs:
+            a.record(st)
+            fn()
+            e.record(st)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / iters
+        ms = np.array([a.elapsed_time(e) for a, e in evs])
+        return dict(p50_ms=float(np.percentile(ms, 50)), p99_ms=float(np.percentile(ms, 99)),
+                    mean_ms=float(ms.mean()), wall_ms_per_iter=wall * 1e3, iters=iters)
+
+    iters = max(args.steps, 1)
+    for _ in range(args.warmup):
+        b.iteration(serial=True)
+    serial = timed(lambda: b.iteration(serial=True), max(10, iters // 10))
+    log(f"[bench] c5 per-instance calls: {serial}")
+    eager = timed(lambda: b.iteration(), max(10, iters // 10))
+    log(f"[bench] c5 multi-stream eager: {eager}")
+    b.capture(warmup=args.warmup)
+    graph = timed(b.replay, iters)
+    log(f"[bench] c5 graph replays: {graph}")
+    warn = b.taylor_warnings()
+    flops = batch_work(probs, b)
+    t = graph["p50_ms"] / 1e3
+    value = b.total_steps / t
+    peak = PEAK[args.precision]["mfma"]
+    res = dict(metric=METRIC, value=value, unit="time-steps/s", n_gpus=1, steps=iters,
+               warmup=args.warmup, ms_per_step=graph["p50_ms"], higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype=args.precision,
+               data="synthetic (seeded generators)",
+               config=dict(workload="c5_batched_uneven", instances=len(probs),
+                           sum_N=b.total_steps, d_range=[min(p.d for p in probs),
+                                                         max(p.d for p in probs)],
+                           optimizer="Adam lr=1e-2 (torch, capturable)", streams=len(b.streams),
+                           precision=args.precision),
+               roofline=dict(kernel="whole iteration (graph)", bound="mfma",
+                             achieved=flops / t / 1e12, peak=peak / 1e12, unit="TFLOP/s",
+                             frac=flops / t / peak, traffic=None),
+               graph=graph, eager_multistream=eager, per_instance_calls=serial,
+               speedup_graph_vs_per_instance=serial["p50_ms"] / graph["p50_ms"],
+               taylor_warnings=len(warn))
+    if res_acc:
+        res["accuracy_sample"] = res_acc
+    b.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +253,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-torch-baseline", action="store_true")
+    ap.add_argument("--streams", type=int, default=4, help="c5: streams per iteration")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -163,6 +266,8 @@ def main():
     import workloads
     from paper_1612_04929_amd import qoc
 
+    if args.config == "c5":
+        return bench_batch(args)
     dev = torch.device("cuda:0")
     prob = workloads.make_config(args.config)
     log(f"[bench] {prob.name}: d={prob.d} M={prob.M} N={prob.N} S={prob.S} "

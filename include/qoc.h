@@ -68,7 +68,11 @@ enum { QOC_FP64 = 0, QOC_FP32 = 1, QOC_BF16X3 = 2 };
 enum { QOC_FID_COHERENT = 0, QOC_FID_INCOHERENT = 1 };
 
 /* Bits of *flags_out. */
-enum { QOC_WARN_DRIFT = 1 };
+enum {
+  QOC_WARN_DRIFT = 1,  /* norm drift of the propagated columns above drift_warn */
+  QOC_WARN_TAYLOR = 2  /* a fixed (taylor_p, taylor_n) misses taylor_tol at this
+                          call's theta_max (the call still uses the fixed pair) */
+};
 
 typedef struct {
   int d;                    /* Hilbert-space dimension, 1 <= d <= 1024     */
@@ -110,6 +114,7 @@ typedef struct {
   int block_len;            /* checkpoint interval L actually used           */
   int n_blocks;             /* ceil(N / L)                                   */
   int d_pad;                /* device padding of d (multiple of 16)          */
+  int flags;                /* warning bits (QOC_WARN_*) of the last call    */
   size_t device_bytes;      /* device memory held by the handle              */
 } qoc_info;
 
@@ -140,7 +145,10 @@ qoc_status qoc_cost_grad(qoc_handle *h, const double *u, double *cost,
  * [C, C_fid, c_1, ..., c_N]; grad_dev: M*N doubles.  Work is enqueued on
  * `stream` (a hipStream_t; NULL = the default stream).  When (p, n) is not
  * fixed in the descriptor the call synchronises `stream` once to read
- * theta_max back; with a fixed (p, n) it is fully asynchronous. */
+ * theta_max back (padded d >= 64; smaller d choose (p, n) on the device);
+ * with a fixed (p, n) it is fully asynchronous and capturable in a HIP
+ * graph, the fixed pair being checked against taylor_tol on the device
+ * (QOC_WARN_TAYLOR in qoc_info.flags). */
 qoc_status qoc_cost_grad_device(qoc_handle *h, const double *u_dev,
                                 double *out_dev, double *grad_dev, void *stream);
 
@@ -185,6 +193,13 @@ qoc_status qoc_profile_read(qoc_handle *h, double *ms, long long *calls,
  * 2^n (theta/2^n)^(p+1)/(p+1)! e^(theta/2^n) <= tol, ties to smaller n,
  * p >= 2 (Sec. III: global conservative truncation and scaling). */
 qoc_status qoc_taylor_select(double theta, double tol, int *p, int *n);
+
+/* Fix the global (p, n) of later calls on h (p in [2, 64], n in [0, 60]),
+ * or return to the per-call choice (p = 0).  A fixed pair makes the
+ * device-pointer calls free of host round trips (HIP-graph capturable);
+ * each call checks it against taylor_tol on the device and reports a miss
+ * as QOC_WARN_TAYLOR.  Sec. III: one conservative pair for all steps. */
+qoc_status qoc_set_taylor(qoc_handle *h, int p, int n);
 
 void qoc_destroy(qoc_handle *h);
 const char *qoc_status_string(qoc_status s);

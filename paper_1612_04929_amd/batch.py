@@ -1,0 +1,138 @@
+"""Many independent control problems per optimizer iteration.
+
+A :class:`Batch` holds one libqoc handle per instance (uneven d, N, M), the
+instances' amplitudes, outputs and gradients as device tensors, and
+torch's capturable Adam over the amplitudes (the optimizer of the
+workload, not part of the cost + gradient path).  One iteration enqueues
+``qoc_cost_grad_batched`` for every instance, split over a few streams
+(default priority) forked from and joined back into the current stream,
+then the Adam update.  Handles whose padded d is 64 or more get a fixed
+(p, n) chosen from their initial theta_max times a margin, so no call
+needs a host round trip (smaller d choose (p, n) on the device anyway);
+the device checks a fixed pair against the tolerance on every call
+(QOC_WARN_TAYLOR, see :meth:`taylor_warnings`).  The whole iteration can
+then be captured in one HIP graph and replayed.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import heapq
+
+import numpy as np
+import torch
+
+from . import qoc
+
+
+class Batch:
+    def __init__(self, problems, precision="fp32", streams=4, device=0, margin=1.1,
+                 lr=1e-2, betas=(0.9, 0.999), eps=1e-8):
+        self.dev = torch.device(f"cuda:{device}")
+        self.problems = list(problems)
+        self.handles = [qoc.Problem(p, precision=precision, device=device) for p in self.problems]
+        f64 = torch.float64
+        self.u = [torch.tensor(np.asarray(p.u, dtype=np.float64).reshape(p.M, p.N), dtype=f64,
+                               device=self.dev).requires_grad_(True) for p in self.problems]
+        self.out = [torch.zeros(2 + p.N, dtype=f64, device=self.dev) for p in self.problems]
+        self.grad = [torch.zeros(max(1, p.M * p.N), dtype=f64, device=self.dev)
+                     for p in self.problems]
+        for u, g, p in zip(self.u, self.grad, self.problems):
+            u.grad = g[: p.M * p.N].view(p.M, p.N)
+        self.total_steps = int(sum(p.N for p in self.problems))
+        # initial (p, n): one call per instance, then fix the pair of the
+        # instances that would otherwise read theta_max back on the host
+        st = torch.cuda.current_stream(self.dev).cuda_stream
+        for h, u, o, g in zip(self.handles, self.u, self.out, self.grad):
+            h.cost_grad_device(u.data_ptr(), o.data_ptr(), g.data_ptr(), st)
+        torch.cuda.synchronize(self.dev)
+        self.pn = []
+        for h in self.handles:
+            inf = h.info()
+            if inf["d_pad"] >= 64:
+                tol = 1e-15 if precision == "fp64" else 1e-10
+                p, n = qoc.taylor_select(inf["theta_max"] * margin, tol)
+                h.set_taylor(p, n)
+                self.pn.append((p, n))
+            else:
+                self.pn.append(None)
+        # longest-processing-time assignment of instances to streams
+        cost = [p.N * (max(16, (p.d + 15) // 16 * 16) ** 3 + 16 ** 3 * 8) for p in self.problems]
+        nstr = max(1, int(streams))
+        heap = [(0.0, k) for k in range(nstr)]
+        self.groups = [[] for _ in range(nstr)]
+        for i in sorted(range(len(cost)), key=lambda i: -cost[i]):
+            load, k = heapq.heappop(heap)
+            self.groups[k].append(i)
+            heapq.heappush(heap, (load + cost[i], k))
+        self.groups = [g for g in self.groups if g]
+        self.streams = [torch.cuda.Stream(self.dev) for _ in self.groups]
+        self._fork = torch.cuda.Event()
+        self._join = [torch.cuda.Event() for _ in self.groups]
+        self._arrays = []
+        for g in self.groups:
+            B = len(g)
+            arr = lambda xs: (C.c_void_p * B)(*[C.c_void_p(int(x)) for x in xs])
+            self._arrays.append((B, (C.c_void_p * B)(*[self.handles[i]._h for i in g]),
+                                 arr([self.u[i].data_ptr() for i in g]),
+                                 arr([self.out[i].data_ptr() for i in g]),
+                                 arr([self.grad[i].data_ptr() for i in g])))
+        self.opt = torch.optim.Adam(self.u, lr=lr, betas=betas, eps=eps, capturable=True,
+                                    foreach=True)
+        self.graph = None
+
+    # ------------------------------------------------------------------
+    def cost_grad(self):
+        """Enqueue cost + gradient of every instance (multi-stream fork/join)."""
+        lib = qoc.load()
+        main = torch.cuda.current_stream(self.dev)
+        self._fork.record(main)
+        for s, ev, (B, hs, us, outs, grads) in zip(self.streams, self._join, self._arrays):
+            s.wait_event(self._fork)
+            qoc._check(lib.qoc_cost_grad_batched(B, hs, us, outs, grads,
+                                                 C.c_void_p(s.cuda_stream)))
+            ev.record(s)
+        for ev in self._join:
+            main.wait_event(ev)
+
+    def cost_grad_serial(self):
+        """Per-instance calls on the current stream (the unbatched baseline)."""
+        st = torch.cuda.current_stream(self.dev).cuda_stream
+        for h, u, o, g in zip(self.handles, self.u, self.out, self.grad):
+            h.cost_grad_device(u.data_ptr(), o.data_ptr(), g.data_ptr(), st)
+
+    def iteration(self, serial=False):
+        (self.cost_grad_serial if serial else self.cost_grad)()
+        self.opt.step()
+
+    def capture(self, warmup=3):
+        """Capture one iteration (all cost + gradient calls and the Adam
+        update) in a HIP graph; warm-up iterations run first on a side
+        stream."""
+        side = torch.cuda.Stream(self.dev)
+        side.wait_stream(torch.cuda.current_stream(self.dev))
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                self.iteration()
+        torch.cuda.current_stream(self.dev).wait_stream(side)
+        torch.cuda.synchronize(self.dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.iteration()
+        torch.cuda.synchronize(self.dev)
+
+    def replay(self):
+        self.graph.replay()
+
+    # ------------------------------------------------------------------
+    def costs(self):
+        return np.array([float(o[0]) for o in self.out])
+
+    def taylor_warnings(self):
+        """Indices of instances whose fixed (p, n) missed the tolerance on
+        their last call."""
+        return [i for i, h in enumerate(self.handles) if h.info()["flags"] & qoc.QOC_WARN_TAYLOR]
+
+    def close(self):
+        for h in self.handles:
+            h.close()
+        self.handles = []

@@ -262,6 +262,22 @@ template <typename T> hipError_t launch_fill(T *p, long n, T v, hipStream_t st) 
   return hipGetLastError();
 }
 
+template <typename T> __global__ void k_copy(T *dst, const T *src, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+template <typename T> hipError_t launch_copy(T *dst, const T *src, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  long blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)blocks), dim3(256), 0, st, dst, src, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_copy<float>(float *, const float *, long, hipStream_t);
+template hipError_t launch_copy<double>(double *, const double *, long, hipStream_t);
 template hipError_t launch_assemble<float>(const float *, const double *, int, int, int, float,
                                            float, float *, float *, hipStream_t);
 template hipError_t launch_assemble<double>(const double *, const double *, int, int, int, double,

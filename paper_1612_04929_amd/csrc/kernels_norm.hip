@@ -4,19 +4,24 @@
 // for all steps instead of estimating each step's spectral radius
 // (Sec. III); this kernel supplies the global norm that choice is made
 // from, in FP64 from the FP64 copies of the Hamiltonians.
+#include <type_traits>
+
 #include "qoc_device.h"
 #include "qoc_kernels.h"
 
 namespace qoc {
 
-// Block: 64 columns (one per lane) x NRM_STEPS steps (NRM_SW per wave);
-// each Hamiltonian entry loaded feeds NRM_SW steps, and the 4 waves of a
-// block read the same entries (L1 hits).  NRM_KC control Hamiltonians are
-// held in registers at a time.
-constexpr int NRM_SW = 4, NRM_STEPS = 4 * NRM_SW, NRM_KC = 8;
+// Block: COLS columns (one per thread, COLS = 64 for d > 32, else 32 or 16)
+// x (256 / COLS) step lanes, each thread NRM_SW steps; each Hamiltonian
+// entry loaded feeds NRM_SW steps, and the step lanes of a block read the
+// same entries (L1 hits).  NRM_KC control Hamiltonians are held in
+// registers at a time.
+constexpr int NRM_SW = 4, NRM_KC = 8;
 
 // (p, n) from theta by the rule of qoc_taylor_select, one wavefront, one
-// lane per squaring count n; returns {p, n, status} and dt / 2^n.
+// lane per squaring count n; returns {p, n, status} and dt / 2^n.  status:
+// 0 ok, 1 no pair / pair beyond the caps (error), 2 a fixed pair that
+// misses the tolerance (warning).
 __device__ void select_pn(double theta, double dt, double tol, int n_cap, int p_cap, int fixed_p,
                           int fixed_n, int *pn, double *sc) {
   const int lane = threadIdx.x & 63;
@@ -48,9 +53,18 @@ __device__ void select_pn(double theta, double dt, double tol, int n_cap, int p_
     int p = bp, n = bn, status = 0;
     bool found = best != 0x7fffffffffffL;
     if (fixed_p >= 2) {
+      // a fixed pair is used as given; status 2 flags that it misses the
+      // tolerance at this theta
       p = fixed_p;
       n = fixed_n;
       found = true;
+      const double x = ldexp(theta, -n);
+      double f = 1.0, pw = x;
+      for (int q = 1; q <= p; ++q) {
+        f *= (q + 1);
+        pw *= x;
+      }
+      if (!(ldexp(1.0, n) * pw / f * exp(x) <= tol)) status = 2;
     }
     if (!found || !(theta >= 0.0)) {
       status = 1;
@@ -69,23 +83,26 @@ __device__ void select_pn(double theta, double dt, double tol, int n_cap, int p_
   }
 }
 
+template <int COLS>
 __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
                                               const double *__restrict__ u, int d, int M, int N,
                                               double dt, unsigned long long *theta_bits,
                                               SelectArgs sel) {
-  extern __shared__ double coef[];  // [NRM_STEPS][M] control amplitudes of the block's steps
+  constexpr int LANES = 256 / COLS, STEPS = LANES * NRM_SW;
+  extern __shared__ double coef[];  // [STEPS][M] control amplitudes of the block's steps
   __shared__ unsigned long long red[4];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int col = blockIdx.y * 64 + lane;
-  const int j0 = blockIdx.x * NRM_STEPS;
-  for (int e = t; e < NRM_STEPS * M; e += 256) {
+  const int t = threadIdx.x;
+  const int sl = t / COLS;
+  const int col = blockIdx.y * COLS + (t - sl * COLS);
+  const int j0 = blockIdx.x * STEPS;
+  for (int e = t; e < STEPS * M; e += 256) {
     const int sj = e / M, k = e - sj * M;
     coef[e] = (j0 + sj < N) ? u[(long)k * N + j0 + sj] : 0.0;
   }
   __syncthreads();
-  // wave w: steps j0 + NRM_SW w .. + NRM_SW - 1 (coefficient reads are
-  // wave-uniform LDS broadcasts); lane: one column; rows streamed
-  const double *cw = coef + w * NRM_SW * M;
+  // step lane sl: steps j0 + NRM_SW sl .. + NRM_SW - 1 (LDS broadcasts of
+  // the coefficients); column col; rows streamed
+  const double *cw = coef + sl * NRM_SW * M;
   double nrm[NRM_SW];
 #pragma unroll
   for (int s = 0; s < NRM_SW; ++s) nrm[s] = 0.0;
@@ -127,7 +144,7 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
   unsigned long long v = 0ull;
 #pragma unroll
   for (int s = 0; s < NRM_SW; ++s) {
-    if (col < d && j0 + w * NRM_SW + s < N) {
+    if (col < d && j0 + sl * NRM_SW + s < N) {
       const double x = dt * nrm[s];
       const unsigned long long b =
           (x != x) ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(x);
@@ -160,9 +177,19 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
 
 hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, double dt,
                        unsigned long long *theta_bits, const SelectArgs &sel, hipStream_t st) {
-  dim3 grid((N + NRM_STEPS - 1) / NRM_STEPS, (d + 63) / 64);
-  const size_t shm = sizeof(double) * NRM_STEPS * M;
-  hipLaunchKernelGGL(k_norm, grid, dim3(256), shm, st, H64, u, d, M, N, dt, theta_bits, sel);
+  auto go = [&](auto cols) {
+    constexpr int COLS = decltype(cols)::value, STEPS = 256 / COLS * NRM_SW;
+    dim3 grid((N + STEPS - 1) / STEPS, (d + COLS - 1) / COLS);
+    const size_t shm = sizeof(double) * STEPS * M;
+    hipLaunchKernelGGL(k_norm<COLS>, grid, dim3(256), shm, st, H64, u, d, M, N, dt, theta_bits,
+                       sel);
+  };
+  if (d > 32)
+    go(std::integral_constant<int, 64>());
+  else if (d > 16)
+    go(std::integral_constant<int, 32>());
+  else
+    go(std::integral_constant<int, 16>());
   return hipGetLastError();
 }
 

@@ -77,6 +77,7 @@ struct qoc_handle {
   // problem
   int d = 0, dp = 0, M = 0, N = 0, S = 0, prec = QOC_FP32, fid_mode = 0;
   int bf3 = 0;  // bf16x3 split products in the batched chains (padded d >= 64)
+  int last_flags = 0;  // warning bits of the last call
   double dt = 0, a_fid = 0, a_amp = 0, a_var = 0, a_pen = 0, tol = 0, drift_warn = 0;
   bool has_pen = false;
   int fixed_p = 0, fixed_n = 0;
@@ -433,7 +434,12 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     HIP_TRY(qoc::launch_fill<unsigned long long>(h->bits, 4, 0ull, st));
     {
       PhaseTimer tm(h, QOC_PHASE_NORM, st);
+      // a fixed (p, n) is checked against the tolerance on the device
+      // (status 2 in pn_dev), so the call needs no host round trip
       qoc::SelectArgs sel{};
+      if (h->fixed_p >= 2)
+        sel = qoc::SelectArgs{h->pn_dev, h->sc_dev, (unsigned *)(h->bits + 2), h->tol, 60, 30,
+                              h->fixed_p, h->fixed_n};
       HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, sel, st));
     }
     if (h->fixed_p >= 2) {
@@ -497,8 +503,7 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
       HIP_TRY(qoc::launch_stage<T>(0, a, st));
       tm.done();
       if (cnt & 1)
-        HIP_TRY(hipMemcpyAsync(outb + pairs * mat, in + (cnt - 1) * mat, mat * sizeof(T),
-                               hipMemcpyDeviceToDevice, st));
+        HIP_TRY(qoc::launch_copy<T>(outb + pairs * mat, in + (cnt - 1) * mat, mat, st));
       cnt = (cnt + 1) / 2;
       in = outb;
       outb = (outb == Qa) ? Qb : Qa;
@@ -586,20 +591,23 @@ qoc_status finish_diag(qoc_handle *h, hipStream_t st, int *flags) {
   const bool small_path = h->prec == QOC_FP64
                               ? (qoc::small_expm_ok<double>(h->dp) && qoc::small_sweep_ok<double>(h->dp, h->S))
                               : (qoc::small_expm_ok<float>(h->dp) && qoc::small_sweep_ok<float>(h->dp, h->S));
-  if (small_path) HIP_TRY(hipMemcpyAsync(pn, h->pn_dev, sizeof(pn), hipMemcpyDeviceToHost, st));
+  const bool dev_pn = small_path || h->fixed_p >= 2;
+  if (dev_pn) HIP_TRY(hipMemcpyAsync(pn, h->pn_dev, sizeof(pn), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (small_path) {
+  if (dev_pn) {
     h->last_p = pn[0];
     h->last_n = pn[1];
-    if (pn[2]) return fail(QOC_ERR_UNSUPPORTED, "the (p, n) required by theta_max exceeds the "
-                                                "preallocated capacity of the small-d path");
+    if (pn[2] == 1) return fail(QOC_ERR_UNSUPPORTED, "the (p, n) required by theta_max exceeds the "
+                                                     "preallocated capacity of the small-d path");
   }
   double th, dr;
   std::memcpy(&th, &b[0], 8);
   std::memcpy(&dr, &b[1], 8);
   h->last_theta = th;
   h->last_drift = dr;
-  if (flags) *flags = (dr > h->drift_warn) ? QOC_WARN_DRIFT : 0;
+  h->last_flags = ((dr > h->drift_warn) ? QOC_WARN_DRIFT : 0) |
+                  ((dev_pn && pn[2] == 2) ? QOC_WARN_TAYLOR : 0);
+  if (flags) *flags = h->last_flags;
   if (h->prof) return drain_pending(h);
   return QOC_OK;
 }
@@ -638,6 +646,15 @@ qoc_status qoc_taylor_select(double theta, double tol, int *p, int *n) {
   if (!(theta >= 0.0) || !std::isfinite(theta) || !(tol > 0.0))
     return fail(QOC_ERR_ARG, "theta must be finite and >= 0, tol > 0");
   if (!taylor_select(theta, tol, p, n)) return fail(QOC_ERR_UNSUPPORTED, "no (p, n) meets tol");
+  return QOC_OK;
+}
+
+qoc_status qoc_set_taylor(qoc_handle *h, int p, int n) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  if (!(p == 0 || (p >= 2 && p <= 64 && n >= 0 && n <= 60)))
+    return fail(QOC_ERR_ARG, "p must be 0 (automatic) or in [2, 64] with n in [0, 60]");
+  h->fixed_p = p;
+  h->fixed_n = p ? n : 0;
   return QOC_OK;
 }
 
@@ -874,7 +891,10 @@ qoc_status qoc_get_info(const qoc_handle *hc, qoc_info *info) {
       h->last_p = pn[0];
       h->last_n = pn[1];
     }
+    h->last_flags = ((h->last_drift > h->drift_warn) ? QOC_WARN_DRIFT : 0) |
+                    (((small_path || h->fixed_p >= 2) && pn[2] == 2) ? QOC_WARN_TAYLOR : 0);
   }
+  info->flags = h->last_flags;
   info->p = h->last_p;
   info->n = h->last_n;
   info->theta_max = h->last_theta;

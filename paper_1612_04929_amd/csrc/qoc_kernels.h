@@ -31,8 +31,9 @@ template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hi
 
 // Device-side (p, n) choice made by the last workgroup of the norm kernel
 // (pn = null: no choice).  pn = {p, n, status}, sc = {dt / 2^n, theta};
-// status 1 when the pair exceeds n_cap / p_cap or none meets tol.  `ticket`
-// must be zero at launch.
+// status 1 when the pair exceeds n_cap / p_cap or none meets tol, 2 when a
+// fixed pair (fixed_p >= 2) misses tol at this theta.  `ticket` must be
+// zero at launch.
 struct SelectArgs {
   int *pn;
   double *sc;
@@ -45,6 +46,8 @@ hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, 
                        unsigned long long *theta_bits, const SelectArgs &sel, hipStream_t st);
 
 template <typename T> hipError_t launch_fill(T *p, long n, T v, hipStream_t st);
+// dst[0:n] = src[0:n] (a kernel, so that captured graphs hold no copy nodes)
+template <typename T> hipError_t launch_copy(T *dst, const T *src, long n, hipStream_t st);
 
 // Small padded d (16, 32; 48 in FP32): the whole Taylor + squaring chain of
 // a step in LDS, (p, n, dt/2^n) read from device memory (pn, sc).  Level

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libqoc.so")
 QOC_FP64, QOC_FP32, QOC_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": QOC_FP64, "fp32": QOC_FP32, "bf16x3": QOC_BF16X3}
 QOC_FID_COHERENT, QOC_FID_INCOHERENT = 0, 1
-QOC_WARN_DRIFT = 1
+QOC_WARN_DRIFT, QOC_WARN_TAYLOR = 1, 2
 PHASES = ["norm", "assemble", "taylor", "blockprod", "fwd_blocks", "fwd_replay", "cost",
           "bwd_blocks", "bwd_pairs", "adjoint"]
 STATUS = {0: "QOC_OK", -1: "QOC_ERR_ARG", -2: "QOC_ERR_SHAPE", -3: "QOC_ERR_NOT_HERMITIAN",
@@ -27,7 +27,8 @@ STATUS = {0: "QOC_OK", -1: "QOC_ERR_ARG", -2: "QOC_ERR_SHAPE", -3: "QOC_ERR_NOT_
           -7: "QOC_ERR_UNSUPPORTED"}
 EXPORTS = ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
            "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
-           "qoc_profile_read", "qoc_taylor_select", "qoc_destroy", "qoc_status_string",
+           "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_destroy",
+           "qoc_status_string",
            "qoc_last_error", "qoc_version"]
 
 _dp = C.POINTER(C.c_double)
@@ -46,7 +47,7 @@ class Desc(C.Structure):
 class Info(C.Structure):
     _fields_ = [("p", C.c_int), ("n", C.c_int), ("theta_max", C.c_double),
                 ("norm_drift", C.c_double), ("block_len", C.c_int), ("n_blocks", C.c_int),
-                ("d_pad", C.c_int), ("device_bytes", C.c_size_t)]
+                ("d_pad", C.c_int), ("flags", C.c_int), ("device_bytes", C.c_size_t)]
 
 
 class QocError(RuntimeError):
@@ -79,6 +80,7 @@ def load(path: str = LIB_PATH):
     lib.qoc_profile_read.argtypes = [vp, _dp, C.POINTER(C.c_longlong), C.c_int]
     lib.qoc_taylor_select.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]
+    lib.qoc_set_taylor.argtypes = [vp, C.c_int, C.c_int]
     lib.qoc_destroy.argtypes = [vp]
     lib.qoc_destroy.restype = None
     for f in ["qoc_status_string", "qoc_last_error", "qoc_version"]:
@@ -86,7 +88,7 @@ def load(path: str = LIB_PATH):
     lib.qoc_status_string.argtypes = [C.c_int]
     for f in ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
               "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
-              "qoc_profile_read", "qoc_taylor_select"]:
+              "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor"]:
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -161,7 +163,7 @@ class Problem:
         flags = C.c_int()
         _check(load().qoc_forward(self._h, pu, C.byref(cf), c.ctypes.data_as(_dp),
                                   psiN.view(np.float64).ctypes.data_as(_dp), C.byref(flags)))
-        return dict(C_fid=cf.value, c=c, psiN=psiN, flags=flags.value, **self.info())
+        return {**self.info(), **dict(C_fid=cf.value, c=c, psiN=psiN, flags=flags.value)}
 
     def cost_grad(self, u):
         u, pu = self._u(u)
@@ -172,20 +174,24 @@ class Problem:
         _check(load().qoc_cost_grad(self._h, pu, C.byref(cc), C.byref(cf),
                                     c.ctypes.data_as(_dp), g.ctypes.data_as(_dp),
                                     C.byref(flags)))
-        return dict(C=cc.value, C_fid=cf.value, c=c, grad=g[: self.M], flags=flags.value,
-                    **self.info())
+        return {**self.info(), **dict(C=cc.value, C_fid=cf.value, c=c, grad=g[: self.M],
+                                      flags=flags.value)}
 
     # -- device-pointer call (e.g. torch tensors) ---------------------------
     def cost_grad_device(self, u_ptr: int, out_ptr: int, grad_ptr: int, stream: int = 0):
         _check(load().qoc_cost_grad_device(self._h, C.c_void_p(u_ptr), C.c_void_p(out_ptr),
                                            C.c_void_p(grad_ptr), C.c_void_p(stream)))
 
+    def set_taylor(self, p: int, n: int = 0):
+        """Fix (p, n) for later calls (p = 0: choose per call)."""
+        _check(load().qoc_set_taylor(self._h, int(p), int(n)))
+
     def info(self):
         inf = Info()
         _check(load().qoc_get_info(self._h, C.byref(inf)))
         return dict(p=inf.p, n=inf.n, theta_max=inf.theta_max, norm_drift=inf.norm_drift,
                     block_len=inf.block_len, n_blocks=inf.n_blocks, d_pad=inf.d_pad,
-                    device_bytes=inf.device_bytes)
+                    flags=inf.flags, device_bytes=inf.device_bytes)
 
     def profile_enable(self, on=True):
         _check(load().qoc_profile_enable(self._h, 1 if on else 0))

@@ -40,15 +40,16 @@ def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "lay.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "qoc.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(qoc_problem_desc),'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(qoc_problem_desc),'
         ' offsetof(qoc_problem_desc, taylor_tol), offsetof(qoc_problem_desc, device),'
-        ' sizeof(qoc_info), offsetof(qoc_info, device_bytes)); return 0;}\n')
+        ' sizeof(qoc_info), offsetof(qoc_info, device_bytes), offsetof(qoc_info, flags));'
+        ' return 0;}\n')
     exe = tmp_path / "lay"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
     assert got == [C.sizeof(qoc.Desc), qoc.Desc.taylor_tol.offset, qoc.Desc.device.offset,
-                   C.sizeof(qoc.Info), qoc.Info.device_bytes.offset]
+                   C.sizeof(qoc.Info), qoc.Info.device_bytes.offset, qoc.Info.flags.offset]
 
 
 @pytest.mark.parametrize("theta", [0.0, 1e-6, 0.034, 0.37, 0.78, 1.22, 4.66, 6.5, 30.0])
@@ -103,3 +104,8 @@ def test_status_strings():
     for s in range(-7, 1):
         assert lib.qoc_status_string(s)
     assert lib.qoc_version().decode().startswith("libqoc")
+
+
+def test_set_taylor_validates_arguments():
+    lib = qoc.load()
+    assert lib.qoc_set_taylor(None, 8, 2) == -1
