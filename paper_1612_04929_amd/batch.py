@@ -6,9 +6,10 @@ torch's capturable Adam over the amplitudes (the optimizer of the
 workload, not part of the cost + gradient path).  One iteration enqueues
 ``qoc_cost_grad_batched`` for every instance, split over a few streams
 (default priority) forked from and joined back into the current stream,
-then the Adam update.  Handles whose padded d is 64 or more get a fixed
-(p, n) chosen from their initial theta_max times a margin, so no call
-needs a host round trip (smaller d choose (p, n) on the device anyway);
+then the Adam update.  Handles whose padded d is 32 or more get a fixed
+(p, n) chosen from their initial theta_max times a margin: from 64 on no
+call then needs a host round trip, and from 32 on the per-step derivative
+runs as batched tile products (padded d 16 choose (p, n) on the device);
 the device checks a fixed pair against the tolerance on every call
 (QOC_WARN_TAYLOR, see :meth:`taylor_warnings`).  The whole iteration can
 then be captured in one HIP graph and replayed.
@@ -48,7 +49,7 @@ class Batch:
         self.pn = []
         for h in self.handles:
             inf = h.info()
-            if inf["d_pad"] >= 64:
+            if inf["d_pad"] >= 32:
                 tol = 1e-15 if precision == "fp64" else 1e-10
                 p, n = qoc.taylor_select(inf["theta_max"] * margin, tol)
                 h.set_taylor(p, n)

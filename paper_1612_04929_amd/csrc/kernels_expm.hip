@@ -164,6 +164,84 @@ __global__ __launch_bounds__(256) void k_stage64(StageArgs<T> a, long padded) {
                     acc[m][n][0][v], acc[m][n][1][v]);
 }
 
+// dp a multiple of 16 but not of 64 (80, 96, 112, ...): one workgroup per
+// 32x32 output tile (4 waves, one 16x16 MFMA tile each), operand chunks of
+// 16 inner indices staged in LDS; rows / columns beyond dp read as zero and
+// are not stored.  Waste is at most (dp + 16)^2 / dp^2 instead of the
+// (dp + 48)^2 / dp^2 of 64-wide tiles.
+constexpr int T32_BK = 16, T32_LD = 32 + 16;
+
+template <typename T, int OPA>
+__global__ __launch_bounds__(256) void k_stage32(StageArgs<T> a, long padded) {
+  __shared__ T Asr[T32_BK * T32_LD], Asi[T32_BK * T32_LD];
+  __shared__ T Bsr[T32_BK * T32_LD], Bsi[T32_BK * T32_LD];
+  const int t1 = (a.dp + 31) >> 5;
+  const long tiles = (long)t1 * t1;
+  const long logical = xcd_logical_block(blockIdx.x, padded);
+  if (logical >= (long)a.nmat * tiles) return;  // block-uniform
+  const long j = logical / tiles;
+  const int tt = (int)(logical - j * tiles);
+  const int r0 = (tt / t1) * 32, c0 = (tt % t1) * 32;
+  const int dp = a.dp;
+  const long plane = (long)dp * dp;
+  const T *Aj = a.A + j * a.strideA, *Bj = a.B + j * a.strideB;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
+  v4<T> cr = vzero<T>(), ci = vzero<T>();
+  for (int k0 = 0; k0 < dp; k0 += T32_BK) {
+    // op(A)[r0 .. r0+31][k0 .. k0+15] as As[k][r]; two elements per thread
+    if (OPA == 0) {
+      const int r = t >> 3, kq = (t & 7) * 2;
+      const bool ok = r0 + r < dp;
+      const long o = ok ? (long)(r0 + r) * dp + k0 + kq : 0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const T vr = Aj[o + q], vi = Aj[plane + o + q];
+        Asr[(kq + q) * T32_LD + r] = ok ? vr : (T)0;
+        Asi[(kq + q) * T32_LD + r] = ok ? vi : (T)0;
+      }
+    } else {
+      const int k = t >> 4, rq = (t & 15) * 2;
+      const bool ok = r0 + rq < dp;
+      const long o = ok ? (long)(k0 + k) * dp + r0 + rq : 0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const T vr = Aj[o + q], vi = Aj[plane + o + q];
+        Asr[k * T32_LD + rq + q] = ok ? vr : (T)0;
+        Asi[k * T32_LD + rq + q] = ok ? -vi : (T)0;
+      }
+    }
+    {
+      const int k = t >> 4, cq = (t & 15) * 2;
+      const bool ok = c0 + cq < dp;
+      const long o = ok ? (long)(k0 + k) * dp + c0 + cq : 0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const T vr = Bj[o + q], vi = Bj[plane + o + q];
+        Bsr[k * T32_LD + cq + q] = ok ? vr : (T)0;
+        Bsi[k * T32_LD + cq + q] = ok ? vi : (T)0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < T32_BK; k4 += 4) {
+      const T ar = Asr[(k4 + kk) * T32_LD + wr + i], ai = Asi[(k4 + kk) * T32_LD + wr + i];
+      const T br = Bsr[(k4 + kk) * T32_LD + wc + i], bi = Bsi[(k4 + kk) * T32_LD + wc + i];
+      cr = mfma4(ar, br, cr);
+      cr = mfma4(-ai, bi, cr);
+      ci = mfma4(ar, bi, ci);
+      ci = mfma4(ai, br, ci);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = r0 + wr + acc_row<T>(lane, v), col = c0 + wc + (lane & 15);
+    if (row < dp && col < dp) stage_store(a, j, row, col, cr[v], ci[v]);
+  }
+}
+
 // bf16x3 variant of k_stage64 (FP32 storage; the split-product tile of
 // qoc_tile.h), same tiling, epilogue and block order.
 template <int OPA>
@@ -236,6 +314,14 @@ template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hi
       hipLaunchKernelGGL((k_stage64<T, 1>), dim3((unsigned)padded), dim3(256), 0, st, a, padded);
     else
       hipLaunchKernelGGL((k_stage64<T, 0>), dim3((unsigned)padded), dim3(256), 0, st, a, padded);
+  } else if (a.dp > 48) {
+    const long t1 = (a.dp + 31) / 32;
+    const long total = (long)a.nmat * t1 * t1;
+    const long padded = (total + 7) / 8 * 8;
+    if (opa)
+      hipLaunchKernelGGL((k_stage32<T, 1>), dim3((unsigned)padded), dim3(256), 0, st, a, padded);
+    else
+      hipLaunchKernelGGL((k_stage32<T, 0>), dim3((unsigned)padded), dim3(256), 0, st, a, padded);
   } else {
     const long t1 = a.dp / 16;
     const long total = (long)a.nmat * t1 * t1;

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "qoc_kernels.h"
@@ -272,9 +273,9 @@ template <typename T> qoc_status ensure_levels(qoc_handle *h, int levels) {
   return QOC_OK;
 }
 
-template <typename T> qoc_status ensure_adjoint(qoc_handle *h, int p, int Rcap) {
+template <typename T> qoc_status ensure_adjoint(qoc_handle *h, int p, int Rcap, bool big) {
   long total;
-  if (qoc::adjoint_big_ok<T>(h->dp)) {
+  if (big) {
     // batched large-d adjoint: scratch per step, partial sums per tile
     total = qoc::adjoint_big_scratch_per_step<T>(h->dp, p, Rcap) * (long)h->N;
     const long parts = (long)h->N * qoc::adjoint_big_slices(h->dp) * std::max(h->M, 1);
@@ -393,6 +394,20 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
 }
 
 // ------------------------------------------------------------------ pipeline
+// A fixed (p, n) on the small-d path, as the device applies it (clamped to
+// the preallocated capacity), and the cotangent rank bound it implies.
+std::pair<int, int> small_fixed_pn(const qoc_handle *h) {
+  return {std::min(h->fixed_p, kSmallPCap), std::min(h->fixed_n, kSmallNCap)};
+}
+int small_fixed_rcap(const qoc_handle *h) {
+  const int n = small_fixed_pn(h).second;
+  const long raw = n >= 30 ? h->dp : std::min<long>((long)h->S << n, h->dp);
+  return (int)std::min<long>((raw + 15) & ~15L, h->dp);
+}
+template <typename T> bool small_big_adjoint(const qoc_handle *h) {
+  return h->fixed_p >= 2 && h->dp >= 32 && !qoc::adjoint16_ok<T>(h->dp, kSmallPCap);
+}
+
 template <typename T>
 qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad_dev,
                hipStream_t st, bool want_grad) {
@@ -408,9 +423,13 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     const int n_cap = kSmallNCap, p_cap = kSmallPCap;
     qoc_status s = ensure_levels<T>(h, n_cap + 1);
     if (s) return s;
-    if (want_grad && !qoc::adjoint16_ok<T>(dp, p_cap) &&
-        (s = ensure_adjoint<T>(h, p_cap, dp)) != QOC_OK)
-      return s;
+    if (want_grad && !qoc::adjoint16_ok<T>(dp, p_cap)) {
+      if (small_big_adjoint<T>(h))
+        s = ensure_adjoint<T>(h, small_fixed_pn(h).first, small_fixed_rcap(h), true);
+      else
+        s = ensure_adjoint<T>(h, p_cap, dp, false);
+      if (s) return s;
+    }
     HIP_TRY(qoc::launch_fill<unsigned long long>(h->bits, 4, 0ull, st));
     {
       PhaseTimer tm(h, QOC_PHASE_NORM, st);
@@ -461,7 +480,9 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     Rcap_used = std::min((Rraw + 15) & ~15, dp);
     qoc_status s = ensure_levels<T>(h, n + 1);
     if (s) return s;
-    if (want_grad && (s = ensure_adjoint<T>(h, p, Rcap_used)) != QOC_OK) return s;
+    if (want_grad &&
+        (s = ensure_adjoint<T>(h, p, Rcap_used, qoc::adjoint_big_ok<T>(dp))) != QOC_OK)
+      return s;
     h->last_p = p;
     h->last_n = n;
     T *Dl = (T *)h->Dlev;
@@ -558,8 +579,17 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   if (M > 0) {
     PhaseTimer tm(h, QOC_PHASE_ADJOINT, st);
     qoc::AdjointArgs<T> ad{};
-    ad.N = N; ad.dp = dp; ad.M = M; ad.S = S; ad.p = small_path ? kSmallPCap : p; ad.n = n;
-    ad.Rcap = Rcap_used; ad.nblocks = h->adj_blocks;
+    // batched per-step derivative for padded d >= 64, and for d >= 32 on the
+    // small-d path when a fixed (p, n) makes the pair known on the host
+    const bool sbig = small_path && small_big_adjoint<T>(h);
+    const bool big = sbig || (!small_path && qoc::adjoint_big_ok<T>(dp));
+    if (sbig) {
+      p = small_fixed_pn(h).first;
+      n = small_fixed_pn(h).second;
+      Rcap_used = small_fixed_rcap(h);
+    }
+    ad.N = N; ad.dp = dp; ad.M = M; ad.S = S; ad.p = small_path && !sbig ? kSmallPCap : p;
+    ad.n = n; ad.Rcap = Rcap_used; ad.nblocks = h->adj_blocks;
     ad.pn = small_path ? h->pn_dev : nullptr; ad.sc = small_path ? h->sc_dev : nullptr;
     ad.X = X; ad.Dlev = (const T *)h->Dlev; ad.lam_buf = (const T *)h->lam_buf; ad.psi_buf = (const T *)h->psi_buf;
     ad.Hf = (const T *)h->Hf; ad.u = u_dev; ad.s_scale = std::ldexp(h->dt, -n);
@@ -568,9 +598,9 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     ad.part = h->adj_part;
     ad.xbar = Qa;  // the Taylor work space is free once the sweeps are done
     ad.bf3 = h->bf3;
-    if (qoc::adjoint16_ok<T>(dp, ad.p))
+    if (!big && qoc::adjoint16_ok<T>(dp, ad.p))
       HIP_TRY(qoc::launch_adjoint16<T>(ad, st));
-    else if (qoc::adjoint_big_ok<T>(dp))
+    else if (big)
       HIP_TRY(qoc::launch_adjoint_big<T>(ad, st));
     else
       HIP_TRY(qoc::launch_adjoint<T>(ad, st));

@@ -127,6 +127,16 @@ def test_fixed_taylor_parameters():
     assert (e["p"], e["n"]) == (12, 2)
 
 
+@pytest.mark.parametrize("d,S,pn", [(30, 2, (9, 2)), (40, 3, (10, 3)), (40, 40, (8, 2))])
+def test_fixed_pair_small_path_batched_adjoint(d, S, pn):
+    # padded d 32 / 48 with a fixed pair: device-side chains, batched adjoint
+    rng = np.random.default_rng(300 + d + S)
+    p = workloads.random_problem(rng, d=d, M=3, N=45, S=S, dt=0.2, scale=2.0)
+    out, ref, e = compare(f"fixed_small_d{d}_S{S}", p, taylor_pn=pn)
+    check(p, e)
+    assert (e["p"], e["n"]) == pn
+
+
 def test_no_controls_and_no_penalty():
     rng = np.random.default_rng(11)
     p = workloads.random_problem(rng, d=6, M=0, N=20, S=2, with_penalty=False)
