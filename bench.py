@@ -205,18 +205,36 @@ def bench_batch(args):
         wall = (time.perf_counter() - t0) / iters
         ms = np.array([a.elapsed_time(e) for a, e in evs])
         return dict(p50_ms=float(np.percentile(ms, 50)), p99_ms=float(np.percentile(ms, 99)),
-                    mean_ms=float(ms.mean()), wall_ms_per_iter=wall * 1e3, iters=iters)
+                    mean_ms=float(ms.mean()), wall_ms_per_iter=wall * 1e3, iters=iters,
+                    ms=list(ms))
 
     iters = max(args.steps, 1)
     for _ in range(args.warmup):
         b.iteration(serial=True)
     serial = timed(lambda: b.iteration(serial=True), max(10, iters // 10))
+    serial.pop("ms")
     log(f"[bench] c5 per-instance calls: {serial}")
+    b.refresh()
     eager = timed(lambda: b.iteration(), max(10, iters // 10))
+    eager.pop("ms")
     log(f"[bench] c5 multi-stream eager: {eager}")
     b.capture(warmup=args.warmup)
-    graph = timed(b.replay, iters)
-    log(f"[bench] c5 graph replays: {graph}")
+    # timed replays in chunks; between chunks (untimed) the fixed (p, n) of
+    # instances whose theta_max has grown are re-chosen and the graph
+    # re-captured
+    chunk, ms_all, refreshes = 25, [], 0
+    refreshes += b.refresh()
+    done = 0
+    while done < iters:
+        k = min(chunk, iters - done)
+        r = timed(b.replay, k)
+        ms_all += r.pop("ms")
+        done += k
+        refreshes += b.refresh()
+    ms_all = np.array(ms_all)
+    graph = dict(p50_ms=float(np.percentile(ms_all, 50)), p99_ms=float(np.percentile(ms_all, 99)),
+                 mean_ms=float(ms_all.mean()), iters=int(len(ms_all)))
+    log(f"[bench] c5 graph replays: {graph}, pair refreshes {refreshes}")
     warn = b.taylor_warnings()
     flops = batch_work(probs, b)
     t = graph["p50_ms"] / 1e3
@@ -236,7 +254,7 @@ def bench_batch(args):
                              frac=flops / t / peak, traffic=None),
                graph=graph, eager_multistream=eager, per_instance_calls=serial,
                speedup_graph_vs_per_instance=serial["p50_ms"] / graph["p50_ms"],
-               taylor_warnings=len(warn))
+               taylor_pair_refreshes=refreshes, taylor_warnings_last_chunk=len(warn))
     if res_acc:
         res["accuracy_sample"] = res_acc
     b.close()

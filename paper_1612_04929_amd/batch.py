@@ -11,18 +11,27 @@ then the Adam update.  Handles whose padded d is 32 or more get a fixed
 call then needs a host round trip, and from 32 on the per-step derivative
 runs as batched tile products (padded d 16 choose (p, n) on the device);
 the device checks a fixed pair against the tolerance on every call
-(QOC_WARN_TAYLOR, see :meth:`taylor_warnings`).  The whole iteration can
-then be captured in one HIP graph and replayed.
+(QOC_WARN_TAYLOR, see :meth:`taylor_warnings`), and :meth:`refresh`
+re-chooses pairs that no longer hold.  The whole iteration can then be
+captured in one HIP graph and replayed.
 """
 from __future__ import annotations
 
 import ctypes as C
 import heapq
+import math
 
 import numpy as np
 import torch
 
 from . import qoc
+
+
+def taylor_ok(p, n, theta, tol):
+    """The truncation bound of the (p, n) rule, 2^n x^(p+1)/(p+1)! e^x <= tol
+    with x = theta / 2^n (Sec. III), for a given pair."""
+    x = math.ldexp(theta, -n)
+    return math.ldexp(1.0, n) * x ** (p + 1) / math.factorial(p + 1) * math.exp(x) <= tol
 
 
 class Batch:
@@ -47,11 +56,11 @@ class Batch:
             h.cost_grad_device(u.data_ptr(), o.data_ptr(), g.data_ptr(), st)
         torch.cuda.synchronize(self.dev)
         self.pn = []
+        self.tol = 1e-15 if precision == "fp64" else 1e-10
         for h in self.handles:
             inf = h.info()
             if inf["d_pad"] >= 32:
-                tol = 1e-15 if precision == "fp64" else 1e-10
-                p, n = qoc.taylor_select(inf["theta_max"] * margin, tol)
+                p, n = qoc.taylor_select(inf["theta_max"] * margin, self.tol)
                 h.set_taylor(p, n)
                 self.pn.append((p, n))
             else:
@@ -127,6 +136,32 @@ class Batch:
     # ------------------------------------------------------------------
     def costs(self):
         return np.array([float(o[0]) for o in self.out])
+
+    def refresh(self, margin=1.25, ahead=1.1):
+        """Re-choose the fixed (p, n) of every instance whose pair missed the
+        tolerance on its last call or would miss it at `ahead` times its
+        current theta_max (from `margin` times theta_max), then re-capture
+        the graph if any pair changed.  Synchronises; run it between timed
+        replays.  Returns the number of instances changed."""
+        torch.cuda.synchronize(self.dev)
+        changed = 0
+        for i, h in enumerate(self.handles):
+            if self.pn[i] is None:
+                continue
+            inf = h.info()
+            tol = self.tol
+            p, n = self.pn[i]
+            if (inf["flags"] & qoc.QOC_WARN_TAYLOR) or not taylor_ok(p, n, inf["theta_max"] * ahead,
+                                                                    tol):
+                pn = qoc.taylor_select(inf["theta_max"] * margin, tol)
+                if pn != (p, n):
+                    h.set_taylor(*pn)
+                    self.pn[i] = pn
+                    changed += 1
+        if changed and self.graph is not None:
+            self.graph = None
+            self.capture(warmup=1)
+        return changed
 
     def taylor_warnings(self):
         """Indices of instances whose fixed (p, n) missed the tolerance on
