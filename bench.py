@@ -53,7 +53,7 @@ def algorithmic_work(prob, info, phase, calls, precision, steps_timed=1):
         return "mfma", N * 8.0 * d ** 3 * G / per_call
     if phase == "blockprod":
         total = (N - info["n_blocks"]) * 8.0 * d ** 3
-        return "mfma", total / max(calls, 1)
+        return "mfma", total / max(calls // max(steps_timed, 1), 1)
     if phase in ("fwd_replay", "bwd_pairs"):
         return "hbm", N * 2.0 * d * d * esz
     if phase in ("fwd_blocks", "bwd_blocks"):
@@ -272,6 +272,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-torch-baseline", action="store_true")
     ap.add_argument("--streams", type=int, default=4, help="c5: streams per iteration")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the sweep autotuner (checkpoint interval, sweep variants)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -290,7 +292,16 @@ def main():
     prob = workloads.make_config(args.config)
     log(f"[bench] {prob.name}: d={prob.d} M={prob.M} N={prob.N} S={prob.S} "
         f"precision={args.precision}")
-    h = qoc.Problem(prob, precision=args.precision, device=0)
+    tuned = None
+    if not args.no_tune:
+        from paper_1612_04929_amd import tune as qtune
+        tuned = qtune.tune(prob, precision=args.precision)
+        log(f"[bench] tuned: L={tuned['checkpoint_every']} sweeps={tuned['sweep']} "
+            f"({tuned['seconds']:.1f} s)")
+    h = qoc.Problem(prob, precision=args.precision, device=0,
+                    checkpoint_every=tuned["checkpoint_every"] if tuned else 0)
+    if tuned:
+        qtune.apply(h, tuned)
     u = torch.from_numpy(np.ascontiguousarray(prob.u)).to(dev)
     out = torch.zeros(2 + prob.N, dtype=torch.float64, device=dev)
     grad = torch.zeros(max(1, prob.M * prob.N), dtype=torch.float64, device=dev)
@@ -374,6 +385,10 @@ def main():
         res["fp64_gpu_path"] = tb
         res["speedup_vs_fp64_gpu_path"] = value / tb["value"]
     res["kernels"] = kernels
+    if tuned:
+        res["tuning"] = dict(checkpoint_every=tuned["checkpoint_every"], sweep=tuned["sweep"],
+                             seconds=tuned["seconds"],
+                             candidates={r["L"]: round(r["ms"], 4) for r in tuned["table"]})
     res["diagnostics"] = dict(theta_max=info["theta_max"], norm_drift=info["norm_drift"],
                               n_blocks=info["n_blocks"], d_pad=info["d_pad"],
                               device_bytes=info["device_bytes"])

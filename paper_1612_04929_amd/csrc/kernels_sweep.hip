@@ -17,6 +17,8 @@
 // Columns (states) propagate independently, so every sweep runs one
 // workgroup per column (F2, B2) or per (block, column) (F3, B3).
 // All updates are in D-form: y = x + D x.
+#include <algorithm>
+
 #include "qoc_device.h"
 #include "qoc_kernels.h"
 
@@ -429,6 +431,339 @@ template <typename T> __global__ __launch_bounds__(256) void k_bwd_pairs(SweepAr
   }
 }
 
+// ------------------------------------------------------------------ wide
+// Large d: one launch per step of a sequential chain, the step's matrix
+// spread over many workgroups (the chains above keep one workgroup per
+// column and stream a d x d matrix per step through one compute unit).
+//   F2   per block b:        ckpt[b+1] = ckpt[b] + E_b ckpt[b]
+//   F3   per offset t:       psi[j+1] = psi[j] + D_j psi[j], j = bL + t, all blocks
+//   F3mu per offset t (down): mu_b <- mu_b + D_j^H mu_b + pw o psi_j
+//   B2   per block b (down): lam_ckpt[b] = lam_ckpt[b+1] + E_b^H lam_ckpt[b+1] + mu_b
+//   B3   per offset t (down): lam[j-1] = lam[j] + D_j^H lam[j] + pw o psi_j
+// A launch covers all blocks (grid y) for one offset t.  Forward products
+// give each wavefront WR_ROWS output rows (lanes along the row, 16-byte
+// loads, wavefront reductions); adjoint products give each workgroup 64
+// output columns (lane = column, coalesced row reads) with the rows split
+// over the 4 wavefronts.  States are staged in LDS, SW columns at a time.
+constexpr int WR_ROWS = 2, WA_UNR = 8;
+
+template <typename T> struct WideStep {
+  int mode;  // 0 F2, 1 F3, 2 F3mu, 3 B2, 4 B3
+  int t;     // block (F2, B2) or offset inside the block (F3, F3mu, B3)
+  T *mu_in, *mu_out;  // F3mu ping-pong sets (nb each)
+  int sw;             // state columns staged in LDS at a time (<= WIDE_SWM)
+};
+constexpr int WIDE_SWM = 8;
+// Columns per LDS chunk so that states and partial sums fit in 64 KB.
+template <typename T> int wide_sw(int dp) {
+  const long per = (long)sizeof(T) * (2L * dp + 512);
+  long sw = 65536 / per;
+  return (int)std::max(1L, std::min<long>(WIDE_SWM, sw));
+}
+
+// Operands of one (mode, t, block) job; false if the block has no work.
+template <typename T>
+__device__ __forceinline__ bool wide_job(const SweepArgs<T> &a, const WideStep<T> &w, int b,
+                                         const T *&D, const T *&X, T *&Y, const T *&add,
+                                         bool &addw) {
+  const long set = 2L * a.S * a.dp, mat = 2L * a.dp * a.dp;
+  add = nullptr;
+  addw = false;
+  if (w.mode == 0 || w.mode == 3) {
+    if (b != 0) return false;
+    const int blk = w.t;
+    D = a.E + (long)blk * mat;
+    if (w.mode == 0) {
+      X = blk == 0 ? a.psi0 : a.ckpt + (long)blk * set;
+      Y = a.ckpt + (long)(blk + 1) * set;
+    } else {
+      X = a.lam_ckpt + (long)(blk + 1) * set;
+      Y = a.lam_ckpt + (long)blk * set;
+      add = a.mu ? a.mu + (long)blk * set : nullptr;
+    }
+    return true;
+  }
+  const int start = b * a.L, end = min(a.N, start + a.L);
+  const int j = start + w.t;
+  if (j >= end) return false;
+  D = a.D + (long)j * mat;
+  if (w.mode == 1) {
+    if (!((j + 1 < end) || (j + 1 == a.N))) return false;  // block ends come from F2
+    X = a.psi_buf + (long)j * set;
+    Y = a.psi_buf + (long)(j + 1) * set;
+    return true;
+  }
+  if (w.mode == 2) {
+    X = w.mu_in + (long)b * set;
+    Y = w.mu_out + (long)b * set;
+    add = a.psi_buf + (long)j * set;
+    addw = j >= 1;
+    return true;
+  }
+  // B3: lambda_j from lambda_{j+1} (stored at lam_buf[j]), j > start
+  if (w.t == 0) return false;
+  X = a.lam_buf + (long)j * set;
+  Y = a.lam_buf + (long)(j - 1) * set;
+  add = a.psi_buf + (long)j * set;
+  addw = a.pw != nullptr;
+  return true;
+}
+
+// Y = X + D X on WR_ROWS rows per wavefront, all columns of the set.
+template <typename T> __global__ __launch_bounds__(256) void k_wide_fwd(SweepArgs<T> a, WideStep<T> w) {
+  extern __shared__ unsigned char shraw[];
+  typedef typename Vec16<T>::type V;
+  constexpr int VN = Vec16<T>::n, SW = WIDE_SWM;
+  const int swr = w.sw;
+  T *xs = (T *)shraw, *xsi = xs + (long)swr * a.dp;  // [2][swr][dp]
+  const T *D, *X, *add;
+  T *Y;
+  bool addw;
+  if (!wide_job(a, w, blockIdx.y, D, X, Y, add, addw)) return;  // block-uniform
+  const int dp = a.dp, S = a.S;
+  const long plane = (long)dp * dp;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r0 = (blockIdx.x * 4 + wv) * WR_ROWS;
+  const int nv = dp / VN;
+  for (int s0 = 0; s0 < S; s0 += swr) {
+    const int sc = min(swr, S - s0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < sc * dp; e += 256) {
+      const int s = e / dp, m = e - s * dp;
+      xs[s * dp + m] = X[(long)(s0 + s) * dp + m];
+      xsi[s * dp + m] = X[(long)S * dp + (long)(s0 + s) * dp + m];
+    }
+    __syncthreads();
+    if (r0 >= dp) continue;  // wave-uniform, no barrier until the next chunk
+    T ar[WR_ROWS][SW], ai[WR_ROWS][SW];
+#pragma unroll
+    for (int q = 0; q < WR_ROWS; ++q)
+#pragma unroll
+      for (int s = 0; s < SW; ++s) {
+        ar[q][s] = 0;
+        ai[q][s] = 0;
+      }
+    for (int kv = lane; kv < nv; kv += 64) {
+      const int k = kv * VN;
+      V dr[WR_ROWS], di[WR_ROWS];
+#pragma unroll
+      for (int q = 0; q < WR_ROWS; ++q) {
+        dr[q] = *reinterpret_cast<const V *>(D + (long)(r0 + q) * dp + k);
+        di[q] = *reinterpret_cast<const V *>(D + plane + (long)(r0 + q) * dp + k);
+      }
+#pragma unroll
+      for (int s = 0; s < SW; ++s) {
+        if (s < sc) {
+#pragma unroll
+          for (int e = 0; e < VN; ++e) {
+            const T xr = xs[s * dp + k + e], xi = xsi[s * dp + k + e];
+#pragma unroll
+            for (int q = 0; q < WR_ROWS; ++q) {
+              const T vr = vget<T>(dr[q], e), vi = vget<T>(di[q], e);
+              ar[q][s] += vr * xr - vi * xi;
+              ai[q][s] += vr * xi + vi * xr;
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < WR_ROWS; ++q)
+#pragma unroll
+      for (int s = 0; s < SW; ++s) {
+        if (s < sc) {
+          const T vr = wave_sum(ar[q][s]), vi = wave_sum(ai[q][s]);
+          if (lane == 0) {
+            const int m = r0 + q;
+            Y[(long)(s0 + s) * dp + m] = xs[s * dp + m] + vr;
+            Y[(long)S * dp + (long)(s0 + s) * dp + m] = xsi[s * dp + m] + vi;
+          }
+        }
+      }
+  }
+}
+
+// Y = X + D^H X (+ ADD): workgroup = 64 output columns, 4 row slices.
+template <typename T> __global__ __launch_bounds__(256) void k_wide_adj(SweepArgs<T> a, WideStep<T> w) {
+  extern __shared__ unsigned char shraw[];
+  constexpr int SW = WIDE_SWM;
+  const int swr = w.sw;
+  T *xs = (T *)shraw, *xsi = xs + (long)swr * a.dp;  // [2][swr][dp]
+  T *red = xs + 2L * swr * a.dp;                      // [4][2][swr][64]
+  const T *D, *X, *add;
+  T *Y;
+  bool addw;
+  if (!wide_job(a, w, blockIdx.y, D, X, Y, add, addw)) return;  // block-uniform
+  const int dp = a.dp, S = a.S;
+  const long plane = (long)dp * dp;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
+  const bool cok = c < dp;
+  const int rper = (dp + 3) / 4, rb = wv * rper, re = min(dp, rb + rper);
+  for (int s0 = 0; s0 < S; s0 += swr) {
+    const int sc = min(swr, S - s0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < sc * dp; e += 256) {
+      const int s = e / dp, m = e - s * dp;
+      xs[s * dp + m] = X[(long)(s0 + s) * dp + m];
+      xsi[s * dp + m] = X[(long)S * dp + (long)(s0 + s) * dp + m];
+    }
+    __syncthreads();
+    T yr[SW], yi[SW];
+#pragma unroll
+    for (int s = 0; s < SW; ++s) {
+      yr[s] = 0;
+      yi[s] = 0;
+    }
+    if (cok) {
+      // WA_UNR rows of loads in flight per step of the loop (rper is a
+      // multiple of 4, dp of 16; the tail loop takes the rest)
+      int r = rb;
+      for (; r + WA_UNR <= re; r += WA_UNR) {
+        T dr[WA_UNR], di[WA_UNR];
+#pragma unroll
+        for (int q = 0; q < WA_UNR; ++q) {
+          dr[q] = D[(long)(r + q) * dp + c];
+          di[q] = -D[plane + (long)(r + q) * dp + c];  // conj(D[r][c])
+        }
+#pragma unroll
+        for (int q = 0; q < WA_UNR; ++q)
+#pragma unroll
+          for (int s = 0; s < SW; ++s) {
+            if (s < sc) {
+              const T xr = xs[s * dp + r + q], xi = xsi[s * dp + r + q];
+              yr[s] += dr[q] * xr - di[q] * xi;
+              yi[s] += dr[q] * xi + di[q] * xr;
+            }
+          }
+      }
+      for (; r < re; ++r) {
+        const T dr = D[(long)r * dp + c], di = -D[plane + (long)r * dp + c];
+#pragma unroll
+        for (int s = 0; s < SW; ++s) {
+          if (s < sc) {
+            const T xr = xs[s * dp + r], xi = xsi[s * dp + r];
+            yr[s] += dr * xr - di * xi;
+            yi[s] += dr * xi + di * xr;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < SW; ++s) {
+      if (s < sc) {
+        red[((wv * 2 + 0) * swr + s) * 64 + lane] = yr[s];
+        red[((wv * 2 + 1) * swr + s) * 64 + lane] = yi[s];
+      }
+    }
+    __syncthreads();
+    if (wv == 0 && cok) {
+      for (int s = 0; s < sc; ++s) {
+        T vr = xs[s * dp + c], vi = xsi[s * dp + c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          vr += red[((q * 2 + 0) * swr + s) * 64 + lane];
+          vi += red[((q * 2 + 1) * swr + s) * 64 + lane];
+        }
+        if (add) {
+          if (w.mode == 3) {
+            vr += add[(long)(s0 + s) * dp + c];
+            vi += add[(long)S * dp + (long)(s0 + s) * dp + c];
+          } else if (addw) {
+            const T wg = a.pw[c];
+            vr += wg * add[(long)(s0 + s) * dp + c];
+            vi += wg * add[(long)S * dp + (long)(s0 + s) * dp + c];
+          }
+        }
+        Y[(long)(s0 + s) * dp + c] = vr;
+        Y[(long)S * dp + (long)(s0 + s) * dp + c] = vi;
+      }
+    }
+  }
+}
+
+template <typename T> bool wide_sweep_ok(int dp, int S) {
+  (void)S;
+  return dp >= 80;
+}
+
+// The four sweeps of the blocked scan as per-step launches.  Scratch: the
+// F3mu ping-pong partner of mu uses lam_buf (free until B3).
+template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T> &a,
+                                                   hipStream_t st) {
+  const int SW = wide_sw<T>(a.dp);
+  const long set = 2L * a.S * a.dp;
+  const size_t shf = 2 * SW * a.dp * sizeof(T);
+  const size_t sha = shf + 4 * 2 * SW * 64 * sizeof(T);
+  const unsigned rowg = (unsigned)((a.dp + 4 * WR_ROWS - 1) / (4 * WR_ROWS));
+  const unsigned colg = (unsigned)((a.dp + 63) / 64);
+  const int Lmax = a.nb > 1 ? a.L : a.N;  // longest block
+  hipError_t e;
+  WideStep<T> w{};
+  w.sw = SW;
+  switch (which) {
+    case 0:  // F2
+      if ((e = launch_copy<T>(a.ckpt, a.psi0, set, st)) != hipSuccess) return e;
+      for (int b = 0; b < a.nb; ++b) {
+        w.mode = 0;
+        w.t = b;
+        hipLaunchKernelGGL(k_wide_fwd<T>, dim3(rowg, 1), dim3(256), shf, st, a, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      return hipSuccess;
+    case 1: {  // F3: block starts from the checkpoints, then every offset
+      for (int b = 0; b < a.nb; ++b)
+        if ((e = launch_copy<T>(a.psi_buf + (long)b * a.L * set, a.ckpt + (long)b * set, set,
+                                st)) != hipSuccess)
+          return e;
+      for (int t = 0; t < Lmax; ++t) {
+        w.mode = 1;
+        w.t = t;
+        hipLaunchKernelGGL(k_wide_fwd<T>, dim3(rowg, a.nb), dim3(256), shf, st, a, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      if (!a.pw) return hipSuccess;
+      // block-local penalty costates, from zero at each block end
+      T *bufs[2] = {a.mu, a.lam_buf};
+      if ((e = launch_fill<T>(a.mu, (long)a.nb * set, (T)0, st)) != hipSuccess) return e;
+      if ((e = launch_fill<T>(a.lam_buf, (long)a.nb * set, (T)0, st)) != hipSuccess) return e;
+      for (int t = Lmax - 1; t >= 0; --t) {
+        // the launch for offset t writes the buffer that t = 0 ends in (mu)
+        w.mode = 2;
+        w.t = t;
+        w.mu_out = bufs[t & 1];
+        w.mu_in = bufs[(t + 1) & 1];
+        hipLaunchKernelGGL(k_wide_adj<T>, dim3(colg, a.nb), dim3(256), sha, st, a, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      return hipSuccess;
+    }
+    case 2:  // B2
+      for (int b = a.nb - 1; b >= 1; --b) {
+        w.mode = 3;
+        w.t = b;
+        hipLaunchKernelGGL(k_wide_adj<T>, dim3(colg, 1), dim3(256), sha, st, a, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      return hipSuccess;
+    default: {  // B3: lam_buf[end-1] = lambda_end, then every offset downwards
+      for (int b = 0; b < a.nb; ++b) {
+        const int end = std::min(a.N, (b + 1) * a.L);
+        if ((e = launch_copy<T>(a.lam_buf + (long)(end - 1) * set,
+                                a.lam_ckpt + (long)(b + 1) * set, set, st)) != hipSuccess)
+          return e;
+      }
+      for (int t = Lmax - 1; t >= 1; --t) {
+        w.mode = 4;
+        w.t = t;
+        hipLaunchKernelGGL(k_wide_adj<T>, dim3(colg, a.nb), dim3(256), sha, st, a, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      return hipSuccess;
+    }
+  }
+}
+
 template <typename T> hipError_t launch_fwd_blocks(const SweepArgs<T> &a, hipStream_t st) {
   hipLaunchKernelGGL(k_fwd_blocks<T>, dim3(a.S), dim3(256), 4 * a.dp * sizeof(T), st, a);
   return hipGetLastError();
@@ -451,6 +786,8 @@ template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStre
 }
 
 #define QOC_INST(T)                                                                   \
+  template bool wide_sweep_ok<T>(int, int);                                           \
+  template hipError_t launch_wide_sweep<T>(int, const SweepArgs<T> &, hipStream_t);   \
   template hipError_t launch_fwd_blocks<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_fwd_replay<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_cost<T>(const SweepArgs<T> &, hipStream_t);             \

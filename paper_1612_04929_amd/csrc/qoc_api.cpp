@@ -79,6 +79,7 @@ struct qoc_handle {
   int d = 0, dp = 0, M = 0, N = 0, S = 0, prec = QOC_FP32, fid_mode = 0;
   int bf3 = 0;  // bf16x3 split products in the batched chains (padded d >= 64)
   int last_flags = 0;  // warning bits of the last call
+  int sweep_mode[4] = {0, 0, 0, 0};  // per sweep: 0 auto, 1 per-block, 2 per-step launches
   double dt = 0, a_fid = 0, a_amp = 0, a_var = 0, a_pen = 0, tol = 0, drift_warn = 0;
   bool has_pen = false;
   int fixed_p = 0, fixed_n = 0;
@@ -544,9 +545,15 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   // prefetch ring (d_pad <= 64), or the generic streaming kernels
   const bool wave = qoc::wave_sweep_ok<T>(dp, S);
   const bool small = !wave && qoc::small_sweep_ok<T>(dp, S);
+  const bool wide_ok = !wave && !small && qoc::wide_sweep_ok<T>(dp, S);
   auto sweep = [&](int which) -> hipError_t {
     if (wave) return qoc::launch_wave_sweep<T>(which, sw, st);
     if (small) return qoc::launch_small_sweep<T>(which, sw, st);
+    // per-step launches: the block sweeps (F2, B2) from padded d 80, the
+    // in-block passes (F3, B3) from 256, unless set per handle
+    const int mode = h->sweep_mode[which];
+    const bool wide = wide_ok && (mode == 2 || (mode == 0 && (which == 0 || which == 2 || dp >= 256)));
+    if (wide) return qoc::launch_wide_sweep<T>(which, sw, st);
     switch (which) {
       case 0: return qoc::launch_fwd_blocks<T>(sw, st);
       case 1: return qoc::launch_fwd_replay<T>(sw, st);
@@ -685,6 +692,15 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n) {
     return fail(QOC_ERR_ARG, "p must be 0 (automatic) or in [2, 64] with n in [0, 60]");
   h->fixed_p = p;
   h->fixed_n = p ? n : 0;
+  return QOC_OK;
+}
+
+qoc_status qoc_set_sweep(qoc_handle *h, int which, int variant) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  if (which < -1 || which > 3 || variant < 0 || variant > 2)
+    return fail(QOC_ERR_ARG, "which must be -1..3 and variant 0..2");
+  for (int w = 0; w < 4; ++w)
+    if (which == -1 || which == w) h->sweep_mode[w] = variant;
   return QOC_OK;
 }
 

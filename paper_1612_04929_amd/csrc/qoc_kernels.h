@@ -96,6 +96,10 @@ template <typename T> hipError_t launch_small_sweep(int which, const SweepArgs<T
 // One wavefront holding the whole state set (S * dp <= 64, dp = 16 or 32).
 template <typename T> bool wave_sweep_ok(int dp, int S);
 template <typename T> hipError_t launch_wave_sweep(int which, const SweepArgs<T> &a, hipStream_t st);
+// Large padded d (>= 80): the sweeps as per-step launches spread over many
+// workgroups.  which: 0 = F2, 1 = F3, 2 = B2, 3 = B3.
+template <typename T> bool wide_sweep_ok(int dp, int S);
+template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T> &a, hipStream_t st);
 // Per-step penalties c_j (FP64) and the norm drift, parallel over (j, s).
 template <typename T> hipError_t launch_pen(const SweepArgs<T> &a, hipStream_t st);
 

@@ -27,7 +27,8 @@ STATUS = {0: "QOC_OK", -1: "QOC_ERR_ARG", -2: "QOC_ERR_SHAPE", -3: "QOC_ERR_NOT_
           -7: "QOC_ERR_UNSUPPORTED"}
 EXPORTS = ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
            "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
-           "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_destroy",
+           "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
+           "qoc_destroy",
            "qoc_status_string",
            "qoc_last_error", "qoc_version"]
 
@@ -81,6 +82,7 @@ def load(path: str = LIB_PATH):
     lib.qoc_taylor_select.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]
     lib.qoc_set_taylor.argtypes = [vp, C.c_int, C.c_int]
+    lib.qoc_set_sweep.argtypes = [vp, C.c_int, C.c_int]
     lib.qoc_destroy.argtypes = [vp]
     lib.qoc_destroy.restype = None
     for f in ["qoc_status_string", "qoc_last_error", "qoc_version"]:
@@ -88,7 +90,7 @@ def load(path: str = LIB_PATH):
     lib.qoc_status_string.argtypes = [C.c_int]
     for f in ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
               "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
-              "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor"]:
+              "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep"]:
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -185,6 +187,11 @@ class Problem:
     def set_taylor(self, p: int, n: int = 0):
         """Fix (p, n) for later calls (p = 0: choose per call)."""
         _check(load().qoc_set_taylor(self._h, int(p), int(n)))
+
+    def set_sweep(self, which: int, variant: int):
+        """Sweep kernel variant (which: 0..3 or -1 for all; variant 0 auto,
+        1 per-block workgroups, 2 per-step launches)."""
+        _check(load().qoc_set_sweep(self._h, int(which), int(variant)))
 
     def info(self):
         inf = Info()

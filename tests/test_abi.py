@@ -109,3 +109,8 @@ def test_status_strings():
 def test_set_taylor_validates_arguments():
     lib = qoc.load()
     assert lib.qoc_set_taylor(None, 8, 2) == -1
+
+
+def test_set_sweep_validates_arguments():
+    lib = qoc.load()
+    assert lib.qoc_set_sweep(None, 0, 1) == -1

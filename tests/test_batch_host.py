@@ -27,3 +27,11 @@ def test_taylor_ok_monotone_in_theta():
     # valid up to some theta, invalid beyond it
     first_bad = ok.index(False)
     assert all(ok[:first_bad]) and not any(ok[first_bad:])
+
+
+def test_tuner_candidate_intervals():
+    from paper_1612_04929_amd.tune import candidate_intervals
+    assert candidate_intervals(1) == [1]
+    c = candidate_intervals(5000)
+    assert c == sorted(set(c)) and 64 in c and all(1 <= x <= 5000 for x in c)
+    assert all(x & (x - 1) == 0 for x in c)

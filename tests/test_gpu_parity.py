@@ -120,6 +120,16 @@ def test_checkpoint_interval_does_not_change_results(L):
     assert e["L"] == L
 
 
+@pytest.mark.parametrize("L", [1, 4, 64])
+def test_wide_sweeps_checkpoint_intervals(L):
+    # padded d 96: per-step launches of the sweeps, ragged last block, penalty
+    rng = np.random.default_rng(17)
+    p = workloads.random_problem(rng, d=90, M=2, N=50, S=3, dt=0.25, scale=1.5)
+    out, ref, e = compare(f"wide_L{L}", p, checkpoint_every=L)
+    check(p, e)
+    assert e["L"] == L
+
+
 def test_fixed_taylor_parameters():
     p = workloads.config2().with_steps(400)
     out, ref, e = compare("c2_fixed_pn", p, taylor_pn=(12, 2))

@@ -1,0 +1,45 @@
+"""The sweep autotuner and the sweep variants: every variant gives the
+oracle's cost and gradient, and the tuned configuration does too."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from test_gpu_parity import check, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_sweep_variants_match_oracle(variant):
+    rng = np.random.default_rng(23)
+    p = workloads.random_problem(rng, d=100, M=2, N=70, S=2, dt=0.25, scale=1.5)
+    from paper_1612_04929_amd import qoc
+    import oracle
+    ref = oracle.cost_grad(p)
+    say(f"[tune] variant {variant}")
+    h = qoc.Problem(p, precision="fp32", checkpoint_every=8)
+    h.set_sweep(-1, variant)
+    out = h.cost_grad(p.u)
+    h.close()
+    dF = abs((1 - out["C_fid"]) - ref["F"])
+    rel = np.linalg.norm(out["grad"] - ref["grad"]) / np.linalg.norm(ref["grad"])
+    say(f"[tune] variant {variant}: dF={dF:.2e} grad_rel={rel:.2e}")
+    assert dF <= 1e-6 and rel <= 1e-4
+
+
+def test_tuned_configuration_matches_oracle():
+    from paper_1612_04929_amd import tune
+    rng = np.random.default_rng(29)
+    p = workloads.random_problem(rng, d=90, M=2, N=120, S=3, dt=0.25, scale=1.5)
+    cfg = tune.tune(p, precision="fp32", reps=1)
+    say(f"[tune] chose L={cfg['checkpoint_every']} sweeps={cfg['sweep']} in {cfg['seconds']:.2f} s")
+    assert cfg["checkpoint_every"] in [r["L"] for r in cfg["table"]]
+    out, ref, e = compare("tuned", p, checkpoint_every=cfg["checkpoint_every"])
+    check(p, e)
