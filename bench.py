@@ -47,10 +47,12 @@ def algorithmic_work(prob, info, phase, calls, precision, steps_timed=1):
     p, n, L = info["p"], info["n"], info["block_len"]
     esz = 8 if precision == "fp64" else 4  # bf16x3 keeps FP32 storage
     if phase == "taylor":
-        # p - 1 + n complex products per step, spread over the launches
-        G = p - 1 + n
+        # batched path: every launch is one complex product per step (Horner
+        # or Paterson-Stockmeyer stages, squarings); small-d path: one launch
+        # runs the whole Horner chain, p - 1 + n products per step
         per_call = max(calls // max(steps_timed, 1), 1)
-        return "mfma", N * 8.0 * d ** 3 * G / per_call
+        G = 1 if per_call > 1 else p - 1 + n
+        return "mfma", N * 8.0 * d ** 3 * G
     if phase == "blockprod":
         total = (N - info["n_blocks"]) * 8.0 * d ** 3
         return "mfma", total / max(calls // max(steps_timed, 1), 1)
@@ -70,6 +72,17 @@ def algorithmic_work(prob, info, phase, calls, precision, steps_timed=1):
     if phase == "assemble":
         return "hbm", N * 2.0 * d * d * esz * 2
     return "hbm", 0.0
+
+
+def ps_products(p):
+    """Products of the batched Taylor stage for order p: Paterson-Stockmeyer
+    with block s in 2..4 when that beats the p - 1 of Horner (the rule of
+    the library's host plan)."""
+    best = p - 1
+    for s in range(2, min(p, 4) + 1):
+        Q, rem = divmod(p, s)
+        best = min(best, (s - 1) + Q - (1 if rem == 0 else 0))
+    return best
 
 
 def fp64_torch_path(prob, dev, reps=2):
@@ -154,7 +167,7 @@ def batch_work(probs, batch):
         inf = h.info()
         d, N, M, S = p.d, p.N, p.M, p.S
         pp, nn = inf["p"], inf["n"]
-        G = pp - 1 + nn
+        G = ps_products(pp) + nn if inf["d_pad"] > 48 else pp - 1 + nn
         f = N * 8.0 * d ** 3 * G + (N - inf["n_blocks"]) * 8.0 * d ** 3
         _, fa = algorithmic_work(p, inf, "adjoint", 1, "fp32")
         tot += f + fa

@@ -90,20 +90,45 @@ __device__ __forceinline__ void stage_store(const StageArgs<T> &a, long j, int r
   const long plane = (long)a.dp * a.dp;
   const long o = (long)row * a.dp + col;
   T vr = a.alpha * accr, vi = a.alpha * acci;
-  if (a.betaA != (T)0) {
+  T ar = 0, ai = 0, br = 0, bi = 0;
+  const bool needA = a.betaA != (T)0 || (a.C2 && a.c2A != (T)0);
+  const bool needB = a.betaB != (T)0 || (a.C2 && a.c2B != (T)0);
+  if (needA) {
     const T *Aj = a.A + j * a.strideA;
-    vr += a.betaA * Aj[o];
-    vi += a.betaA * Aj[plane + o];
+    ar = Aj[o];
+    ai = Aj[plane + o];
   }
-  if (a.betaB != (T)0) {
+  if (needB) {
     const T *Bj = a.B + j * a.strideB;
-    vr += a.betaB * Bj[o];
-    vi += a.betaB * Bj[plane + o];
+    br = Bj[o];
+    bi = Bj[plane + o];
   }
+  vr += a.betaA * ar + a.betaB * br;
+  vi += a.betaA * ai + a.betaB * bi;
   if (row == col) vr += a.gamma;
+  T xr[3] = {0, 0, 0}, xi[3] = {0, 0, 0};
+  for (int q = 0; q < a.nx; ++q) {
+    const T *Xq = a.xadd[q] + j * a.strideC;
+    xr[q] = Xq[o];
+    xi[q] = Xq[plane + o];
+    vr += a.xc[q] * xr[q];
+    vi += a.xc[q] * xi[q];
+  }
   T *Cj = a.C + j * a.strideC;
   Cj[o] = vr;
   Cj[plane + o] = vi;
+  if (a.C2) {
+    T wr = a.c2P * accr + a.c2A * ar + a.c2B * br;
+    T wi = a.c2P * acci + a.c2A * ai + a.c2B * bi;
+    if (row == col) wr += a.g2;
+    for (int q = 0; q < a.nx; ++q) {
+      wr += a.xc2[q] * xr[q];
+      wi += a.xc2[q] * xi[q];
+    }
+    T *C2j = a.C2 + j * a.strideC;
+    C2j[o] = wr;
+    C2j[plane + o] = wi;
+  }
 }
 
 // dp a multiple of 16: one wavefront per 16x16 output tile, operands read

@@ -395,6 +395,91 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
 }
 
 // ------------------------------------------------------------------ pipeline
+// Paterson-Stockmeyer evaluation of D^(0) = T_p(X) - I = sum_{k=1..p} X^k/k!
+// (the same polynomial as the Horner form, fewer products): powers
+// X^2 .. X^s (s - 1 products), then Horner in Y = X^s over the blocks
+// B_q = sum_{r<s} c_{qs+r} X^r (X^0 = I, c_0 = 0, c_k = 0 beyond p):
+// W_Q = B_Q, W_q = B_q + Y W_{q+1}, D^(0) = W_0.  When s divides p,
+// B_Q = c_p I and W_{Q-1} = B_{Q-1} + c_p Y needs no product.
+struct PsPlan {
+  int s, Q, rem, cost;
+};
+PsPlan ps_plan(int p) {
+  PsPlan best{0, 0, 0, 1 << 30};
+  for (int s = 2; s <= std::min(p, 4); ++s) {
+    const int Q = p / s, rem = p - Q * s;
+    const int cost = (s - 1) + Q - (rem == 0 ? 1 : 0);
+    if (cost < best.cost) best = PsPlan{s, Q, rem, cost};
+  }
+  return best;
+}
+
+template <typename T>
+hipError_t taylor_ps(qoc_handle *h, const PsPlan &ps, int p, int nslots, T *X, T *Qa, T *Qb,
+                     T *Dl, long lev, long mat, int N, int dp, hipStream_t st) {
+  const int s = ps.s;
+  std::vector<double> c(p + s + 1, 0.0);
+  {
+    double f = 1.0;
+    for (int k = 1; k <= p; ++k) {
+      f *= k;
+      c[k] = 1.0 / f;
+    }
+  }
+  // storage: P[1] = X, P[2] = Qa, P[3] = Qb, P[4] and the two Horner
+  // panels in level slots 1.. (free until the squarings)
+  std::vector<T *> tmp;
+  for (int i = 1; i < nslots; ++i) tmp.push_back(Dl + (long)i * lev);
+  size_t ti = 0;
+  T *P[5] = {nullptr, X, Qa, Qb, nullptr};
+  if (s == 4) P[4] = tmp[ti++];
+  T *Wa = tmp[ti++], *Wb = tmp[ti++];
+  const int H = ps.rem == 0 ? ps.Q - 1 : ps.Q;  // Horner products
+  // destination of the Horner output i (i = -1: the panel formed with the
+  // last power); the last one is D^(0) in level slot 0
+  auto dest = [&](int i) -> T * {
+    if (i == H - 1) return Dl;
+    return ((H - 1 - i) & 1) ? Wa : Wb;
+  };
+  auto B = [&](int q, qoc::StageArgs<T> &a, bool second) {
+    // addends of B_q: X^0 -> gamma, X^1 .. X^(s-1) -> extra addends
+    T *g = second ? &a.g2 : &a.gamma;
+    *g = (T)c[q * s];
+    for (int r = 1; r < s; ++r) {
+      a.xadd[r - 1] = P[r];
+      (second ? a.xc2 : a.xc)[r - 1] = (T)c[q * s + r];
+    }
+    a.nx = s - 1;
+  };
+  for (int r = 2; r <= s; ++r) {
+    qoc::StageArgs<T> a{P[r - 1], mat, X, mat, P[r], mat, N, dp, (T)1, (T)0, (T)0, (T)0, h->bf3};
+    if (r == s) {
+      // second output: W_Q = B_Q, or W_{Q-1} = B_{Q-1} + c_p Y when s | p
+      a.C2 = dest(-1);
+      if (ps.rem == 0) {
+        B(ps.Q - 1, a, true);
+        a.c2P = (T)c[p];
+      } else {
+        B(ps.Q, a, true);
+      }
+    }
+    PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
+    hipError_t e = qoc::launch_stage<T>(0, a, st);
+    if (e != hipSuccess) return e;
+  }
+  const int q0 = ps.rem == 0 ? ps.Q - 2 : ps.Q - 1;
+  for (int i = 0; i < H; ++i) {
+    const int q = q0 - i;
+    qoc::StageArgs<T> a{P[s], mat, dest(i - 1), mat, dest(i), mat, N, dp, (T)1, (T)0, (T)0,
+                        (T)0, h->bf3};
+    B(q, a, false);
+    PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
+    hipError_t e = qoc::launch_stage<T>(0, a, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // A fixed (p, n) on the small-d path, as the device applies it (clamped to
 // the preallocated capacity), and the cotangent rank bound it implies.
 std::pair<int, int> small_fixed_pn(const qoc_handle *h) {
@@ -479,7 +564,13 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     }
     const int Rraw = (long)S << std::min(n, 30) > dp ? dp : (S << n);
     Rcap_used = std::min((Rraw + 15) & ~15, dp);
-    qoc_status s = ensure_levels<T>(h, n + 1);
+    const PsPlan ps = ps_plan(p);
+    const bool use_ps = ps.cost < p - 1;
+    // PS temporaries beyond the levels 1..n: the two ping-pong panels and,
+    // for s = 4, the fourth power
+    const int ps_need = use_ps ? 2 + (ps.s == 4 ? 1 : 0) : 0;
+    const int ps_extra = std::max(0, ps_need - n);
+    qoc_status s = ensure_levels<T>(h, n + 1 + ps_extra);
     if (s) return s;
     if (want_grad &&
         (s = ensure_adjoint<T>(h, p, Rcap_used, qoc::adjoint_big_ok<T>(dp))) != QOC_OK)
@@ -492,16 +583,19 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     {
       PhaseTimer tm(h, QOC_PHASE_ASSEMBLE, st);
       HIP_TRY(qoc::launch_assemble<T>((const T *)h->Hf, u_dev, dp, M, N, (T)sc, (T)(1.0 / p), X,
-                                      Qa, st));
+                                      use_ps ? nullptr : Qa, st));
     }
-    T *cur = Qa, *nxt = Qb;
-    for (int k = p - 1; k >= 2; --k) {
-      qoc::StageArgs<T> a{X, mat, cur, mat, nxt, mat, N, dp, (T)(1.0 / k), (T)0, (T)0, (T)1, h->bf3};
-      PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
-      HIP_TRY(qoc::launch_stage<T>(0, a, st));
-      std::swap(cur, nxt);
-    }
-    {
+    if (use_ps) {
+      HIP_TRY(taylor_ps<T>(h, ps, p, n + 1 + ps_extra, X, Qa, Qb, Dl, lev, mat, N, dp, st));
+    } else {
+      T *cur = Qa, *nxt = Qb;
+      for (int k = p - 1; k >= 2; --k) {
+        qoc::StageArgs<T> a{X, mat, cur, mat, nxt, mat, N, dp, (T)(1.0 / k), (T)0, (T)0, (T)1,
+                            h->bf3};
+        PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
+        HIP_TRY(qoc::launch_stage<T>(0, a, st));
+        std::swap(cur, nxt);
+      }
       qoc::StageArgs<T> a{X, mat, cur, mat, Dl, mat, N, dp, (T)1, (T)0, (T)0, (T)0, h->bf3};
       PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
       HIP_TRY(qoc::launch_stage<T>(0, a, st));

@@ -6,9 +6,11 @@
 namespace qoc {
 
 // Batched complex product with a fused epilogue, one matrix per step:
-//   C_j = alpha * op(A_j) * B_j + betaA * A_j + betaB * B_j + gamma * I
-// Matrices are dp x dp planar (re plane, then im plane), matrix j of a
-// stack at base + j * stride.  op(A) = A (opa = 0) or A^H (opa = 1).
+//   C_j  = alpha P + betaA A_j + betaB B_j + gamma I + sum_i xc[i] Xi_j
+//   C2_j = c2P P + c2A A_j + c2B B_j + g2 I + sum_i xc2[i] Xi_j  (if C2)
+// with P = op(A_j) B_j.  Matrices are dp x dp planar (re plane, then im
+// plane), matrix j of a stack at base + j * stride (the extra addends Xi
+// and C2 at base + j * strideC).  op(A) = A (opa = 0) or A^H (opa = 1).
 template <typename T> struct StageArgs {
   const T *A;
   long strideA;
@@ -19,6 +21,12 @@ template <typename T> struct StageArgs {
   int nmat, dp;
   T alpha, betaA, betaB, gamma;
   int bf3;  // 1: bf16x3 split products (FP32 storage, padded d multiple of 64)
+  int nx;                 // extra addends used (0..3)
+  const T *xadd[3];
+  T xc[3];
+  T *C2;                  // optional second output (null: none)
+  T c2P, c2A, c2B, g2;
+  T xc2[3];
 };
 
 // X_j = -i s (H_0 + sum_k u_{k,j} H_k) for all steps and, when Q is not

@@ -130,6 +130,16 @@ def test_wide_sweeps_checkpoint_intervals(L):
     assert e["L"] == L
 
 
+@pytest.mark.parametrize("pn", [(4, 3), (5, 3), (9, 2), (12, 1), (16, 0)])
+def test_batched_taylor_orders(pn):
+    # padded d 80: Paterson-Stockmeyer blocks s = 2, 3, 4 and both endings
+    rng = np.random.default_rng(41)
+    p = workloads.random_problem(rng, d=70, M=2, N=30, S=2, dt=0.15, scale=1.5)
+    out, ref, e = compare(f"orders_p{pn[0]}_n{pn[1]}", p, taylor_pn=pn)
+    check(p, e)
+    assert (e["p"], e["n"]) == pn
+
+
 def test_fixed_taylor_parameters():
     p = workloads.config2().with_steps(400)
     out, ref, e = compare("c2_fixed_pn", p, taylor_pn=(12, 2))
