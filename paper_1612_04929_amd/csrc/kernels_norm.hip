@@ -108,6 +108,7 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
   for (int s = 0; s < NRM_SW; ++s) nrm[s] = 0.0;
   if (col < d) {
     const long dd = (long)d * d;
+#pragma unroll 4
     for (int r = 0; r < d; ++r) {
       const double2 h0 = *(const double2 *)(H64 + ((long)r * d + col) * 2);
       double hr[NRM_SW], hi[NRM_SW];
@@ -155,23 +156,40 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
   if ((t & 63) == 0) red[t >> 6] = v;
   __syncthreads();
   __shared__ int last;
+  const unsigned nblk = gridDim.x * gridDim.y;
+  const unsigned bid = blockIdx.y * gridDim.x + blockIdx.x;
   if (t == 0) {
     unsigned long long m = red[0];
     for (int i = 1; i < 4; ++i) m = red[i] > m ? red[i] : m;
-    atomicMax(theta_bits, m);
-    last = 0;
-    if (sel.pn) {
-      __threadfence();
-      const unsigned total = gridDim.x * gridDim.y;
-      last = atomicAdd(sel.ticket, 1u) == total - 1;
-    }
+    sel.part[bid] = m;
+    __threadfence();
+    last = atomicAdd(sel.ticket, 1u) == nblk - 1;
   }
   __syncthreads();
-  if (last && t < 64) {  // the last workgroup to finish chooses (p, n)
-    __threadfence();
-    const double theta =
-        __longlong_as_double((long long)atomicAdd(theta_bits, 0ull));
-    select_pn(theta, dt, sel.tol, sel.n_cap, sel.p_cap, sel.fixed_p, sel.fixed_n, sel.pn, sel.sc);
+  if (!last) return;  // block-uniform
+  // the last workgroup: theta_max from the per-workgroup maxima, the
+  // drift word cleared for this call, (p, n) chosen, the ticket reset
+  __threadfence();
+  unsigned long long m = 0ull;
+  for (unsigned i = t; i < nblk; i += 256) {
+    const unsigned long long x =
+        __hip_atomic_load(sel.part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    m = x > m ? x : m;
+  }
+  m = wave_max(m);
+  if ((t & 63) == 0) red[t >> 6] = m;
+  __syncthreads();
+  if (t < 64) {
+    unsigned long long tb = red[0];
+    for (int i = 1; i < 4; ++i) tb = red[i] > tb ? red[i] : tb;
+    if (t == 0) {
+      theta_bits[0] = tb;
+      theta_bits[1] = 0ull;  // drift, accumulated by the penalty kernel
+    }
+    if (sel.pn)
+      select_pn(__longlong_as_double((long long)tb), dt, sel.tol, sel.n_cap, sel.p_cap,
+                sel.fixed_p, sel.fixed_n, sel.pn, sel.sc);
+    if (t == 0) *sel.ticket = 0u;
   }
 }
 

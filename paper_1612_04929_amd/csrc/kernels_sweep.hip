@@ -289,8 +289,9 @@ template <typename T> __global__ __launch_bounds__(256) void k_fwd_replay(SweepA
 
 // ------------------------------------------------------------------ cost
 // FP64: overlaps, fidelity, per-step penalties, regularisers, total cost,
-// and the final costate lambda_N (rounded to the chain precision).
-template <typename T> __global__ __launch_bounds__(256) void k_cost(SweepArgs<T> a) {
+// and the final costate lambda_N (rounded to the chain precision), by one
+// workgroup.
+template <typename T> __device__ void cost_body(const SweepArgs<T> &a) {
   __shared__ double red[4];
   const int dp = a.dp, d = a.d, S = a.S, N = a.N, M = a.M;
   const long set = 2L * S * dp;
@@ -320,9 +321,10 @@ template <typename T> __global__ __launch_bounds__(256) void k_cost(SweepArgs<T>
   // per-step penalties were written to out[2..] by k_pen, with partial sums
   double cpen = 0.0, camp = 0.0, cvar = 0.0;
   for (int q = threadIdx.x; q < a.npart; q += blockDim.x) {
-    cpen += a.part[q];
-    camp += a.part[a.npart + q];
-    cvar += a.part[2 * a.npart + q];
+    cpen += __hip_atomic_load(a.part + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    camp += __hip_atomic_load(a.part + a.npart + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cvar += __hip_atomic_load(a.part + 2 * a.npart + q, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
   }
   cpen = block_sum(cpen, red);
   camp = block_sum(camp, red);
@@ -363,6 +365,87 @@ template <typename T> __global__ __launch_bounds__(256) void k_cost(SweepArgs<T>
       set_imw(lamN, S, dp, s)[m] = (T)li;
     }
   }
+}
+
+// ------------------------------------------------------------------ penalties
+// One wavefront per step transition j -> j+1 (FP64): c_{j+1} =
+// (1/S) sum_s sum_m w_m |psi_{j+1}^s[m]|^2 written to out, the norm drift
+// max_{j,s} | ||psi_{j+1}^s||^2 - ||psi_j^s||^2 |, and per-workgroup partial
+// sums of the penalties and of the regularisers C3 (|u|^2) and C4 (control
+// variations) for the final reduction (deterministic order) in k_cost.
+template <typename T> __global__ __launch_bounds__(256) void k_pen(SweepArgs<T> a) {
+  __shared__ double red[3][4];
+  __shared__ double dred[4];
+  const int dp = a.dp, S = a.S, N = a.N;
+  const long set = 2L * S * dp;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double cpen = 0.0, dmax = 0.0;
+  for (long j = (long)blockIdx.x * 4 + w; j < N; j += (long)gridDim.x * 4) {
+    double csum = 0.0;
+    for (int s = 0; s < S; ++s) {
+      const T *p0r = a.psi_buf + j * set + (long)s * dp, *p0i = p0r + (long)S * dp;
+      const T *p1r = a.psi_buf + (j + 1) * set + (long)s * dp, *p1i = p1r + (long)S * dp;
+      double n0 = 0.0, n1 = 0.0, pen = 0.0;
+      for (int m = lane; m < dp; m += 64) {
+        const double ar = p0r[m], ai = p0i[m], br = p1r[m], bi = p1i[m];
+        const double q1 = br * br + bi * bi;
+        n0 += ar * ar + ai * ai;
+        n1 += q1;
+        if (a.w64) pen += a.w64[m] * q1;
+      }
+      n0 = wave_sum(n0);
+      n1 = wave_sum(n1);
+      if (a.w64) csum += wave_sum(pen);
+      dmax = fmax(dmax, fabs(n1 - n0));
+    }
+    const double cj = csum / S;
+    if (lane == 0) a.out[2 + j] = cj;
+    cpen += cj;
+  }
+  double camp = 0.0, cvar = 0.0;
+  const long MN = (long)a.M * N;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < MN; e += (long)gridDim.x * 256) {
+    const double x = a.u[e];
+    camp += x * x;
+    if (e % N >= 1) {
+      const double dx = x - a.u[e - 1];
+      cvar += dx * dx;
+    }
+  }
+  camp = wave_sum(camp);
+  cvar = wave_sum(cvar);
+  dmax = wave_max(dmax);
+  if (lane == 0) {
+    red[0][w] = cpen;  // identical on all lanes of the wave
+    red[1][w] = camp;
+    red[2][w] = cvar;
+    dred[w] = dmax;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int q = threadIdx.x;
+    a.part[q * gridDim.x + blockIdx.x] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
+  }
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(dred[0], dred[1]), fmax(dred[2], dred[3]));
+    atomicMax(a.drift_bits, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// The cost as a kernel of its own: a kernel boundary orders the partial
+// sums more cheaply than a device-scope fence in every workgroup of k_pen
+// (the last-workgroup pattern), whose L2 write-backs cost more on this
+// multi-die chip than the extra launch.
+template <typename T> __global__ __launch_bounds__(256) void k_cost(SweepArgs<T> a) {
+  cost_body(a);
+}
+
+template <typename T> hipError_t launch_pen(const SweepArgs<T> &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_pen<T>, dim3(a.npart), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cost<T>, dim3(1), dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ B2
@@ -772,10 +855,7 @@ template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStr
   hipLaunchKernelGGL(k_fwd_replay<T>, dim3(a.nb * a.S), dim3(256), 6 * a.dp * sizeof(T) + 8192, st, a);
   return hipGetLastError();
 }
-template <typename T> hipError_t launch_cost(const SweepArgs<T> &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_cost<T>, dim3(1), dim3(256), 0, st, a);
-  return hipGetLastError();
-}
+
 template <typename T> hipError_t launch_bwd_blocks(const SweepArgs<T> &a, hipStream_t st) {
   hipLaunchKernelGGL(k_bwd_blocks<T>, dim3(a.S), dim3(256), 6 * a.dp * sizeof(T) + 8192, st, a);
   return hipGetLastError();
@@ -790,7 +870,7 @@ template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStre
   template hipError_t launch_wide_sweep<T>(int, const SweepArgs<T> &, hipStream_t);   \
   template hipError_t launch_fwd_blocks<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_fwd_replay<T>(const SweepArgs<T> &, hipStream_t);       \
-  template hipError_t launch_cost<T>(const SweepArgs<T> &, hipStream_t);             \
+  template hipError_t launch_pen<T>(const SweepArgs<T> &, hipStream_t);              \
   template hipError_t launch_bwd_blocks<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_bwd_pairs<T>(const SweepArgs<T> &, hipStream_t);
 QOC_INST(float)

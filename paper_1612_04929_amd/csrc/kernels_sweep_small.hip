@@ -286,81 +286,9 @@ template <typename T> hipError_t launch_small_sweep(int which, const SweepArgs<T
   return hipErrorInvalidValue;
 }
 
-// ------------------------------------------------------------------ penalties
-// One wavefront per step transition j -> j+1 (FP64): c_{j+1} =
-// (1/S) sum_s sum_m w_m |psi_{j+1}^s[m]|^2 written to out, the norm drift
-// max_{j,s} | ||psi_{j+1}^s||^2 - ||psi_j^s||^2 |, and per-workgroup partial
-// sums of the penalties and of the regularisers C3 (|u|^2) and C4 (control
-// variations) for the final reduction in k_cost (deterministic order).
-template <typename T> __global__ __launch_bounds__(256) void k_pen(SweepArgs<T> a) {
-  __shared__ double red[3][4];
-  __shared__ double dred[4];
-  const int dp = a.dp, S = a.S, N = a.N;
-  const long set = 2L * S * dp;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double cpen = 0.0, dmax = 0.0;
-  for (long j = (long)blockIdx.x * 4 + w; j < N; j += (long)gridDim.x * 4) {
-    double csum = 0.0;
-    for (int s = 0; s < S; ++s) {
-      const T *p0r = a.psi_buf + j * set + (long)s * dp, *p0i = p0r + (long)S * dp;
-      const T *p1r = a.psi_buf + (j + 1) * set + (long)s * dp, *p1i = p1r + (long)S * dp;
-      double n0 = 0.0, n1 = 0.0, pen = 0.0;
-      for (int m = lane; m < dp; m += 64) {
-        const double ar = p0r[m], ai = p0i[m], br = p1r[m], bi = p1i[m];
-        const double q1 = br * br + bi * bi;
-        n0 += ar * ar + ai * ai;
-        n1 += q1;
-        if (a.w64) pen += a.w64[m] * q1;
-      }
-      n0 = wave_sum(n0);
-      n1 = wave_sum(n1);
-      if (a.w64) csum += wave_sum(pen);
-      dmax = fmax(dmax, fabs(n1 - n0));
-    }
-    const double cj = csum / S;
-    if (lane == 0) a.out[2 + j] = cj;
-    cpen += cj;
-  }
-  double camp = 0.0, cvar = 0.0;
-  const long MN = (long)a.M * N;
-  for (long e = blockIdx.x * 256L + threadIdx.x; e < MN; e += (long)gridDim.x * 256) {
-    const double x = a.u[e];
-    camp += x * x;
-    if (e % N >= 1) {
-      const double dx = x - a.u[e - 1];
-      cvar += dx * dx;
-    }
-  }
-  camp = wave_sum(camp);
-  cvar = wave_sum(cvar);
-  dmax = wave_max(dmax);
-  if (lane == 0) {
-    red[0][w] = cpen;  // identical on all lanes of the wave
-    red[1][w] = camp;
-    red[2][w] = cvar;
-    dred[w] = dmax;
-  }
-  __syncthreads();
-  if (threadIdx.x < 3) {
-    const int q = threadIdx.x;
-    a.part[q * gridDim.x + blockIdx.x] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
-  }
-  if (threadIdx.x == 0) {
-    const double m = fmax(fmax(dred[0], dred[1]), fmax(dred[2], dred[3]));
-    atomicMax(a.drift_bits, (unsigned long long)__double_as_longlong(m));
-  }
-}
-
-template <typename T> hipError_t launch_pen(const SweepArgs<T> &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_pen<T>, dim3(a.npart), dim3(256), 0, st, a);
-  return hipGetLastError();
-}
-
 template bool small_sweep_ok<float>(int, int);
 template bool small_sweep_ok<double>(int, int);
 template hipError_t launch_small_sweep<float>(int, const SweepArgs<float> &, hipStream_t);
 template hipError_t launch_small_sweep<double>(int, const SweepArgs<double> &, hipStream_t);
-template hipError_t launch_pen<float>(const SweepArgs<float> &, hipStream_t);
-template hipError_t launch_pen<double>(const SweepArgs<double> &, hipStream_t);
 
 }  // namespace qoc

@@ -8,6 +8,8 @@
 // its new entry back; there is no workgroup barrier on the sequential path.
 // Lanes beyond S d_pad duplicate an owner lane exactly, so every store is
 // unconditional and the compiler's wait counts stay exact.
+#include <type_traits>
+
 #include "qoc_device.h"
 #include "qoc_kernels.h"
 
@@ -47,16 +49,38 @@ struct WLane {
 };
 
 // y = x + op(D) x (+ w o aux) for this lane's output; x lives in LDS xs.
+// The dot product runs as WA independent partial sums (a short dependency
+// chain on the sequential path), the state column read in 16-byte pieces.
 template <typename T, int DP>
 __device__ __forceinline__ void w_apply(const WLane &L, const T (&r)[2 * DP], const T *xs,
                                         T aux_r, T aux_i, T wgt, T &yr, T &yi) {
+  constexpr int WA = 4;
+  typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
+  constexpr int VN = 16 / sizeof(T);
   const T *xr = xs + L.s * DP, *xi = xs + L.SD + L.s * DP;
+  T pr[WA], pi[WA];
+#pragma unroll
+  for (int q = 0; q < WA; ++q) {
+    pr[q] = 0;
+    pi[q] = 0;
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < DP; k0 += VN) {
+    const V xv = *reinterpret_cast<const V *>(xr + k0);
+    const V yv = *reinterpret_cast<const V *>(xi + k0);
+    const T *xa = reinterpret_cast<const T *>(&xv), *ya = reinterpret_cast<const T *>(&yv);
+#pragma unroll
+    for (int e = 0; e < VN; ++e) {
+      const int k = k0 + e, q = k % WA;
+      pr[q] += r[k] * xa[e] - r[DP + k] * ya[e];
+      pi[q] += r[k] * ya[e] + r[DP + k] * xa[e];
+    }
+  }
   T ar = 0, ai = 0;
 #pragma unroll
-  for (int k = 0; k < DP; ++k) {
-    const T vr = xr[k], vi = xi[k];
-    ar += r[k] * vr - r[DP + k] * vi;
-    ai += r[k] * vi + r[DP + k] * vr;
+  for (int q = 0; q < WA; ++q) {
+    ar += pr[q];
+    ai += pi[q];
   }
   // select, not multiply: an unused auxiliary operand is never touched
   yr = xr[L.m] + ar + (wgt != (T)0 ? wgt * aux_r : (T)0);
@@ -97,7 +121,7 @@ __device__ __forceinline__ void w_pipeline(const WLane &L, int count, DPtr dptr,
 }
 
 #define W_SETUP                                                        \
-  __shared__ T xs[2][128];                                             \
+  __shared__ __align__(16) T xs[2][128];                               \
   WLane L;                                                             \
   L.S = a.S;                                                           \
   L.SD = a.S * DP;                                                     \

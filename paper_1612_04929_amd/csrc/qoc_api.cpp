@@ -102,6 +102,7 @@ struct qoc_handle {
   void *ckpt = nullptr, *lam_ckpt = nullptr, *mu = nullptr;  // (nb+1) sets
   void *psi_buf = nullptr, *lam_buf = nullptr;                // N+1, N sets
   unsigned long long *bits = nullptr;  // [theta, drift, norm ticket, pen ticket]
+  unsigned long long *norm_part = nullptr;  // per-workgroup maxima of the norm kernel
   double *zinfo = nullptr;    // 3 + 2S
   double *part = nullptr;     // 3 x npart
   int *pn_dev = nullptr;      // device-side (p, n, status)
@@ -169,7 +170,7 @@ void release(qoc_handle *h) {
   void **ptrs[] = {&h->Hf, (void **)&h->H64, (void **)&h->u_dev, (void **)&h->out_dev,
                    (void **)&h->grad_dev, &h->psi0, (void **)&h->psiT64, (void **)&h->w64,
                    &h->pw, &h->X, &h->Qa, &h->Qb, &h->Dlev, &h->ckpt, &h->lam_ckpt, &h->mu,
-                   &h->psi_buf, &h->lam_buf, (void **)&h->bits,
+                   &h->psi_buf, &h->lam_buf, (void **)&h->bits, (void **)&h->norm_part,
                    (void **)&h->zinfo, (void **)&h->part, (void **)&h->pn_dev,
                    (void **)&h->sc_dev, &h->adj, (void **)&h->adj_part};
   for (void **p : ptrs)
@@ -331,6 +332,8 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   ALLOC(h->psi_buf, ((size_t)(N + 1) * set + slack) * sizeof(T));
   ALLOC(h->lam_buf, ((size_t)N * set + slack) * sizeof(T));
   ALLOC(h->bits, 4 * sizeof(unsigned long long));  // theta, drift, tickets
+  HIP_TRY(hipMemset(h->bits, 0, 4 * sizeof(unsigned long long)));  // tickets start at zero
+  ALLOC(h->norm_part, ((size_t)N + 64) * sizeof(unsigned long long));
   ALLOC(h->zinfo, (size_t)(3 + 2 * S) * sizeof(double));
   h->npart = std::max(1, std::min(1024, (N + 3) / 4));
   ALLOC(h->part, (size_t)3 * h->npart * sizeof(double));
@@ -516,11 +519,10 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
         s = ensure_adjoint<T>(h, p_cap, dp, false);
       if (s) return s;
     }
-    HIP_TRY(qoc::launch_fill<unsigned long long>(h->bits, 4, 0ull, st));
     {
       PhaseTimer tm(h, QOC_PHASE_NORM, st);
       qoc::SelectArgs sel{h->pn_dev, h->sc_dev, (unsigned *)(h->bits + 2), h->tol, n_cap, p_cap,
-                          h->fixed_p, h->fixed_n};
+                          h->fixed_p, h->fixed_n, h->norm_part};
       HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, sel, st));
     }
     {
@@ -536,15 +538,15 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     E = Qa;
   } else {
     // ---- (p, n): fixed, or from theta_max (FP64 norms on the device)
-    HIP_TRY(qoc::launch_fill<unsigned long long>(h->bits, 4, 0ull, st));
     {
       PhaseTimer tm(h, QOC_PHASE_NORM, st);
       // a fixed (p, n) is checked against the tolerance on the device
       // (status 2 in pn_dev), so the call needs no host round trip
-      qoc::SelectArgs sel{};
+      qoc::SelectArgs sel{nullptr, nullptr, (unsigned *)(h->bits + 2), h->tol, 60, 30, 0, 0,
+                          h->norm_part};
       if (h->fixed_p >= 2)
         sel = qoc::SelectArgs{h->pn_dev, h->sc_dev, (unsigned *)(h->bits + 2), h->tol, 60, 30,
-                              h->fixed_p, h->fixed_n};
+                              h->fixed_p, h->fixed_n, h->norm_part};
       HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, sel, st));
     }
     if (h->fixed_p >= 2) {
@@ -666,7 +668,6 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   {
     PhaseTimer tm(h, QOC_PHASE_COST, st);
     HIP_TRY(qoc::launch_pen<T>(sw, st));
-    HIP_TRY(qoc::launch_cost<T>(sw, st));
   }
   if (!want_grad) return QOC_OK;
   {

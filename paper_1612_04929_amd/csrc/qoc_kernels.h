@@ -37,19 +37,22 @@ hipError_t launch_assemble(const T *Hf, const double *u, int dp, int M, int N, T
 
 template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hipStream_t st);
 
-// Device-side (p, n) choice made by the last workgroup of the norm kernel
-// (pn = null: no choice).  pn = {p, n, status}, sc = {dt / 2^n, theta};
-// status 1 when the pair exceeds n_cap / p_cap or none meets tol, 2 when a
-// fixed pair (fixed_p >= 2) misses tol at this theta.  `ticket` must be
-// zero at launch.
+// The last workgroup of the norm kernel (found with `ticket`, zero at the
+// first launch and reset by that workgroup) reduces the per-workgroup
+// maxima in `part` (one word per workgroup; at most N + 64 words), writes
+// theta_bits[0], clears theta_bits[1] (the drift word of the call) and,
+// when pn is not null, chooses (p, n): pn = {p, n, status},
+// sc = {dt / 2^n, theta}; status 1 when the pair exceeds n_cap / p_cap or
+// none meets tol, 2 when a fixed pair (fixed_p >= 2) misses tol here.
 struct SelectArgs {
   int *pn;
   double *sc;
   unsigned *ticket;
   double tol;
   int n_cap, p_cap, fixed_p, fixed_n;
+  unsigned long long *part;
 };
-// theta_max = max_j ||dt H_j||_1 in FP64 (atomic max on the bit pattern).
+// theta_max = max_j ||dt H_j||_1 in FP64 (maximum on the bit pattern).
 hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, double dt,
                        unsigned long long *theta_bits, const SelectArgs &sel, hipStream_t st);
 
@@ -94,7 +97,6 @@ template <typename T> struct SweepArgs {
 };
 template <typename T> hipError_t launch_fwd_blocks(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStream_t st);
-template <typename T> hipError_t launch_cost(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_bwd_blocks(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStream_t st);
 // Small padded d (<= 64): all columns per workgroup, prefetched step matrices.
@@ -108,7 +110,8 @@ template <typename T> hipError_t launch_wave_sweep(int which, const SweepArgs<T>
 // workgroups.  which: 0 = F2, 1 = F3, 2 = B2, 3 = B3.
 template <typename T> bool wide_sweep_ok(int dp, int S);
 template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T> &a, hipStream_t st);
-// Per-step penalties c_j (FP64) and the norm drift, parallel over (j, s).
+// Per-step penalties c_j (FP64) and the norm drift, parallel over (j, s),
+// then (a second kernel) the fidelity, the total cost and lambda_N.
 template <typename T> hipError_t launch_pen(const SweepArgs<T> &a, hipStream_t st);
 
 // Exact per-step derivative of the Taylor + squaring evaluation, contracted
