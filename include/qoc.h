@@ -204,10 +204,13 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n);
 /* Kernel variant of the sweeps of later calls (a tuning knob; results are
  * the same up to rounding order).  which: 0 forward block sweep, 1 forward
  * in-block replay, 2 costate block sweep, 3 costate in-block pass, -1 all.
- * variant: 0 automatic, 1 one workgroup per block and column, 2 one launch
- * per step spread over many workgroups.  Variant 2 applies from padded
- * d 80 on; smaller d always use their single-wavefront / single-workgroup
- * kernels.  Sec. II, eqs. 2-4 (the sequential product of propagators). */
+ * variant: 0 automatic, 1 one workgroup per block (per column for padded
+ * d >= 80; a single wavefront for the whole state set where it fits),
+ * 2 one launch per step spread over many workgroups (padded d >= 80),
+ * 3 a four-wavefront workgroup per block with the step matrices staged in
+ * LDS (padded d <= 64).  A variant that does not apply falls back to the
+ * automatic choice.  Sec. II, eqs. 2-4 (the sequential product of
+ * propagators). */
 qoc_status qoc_set_sweep(qoc_handle *h, int which, int variant);
 
 void qoc_destroy(qoc_handle *h);

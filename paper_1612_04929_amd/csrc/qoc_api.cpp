@@ -643,11 +643,12 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   const bool small = !wave && qoc::small_sweep_ok<T>(dp, S);
   const bool wide_ok = !wave && !small && qoc::wide_sweep_ok<T>(dp, S);
   auto sweep = [&](int which) -> hipError_t {
-    if (wave) return qoc::launch_wave_sweep<T>(which, sw, st);
-    if (small) return qoc::launch_small_sweep<T>(which, sw, st);
+    const int mode = h->sweep_mode[which];
+    if (wave && !(mode == 3 && qoc::small_sweep_ok<T>(dp, S)))
+      return qoc::launch_wave_sweep<T>(which, sw, st);
+    if (wave || small) return qoc::launch_small_sweep<T>(which, sw, st);
     // per-step launches: the block sweeps (F2, B2) from padded d 80, the
     // in-block passes (F3, B3) from 256, unless set per handle
-    const int mode = h->sweep_mode[which];
     const bool wide = wide_ok && (mode == 2 || (mode == 0 && (which == 0 || which == 2 || dp >= 256)));
     if (wide) return qoc::launch_wide_sweep<T>(which, sw, st);
     switch (which) {
@@ -792,8 +793,8 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n) {
 
 qoc_status qoc_set_sweep(qoc_handle *h, int which, int variant) {
   if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
-  if (which < -1 || which > 3 || variant < 0 || variant > 2)
-    return fail(QOC_ERR_ARG, "which must be -1..3 and variant 0..2");
+  if (which < -1 || which > 3 || variant < 0 || variant > 3)
+    return fail(QOC_ERR_ARG, "which must be -1..3 and variant 0..3");
   for (int w = 0; w < 4; ++w)
     if (which == -1 || which == w) h->sweep_mode[w] = variant;
   return QOC_OK;

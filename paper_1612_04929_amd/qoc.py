@@ -68,6 +68,16 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing; build it with "
                           "`python -m paper_1612_04929_amd.build`")
+    # One HIP runtime per process.  PyTorch-ROCm ships its own HIP and HSA
+    # runtimes (under sonames of their own) and places them in the global
+    # symbol scope when it is imported; loading torch first makes the
+    # library bind to that runtime, so device pointers and stream handles
+    # from torch are the library's own.  Loaded the other way round, the
+    # process would hold two runtimes and torch's would fail to start.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     vp = C.c_void_p
     lib.qoc_create.argtypes = [C.POINTER(Desc), C.POINTER(vp)]
@@ -190,7 +200,8 @@ class Problem:
 
     def set_sweep(self, which: int, variant: int):
         """Sweep kernel variant (which: 0..3 or -1 for all; variant 0 auto,
-        1 per-block workgroups, 2 per-step launches)."""
+        1 per-block workgroups, 2 per-step launches, 3 four-wavefront LDS
+        workgroups for padded d <= 64)."""
         _check(load().qoc_set_sweep(self._h, int(which), int(variant)))
 
     def info(self):

@@ -6,7 +6,9 @@ inside the blocks).  Their cost depends on L, on the padded dimension and
 on the number of columns in ways that launch overheads, occupancy and
 cache reuse decide, so the interval and the kernel variant of each sweep
 are chosen by timing them on the problem itself: for every candidate L a
-handle is built, each sweep is timed in both variants with the library's
+handle is built, each sweep is timed in the applicable variants (padded
+d >= 80: per-block workgroups or per-step launches; smaller d: one
+wavefront or a four-wavefront LDS-staged workgroup) with the library's
 per-phase HIP events, and the L that minimises block products plus the
 best variant of each sweep wins.  Other phases do not depend on these
 choices.
@@ -43,7 +45,8 @@ def tune(prob, precision="fp32", intervals=None, reps=3, device=0, **kw):
     for L in intervals or candidate_intervals(prob.N):
         h = Problem(prob, precision=precision, checkpoint_every=L, device=device, **kw)
         times = {}
-        for variant in (1, 2):
+        variants = (1, 2) if h.info()["d_pad"] >= 80 else (1, 3)
+        for variant in variants:
             h.set_sweep(-1, variant)
             h.cost_grad_device(u.data_ptr(), out.data_ptr(), grad.data_ptr(), st)
             torch.cuda.synchronize(dev)
@@ -55,10 +58,10 @@ def tune(prob, precision="fp32", intervals=None, reps=3, device=0, **kw):
             h.profile_enable(False)
             times[variant] = {ph: prof[ph][0] / reps for ph in SWEEPS + ["blockprod"]}
         h.close()
-        choice = [min((1, 2), key=lambda v: times[v][ph]) for ph in SWEEPS]
+        choice = [min(variants, key=lambda v: times[v][ph]) for ph in SWEEPS]
         total = times[1]["blockprod"] + sum(times[v][ph] for v, ph in zip(choice, SWEEPS))
         table.append(dict(L=L, sweep=choice, ms=total,
-                          phases={ph: {v: times[v][ph] for v in (1, 2)} for ph in SWEEPS}))
+                          phases={ph: {v: times[v][ph] for v in variants} for ph in SWEEPS}))
     best = min(table, key=lambda r: r["ms"])
     return dict(checkpoint_every=best["L"], sweep=best["sweep"], table=table,
                 seconds=time.perf_counter() - t0)

@@ -16,14 +16,15 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("variant", [1, 2])
-def test_sweep_variants_match_oracle(variant):
-    rng = np.random.default_rng(23)
-    p = workloads.random_problem(rng, d=100, M=2, N=70, S=2, dt=0.25, scale=1.5)
+@pytest.mark.parametrize("d,S,variant", [(100, 2, 1), (100, 2, 2), (12, 4, 1), (12, 4, 3),
+                                         (40, 3, 3)])
+def test_sweep_variants_match_oracle(d, S, variant):
+    rng = np.random.default_rng(23 + d)
+    p = workloads.random_problem(rng, d=d, M=2, N=70, S=S, dt=0.25, scale=1.5)
     from paper_1612_04929_amd import qoc
     import oracle
     ref = oracle.cost_grad(p)
-    say(f"[tune] variant {variant}")
+    say(f"[tune] d={d} S={S} variant {variant}")
     h = qoc.Problem(p, precision="fp32", checkpoint_every=8)
     h.set_sweep(-1, variant)
     out = h.cost_grad(p.u)
