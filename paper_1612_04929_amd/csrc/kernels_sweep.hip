@@ -288,12 +288,14 @@ template <typename T> __global__ __launch_bounds__(256) void k_fwd_replay(SweepA
 }
 
 // ------------------------------------------------------------------ cost
-// FP64: overlaps, fidelity, per-step penalties, regularisers, total cost,
-// and the final costate lambda_N (rounded to the chain precision), by one
-// workgroup.
-template <typename T> __device__ void cost_body(const SweepArgs<T> &a) {
+// FP64, one workgroup each.  k_lam: the fidelity overlaps, F, C_fid and the
+// final costate lambda_N (rounded to the chain precision) -- all the
+// costate sweeps need.  k_total: the weighted total cost from F and the
+// per-workgroup partial sums of k_pen (penalties, |u|^2, variations), so
+// the penalty pass can run beside the costate sweeps.
+template <typename T> __global__ __launch_bounds__(256) void k_lam(SweepArgs<T> a) {
   __shared__ double red[4];
-  const int dp = a.dp, d = a.d, S = a.S, N = a.N, M = a.M;
+  const int dp = a.dp, d = a.d, S = a.S, N = a.N;
   const long set = 2L * S * dp;
   const T *psiN = a.psi_buf + (long)N * set;
   double zr = 0.0, zi = 0.0, Finc = 0.0;
@@ -318,21 +320,8 @@ template <typename T> __device__ void cost_body(const SweepArgs<T> &a) {
   zr /= S;
   zi /= S;
   const double F = (a.fid_mode == 0) ? (zr * zr + zi * zi) : Finc / S;
-  // per-step penalties were written to out[2..] by k_pen, with partial sums
-  double cpen = 0.0, camp = 0.0, cvar = 0.0;
-  for (int q = threadIdx.x; q < a.npart; q += blockDim.x) {
-    cpen += __hip_atomic_load(a.part + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    camp += __hip_atomic_load(a.part + a.npart + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    cvar += __hip_atomic_load(a.part + 2 * a.npart + q, __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_AGENT);
-  }
-  cpen = block_sum(cpen, red);
-  camp = block_sum(camp, red);
-  cvar = block_sum(cvar, red);
-  const double Cfid = 1.0 - F;
   if (threadIdx.x == 0) {
-    a.out[0] = a.alpha_fid * Cfid + a.alpha_pen * cpen + a.alpha_amp * camp + a.alpha_var * cvar;
-    a.out[1] = Cfid;
+    a.out[1] = 1.0 - F;
     a.zinfo[0] = zr;
     a.zinfo[1] = zi;
     a.zinfo[2] = F;
@@ -367,12 +356,29 @@ template <typename T> __device__ void cost_body(const SweepArgs<T> &a) {
   }
 }
 
+template <typename T> __global__ __launch_bounds__(256) void k_total(SweepArgs<T> a) {
+  __shared__ double red[4];
+  double cpen = 0.0, camp = 0.0, cvar = 0.0;
+  for (int q = threadIdx.x; q < a.npart; q += blockDim.x) {
+    cpen += a.part[q];
+    camp += a.part[a.npart + q];
+    cvar += a.part[2 * a.npart + q];
+  }
+  cpen = block_sum(cpen, red);
+  camp = block_sum(camp, red);
+  cvar = block_sum(cvar, red);
+  if (threadIdx.x == 0) {
+    const double Cfid = 1.0 - a.zinfo[2];
+    a.out[0] = a.alpha_fid * Cfid + a.alpha_pen * cpen + a.alpha_amp * camp + a.alpha_var * cvar;
+  }
+}
+
 // ------------------------------------------------------------------ penalties
 // One wavefront per step transition j -> j+1 (FP64): c_{j+1} =
 // (1/S) sum_s sum_m w_m |psi_{j+1}^s[m]|^2 written to out, the norm drift
 // max_{j,s} | ||psi_{j+1}^s||^2 - ||psi_j^s||^2 |, and per-workgroup partial
 // sums of the penalties and of the regularisers C3 (|u|^2) and C4 (control
-// variations) for the final reduction (deterministic order) in k_cost.
+// variations) for the final reduction (deterministic order) in k_total.
 template <typename T> __global__ __launch_bounds__(256) void k_pen(SweepArgs<T> a) {
   __shared__ double red[3][4];
   __shared__ double dred[4];
@@ -432,19 +438,17 @@ template <typename T> __global__ __launch_bounds__(256) void k_pen(SweepArgs<T> 
   }
 }
 
-// The cost as a kernel of its own: a kernel boundary orders the partial
-// sums more cheaply than a device-scope fence in every workgroup of k_pen
-// (the last-workgroup pattern), whose L2 write-backs cost more on this
-// multi-die chip than the extra launch.
-template <typename T> __global__ __launch_bounds__(256) void k_cost(SweepArgs<T> a) {
-  cost_body(a);
-}
 
 template <typename T> hipError_t launch_pen(const SweepArgs<T> &a, hipStream_t st) {
   hipLaunchKernelGGL(k_pen<T>, dim3(a.npart), dim3(256), 0, st, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cost<T>, dim3(1), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+template <typename T> hipError_t launch_lam(const SweepArgs<T> &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_lam<T>, dim3(1), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+template <typename T> hipError_t launch_total(const SweepArgs<T> &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_total<T>, dim3(1), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -871,6 +875,8 @@ template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStre
   template hipError_t launch_fwd_blocks<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_fwd_replay<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_pen<T>(const SweepArgs<T> &, hipStream_t);              \
+  template hipError_t launch_lam<T>(const SweepArgs<T> &, hipStream_t);              \
+  template hipError_t launch_total<T>(const SweepArgs<T> &, hipStream_t);            \
   template hipError_t launch_bwd_blocks<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_bwd_pairs<T>(const SweepArgs<T> &, hipStream_t);
 QOC_INST(float)

@@ -191,6 +191,7 @@ void release(qoc_handle *h) {
   h->event_pool.clear();
   if (h->stream) (void)hipStreamDestroy(h->stream);
   h->stream = nullptr;
+
   h->bytes = 0;
 }
 
@@ -666,10 +667,15 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     PhaseTimer tm(h, QOC_PHASE_FWD_REPLAY, st);
     HIP_TRY(sweep(1));
   }
+  // penalties, fidelity / lambda_N, total cost (all on st: a side stream
+  // for the penalties measured slower here, its events costing more than
+  // the overlap gains)
+  HIP_TRY(qoc::launch_pen<T>(sw, st));
   {
     PhaseTimer tm(h, QOC_PHASE_COST, st);
-    HIP_TRY(qoc::launch_pen<T>(sw, st));
+    HIP_TRY(qoc::launch_lam<T>(sw, st));
   }
+  HIP_TRY(qoc::launch_total<T>(sw, st));
   if (!want_grad) return QOC_OK;
   {
     PhaseTimer tm(h, QOC_PHASE_BWD_BLOCKS, st);

@@ -110,9 +110,12 @@ template <typename T> hipError_t launch_wave_sweep(int which, const SweepArgs<T>
 // workgroups.  which: 0 = F2, 1 = F3, 2 = B2, 3 = B3.
 template <typename T> bool wide_sweep_ok(int dp, int S);
 template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T> &a, hipStream_t st);
-// Per-step penalties c_j (FP64) and the norm drift, parallel over (j, s),
-// then (a second kernel) the fidelity, the total cost and lambda_N.
+// Per-step penalties c_j (FP64) and the norm drift, parallel over (j, s).
 template <typename T> hipError_t launch_pen(const SweepArgs<T> &a, hipStream_t st);
+// Fidelity, C_fid and lambda_N (needs the final states only).
+template <typename T> hipError_t launch_lam(const SweepArgs<T> &a, hipStream_t st);
+// Total cost (needs launch_pen's partial sums and launch_lam's fidelity).
+template <typename T> hipError_t launch_total(const SweepArgs<T> &a, hipStream_t st);
 
 // Exact per-step derivative of the Taylor + squaring evaluation, contracted
 // with the control Hamiltonians (see kernels_adjoint.hip).
