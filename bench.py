@@ -33,6 +33,23 @@ BF3_PHASES = ("taylor", "blockprod")  # phases that run bf16x3 products (padded 
 HBM_PEAK = 8.0e12
 
 
+# HBM bytes per launch (read, written) of the kernel behind a timed phase,
+# from two rocprofv3 PMC runs (FETCH_SIZE, WRITE_SIZE) scaled by the same
+# counters on a 256 MiB device copy (x2.0 and x1.0); the table, commands
+# and calibration are in profiles/hbm_traffic_pmc.md.  FP32 chains.
+TRAFFIC = {
+    ("c2_transmon_cnot", "bwd_blocks"): ("k_wB2", 177385, 31744),
+    ("c2_transmon_cnot", "fwd_blocks"): ("k_wF2", 138760, 32768),
+    ("c2_transmon_cnot", "fwd_replay"): ("k_wF3", 4964095, 1056768),
+    ("c2_transmon_cnot", "bwd_pairs"): ("k_wB3", 5136130, 1024000),
+    ("c2_transmon_cnot", "adjoint"): ("k_adjoint16", 15218155, 64000),
+    ("c2_transmon_cnot", "blockprod"): ("k_blockprod_small", 4186595, 129024),
+    ("c2_transmon_cnot", "taylor"): ("k_expm_small", 405554, 16384000),
+    ("c2_transmon_cnot", "norm"): ("k_norm<16>", 451910, 2144),
+    ("c4_spin_chain", "taylor"): ("k_stage64", 6357023639, 3036795838),
+}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -372,8 +389,13 @@ def main():
         achieved, peak, unit = units / avg_s / 1e9, HBM_PEAK / 1e9, "GB/s"
     else:
         achieved, peak, unit = units / avg_s / 1e12, peak_of(dom, bound) / 1e12, "TFLOP/s"
+    tr = TRAFFIC.get((prob.name, dom)) if args.precision == "fp32" else None
     roofline = dict(kernel=dom, bound=bound, achieved=achieved, peak=peak, unit=unit,
-                    frac=achieved / peak, traffic=None)
+                    frac=achieved / peak, traffic=(tr[1] + tr[2]) if tr else None)
+    if tr:
+        roofline["traffic_kernel"] = tr[0]
+        roofline["traffic_read_bytes"] = tr[1]
+        roofline["traffic_written_bytes"] = tr[2]
     for k, v in kernels.items():
         b, un = algorithmic_work(prob, info, k, v["launches"] * args.steps, args.precision,
                                  args.steps)
