@@ -45,7 +45,6 @@ TRAFFIC = {
     ("c2_transmon_cnot", "adjoint"): ("k_adjoint16", 15218155, 64000),
     ("c2_transmon_cnot", "blockprod"): ("k_blockprod_small", 4186595, 129024),
     ("c2_transmon_cnot", "taylor"): ("k_expm_small", 405554, 16384000),
-    ("c2_transmon_cnot", "norm"): ("k_norm<16>", 451910, 2144),
     ("c4_spin_chain", "taylor"): ("k_stage64", 6357023639, 3036795838),
 }
 

@@ -87,9 +87,10 @@ template <int COLS>
 __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
                                               const double *__restrict__ u, int d, int M, int N,
                                               double dt, unsigned long long *theta_bits,
-                                              SelectArgs sel) {
+                                              SelectArgs sel, int hs_lds) {
   constexpr int LANES = 256 / COLS, STEPS = LANES * NRM_SW;
-  extern __shared__ double coef[];  // [STEPS][M] control amplitudes of the block's steps
+  extern __shared__ __align__(16) double coef[];  // [STEPS][M] amplitudes, then (hs) the
+                                    // Hamiltonians when they fit (d <= 32)
   __shared__ unsigned long long red[4];
   const int t = threadIdx.x;
   const int sl = t / COLS;
@@ -98,6 +99,15 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
   for (int e = t; e < STEPS * M; e += 256) {
     const int sj = e / M, k = e - sj * M;
     coef[e] = (j0 + sj < N) ? u[(long)k * N + j0 + sj] : 0.0;
+  }
+  // small d: all (M+1) Hamiltonians staged in LDS once (coalesced), so the
+  // row loop below reads LDS instead of waiting on L2 row by row
+  const double *Hsrc = H64;
+  if (hs_lds) {
+    double *hs = coef + STEPS * M;
+    const long tot = (long)(M + 1) * d * d * 2;
+    for (long e = t; e < tot; e += 256) hs[e] = H64[e];
+    Hsrc = hs;
   }
   __syncthreads();
   // step lane sl: steps j0 + NRM_SW sl .. + NRM_SW - 1 (LDS broadcasts of
@@ -110,7 +120,7 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
     const long dd = (long)d * d;
 #pragma unroll 4
     for (int r = 0; r < d; ++r) {
-      const double2 h0 = *(const double2 *)(H64 + ((long)r * d + col) * 2);
+      const double2 h0 = *(const double2 *)(Hsrc + ((long)r * d + col) * 2);
       double hr[NRM_SW], hi[NRM_SW];
 #pragma unroll
       for (int s = 0; s < NRM_SW; ++s) {
@@ -122,7 +132,7 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
 #pragma unroll
         for (int q = 0; q < NRM_KC; ++q)
           hk[q] = (k0 + q < M)
-                      ? *(const double2 *)(H64 + ((long)(k0 + q + 1) * dd + (long)r * d + col) * 2)
+                      ? *(const double2 *)(Hsrc + ((long)(k0 + q + 1) * dd + (long)r * d + col) * 2)
                       : make_double2(0.0, 0.0);
 #pragma unroll
         for (int q = 0; q < NRM_KC; ++q) {
@@ -198,9 +208,12 @@ hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, 
   auto go = [&](auto cols) {
     constexpr int COLS = decltype(cols)::value, STEPS = 256 / COLS * NRM_SW;
     dim3 grid((N + STEPS - 1) / STEPS, (d + COLS - 1) / COLS);
-    const size_t shm = sizeof(double) * STEPS * M;
+    const size_t shc = sizeof(double) * STEPS * M;
+    const size_t shh = sizeof(double) * (size_t)(M + 1) * d * d * 2;
+    const int hs_lds = (COLS < 64 && shc + shh <= 48 * 1024) ? 1 : 0;
+    const size_t shm = shc + (hs_lds ? shh : 0);
     hipLaunchKernelGGL(k_norm<COLS>, grid, dim3(256), shm, st, H64, u, d, M, N, dt, theta_bits,
-                       sel);
+                       sel, hs_lds);
   };
   if (d > 32)
     go(std::integral_constant<int, 64>());
