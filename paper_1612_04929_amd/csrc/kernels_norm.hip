@@ -167,31 +167,29 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
   __syncthreads();
   __shared__ int last;
   const unsigned nblk = gridDim.x * gridDim.y;
-  const unsigned bid = blockIdx.y * gridDim.x + blockIdx.x;
   if (t == 0) {
     unsigned long long m = red[0];
     for (int i = 1; i < 4; ++i) m = red[i] > m ? red[i] : m;
-    sel.part[bid] = m;
-    __threadfence();
-    last = atomicAdd(sel.ticket, 1u) == nblk - 1;
+    // Two device-scope atomics; the ticket's operand is made to depend on
+    // the value the maximum returns (the empty asm hides that it is always
+    // one), so the ticket is taken only once the maximum has been performed
+    // at the device's coherence point, where the last workgroup reads it.
+    // No fence: on this multi-die chip a device-scope release writes back
+    // the L2, which costs more than the whole kernel at small sizes.
+    const unsigned long long prev = atomicMax(sel.acc, m);
+    unsigned one = 1u;
+    asm volatile("" : "+v"(one) : "v"(prev));
+    last = atomicAdd(sel.ticket, one) == nblk - 1;
   }
   __syncthreads();
   if (!last) return;  // block-uniform
-  // the last workgroup: theta_max from the per-workgroup maxima, the
-  // drift word cleared for this call, (p, n) chosen, the ticket reset
-  __threadfence();
-  unsigned long long m = 0ull;
-  for (unsigned i = t; i < nblk; i += 256) {
-    const unsigned long long x =
-        __hip_atomic_load(sel.part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    m = x > m ? x : m;
-  }
-  m = wave_max(m);
-  if ((t & 63) == 0) red[t >> 6] = m;
-  __syncthreads();
+  // the last workgroup: theta_max (reading and clearing the accumulator in
+  // one atomic), the drift word cleared for this call, (p, n) chosen, the
+  // ticket reset
   if (t < 64) {
-    unsigned long long tb = red[0];
-    for (int i = 1; i < 4; ++i) tb = red[i] > tb ? red[i] : tb;
+    unsigned long long tb = 0ull;
+    if (t == 0) tb = atomicExch(sel.acc, 0ull);
+    tb = __shfl(tb, 0, 64);
     if (t == 0) {
       theta_bits[0] = tb;
       theta_bits[1] = 0ull;  // drift, accumulated by the penalty kernel
@@ -199,7 +197,7 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
     if (sel.pn)
       select_pn(__longlong_as_double((long long)tb), dt, sel.tol, sel.n_cap, sel.p_cap,
                 sel.fixed_p, sel.fixed_n, sel.pn, sel.sc);
-    if (t == 0) *sel.ticket = 0u;
+    if (t == 0) atomicExch(sel.ticket, 0u);
   }
 }
 

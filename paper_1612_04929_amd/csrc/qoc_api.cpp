@@ -101,8 +101,7 @@ struct qoc_handle {
   int levels_alloc = 0;
   void *ckpt = nullptr, *lam_ckpt = nullptr, *mu = nullptr;  // (nb+1) sets
   void *psi_buf = nullptr, *lam_buf = nullptr;                // N+1, N sets
-  unsigned long long *bits = nullptr;  // [theta, drift, norm ticket, pen ticket]
-  unsigned long long *norm_part = nullptr;  // per-workgroup maxima of the norm kernel
+  unsigned long long *bits = nullptr;  // [theta, drift, norm ticket, -, norm accumulator]
   double *zinfo = nullptr;    // 3 + 2S
   double *part = nullptr;     // 3 x npart
   int *pn_dev = nullptr;      // device-side (p, n, status)
@@ -170,7 +169,7 @@ void release(qoc_handle *h) {
   void **ptrs[] = {&h->Hf, (void **)&h->H64, (void **)&h->u_dev, (void **)&h->out_dev,
                    (void **)&h->grad_dev, &h->psi0, (void **)&h->psiT64, (void **)&h->w64,
                    &h->pw, &h->X, &h->Qa, &h->Qb, &h->Dlev, &h->ckpt, &h->lam_ckpt, &h->mu,
-                   &h->psi_buf, &h->lam_buf, (void **)&h->bits, (void **)&h->norm_part,
+                   &h->psi_buf, &h->lam_buf, (void **)&h->bits,
                    (void **)&h->zinfo, (void **)&h->part, (void **)&h->pn_dev,
                    (void **)&h->sc_dev, &h->adj, (void **)&h->adj_part};
   for (void **p : ptrs)
@@ -332,9 +331,9 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   if (h->has_pen) ALLOC(h->mu, ((size_t)h->nb * set + slack) * sizeof(T));
   ALLOC(h->psi_buf, ((size_t)(N + 1) * set + slack) * sizeof(T));
   ALLOC(h->lam_buf, ((size_t)N * set + slack) * sizeof(T));
-  ALLOC(h->bits, 4 * sizeof(unsigned long long));  // theta, drift, tickets
-  HIP_TRY(hipMemset(h->bits, 0, 4 * sizeof(unsigned long long)));  // tickets start at zero
-  ALLOC(h->norm_part, ((size_t)N + 64) * sizeof(unsigned long long));
+  // theta, drift, norm ticket, (unused), norm accumulator
+  ALLOC(h->bits, 8 * sizeof(unsigned long long));
+  HIP_TRY(hipMemset(h->bits, 0, 8 * sizeof(unsigned long long)));  // ticket, accumulator start at zero
   ALLOC(h->zinfo, (size_t)(3 + 2 * S) * sizeof(double));
   h->npart = std::max(1, std::min(1024, (N + 3) / 4));
   ALLOC(h->part, (size_t)3 * h->npart * sizeof(double));
@@ -523,7 +522,7 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     {
       PhaseTimer tm(h, QOC_PHASE_NORM, st);
       qoc::SelectArgs sel{h->pn_dev, h->sc_dev, (unsigned *)(h->bits + 2), h->tol, n_cap, p_cap,
-                          h->fixed_p, h->fixed_n, h->norm_part};
+                          h->fixed_p, h->fixed_n, h->bits + 4};
       HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, sel, st));
     }
     {
@@ -544,10 +543,10 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
       // a fixed (p, n) is checked against the tolerance on the device
       // (status 2 in pn_dev), so the call needs no host round trip
       qoc::SelectArgs sel{nullptr, nullptr, (unsigned *)(h->bits + 2), h->tol, 60, 30, 0, 0,
-                          h->norm_part};
+                          h->bits + 4};
       if (h->fixed_p >= 2)
         sel = qoc::SelectArgs{h->pn_dev, h->sc_dev, (unsigned *)(h->bits + 2), h->tol, 60, 30,
-                              h->fixed_p, h->fixed_n, h->norm_part};
+                              h->fixed_p, h->fixed_n, h->bits + 4};
       HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, sel, st));
     }
     if (h->fixed_p >= 2) {

@@ -37,11 +37,11 @@ hipError_t launch_assemble(const T *Hf, const double *u, int dp, int M, int N, T
 
 template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hipStream_t st);
 
-// The last workgroup of the norm kernel (found with `ticket`, zero at the
-// first launch and reset by that workgroup) reduces the per-workgroup
-// maxima in `part` (one word per workgroup; at most N + 64 words), writes
-// theta_bits[0], clears theta_bits[1] (the drift word of the call) and,
-// when pn is not null, chooses (p, n): pn = {p, n, status},
+// Each workgroup of the norm kernel folds its maximum into `acc` (atomic
+// max on the FP64 bit pattern) and takes a number from `ticket`; the last
+// one (both words zero at the first launch and cleared by that workgroup)
+// writes theta_bits[0], clears theta_bits[1] (the drift word of the call)
+// and, when pn is not null, chooses (p, n): pn = {p, n, status},
 // sc = {dt / 2^n, theta}; status 1 when the pair exceeds n_cap / p_cap or
 // none meets tol, 2 when a fixed pair (fixed_p >= 2) misses tol here.
 struct SelectArgs {
@@ -50,7 +50,7 @@ struct SelectArgs {
   unsigned *ticket;
   double tol;
   int n_cap, p_cap, fixed_p, fixed_n;
-  unsigned long long *part;
+  unsigned long long *acc;
 };
 // theta_max = max_j ||dt H_j||_1 in FP64 (maximum on the bit pattern).
 hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, double dt,
