@@ -290,6 +290,28 @@ def bench_batch(args):
     print(json.dumps(res), flush=True)
 
 
+def single_kernel_phases(info, sweep):
+    """Phases of a cost + gradient call whose every timer brackets exactly
+    one kernel launch: the norm (k_norm), the step assembly, each Taylor /
+    Paterson-Stockmeyer / squaring stage, the sweeps that run as one kernel
+    (not the per-step variant, which padded d >= 80 picks by default for
+    the block sweeps), on the small path (padded d <= 32) the block-product
+    tree, and at padded d 16 the per-step derivative kernel.  The cost phase
+    (three kernels) and the tiled adjoint (a dozen) are not single kernels."""
+    dp = info["d_pad"]
+    ph = {"norm", "assemble", "taylor"}
+    if dp <= 32:
+        ph.add("blockprod")
+    if dp == 16:
+        ph.add("adjoint")
+    for name, v in zip(["fwd_blocks", "fwd_replay", "bwd_blocks", "bwd_pairs"], sweep):
+        blocks = name in ("fwd_blocks", "bwd_blocks")
+        if dp >= 80 and (v == 2 or (v == 0 and (blocks or dp >= 256))):
+            continue
+        ph.add(name)
+    return ph
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,6 +325,10 @@ def main():
     ap.add_argument("--streams", type=int, default=4, help="c5: streams per iteration")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the sweep autotuner (checkpoint interval, sweep variants)")
+    ap.add_argument("--checkpoint-every", type=int, default=None,
+                    help="fix the checkpoint interval instead of tuning it (with --sweep)")
+    ap.add_argument("--sweep", default=None,
+                    help="fix the four sweep variants, e.g. 1,1,1,1 (with --checkpoint-every)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -322,7 +348,16 @@ def main():
     log(f"[bench] {prob.name}: d={prob.d} M={prob.M} N={prob.N} S={prob.S} "
         f"precision={args.precision}")
     tuned = None
-    if not args.no_tune:
+    if args.checkpoint_every is not None or args.sweep is not None:
+        # a fixed configuration (e.g. the tuned one, for a profiler run
+        # whose kernel averages should cover that configuration alone)
+        sw = [int(x) for x in (args.sweep or "0,0,0,0").split(",")]
+        if len(sw) != 4:
+            ap.error("--sweep takes four comma-separated variants")
+        tuned = dict(checkpoint_every=args.checkpoint_every or 0, sweep=sw, seconds=0.0,
+                     table=[], fixed=True)
+        from paper_1612_04929_amd import tune as qtune
+    elif not args.no_tune:
         from paper_1612_04929_amd import tune as qtune
         tuned = qtune.tune(prob, precision=args.precision)
         log(f"[bench] tuned: L={tuned['checkpoint_every']} sweeps={tuned['sweep']} "
@@ -374,7 +409,10 @@ def main():
         if calls:
             kernels[ph] = dict(total_ms=tms / args.steps, launches=calls // args.steps,
                                avg_launch_ms=tms / calls)
-    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    # the roofline kernel: the largest phase whose every timer brackets one
+    # kernel launch (so its average is one kernel's average launch time)
+    single = single_kernel_phases(info, tuned["sweep"] if tuned else [0, 0, 0, 0])
+    dom = max((k for k in kernels if k in single), key=lambda k: kernels[k]["total_ms"])
     bound, units = algorithmic_work(prob, info, dom, kernels[dom]["launches"] * args.steps,
                                     args.precision, args.steps)
     avg_s = kernels[dom]["avg_launch_ms"] / 1e3
@@ -431,7 +469,7 @@ def main():
     res["ms_per_step_with_phase_events"] = ms_profiled
     if tuned:
         res["tuning"] = dict(checkpoint_every=tuned["checkpoint_every"], sweep=tuned["sweep"],
-                             seconds=tuned["seconds"],
+                             seconds=tuned["seconds"], fixed=bool(tuned.get("fixed")),
                              candidates={r["L"]: round(r["ms"], 4) for r in tuned["table"]})
     res["diagnostics"] = dict(theta_max=info["theta_max"], norm_drift=info["norm_drift"],
                               n_blocks=info["n_blocks"], d_pad=info["d_pad"],

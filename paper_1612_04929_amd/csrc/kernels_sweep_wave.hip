@@ -15,8 +15,14 @@
 
 namespace qoc {
 
+#ifndef QOC_WAVE_RD16
+#define QOC_WAVE_RD16 4
+#endif
+#ifndef QOC_WAVE_RD32
+#define QOC_WAVE_RD32 2
+#endif
 template <int DP> struct WaveRing {
-  static constexpr int RD = DP <= 16 ? 4 : 2;  // steps prefetched ahead
+  static constexpr int RD = DP <= 16 ? QOC_WAVE_RD16 : QOC_WAVE_RD32;  // steps prefetched ahead
 };
 
 __device__ __forceinline__ void wave_lds_fence() {
