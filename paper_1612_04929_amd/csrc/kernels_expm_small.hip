@@ -12,6 +12,11 @@
 // Also: block products E_b = U_{end-1} ... U_{start} - I of the two-level
 // sweep, one group per block, accumulated in LDS in D-form
 // (E <- D + E + D E).
+//
+// When asked for (Dh / Eh not null), both kernels also write the conjugate
+// transposes D^H and E^H, read from the LDS copy they already hold: the
+// costate sweeps then stream rows of D^H with the same contiguous 16-byte
+// loads as the state sweeps stream rows of D.
 #include "qoc_device.h"
 #include "qoc_kernels.h"
 
@@ -99,7 +104,7 @@ __global__ __launch_bounds__(256) void k_expm_small(const T *__restrict__ Hf,
                                                     const double *__restrict__ u, int M, int N,
                                                     const int *__restrict__ pn,
                                                     const double *__restrict__ sc, T *X,
-                                                    T *Dlev) {
+                                                    T *Dlev, T *Dh) {
   constexpr int GS = 64 * GW, GPB = 4 / GW;
   constexpr int PL = DP * DP;
   constexpr int MAXT = (DP / 16) * (DP / 16) / GW + 1;
@@ -151,6 +156,15 @@ __global__ __launch_bounds__(256) void k_expm_small(const T *__restrict__ Hf,
       lds_epilogue<T, DP, GW>(cr, ci, (T)1, Qr, Qi, (T)2, (T)0, Qr, Qi, Di, Di + PL);
       gsync<GW>();
     }
+    if (Dh) {  // uniform
+      T *o = Dh + j * 2 * PL;
+      for (int e = gt; e < PL; e += GS) {
+        const int r = e / DP, c = e - r * DP;
+        o[e] = Qr[c * DP + r];
+        o[PL + e] = -Qi[c * DP + r];
+      }
+      gsync<GW>();
+    }
   }
 }
 
@@ -158,7 +172,7 @@ __global__ __launch_bounds__(256) void k_expm_small(const T *__restrict__ Hf,
 // step matrices of the next RD steps held in a register ring.
 template <typename T, int DP, int GW>
 __global__ __launch_bounds__(256) void k_blockprod_small(const T *__restrict__ D, int N, int L,
-                                                         int nb, T *E) {
+                                                         int nb, T *E, T *Eh) {
   constexpr int GS = 64 * GW, GPB = 4 / GW;
   constexpr int PL = DP * DP;
   constexpr int MAXT = (DP / 16) * (DP / 16) / GW + 1;
@@ -220,6 +234,13 @@ __global__ __launch_bounds__(256) void k_blockprod_small(const T *__restrict__ D
       }
     }
     for (int e = gt; e < 2 * PL; e += GS) E[b * 2 * PL + e] = Er[e];
+    if (Eh) {  // uniform
+      for (int e = gt; e < PL; e += GS) {
+        const int r = e / DP, c = e - r * DP;
+        Eh[b * 2 * PL + e] = Er[c * DP + r];
+        Eh[b * 2 * PL + PL + e] = -Ei[c * DP + r];
+      }
+    }
     gsync<GW>();
   }
 }
@@ -230,25 +251,25 @@ template <typename T> bool small_expm_ok(int dp) {
 
 template <typename T>
 hipError_t launch_expm_small(const T *Hf, const double *u, int dp, int M, int N, const int *pn,
-                             const double *sc, T *X, T *Dlev, hipStream_t st) {
+                             const double *sc, T *X, T *Dlev, T *Dh, hipStream_t st) {
   switch (dp) {
     case 16: {
       const long blocks = std::min<long>((N + 3) / 4, 4096);
       hipLaunchKernelGGL((k_expm_small<T, 16, 1>), dim3(blocks), dim3(256), 0, st, Hf, u, M, N,
-                         pn, sc, X, Dlev);
+                         pn, sc, X, Dlev, Dh);
       break;
     }
     case 32: {
       const long blocks = std::min<long>(N, 4096);
       hipLaunchKernelGGL((k_expm_small<T, 32, 4>), dim3(blocks), dim3(256), 0, st, Hf, u, M, N,
-                         pn, sc, X, Dlev);
+                         pn, sc, X, Dlev, Dh);
       break;
     }
     case 48: {
       if constexpr (sizeof(T) == 4) {
         const long blocks = std::min<long>(N, 4096);
         hipLaunchKernelGGL((k_expm_small<T, 48, 4>), dim3(blocks), dim3(256), 0, st, Hf, u, M,
-                           N, pn, sc, X, Dlev);
+                           N, pn, sc, X, Dlev, Dh);
         break;
       }
       return hipErrorInvalidValue;
@@ -260,20 +281,21 @@ hipError_t launch_expm_small(const T *Hf, const double *u, int dp, int M, int N,
 }
 
 template <typename T>
-hipError_t launch_blockprod_small(const T *D, int dp, int N, int L, int nb, T *E, hipStream_t st) {
+hipError_t launch_blockprod_small(const T *D, int dp, int N, int L, int nb, T *E, T *Eh,
+                                  hipStream_t st) {
   switch (dp) {
     case 16:
       hipLaunchKernelGGL((k_blockprod_small<T, 16, 1>), dim3((nb + 3) / 4), dim3(256), 0, st, D,
-                         N, L, nb, E);
+                         N, L, nb, E, Eh);
       break;
     case 32:
       hipLaunchKernelGGL((k_blockprod_small<T, 32, 4>), dim3(nb), dim3(256), 0, st, D, N, L, nb,
-                         E);
+                         E, Eh);
       break;
     case 48:
       if constexpr (sizeof(T) == 4) {
         hipLaunchKernelGGL((k_blockprod_small<T, 48, 4>), dim3(nb), dim3(256), 0, st, D, N, L,
-                           nb, E);
+                           nb, E, Eh);
         break;
       }
       return hipErrorInvalidValue;
@@ -287,13 +309,13 @@ template bool small_expm_ok<float>(int);
 template bool small_expm_ok<double>(int);
 template hipError_t launch_expm_small<float>(const float *, const double *, int, int, int,
                                              const int *, const double *, float *, float *,
-                                             hipStream_t);
+                                             float *, hipStream_t);
 template hipError_t launch_expm_small<double>(const double *, const double *, int, int, int,
                                               const int *, const double *, double *, double *,
-                                              hipStream_t);
+                                              double *, hipStream_t);
 template hipError_t launch_blockprod_small<float>(const float *, int, int, int, int, float *,
-                                                  hipStream_t);
+                                                  float *, hipStream_t);
 template hipError_t launch_blockprod_small<double>(const double *, int, int, int, int, double *,
-                                                   hipStream_t);
+                                                   double *, hipStream_t);
 
 }  // namespace qoc

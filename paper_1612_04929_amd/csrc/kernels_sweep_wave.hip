@@ -1,13 +1,22 @@
-// Single-wavefront sweeps for the smallest problems (S * d_pad <= 64).
+// Single-wavefront sweeps for the smallest problems (padded d 16 or 32).
 //
 // The blocked two-level scan of kernels_sweep.hip (F2 / F3 / B2 / B3) with
-// the whole state set in one wavefront: lane l owns output (s, m) with
-// l mod (S d_pad) = s d_pad + m.  Each lane keeps its row of op(D_j) for the
-// next RD steps in registers (a prefetch ring), reads its column of the
-// state from LDS (a broadcast within the lanes of one column) and writes
-// its new entry back; there is no workgroup barrier on the sequential path.
-// Lanes beyond S d_pad duplicate an owner lane exactly, so every store is
-// unconditional and the compiler's wait counts stay exact.
+// one wavefront per state (the S states of a set never mix, so they run as
+// independent wavefronts, grid dimension y).  Output row m of a step is
+// shared by KQ = 64 / d_pad adjacent lanes: lane (m, kq) takes the inner
+// indices kq KC .. kq KC + KC - 1 (KC = d_pad / KQ) of
+//   y_m = x_m + sum_k op(D)[m][k] x_k  (+ w_m aux_m),
+// and the KQ partial sums are combined with DPP lane swizzles, which leave
+// the bitwise identical total in every lane of the group (each swizzle adds
+// the same two values in either order).  Each lane keeps its KC-wide slice
+// of row m for the next RD steps in registers (a prefetch ring), reads its
+// KC entries of the state from LDS and, after the update, the group writes
+// y_m back; there is no workgroup barrier on the sequential path.  The
+// costate passes read rows of D^H and E^H, written by the small-path
+// kernels, so every pass streams contiguous 16-byte pieces and no
+// arithmetic waits on a load in flight.  All lanes of a group store the
+// same value to the same address, so every store is unconditional and the
+// compiler's wait counts stay exact.
 #include <type_traits>
 
 #include "qoc_device.h"
@@ -16,12 +25,14 @@
 namespace qoc {
 
 #ifndef QOC_WAVE_RD16
-#define QOC_WAVE_RD16 4
+#define QOC_WAVE_RD16 8
 #endif
 #ifndef QOC_WAVE_RD32
-#define QOC_WAVE_RD32 2
+#define QOC_WAVE_RD32 4
 #endif
-template <int DP> struct WaveRing {
+template <int DP> struct WaveGeo {
+  static constexpr int KQ = 64 / DP;  // lanes per output row
+  static constexpr int KC = DP / KQ;  // inner indices per lane
   static constexpr int RD = DP <= 16 ? QOC_WAVE_RD16 : QOC_WAVE_RD32;  // steps prefetched ahead
 };
 
@@ -32,38 +43,51 @@ __device__ __forceinline__ void wave_lds_fence() {
   asm volatile("" ::: "memory");
 }
 
-// Row m of op(D): D itself (ADJ = false) or D^H (ADJ = true).
-template <typename T, int DP, bool ADJ>
-__device__ __forceinline__ void w_load_row(const T *__restrict__ D, int m, T (&r)[2 * DP]) {
-  if (!ADJ) {
-#pragma unroll
-    for (int k = 0; k < DP; ++k) {
-      r[k] = D[m * DP + k];
-      r[DP + k] = D[DP * DP + m * DP + k];
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < DP; ++k) {
-      r[k] = D[k * DP + m];
-      r[DP + k] = -D[DP * DP + k * DP + m];
-    }
-  }
+// v from lane l ^ 1 (CTRL 0xB1) or l ^ 2 (CTRL 0x4E): DPP quad permutations
+template <int CTRL> __device__ __forceinline__ float dpp_swz(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_swz(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <typename T, int KQ> __device__ __forceinline__ T group_sum(T v) {
+  v += dpp_swz<0xB1>(v);
+  if (KQ == 4) v += dpp_swz<0x4E>(v);
+  return v;
 }
 
 struct WLane {
-  int s, m, SD, S;
+  int m, kq;  // output row, inner-index slice
+  int o, oi;  // (s, m) in a state set: real and imaginary entries
 };
 
-// y = x + op(D) x (+ w o aux) for this lane's output; x lives in LDS xs.
-// The dot product runs as WA independent partial sums (a short dependency
-// chain on the sequential path), the state column read in 16-byte pieces.
+// Slice kq of row m of a step matrix (D, or D^H for the costate passes).
 template <typename T, int DP>
-__device__ __forceinline__ void w_apply(const WLane &L, const T (&r)[2 * DP], const T *xs,
-                                        T aux_r, T aux_i, T wgt, T &yr, T &yi) {
-  constexpr int WA = 4;
+__device__ __forceinline__ void w_load(const T *__restrict__ D, const WLane &L,
+                                       T (&r)[2 * WaveGeo<DP>::KC]) {
+  constexpr int KC = WaveGeo<DP>::KC;
+  const T *p = D + L.m * DP + L.kq * KC;
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    r[k] = p[k];
+    r[KC + k] = p[DP * DP + k];
+  }
+}
+
+// sum_k row[k] x_k over the whole row (all KQ lanes of the group); xs is
+// this wavefront's state in LDS, [re DP][im DP].  The slice's dot product
+// runs as WA independent partial sums, the state read in 16-byte pieces.
+template <typename T, int DP>
+__device__ __forceinline__ void w_dot(const WLane &L, const T (&r)[2 * WaveGeo<DP>::KC],
+                                      const T *xs, T &sr, T &si) {
+  constexpr int KC = WaveGeo<DP>::KC, KQ = WaveGeo<DP>::KQ;
+  constexpr int WA = KC < 4 ? KC : 4;
   typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
   constexpr int VN = 16 / sizeof(T);
-  const T *xr = xs + L.s * DP, *xi = xs + L.SD + L.s * DP;
+  const T *xr = xs + L.kq * KC, *xi = xs + DP + L.kq * KC;
   T pr[WA], pi[WA];
 #pragma unroll
   for (int q = 0; q < WA; ++q) {
@@ -71,99 +95,101 @@ __device__ __forceinline__ void w_apply(const WLane &L, const T (&r)[2 * DP], co
     pi[q] = 0;
   }
 #pragma unroll
-  for (int k0 = 0; k0 < DP; k0 += VN) {
+  for (int k0 = 0; k0 < KC; k0 += VN) {
     const V xv = *reinterpret_cast<const V *>(xr + k0);
     const V yv = *reinterpret_cast<const V *>(xi + k0);
     const T *xa = reinterpret_cast<const T *>(&xv), *ya = reinterpret_cast<const T *>(&yv);
 #pragma unroll
     for (int e = 0; e < VN; ++e) {
       const int k = k0 + e, q = k % WA;
-      pr[q] += r[k] * xa[e] - r[DP + k] * ya[e];
-      pi[q] += r[k] * ya[e] + r[DP + k] * xa[e];
+      pr[q] += r[k] * xa[e] - r[KC + k] * ya[e];
+      pi[q] += r[k] * ya[e] + r[KC + k] * xa[e];
     }
   }
-  T ar = 0, ai = 0;
+  T ar = pr[0], ai = pi[0];
 #pragma unroll
-  for (int q = 0; q < WA; ++q) {
+  for (int q = 1; q < WA; ++q) {
     ar += pr[q];
     ai += pi[q];
   }
-  // select, not multiply: an unused auxiliary operand is never touched
-  yr = xr[L.m] + ar + (wgt != (T)0 ? wgt * aux_r : (T)0);
-  yi = xi[L.m] + ai + (wgt != (T)0 ? wgt * aux_i : (T)0);
+  sr = group_sum<T, KQ>(ar);
+  si = group_sum<T, KQ>(ai);
 }
 
-// Ring-pipelined loop over `count` steps.  step(i, row, aux_r, aux_i).
-template <typename T, int DP, bool ADJ, class DPtr, class APtr, class Step>
+// Ring-pipelined loop over `count` steps: step i uses the slice loaded RD
+// steps earlier.  Whole chunks of RD steps run with no condition around
+// the loads (the index is clamped to the last step), so the compiler can
+// count the loads in flight exactly and wait only for the slot it reads;
+// a last partial chunk only drains the ring.  step(i, slice, aux_r, aux_i).
+template <typename T, int DP, class DPtr, class APtr, class Step>
 __device__ __forceinline__ void w_pipeline(const WLane &L, int count, DPtr dptr, APtr aptr,
                                            Step step) {
-  constexpr int RD = WaveRing<DP>::RD;
+  constexpr int RD = WaveGeo<DP>::RD, KC = WaveGeo<DP>::KC;
   if (count <= 0) return;
-  T r[RD][2 * DP];
+  T r[RD][2 * KC];
   T ar[RD], ai[RD];
-  const int o = L.s * DP + L.m;
 #pragma unroll
   for (int q = 0; q < RD; ++q) {
     const int i = q < count ? q : count - 1;
-    w_load_row<T, DP, ADJ>(dptr(i), L.m, r[q]);
+    w_load<T, DP>(dptr(i), L, r[q]);
     const T *a = aptr(i);
-    ar[q] = a[o];
-    ai[q] = a[L.SD + o];
+    ar[q] = a[L.o];
+    ai[q] = a[L.oi];
   }
-  for (int i0 = 0; i0 < count; i0 += RD) {
+  int i0 = 0;
+  for (; i0 + RD <= count; i0 += RD) {
 #pragma unroll
     for (int q = 0; q < RD; ++q) {
-      const int i = i0 + q;
-      if (i < count) {
-        step(i, r[q], ar[q], ai[q]);
-        const int nx = (i + RD < count) ? i + RD : count - 1;
-        w_load_row<T, DP, ADJ>(dptr(nx), L.m, r[q]);
-        const T *a = aptr(nx);
-        ar[q] = a[o];
-        ai[q] = a[L.SD + o];
-      }
+      step(i0 + q, r[q], ar[q], ai[q]);
+      const int nx = (i0 + q + RD < count) ? i0 + q + RD : count - 1;
+      w_load<T, DP>(dptr(nx), L, r[q]);
+      const T *a = aptr(nx);
+      ar[q] = a[L.o];
+      ai[q] = a[L.oi];
     }
   }
+#pragma unroll
+  for (int q = 0; q < RD - 1; ++q)
+    if (i0 + q < count) step(i0 + q, r[q], ar[q], ai[q]);
 }
 
-#define W_SETUP                                                        \
-  __shared__ __align__(16) T xs[2][128];                               \
-  WLane L;                                                             \
-  L.S = a.S;                                                           \
-  L.SD = a.S * DP;                                                     \
-  {                                                                    \
-    const int l = threadIdx.x % L.SD;                                  \
-    L.s = l / DP;                                                      \
-    L.m = l - L.s * DP;                                                \
-  }                                                                    \
-  const int o = L.s * DP + L.m;                                        \
-  const long set = 2L * a.S * DP, mat = 2L * DP * DP;                  \
-  int cur = 0;                                                         \
+// One wavefront: state s = blockIdx.y of a set [2][S][DP].
+#define W_SETUP                                                  \
+  constexpr int KC = WaveGeo<DP>::KC;                            \
+  __shared__ __align__(16) T xs[2][2 * DP];                      \
+  WLane L;                                                       \
+  L.m = threadIdx.x / WaveGeo<DP>::KQ;                           \
+  L.kq = threadIdx.x - L.m * WaveGeo<DP>::KQ;                    \
+  L.o = (int)blockIdx.y * DP + L.m;                              \
+  L.oi = (a.S + (int)blockIdx.y) * DP + L.m;                     \
+  const long set = 2L * a.S * DP, mat = 2L * DP * DP;            \
+  int cur = 0;                                                   \
   (void)mat;
 
-template <typename T>
-__device__ __forceinline__ void w_put(T *xs, const WLane &L, int o, T vr, T vi) {
-  xs[o] = vr;
-  xs[L.SD + o] = vi;
+template <typename T> __device__ __forceinline__ void w_put(T *xs, int m, int dp, T vr, T vi) {
+  xs[m] = vr;
+  xs[dp + m] = vi;
 }
 
 // ------------------------------------------------------------------ F2
 template <typename T, int DP> __global__ __launch_bounds__(64) void k_wF2(SweepArgs<T> a) {
   W_SETUP
-  T vr = a.psi0[o], vi = a.psi0[L.SD + o];
-  w_put(xs[0], L, o, vr, vi);
-  a.ckpt[o] = vr;
-  a.ckpt[L.SD + o] = vi;
+  T xr = a.psi0[L.o], xi = a.psi0[L.oi];
+  w_put(xs[0], L.m, DP, xr, xi);
+  a.ckpt[L.o] = xr;
+  a.ckpt[L.oi] = xi;
   wave_lds_fence();
   auto dptr = [&](int i) -> const T * { return a.E + i * mat; };
   auto aptr = [&](int) -> const T * { return a.psi0; };  // unused
-  w_pipeline<T, DP, false>(L, a.nb, dptr, aptr, [&](int b, const T (&r)[2 * DP], T, T) {
-    T yr, yi;
-    w_apply<T, DP>(L, r, xs[cur], (T)0, (T)0, (T)0, yr, yi);
-    w_put(xs[cur ^ 1], L, o, yr, yi);
+  w_pipeline<T, DP>(L, a.nb, dptr, aptr, [&](int b, const T (&r)[2 * KC], T, T) {
+    T sr, si;
+    w_dot<T, DP>(L, r, xs[cur], sr, si);
+    xr += sr;
+    xi += si;
+    w_put(xs[cur ^ 1], L.m, DP, xr, xi);
     T *c = a.ckpt + (long)(b + 1) * set;
-    c[o] = yr;
-    c[L.SD + o] = yi;
+    c[L.o] = xr;
+    c[L.oi] = xi;
     cur ^= 1;
     wave_lds_fence();
   });
@@ -175,21 +201,23 @@ template <typename T, int DP> __global__ __launch_bounds__(64) void k_wF3(SweepA
   const int b = blockIdx.x;
   const int start = b * a.L, end = min(a.N, start + a.L), cnt = end - start;
   const T *ck = a.ckpt + (long)b * set;
-  T vr = ck[o], vi = ck[L.SD + o];
-  w_put(xs[0], L, o, vr, vi);
-  a.psi_buf[(long)start * set + o] = vr;
-  a.psi_buf[(long)start * set + L.SD + o] = vi;
+  T xr = ck[L.o], xi = ck[L.oi];
+  w_put(xs[0], L.m, DP, xr, xi);
+  a.psi_buf[(long)start * set + L.o] = xr;
+  a.psi_buf[(long)start * set + L.oi] = xi;
   wave_lds_fence();
   auto fptr = [&](int i) -> const T * { return a.D + (start + i) * mat; };
   auto dummy = [&](int) -> const T * { return ck; };
-  w_pipeline<T, DP, false>(L, cnt, fptr, dummy, [&](int i, const T (&r)[2 * DP], T, T) {
-    T yr, yi;
-    w_apply<T, DP>(L, r, xs[cur], (T)0, (T)0, (T)0, yr, yi);
-    w_put(xs[cur ^ 1], L, o, yr, yi);
+  w_pipeline<T, DP>(L, cnt, fptr, dummy, [&](int i, const T (&r)[2 * KC], T, T) {
+    T sr, si;
+    w_dot<T, DP>(L, r, xs[cur], sr, si);
+    xr += sr;
+    xi += si;
+    w_put(xs[cur ^ 1], L.m, DP, xr, xi);
     const int j = start + i;
     if (j + 1 < end || j + 1 == a.N) {  // wave-uniform
-      a.psi_buf[(long)(j + 1) * set + o] = yr;
-      a.psi_buf[(long)(j + 1) * set + L.SD + o] = yi;
+      a.psi_buf[(long)(j + 1) * set + L.o] = xr;
+      a.psi_buf[(long)(j + 1) * set + L.oi] = xi;
     }
     cur ^= 1;
     wave_lds_fence();
@@ -199,41 +227,48 @@ template <typename T, int DP> __global__ __launch_bounds__(64) void k_wF3(SweepA
   // mu <- mu + D_j^H mu + pw o psi_j (j >= 1), over the states written above
   __threadfence_block();
   const T wgt = a.pw[L.m];
-  w_put(xs[cur], L, o, (T)0, (T)0);
+  T mr = (T)0, mi = (T)0;
+  w_put(xs[cur], L.m, DP, mr, mi);
   wave_lds_fence();
-  auto bptr = [&](int i) -> const T * { return a.D + (end - 1 - i) * mat; };
+  auto bptr = [&](int i) -> const T * { return a.Dh + (end - 1 - i) * mat; };
   auto pptr = [&](int i) -> const T * { return a.psi_buf + (long)(end - 1 - i) * set; };
-  w_pipeline<T, DP, true>(L, cnt, bptr, pptr, [&](int i, const T (&r)[2 * DP], T pr, T pi) {
+  w_pipeline<T, DP>(L, cnt, bptr, pptr, [&](int i, const T (&r)[2 * KC], T pr, T pi) {
     const int j = end - 1 - i;
-    T yr, yi;
-    w_apply<T, DP>(L, r, xs[cur], pr, pi, j >= 1 ? wgt : (T)0, yr, yi);
-    w_put(xs[cur ^ 1], L, o, yr, yi);
+    T sr, si;
+    w_dot<T, DP>(L, r, xs[cur], sr, si);
+    // select, not multiply: an unused auxiliary operand is never touched
+    mr += sr + (j >= 1 ? wgt * pr : (T)0);
+    mi += si + (j >= 1 ? wgt * pi : (T)0);
+    w_put(xs[cur ^ 1], L.m, DP, mr, mi);
     cur ^= 1;
     wave_lds_fence();
   });
   T *mu = a.mu + (long)b * set;
-  mu[o] = xs[cur][o];
-  mu[L.SD + o] = xs[cur][L.SD + o];
+  mu[L.o] = mr;
+  mu[L.oi] = mi;
 }
 
 // ------------------------------------------------------------------ B2
 template <typename T, int DP> __global__ __launch_bounds__(64) void k_wB2(SweepArgs<T> a) {
   W_SETUP
   const T *lN = a.lam_ckpt + (long)a.nb * set;
-  w_put(xs[0], L, o, lN[o], lN[L.SD + o]);
+  T xr = lN[L.o], xi = lN[L.oi];
+  w_put(xs[0], L.m, DP, xr, xi);
   wave_lds_fence();
-  const T one = a.mu ? (T)1 : (T)0;
-  auto dptr = [&](int i) -> const T * { return a.E + (a.nb - 1 - i) * mat; };
+  const bool has_mu = a.mu != nullptr;
+  auto dptr = [&](int i) -> const T * { return a.Eh + (a.nb - 1 - i) * mat; };
   auto mptr = [&](int i) -> const T * {
-    return a.mu ? a.mu + (long)(a.nb - 1 - i) * set : a.psi0;  // psi0: finite placeholder
+    return has_mu ? a.mu + (long)(a.nb - 1 - i) * set : a.psi0;  // psi0: finite placeholder
   };
-  w_pipeline<T, DP, true>(L, a.nb - 1, dptr, mptr, [&](int i, const T (&r)[2 * DP], T mr, T mi) {
-    T yr, yi;
-    w_apply<T, DP>(L, r, xs[cur], mr, mi, one, yr, yi);
-    w_put(xs[cur ^ 1], L, o, yr, yi);
+  w_pipeline<T, DP>(L, a.nb - 1, dptr, mptr, [&](int i, const T (&r)[2 * KC], T mr, T mi) {
+    T sr, si;
+    w_dot<T, DP>(L, r, xs[cur], sr, si);
+    xr += sr + (has_mu ? mr : (T)0);
+    xi += si + (has_mu ? mi : (T)0);
+    w_put(xs[cur ^ 1], L.m, DP, xr, xi);
     T *c = a.lam_ckpt + (long)(a.nb - 1 - i) * set;
-    c[o] = yr;
-    c[L.SD + o] = yi;
+    c[L.o] = xr;
+    c[L.oi] = xi;
     cur ^= 1;
     wave_lds_fence();
   });
@@ -245,26 +280,29 @@ template <typename T, int DP> __global__ __launch_bounds__(64) void k_wB3(SweepA
   const int b = blockIdx.x;
   const int start = b * a.L, end = min(a.N, start + a.L);
   const T *c = a.lam_ckpt + (long)(b + 1) * set;
-  w_put(xs[0], L, o, c[o], c[L.SD + o]);
+  T xr = c[L.o], xi = c[L.oi];
+  w_put(xs[0], L.m, DP, xr, xi);
   wave_lds_fence();
   const T wgt = a.pw ? a.pw[L.m] : (T)0;
-  auto dptr = [&](int i) -> const T * { return a.D + (end - 1 - i) * mat; };
+  auto dptr = [&](int i) -> const T * { return a.Dh + (end - 1 - i) * mat; };
   auto pptr = [&](int i) -> const T * { return a.psi_buf + (long)(end - 1 - i) * set; };
-  w_pipeline<T, DP, true>(L, end - 1 - start, dptr, pptr,
-                          [&](int i, const T (&r)[2 * DP], T pr, T pi) {
+  w_pipeline<T, DP>(L, end - 1 - start, dptr, pptr,
+                    [&](int i, const T (&r)[2 * KC], T pr, T pi) {
     const int j = end - 1 - i;
     T *lb = a.lam_buf + (long)j * set;
-    lb[o] = xs[cur][o];  // lambda_{j+1}
-    lb[L.SD + o] = xs[cur][L.SD + o];
-    T yr, yi;
-    w_apply<T, DP>(L, r, xs[cur], pr, pi, j >= 1 ? wgt : (T)0, yr, yi);
-    w_put(xs[cur ^ 1], L, o, yr, yi);
+    lb[L.o] = xr;  // lambda_{j+1}
+    lb[L.oi] = xi;
+    T sr, si;
+    w_dot<T, DP>(L, r, xs[cur], sr, si);
+    xr += sr + (j >= 1 ? wgt * pr : (T)0);
+    xi += si + (j >= 1 ? wgt * pi : (T)0);
+    w_put(xs[cur ^ 1], L.m, DP, xr, xi);
     cur ^= 1;
     wave_lds_fence();
   });
   T *lb = a.lam_buf + (long)start * set;
-  lb[o] = xs[cur][o];
-  lb[L.SD + o] = xs[cur][L.SD + o];
+  lb[L.o] = xr;
+  lb[L.oi] = xi;
 }
 
 template <typename T> bool wave_sweep_ok(int dp, int S) {
@@ -272,16 +310,18 @@ template <typename T> bool wave_sweep_ok(int dp, int S) {
 }
 
 template <typename T, int DP> hipError_t w_launch(int which, const SweepArgs<T> &a, hipStream_t st) {
+  const unsigned S = (unsigned)a.S;
   switch (which) {
-    case 0: hipLaunchKernelGGL((k_wF2<T, DP>), dim3(1), dim3(64), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((k_wF3<T, DP>), dim3(a.nb), dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_wB2<T, DP>), dim3(1), dim3(64), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_wB3<T, DP>), dim3(a.nb), dim3(64), 0, st, a); break;
+    case 0: hipLaunchKernelGGL((k_wF2<T, DP>), dim3(1, S), dim3(64), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_wF3<T, DP>), dim3(a.nb, S), dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_wB2<T, DP>), dim3(1, S), dim3(64), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_wB3<T, DP>), dim3(a.nb, S), dim3(64), 0, st, a); break;
   }
   return hipGetLastError();
 }
 
 template <typename T> hipError_t launch_wave_sweep(int which, const SweepArgs<T> &a, hipStream_t st) {
+  if (!a.Dh || !a.Eh) return hipErrorInvalidValue;
   if (a.dp == 16) return w_launch<T, 16>(which, a, st);
   if (a.dp == 32) return w_launch<T, 32>(which, a, st);
   return hipErrorInvalidValue;

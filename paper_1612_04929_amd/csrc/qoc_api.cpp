@@ -97,6 +97,7 @@ struct qoc_handle {
   double *w64 = nullptr;      // dp
   void *pw = nullptr;         // dp, a_pen / S * w
   void *X = nullptr, *Qa = nullptr, *Qb = nullptr;  // N x 2 dp^2 each
+  void *Eh = nullptr;  // nb x 2 dp^2: E_b^H for the single-wavefront sweeps
   void *Dlev = nullptr;       // levels x N x 2 dp^2
   int levels_alloc = 0;
   void *ckpt = nullptr, *lam_ckpt = nullptr, *mu = nullptr;  // (nb+1) sets
@@ -168,7 +169,7 @@ void dfree(qoc_handle *h, void **p, size_t bytes) {
 void release(qoc_handle *h) {
   void **ptrs[] = {&h->Hf, (void **)&h->H64, (void **)&h->u_dev, (void **)&h->out_dev,
                    (void **)&h->grad_dev, &h->psi0, (void **)&h->psiT64, (void **)&h->w64,
-                   &h->pw, &h->X, &h->Qa, &h->Qb, &h->Dlev, &h->ckpt, &h->lam_ckpt, &h->mu,
+                   &h->pw, &h->X, &h->Qa, &h->Qb, &h->Eh, &h->Dlev, &h->ckpt, &h->lam_ckpt, &h->mu,
                    &h->psi_buf, &h->lam_buf, (void **)&h->bits,
                    (void **)&h->zinfo, (void **)&h->part, (void **)&h->pn_dev,
                    (void **)&h->sc_dev, &h->adj, (void **)&h->adj_part};
@@ -323,6 +324,7 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   ALLOC(h->X, (size_t)N * mat * sizeof(T));
   ALLOC(h->Qa, (size_t)N * mat * sizeof(T));
   ALLOC(h->Qb, (size_t)N * mat * sizeof(T));
+  if (qoc::wave_sweep_ok<T>(dp, S)) ALLOC(h->Eh, (size_t)h->nb * mat * sizeof(T));
   // state buffers carry kRingSlack elements of padding: the small-d sweeps
   // load fixed-size ring slots that may run past the last state set
   const size_t slack = kRingSlack;
@@ -507,6 +509,9 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   T *X = (T *)h->X, *Qa = (T *)h->Qa, *Qb = (T *)h->Qb;
   const T *D = nullptr, *E = nullptr;
   int p = 0, n = 0, Rcap_used = dp;
+  // the single-wavefront sweeps read D^H / E^H (written by the small-path
+  // kernels into Qb, unused there, and Eh)
+  T *Dh_small = (small_path && h->Eh) ? Qb : nullptr;
   if (small_path) {
     // ---- no host round trip: (p, n) chosen on the device, fused chains
     const int n_cap = kSmallNCap, p_cap = kSmallPCap;
@@ -528,12 +533,12 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     {
       PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
       HIP_TRY(qoc::launch_expm_small<T>((const T *)h->Hf, u_dev, dp, M, N, h->pn_dev, h->sc_dev,
-                                        X, (T *)h->Dlev, st));
+                                        X, (T *)h->Dlev, Dh_small, st));
     }
     D = (const T *)h->Dlev;  // slot 0 = D^(n)
     {
       PhaseTimer tm(h, QOC_PHASE_BLOCKPROD, st);
-      HIP_TRY(qoc::launch_blockprod_small<T>(D, dp, N, h->L, h->nb, Qa, st));
+      HIP_TRY(qoc::launch_blockprod_small<T>(D, dp, N, h->L, h->nb, Qa, (T *)h->Eh, st));
     }
     E = Qa;
   } else {
@@ -630,7 +635,7 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   }
   qoc::SweepArgs<T> sw{};
   sw.N = N; sw.L = h->L; sw.nb = h->nb; sw.dp = dp; sw.d = h->d; sw.S = S; sw.M = M;
-  sw.D = D; sw.E = E; sw.psi0 = (const T *)h->psi0; sw.ckpt = (T *)h->ckpt;
+  sw.D = D; sw.E = E; sw.Dh = Dh_small; sw.Eh = Dh_small ? (const T *)h->Eh : nullptr; sw.psi0 = (const T *)h->psi0; sw.ckpt = (T *)h->ckpt;
   sw.psi_buf = (T *)h->psi_buf; sw.lam_ckpt = (T *)h->lam_ckpt; sw.mu = (T *)h->mu;
   sw.lam_buf = (T *)h->lam_buf; sw.w64 = h->w64; sw.pw = (const T *)h->pw;
   sw.drift_bits = h->bits + 1; sw.psiT64 = h->psiT64; sw.u = u_dev;
@@ -639,7 +644,7 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   sw.part = h->part; sw.npart = h->npart;
   // sweep kernels: one wavefront (S d_pad <= 64), one workgroup with a
   // prefetch ring (d_pad <= 64), or the generic streaming kernels
-  const bool wave = qoc::wave_sweep_ok<T>(dp, S);
+  const bool wave = qoc::wave_sweep_ok<T>(dp, S) && sw.Dh && sw.Eh;
   const bool small = !wave && qoc::small_sweep_ok<T>(dp, S);
   const bool wide_ok = !wave && !small && qoc::wide_sweep_ok<T>(dp, S);
   auto sweep = [&](int which) -> hipError_t {

@@ -66,9 +66,11 @@ template <typename T> hipError_t launch_copy(T *dst, const T *src, long n, hipSt
 template <typename T> bool small_expm_ok(int dp);
 template <typename T>
 hipError_t launch_expm_small(const T *Hf, const double *u, int dp, int M, int N, const int *pn,
-                             const double *sc, T *X, T *Dlev, hipStream_t st);
+                             const double *sc, T *X, T *Dlev, T *Dh, hipStream_t st);
+// Dh / Eh: optional conjugate transposes of the final D_j / of E_b (null: not written)
 template <typename T>
-hipError_t launch_blockprod_small(const T *D, int dp, int N, int L, int nb, T *E, hipStream_t st);
+hipError_t launch_blockprod_small(const T *D, int dp, int N, int L, int nb, T *E, T *Eh,
+                                  hipStream_t st);
 
 // Blocked two-level sweep.  State sets are [2][S][dp] (re plane of S
 // states, then im plane).  Block b covers steps [b*L, min(N, (b+1)*L)).
@@ -76,6 +78,7 @@ template <typename T> struct SweepArgs {
   int N, L, nb, dp, d, S, M;
   const T *D;          // N x (2 dp^2): D_j = U_j - I
   const T *E;          // nb x (2 dp^2): block products minus identity
+  const T *Dh, *Eh;    // D_j^H, E_b^H (single-wavefront sweeps)
   const T *psi0;       // one state set
   T *ckpt;             // (nb+1) state sets: psi at block starts
   T *psi_buf;          // (N+1) state sets: psi_j
