@@ -16,7 +16,13 @@ namespace qoc {
 // entry loaded feeds NRM_SW steps, and the step lanes of a block read the
 // same entries (L1 hits).  NRM_KC control Hamiltonians are held in
 // registers at a time.
-constexpr int NRM_SW = 4, NRM_KC = 8;
+constexpr int NRM_KC = 8;
+// steps per thread: one for the small column counts (there the work is a
+// latency chain, and more threads run it), four at 64 columns (reuse of
+// each loaded entry)
+template <int COLS> struct NrmSw {
+  static constexpr int value = COLS >= 64 ? 4 : 1;
+};
 
 // (p, n) from theta by the rule of qoc_taylor_select, one wavefront, one
 // lane per squaring count n; returns {p, n, status} and dt / 2^n.  status:
@@ -29,12 +35,12 @@ __device__ void select_pn(double theta, double dt, double tol, int n_cap, int p_
   int my_p = 0;
   if (lane < 60 && theta >= 0.0) {
     const int n = lane;
-    const double x = ldexp(theta, -n);
+    const double x = ldexp(theta, -n), ex = exp(x), tn = ldexp(1.0, n);
     double f = 1.0, pw = x;
     for (int p = 1; p <= 30; ++p) {
       f *= (p + 1);
       pw *= x;  // x^(p+1)
-      if (p >= 2 && ldexp(1.0, n) * pw / f * exp(x) <= tol) {
+      if (p >= 2 && tn * pw / f * ex <= tol) {
         my_p = p;
         key = (long)(p - 1 + n) * 64 + n;
         break;
@@ -88,6 +94,7 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
                                               const double *__restrict__ u, int d, int M, int N,
                                               double dt, unsigned long long *theta_bits,
                                               SelectArgs sel, int hs_lds) {
+  constexpr int NRM_SW = NrmSw<COLS>::value;
   constexpr int LANES = 256 / COLS, STEPS = LANES * NRM_SW;
   extern __shared__ __align__(16) double coef[];  // [STEPS][M] amplitudes, then (hs) the
                                     // Hamiltonians when they fit (d <= 32)
@@ -106,7 +113,16 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
   if (hs_lds) {
     double *hs = coef + STEPS * M;
     const long tot = (long)(M + 1) * d * d * 2;
-    for (long e = t; e < tot; e += 256) hs[e] = H64[e];
+    // eight loads in flight per lane before the first LDS store
+    long e = t;
+    for (; e + 7 * 256 < tot; e += 8 * 256) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = H64[e + q * 256];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) hs[e + q * 256] = v[q];
+    }
+    for (; e < tot; e += 256) hs[e] = H64[e];
     Hsrc = hs;
   }
   __syncthreads();
@@ -204,7 +220,7 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
 hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, double dt,
                        unsigned long long *theta_bits, const SelectArgs &sel, hipStream_t st) {
   auto go = [&](auto cols) {
-    constexpr int COLS = decltype(cols)::value, STEPS = 256 / COLS * NRM_SW;
+    constexpr int COLS = decltype(cols)::value, STEPS = 256 / COLS * NrmSw<COLS>::value;
     dim3 grid((N + STEPS - 1) / STEPS, (d + COLS - 1) / COLS);
     const size_t shc = sizeof(double) * STEPS * M;
     const size_t shh = sizeof(double) * (size_t)(M + 1) * d * d * 2;

@@ -9,7 +9,7 @@
 //   F3  parallel over blocks and columns: replay psi_j inside each block
 //       from its checkpoint, and the block-local penalty costate mu_b
 //       (the per-step penalties c_j of Table I, C5, are then reduced in
-//       parallel over all steps by k_pen);
+//       parallel over all steps by k_cost);
 //   cost: fidelity overlap in FP64 and the final costate lambda_N;
 //   B2  sequential over blocks: lambda_{bL} = (I + E_b)^H lambda_{(b+1)L} + mu_b;
 //   B3  parallel over blocks and columns: lambda_{j+1} for every step, the
@@ -288,12 +288,14 @@ template <typename T> __global__ __launch_bounds__(256) void k_fwd_replay(SweepA
 }
 
 // ------------------------------------------------------------------ cost
-// FP64, one workgroup each.  k_lam: the fidelity overlaps, F, C_fid and the
-// final costate lambda_N (rounded to the chain precision) -- all the
-// costate sweeps need.  k_total: the weighted total cost from F and the
-// per-workgroup partial sums of k_pen (penalties, |u|^2, variations), so
-// the penalty pass can run beside the costate sweeps.
-template <typename T> __global__ __launch_bounds__(256) void k_lam(SweepArgs<T> a) {
+// FP64.  One launch (k_cost): its last workgroup computes the fidelity
+// overlaps, F, C_fid and the final costate lambda_N (rounded to the chain
+// precision) -- all the costate sweeps need -- while the other workgroups
+// run the penalty pass below.  k_total: the weighted total cost from F and
+// the per-workgroup partial sums of the penalty pass (penalties, |u|^2,
+// variations) and the norm drift from its per-workgroup maxima, in a fixed
+// order.
+template <typename T> __device__ void lam_block(const SweepArgs<T> &a) {
   __shared__ double red[4];
   const int dp = a.dp, d = a.d, S = a.S, N = a.N;
   const long set = 2L * S * dp;
@@ -358,18 +360,25 @@ template <typename T> __global__ __launch_bounds__(256) void k_lam(SweepArgs<T> 
 
 template <typename T> __global__ __launch_bounds__(256) void k_total(SweepArgs<T> a) {
   __shared__ double red[4];
-  double cpen = 0.0, camp = 0.0, cvar = 0.0;
+  __shared__ double dred[4];
+  double cpen = 0.0, camp = 0.0, cvar = 0.0, dmax = 0.0;
   for (int q = threadIdx.x; q < a.npart; q += blockDim.x) {
     cpen += a.part[q];
     camp += a.part[a.npart + q];
     cvar += a.part[2 * a.npart + q];
+    dmax = fmax(dmax, a.part[3 * a.npart + q]);
   }
   cpen = block_sum(cpen, red);
   camp = block_sum(camp, red);
   cvar = block_sum(cvar, red);
+  dmax = wave_max(dmax);
+  if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = dmax;
+  __syncthreads();
   if (threadIdx.x == 0) {
     const double Cfid = 1.0 - a.zinfo[2];
     a.out[0] = a.alpha_fid * Cfid + a.alpha_pen * cpen + a.alpha_amp * camp + a.alpha_var * cvar;
+    const double m = fmax(fmax(dred[0], dred[1]), fmax(dred[2], dred[3]));
+    *a.drift_bits = (unsigned long long)__double_as_longlong(m);
   }
 }
 
@@ -378,15 +387,20 @@ template <typename T> __global__ __launch_bounds__(256) void k_total(SweepArgs<T
 // (1/S) sum_s sum_m w_m |psi_{j+1}^s[m]|^2 written to out, the norm drift
 // max_{j,s} | ||psi_{j+1}^s||^2 - ||psi_j^s||^2 |, and per-workgroup partial
 // sums of the penalties and of the regularisers C3 (|u|^2) and C4 (control
-// variations) for the final reduction (deterministic order) in k_total.
-template <typename T> __global__ __launch_bounds__(256) void k_pen(SweepArgs<T> a) {
+// variations) and of the drift for the final reduction (fixed order) in
+// k_total.  The last workgroup of the launch is the fidelity block.
+template <typename T> __global__ __launch_bounds__(256) void k_cost(SweepArgs<T> a) {
+  if (blockIdx.x == gridDim.x - 1) {  // block-uniform
+    lam_block(a);
+    return;
+  }
   __shared__ double red[3][4];
   __shared__ double dred[4];
   const int dp = a.dp, S = a.S, N = a.N;
   const long set = 2L * S * dp;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double cpen = 0.0, dmax = 0.0;
-  for (long j = (long)blockIdx.x * 4 + w; j < N; j += (long)gridDim.x * 4) {
+  for (long j = (long)blockIdx.x * 4 + w; j < N; j += (long)a.npart * 4) {
     double csum = 0.0;
     for (int s = 0; s < S; ++s) {
       const T *p0r = a.psi_buf + j * set + (long)s * dp, *p0i = p0r + (long)S * dp;
@@ -410,7 +424,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_pen(SweepArgs<T> 
   }
   double camp = 0.0, cvar = 0.0;
   const long MN = (long)a.M * N;
-  for (long e = blockIdx.x * 256L + threadIdx.x; e < MN; e += (long)gridDim.x * 256) {
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < MN; e += (long)a.npart * 256) {
     const double x = a.u[e];
     camp += x * x;
     if (e % N >= 1) {
@@ -430,21 +444,15 @@ template <typename T> __global__ __launch_bounds__(256) void k_pen(SweepArgs<T> 
   __syncthreads();
   if (threadIdx.x < 3) {
     const int q = threadIdx.x;
-    a.part[q * gridDim.x + blockIdx.x] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
+    a.part[q * a.npart + blockIdx.x] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
   }
-  if (threadIdx.x == 0) {
-    const double m = fmax(fmax(dred[0], dred[1]), fmax(dred[2], dred[3]));
-    atomicMax(a.drift_bits, (unsigned long long)__double_as_longlong(m));
-  }
+  if (threadIdx.x == 0)
+    a.part[3 * a.npart + blockIdx.x] = fmax(fmax(dred[0], dred[1]), fmax(dred[2], dred[3]));
 }
 
 
-template <typename T> hipError_t launch_pen(const SweepArgs<T> &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_pen<T>, dim3(a.npart), dim3(256), 0, st, a);
-  return hipGetLastError();
-}
-template <typename T> hipError_t launch_lam(const SweepArgs<T> &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_lam<T>, dim3(1), dim3(256), 0, st, a);
+template <typename T> hipError_t launch_cost(const SweepArgs<T> &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_cost<T>, dim3(a.npart + 1), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 template <typename T> hipError_t launch_total(const SweepArgs<T> &a, hipStream_t st) {
@@ -874,8 +882,7 @@ template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStre
   template hipError_t launch_wide_sweep<T>(int, const SweepArgs<T> &, hipStream_t);   \
   template hipError_t launch_fwd_blocks<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_fwd_replay<T>(const SweepArgs<T> &, hipStream_t);       \
-  template hipError_t launch_pen<T>(const SweepArgs<T> &, hipStream_t);              \
-  template hipError_t launch_lam<T>(const SweepArgs<T> &, hipStream_t);              \
+  template hipError_t launch_cost<T>(const SweepArgs<T> &, hipStream_t);             \
   template hipError_t launch_total<T>(const SweepArgs<T> &, hipStream_t);            \
   template hipError_t launch_bwd_blocks<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_bwd_pairs<T>(const SweepArgs<T> &, hipStream_t);

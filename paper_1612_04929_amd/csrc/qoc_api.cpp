@@ -104,7 +104,7 @@ struct qoc_handle {
   void *psi_buf = nullptr, *lam_buf = nullptr;                // N+1, N sets
   unsigned long long *bits = nullptr;  // [theta, drift, norm ticket, -, norm accumulator]
   double *zinfo = nullptr;    // 3 + 2S
-  double *part = nullptr;     // 3 x npart
+  double *part = nullptr;     // 4 x npart
   int *pn_dev = nullptr;      // device-side (p, n, status)
   double *sc_dev = nullptr;   // device-side (dt / 2^n, theta)
   int npart = 1;
@@ -338,7 +338,7 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   HIP_TRY(hipMemset(h->bits, 0, 8 * sizeof(unsigned long long)));  // ticket, accumulator start at zero
   ALLOC(h->zinfo, (size_t)(3 + 2 * S) * sizeof(double));
   h->npart = std::max(1, std::min(1024, (N + 3) / 4));
-  ALLOC(h->part, (size_t)3 * h->npart * sizeof(double));
+  ALLOC(h->part, (size_t)4 * h->npart * sizeof(double));
   ALLOC(h->pn_dev, 4 * sizeof(int));
   ALLOC(h->sc_dev, 2 * sizeof(double));
 #undef ALLOC
@@ -671,15 +671,14 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     PhaseTimer tm(h, QOC_PHASE_FWD_REPLAY, st);
     HIP_TRY(sweep(1));
   }
-  // penalties, fidelity / lambda_N, total cost (all on st: a side stream
-  // for the penalties measured slower here, its events costing more than
-  // the overlap gains)
-  HIP_TRY(qoc::launch_pen<T>(sw, st));
+  // penalties beside fidelity / lambda_N in one launch, then the total cost
+  // and drift (a side stream for the penalties measured slower here, its
+  // events costing more than the overlap gained)
   {
     PhaseTimer tm(h, QOC_PHASE_COST, st);
-    HIP_TRY(qoc::launch_lam<T>(sw, st));
+    HIP_TRY(qoc::launch_cost<T>(sw, st));
+    HIP_TRY(qoc::launch_total<T>(sw, st));
   }
-  HIP_TRY(qoc::launch_total<T>(sw, st));
   if (!want_grad) return QOC_OK;
   {
     PhaseTimer tm(h, QOC_PHASE_BWD_BLOCKS, st);

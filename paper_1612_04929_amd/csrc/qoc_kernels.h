@@ -95,8 +95,8 @@ template <typename T> struct SweepArgs {
   int fid_mode;
   double *out;          // [C, C_fid, c_1..c_N]
   double *zinfo;        // [Re z, Im z, F, then Re/Im overlap of each column]
-  double *part;         // 3 x npart partial sums (penalties, |u|^2, variations)
-  int npart;            // workgroups of k_pen
+  double *part;         // 4 x npart partials (penalties, |u|^2, variations, drift max)
+  int npart;            // penalty workgroups of k_cost
 };
 template <typename T> hipError_t launch_fwd_blocks(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStream_t st);
@@ -113,11 +113,11 @@ template <typename T> hipError_t launch_wave_sweep(int which, const SweepArgs<T>
 // workgroups.  which: 0 = F2, 1 = F3, 2 = B2, 3 = B3.
 template <typename T> bool wide_sweep_ok(int dp, int S);
 template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T> &a, hipStream_t st);
-// Per-step penalties c_j (FP64) and the norm drift, parallel over (j, s).
-template <typename T> hipError_t launch_pen(const SweepArgs<T> &a, hipStream_t st);
-// Fidelity, C_fid and lambda_N (needs the final states only).
-template <typename T> hipError_t launch_lam(const SweepArgs<T> &a, hipStream_t st);
-// Total cost (needs launch_pen's partial sums and launch_lam's fidelity).
+// One launch: per-step penalties c_j (FP64) and norm drift partials,
+// parallel over steps, beside the fidelity, C_fid and lambda_N (one
+// workgroup; needs the final states only).  npart + 1 workgroups.
+template <typename T> hipError_t launch_cost(const SweepArgs<T> &a, hipStream_t st);
+// Total cost and norm drift from launch_cost's partials and fidelity.
 template <typename T> hipError_t launch_total(const SweepArgs<T> &a, hipStream_t st);
 
 // Exact per-step derivative of the Taylor + squaring evaluation, contracted
