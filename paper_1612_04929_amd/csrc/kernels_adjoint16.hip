@@ -2,124 +2,20 @@
 // for padded d = 16, where every matrix of the recurrence is one 16x16
 // MFMA tile.  One wavefront handles one time step with all cotangent
 // factors, the Horner chain V_k and the running At_k held in registers in
-// MFMA result layout; a two-tile LDS scratch per wavefront converts a
-// result tile into operand fragments of the next product.  Xbar is
-// accumulated while the At chain runs (Xbar += At_k V_{k+1}^H), so no
-// intermediate leaves the compute unit.
+// MFMA result layout.  Xbar is accumulated while the At chain runs
+// (Xbar += At_k V_{k+1}^H), so no intermediate leaves the compute unit.
+//
+// With the operand order of qoc_tile16.h the squaring levels, the V chain
+// and the At chain feed results straight back in as right-hand operands;
+// only the Xbar products (At on the left, V^H on the right) go through the
+// two-tile LDS scratch of the wavefront.
 #include "qoc_device.h"
 #include "qoc_kernels.h"
+#include "qoc_tile16.h"
 
 namespace qoc {
 
 constexpr int A16_PMAX = 16;  // largest Taylor order handled (p <= 16)
-constexpr int A16_LD = 17;    // padded LDS row stride of a staged tile
-
-template <typename T> struct CTile {  // 16x16 complex tile, MFMA result layout
-  v4<T> r, i;
-};
-
-template <typename T> __device__ __forceinline__ CTile<T> ctile_zero() {
-  CTile<T> z;
-  z.r = vzero<T>();
-  z.i = vzero<T>();
-  return z;
-}
-
-__device__ __forceinline__ void wave_lds_sync() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-  __builtin_amdgcn_wave_barrier();
-  asm volatile("" ::: "memory");
-}
-
-// fragments: lane (q = l%16, kk = l/16), entry t = k-step (k = 4t + kk)
-template <typename T> struct Frag {
-  T r[4], i[4];
-};
-
-template <typename T>
-__device__ __forceinline__ void stage(T *tr, T *ti, const CTile<T> &c) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int o = acc_row<T>(lane, v) * A16_LD + (lane & 15);
-    tr[o] = c.r[v];
-    ti[o] = c.i[v];
-  }
-}
-// A-operand of M: A[q][k]
-template <typename T> __device__ __forceinline__ Frag<T> fragA(const T *tr, const T *ti) {
-  const int lane = threadIdx.x & 63, q = lane & 15, kk = lane >> 4;
-  Frag<T> f;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    f.r[t] = tr[q * A16_LD + 4 * t + kk];
-    f.i[t] = ti[q * A16_LD + 4 * t + kk];
-  }
-  return f;
-}
-// B-operand of M: B[k][q]
-template <typename T> __device__ __forceinline__ Frag<T> fragB(const T *tr, const T *ti) {
-  const int lane = threadIdx.x & 63, q = lane & 15, kk = lane >> 4;
-  Frag<T> f;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    f.r[t] = tr[(4 * t + kk) * A16_LD + q];
-    f.i[t] = ti[(4 * t + kk) * A16_LD + q];
-  }
-  return f;
-}
-// B-operand of M^H: conj(M[q][k])
-template <typename T> __device__ __forceinline__ Frag<T> fragBH(const T *tr, const T *ti) {
-  const int lane = threadIdx.x & 63, q = lane & 15, kk = lane >> 4;
-  Frag<T> f;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    f.r[t] = tr[q * A16_LD + 4 * t + kk];
-    f.i[t] = -ti[q * A16_LD + 4 * t + kk];
-  }
-  return f;
-}
-// A-operand of a global 16x16 matrix (OPH = conjugate transpose)
-template <typename T, bool OPH>
-__device__ __forceinline__ Frag<T> fragA_global(const T *__restrict__ g) {
-  const int lane = threadIdx.x & 63, q = lane & 15, kk = lane >> 4;
-  Frag<T> f;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int k = 4 * t + kk;
-    if (!OPH) {
-      f.r[t] = g[q * 16 + k];
-      f.i[t] = g[256 + q * 16 + k];
-    } else {
-      f.r[t] = g[k * 16 + q];
-      f.i[t] = -g[256 + k * 16 + q];
-    }
-  }
-  return f;
-}
-
-template <typename T>
-__device__ __forceinline__ void cmma(const Frag<T> &a, const Frag<T> &b, CTile<T> &c) {
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    c.r = mfma4(a.r[t], b.r[t], c.r);
-    c.r = mfma4(-a.i[t], b.i[t], c.r);
-    c.i = mfma4(a.r[t], b.i[t], c.i);
-    c.i = mfma4(a.i[t], b.r[t], c.i);
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ CTile<T> axpy(T alpha, const CTile<T> &x, const CTile<T> &y) {
-  CTile<T> o;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    o.r[v] = alpha * x.r[v] + y.r[v];
-    o.i[v] = alpha * x.i[v] + y.i[v];
-  }
-  return o;
-}
 
 template <typename T> __global__ __launch_bounds__(256) void k_adjoint16(AdjointArgs<T> a) {
   __shared__ T lds[4][2][2][16 * A16_LD];
@@ -144,19 +40,23 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint16(Adjoint
       B.i[v] = on ? psi[S * 16 + cs * 16 + row] : (T)0;
     }
     int r = S;
+    // operand fragments of the next level's D (then of X), loaded one level
+    // ahead so the global loads overlap the current level's products
+    auto level_ptr = [&](int lv) -> const T * {
+      const long slot = a.pn ? (long)(n - lv) : (long)lv;
+      return a.Dlev + (slot * N + j) * mat;
+    };
+    const T *Xg = a.X + j * mat;
+    Frag<T> fD = fragA_global<T, false>(n > 0 ? level_ptr(n - 1) : Xg);
+    Frag<T> fDh = fragA_global<T, true>(n > 0 ? level_ptr(n - 1) : Xg);
     // ---- squaring levels: A' = [A, U^H A], B' = [U B, B]
     for (int lv = n - 1; lv >= 0; --lv) {
-      const long slot = a.pn ? (long)(n - lv) : (long)lv;
-      const T *Dg = a.Dlev + (slot * N + j) * mat;
-      const Frag<T> fD = fragA_global<T, false>(Dg);
-      const Frag<T> fDh = fragA_global<T, true>(Dg);
-      stage(t0r, t0i, A);
-      stage(t1r, t1i, B);
-      wave_lds_sync();
-      const Frag<T> bA = fragB(t0r, t0i), bB = fragB(t1r, t1i);
+      const T *nxt = lv > 0 ? level_ptr(lv - 1) : Xg;
+      const Frag<T> nD = fragA_global<T, false>(nxt);
+      const Frag<T> nDh = fragA_global<T, true>(nxt);
       CTile<T> T1 = A, T2 = B;  // T1 = A + D^H A, T2 = B + D B
-      cmma(fDh, bA, T1);
-      cmma(fD, bB, T2);
+      cmma(fDh, asB(A), T1);
+      cmma(fD, asB(B), T2);
       if (2 * r <= 16) {
         CTile<T> An, Bn;
         const int src = lane >= r ? lane - r : lane;
@@ -197,23 +97,20 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint16(Adjoint
         r = 16;
       }
       wave_lds_sync();
+      fD = nD;
+      fDh = nDh;
     }
-    // ---- Horner reverse
-    const T *Xg = a.X + j * mat;
-    const Frag<T> fX = fragA_global<T, false>(Xg);
-    const Frag<T> fXh = fragA_global<T, true>(Xg);
+    // ---- Horner reverse (fD, fDh now hold X)
+    const Frag<T> fX = fD;
+    const Frag<T> fXh = fDh;
     CTile<T> V[A16_PMAX];  // V[k-2] = V_k, k = 2 .. p+1
 #pragma unroll
     for (int q = 0; q < A16_PMAX; ++q) V[q] = (q == p - 1) ? B : ctile_zero<T>();
 #pragma unroll
     for (int k = A16_PMAX; k >= 2; --k) {
       if (k <= p) {  // V_k = B + (1/k) X V_{k+1}
-        stage(t0r, t0i, V[k - 1]);
-        wave_lds_sync();
-        const Frag<T> b = fragB(t0r, t0i);
-        wave_lds_sync();
         CTile<T> acc = ctile_zero<T>();
-        cmma(fX, b, acc);
+        cmma(fX, asB(V[k - 1]), acc);
         V[k - 2] = axpy((T)1 / (T)k, acc, B);
       }
     }
@@ -224,34 +121,45 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint16(Adjoint
         stage(t0r, t0i, At);
         stage(t1r, t1i, V[k - 1]);  // V_{k+1}
         wave_lds_sync();
-        const Frag<T> aAt = fragA(t0r, t0i), bAt = fragB(t0r, t0i);
+        const Frag<T> aAt = fragA(t0r, t0i);
         const Frag<T> bVh = fragBH(t1r, t1i);
         wave_lds_sync();
         cmma(aAt, bVh, Xb);  // Xbar += At_k V_{k+1}^H
         if (k < p) {         // At_{k+1} = X^H At_k / (k+1)
           CTile<T> acc = ctile_zero<T>();
-          cmma(fXh, bAt, acc);
+          cmma(fXh, asB(At), acc);
           At = axpy((T)1 / (T)(k + 1), acc, ctile_zero<T>());
         }
       }
     }
     // ---- dC/du_{k,j} = 2 (dt/2^n) Im tr(Xbar^H H_k) + regulariser terms
+    // four controls at a time: their loads and wavefront sums overlap
     const double two_s = 2.0 * s_scale;
-    for (int k = 0; k < M; ++k) {
-      const T *H = a.Hf + (long)(1 + k) * mat;
-      double part = 0.0;
+    for (int k0 = 0; k0 < M; k0 += 4) {
+      double part[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int o = acc_row<T>(lane, v) * 16 + col;
-        part += (double)Xb.r[v] * (double)H[256 + o] - (double)Xb.i[v] * (double)H[o];
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + q < M ? k0 + q : M - 1;
+        const T *H = a.Hf + (long)(1 + k) * mat;
+        part[q] = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int o = acc_row<T>(lane, v) * 16 + col;
+          part[q] += (double)Xb.r[v] * (double)H[256 + o] - (double)Xb.i[v] * (double)H[o];
+        }
       }
-      part = wave_sum(part);
-      if (lane == 0) {
-        const double *uk = a.u + (long)k * N;
-        double reg = 2.0 * a.alpha_amp * uk[j];
-        if (j >= 1) reg += 2.0 * a.alpha_var * (uk[j] - uk[j - 1]);
-        if (j <= N - 2) reg -= 2.0 * a.alpha_var * (uk[j + 1] - uk[j]);
-        a.grad[(long)k * N + j] = two_s * part + reg;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) part[q] = wave_sum(part[q]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + q;
+        if (lane == 0 && k < M) {
+          const double *uk = a.u + (long)k * N;
+          double reg = 2.0 * a.alpha_amp * uk[j];
+          if (j >= 1) reg += 2.0 * a.alpha_var * (uk[j] - uk[j - 1]);
+          if (j <= N - 2) reg -= 2.0 * a.alpha_var * (uk[j + 1] - uk[j]);
+          a.grad[(long)k * N + j] = two_s * part[q] + reg;
+        }
       }
     }
   }

@@ -135,16 +135,19 @@ template <typename T> struct ThinBatch {
 
 // Out_j = alpha op(A_j) B_j + addS Add_j over 64-row x TN-column panels,
 // for one or two independent products (halves) and every step j.
+// Workgroups are numbered step-major (step, half, tile), so both halves of
+// a step run on one XCD at about the same time and the second reads the
+// step's matrix from L2.
 template <typename T, int TN> __global__ __launch_bounds__(256) void k_thin_batch(ThinBatch<T> a, long padded) {
   __shared__ BigLds<T> L;
   const int rp = (a.dp + 63) / 64, cp = a.W / TN;
-  const long per_step = (long)rp * cp, per_half = per_step * a.N;
+  const long per_step = (long)rp * cp, per_j = per_step * a.nhalf;
   const long logical = xcd_logical_block(blockIdx.x, padded);
-  if (logical >= per_half * a.nhalf) return;  // block-uniform
-  const int h = (int)(logical / per_half);
-  const long rem = logical - h * per_half;
-  const long j = rem / per_step;
-  const int t = (int)(rem - j * per_step);
+  if (logical >= per_j * a.N) return;  // block-uniform
+  const long j = logical / per_j;
+  const long rem = logical - j * per_j;
+  const int h = (int)(rem / per_step);
+  const int t = (int)(rem - h * per_step);
   const int r0 = (t / cp) * 64, c0 = (t % cp) * TN;
   v4<T> cr[TN / 16], ci[TN / 16];
 #pragma unroll
@@ -184,13 +187,13 @@ template <typename T, bool BF3>
 __global__ __launch_bounds__(256) void k_thin64(ThinBatch<T> a, long padded) {
   __shared__ __align__(16) char lds[TILE64_LDS_BYTES];
   const int rp = (a.dp + 63) / 64, cp = (a.W + 63) / 64;
-  const long per_step = (long)rp * cp, per_half = per_step * a.N;
+  const long per_step = (long)rp * cp, per_j = per_step * a.nhalf;
   const long logical = xcd_logical_block(blockIdx.x, padded);
-  if (logical >= per_half * a.nhalf) return;  // block-uniform
-  const int h = (int)(logical / per_half);
-  const long rem = logical - h * per_half;
-  const long j = rem / per_step;
-  const int t = (int)(rem - j * per_step);
+  if (logical >= per_j * a.N) return;  // block-uniform (step-major numbering)
+  const long j = logical / per_j;
+  const long rem = logical - j * per_j;
+  const int h = (int)(rem / per_step);
+  const int t = (int)(rem - h * per_step);
   const int r0 = (t / cp) * 64, c0 = (t % cp) * 64;
   const TOp<T> A = a.A[h].top(j, a.dp);
   const TOp<T> B = a.B[h].top(j, a.W);

@@ -341,6 +341,9 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   ALLOC(h->part, (size_t)4 * h->npart * sizeof(double));
   ALLOC(h->pn_dev, 4 * sizeof(int));
   ALLOC(h->sc_dev, 2 * sizeof(double));
+  // no pair yet: the first speculative pass of the padded-d-16 kernel is redone
+  HIP_TRY(hipMemset(h->pn_dev, 0, 4 * sizeof(int)));
+  HIP_TRY(hipMemset(h->sc_dev, 0, 2 * sizeof(double)));
 #undef ALLOC
   if (hipHostMalloc((void **)&h->h_u, (size_t)std::max(1, M * N) * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void **)&h->h_out, (size_t)(2 + N + 2 * S * d) * sizeof(double)) !=
@@ -524,13 +527,23 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
         s = ensure_adjoint<T>(h, p_cap, dp, false);
       if (s) return s;
     }
-    {
-      PhaseTimer tm(h, QOC_PHASE_NORM, st);
-      qoc::SelectArgs sel{h->pn_dev, h->sc_dev, (unsigned *)(h->bits + 2), h->tol, n_cap, p_cap,
-                          h->fixed_p, h->fixed_n, h->bits + 4};
-      HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, sel, st));
-    }
-    {
+    const qoc::SelectArgs sel{h->pn_dev, h->sc_dev, (unsigned *)(h->bits + 2), h->tol, n_cap,
+                              p_cap, h->fixed_p, h->fixed_n, h->bits + 4};
+    // padded d 16: the norms ride along the exponential pass (its workgroup
+    // maxima kept in `part`, free until the cost kernel), the (p, n) choice
+    // and any recompute along the block products
+    const qoc::Norm16 nm{h->H64, h->d, h->dt, h->bits, (unsigned long long *)h->part, sel};
+    const qoc::Pick16<T> pick{nm, (int)qoc::expm16_blocks<T>(N), (const T *)h->Hf, u_dev, M, X,
+                              (T *)h->Dlev, Dh_small};
+    if (dp == 16) {
+      PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
+      HIP_TRY(qoc::launch_expm16<T>((const T *)h->Hf, u_dev, M, N, X, (T *)h->Dlev, Dh_small, nm,
+                                    st));
+    } else {
+      {
+        PhaseTimer tm(h, QOC_PHASE_NORM, st);
+        HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, sel, st));
+      }
       PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
       HIP_TRY(qoc::launch_expm_small<T>((const T *)h->Hf, u_dev, dp, M, N, h->pn_dev, h->sc_dev,
                                         X, (T *)h->Dlev, Dh_small, st));
@@ -538,7 +551,8 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     D = (const T *)h->Dlev;  // slot 0 = D^(n)
     {
       PhaseTimer tm(h, QOC_PHASE_BLOCKPROD, st);
-      HIP_TRY(qoc::launch_blockprod_small<T>(D, dp, N, h->L, h->nb, Qa, (T *)h->Eh, st));
+      HIP_TRY(qoc::launch_blockprod_small<T>(D, dp, N, h->L, h->nb, Qa, (T *)h->Eh,
+                                             dp == 16 ? &pick : nullptr, st));
     }
     E = Qa;
   } else {

@@ -67,10 +67,36 @@ template <typename T> bool small_expm_ok(int dp);
 template <typename T>
 hipError_t launch_expm_small(const T *Hf, const double *u, int dp, int M, int N, const int *pn,
                              const double *sc, T *X, T *Dlev, T *Dh, hipStream_t st);
+// Padded d 16: the step exponentials with their FP64 norms fused in,
+// computed with the pair held in sel.pn (the previous call's, recorded in
+// pn[3]); each of the expm16_blocks(N) workgroups stores its largest
+// ||dt H_j||_1 bit pattern in part.  The block-product kernel then chooses
+// (p, n) (Pick16) and recomputes where the pair changed.
+struct Norm16 {
+  const double *H64;  // FP64 Hamiltonians, (M + 1) x d x d interleaved complex
+  int d;
+  double dt;
+  unsigned long long *theta_bits;  // [0] receives theta_max
+  unsigned long long *part;        // one word per workgroup of the exponential pass
+  SelectArgs sel;
+};
+template <typename T> unsigned expm16_blocks(int N);
+template <typename T>
+hipError_t launch_expm16(const T *Hf, const double *u, int M, int N, T *X, T *Dlev, T *Dh,
+                         const Norm16 &nm, hipStream_t st);
+// Pair choice and recompute inputs for the padded-d-16 block products.
+template <typename T> struct Pick16 {
+  Norm16 nm;  // nm.part null: no choice to make
+  int nparts;
+  const T *Hf;
+  const double *u;
+  int M;
+  T *X, *Dlev, *Dh;
+};
 // Dh / Eh: optional conjugate transposes of the final D_j / of E_b (null: not written)
 template <typename T>
 hipError_t launch_blockprod_small(const T *D, int dp, int N, int L, int nb, T *E, T *Eh,
-                                  hipStream_t st);
+                                  const Pick16<T> *pick, hipStream_t st);
 
 // Blocked two-level sweep.  State sets are [2][S][dp] (re plane of S
 // states, then im plane).  Block b covers steps [b*L, min(N, (b+1)*L)).
