@@ -38,14 +38,12 @@ HBM_PEAK = 8.0e12
 # counters on a 256 MiB device copy (x2.0 and x1.0); the table, commands
 # and calibration are in profiles/hbm_traffic_pmc.md.  FP32 chains.
 TRAFFIC = {
-    ("c2_transmon_cnot", "bwd_blocks"): ("k_wB2", 177385, 31744),
-    ("c2_transmon_cnot", "fwd_blocks"): ("k_wF2", 138760, 32768),
-    ("c2_transmon_cnot", "fwd_replay"): ("k_wF3", 4964095, 1056768),
-    ("c2_transmon_cnot", "bwd_pairs"): ("k_wB3", 5136130, 1024000),
-    ("c2_transmon_cnot", "adjoint"): ("k_adjoint16", 15218155, 64000),
-    ("c2_transmon_cnot", "blockprod"): ("k_blockprod_small", 4186595, 129024),
-    ("c2_transmon_cnot", "taylor"): ("k_expm_small", 405554, 16384000),
-    ("c4_spin_chain", "taylor"): ("k_stage64", 6357023639, 3036795838),
+    ("c2_transmon_cnot", "adjoint"): ("k_adjoint16", 15207329, 64000),
+    ("c2_transmon_cnot", "taylor"): ("k_expm16", 618904, 18857632),
+    ("c2_transmon_cnot", "bwd_blocks"): ("k_wB2", 643476, 31744),
+    ("c2_transmon_cnot", "fwd_replay"): ("k_wF3", 35035399, 1056768),
+    ("c3_transmon_cavity", "taylor"): ("k_stage64", 1678776510, 944084993),
+    ("c4_spin_chain", "taylor"): ("k_stage64", 6355262327, 3037389901),
 }
 
 
