@@ -2,6 +2,8 @@
 FP64 oracle (``oracle/``) on seeded inputs from ``workloads``.
 
 Run from the repository root:  python tests/golden/make_golden.py
+(the single-qubit fixture) and  python tests/golden/make_golden.py --full c3 c4
+(full-size transmon-cavity and spin-chain workloads; minutes of CPU time).
 """
 import json
 import os
@@ -34,5 +36,35 @@ def main():
     print("wrote c1_oracle.json")
 
 
+def full(name, samples=256, top=16):
+    """Full-size workload: cost, fidelity, theta_max, the gradient's l2 norm
+    and a seeded sample of gradient entries (plus the largest ones), small
+    enough to store; the GPU tests compare the full-size run against them."""
+    p = workloads.make_config(name)
+    out = oracle.cost_grad(p)
+    g = np.asarray(out["grad"], dtype=np.float64).ravel()
+    rng = np.random.default_rng(2024)
+    idx = set(rng.choice(g.size, size=min(samples, g.size), replace=False).tolist())
+    idx |= set(np.argsort(-np.abs(g))[:top].tolist())
+    idx = sorted(int(i) for i in idx)
+    c = np.asarray(out["c"], dtype=np.float64)
+    rec = {
+        "source": f"oracle.cost_grad on workloads.make_config({name!r}) ({p.name})",
+        "d": p.d, "M": p.M, "N": p.N, "S": p.S,
+        "C": out["C"], "C_fid": out["C_fid"], "F": out["F"], "theta_max": out["theta_max"],
+        "grad_l2": float(np.linalg.norm(g)),
+        "grad_index": idx, "grad_sample": [float(g[i]) for i in idx],
+        "penalty_sum": float(c.sum()),
+    }
+    fname = f"{name}_full_oracle.json"
+    with open(os.path.join(HERE, fname), "w") as f:
+        json.dump(rec, f, indent=1)
+    print("wrote", fname)
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "--full":
+        for name in sys.argv[2:] or ["c3", "c4"]:
+            full(name)
+    else:
+        main()
