@@ -18,6 +18,13 @@ namespace qoc {
 constexpr int A16_PMAX = 16;  // largest Taylor order handled (p <= 16)
 
 template <typename T> __global__ __launch_bounds__(256) void k_adjoint16(AdjointArgs<T> a) {
+  // the last workgroup, when asked, reduces the call's total cost beside
+  // the steps (its inputs were complete before this launch)
+  const unsigned step_blocks = gridDim.x - (a.with_total ? 1u : 0u);
+  if (a.with_total && blockIdx.x == step_blocks) {  // block-uniform
+    cost_total_block(a.total);
+    return;
+  }
   __shared__ T lds[4][2][2][16 * A16_LD];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15;
   const int S = a.S, M = a.M, N = a.N;
@@ -25,7 +32,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint16(Adjoint
   const double s_scale = a.pn ? a.sc[0] : a.s_scale;
   T *t0r = lds[w][0][0], *t0i = lds[w][0][1], *t1r = lds[w][1][0], *t1i = lds[w][1][1];
   const long set = 2L * S * 16, mat = 512;
-  for (long j = (long)blockIdx.x * 4 + w; j < N; j += (long)gridDim.x * 4) {
+  for (long j = (long)blockIdx.x * 4 + w; j < N; j += (long)step_blocks * 4) {
     // ---- cotangent factors A = [lambda_{j+1}], B = [psi_j], zero columns >= S
     const T *lam = a.lam_buf + j * set, *psi = a.psi_buf + j * set;
     CTile<T> A, B;
@@ -168,7 +175,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint16(Adjoint
 template <typename T> bool adjoint16_ok(int dp, int p_max) { return dp == 16 && p_max <= A16_PMAX; }
 
 template <typename T> hipError_t launch_adjoint16(const AdjointArgs<T> &a, hipStream_t st) {
-  const long blocks = std::min<long>((a.N + 3) / 4, 2048);
+  const long blocks = std::min<long>((a.N + 3) / 4, 2048) + (a.with_total ? 1 : 0);
   hipLaunchKernelGGL(k_adjoint16<T>, dim3((unsigned)blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }

@@ -21,6 +21,7 @@
 
 #include "qoc_device.h"
 #include "qoc_kernels.h"
+#include "qoc_total.h"
 
 namespace qoc {
 
@@ -170,17 +171,6 @@ __device__ __forceinline__ void mv_plus_adj(const T *__restrict__ Dr, const T *_
       }
     }
   }
-}
-
-// Block-wide FP64 sum (256 threads).
-__device__ __forceinline__ double block_sum(double v, double *red) {
-  v = wave_sum(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
-  return s;
 }
 
 template <typename T> __device__ __forceinline__ const T *set_re(const T *base, int S, int dp, int s) {
@@ -359,27 +349,7 @@ template <typename T> __device__ void lam_block(const SweepArgs<T> &a) {
 }
 
 template <typename T> __global__ __launch_bounds__(256) void k_total(SweepArgs<T> a) {
-  __shared__ double red[4];
-  __shared__ double dred[4];
-  double cpen = 0.0, camp = 0.0, cvar = 0.0, dmax = 0.0;
-  for (int q = threadIdx.x; q < a.npart; q += blockDim.x) {
-    cpen += a.part[q];
-    camp += a.part[a.npart + q];
-    cvar += a.part[2 * a.npart + q];
-    dmax = fmax(dmax, a.part[3 * a.npart + q]);
-  }
-  cpen = block_sum(cpen, red);
-  camp = block_sum(camp, red);
-  cvar = block_sum(cvar, red);
-  dmax = wave_max(dmax);
-  if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = dmax;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double Cfid = 1.0 - a.zinfo[2];
-    a.out[0] = a.alpha_fid * Cfid + a.alpha_pen * cpen + a.alpha_amp * camp + a.alpha_var * cvar;
-    const double m = fmax(fmax(dred[0], dred[1]), fmax(dred[2], dred[3]));
-    *a.drift_bits = (unsigned long long)__double_as_longlong(m);
-  }
+  cost_total_block(total_args(a));
 }
 
 // ------------------------------------------------------------------ penalties

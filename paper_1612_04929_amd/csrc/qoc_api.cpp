@@ -688,10 +688,14 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   // penalties beside fidelity / lambda_N in one launch, then the total cost
   // and drift (a side stream for the penalties measured slower here, its
   // events costing more than the overlap gained)
+  // padded d 16 with a gradient: the total runs as an extra workgroup of
+  // the derivative kernel instead of a launch of its own
+  const bool total_in_adjoint = want_grad && M > 0 && small_path && !small_big_adjoint<T>(h) &&
+                                qoc::adjoint16_ok<T>(dp, kSmallPCap);
   {
     PhaseTimer tm(h, QOC_PHASE_COST, st);
     HIP_TRY(qoc::launch_cost<T>(sw, st));
-    HIP_TRY(qoc::launch_total<T>(sw, st));
+    if (!total_in_adjoint) HIP_TRY(qoc::launch_total<T>(sw, st));
   }
   if (!want_grad) return QOC_OK;
   {
@@ -724,6 +728,8 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     ad.part = h->adj_part;
     ad.xbar = Qa;  // the Taylor work space is free once the sweeps are done
     ad.bf3 = h->bf3;
+    ad.with_total = total_in_adjoint ? 1 : 0;
+    ad.total = qoc::total_args(sw);
     if (!big && qoc::adjoint16_ok<T>(dp, ad.p))
       HIP_TRY(qoc::launch_adjoint16<T>(ad, st));
     else if (big)

@@ -205,4 +205,16 @@ template <typename T> __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
+// Block-wide FP64 sum (blockDim.x a multiple of 64, at most 256 threads);
+// `red` holds one double per wavefront.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  return s;
+}
+
 }  // namespace qoc

@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "qoc_total.h"
+
 namespace qoc {
 
 // Batched complex product with a fused epilogue, one matrix per step:
@@ -124,6 +126,10 @@ template <typename T> struct SweepArgs {
   double *part;         // 4 x npart partials (penalties, |u|^2, variations, drift max)
   int npart;            // penalty workgroups of k_cost
 };
+template <typename T> __host__ __device__ inline TotalArgs total_args(const SweepArgs<T> &a) {
+  return TotalArgs{a.part, a.npart, a.zinfo, a.out, a.alpha_fid, a.alpha_pen,
+                   a.alpha_amp, a.alpha_var, a.drift_bits};
+}
 template <typename T> hipError_t launch_fwd_blocks(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_bwd_blocks(const SweepArgs<T> &a, hipStream_t st);
@@ -166,6 +172,8 @@ template <typename T> struct AdjointArgs {
   double *part;        // batched variant: N x slices x M partial sums
   T *xbar;             // batched variant: N x 2 dp^2 work space for Xbar_j
   int bf3;             // batched variant: bf16x3 split products
+  int with_total;      // padded d 16: one extra workgroup reduces the cost (total)
+  TotalArgs total;
 };
 template <typename T> long adjoint_scratch_elems(int dp, int p, int Rcap);
 // Time steps processed concurrently per workgroup (one per wave for small d).
