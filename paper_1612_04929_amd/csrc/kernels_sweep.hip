@@ -21,6 +21,7 @@
 
 #include "qoc_device.h"
 #include "qoc_kernels.h"
+#include "qoc_cost.h"
 #include "qoc_total.h"
 
 namespace qoc {
@@ -366,45 +367,9 @@ template <typename T> __global__ __launch_bounds__(256) void k_cost(SweepArgs<T>
   }
   __shared__ double red[3][4];
   __shared__ double dred[4];
-  const int dp = a.dp, S = a.S, N = a.N;
-  const long set = 2L * S * dp;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double cpen = 0.0, dmax = 0.0;
-  for (long j = (long)blockIdx.x * 4 + w; j < N; j += (long)a.npart * 4) {
-    double csum = 0.0;
-    for (int s = 0; s < S; ++s) {
-      const T *p0r = a.psi_buf + j * set + (long)s * dp, *p0i = p0r + (long)S * dp;
-      const T *p1r = a.psi_buf + (j + 1) * set + (long)s * dp, *p1i = p1r + (long)S * dp;
-      double n0 = 0.0, n1 = 0.0, pen = 0.0;
-      for (int m = lane; m < dp; m += 64) {
-        const double ar = p0r[m], ai = p0i[m], br = p1r[m], bi = p1i[m];
-        const double q1 = br * br + bi * bi;
-        n0 += ar * ar + ai * ai;
-        n1 += q1;
-        if (a.w64) pen += a.w64[m] * q1;
-      }
-      n0 = wave_sum(n0);
-      n1 = wave_sum(n1);
-      if (a.w64) csum += wave_sum(pen);
-      dmax = fmax(dmax, fabs(n1 - n0));
-    }
-    const double cj = csum / S;
-    if (lane == 0) a.out[2 + j] = cj;
-    cpen += cj;
-  }
-  double camp = 0.0, cvar = 0.0;
-  const long MN = (long)a.M * N;
-  for (long e = blockIdx.x * 256L + threadIdx.x; e < MN; e += (long)a.npart * 256) {
-    const double x = a.u[e];
-    camp += x * x;
-    if (e % N >= 1) {
-      const double dx = x - a.u[e - 1];
-      cvar += dx * dx;
-    }
-  }
-  camp = wave_sum(camp);
-  cvar = wave_sum(cvar);
-  dmax = wave_max(dmax);
+  double cpen, camp, cvar, dmax;
+  pen_wave(a, (long)blockIdx.x * 4 + w, (long)a.npart * 4, cpen, camp, cvar, dmax);
   if (lane == 0) {
     red[0][w] = cpen;  // identical on all lanes of the wave
     red[1][w] = camp;

@@ -20,6 +20,7 @@
 #include <type_traits>
 
 #include "qoc_device.h"
+#include "qoc_cost.h"
 #include "qoc_kernels.h"
 
 namespace qoc {
@@ -153,18 +154,20 @@ __device__ __forceinline__ void w_pipeline(const WLane &L, int count, DPtr dptr,
     if (i0 + q < count) step(i0 + q, r[q], ar[q], ai[q]);
 }
 
-// One wavefront: state s = blockIdx.y of a set [2][S][DP].
-#define W_SETUP                                                  \
+// One wavefront: state ws (blockIdx.y unless given) of a set [2][S][DP].
+#define W_SETUP_STATE(state)                                     \
   constexpr int KC = WaveGeo<DP>::KC;                            \
   __shared__ __align__(16) T xs[2][2 * DP];                      \
+  const int ws = (state);                                        \
   WLane L;                                                       \
   L.m = threadIdx.x / WaveGeo<DP>::KQ;                           \
   L.kq = threadIdx.x - L.m * WaveGeo<DP>::KQ;                    \
-  L.o = (int)blockIdx.y * DP + L.m;                              \
-  L.oi = (a.S + (int)blockIdx.y) * DP + L.m;                     \
+  L.o = ws * DP + L.m;                                           \
+  L.oi = (a.S + ws) * DP + L.m;                                  \
   const long set = 2L * a.S * DP, mat = 2L * DP * DP;            \
   int cur = 0;                                                   \
   (void)mat;
+#define W_SETUP W_SETUP_STATE((int)blockIdx.y)
 
 template <typename T> __device__ __forceinline__ void w_put(T *xs, int m, int dp, T vr, T vi) {
   xs[m] = vr;
@@ -249,10 +252,34 @@ template <typename T, int DP> __global__ __launch_bounds__(64) void k_wF3(SweepA
 }
 
 // ------------------------------------------------------------------ B2
+// With fuse_cost (a 1-D grid of S + npart wavefronts): wavefronts 0..S-1
+// form lambda_N of their state themselves (fidelity included) and run the
+// chain; the others run the penalty pass beside them, each storing its
+// partials for the total.  Otherwise (grid 1 x S) lambda_N is read.
 template <typename T, int DP> __global__ __launch_bounds__(64) void k_wB2(SweepArgs<T> a) {
-  W_SETUP
-  const T *lN = a.lam_ckpt + (long)a.nb * set;
-  T xr = lN[L.o], xi = lN[L.oi];
+  if (a.fuse_cost && (int)blockIdx.x >= a.S) {  // block-uniform: a penalty wavefront
+    const long wi = (long)blockIdx.x - a.S;
+    double cpen, camp, cvar, dmax;
+    pen_wave(a, wi, (long)a.npart, cpen, camp, cvar, dmax);
+    if (threadIdx.x == 0) {
+      a.part[wi] = cpen;
+      a.part[a.npart + wi] = camp;
+      a.part[2 * a.npart + wi] = cvar;
+      a.part[3 * a.npart + wi] = dmax;
+    }
+    return;
+  }
+  W_SETUP_STATE(a.fuse_cost ? (int)blockIdx.x : (int)blockIdx.y)
+  T *lN = a.lam_ckpt + (long)a.nb * set;
+  T xr, xi;
+  if (a.fuse_cost) {
+    lam_wave<T, DP>(a, ws, L.m, L.kq, xr, xi);
+    lN[L.o] = xr;  // lambda_N for the in-block costate pass
+    lN[L.oi] = xi;
+  } else {
+    xr = lN[L.o];
+    xi = lN[L.oi];
+  }
   w_put(xs[0], L.m, DP, xr, xi);
   wave_lds_fence();
   const bool has_mu = a.mu != nullptr;
@@ -314,7 +341,12 @@ template <typename T, int DP> hipError_t w_launch(int which, const SweepArgs<T> 
   switch (which) {
     case 0: hipLaunchKernelGGL((k_wF2<T, DP>), dim3(1, S), dim3(64), 0, st, a); break;
     case 1: hipLaunchKernelGGL((k_wF3<T, DP>), dim3(a.nb, S), dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_wB2<T, DP>), dim3(1, S), dim3(64), 0, st, a); break;
+    case 2:
+      if (a.fuse_cost)
+        hipLaunchKernelGGL((k_wB2<T, DP>), dim3(a.S + a.npart), dim3(64), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_wB2<T, DP>), dim3(1, S), dim3(64), 0, st, a);
+      break;
     default: hipLaunchKernelGGL((k_wB3<T, DP>), dim3(a.nb, S), dim3(64), 0, st, a); break;
   }
   return hipGetLastError();

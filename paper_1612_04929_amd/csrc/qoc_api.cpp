@@ -659,6 +659,13 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   // sweep kernels: one wavefront (S d_pad <= 64), one workgroup with a
   // prefetch ring (d_pad <= 64), or the generic streaming kernels
   const bool wave = qoc::wave_sweep_ok<T>(dp, S) && sw.Dh && sw.Eh;
+  // padded d 16 with a gradient: the total runs as an extra workgroup of
+  // the derivative kernel instead of a launch of its own, and (single-
+  // wavefront block sweep) lambda_N, the fidelity and the penalty pass run
+  // inside the backward block sweep's launch instead of the cost launch
+  const bool total_in_adjoint = want_grad && M > 0 && small_path && !small_big_adjoint<T>(h) &&
+                                qoc::adjoint16_ok<T>(dp, kSmallPCap);
+  sw.fuse_cost = (total_in_adjoint && wave && h->sweep_mode[2] != 3) ? 1 : 0;
   const bool small = !wave && qoc::small_sweep_ok<T>(dp, S);
   const bool wide_ok = !wave && !small && qoc::wide_sweep_ok<T>(dp, S);
   auto sweep = [&](int which) -> hipError_t {
@@ -688,11 +695,7 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   // penalties beside fidelity / lambda_N in one launch, then the total cost
   // and drift (a side stream for the penalties measured slower here, its
   // events costing more than the overlap gained)
-  // padded d 16 with a gradient: the total runs as an extra workgroup of
-  // the derivative kernel instead of a launch of its own
-  const bool total_in_adjoint = want_grad && M > 0 && small_path && !small_big_adjoint<T>(h) &&
-                                qoc::adjoint16_ok<T>(dp, kSmallPCap);
-  {
+  if (!sw.fuse_cost) {
     PhaseTimer tm(h, QOC_PHASE_COST, st);
     HIP_TRY(qoc::launch_cost<T>(sw, st));
     if (!total_in_adjoint) HIP_TRY(qoc::launch_total<T>(sw, st));

@@ -124,7 +124,8 @@ template <typename T> struct SweepArgs {
   double *out;          // [C, C_fid, c_1..c_N]
   double *zinfo;        // [Re z, Im z, F, then Re/Im overlap of each column]
   double *part;         // 4 x npart partials (penalties, |u|^2, variations, drift max)
-  int npart;            // penalty workgroups of k_cost
+  int npart;            // penalty workgroups of k_cost (wavefronts when fused)
+  int fuse_cost;        // single-wavefront B2 computes lambda_N and runs the penalties
 };
 template <typename T> __host__ __device__ inline TotalArgs total_args(const SweepArgs<T> &a) {
   return TotalArgs{a.part, a.npart, a.zinfo, a.out, a.alpha_fid, a.alpha_pen,
