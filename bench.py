@@ -288,23 +288,25 @@ def bench_batch(args):
     print(json.dumps(res), flush=True)
 
 
-def single_kernel_phases(info, sweep):
+def single_kernel_phases(info, sweep, precision="fp32"):
     """Phases of a cost + gradient call whose every timer brackets exactly
     one kernel launch: the norm (k_norm), the step assembly, each Taylor /
     Paterson-Stockmeyer / squaring stage, the sweeps that run as one kernel
     (not the per-step variant, which padded d >= 80 picks by default for
     the block sweeps), on the small path (padded d <= 32) the block-product
     tree, and at padded d 16 the per-step derivative kernel.  The cost phase
-    (three kernels) and the tiled adjoint (a dozen) are not single kernels."""
+    (two kernels) and the tiled adjoint (a dozen) are not single kernels."""
     dp = info["d_pad"]
     ph = {"norm", "assemble", "taylor"}
     if dp <= 32:
         ph.add("blockprod")
     if dp == 16:
         ph.add("adjoint")
+    chain = precision != "fp64" and 64 <= dp <= 128  # variant 4, the default from 80
     for name, v in zip(["fwd_blocks", "fwd_replay", "bwd_blocks", "bwd_pairs"], sweep):
         blocks = name in ("fwd_blocks", "bwd_blocks")
-        if dp >= 80 and (v == 2 or (v == 0 and (blocks or dp >= 256))):
+        auto_wide = v == 0 and not chain and (blocks or dp >= 256)
+        if dp >= 80 and (v == 2 or auto_wide):
             continue
         ph.add(name)
     return ph
@@ -409,7 +411,7 @@ def main():
                                avg_launch_ms=tms / calls)
     # the roofline kernel: the largest phase whose every timer brackets one
     # kernel launch (so its average is one kernel's average launch time)
-    single = single_kernel_phases(info, tuned["sweep"] if tuned else [0, 0, 0, 0])
+    single = single_kernel_phases(info, tuned["sweep"] if tuned else [0, 0, 0, 0], args.precision)
     dom = max((k for k in kernels if k in single), key=lambda k: kernels[k]["total_ms"])
     bound, units = algorithmic_work(prob, info, dom, kernels[dom]["launches"] * args.steps,
                                     args.precision, args.steps)

@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "libqoc.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["kernels_expm.hip", "kernels_norm.hip", "kernels_sweep.hip", "kernels_sweep_small.hip",
            "kernels_expm_small.hip",
-           "kernels_sweep_wave.hip",
+           "kernels_sweep_wave.hip", "kernels_sweep_chain.hip",
            "kernels_adjoint.hip", "kernels_adjoint16.hip",
            "kernels_adjoint_big.hip", "qoc_api.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

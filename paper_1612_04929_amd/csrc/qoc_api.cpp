@@ -79,7 +79,8 @@ struct qoc_handle {
   int d = 0, dp = 0, M = 0, N = 0, S = 0, prec = QOC_FP32, fid_mode = 0;
   int bf3 = 0;  // bf16x3 split products in the batched chains (padded d >= 64)
   int last_flags = 0;  // warning bits of the last call
-  int sweep_mode[4] = {0, 0, 0, 0};  // per sweep: 0 auto, 1 per-block, 2 per-step launches
+  int sweep_mode[4] = {0, 0, 0, 0};  // per sweep: 0 auto, 1 per-block, 2 per-step launches,
+                                     // 3 four-wavefront LDS (small d), 4 chain workgroup
   double dt = 0, a_fid = 0, a_amp = 0, a_var = 0, a_pen = 0, tol = 0, drift_warn = 0;
   bool has_pen = false;
   int fixed_p = 0, fixed_n = 0;
@@ -672,6 +673,9 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     const int mode = h->sweep_mode[which];
     if (wave && !(mode == 3 && qoc::small_sweep_ok<T>(dp, S)))
       return qoc::launch_wave_sweep<T>(which, sw, st);
+    // chain workgroups: by default for FP32 padded d 80 .. 128
+    if (qoc::chain_sweep_ok<T>(dp, S) && (mode == 4 || (mode == 0 && dp >= 80)))
+      return qoc::launch_chain_sweep<T>(which, sw, st);
     if (wave || small) return qoc::launch_small_sweep<T>(which, sw, st);
     // per-step launches: the block sweeps (F2, B2) from padded d 80, the
     // in-block passes (F3, B3) from 256, unless set per handle
@@ -825,8 +829,8 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n) {
 
 qoc_status qoc_set_sweep(qoc_handle *h, int which, int variant) {
   if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
-  if (which < -1 || which > 3 || variant < 0 || variant > 3)
-    return fail(QOC_ERR_ARG, "which must be -1..3 and variant 0..3");
+  if (which < -1 || which > 3 || variant < 0 || variant > 4)
+    return fail(QOC_ERR_ARG, "which must be -1..3 and variant 0..4");
   for (int w = 0; w < 4; ++w)
     if (which == -1 || which == w) h->sweep_mode[w] = variant;
   return QOC_OK;

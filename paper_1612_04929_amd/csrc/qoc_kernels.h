@@ -142,6 +142,10 @@ template <typename T> hipError_t launch_small_sweep(int which, const SweepArgs<T
 // One wavefront holding the whole state set (S * dp <= 64, dp = 16 or 32).
 template <typename T> bool wave_sweep_ok(int dp, int S);
 template <typename T> hipError_t launch_wave_sweep(int which, const SweepArgs<T> &a, hipStream_t st);
+// Padded d 64 .. 128 (FP32): one workgroup of 8 d_pad threads per chain
+// with a register prefetch ring of matrix slices.  which as below.
+template <typename T> bool chain_sweep_ok(int dp, int S);
+template <typename T> hipError_t launch_chain_sweep(int which, const SweepArgs<T> &a, hipStream_t st);
 // Large padded d (>= 80): the sweeps as per-step launches spread over many
 // workgroups.  which: 0 = F2, 1 = F3, 2 = B2, 3 = B3.
 template <typename T> bool wide_sweep_ok(int dp, int S);

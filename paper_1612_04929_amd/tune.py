@@ -8,7 +8,8 @@ cache reuse decide, so the interval and the kernel variant of each sweep
 are chosen by timing them on the problem itself: for every candidate L a
 handle is built, each sweep is timed in the applicable variants (padded
 d >= 80: per-block workgroups or per-step launches; smaller d: one
-wavefront or a four-wavefront LDS-staged workgroup) with the library's
+wavefront or a four-wavefront LDS-staged workgroup; FP32 padded d 64 ..
+128 also one 8 d_pad-thread chain workgroup per block) with the library's
 per-phase HIP events, and the L that minimises block products plus the
 best variant of each sweep wins.  Other phases do not depend on these
 choices.
@@ -45,7 +46,10 @@ def tune(prob, precision="fp32", intervals=None, reps=3, device=0, **kw):
     for L in intervals or candidate_intervals(prob.N):
         h = Problem(prob, precision=precision, checkpoint_every=L, device=device, **kw)
         times = {}
-        variants = (1, 2) if h.info()["d_pad"] >= 80 else (1, 3)
+        dp = h.info()["d_pad"]
+        variants = (1, 2) if dp >= 80 else (1, 3)
+        if precision != "fp64" and 64 <= dp <= 128:
+            variants += (4,)  # chain workgroups (FP32 chains)
         for variant in variants:
             h.set_sweep(-1, variant)
             h.cost_grad_device(u.data_ptr(), out.data_ptr(), grad.data_ptr(), st)

@@ -1,6 +1,6 @@
 """Full-size transmon-cavity (d=128, N=5000) and spin-chain (d=512, N=1000)
-workloads in the launch configuration bench.py times (checkpoint interval
-32 and the sweep variants its autotuner picks there), against stored FP64
+workloads in the launch configuration bench.py times (the checkpoint
+interval and sweep variants its autotuner picks there), against stored FP64
 oracle values (tests/golden/*_full_oracle.json, written by
 make_golden.py --full, which calls only the oracle): fidelity, cost,
 theta_max and penalty sum directly; the gradient through its l2 norm and a
@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 # (workload, checkpoint interval, sweep variants F2, F3, B2, B3)
-CASES = [("c3", 32, (2, 1, 2, 1)), ("c4", 32, (2, 2, 2, 2))]
+CASES = [("c3", 64, (4, 4, 4, 4)), ("c4", 32, (2, 2, 2, 2))]
 
 
 def say(*a):

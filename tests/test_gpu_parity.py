@@ -36,10 +36,12 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
-def compare(name, prob, precision="fp32", oracle_out=None, **kw):
+def compare(name, prob, precision="fp32", oracle_out=None, sweep=None, **kw):
     say(f"[parity] {name}: d={prob.d} M={prob.M} N={prob.N} S={prob.S} prec={precision}")
     ref = oracle_out if oracle_out is not None else oracle.cost_grad(prob)
     h = qoc.Problem(prob, precision=precision, **kw)
+    if sweep is not None:
+        h.set_sweep(-1, sweep)
     out = h.cost_grad(prob.u)
     fwd = h.forward(prob.u)
     h.close()
@@ -126,6 +128,18 @@ def test_wide_sweeps_checkpoint_intervals(L):
     rng = np.random.default_rng(17)
     p = workloads.random_problem(rng, d=90, M=2, N=50, S=3, dt=0.25, scale=1.5)
     out, ref, e = compare(f"wide_L{L}", p, checkpoint_every=L)
+    check(p, e)
+    assert e["L"] == L
+
+
+@pytest.mark.parametrize("d,S,N,L", [(64, 2, 45, 8), (70, 3, 50, 16), (120, 1, 70, 32),
+                                     (100, 2, 33, 1)])
+def test_chain_workgroup_sweeps(d, S, N, L):
+    # sweep variant 4 on padded d 64 / 80 / 128 / 112: every sweep as one
+    # 8 d_pad-thread workgroup per block, ragged last block, penalty
+    rng = np.random.default_rng(500 + d + N)
+    p = workloads.random_problem(rng, d=d, M=2, N=N, S=S, dt=0.2, scale=1.5)
+    out, ref, e = compare(f"chain_d{d}_S{S}_L{L}", p, checkpoint_every=L, sweep=4)
     check(p, e)
     assert e["L"] == L
 
