@@ -57,6 +57,47 @@ __device__ __forceinline__ void ld4(const double *p, double (&v)[4]) {
 // LDS: A and B chunks of 16 inner indices, k-major with row stride T64_LD
 // (the layout of wg_cgemm64), T64_LDS_ELEMS elements.
 
+// The chunk load split in two halves: global loads into registers, then the
+// LDS stores, so the next chunk can be in flight while one is multiplied.
+template <typename T, bool KC>
+__device__ __forceinline__ void load_op16(const TOp<T> &X, int i0, int k0, T (&vr)[4], T (&vi)[4],
+                                          bool &ok) {
+  const int t = threadIdx.x;
+  if (KC) {
+    const int i = t >> 2, kq = (t & 3) * 4;
+    ok = i0 + i < X.rows;
+    const long o = ok ? (long)(i0 + i) * X.ld + X.col(k0 + kq) : 0;
+    ld4(X.re + o, vr);
+    ld4(X.im + o, vi);
+  } else {
+    const int k = t >> 4, iq = (t & 15) * 4;
+    ok = i0 + iq < X.rows;
+    const long o = ok ? (long)X.col(k0 + k) * X.ld + i0 + iq : 0;
+    ld4(X.re + o, vr);
+    ld4(X.im + o, vi);
+  }
+}
+template <typename T, bool KC, bool CJ>
+__device__ __forceinline__ void store_op16(const T (&vr)[4], const T (&vi)[4], bool ok, T *Sr,
+                                           T *Si) {
+  const int t = threadIdx.x;
+  if (KC) {
+    const int i = t >> 2, kq = (t & 3) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Sr[(kq + q) * T64_LD + i] = ok ? vr[q] : (T)0;
+      Si[(kq + q) * T64_LD + i] = ok ? (CJ ? -vi[q] : vi[q]) : (T)0;
+    }
+  } else {
+    const int k = t >> 4, iq = (t & 15) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Sr[k * T64_LD + iq + q] = ok ? vr[q] : (T)0;
+      Si[k * T64_LD + iq + q] = ok ? (CJ ? -vi[q] : vi[q]) : (T)0;
+    }
+  }
+}
+
 template <typename T, bool KC, bool CJ>
 __device__ __forceinline__ void stage_op16(const TOp<T> &X, int i0, int k0, T *Sr, T *Si) {
   const int t = threadIdx.x;
@@ -98,10 +139,19 @@ __device__ __forceinline__ void ctile64(const TOp<T> &A, const TOp<T> &B, int i0
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = lane & 15, kk = lane >> 4;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  // register prefetch: chunk k0 + 16 is loaded while chunk k0 is multiplied
+  T avr[4], avi[4], bvr[4], bvi[4];
+  bool aok, bok;
+  load_op16<T, AKC>(A, i0, 0, avr, avi, aok);
+  load_op16<T, BKC>(B, j0, 0, bvr, bvi, bok);
   for (int k0 = 0; k0 < K; k0 += T64_BK) {
-    stage_op16<T, AKC, ACJ>(A, i0, k0, Asr, Asi);
-    stage_op16<T, BKC, BCJ>(B, j0, k0, Bsr, Bsi);
+    store_op16<T, AKC, ACJ>(avr, avi, aok, Asr, Asi);
+    store_op16<T, BKC, BCJ>(bvr, bvi, bok, Bsr, Bsi);
     __syncthreads();
+    if (k0 + T64_BK < K) {  // uniform
+      load_op16<T, AKC>(A, i0, k0 + T64_BK, avr, avi, aok);
+      load_op16<T, BKC>(B, j0, k0 + T64_BK, bvr, bvi, bok);
+    }
 #pragma unroll
     for (int k4 = 0; k4 < T64_BK; k4 += 4) {
       T ar[2], ai[2], br[2], bi[2];
@@ -122,7 +172,7 @@ __device__ __forceinline__ void ctile64(const TOp<T> &A, const TOp<T> &B, int i0
           acc[m][n][1] = mfma4(ai[m], br[n], acc[m][n][1]);
         }
     }
-    __syncthreads();
+    lds_barrier();  // the chunk's LDS reads are done; the prefetch stays in flight
   }
 }
 
