@@ -131,6 +131,63 @@ __device__ __forceinline__ void stage_store(const StageArgs<T> &a, long j, int r
   }
 }
 
+// The epilogue for NV outputs of one thread at once: every addend of the NV
+// outputs is loaded before the first store.  The stage launches never let
+// C or C2 overlap A, B or an extra addend (outputs go to buffers of their
+// own), so the loads need not wait behind the stores.
+template <typename T, int NV>
+__device__ __forceinline__ void stage_store_n(const StageArgs<T> &a, long j, const int (&row)[NV],
+                                              const int (&col)[NV], const T (&accr)[NV],
+                                              const T (&acci)[NV]) {
+  const long plane = (long)a.dp * a.dp;
+  const bool needA = a.betaA != (T)0 || (a.C2 && a.c2A != (T)0);
+  const bool needB = a.betaB != (T)0 || (a.C2 && a.c2B != (T)0);
+  const T *Aj = a.A + j * a.strideA, *Bj = a.B + j * a.strideB;
+  T ar[NV], ai[NV], br[NV], bi[NV], xr[3][NV], xi[3][NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const long o = (long)row[v] * a.dp + col[v];
+    ar[v] = needA ? Aj[o] : (T)0;
+    ai[v] = needA ? Aj[plane + o] : (T)0;
+    br[v] = needB ? Bj[o] : (T)0;
+    bi[v] = needB ? Bj[plane + o] : (T)0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const T *Xq = a.xadd[q] + j * a.strideC;
+      xr[q][v] = q < a.nx ? Xq[o] : (T)0;
+      xi[q][v] = q < a.nx ? Xq[plane + o] : (T)0;
+    }
+  }
+  T *Cj = a.C + j * a.strideC;
+  T *C2j = a.C2 ? a.C2 + j * a.strideC : nullptr;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const long o = (long)row[v] * a.dp + col[v];
+    T vr = a.alpha * accr[v] + a.betaA * ar[v] + a.betaB * br[v];
+    T vi = a.alpha * acci[v] + a.betaA * ai[v] + a.betaB * bi[v];
+    if (row[v] == col[v]) vr += a.gamma;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      vr += a.xc[q] * xr[q][v];
+      vi += a.xc[q] * xi[q][v];
+    }
+    Cj[o] = vr;
+    Cj[plane + o] = vi;
+    if (C2j) {
+      T wr = a.c2P * accr[v] + a.c2A * ar[v] + a.c2B * br[v];
+      T wi = a.c2P * acci[v] + a.c2A * ai[v] + a.c2B * bi[v];
+      if (row[v] == col[v]) wr += a.g2;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        wr += a.xc2[q] * xr[q][v];
+        wi += a.xc2[q] * xi[q][v];
+      }
+      C2j[o] = wr;
+      C2j[plane + o] = wi;
+    }
+  }
+}
+
 // dp a multiple of 16: one wavefront per 16x16 output tile, operands read
 // straight from L1/L2 (small matrices: the whole matrix is a few tiles).
 template <typename T, int OPA>
@@ -155,7 +212,7 @@ __global__ __launch_bounds__(256) void k_stage16(StageArgs<T> a) {
 
 // dp a multiple of 64: one workgroup per 64x64 output tile, LDS-staged,
 // XCD-aware block order (all tiles of one step on one XCD's L2).
-template <typename T, int OPA>
+template <typename T, int OPA, bool PF>
 __global__ __launch_bounds__(256) void k_stage64(StageArgs<T> a, long padded) {
   __shared__ T lds[T64_LDS_ELEMS];
   const int t1 = a.dp >> 6;
@@ -176,9 +233,10 @@ __global__ __launch_bounds__(256) void k_stage64(StageArgs<T> a, long padded) {
       acc[m][n][0] = vzero<T>();
       acc[m][n][1] = vzero<T>();
     }
-  wg_cgemm64<T, OPA>(A, B, r0, c0, a.dp, lds, acc);
+  wg_cgemm64<T, OPA, PF>(A, B, r0, c0, a.dp, lds, acc);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  if constexpr (!PF) {
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -187,6 +245,25 @@ __global__ __launch_bounds__(256) void k_stage64(StageArgs<T> a, long padded) {
       for (int v = 0; v < 4; ++v)
         stage_store(a, j, r0 + wr + 16 * m + acc_row<T>(lane, v), c0 + wc + 16 * n + (lane & 15),
                     acc[m][n][0][v], acc[m][n][1][v]);
+  } else {
+  constexpr int NV = 8, NPG = NV / 4;  // outputs and 16x16 tiles per batch
+#pragma unroll
+  for (int g = 0; g < 4 / NPG; ++g) {
+    int row[NV], col[NV];
+    T pr[NV], pi[NV];
+#pragma unroll
+    for (int u = 0; u < NPG; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int tn = g * NPG + u, m = tn >> 1, n = tn & 1;
+        row[4 * u + v] = r0 + wr + 16 * m + acc_row<T>(lane, v);
+        col[4 * u + v] = c0 + wc + 16 * n + (lane & 15);
+        pr[4 * u + v] = acc[m][n][0][v];
+        pi[4 * u + v] = acc[m][n][1][v];
+      }
+    stage_store_n<T, NV>(a, j, row, col, pr, pi);
+  }
+  }
 }
 
 // dp a multiple of 16 but not of 64 (80, 96, 112, ...): one workgroup per
@@ -269,7 +346,7 @@ __global__ __launch_bounds__(256) void k_stage32(StageArgs<T> a, long padded) {
 
 // bf16x3 variant of k_stage64 (FP32 storage; the split-product tile of
 // qoc_tile.h), same tiling, epilogue and block order.
-template <int OPA>
+template <int OPA, bool EB>
 __global__ __launch_bounds__(256) void k_stage64_bf3(StageArgs<float> a, long padded) {
   __shared__ BfLds L;
   const int t1 = a.dp >> 6;
@@ -293,16 +370,36 @@ __global__ __launch_bounds__(256) void k_stage64_bf3(StageArgs<float> a, long pa
   // op(A) = A: inner index along rows of A; op(A) = A^H: along columns,
   // conjugated; B as stored: inner index along columns of B
   ctile64_bf3<OPA == 0, OPA == 1, false, false>(A, B, r0, c0, a.dp, L, acc);
+  if constexpr (EB) {  // batched epilogue (d_pad <= 128)
 #pragma unroll
-  for (int m = 0; m < 2; ++m)
+    for (int m = 0; m < 2; ++m) {
+      int row[8], col[8];
+      float pr[8], pi[8];
 #pragma unroll
-    for (int n = 0; n < 2; ++n)
+      for (int n = 0; n < 2; ++n)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        int r, c;
-        tile64_pos<float>(m, n, v, r, c);
-        stage_store(a, j, r0 + r, c0 + c, acc[m][n][0][v], acc[m][n][1][v]);
-      }
+        for (int v = 0; v < 4; ++v) {
+          int r, c;
+          tile64_pos<float>(m, n, v, r, c);
+          row[4 * n + v] = r0 + r;
+          col[4 * n + v] = c0 + c;
+          pr[4 * n + v] = acc[m][n][0][v];
+          pi[4 * n + v] = acc[m][n][1][v];
+        }
+      stage_store_n<float, 8>(a, j, row, col, pr, pi);
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int r, c;
+          tile64_pos<float>(m, n, v, r, c);
+          stage_store(a, j, r0 + r, c0 + c, acc[m][n][0][v], acc[m][n][1][v]);
+        }
+  }
 }
 
 template <typename T>
@@ -322,12 +419,19 @@ template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hi
       const long t1 = a.dp / 64;
       const long total = (long)a.nmat * t1 * t1;
       const long padded = (total + 7) / 8 * 8;
-      if (opa)
-        hipLaunchKernelGGL((k_stage64_bf3<1>), dim3((unsigned)padded), dim3(256), 0, st, a,
+      const bool eb = a.dp <= 128;
+      if (opa && eb)
+        hipLaunchKernelGGL((k_stage64_bf3<1, true>), dim3((unsigned)padded), dim3(256), 0, st, a,
+                           padded);
+      else if (opa)
+        hipLaunchKernelGGL((k_stage64_bf3<1, false>), dim3((unsigned)padded), dim3(256), 0, st, a,
+                           padded);
+      else if (eb)
+        hipLaunchKernelGGL((k_stage64_bf3<0, true>), dim3((unsigned)padded), dim3(256), 0, st, a,
                            padded);
       else
-        hipLaunchKernelGGL((k_stage64_bf3<0>), dim3((unsigned)padded), dim3(256), 0, st, a,
-                           padded);
+        hipLaunchKernelGGL((k_stage64_bf3<0, false>), dim3((unsigned)padded), dim3(256), 0, st,
+                           a, padded);
       return hipGetLastError();
     }
   }
@@ -335,10 +439,21 @@ template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hi
     const long t1 = a.dp / 64;
     const long total = (long)a.nmat * t1 * t1;
     const long padded = (total + 7) / 8 * 8;
-    if (opa)
-      hipLaunchKernelGGL((k_stage64<T, 1>), dim3((unsigned)padded), dim3(256), 0, st, a, padded);
+    // short inner dimension (d_pad <= 128): register prefetch and batched
+    // epilogue; longer ones: the occupancy-friendly loop
+    const bool pf = a.dp <= 128;
+    if (opa && pf)
+      hipLaunchKernelGGL((k_stage64<T, 1, true>), dim3((unsigned)padded), dim3(256), 0, st, a,
+                         padded);
+    else if (opa)
+      hipLaunchKernelGGL((k_stage64<T, 1, false>), dim3((unsigned)padded), dim3(256), 0, st, a,
+                         padded);
+    else if (pf)
+      hipLaunchKernelGGL((k_stage64<T, 0, true>), dim3((unsigned)padded), dim3(256), 0, st, a,
+                         padded);
     else
-      hipLaunchKernelGGL((k_stage64<T, 0>), dim3((unsigned)padded), dim3(256), 0, st, a, padded);
+      hipLaunchKernelGGL((k_stage64<T, 0, false>), dim3((unsigned)padded), dim3(256), 0, st, a,
+                         padded);
   } else if (a.dp > 48) {
     const long t1 = (a.dp + 31) / 32;
     const long total = (long)a.nmat * t1 * t1;

@@ -92,11 +92,27 @@ __device__ __forceinline__ void wave_cgemm16(CView<const T> A, CView<const T> B,
 }
 
 // ---------------------------------------------------------------------------
+// Workgroup barrier that orders LDS traffic only.  __syncthreads() also
+// waits for every outstanding global-memory operation of the wave (vmcnt
+// covers loads and stores on this architecture), which would drain a
+// register prefetch ring at every step.  Use only where no global-memory
+// visibility between the waves of the workgroup is needed.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  // s_waitcnt lgkmcnt(0), vmcnt and expcnt left at their maxima
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Workgroup (256 threads, 4 waves) LDS-tiled 64x64 complex tile of
 // C = op(A) * B, with op(A) = A or A^H and B as stored.  The inner
 // dimension runs in chunks of BK = 16 staged in LDS in k-major layout
 // (row stride 64 + 16 elements, which keeps the 16-lane fragment reads of
-// each half-wave on distinct banks).  Wave w owns the 32x32 sub-tile
+// each half-wave on distinct banks); with PF the next chunk is loaded into
+// registers while the current one is multiplied (short inner dimensions:
+// it pays at d_pad 128, while at d_pad 512 the registers it takes cost more
+// occupancy than it hides latency).  Wave w owns the 32x32 sub-tile
 // (32*(w>>1), 32*(w&1)) as 2x2 MFMA tiles.
 // ---------------------------------------------------------------------------
 constexpr int T64_BK = 16;
@@ -104,7 +120,7 @@ constexpr int T64_LD = 64 + 16;
 // LDS elements of T needed by wg_cgemm64: A and B chunks, re and im planes.
 constexpr int T64_LDS_ELEMS = 4 * T64_BK * T64_LD;
 
-template <typename T, int OPA>
+template <typename T, int OPA, bool PF = true>
 __device__ __forceinline__ void wg_cgemm64(CView<const T> A, CView<const T> B, int r0, int c0,
                                            int K, T *lds, v4<T> (&acc)[2][2][2]) {
   T *Asr = lds;
@@ -114,35 +130,39 @@ __device__ __forceinline__ void wg_cgemm64(CView<const T> A, CView<const T> B, i
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int i = lane & 15, kk = lane >> 4;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  for (int k0 = 0; k0 < K; k0 += T64_BK) {
-    // stage op(A)[r0:r0+64, k0:k0+16] as As[k][r]
-    if (OPA == 0) {
-      const int r = t >> 2, kq = (t & 3) * 4;
-      const long o = (long)(r0 + r) * A.ld + k0 + kq;
+  // this thread's slots of a chunk: op(A) as As[k][r], B as Bs[k][c]
+  const int ar_ = t >> 2, akq = (t & 3) * 4;   // OPA = 0: row, inner offset
+  const int ak = t >> 4, arq = (t & 15) * 4;   // OPA = 1: inner, row offset
+  const int bk = t >> 4, bcq = (t & 15) * 4;
+  T va[2][4], vb[2][4];  // next chunk, loaded while the current one is multiplied
+  auto load = [&](int k0) {
+    const long oa = OPA == 0 ? (long)(r0 + ar_) * A.ld + k0 + akq : (long)(k0 + ak) * A.ld + r0 + arq;
+    const long ob = (long)(k0 + bk) * B.ld + c0 + bcq;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        Asr[(kq + q) * T64_LD + r] = A.re[o + q];
-        Asi[(kq + q) * T64_LD + r] = A.im[o + q];
-      }
-    } else {
-      const int k = t >> 4, rq = (t & 15) * 4;
-      const long o = (long)(k0 + k) * A.ld + r0 + rq;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        Asr[k * T64_LD + rq + q] = A.re[o + q];
-        Asi[k * T64_LD + rq + q] = -A.im[o + q];
-      }
+    for (int q = 0; q < 4; ++q) {
+      va[0][q] = A.re[oa + q];
+      va[1][q] = A.im[oa + q];
+      vb[0][q] = B.re[ob + q];
+      vb[1][q] = B.im[ob + q];
     }
-    {
-      const int k = t >> 4, cq = (t & 15) * 4;
-      const long o = (long)(k0 + k) * B.ld + c0 + cq;
+  };
+  if (PF) load(0);
+  for (int k0 = 0; k0 < K; k0 += T64_BK) {
+    if (!PF) load(k0);  // without prefetch: fewer registers, more workgroups per unit
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        Bsr[k * T64_LD + cq + q] = B.re[o + q];
-        Bsi[k * T64_LD + cq + q] = B.im[o + q];
+    for (int q = 0; q < 4; ++q) {
+      if (OPA == 0) {
+        Asr[(akq + q) * T64_LD + ar_] = va[0][q];
+        Asi[(akq + q) * T64_LD + ar_] = va[1][q];
+      } else {
+        Asr[ak * T64_LD + arq + q] = va[0][q];
+        Asi[ak * T64_LD + arq + q] = -va[1][q];
       }
+      Bsr[bk * T64_LD + bcq + q] = vb[0][q];
+      Bsi[bk * T64_LD + bcq + q] = vb[1][q];
     }
     __syncthreads();
+    if (PF && k0 + T64_BK < K) load(k0 + T64_BK);  // uniform
 #pragma unroll
     for (int k4 = 0; k4 < T64_BK; k4 += 4) {
       T ar[2], ai[2], br[2], bi[2];
@@ -163,7 +183,10 @@ __device__ __forceinline__ void wg_cgemm64(CView<const T> A, CView<const T> B, i
           acc[m][n][1] = mfma4(ai[m], br[n], acc[m][n][1]);
         }
     }
-    __syncthreads();
+    if (PF)
+      lds_barrier();  // the chunk's LDS reads are done; the prefetch stays in flight
+    else
+      __syncthreads();
   }
 }
 
@@ -176,18 +199,6 @@ __device__ __forceinline__ long xcd_logical_block(long b, long padded) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Workgroup barrier that orders LDS traffic only.  __syncthreads() also
-// waits for every outstanding global-memory operation of the wave (vmcnt
-// covers loads and stores on this architecture), which would drain a
-// register prefetch ring at every step.  Use only where no global-memory
-// visibility between the waves of the workgroup is needed.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("" ::: "memory");
-  // s_waitcnt lgkmcnt(0), vmcnt and expcnt left at their maxima
-  __builtin_amdgcn_s_waitcnt(0xC07F);
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
 
 // Wave-wide sum (64 lanes) with cross-lane shuffles.
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
