@@ -34,6 +34,8 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint16(Adjoint
   const long set = 2L * S * 16, mat = 512;
   for (long j = (long)blockIdx.x * 4 + w; j < N; j += (long)step_blocks * 4) {
     // ---- cotangent factors A = [lambda_{j+1}], B = [psi_j], zero columns >= S
+    // (read at a clamped column and masked: a load under a lane-dependent
+    // condition would get a branch of its own and an immediate wait)
     const T *lam = a.lam_buf + j * set, *psi = a.psi_buf + j * set;
     CTile<T> A, B;
 #pragma unroll
@@ -41,10 +43,12 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint16(Adjoint
       const int row = acc_row<T>(lane, v);
       const bool on = col < S;
       const int cs = on ? col : 0;
-      A.r[v] = on ? lam[cs * 16 + row] : (T)0;
-      A.i[v] = on ? lam[S * 16 + cs * 16 + row] : (T)0;
-      B.r[v] = on ? psi[cs * 16 + row] : (T)0;
-      B.i[v] = on ? psi[S * 16 + cs * 16 + row] : (T)0;
+      const T lr = lam[cs * 16 + row], li = lam[S * 16 + cs * 16 + row];
+      const T pr = psi[cs * 16 + row], pi = psi[S * 16 + cs * 16 + row];
+      A.r[v] = on ? lr : (T)0;
+      A.i[v] = on ? li : (T)0;
+      B.r[v] = on ? pr : (T)0;
+      B.i[v] = on ? pi : (T)0;
     }
     int r = S;
     // operand fragments of the next level's D (then of X), loaded one level
@@ -142,12 +146,20 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint16(Adjoint
     // ---- dC/du_{k,j} = 2 (dt/2^n) Im tr(Xbar^H H_k) + regulariser terms
     // four controls at a time: their loads and wavefront sums overlap
     const double two_s = 2.0 * s_scale;
+    const long jm = j >= 1 ? j - 1 : j, jp = j <= N - 2 ? j + 1 : j;  // clamped neighbours
     for (int k0 = 0; k0 < M; k0 += 4) {
-      double part[4];
+      double part[4], reg[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int k = k0 + q < M ? k0 + q : M - 1;
         const T *H = a.Hf + (long)(1 + k) * mat;
+        // regulariser: 2 a_amp u_j + 2 a_var ((u_j - u_{j-1}) - (u_{j+1} - u_j));
+        // a missing neighbour is read as u_j itself, which adds exact zeros
+        const double *uk = a.u + (long)k * N;
+        const double u0 = uk[j], um = uk[jm], up = uk[jp];
+        reg[q] = 2.0 * a.alpha_amp * u0;
+        reg[q] += 2.0 * a.alpha_var * (u0 - um);
+        reg[q] -= 2.0 * a.alpha_var * (up - u0);
         part[q] = 0.0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -160,13 +172,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_adjoint16(Adjoint
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int k = k0 + q;
-        if (lane == 0 && k < M) {
-          const double *uk = a.u + (long)k * N;
-          double reg = 2.0 * a.alpha_amp * uk[j];
-          if (j >= 1) reg += 2.0 * a.alpha_var * (uk[j] - uk[j - 1]);
-          if (j <= N - 2) reg -= 2.0 * a.alpha_var * (uk[j + 1] - uk[j]);
-          a.grad[(long)k * N + j] = two_s * part[q] + reg;
-        }
+        if (lane == 0 && k < M) a.grad[(long)k * N + j] = two_s * part[q] + reg[q];
       }
     }
   }

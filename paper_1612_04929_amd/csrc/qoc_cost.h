@@ -72,14 +72,17 @@ __device__ inline void lam_wave(const SweepArgs<T> &a, int s, int m, int kq, T &
   const T *psiN = a.psi_buf + (long)N * set;
   const int lane = threadIdx.x & 63;
   double zr = 0.0, zi = 0.0, Finc = 0.0, own_r = 0.0, own_i = 0.0;
+  // every operand is read at a clamped row and masked afterwards (a load
+  // under a lane-dependent condition gets a branch and a wait of its own)
+  const int mc = m < d ? m : d - 1;
+  const bool on = kq == 0 && m < d;
   for (int q = 0; q < S; ++q) {
-    double pr = 0.0, pi = 0.0;
-    if (kq == 0 && m < d) {
-      const double tr = a.psiT64[((long)q * d + m) * 2], ti = a.psiT64[((long)q * d + m) * 2 + 1];
-      const double yr = (double)psiN[q * DP + m], yi = (double)psiN[(S + q) * DP + m];
-      pr = tr * yr + ti * yi;  // conj(T) psi
-      pi = tr * yi - ti * yr;
-    }
+    const double tr = a.psiT64[((long)q * d + mc) * 2], ti = a.psiT64[((long)q * d + mc) * 2 + 1];
+    const double yr = (double)psiN[q * DP + m], yi = (double)psiN[(S + q) * DP + m];
+    double pr = tr * yr + ti * yi;  // conj(T) psi
+    double pi = tr * yi - ti * yr;
+    pr = on ? pr : 0.0;
+    pi = on ? pi : 0.0;
     pr = wave_sum(pr);
     pi = wave_sum(pi);
     zr += pr;
@@ -104,11 +107,9 @@ __device__ inline void lam_wave(const SweepArgs<T> &a, int s, int m, int kq, T &
     a.zinfo[2] = F;
   }
   const double cr = (a.fid_mode == 0 ? zr : own_r) / S, ci = (a.fid_mode == 0 ? zi : own_i) / S;
-  double tr = 0.0, ti = 0.0;
-  if (m < d) {
-    tr = a.psiT64[((long)s * d + m) * 2];
-    ti = a.psiT64[((long)s * d + m) * 2 + 1];
-  }
+  double tr = a.psiT64[((long)s * d + mc) * 2], ti = a.psiT64[((long)s * d + mc) * 2 + 1];
+  tr = m < d ? tr : 0.0;
+  ti = m < d ? ti : 0.0;
   double lr = -a.alpha_fid * (cr * tr - ci * ti);
   double li = -a.alpha_fid * (cr * ti + ci * tr);
   if (a.pw) {
