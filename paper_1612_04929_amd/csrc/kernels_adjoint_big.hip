@@ -163,18 +163,35 @@ template <typename T, int TN> __global__ __launch_bounds__(256) void k_thin_batc
   if (r0 + 16 * w >= a.dp) return;
   CView<const T> Ad = a.Add[h].at(j);
   T *ore = const_cast<T *>(a.Out[h].at(j).re), *oim = const_cast<T *>(a.Out[h].at(j).im);
-  const int old = a.Out[h].ld;
+  const int old = a.Out[h].ld, sp = a.split[h];
+  const T addS = a.addS[h];
+  const bool add = addS != (T)0 && sp > 0;  // uniform
+  // the addends of the first `split` columns: all read (at a clamped column,
+  // so no load sits under a per-lane condition) before any output is
+  // stored; outputs never alias addends
+  T xr[TN / 16][4], xi[TN / 16][4];
+  if (add) {
+#pragma unroll
+    for (int q = 0; q < TN / 16; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * w + acc_row<T>(lane, v), col = c0 + 16 * q + (lane & 15);
+        const long o = (long)row * Ad.ld + (col < sp ? col : sp - 1);
+        xr[q][v] = Ad.re[o];
+        xi[q][v] = Ad.im[o];
+      }
+  }
 #pragma unroll
   for (int q = 0; q < TN / 16; ++q)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = r0 + 16 * w + acc_row<T>(lane, v), col = c0 + 16 * q + (lane & 15);
-      const bool first = col < a.split[h];
+      const bool first = col < sp;
       const T al = first ? a.alpha[h] : a.alpha2[h];
       T vr = al * cr[q][v], vi = al * ci[q][v];
-      if (first && a.addS[h] != (T)0) {
-        vr += a.addS[h] * Ad.re[(long)row * Ad.ld + col];
-        vi += a.addS[h] * Ad.im[(long)row * Ad.ld + col];
+      if (add) {
+        vr = first ? vr + addS * xr[q][v] : vr;
+        vi = first ? vi + addS * xi[q][v] : vi;
       }
       ore[(long)row * old + col] = vr;
       oim[(long)row * old + col] = vi;
@@ -213,7 +230,26 @@ __global__ __launch_bounds__(256) void k_thin64(ThinBatch<T> a, long padded) {
     tile64<T, BF3, true, false, false, false>(A, B, r0, c0, a.dp, lds, acc);
   CView<const T> Ad = a.Add[h].at(j);
   T *ore = const_cast<T *>(a.Out[h].at(j).re), *oim = const_cast<T *>(a.Out[h].at(j).im);
-  const int old = a.Out[h].ld;
+  const int old = a.Out[h].ld, sp = a.split[h];
+  const T addS = a.addS[h];
+  const bool add = addS != (T)0 && sp > 0;  // uniform
+  // addends read first, at clamped positions (see k_thin_batch)
+  T xr[2][2][4], xi[2][2][4];
+  if (add) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int r, c;
+          tile64_pos<T>(m, n, v, r, c);
+          const int row = r0 + r, col = c0 + c;
+          const long o = (long)(row < a.dp ? row : a.dp - 1) * Ad.ld + (col < sp ? col : sp - 1);
+          xr[m][n][v] = Ad.re[o];
+          xi[m][n][v] = Ad.im[o];
+        }
+  }
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -223,14 +259,14 @@ __global__ __launch_bounds__(256) void k_thin64(ThinBatch<T> a, long padded) {
         int r, c;
         tile64_pos<T>(m, n, v, r, c);
         const int row = r0 + r, col = c0 + c;
+        const bool first = col < sp;
+        const T al = first ? a.alpha[h] : a.alpha2[h];
+        T vr = al * acc[m][n][0][v], vi = al * acc[m][n][1][v];
+        if (add) {
+          vr = first ? vr + addS * xr[m][n][v] : vr;
+          vi = first ? vi + addS * xi[m][n][v] : vi;
+        }
         if (row < a.dp && col < a.W) {
-          const bool first = col < a.split[h];
-          const T al = first ? a.alpha[h] : a.alpha2[h];
-          T vr = al * acc[m][n][0][v], vi = al * acc[m][n][1][v];
-          if (first && a.addS[h] != (T)0) {
-            vr += a.addS[h] * Ad.re[(long)row * Ad.ld + col];
-            vi += a.addS[h] * Ad.im[(long)row * Ad.ld + col];
-          }
           ore[(long)row * old + col] = vr;
           oim[(long)row * old + col] = vi;
         }

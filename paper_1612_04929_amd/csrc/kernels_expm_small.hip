@@ -224,33 +224,72 @@ __device__ __forceinline__ unsigned long long expm16_step(long j, int p, int n, 
   const int d = nm.d;
   const long dd = (long)d * d;
   // X_j = -i s H_j: entries lane + 64 q of each plane (row lane / 16 + 4 q,
-  // column lane % 16); with NORM also H_j in FP64
+  // column lane % 16); with NORM also H_j in FP64.  The FP64 entries are
+  // read at clamped (always valid) positions, summed, and masked only at
+  // the end: a load under a lane-dependent condition would sit in a branch
+  // of its own, and a mask applied at once would wait for the load there,
+  // before the control terms' loads are issued.
+  // The drift term's offset is an opaque zero, so its loads are issued here
+  // beside the others rather than hoisted out of the caller's step loop
+  // (where the copy into the accumulators would wait for them on their own).
+  int z0;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z0));
   T hr[4], hi[4];
   double gr[4], gi[4];
+  int go[4];     // FP64 entry offset (complex pairs) of row, column
+  bool gin[4];   // inside the true d x d block
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    hr[q] = Hf[lane + 64 * q];
-    hi[q] = Hf[PL + lane + 64 * q];
+    hr[q] = Hf[z0 + lane + 64 * q];
+    hi[q] = Hf[z0 + PL + lane + 64 * q];
     const int row = (lane >> 4) + 4 * q;
-    const bool in = NORM && row < d && col < d;
-    gr[q] = in ? nm.H64[(row * d + col) * 2] : 0.0;
-    gi[q] = in ? nm.H64[(row * d + col) * 2 + 1] : 0.0;
+    gin[q] = row < d && col < d;
+    go[q] = ((row < d ? row : d - 1) * d + (col < d ? col : d - 1)) * 2;
+    if (NORM) {
+      const double2 g = *reinterpret_cast<const double2 *>(nm.H64 + z0 + go[q]);
+      gr[q] = g.x;
+      gi[q] = g.y;
+    }
   }
-#pragma unroll 4
-  for (int k = 0; k < M; ++k) {
-    const double cd = u[(long)k * N + j];
-    const T c = (T)cd;
-    const T *Hk = Hf + (long)(k + 1) * 2 * PL;
-    const double *Gk = nm.H64 + (k + 1) * dd * 2;
+  // controls in groups of four: every load of a group is issued before the
+  // first use (a short group reads the last control again with a zero
+  // amplitude, which adds exact zeros)
+  for (int k0 = 0; k0 < M; k0 += 4) {
+    double cu[4];
+    T ar[4][4], ai[4][4];
+    double2 ag[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = k0 + t < M ? k0 + t : M - 1;
+      cu[t] = u[(long)k * N + j];
+      const T *Hk = Hf + (long)(k + 1) * 2 * PL;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ar[t][q] = Hk[lane + 64 * q];
+        ai[t][q] = Hk[PL + lane + 64 * q];
+        if (NORM) ag[t][q] = *reinterpret_cast<const double2 *>(nm.H64 + (k + 1) * dd * 2 + go[q]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double cd = k0 + t < M ? cu[t] : 0.0;
+      const T c = (T)cd;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        hr[q] += c * ar[t][q];
+        hi[q] += c * ai[t][q];
+        if (NORM) {
+          gr[q] += cd * ag[t][q].x;
+          gi[q] += cd * ag[t][q].y;
+        }
+      }
+    }
+  }
+  if (NORM) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      hr[q] += c * Hk[lane + 64 * q];
-      hi[q] += c * Hk[PL + lane + 64 * q];
-      const int row = (lane >> 4) + 4 * q;
-      if (NORM && row < d && col < d) {
-        gr[q] += cd * Gk[(row * d + col) * 2];
-        gi[q] += cd * Gk[(row * d + col) * 2 + 1];
-      }
+      gr[q] = gin[q] ? gr[q] : 0.0;
+      gi[q] = gin[q] ? gi[q] : 0.0;
     }
   }
   unsigned long long bits = 0ull;
@@ -340,6 +379,8 @@ __device__ __forceinline__ unsigned long long expm16_step(long j, int p, int n, 
   return bits;
 }
 
+constexpr int E16_WAVES = 4;  // wavefronts (steps in flight) per workgroup of k_expm16
+
 // LDS of one wavefront's step: X (two planes) and a staging tile
 template <typename T> struct Expm16Lds {
   T x[2][256];
@@ -347,11 +388,11 @@ template <typename T> struct Expm16Lds {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_expm16(const T *__restrict__ Hf,
+__global__ __launch_bounds__(64 * E16_WAVES) void k_expm16(const T *__restrict__ Hf,
                                                 const double *__restrict__ u, int M, int N,
                                                 T *X, T *Dlev, T *Dh, Norm16 nm) {
-  __shared__ __align__(16) Expm16Lds<T> lds[4];
-  __shared__ unsigned long long red[4];
+  __shared__ __align__(16) Expm16Lds<T> lds[E16_WAVES];
+  __shared__ unsigned long long red[E16_WAVES];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int *pn = nm.sel.pn;
   const int p0 = pn[0], n0 = pn[1];
@@ -360,7 +401,7 @@ __global__ __launch_bounds__(256) void k_expm16(const T *__restrict__ Hf,
   const T s = (T)nm.sel.sc[0];
   Expm16Lds<T> &L = lds[w];
   unsigned long long vmax = 0ull;  // largest ||dt H_j||_1 bit pattern of this wavefront
-  for (long j = (long)blockIdx.x * 4 + w; j < N; j += (long)gridDim.x * 4) {
+  for (long j = (long)blockIdx.x * E16_WAVES + w; j < N; j += (long)gridDim.x * E16_WAVES) {
     const unsigned long long b = expm16_step<T, true>(j, p, n, s, Hf, u, M, N, X, Dlev, Dh, nm,
                                                       L.x[0], L.x[1], L.t[0], L.t[1]);
     vmax = b > vmax ? b : vmax;
@@ -370,7 +411,7 @@ __global__ __launch_bounds__(256) void k_expm16(const T *__restrict__ Hf,
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long m = red[0];
-    for (int i = 1; i < 4; ++i) m = red[i] > m ? red[i] : m;
+    for (int i = 1; i < E16_WAVES; ++i) m = red[i] > m ? red[i] : m;
     nm.part[blockIdx.x] = m;
     if (blockIdx.x == 0) pn[3] = (p0 & 0xffff) | (n0 << 16);  // the pair used
   }
@@ -620,14 +661,14 @@ hipError_t launch_expm_small(const T *Hf, const double *u, int dp, int M, int N,
 }
 
 template <typename T> unsigned expm16_blocks(int N) {
-  return (unsigned)std::min<long>((N + 3) / 4, 4096);
+  return (unsigned)std::min<long>((N + E16_WAVES - 1) / E16_WAVES, 4096);
 }
 
 template <typename T>
 hipError_t launch_expm16(const T *Hf, const double *u, int M, int N, T *X, T *Dlev, T *Dh,
                          const Norm16 &nm, hipStream_t st) {
-  hipLaunchKernelGGL(k_expm16<T>, dim3(expm16_blocks<T>(N)), dim3(256), 0, st, Hf, u, M, N, X,
-                     Dlev, Dh, nm);
+  hipLaunchKernelGGL(k_expm16<T>, dim3(expm16_blocks<T>(N)), dim3(64 * E16_WAVES), 0, st, Hf,
+                     u, M, N, X, Dlev, Dh, nm);
   return hipGetLastError();
 }
 

@@ -63,13 +63,14 @@ __device__ __forceinline__ CView<T> cview(T *base, long plane, int ld) {
 // One wavefront accumulates the 16x16 complex tile (r0, c0) of
 // op(A) * op(B) over an inner dimension K (multiple of 4), reading operands
 // straight from global memory (L1/L2 resident).  OPA / OPB: 0 = as stored,
-// 1 = conjugate transpose.  cr, ci: real / imaginary accumulators.
+// 1 = conjugate transpose.  cr, ci: real / imaginary accumulators.  The
+// operands of four inner chunks are loaded before their products, so one
+// memory round trip serves sixteen inner indices.
 template <typename T, int OPA, int OPB>
 __device__ __forceinline__ void wave_cgemm16(CView<const T> A, CView<const T> B, int r0,
                                              int c0, int K, v4<T> &cr, v4<T> &ci) {
   const int lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
-  for (int k = 0; k < K; k += 4) {
-    T ar, ai, br, bi;
+  auto ld = [&](int k, T &ar, T &ai, T &br, T &bi) {
     if (OPA == 0) {
       const long o = (long)(r0 + i) * A.ld + (k + kk);
       ar = A.re[o]; ai = A.im[o];
@@ -84,10 +85,25 @@ __device__ __forceinline__ void wave_cgemm16(CView<const T> A, CView<const T> B,
       const long o = (long)(c0 + i) * B.ld + (k + kk);
       br = B.re[o]; bi = -B.im[o];
     }
+  };
+  auto mac = [&](T ar, T ai, T br, T bi) {
     cr = mfma4(ar, br, cr);
     cr = mfma4(-ai, bi, cr);
     ci = mfma4(ar, bi, ci);
     ci = mfma4(ai, br, ci);
+  };
+  int k = 0;
+  for (; k + 16 <= K; k += 16) {
+    T ar[4], ai[4], br[4], bi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ld(k + 4 * u, ar[u], ai[u], br[u], bi[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) mac(ar[u], ai[u], br[u], bi[u]);
+  }
+  for (; k < K; k += 4) {
+    T ar, ai, br, bi;
+    ld(k, ar, ai, br, bi);
+    mac(ar, ai, br, bi);
   }
 }
 
