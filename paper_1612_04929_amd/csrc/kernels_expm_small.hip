@@ -578,8 +578,26 @@ __global__ __launch_bounds__(256) void k_blockprod_tree16(const T *__restrict__ 
       __syncthreads();
     }
   }
-  for (long c0 = start; c0 < end; c0 += CH) {
-    const int cnt = (int)min((long)CH, end - c0);
+  // with sub-block products wanted, chunks hold whole sub-blocks, and the
+  // products of the first tree levels (SUB16 steps) are stored on the way
+  const bool subs = pick.Es != nullptr;  // uniform
+  const int chunk = subs ? (CH / SUB16) * SUB16 : CH;
+  auto store_subs = [&](long c0, int cnt) {
+    const int ns = (cnt + SUB16 - 1) / SUB16;
+    const long s0 = c0 / SUB16;
+    for (int e = threadIdx.x; e < ns * PL; e += 256) {
+      const int q = e / PL, o = e - q * PL, r = o >> 4, c = o & 15;
+      const T *src = m[q * SUB16];
+      T *es = pick.Es + (s0 + q) * 2 * PL, *eh = pick.Ehs + (s0 + q) * 2 * PL;
+      es[o] = src[o];
+      es[PL + o] = src[PL + o];
+      eh[o] = src[c * 16 + r];
+      eh[PL + o] = -src[PL + c * 16 + r];
+    }
+    __syncthreads();  // before the next level overwrites the slots
+  };
+  for (long c0 = start; c0 < end; c0 += chunk) {
+    const int cnt = (int)min((long)chunk, end - c0);
     {
       typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
       constexpr int VN = 16 / sizeof(T);
@@ -598,6 +616,7 @@ __global__ __launch_bounds__(256) void k_blockprod_tree16(const T *__restrict__ 
       for (; e < nv; e += 256) dst[e] = src[e];
     }
     __syncthreads();
+    bool stored = !subs;
     for (int stride = 1; stride < cnt; stride *= 2) {
       const int npair = (cnt - stride + 2 * stride - 1) / (2 * stride);
       for (int q = w; q < npair; q += 4) {
@@ -607,7 +626,12 @@ __global__ __launch_bounds__(256) void k_blockprod_tree16(const T *__restrict__ 
         dform_store(lane, cr[0], ci[0], A, B, B);
       }
       __syncthreads();
+      if (!stored && 2 * stride == SUB16) {  // slot q SUB16: sub-block q's product
+        store_subs(c0, cnt);
+        stored = true;
+      }
     }
+    if (!stored) store_subs(c0, cnt);  // a chunk of at most half a sub-block
     if (c0 == start) {  // uniform: the first chunk's product starts E
       for (int e = threadIdx.x; e < 2 * PL; e += 256) m[CH][e] = m[0][e];
     } else if (w == 0) {  // E <- C + E + C E, C the later chunk

@@ -332,6 +332,194 @@ template <typename T, int DP> __global__ __launch_bounds__(64) void k_wB3(SweepA
   lb[L.oi] = xi;
 }
 
+// ------------------------------------------------------------ F3 / B3 split
+// The in-block passes over sub-blocks of SUB16 steps (padded d 16, given
+// the sub-block products Es / Ehs): one workgroup per (block, state) with
+// one wavefront per sub-block.
+//
+// F3: wavefront 0 walks the sub-block starts, x <- x + Es_q x (at most
+// L / SUB16 - 1 steps); then every wavefront replays its own sub-block
+// from its start and, with a penalty, forms its sub-block's partial
+// costate nu_q from zero at the sub-block end (nu <- nu + D_j^H nu +
+// pw o psi_j, j >= 1), and wavefront 0 combines them into the block's
+// mu = nu_first + (I + Ehs_first) (... (nu_last)).
+// B3: wavefront 0 walks the costate back over the sub-block ends,
+// lambda <- lambda + Ehs_q lambda + nu_q; then every wavefront replays its
+// own sub-block backwards.  The values are those of the sequential passes
+// (the same recursions, regrouped).
+constexpr int WSPLIT_MAX = 16;  // wavefronts per workgroup: L <= 16 SUB16
+
+#define WS_SETUP                                                     \
+  constexpr int KC = WaveGeo<DP>::KC, KQ = WaveGeo<DP>::KQ;          \
+  __shared__ __align__(16) T xs[WSPLIT_MAX][2][2 * DP];              \
+  __shared__ __align__(16) T xb[WSPLIT_MAX][2 * DP];                 \
+  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;           \
+  const int ws = blockIdx.y, b = blockIdx.x;                         \
+  WLane L;                                                           \
+  L.m = lane / KQ;                                                   \
+  L.kq = lane - L.m * KQ;                                            \
+  L.o = ws * DP + L.m;                                               \
+  L.oi = (a.S + ws) * DP + L.m;                                      \
+  const long set = 2L * a.S * DP, mat = 2L * DP * DP;                \
+  const int start = b * a.L, end = min(a.N, start + a.L);            \
+  const int nsub = (end - start + SUB16 - 1) / SUB16;                \
+  const long sb0 = start / SUB16;                                    \
+  T(*x2)[2 * DP] = xs[q];                                            \
+  int cur = 0;
+
+template <typename T, int DP> __global__ __launch_bounds__(64 * WSPLIT_MAX) void k_wF3s(SweepArgs<T> a) {
+  WS_SETUP
+  // ---- sub-block starts (wavefront 0)
+  if (q == 0) {
+    const T *ck = a.ckpt + (long)b * set;
+    T xr = ck[L.o], xi = ck[L.oi];
+    w_put(xb[0], L.m, DP, xr, xi);
+    w_put(x2[0], L.m, DP, xr, xi);
+    wave_lds_fence();
+    auto eptr = [&](int i) -> const T * { return a.Es + (sb0 + i) * mat; };
+    auto dummy = [&](int) -> const T * { return ck; };
+    w_pipeline<T, DP>(L, nsub - 1, eptr, dummy, [&](int i, const T (&r)[2 * KC], T, T) {
+      T sr, si;
+      w_dot<T, DP>(L, r, x2[cur], sr, si);
+      xr += sr;
+      xi += si;
+      w_put(x2[cur ^ 1], L.m, DP, xr, xi);
+      w_put(xb[i + 1], L.m, DP, xr, xi);
+      cur ^= 1;
+      wave_lds_fence();
+    });
+  }
+  __syncthreads();
+  // ---- replay of sub-block q, then its partial penalty costate
+  if (q < nsub) {
+    const int a0 = start + q * SUB16, e0 = min(end, a0 + SUB16);
+    T xr = xb[q][L.m], xi = xb[q][DP + L.m];
+    cur = 0;
+    w_put(x2[0], L.m, DP, xr, xi);
+    a.psi_buf[(long)a0 * set + L.o] = xr;
+    a.psi_buf[(long)a0 * set + L.oi] = xi;
+    wave_lds_fence();
+    auto fptr = [&](int i) -> const T * { return a.D + (a0 + i) * mat; };
+    auto dummy = [&](int) -> const T * { return a.psi0; };
+    w_pipeline<T, DP>(L, e0 - a0, fptr, dummy, [&](int i, const T (&r)[2 * KC], T, T) {
+      T sr, si;
+      w_dot<T, DP>(L, r, x2[cur], sr, si);
+      xr += sr;
+      xi += si;
+      w_put(x2[cur ^ 1], L.m, DP, xr, xi);
+      const int j = a0 + i;
+      if (j + 1 < e0 || j + 1 == a.N) {  // wave-uniform
+        a.psi_buf[(long)(j + 1) * set + L.o] = xr;
+        a.psi_buf[(long)(j + 1) * set + L.oi] = xi;
+      }
+      cur ^= 1;
+      wave_lds_fence();
+    });
+    if (a.pw) {  // uniform
+      __threadfence_block();
+      const T wgt = a.pw[L.m];
+      T mr = (T)0, mi = (T)0;
+      w_put(x2[cur], L.m, DP, mr, mi);
+      wave_lds_fence();
+      auto bptr = [&](int i) -> const T * { return a.Dh + (e0 - 1 - i) * mat; };
+      auto pptr = [&](int i) -> const T * { return a.psi_buf + (long)(e0 - 1 - i) * set; };
+      w_pipeline<T, DP>(L, e0 - a0, bptr, pptr, [&](int i, const T (&r)[2 * KC], T pr, T pi) {
+        const int j = e0 - 1 - i;
+        T sr, si;
+        w_dot<T, DP>(L, r, x2[cur], sr, si);
+        mr += sr + (j >= 1 ? wgt * pr : (T)0);
+        mi += si + (j >= 1 ? wgt * pi : (T)0);
+        w_put(x2[cur ^ 1], L.m, DP, mr, mi);
+        cur ^= 1;
+        wave_lds_fence();
+      });
+      T *nu = a.nu + (sb0 + q) * set;
+      nu[L.o] = mr;
+      nu[L.oi] = mi;
+    }
+  }
+  if (!a.pw) return;  // uniform
+  __threadfence_block();
+  __syncthreads();
+  // ---- the block's penalty costate from the sub-blocks' (wavefront 0)
+  if (q == 0) {
+    const T *nl = a.nu + (sb0 + nsub - 1) * set;
+    T mr = nl[L.o], mi = nl[L.oi];
+    cur = 0;
+    w_put(x2[0], L.m, DP, mr, mi);
+    wave_lds_fence();
+    auto hptr = [&](int i) -> const T * { return a.Ehs + (sb0 + nsub - 2 - i) * mat; };
+    auto nptr = [&](int i) -> const T * { return a.nu + (sb0 + nsub - 2 - i) * set; };
+    w_pipeline<T, DP>(L, nsub - 1, hptr, nptr, [&](int, const T (&r)[2 * KC], T nr, T ni) {
+      T sr, si;
+      w_dot<T, DP>(L, r, x2[cur], sr, si);
+      mr += sr + nr;
+      mi += si + ni;
+      w_put(x2[cur ^ 1], L.m, DP, mr, mi);
+      cur ^= 1;
+      wave_lds_fence();
+    });
+    T *mu = a.mu + (long)b * set;
+    mu[L.o] = mr;
+    mu[L.oi] = mi;
+  }
+}
+
+template <typename T, int DP> __global__ __launch_bounds__(64 * WSPLIT_MAX) void k_wB3s(SweepArgs<T> a) {
+  WS_SETUP
+  const bool has_nu = a.pw != nullptr;
+  // ---- costates at the sub-block ends (wavefront 0), xb[q] = lambda at the
+  // end of sub-block q
+  if (q == 0) {
+    const T *c = a.lam_ckpt + (long)(b + 1) * set;
+    T xr = c[L.o], xi = c[L.oi];
+    w_put(xb[nsub - 1], L.m, DP, xr, xi);
+    w_put(x2[0], L.m, DP, xr, xi);
+    wave_lds_fence();
+    auto hptr = [&](int i) -> const T * { return a.Ehs + (sb0 + nsub - 1 - i) * mat; };
+    auto nptr = [&](int i) -> const T * {
+      return has_nu ? a.nu + (sb0 + nsub - 1 - i) * set : a.psi0;  // psi0: finite placeholder
+    };
+    w_pipeline<T, DP>(L, nsub - 1, hptr, nptr, [&](int i, const T (&r)[2 * KC], T nr, T ni) {
+      T sr, si;
+      w_dot<T, DP>(L, r, x2[cur], sr, si);
+      xr += sr + (has_nu ? nr : (T)0);
+      xi += si + (has_nu ? ni : (T)0);
+      w_put(x2[cur ^ 1], L.m, DP, xr, xi);
+      w_put(xb[nsub - 2 - i], L.m, DP, xr, xi);
+      cur ^= 1;
+      wave_lds_fence();
+    });
+  }
+  __syncthreads();
+  if (q >= nsub) return;
+  // ---- sub-block q backwards: lam_buf[j] = lambda_{j+1}
+  const int a0 = start + q * SUB16, e0 = min(end, a0 + SUB16);
+  T xr = xb[q][L.m], xi = xb[q][DP + L.m];
+  cur = 0;
+  w_put(x2[0], L.m, DP, xr, xi);
+  wave_lds_fence();
+  const T wgt = a.pw ? a.pw[L.m] : (T)0;
+  auto dptr = [&](int i) -> const T * { return a.Dh + (e0 - 1 - i) * mat; };
+  auto pptr = [&](int i) -> const T * { return a.psi_buf + (long)(e0 - 1 - i) * set; };
+  w_pipeline<T, DP>(L, e0 - 1 - a0, dptr, pptr, [&](int i, const T (&r)[2 * KC], T pr, T pi) {
+    const int j = e0 - 1 - i;
+    T *lb = a.lam_buf + (long)j * set;
+    lb[L.o] = xr;  // lambda_{j+1}
+    lb[L.oi] = xi;
+    T sr, si;
+    w_dot<T, DP>(L, r, x2[cur], sr, si);
+    xr += sr + (j >= 1 ? wgt * pr : (T)0);
+    xi += si + (j >= 1 ? wgt * pi : (T)0);
+    w_put(x2[cur ^ 1], L.m, DP, xr, xi);
+    cur ^= 1;
+    wave_lds_fence();
+  });
+  T *lb = a.lam_buf + (long)a0 * set;
+  lb[L.o] = xr;
+  lb[L.oi] = xi;
+}
+
 template <typename T> bool wave_sweep_ok(int dp, int S) {
   return (dp == 16 && S * dp <= 64) || (dp == 32 && S * dp <= 64);
 }
@@ -340,20 +528,33 @@ template <typename T, int DP> hipError_t w_launch(int which, const SweepArgs<T> 
   const unsigned S = (unsigned)a.S;
   switch (which) {
     case 0: hipLaunchKernelGGL((k_wF2<T, DP>), dim3(1, S), dim3(64), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((k_wF3<T, DP>), dim3(a.nb, S), dim3(64), 0, st, a); break;
+    case 1:
+      if (DP == 16 && a.Es)
+        hipLaunchKernelGGL((k_wF3s<T, DP>), dim3(a.nb, S), dim3(64 * (a.L / SUB16)), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_wF3<T, DP>), dim3(a.nb, S), dim3(64), 0, st, a);
+      break;
     case 2:
       if (a.fuse_cost)
         hipLaunchKernelGGL((k_wB2<T, DP>), dim3(a.S + a.npart), dim3(64), 0, st, a);
       else
         hipLaunchKernelGGL((k_wB2<T, DP>), dim3(1, S), dim3(64), 0, st, a);
       break;
-    default: hipLaunchKernelGGL((k_wB3<T, DP>), dim3(a.nb, S), dim3(64), 0, st, a); break;
+    default:
+      if (DP == 16 && a.Es)
+        hipLaunchKernelGGL((k_wB3s<T, DP>), dim3(a.nb, S), dim3(64 * (a.L / SUB16)), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_wB3<T, DP>), dim3(a.nb, S), dim3(64), 0, st, a);
+      break;
   }
   return hipGetLastError();
 }
 
 template <typename T> hipError_t launch_wave_sweep(int which, const SweepArgs<T> &a, hipStream_t st) {
   if (!a.Dh || !a.Eh) return hipErrorInvalidValue;
+  if (a.Es && (a.dp != 16 || !a.Ehs || a.L % SUB16 || a.L > WSPLIT_MAX * SUB16 ||
+               (a.pw && !a.nu)))
+    return hipErrorInvalidValue;
   if (a.dp == 16) return w_launch<T, 16>(which, a, st);
   if (a.dp == 32) return w_launch<T, 32>(which, a, st);
   return hipErrorInvalidValue;

@@ -99,6 +99,9 @@ struct qoc_handle {
   void *pw = nullptr;         // dp, a_pen / S * w
   void *X = nullptr, *Qa = nullptr, *Qb = nullptr;  // N x 2 dp^2 each
   void *Eh = nullptr;  // nb x 2 dp^2: E_b^H for the single-wavefront sweeps
+  // padded d 16, L a multiple of SUB16 above it: sub-block products, their
+  // ^H (ceil(N / SUB16) x 2 dp^2 each) and partial penalty costates
+  void *Es = nullptr, *Ehs = nullptr, *nu = nullptr;
   void *Dlev = nullptr;       // levels x N x 2 dp^2
   int levels_alloc = 0;
   void *ckpt = nullptr, *lam_ckpt = nullptr, *mu = nullptr;  // (nb+1) sets
@@ -170,7 +173,8 @@ void dfree(qoc_handle *h, void **p, size_t bytes) {
 void release(qoc_handle *h) {
   void **ptrs[] = {&h->Hf, (void **)&h->H64, (void **)&h->u_dev, (void **)&h->out_dev,
                    (void **)&h->grad_dev, &h->psi0, (void **)&h->psiT64, (void **)&h->w64,
-                   &h->pw, &h->X, &h->Qa, &h->Qb, &h->Eh, &h->Dlev, &h->ckpt, &h->lam_ckpt, &h->mu,
+                   &h->pw, &h->X, &h->Qa, &h->Qb, &h->Eh, &h->Es, &h->Ehs, &h->nu, &h->Dlev,
+                   &h->ckpt, &h->lam_ckpt, &h->mu,
                    &h->psi_buf, &h->lam_buf, (void **)&h->bits,
                    (void **)&h->zinfo, (void **)&h->part, (void **)&h->pn_dev,
                    (void **)&h->sc_dev, &h->adj, (void **)&h->adj_part};
@@ -304,6 +308,13 @@ template <typename T> qoc_status ensure_adjoint(qoc_handle *h, int p, int Rcap, 
   return QOC_OK;
 }
 
+// In-block passes split over sub-blocks of SUB16 steps: padded d 16 on the
+// single-wavefront sweeps, with L a multiple of SUB16 (at most 16 of them).
+template <typename T> bool split_sweeps(const qoc_handle *h) {
+  return h->dp == 16 && qoc::wave_sweep_ok<T>(h->dp, h->S) && h->L > qoc::SUB16 &&
+         h->L % qoc::SUB16 == 0 && h->L <= 16 * qoc::SUB16;
+}
+
 template <typename T>
 qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   const int d = h->d, dp = h->dp, M = h->M, N = h->N, S = h->S;
@@ -329,6 +340,12 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   // state buffers carry kRingSlack elements of padding: the small-d sweeps
   // load fixed-size ring slots that may run past the last state set
   const size_t slack = kRingSlack;
+  if (split_sweeps<T>(h)) {
+    const size_t nsub = ((size_t)N + qoc::SUB16 - 1) / qoc::SUB16;
+    ALLOC(h->Es, nsub * mat * sizeof(T));
+    ALLOC(h->Ehs, nsub * mat * sizeof(T));
+    if (h->has_pen) ALLOC(h->nu, (nsub * set + slack) * sizeof(T));
+  }
   ALLOC(h->ckpt, ((size_t)(h->nb + 1) * set + slack) * sizeof(T));
   ALLOC(h->lam_ckpt, ((size_t)(h->nb + 1) * set + slack) * sizeof(T));
   if (h->has_pen) ALLOC(h->mu, ((size_t)h->nb * set + slack) * sizeof(T));
@@ -534,8 +551,10 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     // maxima kept in `part`, free until the cost kernel), the (p, n) choice
     // and any recompute along the block products
     const qoc::Norm16 nm{h->H64, h->d, h->dt, h->bits, (unsigned long long *)h->part, sel};
+    const bool subs = h->Es && Dh_small;
     const qoc::Pick16<T> pick{nm, (int)qoc::expm16_blocks<T>(N), (const T *)h->Hf, u_dev, M, X,
-                              (T *)h->Dlev, Dh_small};
+                              (T *)h->Dlev, Dh_small, subs ? (T *)h->Es : nullptr,
+                              subs ? (T *)h->Ehs : nullptr};
     if (dp == 16) {
       PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
       HIP_TRY(qoc::launch_expm16<T>((const T *)h->Hf, u_dev, M, N, X, (T *)h->Dlev, Dh_small, nm,
@@ -652,6 +671,9 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   sw.N = N; sw.L = h->L; sw.nb = h->nb; sw.dp = dp; sw.d = h->d; sw.S = S; sw.M = M;
   sw.D = D; sw.E = E; sw.Dh = Dh_small; sw.Eh = Dh_small ? (const T *)h->Eh : nullptr; sw.psi0 = (const T *)h->psi0; sw.ckpt = (T *)h->ckpt;
   sw.psi_buf = (T *)h->psi_buf; sw.lam_ckpt = (T *)h->lam_ckpt; sw.mu = (T *)h->mu;
+  if (h->Es && Dh_small) {  // sub-block products written by the block-product kernel
+    sw.Es = (const T *)h->Es; sw.Ehs = (const T *)h->Ehs; sw.nu = (T *)h->nu;
+  }
   sw.lam_buf = (T *)h->lam_buf; sw.w64 = h->w64; sw.pw = (const T *)h->pw;
   sw.drift_bits = h->bits + 1; sw.psiT64 = h->psiT64; sw.u = u_dev;
   sw.alpha_fid = h->a_fid; sw.alpha_pen = h->a_pen; sw.alpha_amp = h->a_amp;

@@ -86,7 +86,14 @@ template <typename T> unsigned expm16_blocks(int N);
 template <typename T>
 hipError_t launch_expm16(const T *Hf, const double *u, int M, int N, T *X, T *Dlev, T *Dh,
                          const Norm16 &nm, hipStream_t st);
-// Pair choice and recompute inputs for the padded-d-16 block products.
+// Sub-blocks of the padded-d-16 in-block passes: SUB16 consecutive steps
+// (a block of L = k SUB16 steps holds k of them, the last one of a call may
+// be shorter); sub-block s covers steps [s SUB16, min(N, (s + 1) SUB16)).
+constexpr int SUB16 = 8;
+// Pair choice and recompute inputs for the padded-d-16 block products, and
+// the optional sub-block products (Es, Ehs: one matrix minus identity, and
+// its conjugate transpose, per sub-block; null: not written; L must then be
+// a multiple of SUB16).
 template <typename T> struct Pick16 {
   Norm16 nm;  // nm.part null: no choice to make
   int nparts;
@@ -94,6 +101,7 @@ template <typename T> struct Pick16 {
   const double *u;
   int M;
   T *X, *Dlev, *Dh;
+  T *Es, *Ehs;
 };
 // Dh / Eh: optional conjugate transposes of the final D_j / of E_b (null: not written)
 template <typename T>
@@ -107,6 +115,8 @@ template <typename T> struct SweepArgs {
   const T *D;          // N x (2 dp^2): D_j = U_j - I
   const T *E;          // nb x (2 dp^2): block products minus identity
   const T *Dh, *Eh;    // D_j^H, E_b^H (single-wavefront sweeps)
+  const T *Es, *Ehs;   // sub-block products and their ^H (padded d 16; null: not used)
+  T *nu;               // per sub-block partial penalty costate (with Es and a penalty)
   const T *psi0;       // one state set
   T *ckpt;             // (nb+1) state sets: psi at block starts
   T *psi_buf;          // (N+1) state sets: psi_j

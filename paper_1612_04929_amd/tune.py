@@ -9,7 +9,8 @@ are chosen by timing them on the problem itself: for every candidate L a
 handle is built, each sweep is timed in the applicable variants (padded
 d >= 80: per-block workgroups or per-step launches; smaller d: one
 wavefront or a four-wavefront LDS-staged workgroup; FP32 padded d 64 ..
-128 also one 8 d_pad-thread chain workgroup per block) with the library's
+128 also one 8 d_pad-thread chain workgroup per block; padded d 16 also
+longer blocks, whose in-block passes run over sub-blocks) with the library's
 per-phase HIP events, and the L that minimises block products plus the
 best variant of each sweep wins.  Other phases do not depend on these
 choices.
@@ -24,9 +25,13 @@ from .qoc import Problem
 SWEEPS = ["fwd_blocks", "fwd_replay", "bwd_blocks", "bwd_pairs"]
 
 
-def candidate_intervals(N: int):
+def candidate_intervals(N: int, d: int | None = None):
     base = 1 << max(0, round(math.log2(max(1.0, math.sqrt(N)))))
     cands = {max(1, base // 4), max(1, base // 2), base, base * 2}
+    if d is not None and d <= 16:
+        # padded d 16: the in-block passes run over sub-blocks of 8 steps in
+        # parallel, which makes longer blocks worth timing
+        cands.add(min(base * 4, 128))
     return sorted(c for c in cands if c <= max(1, N))
 
 
@@ -43,7 +48,7 @@ def tune(prob, precision="fp32", intervals=None, reps=3, device=0, **kw):
     grad = torch.zeros(max(1, prob.M * prob.N), dtype=torch.float64, device=dev)
     st = torch.cuda.current_stream(dev).cuda_stream
     table = []
-    for L in intervals or candidate_intervals(prob.N):
+    for L in intervals or candidate_intervals(prob.N, getattr(prob, "d", None)):
         h = Problem(prob, precision=precision, checkpoint_every=L, device=device, **kw)
         times = {}
         dp = h.info()["d_pad"]

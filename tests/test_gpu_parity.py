@@ -122,6 +122,28 @@ def test_checkpoint_interval_does_not_change_results(L):
     assert e["L"] == L
 
 
+@pytest.mark.parametrize("d,S,N,L,pen,mode,prec", [
+    (16, 4, 203, 16, True, "coherent", "fp32"),    # ragged last block: sub-blocks of 8 and 3
+    (12, 2, 131, 32, True, "incoherent", "fp32"),  # last block of 3 steps (one short sub-block)
+    (16, 4, 250, 64, True, "coherent", "fp32"),
+    (9, 1, 257, 128, True, "coherent", "fp32"),    # 16 sub-blocks a block, last block one step
+    (16, 3, 100, 32, False, "coherent", "fp32"),   # no penalty: no partial costates
+    (16, 4, 64, 128, True, "coherent", "fp32"),    # one block shorter than L
+    (16, 2, 90, 32, True, "coherent", "fp64"),
+])
+def test_split_in_block_passes(d, S, N, L, pen, mode, prec):
+    # padded d 16 with L a multiple of 8: the in-block passes (forward replay
+    # with the block penalty costate, costate replay) run over sub-blocks of
+    # 8 steps from the sub-block products of the block-product kernel
+    rng = np.random.default_rng(300 + d + N + L)
+    p = workloads.random_problem(rng, d=d, M=2, N=N, S=S, dt=0.2, scale=1.5,
+                                 with_penalty=pen, fid_mode=mode)
+    out, ref, e = compare(f"split_d{d}_S{S}_N{N}_L{L}_{prec}", p, precision=prec,
+                          checkpoint_every=L, sweep=1)
+    check(p, e, precision=prec)
+    assert e["L"] == L
+
+
 @pytest.mark.parametrize("L", [1, 4, 64])
 def test_wide_sweeps_checkpoint_intervals(L):
     # padded d 96: per-step launches of the sweeps, ragged last block, penalty
