@@ -533,27 +533,33 @@ __device__ __forceinline__ void dform_store(int lane, const v4<T> &pr, const v4<
 // exponential pass, chooses (p, n) (workgroup 0 publishes it), and, if the
 // pair differs from the one that pass used, recomputes the exponentials of
 // its own steps before forming their product.
+template <typename T> struct TreeWaves {  // wavefronts per block-product workgroup
+  // FP64: four, so their recompute buffers fit in the product slots
+  static constexpr int value = sizeof(T) == 4 ? 8 : 4;
+};
 template <typename T>
-__global__ __launch_bounds__(256) void k_blockprod_tree16(const T *__restrict__ D, int N, int L,
-                                                          T *E, T *Eh, Pick16<T> pick) {
+__global__ __launch_bounds__(64 * TreeWaves<T>::value) void k_blockprod_tree16(
+    const T *__restrict__ D, int N, int L, T *E, T *Eh, Pick16<T> pick) {
   constexpr int PL = 256, CH = TreeCh<T>::value;
+  constexpr int TW = TreeWaves<T>::value, NT = 64 * TW;
+  static_assert(TW * sizeof(Expm16Lds<T>) <= sizeof(T) * (CH + 1) * 2 * PL, "recompute buffers");
   constexpr int MAXT = 2;  // lds_product<T, 16, 1> tile slots (one used)
   __shared__ __align__(16) T m[CH + 1][2 * PL];  // slot CH: the running product
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long b = blockIdx.x;
   const long start = b * L, end = min((long)N, start + L);
   if (pick.nm.part) {  // uniform
-    __shared__ unsigned long long tred[4];
+    __shared__ unsigned long long tred[TW];
     __shared__ int spn[4];
     __shared__ double ssc[2];
     const Norm16 &nm = pick.nm;
     unsigned long long v = 0ull;
-    for (int i = threadIdx.x; i < pick.nparts; i += 256) v = nm.part[i] > v ? nm.part[i] : v;
+    for (int i = threadIdx.x; i < pick.nparts; i += NT) v = nm.part[i] > v ? nm.part[i] : v;
     v = wave_max(v);
     if (lane == 0) tred[w] = v;
     __syncthreads();
     unsigned long long tb = tred[0];
-    for (int i = 1; i < 4; ++i) tb = tred[i] > tb ? tred[i] : tb;
+    for (int i = 1; i < TW; ++i) tb = tred[i] > tb ? tred[i] : tb;
     if (w == 0)
       select_pn(__longlong_as_double((long long)tb), nm.dt, nm.sel.tol, nm.sel.n_cap,
                 nm.sel.p_cap, nm.sel.fixed_p, nm.sel.fixed_n, spn, ssc);
@@ -571,7 +577,7 @@ __global__ __launch_bounds__(256) void k_blockprod_tree16(const T *__restrict__ 
     if (p != (used & 0xffff) || n != (used >> 16)) {  // uniform: redo this block's steps
       Expm16Lds<T> &S = reinterpret_cast<Expm16Lds<T> *>(&m[0][0])[w];
       const T sc = (T)ssc[0];
-      for (long j = start + w; j < end; j += 4)
+      for (long j = start + w; j < end; j += TW)
         expm16_step<T, false>(j, p, n, sc, pick.Hf, pick.u, pick.M, N, pick.X, pick.Dlev,
                               pick.Dh, nm, S.x[0], S.x[1], S.t[0], S.t[1]);
       __threadfence_block();
@@ -585,7 +591,7 @@ __global__ __launch_bounds__(256) void k_blockprod_tree16(const T *__restrict__ 
   auto store_subs = [&](long c0, int cnt) {
     const int ns = (cnt + SUB16 - 1) / SUB16;
     const long s0 = c0 / SUB16;
-    for (int e = threadIdx.x; e < ns * PL; e += 256) {
+    for (int e = threadIdx.x; e < ns * PL; e += NT) {
       const int q = e / PL, o = e - q * PL, r = o >> 4, c = o & 15;
       const T *src = m[q * SUB16];
       T *es = pick.Es + (s0 + q) * 2 * PL, *eh = pick.Ehs + (s0 + q) * 2 * PL;
@@ -604,22 +610,22 @@ __global__ __launch_bounds__(256) void k_blockprod_tree16(const T *__restrict__ 
       const V *src = reinterpret_cast<const V *>(D + c0 * 2 * PL);
       V *dst = reinterpret_cast<V *>(&m[0][0]);
       const int nv = cnt * 2 * PL / VN;
-      // eight 16-byte loads in flight per lane before the LDS stores
-      int e = threadIdx.x;
-      for (; e + 7 * 256 < nv; e += 8 * 256) {
+      // eight 16-byte loads in flight per lane before the LDS stores (at a
+      // clamped index, the stores masked: no load under a condition)
+      for (int e = threadIdx.x; e < nv; e += 8 * NT) {
         V t[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) t[q] = src[e + q * 256];
+        for (int q = 0; q < 8; ++q) t[q] = src[min(e + q * NT, nv - 1)];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) dst[e + q * 256] = t[q];
+        for (int q = 0; q < 8; ++q)
+          if (e + q * NT < nv) dst[e + q * NT] = t[q];
       }
-      for (; e < nv; e += 256) dst[e] = src[e];
     }
     __syncthreads();
     bool stored = !subs;
     for (int stride = 1; stride < cnt; stride *= 2) {
       const int npair = (cnt - stride + 2 * stride - 1) / (2 * stride);
-      for (int q = w; q < npair; q += 4) {
+      for (int q = w; q < npair; q += TW) {
         T *B = m[q * 2 * stride], *A = m[q * 2 * stride + stride];
         v4<T> cr[MAXT], ci[MAXT];
         lds_product<T, 16, 1>(A, A + PL, B, B + PL, cr, ci);
@@ -633,7 +639,7 @@ __global__ __launch_bounds__(256) void k_blockprod_tree16(const T *__restrict__ 
     }
     if (!stored) store_subs(c0, cnt);  // a chunk of at most half a sub-block
     if (c0 == start) {  // uniform: the first chunk's product starts E
-      for (int e = threadIdx.x; e < 2 * PL; e += 256) m[CH][e] = m[0][e];
+      for (int e = threadIdx.x; e < 2 * PL; e += NT) m[CH][e] = m[0][e];
     } else if (w == 0) {  // E <- C + E + C E, C the later chunk
       T *C = m[0], *R = m[CH];
       v4<T> cr[MAXT], ci[MAXT];
@@ -643,9 +649,9 @@ __global__ __launch_bounds__(256) void k_blockprod_tree16(const T *__restrict__ 
     __syncthreads();
   }
   const T *R = m[CH];
-  for (int e = threadIdx.x; e < 2 * PL; e += 256) E[b * 2 * PL + e] = R[e];
+  for (int e = threadIdx.x; e < 2 * PL; e += NT) E[b * 2 * PL + e] = R[e];
   if (Eh) {
-    for (int e = threadIdx.x; e < PL; e += 256) {
+    for (int e = threadIdx.x; e < PL; e += NT) {
       const int r = e >> 4, c = e & 15;
       Eh[b * 2 * PL + e] = R[c * 16 + r];
       Eh[b * 2 * PL + PL + e] = -R[PL + c * 16 + r];
@@ -703,7 +709,8 @@ hipError_t launch_blockprod_small(const T *D, int dp, int N, int L, int nb, T *E
     case 16: {
       Pick16<T> pk{};
       if (pick) pk = *pick;
-      hipLaunchKernelGGL(k_blockprod_tree16<T>, dim3(nb), dim3(256), 0, st, D, N, L, E, Eh, pk);
+      hipLaunchKernelGGL(k_blockprod_tree16<T>, dim3(nb), dim3(64 * TreeWaves<T>::value), 0, st,
+                         D, N, L, E, Eh, pk);
       break;
     }
     case 32:

@@ -333,9 +333,9 @@ template <typename T, int DP> __global__ __launch_bounds__(64) void k_wB3(SweepA
 }
 
 // ------------------------------------------------------------ F3 / B3 split
-// The in-block passes over sub-blocks of SUB16 steps (padded d 16, given
-// the sub-block products Es / Ehs): one workgroup per (block, state) with
-// one wavefront per sub-block.
+// The in-block passes over sub-blocks of SUB16 steps (FP32, padded d 16,
+// given the sub-block products Es / Ehs): one workgroup per (block, state)
+// with one wavefront per sub-block.
 //
 // F3: wavefront 0 walks the sub-block starts, x <- x + Es_q x (at most
 // L / SUB16 - 1 steps); then every wavefront replays its own sub-block
@@ -347,10 +347,29 @@ template <typename T, int DP> __global__ __launch_bounds__(64) void k_wB3(SweepA
 // lambda <- lambda + Ehs_q lambda + nu_q; then every wavefront replays its
 // own sub-block backwards.  The values are those of the sequential passes
 // (the same recursions, regrouped).
-constexpr int WSPLIT_MAX = 16;  // wavefronts per workgroup: L <= 16 SUB16
+//
+// Every loop runs over the SUB16 slots of a sub-block, fully unrolled and
+// guarded by a uniform count, so the matrix slices, states and auxiliary
+// terms sit in registers indexed by constants; each pass's loads are
+// issued before the previous pass (or the workgroup barrier) is waited
+// for, and the states and partial costates a later pass needs are kept in
+// registers or LDS instead of being read back from global memory.
+constexpr int WSPLIT_MAX = 8;  // wavefronts per workgroup: L <= 8 SUB16
+
+template <typename T, int DP> struct WSlices {
+  T r[SUB16][2 * WaveGeo<DP>::KC];
+};
+// slot s < count: slice of matrix base + idx(s) * mat (other slots: slot 0's)
+template <typename T, int DP, class Idx>
+__device__ __forceinline__ void ws_load(WSlices<T, DP> &S, const WLane &L, const T *base,
+                                        int count, Idx idx) {
+  constexpr long mat = 2L * DP * DP;
+#pragma unroll
+  for (int t = 0; t < SUB16; ++t) w_load<T, DP>(base + idx(t < count ? t : 0) * mat, L, S.r[t]);
+}
 
 #define WS_SETUP                                                     \
-  constexpr int KC = WaveGeo<DP>::KC, KQ = WaveGeo<DP>::KQ;          \
+  constexpr int KQ = WaveGeo<DP>::KQ;                                \
   __shared__ __align__(16) T xs[WSPLIT_MAX][2][2 * DP];              \
   __shared__ __align__(16) T xb[WSPLIT_MAX][2 * DP];                 \
   const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;           \
@@ -360,105 +379,105 @@ constexpr int WSPLIT_MAX = 16;  // wavefronts per workgroup: L <= 16 SUB16
   L.kq = lane - L.m * KQ;                                            \
   L.o = ws * DP + L.m;                                               \
   L.oi = (a.S + ws) * DP + L.m;                                      \
-  const long set = 2L * a.S * DP, mat = 2L * DP * DP;                \
+  const long set = 2L * a.S * DP;                                    \
   const int start = b * a.L, end = min(a.N, start + a.L);            \
   const int nsub = (end - start + SUB16 - 1) / SUB16;                \
   const long sb0 = start / SUB16;                                    \
+  const int a0 = start + q * SUB16;                                  \
+  const int cnt = max(0, min(end, a0 + SUB16) - a0);                 \
+  const long a0c = cnt > 0 ? a0 : a.N - 1; /* loads of idle slots */ \
   T(*x2)[2 * DP] = xs[q];                                            \
-  int cur = 0;
+  int cur = 0;                                                       \
+  auto wstep = [&](const T(&r)[2 * WaveGeo<DP>::KC], T &xr, T &xi, T ar, T ai) { \
+    T sr, si;                                                        \
+    w_dot<T, DP>(L, r, x2[cur], sr, si);                             \
+    xr += sr + ar;                                                   \
+    xi += si + ai;                                                   \
+    w_put(x2[cur ^ 1], L.m, DP, xr, xi);                             \
+    cur ^= 1;                                                        \
+    wave_lds_fence();                                                \
+  };                                                                 \
+  auto wset = [&](T xr, T xi) {                                      \
+    cur = 0;                                                         \
+    w_put(x2[0], L.m, DP, xr, xi);                                   \
+    wave_lds_fence();                                                \
+  };
 
 template <typename T, int DP> __global__ __launch_bounds__(64 * WSPLIT_MAX) void k_wF3s(SweepArgs<T> a) {
   WS_SETUP
+  const bool pen = a.pw != nullptr;  // uniform
+  // ---- loads: this sub-block's D_j; for wavefront 0 also the Es of the walk
+  WSlices<T, DP> rd, re;
+  ws_load(rd, L, a.D, cnt, [&](int t) { return a0c + t; });
+  const T *ck = a.ckpt + (long)b * set;
+  T xr = ck[L.o], xi = ck[L.oi];
   // ---- sub-block starts (wavefront 0)
   if (q == 0) {
-    const T *ck = a.ckpt + (long)b * set;
-    T xr = ck[L.o], xi = ck[L.oi];
+    ws_load(re, L, a.Es, nsub - 1, [&](int t) { return sb0 + t; });
     w_put(xb[0], L.m, DP, xr, xi);
-    w_put(x2[0], L.m, DP, xr, xi);
-    wave_lds_fence();
-    auto eptr = [&](int i) -> const T * { return a.Es + (sb0 + i) * mat; };
-    auto dummy = [&](int) -> const T * { return ck; };
-    w_pipeline<T, DP>(L, nsub - 1, eptr, dummy, [&](int i, const T (&r)[2 * KC], T, T) {
-      T sr, si;
-      w_dot<T, DP>(L, r, x2[cur], sr, si);
-      xr += sr;
-      xi += si;
-      w_put(x2[cur ^ 1], L.m, DP, xr, xi);
-      w_put(xb[i + 1], L.m, DP, xr, xi);
-      cur ^= 1;
-      wave_lds_fence();
-    });
+    wset(xr, xi);
+#pragma unroll
+    for (int t = 0; t < SUB16 - 1; ++t)
+      if (t < nsub - 1) {
+        wstep(re.r[t], xr, xi, (T)0, (T)0);
+        w_put(xb[t + 1], L.m, DP, xr, xi);
+      }
   }
+  // the penalty pass's D_j^H, in flight across the barrier
+  WSlices<T, DP> rh;
+  if (pen) ws_load(rh, L, a.Dh, cnt, [&](int t) { return a0c + t; });
+  const T wgt = pen ? a.pw[L.m] : (T)0;
   __syncthreads();
-  // ---- replay of sub-block q, then its partial penalty costate
-  if (q < nsub) {
-    const int a0 = start + q * SUB16, e0 = min(end, a0 + SUB16);
-    T xr = xb[q][L.m], xi = xb[q][DP + L.m];
-    cur = 0;
-    w_put(x2[0], L.m, DP, xr, xi);
+  // ---- replay of sub-block q; its states kept for the penalty pass
+  T pr[SUB16 + 1], pi[SUB16 + 1];
+  if (cnt > 0) {
+    xr = xb[q][L.m];
+    xi = xb[q][DP + L.m];
+    pr[0] = xr;
+    pi[0] = xi;
+    wset(xr, xi);
     a.psi_buf[(long)a0 * set + L.o] = xr;
     a.psi_buf[(long)a0 * set + L.oi] = xi;
-    wave_lds_fence();
-    auto fptr = [&](int i) -> const T * { return a.D + (a0 + i) * mat; };
-    auto dummy = [&](int) -> const T * { return a.psi0; };
-    w_pipeline<T, DP>(L, e0 - a0, fptr, dummy, [&](int i, const T (&r)[2 * KC], T, T) {
-      T sr, si;
-      w_dot<T, DP>(L, r, x2[cur], sr, si);
-      xr += sr;
-      xi += si;
-      w_put(x2[cur ^ 1], L.m, DP, xr, xi);
-      const int j = a0 + i;
-      if (j + 1 < e0 || j + 1 == a.N) {  // wave-uniform
-        a.psi_buf[(long)(j + 1) * set + L.o] = xr;
-        a.psi_buf[(long)(j + 1) * set + L.oi] = xi;
+#pragma unroll
+    for (int t = 0; t < SUB16; ++t)
+      if (t < cnt) {
+        wstep(rd.r[t], xr, xi, (T)0, (T)0);
+        pr[t + 1] = xr;
+        pi[t + 1] = xi;
+        const int j = a0 + t;
+        if (j + 1 < a0 + cnt || j + 1 == a.N) {  // wave-uniform
+          a.psi_buf[(long)(j + 1) * set + L.o] = xr;
+          a.psi_buf[(long)(j + 1) * set + L.oi] = xi;
+        }
       }
-      cur ^= 1;
-      wave_lds_fence();
-    });
-    if (a.pw) {  // uniform
-      __threadfence_block();
-      const T wgt = a.pw[L.m];
-      T mr = (T)0, mi = (T)0;
-      w_put(x2[cur], L.m, DP, mr, mi);
-      wave_lds_fence();
-      auto bptr = [&](int i) -> const T * { return a.Dh + (e0 - 1 - i) * mat; };
-      auto pptr = [&](int i) -> const T * { return a.psi_buf + (long)(e0 - 1 - i) * set; };
-      w_pipeline<T, DP>(L, e0 - a0, bptr, pptr, [&](int i, const T (&r)[2 * KC], T pr, T pi) {
-        const int j = e0 - 1 - i;
-        T sr, si;
-        w_dot<T, DP>(L, r, x2[cur], sr, si);
-        mr += sr + (j >= 1 ? wgt * pr : (T)0);
-        mi += si + (j >= 1 ? wgt * pi : (T)0);
-        w_put(x2[cur ^ 1], L.m, DP, mr, mi);
-        cur ^= 1;
-        wave_lds_fence();
-      });
-      T *nu = a.nu + (sb0 + q) * set;
-      nu[L.o] = mr;
-      nu[L.oi] = mi;
-    }
   }
-  if (!a.pw) return;  // uniform
-  __threadfence_block();
+  if (!pen) return;  // uniform
+  // wavefront 0: the combination's Ehs, in flight during the penalty pass
+  WSlices<T, DP> rc;
+  if (q == 0) ws_load(rc, L, a.Ehs, nsub - 1, [&](int t) { return sb0 + t; });
+  // ---- partial penalty costate of sub-block q, from zero at its end
+  if (cnt > 0) {
+    T mr = (T)0, mi = (T)0;
+    wset(mr, mi);
+#pragma unroll
+    for (int t = SUB16 - 1; t >= 0; --t)
+      if (t < cnt) {
+        const bool on = a0 + t >= 1;
+        wstep(rh.r[t], mr, mi, on ? wgt * pr[t] : (T)0, on ? wgt * pi[t] : (T)0);
+      }
+    w_put(xb[q], L.m, DP, mr, mi);  // the sub-block's start state is no longer needed
+    T *nu = a.nu + (sb0 + q) * set;
+    nu[L.o] = mr;
+    nu[L.oi] = mi;
+  }
   __syncthreads();
   // ---- the block's penalty costate from the sub-blocks' (wavefront 0)
   if (q == 0) {
-    const T *nl = a.nu + (sb0 + nsub - 1) * set;
-    T mr = nl[L.o], mi = nl[L.oi];
-    cur = 0;
-    w_put(x2[0], L.m, DP, mr, mi);
-    wave_lds_fence();
-    auto hptr = [&](int i) -> const T * { return a.Ehs + (sb0 + nsub - 2 - i) * mat; };
-    auto nptr = [&](int i) -> const T * { return a.nu + (sb0 + nsub - 2 - i) * set; };
-    w_pipeline<T, DP>(L, nsub - 1, hptr, nptr, [&](int, const T (&r)[2 * KC], T nr, T ni) {
-      T sr, si;
-      w_dot<T, DP>(L, r, x2[cur], sr, si);
-      mr += sr + nr;
-      mi += si + ni;
-      w_put(x2[cur ^ 1], L.m, DP, mr, mi);
-      cur ^= 1;
-      wave_lds_fence();
-    });
+    T mr = xb[nsub - 1][L.m], mi = xb[nsub - 1][DP + L.m];
+    wset(mr, mi);
+#pragma unroll
+    for (int t = SUB16 - 2; t >= 0; --t)
+      if (t < nsub - 1) wstep(rc.r[t], mr, mi, xb[t][L.m], xb[t][DP + L.m]);
     T *mu = a.mu + (long)b * set;
     mu[L.o] = mr;
     mu[L.oi] = mi;
@@ -467,54 +486,60 @@ template <typename T, int DP> __global__ __launch_bounds__(64 * WSPLIT_MAX) void
 
 template <typename T, int DP> __global__ __launch_bounds__(64 * WSPLIT_MAX) void k_wB3s(SweepArgs<T> a) {
   WS_SETUP
-  const bool has_nu = a.pw != nullptr;
-  // ---- costates at the sub-block ends (wavefront 0), xb[q] = lambda at the
-  // end of sub-block q
+  const bool pen = a.pw != nullptr;  // uniform
+  // ---- loads: this sub-block's D_j^H and states (slots 1 .. cnt - 1), and
+  // for wavefront 0 the Ehs and nu of the walk (sub-blocks 1 .. nsub - 1)
+  // (read unconditionally: without a penalty the states are finite and
+  // weighted by zero, and the states stand in for nu)
+  WSlices<T, DP> rd, re;
+  ws_load(rd, L, a.Dh, cnt, [&](int t) { return a0c + t; });
+  T pr[SUB16], pi[SUB16];
+#pragma unroll
+  for (int t = 0; t < SUB16; ++t) {
+    const long j = a0c + (t < cnt ? t : 0);
+    pr[t] = a.psi_buf[j * set + L.o];
+    pi[t] = a.psi_buf[j * set + L.oi];
+  }
+  T nr[SUB16], ni[SUB16];
+  if (q == 0) {
+    ws_load(re, L, a.Ehs, nsub, [&](int t) { return sb0 + t; });
+    const T *nub = pen ? a.nu : a.psi_buf;
+#pragma unroll
+    for (int t = 0; t < SUB16; ++t) {
+      const long sb = sb0 + (t < nsub ? t : 0);
+      nr[t] = nub[sb * set + L.o];
+      ni[t] = nub[sb * set + L.oi];
+    }
+  }
+  // ---- costates at the sub-block ends (wavefront 0): xb[t] = lambda at
+  // the end of sub-block t
   if (q == 0) {
     const T *c = a.lam_ckpt + (long)(b + 1) * set;
     T xr = c[L.o], xi = c[L.oi];
     w_put(xb[nsub - 1], L.m, DP, xr, xi);
-    w_put(x2[0], L.m, DP, xr, xi);
-    wave_lds_fence();
-    auto hptr = [&](int i) -> const T * { return a.Ehs + (sb0 + nsub - 1 - i) * mat; };
-    auto nptr = [&](int i) -> const T * {
-      return has_nu ? a.nu + (sb0 + nsub - 1 - i) * set : a.psi0;  // psi0: finite placeholder
-    };
-    w_pipeline<T, DP>(L, nsub - 1, hptr, nptr, [&](int i, const T (&r)[2 * KC], T nr, T ni) {
-      T sr, si;
-      w_dot<T, DP>(L, r, x2[cur], sr, si);
-      xr += sr + (has_nu ? nr : (T)0);
-      xi += si + (has_nu ? ni : (T)0);
-      w_put(x2[cur ^ 1], L.m, DP, xr, xi);
-      w_put(xb[nsub - 2 - i], L.m, DP, xr, xi);
-      cur ^= 1;
-      wave_lds_fence();
-    });
+    wset(xr, xi);
+#pragma unroll
+    for (int t = SUB16 - 1; t >= 1; --t)
+      if (t < nsub) {
+        wstep(re.r[t], xr, xi, pen ? nr[t] : (T)0, pen ? ni[t] : (T)0);
+        w_put(xb[t - 1], L.m, DP, xr, xi);
+      }
   }
   __syncthreads();
-  if (q >= nsub) return;
+  if (cnt == 0) return;
   // ---- sub-block q backwards: lam_buf[j] = lambda_{j+1}
-  const int a0 = start + q * SUB16, e0 = min(end, a0 + SUB16);
   T xr = xb[q][L.m], xi = xb[q][DP + L.m];
-  cur = 0;
-  w_put(x2[0], L.m, DP, xr, xi);
-  wave_lds_fence();
-  const T wgt = a.pw ? a.pw[L.m] : (T)0;
-  auto dptr = [&](int i) -> const T * { return a.Dh + (e0 - 1 - i) * mat; };
-  auto pptr = [&](int i) -> const T * { return a.psi_buf + (long)(e0 - 1 - i) * set; };
-  w_pipeline<T, DP>(L, e0 - 1 - a0, dptr, pptr, [&](int i, const T (&r)[2 * KC], T pr, T pi) {
-    const int j = e0 - 1 - i;
-    T *lb = a.lam_buf + (long)j * set;
-    lb[L.o] = xr;  // lambda_{j+1}
-    lb[L.oi] = xi;
-    T sr, si;
-    w_dot<T, DP>(L, r, x2[cur], sr, si);
-    xr += sr + (j >= 1 ? wgt * pr : (T)0);
-    xi += si + (j >= 1 ? wgt * pi : (T)0);
-    w_put(x2[cur ^ 1], L.m, DP, xr, xi);
-    cur ^= 1;
-    wave_lds_fence();
-  });
+  wset(xr, xi);
+  const T wgt = pen ? a.pw[L.m] : (T)0;
+#pragma unroll
+  for (int t = SUB16 - 1; t >= 1; --t)
+    if (t < cnt) {
+      const int j = a0 + t;
+      T *lb = a.lam_buf + (long)j * set;
+      lb[L.o] = xr;  // lambda_{j+1}
+      lb[L.oi] = xi;
+      wstep(rd.r[t], xr, xi, wgt * pr[t], wgt * pi[t]);  // j >= 1 here
+    }
   T *lb = a.lam_buf + (long)a0 * set;
   lb[L.o] = xr;
   lb[L.oi] = xi;
@@ -529,10 +554,13 @@ template <typename T, int DP> hipError_t w_launch(int which, const SweepArgs<T> 
   switch (which) {
     case 0: hipLaunchKernelGGL((k_wF2<T, DP>), dim3(1, S), dim3(64), 0, st, a); break;
     case 1:
-      if (DP == 16 && a.Es)
-        hipLaunchKernelGGL((k_wF3s<T, DP>), dim3(a.nb, S), dim3(64 * (a.L / SUB16)), 0, st, a);
-      else
-        hipLaunchKernelGGL((k_wF3<T, DP>), dim3(a.nb, S), dim3(64), 0, st, a);
+      if constexpr (DP == 16 && sizeof(T) == 4) {
+        if (a.Es) {
+          hipLaunchKernelGGL((k_wF3s<T, DP>), dim3(a.nb, S), dim3(64 * (a.L / SUB16)), 0, st, a);
+          break;
+        }
+      }
+      hipLaunchKernelGGL((k_wF3<T, DP>), dim3(a.nb, S), dim3(64), 0, st, a);
       break;
     case 2:
       if (a.fuse_cost)
@@ -541,10 +569,13 @@ template <typename T, int DP> hipError_t w_launch(int which, const SweepArgs<T> 
         hipLaunchKernelGGL((k_wB2<T, DP>), dim3(1, S), dim3(64), 0, st, a);
       break;
     default:
-      if (DP == 16 && a.Es)
-        hipLaunchKernelGGL((k_wB3s<T, DP>), dim3(a.nb, S), dim3(64 * (a.L / SUB16)), 0, st, a);
-      else
-        hipLaunchKernelGGL((k_wB3<T, DP>), dim3(a.nb, S), dim3(64), 0, st, a);
+      if constexpr (DP == 16 && sizeof(T) == 4) {
+        if (a.Es) {
+          hipLaunchKernelGGL((k_wB3s<T, DP>), dim3(a.nb, S), dim3(64 * (a.L / SUB16)), 0, st, a);
+          break;
+        }
+      }
+      hipLaunchKernelGGL((k_wB3<T, DP>), dim3(a.nb, S), dim3(64), 0, st, a);
       break;
   }
   return hipGetLastError();
@@ -552,7 +583,7 @@ template <typename T, int DP> hipError_t w_launch(int which, const SweepArgs<T> 
 
 template <typename T> hipError_t launch_wave_sweep(int which, const SweepArgs<T> &a, hipStream_t st) {
   if (!a.Dh || !a.Eh) return hipErrorInvalidValue;
-  if (a.Es && (a.dp != 16 || !a.Ehs || a.L % SUB16 || a.L > WSPLIT_MAX * SUB16 ||
+  if (a.Es && (a.dp != 16 || sizeof(T) != 4 || !a.Ehs || a.L % SUB16 || a.L > WSPLIT_MAX * SUB16 ||
                (a.pw && !a.nu)))
     return hipErrorInvalidValue;
   if (a.dp == 16) return w_launch<T, 16>(which, a, st);

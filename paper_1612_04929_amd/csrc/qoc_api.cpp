@@ -308,11 +308,12 @@ template <typename T> qoc_status ensure_adjoint(qoc_handle *h, int p, int Rcap, 
   return QOC_OK;
 }
 
-// In-block passes split over sub-blocks of SUB16 steps: padded d 16 on the
-// single-wavefront sweeps, with L a multiple of SUB16 (at most 16 of them).
+// In-block passes split over sub-blocks of SUB16 steps: FP32 chains at
+// padded d 16 on the single-wavefront sweeps, with L a multiple of SUB16
+// (at most 8 of them).
 template <typename T> bool split_sweeps(const qoc_handle *h) {
-  return h->dp == 16 && qoc::wave_sweep_ok<T>(h->dp, h->S) && h->L > qoc::SUB16 &&
-         h->L % qoc::SUB16 == 0 && h->L <= 16 * qoc::SUB16;
+  return sizeof(T) == 4 && h->dp == 16 && qoc::wave_sweep_ok<T>(h->dp, h->S) && h->L > qoc::SUB16 &&
+         h->L % qoc::SUB16 == 0 && h->L <= 8 * qoc::SUB16;
 }
 
 template <typename T>

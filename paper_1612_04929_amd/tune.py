@@ -31,7 +31,7 @@ def candidate_intervals(N: int, d: int | None = None):
     if d is not None and d <= 16:
         # padded d 16: the in-block passes run over sub-blocks of 8 steps in
         # parallel, which makes longer blocks worth timing
-        cands.add(min(base * 4, 128))
+        cands.add(min(base * 4, 64))
     return sorted(c for c in cands if c <= max(1, N))
 
 

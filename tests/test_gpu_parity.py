@@ -125,11 +125,12 @@ def test_checkpoint_interval_does_not_change_results(L):
 @pytest.mark.parametrize("d,S,N,L,pen,mode,prec", [
     (16, 4, 203, 16, True, "coherent", "fp32"),    # ragged last block: sub-blocks of 8 and 3
     (12, 2, 131, 32, True, "incoherent", "fp32"),  # last block of 3 steps (one short sub-block)
-    (16, 4, 250, 64, True, "coherent", "fp32"),
-    (9, 1, 257, 128, True, "coherent", "fp32"),    # 16 sub-blocks a block, last block one step
+    (16, 4, 250, 64, True, "coherent", "fp32"),    # 8 sub-blocks a block, last block of 58
+    (9, 1, 257, 64, True, "coherent", "fp32"),     # last block one step (seven idle wavefronts)
     (16, 3, 100, 32, False, "coherent", "fp32"),   # no penalty: no partial costates
-    (16, 4, 64, 128, True, "coherent", "fp32"),    # one block shorter than L
-    (16, 2, 90, 32, True, "coherent", "fp64"),
+    (16, 4, 40, 64, True, "coherent", "fp32"),     # one block shorter than L
+    (16, 2, 77, 128, True, "coherent", "fp32"),    # L above the split's limit: unsplit passes
+    (16, 2, 90, 32, True, "coherent", "fp64"),     # FP64 chains: unsplit passes
 ])
 def test_split_in_block_passes(d, S, N, L, pen, mode, prec):
     # padded d 16 with L a multiple of 8: the in-block passes (forward replay
