@@ -35,15 +35,15 @@ HBM_PEAK = 8.0e12
 
 # HBM bytes per launch (read, written) of the kernel behind a timed phase,
 # from two rocprofv3 PMC runs (FETCH_SIZE, WRITE_SIZE) scaled by the same
-# counters on a 256 MiB device copy (x2.0 and x1.0); the table, commands
+# counters on a 256 MiB device copy (x2.0 and x1.0 to four digits); the table, commands
 # and calibration are in profiles/hbm_traffic_pmc.md.  FP32 chains.
 TRAFFIC = {
-    ("c2_transmon_cnot", "adjoint"): ("k_adjoint16", 15207329, 64000),
-    ("c2_transmon_cnot", "taylor"): ("k_expm16", 618904, 18857632),
-    ("c2_transmon_cnot", "bwd_blocks"): ("k_wB2", 643476, 31744),
-    ("c2_transmon_cnot", "fwd_replay"): ("k_wF3", 35035399, 1056768),
-    ("c3_transmon_cavity", "taylor"): ("k_stage64", 1678776510, 944084993),
-    ("c4_spin_chain", "taylor"): ("k_stage64", 6355262327, 3037389901),
+    ("c2_transmon_cnot", "adjoint"): ("k_adjoint16", 15221175, 64064),
+    ("c2_transmon_cnot", "taylor"): ("k_expm16", 615762, 18857632),
+    ("c2_transmon_cnot", "bwd_blocks"): ("k_wB2", 2860195, 160384),
+    ("c2_transmon_cnot", "fwd_replay"): ("k_wF3s", 36107709, 1184768),
+    ("c3_transmon_cavity", "taylor"): ("k_stage64", 1296467090, 734498176),
+    ("c4_spin_chain", "taylor"): ("k_stage64", 6248054166, 3049751930),
 }
 
 
