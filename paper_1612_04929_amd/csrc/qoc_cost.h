@@ -72,29 +72,41 @@ __device__ inline void lam_wave(const SweepArgs<T> &a, int s, int m, int kq, T &
   const T *psiN = a.psi_buf + (long)N * set;
   const int lane = threadIdx.x & 63;
   double zr = 0.0, zi = 0.0, Finc = 0.0, own_r = 0.0, own_i = 0.0;
-  // every operand is read at a clamped row and masked afterwards (a load
-  // under a lane-dependent condition gets a branch and a wait of its own)
+  // every operand is read at a clamped row (and state) and masked afterwards
+  // (a load under a lane-dependent condition gets a branch and a wait of its
+  // own); the single-wavefront sweeps hold S <= 64 / DP states, so all the
+  // overlaps' loads and wavefront sums are issued together
+  constexpr int SMAX = 64 / DP;
   const int mc = m < d ? m : d - 1;
   const bool on = kq == 0 && m < d;
-  for (int q = 0; q < S; ++q) {
-    const double tr = a.psiT64[((long)q * d + mc) * 2], ti = a.psiT64[((long)q * d + mc) * 2 + 1];
-    const double yr = (double)psiN[q * DP + m], yi = (double)psiN[(S + q) * DP + m];
-    double pr = tr * yr + ti * yi;  // conj(T) psi
-    double pi = tr * yi - ti * yr;
-    pr = on ? pr : 0.0;
-    pi = on ? pi : 0.0;
-    pr = wave_sum(pr);
-    pi = wave_sum(pi);
-    zr += pr;
-    zi += pi;
-    Finc += pr * pr + pi * pi;
-    if (q == s) {
-      own_r = pr;
-      own_i = pi;
-    }
-    if (s == 0 && lane == 0) {
-      a.zinfo[3 + 2 * q] = pr;
-      a.zinfo[4 + 2 * q] = pi;
+  double pr[SMAX], pi[SMAX];
+#pragma unroll
+  for (int q = 0; q < SMAX; ++q) {
+    const int qc = q < S ? q : S - 1;
+    const double tr = a.psiT64[((long)qc * d + mc) * 2], ti = a.psiT64[((long)qc * d + mc) * 2 + 1];
+    const double yr = (double)psiN[qc * DP + m], yi = (double)psiN[(S + qc) * DP + m];
+    pr[q] = on && q < S ? tr * yr + ti * yi : 0.0;  // conj(T) psi
+    pi[q] = on && q < S ? tr * yi - ti * yr : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < SMAX; ++q) {
+    pr[q] = wave_sum(pr[q]);
+    pi[q] = wave_sum(pi[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < SMAX; ++q) {
+    if (q < S) {  // uniform
+      zr += pr[q];
+      zi += pi[q];
+      Finc += pr[q] * pr[q] + pi[q] * pi[q];
+      if (q == s) {
+        own_r = pr[q];
+        own_i = pi[q];
+      }
+      if (s == 0 && lane == 0) {
+        a.zinfo[3 + 2 * q] = pr[q];
+        a.zinfo[4 + 2 * q] = pi[q];
+      }
     }
   }
   zr /= S;
