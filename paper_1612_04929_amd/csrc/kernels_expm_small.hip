@@ -585,9 +585,11 @@ __global__ __launch_bounds__(64 * TreeWaves<T>::value) void k_blockprod_tree16(
     }
   }
   // with sub-block products wanted, chunks hold whole sub-blocks, and the
-  // products of the first tree levels (SUB16 steps) are stored on the way
+  // products of the first tree levels (SUB16 steps) are stored on the way;
+  // a block that fits all CH + 1 slots is one chunk (the running-product
+  // slot is free until its tree is done)
   const bool subs = pick.Es != nullptr;  // uniform
-  const int chunk = subs ? (CH / SUB16) * SUB16 : CH;
+  const int chunk = L <= CH + 1 ? L : (subs ? (CH / SUB16) * SUB16 : CH);
   auto store_subs = [&](long c0, int cnt) {
     const int ns = (cnt + SUB16 - 1) / SUB16;
     const long s0 = c0 / SUB16;
