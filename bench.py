@@ -39,7 +39,7 @@ HBM_PEAK = 8.0e12
 # and calibration are in profiles/hbm_traffic_pmc.md.  FP32 chains.
 TRAFFIC = {
     ("c2_transmon_cnot", "adjoint"): ("k_adjoint16", 15221175, 64064),
-    ("c2_transmon_cnot", "taylor"): ("k_expm16", 615839, 18857632),
+    ("c2_transmon_cnot", "taylor"): ("k_expm16", 615608, 18857632),
     ("c2_transmon_cnot", "bwd_blocks"): ("k_wB2", 2878010, 160384),
     ("c2_transmon_cnot", "fwd_replay"): ("k_wF3s", 36107709, 1184768),
     ("c3_transmon_cavity", "taylor"): ("k_stage64", 1296467090, 734498176),
