@@ -79,6 +79,10 @@ __device__ inline void lam_wave(const SweepArgs<T> &a, int s, int m, int kq, T &
   constexpr int SMAX = 64 / DP;
   const int mc = m < d ? m : d - 1;
   const bool on = kq == 0 && m < d;
+  // this state's target entry and penalty term, read with the overlaps' operands
+  double tr = a.psiT64[((long)s * d + mc) * 2], ti = a.psiT64[((long)s * d + mc) * 2 + 1];
+  const double wm = a.pw ? (double)a.pw[m] : 0.0;
+  const double ysr = (double)psiN[s * DP + m], ysi = (double)psiN[(S + s) * DP + m];
   double pr[SMAX], pi[SMAX];
 #pragma unroll
   for (int q = 0; q < SMAX; ++q) {
@@ -119,14 +123,13 @@ __device__ inline void lam_wave(const SweepArgs<T> &a, int s, int m, int kq, T &
     a.zinfo[2] = F;
   }
   const double cr = (a.fid_mode == 0 ? zr : own_r) / S, ci = (a.fid_mode == 0 ? zi : own_i) / S;
-  double tr = a.psiT64[((long)s * d + mc) * 2], ti = a.psiT64[((long)s * d + mc) * 2 + 1];
   tr = m < d ? tr : 0.0;
   ti = m < d ? ti : 0.0;
   double lr = -a.alpha_fid * (cr * tr - ci * ti);
   double li = -a.alpha_fid * (cr * ti + ci * tr);
   if (a.pw) {
-    lr += (double)a.pw[m] * (double)psiN[s * DP + m];
-    li += (double)a.pw[m] * (double)psiN[(S + s) * DP + m];
+    lr += wm * ysr;
+    li += wm * ysi;
   }
   xr = (T)lr;
   xi = (T)li;
