@@ -89,12 +89,9 @@ __device__ __forceinline__ void w_dot(const WLane &L, const T (&r)[2 * WaveGeo<D
   typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
   constexpr int VN = 16 / sizeof(T);
   const T *xr = xs + L.kq * KC, *xi = xs + DP + L.kq * KC;
+  // each partial sum starts from its first term (an added zero cannot be
+  // dropped by the compiler and would lengthen the chain)
   T pr[WA], pi[WA];
-#pragma unroll
-  for (int q = 0; q < WA; ++q) {
-    pr[q] = 0;
-    pi[q] = 0;
-  }
 #pragma unroll
   for (int k0 = 0; k0 < KC; k0 += VN) {
     const V xv = *reinterpret_cast<const V *>(xr + k0);
@@ -103,8 +100,15 @@ __device__ __forceinline__ void w_dot(const WLane &L, const T (&r)[2 * WaveGeo<D
 #pragma unroll
     for (int e = 0; e < VN; ++e) {
       const int k = k0 + e, q = k % WA;
-      pr[q] += r[k] * xa[e] - r[KC + k] * ya[e];
-      pi[q] += r[k] * ya[e] + r[KC + k] * xa[e];
+      const T tr = r[k] * xa[e] - r[KC + k] * ya[e];
+      const T ti = r[k] * ya[e] + r[KC + k] * xa[e];
+      if (k < WA) {  // compile-time
+        pr[q] = tr;
+        pi[q] = ti;
+      } else {
+        pr[q] += tr;
+        pi[q] += ti;
+      }
     }
   }
   T ar = pr[0], ai = pi[0];
