@@ -113,16 +113,25 @@ __device__ __forceinline__ bool fwd_step(int t, const T (&r)[ChainGeo<T, DP>::FE
   typedef ChainGeo<T, DP> G;
   const int row = t >> 3, g = t & 7;
   const T *xr = x + g * G::KC, *xi = x + DP + g * G::KC;
-  T pr0 = 0, pr1 = 0, pi0 = 0, pi1 = 0;
+  // two partial sums, each started from its first term (an added zero
+  // cannot be dropped by the compiler)
+  T pr0, pr1, pi0, pi1;
 #pragma unroll
   for (int k = 0; k < G::KC; ++k) {
     const T a = xr[k], b = xi[k];
-    if (k & 1) {
-      pr1 += r[k] * a - r[G::KC + k] * b;
-      pi1 += r[k] * b + r[G::KC + k] * a;
+    const T tr = r[k] * a - r[G::KC + k] * b, ti = r[k] * b + r[G::KC + k] * a;
+    if (k == 0) {
+      pr0 = tr;
+      pi0 = ti;
+    } else if (k == 1) {
+      pr1 = tr;
+      pi1 = ti;
+    } else if (k & 1) {
+      pr1 += tr;
+      pi1 += ti;
     } else {
-      pr0 += r[k] * a - r[G::KC + k] * b;
-      pi0 += r[k] * b + r[G::KC + k] * a;
+      pr0 += tr;
+      pi0 += ti;
     }
   }
   const T sr = sum8(pr0 + pr1), si = sum8(pi0 + pi1);
@@ -143,20 +152,16 @@ __device__ __forceinline__ bool adj_step(int t, const T (&r)[ChainGeo<T, DP>::AE
   const int c = t % G::G, s = t / G::G;
   T pr[G::AV], pi[G::AV];
 #pragma unroll
-  for (int e = 0; e < G::AV; ++e) {
-    pr[e] = 0;
-    pi[e] = 0;
-  }
-#pragma unroll
   for (int i = 0; i < G::RS; ++i) {
     const int k = s + i * G::SL;
-    if (k < DP) {
+    if (i == 0 || k < DP) {  // row s < SL <= DP always exists
       const T a = x[k], b = x[DP + k];
 #pragma unroll
       for (int e = 0; e < G::AV; ++e) {
         const T mr = r[(2 * i) * G::AV + e], mi = -r[(2 * i + 1) * G::AV + e];  // conj
-        pr[e] += mr * a - mi * b;
-        pi[e] += mr * b + mi * a;
+        const T tr = mr * a - mi * b, ti = mr * b + mi * a;
+        pr[e] = i == 0 ? tr : pr[e] + tr;
+        pi[e] = i == 0 ? ti : pi[e] + ti;
       }
     }
   }
@@ -168,12 +173,23 @@ __device__ __forceinline__ bool adj_step(int t, const T (&r)[ChainGeo<T, DP>::AE
   lds_barrier();
   bool own = false;
   if (t < DP) {
-    T sr = 0, si = 0;
-#pragma unroll 8
-    for (int q = 0; q < G::SL; ++q) {
-      sr += red[q * DP + t];
-      si += red[(G::SL + q) * DP + t];
+    // the SL slices' partial sums in four interleaved chains
+    static_assert(G::SL % 4 == 0, "slices");
+    T sr4[4], si4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sr4[u] = red[u * DP + t];
+      si4[u] = red[(G::SL + u) * DP + t];
     }
+#pragma unroll
+    for (int q = 4; q < G::SL; q += 4)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sr4[u] += red[(q + u) * DP + t];
+        si4[u] += red[(G::SL + q + u) * DP + t];
+      }
+    const T sr = (sr4[0] + sr4[1]) + (sr4[2] + sr4[3]);
+    const T si = (si4[0] + si4[1]) + (si4[2] + si4[3]);
     or_ = x[t] + sr + aux_r;
     oi = x[DP + t] + si + aux_i;
     y[t] = or_;
