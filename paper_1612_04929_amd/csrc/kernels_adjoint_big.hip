@@ -413,23 +413,38 @@ template <typename T> struct AdjPrep {
   int N, dp, S, R;
 };
 
-// A_j = [lambda_{j+1}], B_j = [psi_j] (dp x R, zero beyond column S); T1, T2 zeroed
+// The element-wise steps below run on a 2-D grid: blockIdx.y (and its
+// multiples) picks the step, blockIdx.x and the thread the element within
+// it, so the index arithmetic is 32-bit and division-light.
+__device__ __forceinline__ int adj_inner() { return blockIdx.x * blockDim.x + threadIdx.x; }
+
+// A_j = [lambda_{j+1}], B_j = [psi_j] (dp x R, zero beyond column S); T1, T2
+// zeroed.  Four consecutive columns per thread (R is a multiple of 16); the
+// state entries are read at a clamped column and masked (no load under a
+// per-lane condition).
 template <typename T> __global__ void k_adj_prep(AdjPrep<T> a) {
-  const long thin = (long)a.dp * a.R;
-  const long total = (long)a.N * 8 * thin;
+  const int thin = a.dp * a.R, per4 = 2 * thin;  // 8 thin blocks, 4 elements a thread
   const long set = 2L * a.S * a.dp;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-       e += (long)gridDim.x * blockDim.x) {
-    const long j = e / (8 * thin), rem = e - j * 8 * thin;
-    const int blk = (int)(rem / thin);  // 0,1: A re/im  2,3: B re/im  4..7: T1, T2
-    const long o = rem - (long)blk * thin;
-    const int m = (int)(o / a.R), c = (int)(o - (long)m * a.R);
-    T v = (T)0;
-    if (blk < 4 && c < a.S) {
-      const T *src = (blk < 2 ? a.lam_buf : a.psi_buf) + j * set;
-      v = src[(long)((blk & 1) ? a.S : 0) * a.dp + (long)c * a.dp + m];
+  const int e4 = adj_inner();
+  if (e4 >= per4) return;
+  const int elem = 4 * e4;
+  const int blk = elem / thin;  // 0,1: A re/im  2,3: B re/im  4..7: T1, T2
+  const int o = elem - blk * thin;
+  const int m = o / a.R, c = o - m * a.R;
+  for (long j = blockIdx.y; j < a.N; j += gridDim.y) {
+    T v[4] = {(T)0, (T)0, (T)0, (T)0};
+    if (blk < 4) {  // uniform over a thread's four columns
+      const T *src = (blk < 2 ? a.lam_buf : a.psi_buf) + j * set + ((blk & 1) ? (long)a.S * a.dp : 0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int cc = c + u < a.S ? c + u : a.S - 1;
+        const T x = src[(long)cc * a.dp + m];
+        v[u] = c + u < a.S ? x : (T)0;
+      }
     }
-    a.scratch[j * a.per + rem] = v;
+    T *dst = a.scratch + j * a.per + elem;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) dst[u] = v[u];
   }
 }
 
@@ -444,28 +459,28 @@ template <typename T> struct AdjCat {
 // row stride KK by k_xbar_batch) and B = I
 template <typename T> __global__ void k_adj_cat(AdjCat<T> a) {
   const int cols = a.mode ? a.dp : a.r;
-  const long total = (long)a.N * a.dp * cols;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-       e += (long)gridDim.x * blockDim.x) {
-    const long j = e / ((long)a.dp * cols);
-    const long rem = e - j * a.dp * cols;
-    const int m = (int)(rem / cols), c = (int)(rem - (long)m * cols);
+  const int e = adj_inner();
+  if (e >= a.dp * cols) return;
+  const int m = e / cols, c = e - m * cols;
+  const long o = (long)m * a.R + c;
+  for (long j = blockIdx.y; j < a.N; j += gridDim.y) {
     T *base = a.scratch + j * a.per;
     T *Ar = base, *Ai = base + a.thin, *Br = base + 2 * a.thin, *Bi = base + 3 * a.thin;
-    const long o = (long)m * a.R + c;
     if (a.mode == 0) {
       const T *T1r = base + 4 * a.thin, *T1i = base + 5 * a.thin;
       const T *T2r = base + 6 * a.thin, *T2i = base + 7 * a.thin;
-      Ar[o + a.r] = T1r[o];
-      Ai[o + a.r] = T1i[o];
-      Br[o + a.r] = Br[o];
-      Bi[o + a.r] = Bi[o];
-      Br[o] = T2r[o];
-      Bi[o] = T2i[o];
+      const T t1r = T1r[o], t1i = T1i[o], br = Br[o], bi = Bi[o], t2r = T2r[o], t2i = T2i[o];
+      Ar[o + a.r] = t1r;
+      Ai[o + a.r] = t1i;
+      Br[o + a.r] = br;
+      Bi[o + a.r] = bi;
+      Br[o] = t2r;
+      Bi[o] = t2i;
     } else {
       const T *Fr = base + 8 * a.thin, *Fi = Fr + a.big;
-      Ar[o] = Fr[(long)m * a.KK + c];
-      Ai[o] = Fi[(long)m * a.KK + c];
+      const T fr = Fr[(long)m * a.KK + c], fi = Fi[(long)m * a.KK + c];
+      Ar[o] = fr;
+      Ai[o] = fi;
       Br[o] = (m == c) ? (T)1 : (T)0;
       Bi[o] = (T)0;
     }
@@ -482,19 +497,17 @@ template <typename T> struct AdjHorn {
 // of the Big region (row stride KK2)
 template <typename T> __global__ void k_adj_horn_init(AdjHorn<T> a) {
   const int w2 = 2 * a.rr;
-  const long total = (long)a.N * a.dp * w2;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-       e += (long)gridDim.x * blockDim.x) {
-    const long j = e / ((long)a.dp * w2);
-    const long rem = e - j * a.dp * w2;
-    const int m = (int)(rem / w2), c = (int)(rem - (long)m * w2);
+  const int e = adj_inner();
+  if (e >= a.dp * w2) return;
+  const int m = e / w2, c = e - m * w2;
+  const bool vb = c < a.rr;
+  const long so = (vb ? 2 * a.thin : 0) + (long)m * a.R + (vb ? c : c - a.rr);
+  const long po = 8 * a.thin + (long)m * a.KK2 + c;
+  for (long j = blockIdx.y; j < a.N; j += gridDim.y) {
     T *base = a.scratch + j * a.per;
-    T *Pr = base + 8 * a.thin, *Pi = Pr + a.big;
-    const bool vb = c < a.rr;
-    const T *src = base + (vb ? 2 * a.thin : 0);
-    const long o = (long)m * a.R + (vb ? c : c - a.rr);
-    Pr[(long)m * a.KK2 + c] = src[o];
-    Pi[(long)m * a.KK2 + c] = src[a.thin + o];
+    const T xr = base[so], xi = base[a.thin + so];
+    base[po] = xr;
+    base[po + a.big] = xi;
   }
 }
 
@@ -522,6 +535,12 @@ template <typename T> __global__ void k_adj_finish(AdjFinish<T> a) {
     const double two_s = a.sc ? 2.0 * a.sc[0] : a.two_s;
     a.grad[e] = two_s * g + reg;
   }
+}
+
+// (elements of one step / 256) x (steps, at most 65535: the kernels loop)
+static dim3 grid2d(long per_step, long N) {
+  const long bx = (per_step + 255) / 256;
+  return dim3((unsigned)(bx < 1 ? 1 : bx), (unsigned)(N < 1 ? 1 : (N > 65535 ? 65535 : N)));
 }
 
 static long grid_for(long total) {
@@ -561,7 +580,7 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
   hipError_t e;
   {
     AdjPrep<T> pr{a.lam_buf, a.psi_buf, sc, per, N, dp, S, R};
-    hipLaunchKernelGGL(k_adj_prep<T>, dim3(grid_for((long)N * 8 * thin)), dim3(256), 0, st, pr);
+    hipLaunchKernelGGL(k_adj_prep<T>, grid2d(2 * thin, N), dim3(256), 0, st, pr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   auto blk = [&](long off, int ld, long plane) {
@@ -613,7 +632,7 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
     if ((e = launch_thin(tb)) != hipSuccess) return e;
     if (2 * r <= dp) {
       AdjCat<T> c{sc, per, thin, big, N, dp, R, r, (int)KK2, 0};
-      hipLaunchKernelGGL(k_adj_cat<T>, dim3(grid_for((long)N * dp * r)), dim3(256), 0, st, c);
+      hipLaunchKernelGGL(k_adj_cat<T>, grid2d((long)dp * r, N), dim3(256), 0, st, c);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       r *= 2;
     } else {
@@ -625,7 +644,7 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
       xs.N = N; xs.dp = dp;
       if ((e = launch_xstore(xs)) != hipSuccess) return e;
       AdjCat<T> c{sc, per, thin, big, N, dp, R, dp, (int)KK2, 1};
-      hipLaunchKernelGGL(k_adj_cat<T>, dim3(grid_for((long)N * dp * dp)), dim3(256), 0, st, c);
+      hipLaunchKernelGGL(k_adj_cat<T>, grid2d((long)dp * dp, N), dim3(256), 0, st, c);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       r = dp;
     }
@@ -634,8 +653,7 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
   const int rr = (r + 15) & ~15;
   {
     AdjHorn<T> hi{sc, per, thin, big, N, dp, R, (int)KK2, rr};
-    hipLaunchKernelGGL(k_adj_horn_init<T>, dim3(grid_for((long)N * dp * 2 * rr)), dim3(256), 0,
-                       st, hi);
+    hipLaunchKernelGGL(k_adj_horn_init<T>, grid2d((long)dp * 2 * rr, N), dim3(256), 0, st, hi);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const BOp<T> Xop{a.X, mat, (long)dp * dp, dp};
