@@ -288,9 +288,10 @@ template <typename T, int DP> __global__ __launch_bounds__(64) void k_wB2(SweepA
   wave_lds_fence();
   const bool has_mu = a.mu != nullptr;
   auto dptr = [&](int i) -> const T * { return a.Eh + (a.nb - 1 - i) * mat; };
-  auto mptr = [&](int i) -> const T * {
-    return has_mu ? a.mu + (long)(a.nb - 1 - i) * set : a.psi0;  // psi0: finite placeholder
-  };
+  // chosen once: without penalties psi0 (finite) stands in, at stride zero
+  const T *mbase = has_mu ? a.mu : a.psi0;
+  const long mstride = has_mu ? set : 0;
+  auto mptr = [&](int i) -> const T * { return mbase + (long)(a.nb - 1 - i) * mstride; };
   w_pipeline<T, DP>(L, a.nb - 1, dptr, mptr, [&](int i, const T (&r)[2 * KC], T mr, T mi) {
     T sr, si;
     w_dot<T, DP>(L, r, xs[cur], sr, si);
