@@ -205,7 +205,9 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n);
  * the same up to rounding order).  which: 0 forward block sweep, 1 forward
  * in-block replay, 2 costate block sweep, 3 costate in-block pass, -1 all.
  * variant: 0 automatic, 1 one workgroup per block (per column for padded
- * d >= 80; a single wavefront for the whole state set where it fits),
+ * d >= 80; a single wavefront for the whole state set where it fits, and
+ * for FP32 at padded d 16 with a block length of 16..64 the in-block passes
+ * as one wavefront per sub-block of 8 steps),
  * 2 one launch per step spread over many workgroups (padded d >= 80),
  * 3 a four-wavefront workgroup per block with the step matrices staged in
  * LDS (padded d <= 64), 4 one workgroup of 8 d_pad threads per block with
