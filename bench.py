@@ -8,7 +8,10 @@ forward sweeps with penalties and fidelity, costate sweeps, and the exact
 per-step derivative contracted into dC/du.  Inputs are resident in HBM
 before the timed region.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--config c2|c3|c4|c1|c5]
+  python bench.py [--steps K] [--warmup W] [--config c4|c3|c2|c1|c5]
+
+The default workload is the 9-spin chain (d=512, M=18, N=1000, S=8), the
+largest single-GPU configuration of the metric's d = 16..512 range.
 
 c5 (256 uneven instances): a step is one optimizer iteration (every
 instance's cost + gradient and an Adam update), replayed from a HIP graph;
@@ -88,6 +91,34 @@ def algorithmic_work(prob, info, phase, calls, precision, steps_timed=1):
     return "hbm", 0.0
 
 
+def path_work(prob, info):
+    """Algorithmic real flops of one whole cost + gradient call, counted per
+    time step as 3 G products of 8 d^3 (the G = p - 1 + n products of the
+    step exponential and 2 G for its exact derivative), 24 d^2 S for the
+    forward, replay and costate sweeps, 8 d^2 M for the gradient overlaps
+    and 4 d^2 (M + 1) for the assembly, twice (true d).  The kernels execute
+    fewer products than 3 G per step (Paterson-Stockmeyer Taylor stages and
+    rank-S factored derivative products), so the whole-path fraction can
+    exceed what the kernels' own MFMA counters show."""
+    d, N, M, S = prob.d, prob.N, prob.M, prob.S
+    G = info["p"] - 1 + info["n"]
+    return N * (3 * G * 8.0 * d ** 3 + 24.0 * d * d * S + 8.0 * d * d * M
+                + 2 * 4.0 * d * d * (M + 1))
+
+
+def executed_work(prob, info, precision="fp32"):
+    """Real flops the kernels execute as matrix products in one call: the
+    Taylor stages (Paterson-Stockmeyer or Horner, as the library plans
+    them), the squarings, the block products and the per-step derivative
+    with factored cotangents (algorithmic_work's adjoint count)."""
+    d, N = prob.d, prob.N
+    pp, nn = info["p"], info["n"]
+    G = ps_products(pp) + nn if info["d_pad"] > 48 else pp - 1 + nn
+    f = N * 8.0 * d ** 3 * G + (N - info["n_blocks"]) * 8.0 * d ** 3
+    _, fa = algorithmic_work(prob, info, "adjoint", 1, precision)
+    return f + fa
+
+
 def ps_products(p):
     """Products of the batched Taylor stage for order p: Paterson-Stockmeyer
     with block s in 2..4 when that beats the p - 1 of Horner (the rule of
@@ -140,6 +171,50 @@ def fp64_torch_path(prob, dev, reps=2):
     dt = (time.perf_counter() - t0) / reps
     return dict(value=prob.N / dt, unit="time-steps/s", ms_per_step=dt * 1e3, reps=reps,
                 F=F, grad=g)
+
+
+def quick_measure(prob, precision, args, tuned=None):
+    """ms per cost + gradient call of one workload and precision (device-
+    resident inputs, args.steps timed calls after args.warmup), with its
+    accuracy against the stored oracle outputs where they exist."""
+    import numpy as np
+    import torch
+    from paper_1612_04929_amd import qoc
+    from paper_1612_04929_amd import tune as qtune
+    dev = torch.device("cuda:0")
+    h = qoc.Problem(prob, precision=precision, device=0,
+                    checkpoint_every=tuned["checkpoint_every"] if tuned else 0)
+    if tuned:
+        qtune.apply(h, tuned)
+    u = torch.from_numpy(np.ascontiguousarray(prob.u)).to(dev)
+    out = torch.zeros(2 + prob.N, dtype=torch.float64, device=dev)
+    grad = torch.zeros(max(1, prob.M * prob.N), dtype=torch.float64, device=dev)
+    st = torch.cuda.current_stream(dev).cuda_stream
+    step = lambda: h.cost_grad_device(u.data_ptr(), out.data_ptr(), grad.data_ptr(), st)
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    info = h.info()
+    h.close()
+    r = dict(workload=prob.name, precision=precision, ms_per_step=ms, value=prob.N / (ms / 1e3),
+             unit="time-steps/s", taylor_p=info["p"], taylor_n=info["n"],
+             checkpoint_every=info["block_len"], bf16x3_classes=info["bf16x3_classes"],
+             flags=info["flags"])
+    golden = os.path.join(ROOT, "tests", "golden", f"{prob.name[:2]}_full_oracle.npz")
+    if os.path.exists(golden):
+        with np.load(golden) as z:
+            g = grad[: prob.M * prob.N].cpu().numpy().reshape(prob.M, prob.N)
+            r["accuracy_vs_oracle"] = dict(
+                dF=abs((1 - float(out[1])) - float(z["F"])),
+                grad_rel=float(np.linalg.norm(g - z["grad"]) / np.linalg.norm(z["grad"])),
+                max_dc=float(np.max(np.abs(out[2:].cpu().numpy() - z["c"]))))
+    log(f"[bench] {prob.name} {precision}: {ms:.3f} ms/call, {r['value']:.4g} time-steps/s")
+    return r
 
 
 def cpu_baseline(prob, seconds):
@@ -317,11 +392,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c4")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-torch-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the bf16x3 and other-workload extra keys")
+    ap.add_argument("--no-fp64-kernels", action="store_true",
+                    help="skip timing this library's FP64-chain kernels")
     ap.add_argument("--streams", type=int, default=4, help="c5: streams per iteration")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the sweep autotuner (checkpoint interval, sweep variants)")
@@ -347,6 +426,7 @@ def main():
     prob = workloads.make_config(args.config)
     log(f"[bench] {prob.name}: d={prob.d} M={prob.M} N={prob.N} S={prob.S} "
         f"precision={args.precision}")
+    from paper_1612_04929_amd import tune as qtune
     tuned = None
     if args.checkpoint_every is not None or args.sweep is not None:
         # a fixed configuration (e.g. the tuned one, for a profiler run
@@ -427,8 +507,13 @@ def main():
     else:
         achieved, peak, unit = units / avg_s / 1e12, peak_of(dom, bound) / 1e12, "TFLOP/s"
     tr = TRAFFIC.get((prob.name, dom)) if args.precision == "fp32" else None
-    roofline = dict(kernel=dom, bound=bound, achieved=achieved, peak=peak, unit=unit,
-                    frac=achieved / peak, traffic=(tr[1] + tr[2]) if tr else None)
+    # padded d <= 32 is latency-bound (launch and dependent-step latency, not
+    # MFMA or HBM): the kernel's rate is reported without a fraction
+    latency = info["d_pad"] <= 32
+    roofline = dict(kernel=dom, bound="latency" if latency else bound, achieved=achieved,
+                    peak=None if latency else peak, unit=unit,
+                    frac=None if latency else achieved / peak,
+                    traffic=(tr[1] + tr[2]) if tr else None)
     if tr:
         roofline["traffic_kernel"] = tr[0]
         roofline["traffic_read_bytes"] = tr[1]
@@ -450,14 +535,56 @@ def main():
                            dt=prob.dt, precision=args.precision, taylor_p=info["p"],
                            taylor_n=info["n"], checkpoint_every=info["block_len"]),
                roofline=roofline)
+    h.close()  # the comparators below allocate handles and tensors of their own
+    golden = os.path.join(ROOT, "tests", "golden", f"{args.config}_full_oracle.npz")
+    if os.path.exists(golden):
+        # stored FP64 oracle outputs of the full workload (written by
+        # tests/golden/make_golden.py, which calls only the oracle)
+        with np.load(golden) as z:
+            gref, Fref, Cref, cref = z["grad"], float(z["F"]), float(z["C"]), z["c"]
+        c_gpu = out[2:].cpu().numpy()
+        res["accuracy_vs_oracle"] = dict(
+            source=os.path.relpath(golden, ROOT), dF=abs((1 - Cfid_gpu) - Fref),
+            dC=abs(C_gpu - Cref), max_dc=float(np.max(np.abs(c_gpu - cref))),
+            grad_rel=float(np.linalg.norm(g_gpu - gref) / np.linalg.norm(gref)))
     if not args.no_cpu_baseline:
         cb, (sample, ref) = cpu_baseline(prob, args.cpu_seconds)
         res["cpu_baseline"] = cb
-        if sample.N == prob.N:
+        if sample.N == prob.N and "accuracy_vs_oracle" not in res:
             gref = ref["grad"]
             res["accuracy_vs_oracle"] = dict(
+                source="oracle.cost_grad (live)",
                 dF=abs((1 - Cfid_gpu) - ref["F"]), dC=abs(C_gpu - ref["C"]),
+                max_dc=float(np.max(np.abs(out[2:].cpu().numpy() - ref["c"]))),
                 grad_rel=float(np.linalg.norm(g_gpu - gref) / np.linalg.norm(gref)))
+    if not args.no_fp64_kernels and args.precision != "fp64":
+        # secondary comparator: this library's own kernels with FP64 chains
+        # (FP64 MFMA), which separates the algorithmic gain from the precision gain
+        h64 = qoc.Problem(prob, precision="fp64", device=0,
+                          checkpoint_every=tuned["checkpoint_every"] if tuned else 0)
+        g64 = torch.zeros_like(grad)
+        o64 = torch.zeros_like(out)
+        run64 = lambda: h64.cost_grad_device(u.data_ptr(), o64.data_ptr(), g64.data_ptr(), stream)
+        run64()
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run64()
+        torch.cuda.synchronize()
+        t64 = (time.perf_counter() - t0) / reps
+        h64.close()
+        res["fp64_own_kernels"] = dict(value=prob.N / t64, unit="time-steps/s",
+                                       ms_per_step=t64 * 1e3, reps=reps)
+    if not args.no_extras:
+        # the same call in the other precision and on the other workloads of
+        # the metric's range (tuned the same way), as extra keys
+        if args.precision == "fp32":
+            res["bf16x3"] = quick_measure(prob, "bf16x3", args, tuned)
+        for name in [c for c in ("c2", "c3") if c != args.config]:
+            q = workloads.make_config(name)
+            tq = None if args.no_tune else qtune.tune(q, precision=args.precision)
+            res.setdefault("other_workloads", {})[name] = quick_measure(q, args.precision, args, tq)
     if not args.no_torch_baseline:
         tb = fp64_torch_path(prob, dev)
         g64 = tb.pop("grad")
@@ -465,6 +592,17 @@ def main():
         tb["grad_rel_vs_this"] = float(np.linalg.norm(g64 - g_gpu) / np.linalg.norm(g64))
         res["fp64_gpu_path"] = tb
         res["speedup_vs_fp64_gpu_path"] = value / tb["value"]
+        torch.cuda.empty_cache()
+    # whole call against the MFMA peak: the per-step algorithmic count
+    # (3 G products) and the products the kernels execute
+    pk = PEAK["fp64" if args.precision == "fp64" else "fp32"]["mfma"]
+    wa, we = path_work(prob, info), executed_work(prob, info, args.precision)
+    res["path_roofline"] = dict(
+        algorithmic_flops=wa, executed_flops=we, ms=ms,
+        achieved_algorithmic_TFLOPs=wa / (ms / 1e3) / 1e12,
+        achieved_executed_TFLOPs=we / (ms / 1e3) / 1e12, peak_TFLOPs=pk / 1e12,
+        frac_algorithmic=None if latency else wa / (ms / 1e3) / pk,
+        frac_executed=None if latency else we / (ms / 1e3) / pk)
     res["kernels"] = kernels
     res["ms_per_step_with_phase_events"] = ms_profiled
     if tuned:

@@ -70,8 +70,24 @@ enum { QOC_FID_COHERENT = 0, QOC_FID_INCOHERENT = 1 };
 /* Bits of *flags_out. */
 enum {
   QOC_WARN_DRIFT = 1,  /* norm drift of the propagated columns above drift_warn */
-  QOC_WARN_TAYLOR = 2  /* a fixed (taylor_p, taylor_n) misses taylor_tol at this
+  QOC_WARN_TAYLOR = 2, /* a fixed (taylor_p, taylor_n) misses taylor_tol at this
                           call's theta_max (the call still uses the fixed pair) */
+  QOC_WARN_PRECISION = 4 /* QOC_BF16X3: the automatic policy ran some product
+                            classes in FP32 (qoc_info.bf16x3_classes) because
+                            the predicted bf16x3 error exceeded its budget */
+};
+
+/* Product classes of the QOC_BF16X3 precision: each class runs as bf16x3
+ * split products (three bf16 MFMA products of hi/lo operand halves, FP32
+ * accumulation) or as FP32 products.  Sec. III: the Taylor series of
+ * eq. 6 on the scaled generator, the squarings that undo the scaling; Sec.
+ * II.B: the reverse pass. */
+enum {
+  QOC_BF3_TAYLOR = 1,     /* Taylor (Horner / Paterson-Stockmeyer) products   */
+  QOC_BF3_SQUARING = 2,   /* the n squarings D <- 2D + D^2                    */
+  QOC_BF3_BLOCKPROD = 4,  /* block products of the blocked two-level scan     */
+  QOC_BF3_ADJOINT = 8,    /* products of the exact per-step derivative        */
+  QOC_BF3_ALL = 15
 };
 
 typedef struct {
@@ -116,6 +132,7 @@ typedef struct {
   int d_pad;                /* device padding of d (multiple of 16)          */
   int flags;                /* warning bits (QOC_WARN_*) of the last call    */
   size_t device_bytes;      /* device memory held by the handle              */
+  int bf16x3_classes;       /* QOC_BF3_* classes that ran bf16x3 products     */
 } qoc_info;
 
 /* Create a handle: validates and copies the problem to device memory.
@@ -200,6 +217,22 @@ qoc_status qoc_taylor_select(double theta, double tol, int *p, int *n);
  * each call checks it against taylor_tol on the device and reports a miss
  * as QOC_WARN_TAYLOR.  Sec. III: one conservative pair for all steps. */
 qoc_status qoc_set_taylor(qoc_handle *h, int p, int n);
+
+/* Product classes (QOC_BF3_* mask, 0..QOC_BF3_ALL) that later calls of a
+ * QOC_BF16X3 handle run as bf16x3 split products, the others in FP32; -1
+ * (the default) chooses per call.  The automatic choice always splits the
+ * per-step derivative's products (they do not feed the states) and splits
+ * the chain classes (Taylor, squarings, block products) only while an
+ * error index of the states stays within the budget that keeps |dF| <=
+ * 1e-5 at any fidelity: the index adds, per step, 2^-17 times the product
+ * of the operand norms of each split chain product times its amplification
+ * by the later squarings (norms from theta_max, n and the squaring levels),
+ * and grows as sqrt(N) over the steps.  Any class left in FP32 by the
+ * automatic choice sets QOC_WARN_PRECISION.  With a fixed (p, n) the index
+ * uses the largest theta the pair admits.  No effect on other precisions.
+ * Returns QOC_ERR_ARG for a mask outside -1..QOC_BF3_ALL.  Sec. III
+ * (truncated Taylor series with scaling and squaring), Sec. II.B. */
+qoc_status qoc_set_bf16x3(qoc_handle *h, int classes);
 
 /* Kernel variant of the sweeps of later calls (a tuning knob; results are
  * the same up to rounding order).  which: 0 forward block sweep, 1 forward

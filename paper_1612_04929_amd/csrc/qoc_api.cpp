@@ -61,6 +61,68 @@ bool taylor_select(double theta, double tol, int *p_out, int *n_out) {
   return true;
 }
 
+// Largest theta whose truncation bound a fixed (p, n) still meets (the
+// bound grows with theta): what a fixed pair admits without a warning.
+double theta_admitted(int p, int n, double tol) {
+  double lo = 0.0, hi = 1.0;
+  while (taylor_bound(hi, p, n) <= tol && hi < 1e6) hi *= 2.0;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (taylor_bound(mid, p, n) <= tol ? lo : hi) = mid;
+  }
+  return lo;
+}
+
+// Error index of the bf16x3 split products in the step propagators: the
+// l2 error they add to the propagated states, up to a calibration factor.
+// A split product (bf16 hi/lo halves, the lo x lo term dropped) errs by
+// about eps = 2^-17 of the product of its operand norms, where an FP32
+// product errs by 2^-24.  Per step, the first Taylor product (X X, |X| =
+// theta / 2^n) is amplified by the n squarings after it (2^n), squaring i
+// (|D^(i)| = min(2, theta 2^(i - n))) by 2^(n - i - 1); a block product
+// (|E| <= 2) errs by 4 eps once per tree level and block.  Independent
+// errors add in quadrature over the N steps (and the N / L blocks).  Only
+// the classes in `cls` count (the FP32 products are the reference).
+// Measured on MI355X, the state error stayed within 0.7 times the index.
+double bf3_error_index(double theta, int n, int N, int L, int cls) {
+  const double eps = std::ldexp(1.0, -17);
+  const double x = std::ldexp(theta, -n);
+  double step = 0.0;
+  if (cls & QOC_BF3_TAYLOR) step += eps * x * x * std::ldexp(1.0, n);
+  if (cls & QOC_BF3_SQUARING)
+    for (int i = 0; i < n; ++i) {
+      const double di = std::min(2.0, std::ldexp(theta, i - n));
+      step += eps * di * di * std::ldexp(1.0, n - i - 1);
+    }
+  double blocks = 0.0;
+  if (cls & QOC_BF3_BLOCKPROD) {
+    int levels = 0;
+    while ((1 << levels) < L) ++levels;
+    blocks = std::sqrt(std::ceil((double)N / L)) * 4.0 * eps * levels;
+  }
+  return std::sqrt((double)N) * step + blocks;
+}
+
+// Classes the automatic bf16x3 policy runs as split products.  Measured on
+// MI355X (transmon-cavity d = 128, N = 5000, theta_max 5.5, n = 5; spin chain
+// d = 512, N = 1000, theta_max 0.81, n = 2; each chain class split alone and
+// all together), the fidelity error stayed within 0.24 |z| times the index
+// and the gradient's relative error within 1.4 times the index, where |z|
+// <= 1 is the final overlap.  The budget 4e-5 therefore keeps |dF| <= 1e-5
+// at any fidelity and the gradient within 1e-3.  The per-step derivative's
+// products do not feed the states or the fidelity and, measured, leave the
+// gradient error at its FP32 level, so they are always split; of the chain
+// classes, all three are split when the index allows, else the Taylor
+// products and squarings, else the Taylor products alone, else none.
+constexpr double kBf3Budget = 4e-5;
+int bf3_auto_classes(double theta, int n, int N, int L) {
+  const int tries[3] = {QOC_BF3_TAYLOR | QOC_BF3_SQUARING | QOC_BF3_BLOCKPROD,
+                        QOC_BF3_TAYLOR | QOC_BF3_SQUARING, QOC_BF3_TAYLOR};
+  for (int cls : tries)
+    if (bf3_error_index(theta, n, N, L, cls) <= kBf3Budget) return cls | QOC_BF3_ADJOINT;
+  return QOC_BF3_ADJOINT;
+}
+
 // Capacity of the device-side (p, n) choice on the small-d path.
 constexpr int kSmallNCap = 16, kSmallPCap = 16;
 // Padding (elements) of the state buffers read by fixed-size prefetch slots.
@@ -78,6 +140,10 @@ struct qoc_handle {
   // problem
   int d = 0, dp = 0, M = 0, N = 0, S = 0, prec = QOC_FP32, fid_mode = 0;
   int bf3 = 0;  // bf16x3 split products in the batched chains (padded d >= 64)
+  int bf3_req = -1;  // classes allowed bf16x3 products (QOC_BF3_* bits), -1 automatic
+  int bf3_used = 0;  // classes that ran bf16x3 products in the last call
+  int bf3_fallback = 0;  // the automatic choice moved some classes to FP32
+  bool capturing = false;  // the current call's stream is capturing a HIP graph
   int last_flags = 0;  // warning bits of the last call
   int sweep_mode[4] = {0, 0, 0, 0};  // per sweep: 0 auto, 1 per-block, 2 per-step launches,
                                      // 3 four-wavefront LDS (small d), 4 chain workgroup
@@ -150,6 +216,12 @@ struct DeviceGuard {
 
 qoc_status dalloc(qoc_handle *h, void **p, size_t bytes) {
   *p = nullptr;
+  if (h->capturing)
+    return fail(QOC_ERR_UNSUPPORTED,
+                "this call needs " + std::to_string(bytes) +
+                    " more bytes of device work space, which cannot be allocated while its "
+                    "stream captures a HIP graph: run one call with the same (p, n) before "
+                    "capturing");
   if (bytes == 0) bytes = 16;
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
@@ -443,7 +515,7 @@ PsPlan ps_plan(int p) {
 
 template <typename T>
 hipError_t taylor_ps(qoc_handle *h, const PsPlan &ps, int p, int nslots, T *X, T *Qa, T *Qb,
-                     T *Dl, long lev, long mat, int N, int dp, hipStream_t st) {
+                     T *Dl, long lev, long mat, int N, int dp, int bf3, hipStream_t st) {
   const int s = ps.s;
   std::vector<double> c(p + s + 1, 0.0);
   {
@@ -479,7 +551,7 @@ hipError_t taylor_ps(qoc_handle *h, const PsPlan &ps, int p, int nslots, T *X, T
     a.nx = s - 1;
   };
   for (int r = 2; r <= s; ++r) {
-    qoc::StageArgs<T> a{P[r - 1], mat, X, mat, P[r], mat, N, dp, (T)1, (T)0, (T)0, (T)0, h->bf3};
+    qoc::StageArgs<T> a{P[r - 1], mat, X, mat, P[r], mat, N, dp, (T)1, (T)0, (T)0, (T)0, bf3};
     if (r == s) {
       // second output: W_Q = B_Q, or W_{Q-1} = B_{Q-1} + c_p Y when s | p
       a.C2 = dest(-1);
@@ -498,7 +570,7 @@ hipError_t taylor_ps(qoc_handle *h, const PsPlan &ps, int p, int nslots, T *X, T
   for (int i = 0; i < H; ++i) {
     const int q = q0 - i;
     qoc::StageArgs<T> a{P[s], mat, dest(i - 1), mat, dest(i), mat, N, dp, (T)1, (T)0, (T)0,
-                        (T)0, h->bf3};
+                        (T)0, bf3};
     B(q, a, false);
     PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
     hipError_t e = qoc::launch_stage<T>(0, a, st);
@@ -593,6 +665,11 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
       p = h->fixed_p;
       n = h->fixed_n;
     } else {
+      if (h->capturing)
+        return fail(QOC_ERR_UNSUPPORTED,
+                    "choosing (p, n) per call reads theta_max back to the host, which a stream "
+                    "that captures a HIP graph cannot do: fix the pair with qoc_set_taylor "
+                    "before capturing");
       unsigned long long tb = 0;
       HIP_TRY(hipMemcpyAsync(&tb, h->bits, sizeof(tb), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
@@ -619,6 +696,21 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
       return s;
     h->last_p = p;
     h->last_n = n;
+    // product classes that run as bf16x3 split products this call
+    int cls = 0;
+    h->bf3_fallback = 0;
+    if (h->bf3) {
+      if (h->bf3_req >= 0) {
+        cls = h->bf3_req;
+      } else {
+        const double th = h->fixed_p >= 2 ? theta_admitted(p, n, h->tol) : h->last_theta;
+        cls = bf3_auto_classes(th, n, N, h->L);
+        h->bf3_fallback = cls != QOC_BF3_ALL;
+      }
+    }
+    h->bf3_used = cls;
+    const int bT = (cls & QOC_BF3_TAYLOR) ? 1 : 0, bS = (cls & QOC_BF3_SQUARING) ? 1 : 0,
+              bB = (cls & QOC_BF3_BLOCKPROD) ? 1 : 0;
     T *Dl = (T *)h->Dlev;
     // ---- step exponentials: Horner in D-form, then squarings
     const double sc = std::ldexp(h->dt, -n);
@@ -628,23 +720,23 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
                                       use_ps ? nullptr : Qa, st));
     }
     if (use_ps) {
-      HIP_TRY(taylor_ps<T>(h, ps, p, n + 1 + ps_extra, X, Qa, Qb, Dl, lev, mat, N, dp, st));
+      HIP_TRY(taylor_ps<T>(h, ps, p, n + 1 + ps_extra, X, Qa, Qb, Dl, lev, mat, N, dp, bT, st));
     } else {
       T *cur = Qa, *nxt = Qb;
       for (int k = p - 1; k >= 2; --k) {
         qoc::StageArgs<T> a{X, mat, cur, mat, nxt, mat, N, dp, (T)(1.0 / k), (T)0, (T)0, (T)1,
-                            h->bf3};
+                            bT};
         PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
         HIP_TRY(qoc::launch_stage<T>(0, a, st));
         std::swap(cur, nxt);
       }
-      qoc::StageArgs<T> a{X, mat, cur, mat, Dl, mat, N, dp, (T)1, (T)0, (T)0, (T)0, h->bf3};
+      qoc::StageArgs<T> a{X, mat, cur, mat, Dl, mat, N, dp, (T)1, (T)0, (T)0, (T)0, bT};
       PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
       HIP_TRY(qoc::launch_stage<T>(0, a, st));
     }
     for (int i = 0; i < n; ++i) {
       qoc::StageArgs<T> a{Dl + i * lev, mat, Dl + i * lev, mat, Dl + (i + 1) * lev, mat, N, dp,
-                          (T)1, (T)0, (T)2, (T)0, h->bf3};
+                          (T)1, (T)0, (T)2, (T)0, bS};
       PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
       HIP_TRY(qoc::launch_stage<T>(0, a, st));
     }
@@ -656,7 +748,7 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     for (int span = 2; span <= h->L; span <<= 1) {
       const long pairs = cnt / 2;
       qoc::StageArgs<T> a{in + mat, 2 * mat, in, 2 * mat, outb, mat, (int)pairs, dp,
-                          (T)1, (T)1, (T)1, (T)0, h->bf3};
+                          (T)1, (T)1, (T)1, (T)0, bB};
       PhaseTimer tm(h, QOC_PHASE_BLOCKPROD, st);
       HIP_TRY(qoc::launch_stage<T>(0, a, st));
       tm.done();
@@ -757,7 +849,7 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     ad.scratch_elems = qoc::adjoint_scratch_elems<T>(dp, ad.p, ad.Rcap); ad.grad = grad_dev;
     ad.part = h->adj_part;
     ad.xbar = Qa;  // the Taylor work space is free once the sweeps are done
-    ad.bf3 = h->bf3;
+    ad.bf3 = (h->bf3_used & QOC_BF3_ADJOINT) ? 1 : 0;
     ad.with_total = total_in_adjoint ? 1 : 0;
     ad.total = qoc::total_args(sw);
     if (!big && qoc::adjoint16_ok<T>(dp, ad.p))
@@ -798,7 +890,8 @@ qoc_status finish_diag(qoc_handle *h, hipStream_t st, int *flags) {
   h->last_theta = th;
   h->last_drift = dr;
   h->last_flags = ((dr > h->drift_warn) ? QOC_WARN_DRIFT : 0) |
-                  ((dev_pn && pn[2] == 2) ? QOC_WARN_TAYLOR : 0);
+                  ((dev_pn && pn[2] == 2) ? QOC_WARN_TAYLOR : 0) |
+                  (h->bf3_fallback ? QOC_WARN_PRECISION : 0);
   if (flags) *flags = h->last_flags;
   if (h->prof) return drain_pending(h);
   return QOC_OK;
@@ -847,6 +940,14 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n) {
     return fail(QOC_ERR_ARG, "p must be 0 (automatic) or in [2, 64] with n in [0, 60]");
   h->fixed_p = p;
   h->fixed_n = p ? n : 0;
+  return QOC_OK;
+}
+
+qoc_status qoc_set_bf16x3(qoc_handle *h, int classes) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  if (classes < -1 || classes > QOC_BF3_ALL)
+    return fail(QOC_ERR_ARG, "classes must be -1 (automatic) or a mask of QOC_BF3_* bits");
+  h->bf3_req = classes;
   return QOC_OK;
 }
 
@@ -1047,7 +1148,16 @@ qoc_status qoc_cost_grad_device(qoc_handle *h, const double *u_dev, double *out_
   DeviceGuard g(h->device);
   if (!g.ok) return fail(QOC_ERR_DEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)stream;
-  return run_any(h, h->M > 0 ? u_dev : h->u_dev, out_dev, grad_dev, st, true);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(st, &cs));
+  h->capturing = cs != hipStreamCaptureStatusNone;
+  if (h->capturing && h->prof)
+    return fail(QOC_ERR_UNSUPPORTED,
+                "per-phase profiling records events that a captured graph cannot hold: "
+                "disable qoc_profile_enable before capturing");
+  const qoc_status s = run_any(h, h->M > 0 ? u_dev : h->u_dev, out_dev, grad_dev, st, true);
+  h->capturing = false;
+  return s;
 }
 
 qoc_status qoc_cost_grad_batched(int B, qoc_handle *const *hs, const double *const *u_dev,
@@ -1093,7 +1203,8 @@ qoc_status qoc_get_info(const qoc_handle *hc, qoc_info *info) {
       h->last_n = pn[1];
     }
     h->last_flags = ((h->last_drift > h->drift_warn) ? QOC_WARN_DRIFT : 0) |
-                    (((small_path || h->fixed_p >= 2) && pn[2] == 2) ? QOC_WARN_TAYLOR : 0);
+                    (((small_path || h->fixed_p >= 2) && pn[2] == 2) ? QOC_WARN_TAYLOR : 0) |
+                    (h->bf3_fallback ? QOC_WARN_PRECISION : 0);
   }
   info->flags = h->last_flags;
   info->p = h->last_p;
@@ -1104,6 +1215,7 @@ qoc_status qoc_get_info(const qoc_handle *hc, qoc_info *info) {
   info->n_blocks = h->nb;
   info->d_pad = h->dp;
   info->device_bytes = h->bytes;
+  info->bf16x3_classes = h->bf3_used;
   return QOC_OK;
 }
 

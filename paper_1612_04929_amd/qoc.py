@@ -19,7 +19,9 @@ LIB_PATH = os.path.join(HERE, "libqoc.so")
 QOC_FP64, QOC_FP32, QOC_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": QOC_FP64, "fp32": QOC_FP32, "bf16x3": QOC_BF16X3}
 QOC_FID_COHERENT, QOC_FID_INCOHERENT = 0, 1
-QOC_WARN_DRIFT, QOC_WARN_TAYLOR = 1, 2
+QOC_WARN_DRIFT, QOC_WARN_TAYLOR, QOC_WARN_PRECISION = 1, 2, 4
+QOC_BF3_TAYLOR, QOC_BF3_SQUARING, QOC_BF3_BLOCKPROD, QOC_BF3_ADJOINT = 1, 2, 4, 8
+QOC_BF3_ALL = 15
 PHASES = ["norm", "assemble", "taylor", "blockprod", "fwd_blocks", "fwd_replay", "cost",
           "bwd_blocks", "bwd_pairs", "adjoint"]
 STATUS = {0: "QOC_OK", -1: "QOC_ERR_ARG", -2: "QOC_ERR_SHAPE", -3: "QOC_ERR_NOT_HERMITIAN",
@@ -28,7 +30,7 @@ STATUS = {0: "QOC_OK", -1: "QOC_ERR_ARG", -2: "QOC_ERR_SHAPE", -3: "QOC_ERR_NOT_
 EXPORTS = ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
            "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
            "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
-           "qoc_destroy",
+           "qoc_set_bf16x3", "qoc_destroy",
            "qoc_status_string",
            "qoc_last_error", "qoc_version"]
 
@@ -48,7 +50,8 @@ class Desc(C.Structure):
 class Info(C.Structure):
     _fields_ = [("p", C.c_int), ("n", C.c_int), ("theta_max", C.c_double),
                 ("norm_drift", C.c_double), ("block_len", C.c_int), ("n_blocks", C.c_int),
-                ("d_pad", C.c_int), ("flags", C.c_int), ("device_bytes", C.c_size_t)]
+                ("d_pad", C.c_int), ("flags", C.c_int), ("device_bytes", C.c_size_t),
+                ("bf16x3_classes", C.c_int)]
 
 
 class QocError(RuntimeError):
@@ -93,6 +96,7 @@ def load(path: str = LIB_PATH):
                                       C.POINTER(C.c_int)]
     lib.qoc_set_taylor.argtypes = [vp, C.c_int, C.c_int]
     lib.qoc_set_sweep.argtypes = [vp, C.c_int, C.c_int]
+    lib.qoc_set_bf16x3.argtypes = [vp, C.c_int]
     lib.qoc_destroy.argtypes = [vp]
     lib.qoc_destroy.restype = None
     for f in ["qoc_status_string", "qoc_last_error", "qoc_version"]:
@@ -100,7 +104,8 @@ def load(path: str = LIB_PATH):
     lib.qoc_status_string.argtypes = [C.c_int]
     for f in ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
               "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
-              "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep"]:
+              "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
+              "qoc_set_bf16x3"]:
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -204,12 +209,18 @@ class Problem:
         workgroups for padded d <= 64)."""
         _check(load().qoc_set_sweep(self._h, int(which), int(variant)))
 
+    def set_bf16x3(self, classes: int):
+        """Product classes (QOC_BF3_* mask) run as bf16x3 split products by
+        a bf16x3 handle; -1 restores the automatic choice."""
+        _check(load().qoc_set_bf16x3(self._h, int(classes)))
+
     def info(self):
         inf = Info()
         _check(load().qoc_get_info(self._h, C.byref(inf)))
         return dict(p=inf.p, n=inf.n, theta_max=inf.theta_max, norm_drift=inf.norm_drift,
                     block_len=inf.block_len, n_blocks=inf.n_blocks, d_pad=inf.d_pad,
-                    flags=inf.flags, device_bytes=inf.device_bytes)
+                    flags=inf.flags, device_bytes=inf.device_bytes,
+                    bf16x3_classes=inf.bf16x3_classes)
 
     def profile_enable(self, on=True):
         _check(load().qoc_profile_enable(self._h, 1 if on else 0))

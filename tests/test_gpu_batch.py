@@ -65,3 +65,40 @@ def test_graph_replays_equal_eager_iterations():
     assert np.allclose(ca, cb, rtol=1e-12, atol=1e-12)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_full_length_instances_match_stored_oracle(precision):
+    """Full-length instances of the 256-instance workload (the largest d, the
+    longest N and the largest d^3 N; tests/golden/c5_*_oracle.npz, written
+    by make_golden.py --c5 from the oracle alone) through a Batch with its
+    fixed (p, n), element by element: fidelity, every c_j (zero here), the
+    whole gradient."""
+    import glob
+    import os
+    from paper_1612_04929_amd.batch import Batch
+    here = os.path.dirname(os.path.abspath(__file__))
+    files = sorted(glob.glob(os.path.join(here, "golden", "c5_*_oracle.npz")))
+    assert len(files) >= 3
+    allp = workloads.config5()
+    idx = [int(os.path.basename(f)[3:6]) for f in files]
+    probs = [allp[i] for i in idx]
+    say(f"[batch] full-length {precision}: " + ", ".join(f"d{p.d}/N{p.N}/M{p.M}" for p in probs))
+    b = Batch(probs, precision=precision, streams=2)
+    b.cost_grad()
+    torch.cuda.synchronize()
+    tF, tG = (1e-6, 1e-4) if precision == "fp32" else (1e-5, 1e-3)
+    for f, i, p in zip(files, range(len(probs)), probs):
+        with np.load(f) as z:
+            ref = {k: z[k] for k in z.files}
+        assert (p.d, p.M, p.N) == (int(ref["d"]), int(ref["M"]), int(ref["N"]))
+        dF = abs((1 - float(b.out[i][1])) - float(ref["F"]))
+        g = b.grad[i][: p.M * p.N].cpu().numpy().reshape(p.M, p.N)
+        c = b.out[i][2:].cpu().numpy()
+        err, nrm = float(np.linalg.norm(g - ref["grad"])), float(np.linalg.norm(ref["grad"]))
+        say(f"[batch] {p.name} d={p.d} N={p.N} pn={b.pn[i]} dF={dF:.2e} "
+            f"grad_rel={err / max(nrm, 1e-300):.2e} |grad|={nrm:.2e}")
+        assert dF <= tF
+        assert err <= tG * nrm + 1e-9
+        assert np.max(np.abs(c - ref["c"])) <= 2e-6
+    b.close()

@@ -51,6 +51,7 @@ def compare(name, prob, precision="fp32", oracle_out=None, sweep=None, **kw):
         dc=float(np.max(np.abs(out["c"] - ref["c"]))) if prob.N else 0.0,
         grad_rel=rel(out["grad"], ref["grad"]) if prob.M else 0.0,
         psiN=float(np.max(np.abs(fwd["psiN"] - ref["psiN"]))),
+        psiN_l2=float(np.max(np.linalg.norm(fwd["psiN"] - ref["psiN"], axis=1))),
         dF_fwd=abs((1 - fwd["C_fid"]) - ref["F"]),
         p=out["p"], n=out["n"], theta=out["theta_max"], theta_ref=ref["theta_max"],
         drift=out["norm_drift"], L=out["block_len"], nb=out["n_blocks"])
@@ -64,6 +65,18 @@ def compare(name, prob, precision="fp32", oracle_out=None, sweep=None, **kw):
     return out, ref, errs
 
 
+def psi_bound(prob, precision):
+    """Bound on the l2 error of each final state psi_N^s.  Each step's
+    propagator carries about G = p - 1 + n products whose rounding errors
+    (unit roundoff u: 2^-24 FP32, 2^-53 FP64) enter at the scale of the
+    operands, |D| <= 2 after the squarings, and independent errors of the N
+    steps add in quadrature: 8 G u sqrt(N) with G <= 24, floored at 1e-6
+    (FP32) / 1e-12 (FP64)."""
+    u = 2.0 ** -53 if precision == "fp64" else 2.0 ** -24
+    floor = 1e-12 if precision == "fp64" else 1e-6
+    return max(floor, 8 * 24 * u * np.sqrt(prob.N))
+
+
 def check(prob, errs, precision="fp32"):
     if precision == "fp64":
         tF, tG, tc = 1e-11, 1e-9, 1e-11
@@ -71,6 +84,8 @@ def check(prob, errs, precision="fp32"):
         tF, tG, tc = 1e-6, 1e-4, 2e-6
     assert errs["dF"] <= tF, errs
     assert errs["dF_fwd"] <= tF, errs
+    # qoc_forward's psiN output (planar device states to interleaved doubles)
+    assert errs["psiN_l2"] <= psi_bound(prob, precision), errs
     if prob.M:
         assert errs["grad_rel"] <= tG, errs
     pen = prob.w is not None

@@ -326,3 +326,29 @@ def test_taylor_bound_is_tight_on_scalar_rotation(theta):
                 assert err <= b * (1 + 1e-9)
                 if theta / 2 ** n <= 1.0 and err < 1e-2:
                     assert b <= 4.0 * math.exp(theta / 2 ** n) * err
+
+
+# ------------------------------------------------------------ step norms
+def test_step_norms_closed_forms():
+    """theta_j = ||dt H_j||_1, the largest column absolute sum (Sec. III).
+    Diagonal H_j: dt max_m |h_m(j)|.  A dense real symmetric H with column
+    absolute sums (3, 5) separates the 1-norm (5) from the Frobenius norm
+    (sqrt(18)) and the spectral norm (1 + 2 sqrt(2))."""
+    rng = np.random.default_rng(18)
+    d, N, dt = 5, 6, 0.3
+    h0 = rng.normal(size=d)
+    hk = rng.normal(size=(2, d))
+    u = rng.normal(size=(2, N))
+    p = Problem("diag", d, 2, N, 1, dt, np.diag(h0).astype(complex),
+                np.stack([np.diag(x).astype(complex) for x in hk]), u,
+                np.eye(d, dtype=complex)[:1], np.eye(d, dtype=complex)[:1])
+    ref = [dt * np.max(np.abs(h0 + u[0, j] * hk[0] + u[1, j] * hk[1])) for j in range(N)]
+    assert np.max(np.abs(oracle.step_norms(p) - np.array(ref))) < 1e-14
+    H = np.array([[1.0, 2.0], [2.0, -3.0]], dtype=complex)
+    q = Problem("dense", 2, 1, 2, 1, 0.5, H, np.zeros((1, 2, 2), complex),
+                np.array([[0.0, 1.0]]), np.eye(2, dtype=complex)[:1],
+                np.eye(2, dtype=complex)[:1])
+    q.Hk[0] = np.array([[0.0, 1j], [-1j, 0.0]])           # adds |i| to both columns at j=1
+    th = oracle.step_norms(q)
+    assert abs(th[0] - 0.5 * 5.0) < 1e-15
+    assert abs(th[1] - 0.5 * (3.0 + abs(2.0 + 1j))) < 1e-15
