@@ -169,6 +169,26 @@ qoc_status qoc_cost_grad(qoc_handle *h, const double *u, double *cost,
 qoc_status qoc_cost_grad_device(qoc_handle *h, const double *u_dev,
                                 double *out_dev, double *grad_dev, void *stream);
 
+/* Variant of qoc_cost_grad_device that allocates nothing, for callers that
+ * cannot allocate device memory during a call: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and stream semantics as qoc_cost_grad_device; the
+ * per-call work space (the Taylor / squaring levels, the derivative's
+ * scratch and partial sums) is carved from a static device array of 256
+ * MiB that the library holds on each GPU it runs on until the process ends,
+ * instead of the handle's lazily grown buffers (which are left untouched).
+ * A call whose work space exceeds 256 MiB returns QOC_ERR_UNSUPPORTED
+ * before its first kernel on the small-d path (padded d <= 48), and after
+ * the FP64 norm kernel otherwise; so does a handle with per-phase profiling
+ * enabled (events would be created).  All calls on one GPU share that
+ * array: calls that overlap in time on the same GPU (other streams, other
+ * threads) race and must be serialised by the caller.  The array keeps the
+ * last call's contents; every value a call reads from it is written by the
+ * same call first.  Sec. II.B and Sec. III as for qoc_cost_grad_device. */
+qoc_status qoc_cost_grad_device_noalloc(qoc_handle *h, const double *u_dev,
+                                        double *out_dev, double *grad_dev,
+                                        void *stream);
+
 /* Batched variant: B independent handles (uneven d, N, M allowed), each
  * with its own device u / out / grad pointers as in qoc_cost_grad_device,
  * enqueued on one stream. */

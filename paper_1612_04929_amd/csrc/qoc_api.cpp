@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -128,6 +129,34 @@ constexpr int kSmallNCap = 16, kSmallPCap = 16;
 // Padding (elements) of the state buffers read by fixed-size prefetch slots.
 constexpr size_t kRingSlack = 1024;
 
+// Static device scratch of the no-alloc entry point: the per-call work
+// space (Taylor / squaring levels, derivative scratch and partial sums) of
+// calls that may not allocate.  Every GPU the library runs on holds its own
+// copy until the process ends; host code reaches it only through the
+// per-device address from hipGetSymbolAddress (the array's name is a host
+// stand-in, not a device address).
+constexpr size_t kScratchBytes = size_t(256) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of `scratch`; `dev` must be the current device.
+qoc_status scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(QOC_ERR_UNSUPPORTED, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(QOC_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                      hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return QOC_OK;
+}
+
 int pow2_at_least(long v) {
   int l = 1;
   while (l < v) l <<= 1;
@@ -144,6 +173,10 @@ struct qoc_handle {
   int bf3_used = 0;  // classes that ran bf16x3 products in the last call
   int bf3_fallback = 0;  // the automatic choice moved some classes to FP32
   bool capturing = false;  // the current call's stream is capturing a HIP graph
+  // per-call work space carved from the static device scratch instead of
+  // the handle's own allocations (the no-alloc entry point)
+  unsigned char *ws_base = nullptr;
+  size_t ws_cap = 0, ws_used = 0;
   int last_flags = 0;  // warning bits of the last call
   int sweep_mode[4] = {0, 0, 0, 0};  // per sweep: 0 auto, 1 per-block, 2 per-step launches,
                                      // 3 four-wavefront LDS (small d), 4 chain workgroup
@@ -342,9 +375,24 @@ qoc_status drain_pending(qoc_handle *h) {
 }
 
 // ------------------------------------------------------------------ buffers
+// A slice of `bytes` of the static device scratch (256-byte aligned) for
+// the no-alloc entry point, or QOC_ERR_UNSUPPORTED when it does not fit.
+qoc_status carve(qoc_handle *h, void **p, size_t bytes) {
+  const size_t off = (h->ws_used + 255) & ~(size_t)255;
+  if (off > h->ws_cap || bytes > h->ws_cap - off)
+    return fail(QOC_ERR_UNSUPPORTED,
+                "this call needs more than the " + std::to_string(h->ws_cap) +
+                    " bytes of static device scratch the no-alloc entry point may use (" +
+                    std::to_string(off + bytes) + " bytes so far): use qoc_cost_grad_device");
+  *p = h->ws_base + off;
+  h->ws_used = off + bytes;
+  return QOC_OK;
+}
+
 template <typename T> qoc_status ensure_levels(qoc_handle *h, int levels) {
-  if (levels <= h->levels_alloc) return QOC_OK;
   const size_t mat = 2 * (size_t)h->dp * h->dp;
+  if (h->ws_base) return carve(h, &h->Dlev, (size_t)levels * h->N * mat * sizeof(T));
+  if (levels <= h->levels_alloc) return QOC_OK;
   dfree(h, &h->Dlev, (size_t)h->levels_alloc * h->N * mat * sizeof(T));
   h->levels_alloc = 0;
   qoc_status s = dalloc(h, &h->Dlev, (size_t)levels * h->N * mat * sizeof(T));
@@ -359,7 +407,10 @@ template <typename T> qoc_status ensure_adjoint(qoc_handle *h, int p, int Rcap, 
     // batched large-d adjoint: scratch per step, partial sums per tile
     total = qoc::adjoint_big_scratch_per_step<T>(h->dp, p, Rcap) * (long)h->N;
     const long parts = (long)h->N * qoc::adjoint_big_slices(h->dp) * std::max(h->M, 1);
-    if (parts > h->adj_part_alloc) {
+    if (h->ws_base) {
+      qoc_status s = carve(h, (void **)&h->adj_part, (size_t)parts * sizeof(double));
+      if (s) return s;
+    } else if (parts > h->adj_part_alloc) {
       dfree(h, (void **)&h->adj_part, (size_t)h->adj_part_alloc * sizeof(double));
       h->adj_part_alloc = 0;
       qoc_status s = dalloc(h, (void **)&h->adj_part, (size_t)parts * sizeof(double));
@@ -371,6 +422,7 @@ template <typename T> qoc_status ensure_adjoint(qoc_handle *h, int p, int Rcap, 
     h->adj_blocks = std::min((h->N + gpb - 1) / gpb, 1024);
     total = qoc::adjoint_scratch_elems<T>(h->dp, p, Rcap) * (long)h->adj_blocks * gpb;
   }
+  if (h->ws_base) return carve(h, &h->adj, (size_t)total * sizeof(T));
   if (total <= h->adj_elems_alloc) return QOC_OK;
   dfree(h, &h->adj, (size_t)h->adj_elems_alloc * sizeof(T));
   h->adj_elems_alloc = 0;
@@ -1047,6 +1099,18 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
     delete h;
     return fail(QOC_ERR_DEVICE, "hipStreamCreate failed");
   }
+  {
+    // the device's static scratch address, once per device (for the
+    // no-alloc entry point)
+    void *sp = nullptr;
+    const qoc_status ss = scratch_address(h->device, &sp);
+    if (ss != QOC_OK) {
+      const std::string msg = g_err;
+      release(h);
+      delete h;
+      return fail(ss, msg);
+    }
+  }
   qoc_status s = (h->prec == QOC_FP64) ? alloc_all<double>(h, desc) : alloc_all<float>(h, desc);
   if (s != QOC_OK) {
     std::string msg = g_err;
@@ -1156,6 +1220,41 @@ qoc_status qoc_cost_grad_device(qoc_handle *h, const double *u_dev, double *out_
                 "per-phase profiling records events that a captured graph cannot hold: "
                 "disable qoc_profile_enable before capturing");
   const qoc_status s = run_any(h, h->M > 0 ? u_dev : h->u_dev, out_dev, grad_dev, st, true);
+  h->capturing = false;
+  return s;
+}
+
+qoc_status qoc_cost_grad_device_noalloc(qoc_handle *h, const double *u_dev, double *out_dev,
+                                        double *grad_dev, void *stream) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  if ((h->M > 0 && (!u_dev || !grad_dev)) || !out_dev)
+    return fail(QOC_ERR_ARG, "u_dev, out_dev and grad_dev must be non-NULL");
+  if (h->prof)
+    return fail(QOC_ERR_UNSUPPORTED,
+                "per-phase profiling creates events: disable qoc_profile_enable for the no-alloc "
+                "entry point");
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(QOC_ERR_DEVICE, "hipSetDevice failed");
+  void *base = nullptr;
+  qoc_status s = scratch_address(h->device, &base);
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(st, &cs));
+  h->capturing = cs != hipStreamCaptureStatusNone;
+  // the per-call buffers come from the scratch for this call only; the
+  // handle's own ones (if an allocating call made them) are kept aside
+  void *own_lev = h->Dlev, *own_adj = h->adj;
+  double *own_part = h->adj_part;
+  h->ws_base = (unsigned char *)base;
+  h->ws_cap = kScratchBytes;
+  h->ws_used = 0;
+  s = run_any(h, h->M > 0 ? u_dev : h->u_dev, out_dev, grad_dev, st, true);
+  h->Dlev = own_lev;
+  h->adj = own_adj;
+  h->adj_part = own_part;
+  h->ws_base = nullptr;
+  h->ws_cap = h->ws_used = 0;
   h->capturing = false;
   return s;
 }

@@ -28,6 +28,7 @@ STATUS = {0: "QOC_OK", -1: "QOC_ERR_ARG", -2: "QOC_ERR_SHAPE", -3: "QOC_ERR_NOT_
           -4: "QOC_ERR_NONFINITE", -5: "QOC_ERR_NOMEM", -6: "QOC_ERR_DEVICE",
           -7: "QOC_ERR_UNSUPPORTED"}
 EXPORTS = ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
+           "qoc_cost_grad_device_noalloc",
            "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
            "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
            "qoc_set_bf16x3", "qoc_destroy",
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
     lib.qoc_forward.argtypes = [vp, _dp, _dp, _dp, _dp, C.POINTER(C.c_int)]
     lib.qoc_cost_grad.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, C.POINTER(C.c_int)]
     lib.qoc_cost_grad_device.argtypes = [vp, vp, vp, vp, vp]
+    lib.qoc_cost_grad_device_noalloc.argtypes = [vp, vp, vp, vp, vp]
     lib.qoc_cost_grad_batched.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp),
                                           C.POINTER(vp), C.POINTER(vp), vp]
     lib.qoc_get_info.argtypes = [vp, C.POINTER(Info)]
@@ -103,6 +105,7 @@ def load(path: str = LIB_PATH):
         getattr(lib, f).restype = C.c_char_p
     lib.qoc_status_string.argtypes = [C.c_int]
     for f in ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
+              "qoc_cost_grad_device_noalloc",
               "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
               "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
               "qoc_set_bf16x3"]:
@@ -198,6 +201,13 @@ class Problem:
     def cost_grad_device(self, u_ptr: int, out_ptr: int, grad_ptr: int, stream: int = 0):
         _check(load().qoc_cost_grad_device(self._h, C.c_void_p(u_ptr), C.c_void_p(out_ptr),
                                            C.c_void_p(grad_ptr), C.c_void_p(stream)))
+
+    def cost_grad_device_noalloc(self, u_ptr: int, out_ptr: int, grad_ptr: int,
+                                 stream: int = 0):
+        """qoc_cost_grad_device without device allocation (static scratch)."""
+        _check(load().qoc_cost_grad_device_noalloc(self._h, C.c_void_p(u_ptr),
+                                                   C.c_void_p(out_ptr), C.c_void_p(grad_ptr),
+                                                   C.c_void_p(stream)))
 
     def set_taylor(self, p: int, n: int = 0):
         """Fix (p, n) for later calls (p = 0: choose per call)."""
