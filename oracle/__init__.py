@@ -27,6 +27,7 @@ from .grape import (  # noqa: F401
     propagate,
     fidelity,
     step_penalties,
+    time_fidelities,
     regularizers,
     cost,
     cost_grad,

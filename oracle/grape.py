@@ -11,18 +11,25 @@ Notation (paper Sec. II and Table I):
   z   = (1/S) sum_s <T_s | psi_N^s>                    composite C2-sigma (Sec. II.A)
   C_fid = 1 - |z|^2                                    (coherent; equals C1 of Table I
                                                         for S = d, psi_0 = identity)
-  c_j = (1/S) sum_s sum_m w_m |psi_j^s[m]|^2, j=1..N   Table I, C5 (diagonal weights)
+  c_j = (1/S) sum_s [sum_m w_m |psi_j^s[m]|^2          Table I, C5: forbidden basis levels
+                     + sum_f |<F_f|psi_j^s>|^2], j=1..N  (weights w) and forbidden states F_f
   C_amp = sum_{k,j} u_{k,j}^2                          Table I, C3
   C_var = sum_k sum_{j=1}^{N-1} (u_{k,j}-u_{k,j-1})^2  Table I, C4
-  C = a_fid C_fid + a_pen sum_j c_j + a_amp C_amp + a_var C_var     Sec. II (weighted sum)
+  C_time = 1 - (1/N) sum_{j=1}^N F_j                   Table I, C6 (coherent, gate) / C7
+                                                        (incoherent, states); F_j the
+                                                        fidelity of psi_j against the targets
+  C = a_fid C_fid + a_pen sum_j c_j + a_amp C_amp + a_var C_var + a_time C_time
+                                                       Sec. II (weighted sum)
 
 States are stored as rows: ``psi[j, s]`` is the length-d vector psi_j^s.
 
 Readings where the paper is silent or ambiguous (each listed in the design
 notes): N steps j = 0..N-1 with psi_0 the initial state; the 1/S
 normalisation sits inside |.|^2; the projector P_S is implicit (targets
-vanish outside the subspace); C5 sums j = 1..N with a diagonal weight
-vector and a 1/S mean over columns; C4 runs over j = 1..N-1; hbar = 1.
+vanish outside the subspace); C5 sums j = 1..N over a diagonal weight
+vector and a set of forbidden states (summed, Sec. II.A) with a 1/S mean
+over columns; C6/C7 average the fidelity of the same mode as C_fid over
+j = 1..N; C4 runs over j = 1..N-1; hbar = 1.
 """
 from __future__ import annotations
 
@@ -150,17 +157,34 @@ def fidelity(psiN: np.ndarray, psiT: np.ndarray, mode: str = "coherent"):
 
 
 # --------------------------------------------------------------------- a6
-def step_penalties(psi: np.ndarray, w: Optional[np.ndarray]) -> np.ndarray:
-    """c_j = (1/S) sum_s sum_m w_m |psi_j^s[m]|^2 for j = 1..N (Table I, C5).
+def step_penalties(psi: np.ndarray, w: Optional[np.ndarray],
+                   forbidden: Optional[np.ndarray] = None) -> np.ndarray:
+    """c_j = (1/S) sum_s [sum_m w_m |psi_j^s[m]|^2 + sum_f |<F_f|psi_j^s>|^2]
+    for j = 1..N (Table I, C5).
 
-    Forbidden states are basis levels with weights w (a set of forbidden
-    states enters "upon summation", Sec. II.A).  Returns shape (N,).
+    Forbidden basis levels carry weights w; general forbidden states F_f
+    (rows of ``forbidden``) enter "upon summation" (Sec. II.A).  Returns
+    shape (N,).
     """
     N = psi.shape[0] - 1
     S = psi.shape[1]
-    if w is None:
-        return np.zeros(N)
-    return np.einsum("jsm,m->j", np.abs(psi[1:]) ** 2, w) / S
+    c = np.zeros(N)
+    if w is not None:
+        c = c + np.einsum("jsm,m->j", np.abs(psi[1:]) ** 2, w) / S
+    if forbidden is not None:
+        ov = np.einsum("fm,jsm->jsf", np.conj(forbidden), psi[1:])
+        c = c + np.sum(np.abs(ov) ** 2, axis=(1, 2)) / S
+    return c
+
+
+# --------------------------------------------------------------------- C6/C7
+def time_fidelities(psi: np.ndarray, psiT: np.ndarray, mode: str = "coherent") -> np.ndarray:
+    """F_j, j = 1..N: the fidelity of psi_j against the targets, in the mode
+    of the final fidelity (coherent: Table I, C6, for a target gate on a
+    basis; incoherent: C7, for target states).  C_time = 1 - mean_j F_j
+    rewards reaching the target early ("at every time step", Sec. II.A).
+    Returns shape (N,)."""
+    return np.array([fidelity(psi[j], psiT, mode)[2] for j in range(1, psi.shape[0])])
 
 
 # --------------------------------------------------------------------- C3/C4
@@ -176,15 +200,18 @@ def _forward(prob, u):
     U, lam, V = propagators(prob, u)
     psi = propagate(U, prob.psi0)
     ov, z, F = fidelity(psi[-1], prob.psiT, prob.fid_mode)
-    c = step_penalties(psi, prob.w)
+    c = step_penalties(psi, prob.w, getattr(prob, "forbidden", None))
     c_amp, c_var = regularizers(u)
     C_fid = 1.0 - F
+    C_time = 1.0 - float(np.mean(time_fidelities(psi, prob.psiT, prob.fid_mode)))
     C = (prob.alpha_fid * C_fid + prob.alpha_pen * float(c.sum())
-         + prob.alpha_amp * c_amp + prob.alpha_var * c_var)
+         + prob.alpha_amp * c_amp + prob.alpha_var * c_var
+         + getattr(prob, "alpha_time", 0.0) * C_time)
     eye = np.eye(prob.d)
     drift = float(np.max(np.abs(np.conj(np.swapaxes(U, 1, 2)) @ U - eye)))
     out = dict(C=C, C_fid=C_fid, F=F, z=z, overlaps=ov, c=c, C_pen=float(c.sum()),
-               C_amp=c_amp, C_var=c_var, psiN=psi[-1].copy(), unitarity_drift=drift,
+               C_amp=c_amp, C_var=c_var, C_time=C_time, psiN=psi[-1].copy(),
+               unitarity_drift=drift,
                theta_max=float(step_norms(prob, u).max()))
     return out, U, lam, V, psi
 
@@ -216,16 +243,37 @@ def frechet_exp_skew(lam: np.ndarray, V: np.ndarray, dt: float, E: np.ndarray,
 
 
 # --------------------------------------------------------------------- a8-a11
-def _costate_final(prob, psiN, ov, z):
-    """lambda_N = dC/d(psi_N^*) for the fidelity and the j = N penalty."""
+def _fidelity_costate(prob, ov, z, weight):
+    """d(weight (1 - F))/d(psi^*) at a state set with overlaps ov and z."""
     S = prob.S
     if prob.fid_mode == "coherent":
-        lam = -prob.alpha_fid * (z / S) * prob.psiT
-    else:
-        lam = -prob.alpha_fid * (ov[:, None] / S) * prob.psiT
-    if prob.w is not None and prob.alpha_pen != 0.0:
-        lam = lam + prob.alpha_pen / S * prob.w[None, :] * psiN
-    return lam
+        return -weight * (z / S) * prob.psiT
+    return -weight * (ov[:, None] / S) * prob.psiT
+
+
+def _step_source(prob, psi_j):
+    """dC/d(psi_j^*) of the per-step terms at one step j >= 1: the C5
+    penalties (weighted levels and forbidden states) and the time-optimal
+    term a_time (1 - F_j) / N."""
+    S = prob.S
+    src = np.zeros_like(psi_j)
+    if prob.alpha_pen != 0.0:
+        if prob.w is not None:
+            src = src + prob.alpha_pen / S * prob.w[None, :] * psi_j
+        forb = getattr(prob, "forbidden", None)
+        if forb is not None:
+            ovf = np.conj(forb) @ psi_j.T               # (F, S): <F_f|psi_j^s>
+            src = src + prob.alpha_pen / S * (ovf.T @ forb)
+    a_time = getattr(prob, "alpha_time", 0.0)
+    if a_time != 0.0:
+        ovt, zt, _ = fidelity(psi_j, prob.psiT, prob.fid_mode)
+        src = src + _fidelity_costate(prob, ovt, zt, a_time / prob.N)
+    return src
+
+
+def _costate_final(prob, psiN, ov, z):
+    """lambda_N = dC/d(psi_N^*): the final fidelity and the j = N step terms."""
+    return _fidelity_costate(prob, ov, z, prob.alpha_fid) + _step_source(prob, psiN)
 
 
 def _regularizer_grad(prob, u):
@@ -249,7 +297,9 @@ def cost_grad(prob, u: Optional[np.ndarray] = None) -> dict:
         G_j   = sum_s lambda_{j+1}^s (psi_j^s)^dagger   (cotangent of U_j)
         W_j   = L(A_j^dagger, G_j)                      exact Frechet adjoint
         g_kj  = 2 Re tr(W_j^dagger dA_j/du_kj) = 2 dt Im tr(W_j^dagger H_k)
-        lambda_j = U_j^dagger lambda_{j+1} + a_pen/S w o psi_j   (penalty for j >= 1)
+        lambda_j = U_j^dagger lambda_{j+1} + s_j(psi_j)   (per-step terms for j >= 1:
+                   a_pen/S [w o psi_j + sum_f <F_f|psi_j> F_f] and the time-optimal
+                   -a_time/N dF_j/d(psi_j^*))
     plus the closed-form gradients of C3 and C4.  The adjoint identity
     tr(G^dagger L(A,E)) = tr(L(A^dagger,G)^dagger E) lets one Frechet
     evaluation per step serve every control.
@@ -259,15 +309,14 @@ def cost_grad(prob, u: Optional[np.ndarray] = None) -> dict:
     N, S = prob.N, prob.S
     g = np.zeros((prob.M, N))
     lam = _costate_final(prob, psi[N], out["overlaps"], out["z"])
-    pen_on = prob.w is not None and prob.alpha_pen != 0.0
     for j in range(N - 1, -1, -1):
         G = lam.T @ np.conj(psi[j])             # sum_s lam^s (psi_j^s)^dagger
         W = frechet_exp_skew(lamH[j], V[j], prob.dt, G, adjoint=True)
         for k in range(prob.M):
             g[k, j] = 2.0 * prob.dt * np.imag(np.vdot(W, prob.Hk[k]))
         lam = lam @ np.conj(U[j])               # rows: U_j^dagger lambda^s
-        if pen_on and j >= 1:
-            lam = lam + prob.alpha_pen / S * prob.w[None, :] * psi[j]
+        if j >= 1:
+            lam = lam + _step_source(prob, psi[j])
     out["grad"] = g + _regularizer_grad(prob, u)
     return out
 
@@ -284,12 +333,11 @@ def gradient_first_order(prob, u: Optional[np.ndarray] = None) -> np.ndarray:
     N, S = prob.N, prob.S
     g = np.zeros((prob.M, N))
     lam = _costate_final(prob, psi[N], out["overlaps"], out["z"])
-    pen_on = prob.w is not None and prob.alpha_pen != 0.0
     for j in range(N - 1, -1, -1):
         for k in range(prob.M):
             Hpsi = psi[j + 1] @ prob.Hk[k].T
             g[k, j] = 2.0 * prob.dt * np.imag(np.sum(np.conj(lam) * Hpsi))
         lam = lam @ np.conj(U[j])
-        if pen_on and j >= 1:
-            lam = lam + prob.alpha_pen / S * prob.w[None, :] * psi[j]
+        if j >= 1:
+            lam = lam + _step_source(prob, psi[j])
     return g + _regularizer_grad(prob, u)

@@ -50,11 +50,21 @@ MUTATIONS = {
                   "g[k, j] = -2.0 * prob.dt * np.imag(np.vdot(W, prob.Hk[k]))"),
     "costate_operand": ("lam = lam @ np.conj(U[j])               # rows: U_j^dagger lambda^s",
                         "lam = lam @ U[j]"),
-    "costate_penalty_index": ("        if pen_on and j >= 1:\n            lam = lam + prob.alpha_pen / S * prob.w[None, :] * psi[j]\n    out[\"grad\"]",
-                              "        if pen_on and j >= 1:\n            lam = lam + prob.alpha_pen / S * prob.w[None, :] * psi[j + 1]\n    out[\"grad\"]"),
-    # final costate without the j = N penalty, amplitude gradient without 2
-    "costate_final_no_penalty": ("lam = lam + prob.alpha_pen / S * prob.w[None, :] * psiN",
-                                 "lam = lam"),
+    "costate_penalty_index": ("lam = lam @ np.conj(U[j])               # rows: U_j^dagger lambda^s\n        if j >= 1:\n            lam = lam + _step_source(prob, psi[j])",
+                              "lam = lam @ np.conj(U[j])               # rows: U_j^dagger lambda^s\n        if j >= 1:\n            lam = lam + _step_source(prob, psi[j + 1])"),
+    # final costate without the j = N step terms
+    "costate_final_no_step_terms": ("return _fidelity_costate(prob, ov, z, prob.alpha_fid) + _step_source(prob, psiN)",
+                                    "return _fidelity_costate(prob, ov, z, prob.alpha_fid)"),
+    # forbidden states: bilinear overlap in the penalty, transposed source
+    "forbidden_no_conj": ('ov = np.einsum("fm,jsm->jsf", np.conj(forbidden), psi[1:])',
+                          'ov = np.einsum("fm,jsm->jsf", forbidden, psi[1:])'),
+    "forbidden_source_conj": ("src = src + prob.alpha_pen / S * (ovf.T @ forb)",
+                              "src = src + prob.alpha_pen / S * (ovf.T @ np.conj(forb))"),
+    # time-optimal: steps 0..N-1 instead of 1..N, source without the 1/N
+    "time_index": ("return np.array([fidelity(psi[j], psiT, mode)[2] for j in range(1, psi.shape[0])])",
+                   "return np.array([fidelity(psi[j], psiT, mode)[2] for j in range(0, psi.shape[0] - 1)])"),
+    "time_source_scale": ("src = src + _fidelity_costate(prob, ovt, zt, a_time / prob.N)",
+                          "src = src + _fidelity_costate(prob, ovt, zt, a_time)"),
     "amp_grad_factor": ("g = 2.0 * prob.alpha_amp * u", "g = prob.alpha_amp * u"),
 }
 

@@ -352,3 +352,74 @@ def test_step_norms_closed_forms():
     th = oracle.step_norms(q)
     assert abs(th[0] - 0.5 * 5.0) < 1e-15
     assert abs(th[1] - 0.5 * (3.0 + abs(2.0 + 1j))) < 1e-15
+
+
+# ------------------------------------------- forbidden states (C5), C6 / C7
+def test_forbidden_basis_states_equal_level_weights():
+    """Forbidden states sqrt(w_m) e_m give the per-step penalties, cost and
+    gradient of the level weights w (Table I, C5: a set of forbidden states
+    enters upon summation)."""
+    rng = np.random.default_rng(19)
+    p = random_problem(rng, d=4, M=2, N=6, S=2, dt=0.4, scale=1.5)
+    q = random_problem(np.random.default_rng(19), d=4, M=2, N=6, S=2, dt=0.4, scale=1.5)
+    q.forbidden = np.diag(np.sqrt(q.w)).astype(complex)
+    q.w = None
+    a, b = oracle.cost_grad(p), oracle.cost_grad(q)
+    assert np.max(np.abs(a["c"] - b["c"])) < 1e-14
+    assert abs(a["C"] - b["C"]) < 1e-13
+    assert np.max(np.abs(a["grad"] - b["grad"])) < 1e-13
+
+
+def test_forbidden_state_rabi_closed_form_and_phase():
+    """Rabi drive |0> -> |1> with the forbidden state e^{i phi}|1>:
+    c_j = sin^2(theta_j / 2) whatever the phase phi."""
+    theta, N = 2.2, 16
+    p = rabi_problem(theta, N=N, S=1, alpha_pen=0.7)
+    p.forbidden = np.array([[0.0, np.exp(0.9j)]])
+    out = oracle.cost(p)
+    th_j = theta * np.arange(1, N + 1) / N
+    assert np.max(np.abs(out["c"] - np.sin(th_j / 2) ** 2)) < 1e-14
+    # a superposition forbidden state: |<F|psi_j>|^2 with psi_j = cos|0> - i sin|1>
+    f = np.array([0.6, 0.8j])
+    p.forbidden = f[None]
+    ref = np.abs(0.6 * np.cos(th_j / 2) + (-0.8j) * (-1j * np.sin(th_j / 2))) ** 2
+    assert np.max(np.abs(oracle.cost(p)["c"] - ref)) < 1e-14
+
+
+@pytest.mark.parametrize("theta", [0.7, 2.0, 3.0])
+def test_time_optimal_rabi_closed_form(theta):
+    """C7 on the Rabi drive |0> -> |1>: F_j = sin^2(theta_j / 2), so
+    C_time = 1 - (1/N) sum_j sin^2(theta_j / 2), and its gradient along the
+    x control is -(1/N) sum_{k > j} (dt / 2) sin(theta_k), zero along y."""
+    N, dt = 12, 0.1
+    p = rabi_problem(theta, N=N, dt=dt, S=1)
+    p.alpha_fid, p.alpha_time = 0.0, 1.0
+    out = oracle.cost_grad(p)
+    th = theta * np.arange(1, N + 1) / N
+    assert abs(out["C_time"] - (1 - np.mean(np.sin(th / 2) ** 2))) < 1e-14
+    assert abs(out["C"] - out["C_time"]) < 1e-14
+    gx = np.array([-(dt / 2) * np.sum(np.sin(th[j:])) / N for j in range(N)])
+    assert np.max(np.abs(out["grad"][0] - gx)) < 1e-14
+    assert np.max(np.abs(out["grad"][1])) < 1e-14
+
+
+def test_time_optimal_single_step_equals_final_fidelity():
+    rng = np.random.default_rng(20)
+    for mode in ("coherent", "incoherent"):
+        p = random_problem(rng, d=3, M=2, N=1, S=2, fid_mode=mode, with_penalty=False,
+                           alphas=(0.0, 0.0, 0.0, 0.0), alpha_time=1.0)
+        out = oracle.cost_grad(p)
+        assert abs(out["C_time"] - out["C_fid"]) < 1e-15
+        q = random_problem(np.random.default_rng(20 if mode == "coherent" else 0), d=3, M=2,
+                           N=1, S=2, fid_mode=mode, with_penalty=False,
+                           alphas=(1.0, 0.0, 0.0, 0.0))
+        if mode == "coherent":
+            assert np.max(np.abs(out["grad"] - oracle.cost_grad(q)["grad"])) < 1e-14
+
+
+@pytest.mark.parametrize("mode", ["coherent", "incoherent"])
+def test_forbidden_and_time_optimal_gradient_matches_fd(mode):
+    rng = np.random.default_rng(21)
+    p = random_problem(rng, d=3, M=2, N=5, S=2, dt=0.35, scale=1.3, fid_mode=mode,
+                       alphas=(1.0, 0.3, 0.05, 0.02), n_forbidden=2, alpha_time=0.6)
+    assert rel(oracle.cost_grad(p)["grad"], fd_grad(p)) < 1e-7

@@ -64,6 +64,8 @@ class Problem:
     alpha_var: float = 0.0
     fid_mode: str = "coherent"       # "coherent" (C2-sigma) or "incoherent"
     meta: dict = field(default_factory=dict)
+    forbidden: Optional[np.ndarray] = None   # (F, d) complex128 forbidden states, or None
+    alpha_time: float = 0.0          # weight of the time-optimal term (Table I, C6 / C7)
 
     def with_u(self, u: np.ndarray) -> "Problem":
         return replace(self, u=np.ascontiguousarray(u, dtype=np.float64))
@@ -295,8 +297,12 @@ def make_config(name: str, **kw) -> Problem:
 def random_problem(rng: np.random.Generator, d: int, M: int, N: int, S: int,
                    dt: float = 0.1, scale: float = 1.0, u_scale: float = 0.5,
                    with_penalty: bool = True, fid_mode: str = "coherent",
-                   alphas=(1.0, 0.3, 0.05, 0.02)) -> Problem:
-    """Dense random Hermitian drift/controls for small property tests."""
+                   alphas=(1.0, 0.3, 0.05, 0.02), n_forbidden: int = 0,
+                   alpha_time: float = 0.0) -> Problem:
+    """Dense random Hermitian drift/controls for small property tests.
+    ``n_forbidden`` > 0 adds that many Haar-random forbidden states (drawn
+    after the targets and the weights); ``alpha_time`` weights the
+    time-optimal term."""
     def herm():
         A = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
         return scale * (A + A.conj().T) / (2.0 * math.sqrt(d))
@@ -306,7 +312,11 @@ def random_problem(rng: np.random.Generator, d: int, M: int, N: int, S: int,
     psi0 = np.stack([haar_state(rng, d) for _ in range(S)])
     psiT = np.stack([haar_state(rng, d) for _ in range(S)])
     w = rng.uniform(0.0, 1.0, size=d) if with_penalty else None
+    forb = (np.stack([haar_state(rng, d) for _ in range(n_forbidden)])
+            if n_forbidden > 0 else None)
     af, ap, aa, av = alphas
     return Problem(f"rand_d{d}_M{M}_N{N}_S{S}", d, M, N, S, dt, H0, Hk, u, psi0,
-                   psiT, w=w, alpha_fid=af, alpha_pen=ap if with_penalty else 0.0,
-                   alpha_amp=aa, alpha_var=av, fid_mode=fid_mode)
+                   psiT, w=w, alpha_fid=af,
+                   alpha_pen=ap if (with_penalty or n_forbidden > 0) else 0.0,
+                   alpha_amp=aa, alpha_var=av, fid_mode=fid_mode, forbidden=forb,
+                   alpha_time=float(alpha_time))
