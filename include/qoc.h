@@ -13,9 +13,15 @@
  *   z     = (1/S) sum_s <T_s|psi_N^s>,  C_fid = 1 - |z|^2 (composite state
  *           infidelity, Sec. II.A; equals the gate infidelity C1 when the
  *           S = d columns of the identity are propagated)
- *   c_j   = (1/S) sum_s sum_m w_m |psi_j^s[m]|^2, j = 1..N  (Table I, C5)
+ *   c_j   = (1/S) sum_s [sum_m w_m |psi_j^s[m]|^2 + sum_f |<F_f|psi_j^s>|^2],
+ *           j = 1..N  (Table I, C5: forbidden levels with weights w and a set
+ *           of forbidden states F_f, summed, Sec. II.A)
  *   C_amp = sum u^2 (C3),  C_var = sum_k sum_{j>=1} (u_{k,j}-u_{k,j-1})^2 (C4)
+ *   C_time = 1 - (1/N) sum_{j=1..N} F_j, F_j the fidelity of psi_j against the
+ *           targets in the mode of C_fid (Table I, C6 coherent / C7
+ *           incoherent: the time-optimal term)
  *   C     = a_fid C_fid + a_pen sum_j c_j + a_amp C_amp + a_var C_var
+ *           + a_time C_time
  * Each U_j is evaluated by a truncated Taylor series of order p with n
  * scaling-and-squaring steps, with one global (p, n) (Sec. III, eq. 6),
  * and the gradient dC/du_{k,j} is the exact derivative of that evaluation
@@ -118,6 +124,11 @@ typedef struct {
                                theta_max; anything else is QOC_ERR_ARG      */
   double drift_warn;        /* threshold of QOC_WARN_DRIFT; 0 = 1e-4        */
   int device;               /* HIP device ordinal                           */
+  int n_forbidden;          /* forbidden states of C5, 0 .. 16 (weighted by
+                               alpha_pen; ignored when alpha_pen == 0)      */
+  const double *forbidden;  /* n_forbidden*d complex, state-major (state f at
+                               [f*d + m]), or NULL when n_forbidden == 0    */
+  double alpha_time;        /* weight of the time-optimal term C_time        */
 } qoc_problem_desc;
 
 /* Diagnostics of the most recent forward / cost_grad call on a handle. */
@@ -138,7 +149,11 @@ typedef struct {
 /* Create a handle: validates and copies the problem to device memory.
  * Checks: shapes; S <= d; finite inputs; dt > 0; Hermiticity of H_0 and
  * every H_k with ||H - H^dagger||_max <= 1e-12 * max(1, ||H||_max);
- * penalty weights >= 0.  Paper: Sec. II (problem statement), Table I. */
+ * penalty weights >= 0; 0 <= n_forbidden <= 16 (QOC_ERR_SHAPE).  With
+ * forbidden states (and alpha_pen != 0) or alpha_time != 0 the sweeps run on
+ * the generic per-block kernels (the sweep variants of qoc_set_sweep do not
+ * apply) and the per-step terms add one FP64 pass over the states.  Paper:
+ * Sec. II (problem statement), Table I. */
 qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out);
 
 /* Forward pass only (Sec. II, eqs. 1-4; Table I).  u: M*N host doubles.

@@ -226,6 +226,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_fwd_replay(SweepA
   const int start = b * a.L, end = min(a.N, start + a.L);
   T *xr = buf, *xi = buf + dp, *yr = buf + 2 * dp, *yi = buf + 3 * dp;
   const T *c = a.ckpt + (long)b * set;
+  if (a.replay_mode != 2) {  // grid-uniform
   for (int m = threadIdx.x; m < dp; m += blockDim.x) {
     const T vr = set_re(c, S, dp, s)[m], vi = set_im(c, S, dp, s)[m];
     xr[m] = vr; xi[m] = vi;
@@ -247,9 +248,10 @@ template <typename T> __global__ __launch_bounds__(256) void k_fwd_replay(SweepA
     xr = yr; xi = yi; yr = tr; yi = ti;
     __syncthreads();
   }
-  if (!a.pw) return;  // block-uniform
+  }
+  if ((!a.pw && !a.src) || a.replay_mode == 1) return;  // block-uniform
   // block-local penalty costate from zero at the block end:
-  // mu <- mu + D_j^H mu + pw o psi_j   (penalty only for j >= 1)
+  // mu <- mu + D_j^H mu + pw o psi_j + src_j   (per-step terms only for j >= 1)
   T *mr = xr, *mi = xi, *nr = yr, *ni = yi;
   T *pr = buf + 4 * dp, *pi = buf + 5 * dp;
   for (int m = threadIdx.x; m < dp; m += blockDim.x) {
@@ -260,9 +262,14 @@ template <typename T> __global__ __launch_bounds__(256) void k_fwd_replay(SweepA
   for (int j = end - 1; j >= start; --j) {
     const T *ps = a.psi_buf + (long)j * set;
     for (int m = threadIdx.x; m < dp; m += blockDim.x) {
-      const T wgt = (j >= 1) ? a.pw[m] : (T)0;
-      pr[m] = wgt * set_re(ps, S, dp, s)[m];
-      pi[m] = wgt * set_im(ps, S, dp, s)[m];
+      const T wgt = (a.pw && j >= 1) ? a.pw[m] : (T)0;
+      T vr = wgt * set_re(ps, S, dp, s)[m], vi = wgt * set_im(ps, S, dp, s)[m];
+      if (a.src && j >= 1) {
+        vr += set_re(a.src + (long)j * set, S, dp, s)[m];
+        vi += set_im(a.src + (long)j * set, S, dp, s)[m];
+      }
+      pr[m] = vr;
+      pi[m] = vi;
     }
     __syncthreads();
     const T *D = a.D + (long)j * mat;
@@ -448,8 +455,13 @@ template <typename T> __global__ __launch_bounds__(256) void k_bwd_pairs(SweepAr
       set_rew(lb, S, dp, s)[m] = xr[m];
       set_imw(lb, S, dp, s)[m] = xi[m];
       const T wgt = (a.pw && j >= 1) ? a.pw[m] : (T)0;
-      pr[m] = wgt * set_re(ps, S, dp, s)[m];
-      pi[m] = wgt * set_im(ps, S, dp, s)[m];
+      T vr = wgt * set_re(ps, S, dp, s)[m], vi = wgt * set_im(ps, S, dp, s)[m];
+      if (a.src && j >= 1) {
+        vr += set_re(a.src + (long)j * set, S, dp, s)[m];
+        vi += set_im(a.src + (long)j * set, S, dp, s)[m];
+      }
+      pr[m] = vr;
+      pi[m] = vi;
     }
     if (j == start) break;  // lambda_start belongs to the previous block
     __syncthreads();

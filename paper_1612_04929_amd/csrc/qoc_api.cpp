@@ -182,6 +182,15 @@ struct qoc_handle {
                                      // 3 four-wavefront LDS (small d), 4 chain workgroup
   double dt = 0, a_fid = 0, a_amp = 0, a_var = 0, a_pen = 0, tol = 0, drift_warn = 0;
   bool has_pen = false;
+  // per-step terms beyond the level penalty: forbidden states (C5) and the
+  // time-optimal term (C6 / C7); they run on the generic per-block sweeps
+  int nf = 0;
+  double a_time = 0;
+  bool has_ext = false;
+  double *forb64 = nullptr;   // nf x d complex interleaved
+  void *src = nullptr;        // (N + 1) state sets of costate sources
+  double *ext_part = nullptr; // 2 x next
+  int next = 1;
   int fixed_p = 0, fixed_n = 0;
   int L = 1, nb = 1, device = 0;
   size_t esize = 4;  // sizeof(T) of the chain precision
@@ -279,6 +288,7 @@ void release(qoc_handle *h) {
   void **ptrs[] = {&h->Hf, (void **)&h->H64, (void **)&h->u_dev, (void **)&h->out_dev,
                    (void **)&h->grad_dev, &h->psi0, (void **)&h->psiT64, (void **)&h->w64,
                    &h->pw, &h->X, &h->Qa, &h->Qb, &h->Eh, &h->Es, &h->Ehs, &h->nu, &h->Dlev,
+                   (void **)&h->forb64, &h->src, (void **)&h->ext_part,
                    &h->ckpt, &h->lam_ckpt, &h->mu,
                    &h->psi_buf, &h->lam_buf, (void **)&h->bits,
                    (void **)&h->zinfo, (void **)&h->part, (void **)&h->pn_dev,
@@ -473,7 +483,7 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   }
   ALLOC(h->ckpt, ((size_t)(h->nb + 1) * set + slack) * sizeof(T));
   ALLOC(h->lam_ckpt, ((size_t)(h->nb + 1) * set + slack) * sizeof(T));
-  if (h->has_pen) ALLOC(h->mu, ((size_t)h->nb * set + slack) * sizeof(T));
+  if (h->has_pen || h->has_ext) ALLOC(h->mu, ((size_t)h->nb * set + slack) * sizeof(T));
   ALLOC(h->psi_buf, ((size_t)(N + 1) * set + slack) * sizeof(T));
   ALLOC(h->lam_buf, ((size_t)N * set + slack) * sizeof(T));
   // theta, drift, norm ticket, (unused), norm accumulator
@@ -482,6 +492,12 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   ALLOC(h->zinfo, (size_t)(3 + 2 * S) * sizeof(double));
   h->npart = std::max(1, std::min(1024, (N + 3) / 4));
   ALLOC(h->part, (size_t)4 * h->npart * sizeof(double));
+  if (h->has_ext) {
+    if (h->nf > 0) ALLOC(h->forb64, (size_t)h->nf * d * 2 * sizeof(double));
+    ALLOC(h->src, (size_t)(N + 1) * set * sizeof(T));
+    h->next = std::max(1, std::min(1024, (N + 3) / 4));
+    ALLOC(h->ext_part, (size_t)2 * h->next * sizeof(double));
+  }
   ALLOC(h->pn_dev, 4 * sizeof(int));
   ALLOC(h->sc_dev, 2 * sizeof(double));
   // no pair yet: the first speculative pass of the padded-d-16 kernel is redone
@@ -532,6 +548,9 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   HIP_TRY(hipMemcpy(h->psi0, ps.data(), set * sizeof(T), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->psiT64, desc->psiT, (size_t)S * d * 2 * sizeof(double),
                     hipMemcpyHostToDevice));
+  if (h->nf > 0)
+    HIP_TRY(hipMemcpy(h->forb64, desc->forbidden, (size_t)h->nf * d * 2 * sizeof(double),
+                      hipMemcpyHostToDevice));
   if (h->has_pen) {
     std::vector<double> w(dp, 0.0);
     std::vector<T> pw(dp, (T)0);
@@ -824,20 +843,37 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   sw.alpha_fid = h->a_fid; sw.alpha_pen = h->a_pen; sw.alpha_amp = h->a_amp;
   sw.alpha_var = h->a_var; sw.fid_mode = h->fid_mode; sw.out = out_dev; sw.zinfo = h->zinfo;
   sw.part = h->part; sw.npart = h->npart;
+  if (h->has_ext) {
+    sw.src = (const T *)h->src;
+    sw.ext_part = h->ext_part;
+    sw.next = h->next;
+    sw.alpha_time = h->a_time;
+  }
   // sweep kernels: one wavefront (S d_pad <= 64), one workgroup with a
-  // prefetch ring (d_pad <= 64), or the generic streaming kernels
-  const bool wave = qoc::wave_sweep_ok<T>(dp, S) && sw.Dh && sw.Eh;
+  // prefetch ring (d_pad <= 64), or the generic streaming kernels; the
+  // per-step source terms (forbidden states, time-optimal) run on the
+  // generic per-block kernels only
+  const bool ext = h->has_ext;
+  const bool wave = !ext && qoc::wave_sweep_ok<T>(dp, S) && sw.Dh && sw.Eh;
   // padded d 16 with a gradient: the total runs as an extra workgroup of
   // the derivative kernel instead of a launch of its own, and (single-
   // wavefront block sweep) lambda_N, the fidelity and the penalty pass run
   // inside the backward block sweep's launch instead of the cost launch
-  const bool total_in_adjoint = want_grad && M > 0 && small_path && !small_big_adjoint<T>(h) &&
-                                qoc::adjoint16_ok<T>(dp, kSmallPCap);
+  const bool total_in_adjoint = !ext && want_grad && M > 0 && small_path &&
+                                !small_big_adjoint<T>(h) && qoc::adjoint16_ok<T>(dp, kSmallPCap);
   sw.fuse_cost = (total_in_adjoint && wave && h->sweep_mode[2] != 3) ? 1 : 0;
-  const bool small = !wave && qoc::small_sweep_ok<T>(dp, S);
-  const bool wide_ok = !wave && !small && qoc::wide_sweep_ok<T>(dp, S);
+  const bool small = !ext && !wave && qoc::small_sweep_ok<T>(dp, S);
+  const bool wide_ok = !ext && !wave && !small && qoc::wide_sweep_ok<T>(dp, S);
   auto sweep = [&](int which) -> hipError_t {
     const int mode = h->sweep_mode[which];
+    if (ext) {
+      switch (which) {
+        case 0: return qoc::launch_fwd_blocks<T>(sw, st);
+        case 1: return qoc::launch_fwd_replay<T>(sw, st);
+        case 2: return qoc::launch_bwd_blocks<T>(sw, st);
+        default: return qoc::launch_bwd_pairs<T>(sw, st);
+      }
+    }
     if (wave && !(mode == 3 && qoc::small_sweep_ok<T>(dp, S)))
       return qoc::launch_wave_sweep<T>(which, sw, st);
     // chain workgroups: by default for FP32 padded d 80 .. 128
@@ -861,7 +897,10 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   }
   {
     PhaseTimer tm(h, QOC_PHASE_FWD_REPLAY, st);
+    // with source terms the block penalty costates wait for them: replay only
+    sw.replay_mode = ext ? 1 : 0;
     HIP_TRY(sweep(1));
+    sw.replay_mode = 0;
   }
   // penalties beside fidelity / lambda_N in one launch, then the total cost
   // and drift (a side stream for the penalties measured slower here, its
@@ -869,9 +908,24 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   if (!sw.fuse_cost) {
     PhaseTimer tm(h, QOC_PHASE_COST, st);
     HIP_TRY(qoc::launch_cost<T>(sw, st));
+    if (ext) {
+      // forbidden-state occupancies into c_j, the time-optimal fidelities,
+      // the costate sources src_j and src_N into lambda_N
+      const long set = 2L * S * dp;
+      const qoc::ExtArgs<T> ea{h->forb64, h->nf, h->a_time, (T *)h->src,
+                               (T *)h->lam_ckpt + (long)h->nb * set, h->ext_part, h->next};
+      HIP_TRY(qoc::launch_ext<T>(sw, ea, st));
+    }
     if (!total_in_adjoint) HIP_TRY(qoc::launch_total<T>(sw, st));
   }
   if (!want_grad) return QOC_OK;
+  if (ext) {
+    // the block-local penalty costates mu_b with the sources
+    PhaseTimer tm(h, QOC_PHASE_FWD_REPLAY, st);
+    sw.replay_mode = 2;
+    HIP_TRY(qoc::launch_fwd_replay<T>(sw, st));
+    sw.replay_mode = 0;
+  }
   {
     PhaseTimer tm(h, QOC_PHASE_BWD_BLOCKS, st);
     HIP_TRY(sweep(2));
@@ -1035,6 +1089,14 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
                             D.taylor_n <= 60)))
     return fail(QOC_ERR_ARG, "taylor_p must be 0 (automatic) or in [2, 64] with taylor_n in [0, 60]");
   if (!(D.drift_warn >= 0.0)) return fail(QOC_ERR_ARG, "drift_warn must be >= 0");
+  if (D.n_forbidden < 0 || D.n_forbidden > qoc::QOC_MAX_FORBIDDEN)
+    return fail(QOC_ERR_SHAPE, "n_forbidden must be in [0, " +
+                                   std::to_string(qoc::QOC_MAX_FORBIDDEN) + "]");
+  if (D.n_forbidden > 0 && !D.forbidden)
+    return fail(QOC_ERR_ARG, "forbidden must be non-NULL when n_forbidden > 0");
+  if (!std::isfinite(D.alpha_time)) return fail(QOC_ERR_NONFINITE, "alpha_time must be finite");
+  if (D.n_forbidden > 0 && !all_finite(D.forbidden, (size_t)D.n_forbidden * D.d * 2))
+    return fail(QOC_ERR_NONFINITE, "forbidden states contain NaN or Inf");
   const double alphas[4] = {D.alpha_fid, D.alpha_amp, D.alpha_var, D.alpha_pen};
   if (!all_finite(alphas, 4)) return fail(QOC_ERR_NONFINITE, "cost weights must be finite");
   const size_t dd = (size_t)D.d * D.d * 2;
@@ -1075,6 +1137,9 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
   h->a_var = D.alpha_var;
   h->a_pen = D.alpha_pen;
   h->has_pen = D.penalty_w != nullptr;
+  h->nf = (D.alpha_pen != 0.0) ? D.n_forbidden : 0;
+  h->a_time = D.alpha_time;
+  h->has_ext = h->nf > 0 || h->a_time != 0.0;
   h->tol = D.taylor_tol > 0 ? D.taylor_tol : (D.precision == QOC_FP64 ? 1e-15 : 1e-10);
   h->drift_warn = D.drift_warn > 0 ? D.drift_warn : 1e-4;
   h->fixed_p = D.taylor_p;

@@ -136,11 +136,41 @@ template <typename T> struct SweepArgs {
   double *part;         // 4 x npart partials (penalties, |u|^2, variations, drift max)
   int npart;            // penalty workgroups of k_cost (wavefronts when fused)
   int fuse_cost;        // single-wavefront B2 computes lambda_N and runs the penalties
+  // per-step costate sources beyond the level penalty (forbidden states,
+  // time-optimal term; null: none), (N + 1) state sets, src_j at set j; read
+  // by the generic per-block kernels only (k_fwd_replay's mu pass, k_bwd_pairs)
+  const T *src;
+  int replay_mode;      // k_fwd_replay: 0 replay and mu, 1 replay only, 2 mu only
+  // totals of the per-step terms of k_ext (null: none): 2 x next partials
+  const double *ext_part;
+  int next;
+  double alpha_time;
 };
 template <typename T> __host__ __device__ inline TotalArgs total_args(const SweepArgs<T> &a) {
   return TotalArgs{a.part, a.npart, a.zinfo, a.out, a.alpha_fid, a.alpha_pen,
-                   a.alpha_amp, a.alpha_var, a.drift_bits};
+                   a.alpha_amp, a.alpha_var, a.drift_bits, a.ext_part, a.next,
+                   a.alpha_time, a.N};
 }
+
+// Forbidden states and the time-optimal term (kernels_ext.hip): one
+// wavefront per step j = 1..N computes, in FP64, the overlaps of psi_j with
+// the forbidden states and the targets, adds (1/S) sum |<F_f|psi_j^s>|^2 to
+// c_j in out, writes the costate source src_j (chain precision), adds src_N
+// to lambda_N (lamN, written by the cost launch before), and leaves
+// per-workgroup sums of the forbidden occupancies and of F_j in part
+// (2 x nblk) for the total.
+constexpr int QOC_MAX_FORBIDDEN = 16;
+template <typename T> struct ExtArgs {
+  const double *forb64;  // nf x d interleaved complex forbidden states
+  int nf;                // 0 .. QOC_MAX_FORBIDDEN
+  double alpha_time;
+  T *src;                // (N + 1) state sets
+  T *lamN;               // lambda_N state set
+  double *part;          // 2 x nblk
+  int nblk;
+};
+template <typename T>
+hipError_t launch_ext(const SweepArgs<T> &a, const ExtArgs<T> &e, hipStream_t st);
 template <typename T> hipError_t launch_fwd_blocks(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_bwd_blocks(const SweepArgs<T> &a, hipStream_t st);

@@ -16,6 +16,12 @@ struct TotalArgs {
   double *out;          // out[0] receives C
   double alpha_fid, alpha_pen, alpha_amp, alpha_var;
   unsigned long long *drift_bits;
+  // per-step terms of the forbidden-state / time-optimal pass (null: none):
+  // ext_part[q] forbidden occupancies, ext_part[next + q] fidelities F_j
+  const double *ext_part;
+  int next;
+  double alpha_time;
+  int N;
 };
 
 __device__ inline void cost_total_block(const TotalArgs &a) {
@@ -28,15 +34,26 @@ __device__ inline void cost_total_block(const TotalArgs &a) {
     cvar += a.part[2 * a.npart + q];
     dmax = fmax(dmax, a.part[3 * a.npart + q]);
   }
+  double epen = 0.0, eF = 0.0;
+  if (a.ext_part)  // block-uniform
+    for (int q = threadIdx.x; q < a.next; q += blockDim.x) {
+      epen += a.ext_part[q];
+      eF += a.ext_part[a.next + q];
+    }
   cpen = block_sum(cpen, red);
   camp = block_sum(camp, red);
   cvar = block_sum(cvar, red);
+  epen = block_sum(epen, red);
+  eF = block_sum(eF, red);
   dmax = wave_max(dmax);
   if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = dmax;
   __syncthreads();
   if (threadIdx.x == 0) {
     const double Cfid = 1.0 - a.zinfo[2];
-    a.out[0] = a.alpha_fid * Cfid + a.alpha_pen * cpen + a.alpha_amp * camp + a.alpha_var * cvar;
+    double C = a.alpha_fid * Cfid + a.alpha_pen * cpen + a.alpha_amp * camp + a.alpha_var * cvar;
+    // C5 over forbidden states, and C_time = 1 - (1/N) sum_j F_j (C6 / C7)
+    if (a.ext_part) C += a.alpha_pen * epen + a.alpha_time * (1.0 - eF / a.N);
+    a.out[0] = C;
     const double m = fmax(fmax(dred[0], dred[1]), fmax(dred[2], dred[3]));
     *a.drift_bits = (unsigned long long)__double_as_longlong(m);
   }

@@ -45,7 +45,8 @@ class Desc(C.Structure):
                 ("alpha_var", C.c_double), ("alpha_pen", C.c_double), ("fid_mode", C.c_int),
                 ("precision", C.c_int), ("checkpoint_every", C.c_int),
                 ("taylor_tol", C.c_double), ("taylor_p", C.c_int), ("taylor_n", C.c_int),
-                ("drift_warn", C.c_double), ("device", C.c_int)]
+                ("drift_warn", C.c_double), ("device", C.c_int), ("n_forbidden", C.c_int),
+                ("forbidden", _dp), ("alpha_time", C.c_double)]
 
 
 class Info(C.Structure):
@@ -158,6 +159,12 @@ class Problem:
             w = np.ascontiguousarray(np.asarray(prob.w, dtype=np.float64).reshape(self.d))
             keep.append(w)
             pw = w.ctypes.data_as(_dp)
+        forb = getattr(prob, "forbidden", None)
+        nf, pf = 0, None
+        if forb is not None and len(forb):
+            fa, pf = _cplx(forb, (len(forb), self.d))
+            keep.append(fa)
+            nf = len(forb)
         mode = getattr(prob, "fid_mode", "coherent")
         fid = {"coherent": 0, "incoherent": 1}.get(mode, mode)
         tp, tn = (0, 0) if taylor_pn is None else (int(taylor_pn[0]), int(taylor_pn[1]))
@@ -165,7 +172,8 @@ class Problem:
                     pHk if self.M else None, pp0, ppT, pw, float(prob.alpha_fid),
                     float(prob.alpha_amp), float(prob.alpha_var), float(prob.alpha_pen),
                     int(fid), PRECISIONS.get(precision, precision), int(checkpoint_every),
-                    float(taylor_tol), tp, tn, float(drift_warn), int(device))
+                    float(taylor_tol), tp, tn, float(drift_warn), int(device), nf, pf,
+                    float(getattr(prob, "alpha_time", 0.0)))
         self._h = C.c_void_p()
         _check(lib.qoc_create(C.byref(desc), C.byref(self._h)))
         self.precision = precision

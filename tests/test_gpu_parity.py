@@ -88,10 +88,12 @@ def check(prob, errs, precision="fp32"):
     assert errs["psiN_l2"] <= psi_bound(prob, precision), errs
     if prob.M:
         assert errs["grad_rel"] <= tG, errs
-    pen = prob.w is not None
+    pen = prob.w is not None or getattr(prob, "forbidden", None) is not None
     if pen:
         assert errs["dc"] <= tc, errs
-    budget = prob.alpha_fid * tF + (prob.alpha_pen * prob.N * tc if pen else 0.0) + 1e-9
+    # the time-optimal term averages N fidelities, each within tF
+    budget = (prob.alpha_fid * tF + (prob.alpha_pen * prob.N * tc if pen else 0.0)
+              + abs(getattr(prob, "alpha_time", 0.0)) * tF + 1e-9)
     assert errs["dC"] <= budget, errs
     # the GPU chooses (p, n) from its own FP64 theta_max by the same rule
     assert abs(errs["theta"] - errs["theta_ref"]) <= 1e-12 * max(1.0, errs["theta_ref"]), errs
