@@ -78,9 +78,18 @@ enum {
   QOC_WARN_DRIFT = 1,  /* norm drift of the propagated columns above drift_warn */
   QOC_WARN_TAYLOR = 2, /* a fixed (taylor_p, taylor_n) misses taylor_tol at this
                           call's theta_max (the call still uses the fixed pair) */
-  QOC_WARN_PRECISION = 4 /* QOC_BF16X3: the automatic policy ran some product
+  QOC_WARN_PRECISION = 4, /* QOC_BF16X3: the automatic policy ran some product
                             classes in FP32 (qoc_info.bf16x3_classes) because
                             the predicted bf16x3 error exceeded its budget */
+  QOC_WARN_UNITARITY = 8, /* the FP64 unitarity check (qoc_set_unitarity_check)
+                             found max |(U^H U - I)_{rc}| above drift_warn */
+  QOC_WARN_NO_PAIR = 16   /* device-pointer calls (reported by qoc_get_info):
+                             no (p, n) within the path's capacity met
+                             taylor_tol at the call's theta_max, or theta_max
+                             was not finite (NaN / Inf amplitudes); the call
+                             ran with a clamped pair and its results are not
+                             accurate.  Host-array calls return
+                             QOC_ERR_UNSUPPORTED instead. */
 };
 
 /* Product classes of the QOC_BF16X3 precision: each class runs as bf16x3
@@ -144,6 +153,11 @@ typedef struct {
   int flags;                /* warning bits (QOC_WARN_*) of the last call    */
   size_t device_bytes;      /* device memory held by the handle              */
   int bf16x3_classes;       /* QOC_BF3_* classes that ran bf16x3 products     */
+  double unitarity_drift;   /* max over the checked steps of
+                               max_{r,c} |(D_j + D_j^H + D_j^H D_j)_{rc}| =
+                               |(U_j^H U_j - I)_{rc}|, evaluated in FP64 (kept
+                               to FP32 precision); -1 when the last call ran
+                               no check (qoc_set_unitarity_check)           */
 } qoc_info;
 
 /* Create a handle: validates and copies the problem to device memory.
@@ -247,7 +261,10 @@ qoc_status qoc_profile_read(qoc_handle *h, double *ms, long long *calls,
 qoc_status qoc_taylor_select(double theta, double tol, int *p, int *n);
 
 /* Fix the global (p, n) of later calls on h (p in [2, 64], n in [0, 60]),
- * or return to the per-call choice (p = 0).  A fixed pair makes the
+ * or return to the per-call choice (p = 0).  A pair beyond the capacity of
+ * the handle's path (p <= 16 and n <= 16 on the small-d path, padded d <=
+ * 48; p <= 30 on the batched path) is QOC_ERR_UNSUPPORTED, here and in
+ * qoc_create.  A fixed pair makes the
  * device-pointer calls free of host round trips (HIP-graph capturable);
  * each call checks it against taylor_tol on the device and reports a miss
  * as QOC_WARN_TAYLOR.  Sec. III: one conservative pair for all steps. */
@@ -268,6 +285,17 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n);
  * Returns QOC_ERR_ARG for a mask outside -1..QOC_BF3_ALL.  Sec. III
  * (truncated Taylor series with scaling and squaring), Sec. II.B. */
 qoc_status qoc_set_bf16x3(qoc_handle *h, int classes);
+
+/* FP64 unitarity check of later calls: every stride-th step propagator
+ * (steps N-1, N-1-stride, ...; stride 1 checks every step) is tested for
+ * max_{r,c} |(U_j^H U_j - I)_{rc}| with U_j = I + D_j, computed in FP64 on
+ * the MFMA from the stored D_j; the maximum is reported in
+ * qoc_info.unitarity_drift and flagged by QOC_WARN_UNITARITY above
+ * drift_warn.  stride 0 (the default) turns the check off: it is one extra
+ * launch of about N / stride FP64 products, which at padded d 16 costs a few
+ * percent of a call.  Returns QOC_ERR_ARG for stride < 0.  Sec. III (the
+ * truncated series keeps unitarity only to its truncation error). */
+qoc_status qoc_set_unitarity_check(qoc_handle *h, int stride);
 
 /* Kernel variant of the sweeps of later calls (a tuning knob; results are
  * the same up to rounding order).  which: 0 forward block sweep, 1 forward

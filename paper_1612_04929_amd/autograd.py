@@ -31,13 +31,16 @@ class QocCostGrad(torch.autograd.Function):
     """(C, C_fid, c) = QocCostGrad.apply(u, problem); dC/du in backward."""
 
     @staticmethod
-    def forward(ctx, u, problem):
+    def forward(ctx, u, problem, check=False):
         _check_u(u, problem)
         uc = u.detach().contiguous()
         out = torch.empty(2 + problem.N, dtype=torch.float64, device=u.device)
         grad = torch.empty(max(1, problem.M * problem.N), dtype=torch.float64, device=u.device)
         stream = torch.cuda.current_stream(u.device).cuda_stream
         problem.cost_grad_device(uc.data_ptr(), out.data_ptr(), grad.data_ptr(), stream)
+        if check:
+            # synchronises: raises if the call ran with a clamped (p, n)
+            problem.check_last()
         C, C_fid, c = out[0], out[1], out[2:]
         ctx.save_for_backward(grad)
         ctx.shape = (problem.M, problem.N)
@@ -49,9 +52,11 @@ class QocCostGrad(torch.autograd.Function):
         (grad,) = ctx.saved_tensors
         M, N = ctx.shape
         g = grad[: M * N].view(M, N)
-        return (gC * g if gC is not None else None), None
+        return (gC * g if gC is not None else None), None, None
 
 
-def cost(u: torch.Tensor, problem: Problem):
-    """Differentiable weighted cost C(u) (plus C_fid and c_1..c_N)."""
-    return QocCostGrad.apply(u, problem)
+def cost(u: torch.Tensor, problem: Problem, check: bool = False):
+    """Differentiable weighted cost C(u) (plus C_fid and c_1..c_N).  With
+    check=True the call synchronises and raises if no (p, n) met the
+    tolerance (QOC_WARN_NO_PAIR)."""
+    return QocCostGrad.apply(u, problem, check)

@@ -146,9 +146,9 @@ class Batch:
         torch.cuda.synchronize(self.dev)
         changed = 0
         for i, h in enumerate(self.handles):
+            inf = h.check_last()  # raises on a clamped pair (QOC_WARN_NO_PAIR)
             if self.pn[i] is None:
                 continue
-            inf = h.info()
             tol = self.tol
             p, n = self.pn[i]
             if (inf["flags"] & qoc.QOC_WARN_TAYLOR) or not taylor_ok(p, n, inf["theta_max"] * ahead,

@@ -152,4 +152,76 @@ template hipError_t launch_ext<float>(const SweepArgs<float> &, const ExtArgs<fl
 template hipError_t launch_ext<double>(const SweepArgs<double> &, const ExtArgs<double> &,
                                        hipStream_t);
 
+
+// ---------------------------------------------------------------------------
+// Unitarity drift of the step propagators (Sec. III: the truncated series
+// with scaling and squaring is only approximately unitary): with U = I + D,
+//   U^H U - I = D + D^H + D^H D,
+// whose largest entry magnitude over the checked steps is accumulated in
+// FP64 (products on the FP64 MFMA from operands converted to FP64).  One
+// wavefront per 16 x 16 tile of one checked step; the checked steps are
+// j = N-1, N-1-stride, ...  The result is folded into *acc with one atomic
+// maximum per wavefront on (epoch << 32 | FP32 bits of the tile maximum):
+// a later call (larger epoch) supersedes every earlier value without a
+// clearing launch, and positive FP32 values order like their bit patterns.
+namespace {
+template <typename T>
+__global__ __launch_bounds__(256) void k_unitarity(const T *__restrict__ D, int dp, int d, int N,
+                                                   int stride, int nchk, unsigned epoch,
+                                                   unsigned long long *acc) {
+  const int tdim = dp / 16, tiles = tdim * tdim;
+  const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wave >= (long)nchk * tiles) return;  // wavefront-uniform; no barrier below
+  const int q = (int)(wave / tiles), t = (int)(wave - (long)q * tiles);
+  const int r0 = (t / tdim) * 16, c0 = (t % tdim) * 16;
+  const long j = (long)N - 1 - (long)q * stride;
+  const long plane = (long)dp * dp;
+  const T *Dr = D + j * 2 * plane, *Di = Dr + plane;
+  const int lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
+  f64x4 cr = vzero<double>(), ci = vzero<double>();
+  // (D^H D)_{rc} = sum_k conj(D_{kr}) D_{kc}: A = D^H, B = D
+  for (int k = 0; k < dp; k += 4) {
+    const long oa = (long)(k + kk) * dp + (r0 + i), ob = (long)(k + kk) * dp + (c0 + i);
+    const double ar = (double)Dr[oa], ai = -(double)Di[oa];
+    const double br = (double)Dr[ob], bi = (double)Di[ob];
+    cr = mfma4(ar, br, cr);
+    cr = mfma4(-ai, bi, cr);
+    ci = mfma4(ar, bi, ci);
+    ci = mfma4(ai, br, ci);
+  }
+  double m = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = r0 + acc_row<double>(lane, v), c = c0 + i;
+    if (r < d && c < d) {
+      // + D_{rc} + conj(D_{cr})
+      const double er = cr[v] + (double)Dr[(long)r * dp + c] + (double)Dr[(long)c * dp + r];
+      const double ei = ci[v] + (double)Di[(long)r * dp + c] - (double)Di[(long)c * dp + r];
+      m = fmax(m, sqrt(er * er + ei * ei));
+    }
+  }
+  m = wave_max(m);
+  if (lane == 0) {
+    const float mf = (float)m;
+    atomicMax(acc, ((unsigned long long)epoch << 32) | (unsigned long long)__float_as_uint(mf));
+  }
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_unitarity(const T *D, int dp, int d, int N, int stride, unsigned epoch,
+                            unsigned long long *acc, hipStream_t st) {
+  if (N <= 0 || stride <= 0) return hipSuccess;
+  const int nchk = (N + stride - 1) / stride;
+  const long waves = (long)nchk * (dp / 16) * (dp / 16);
+  hipLaunchKernelGGL(k_unitarity<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, D, dp, d,
+                     N, stride, nchk, epoch, acc);
+  return hipGetLastError();
+}
+
+template hipError_t launch_unitarity<float>(const float *, int, int, int, int, unsigned,
+                                            unsigned long long *, hipStream_t);
+template hipError_t launch_unitarity<double>(const double *, int, int, int, int, unsigned,
+                                             unsigned long long *, hipStream_t);
+
 }  // namespace qoc

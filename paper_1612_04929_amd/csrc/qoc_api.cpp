@@ -173,6 +173,11 @@ struct qoc_handle {
   int bf3_used = 0;  // classes that ran bf16x3 products in the last call
   int bf3_fallback = 0;  // the automatic choice moved some classes to FP32
   bool capturing = false;  // the current call's stream is capturing a HIP graph
+  // FP64 unitarity check of the step propagators: every `unit_stride`-th
+  // step (0: off); its result word carries the call's epoch
+  int unit_stride = 0;
+  unsigned epoch = 0, unit_epoch = 0;
+  double last_unitarity = -1.0;
   // per-call work space carved from the static device scratch instead of
   // the handle's own allocations (the no-alloc entry point)
   unsigned char *ws_base = nullptr;
@@ -214,7 +219,7 @@ struct qoc_handle {
   int levels_alloc = 0;
   void *ckpt = nullptr, *lam_ckpt = nullptr, *mu = nullptr;  // (nb+1) sets
   void *psi_buf = nullptr, *lam_buf = nullptr;                // N+1, N sets
-  unsigned long long *bits = nullptr;  // [theta, drift, norm ticket, -, norm accumulator]
+  unsigned long long *bits = nullptr;  // [theta, drift, norm ticket, unitarity, norm accumulator]
   double *zinfo = nullptr;    // 3 + 2S
   double *part = nullptr;     // 4 x npart
   int *pn_dev = nullptr;      // device-side (p, n, status)
@@ -650,6 +655,27 @@ hipError_t taylor_ps(qoc_handle *h, const PsPlan &ps, int p, int nslots, T *X, T
   return hipSuccess;
 }
 
+// Whether a handle runs the small-d path (device-side (p, n), chains in LDS).
+bool on_small_path(const qoc_handle *h) {
+  return h->prec == QOC_FP64
+             ? (qoc::small_expm_ok<double>(h->dp) && qoc::small_sweep_ok<double>(h->dp, h->S))
+             : (qoc::small_expm_ok<float>(h->dp) && qoc::small_sweep_ok<float>(h->dp, h->S));
+}
+
+// A fixed pair within the capacity of the handle's path: p <= 16 and
+// n <= 16 on the small-d path (its preallocated levels and chains), p <= 30
+// and n <= 60 on the batched path (the device-side check of the pair).
+qoc_status check_fixed_pair(const qoc_handle *h, int p, int n) {
+  if (p == 0) return QOC_OK;
+  const bool sp = on_small_path(h);
+  const int pc = sp ? kSmallPCap : 30, nc = sp ? kSmallNCap : 60;
+  if (p > pc || n > nc)
+    return fail(QOC_ERR_UNSUPPORTED, "fixed (p, n) = (" + std::to_string(p) + ", " +
+                                         std::to_string(n) + ") exceeds this path's capacity (p <= " +
+                                         std::to_string(pc) + ", n <= " + std::to_string(nc) + ")");
+  return QOC_OK;
+}
+
 // A fixed (p, n) on the small-d path, as the device applies it (clamped to
 // the preallocated capacity), and the cotangent rank bound it implies.
 std::pair<int, int> small_fixed_pn(const qoc_handle *h) {
@@ -831,6 +857,13 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     }
     E = in;
   }
+  // FP64 unitarity drift of the final propagators (a diagnostic; at padded
+  // d 16 after the block products, which may recompute D with the chosen pair)
+  h->unit_epoch = 0;
+  if (h->unit_stride > 0) {
+    h->unit_epoch = ++h->epoch;
+    HIP_TRY(qoc::launch_unitarity<T>(D, dp, h->d, N, h->unit_stride, h->unit_epoch, h->bits + 3, st));
+  }
   qoc::SweepArgs<T> sw{};
   sw.N = N; sw.L = h->L; sw.nb = h->nb; sw.dp = dp; sw.d = h->d; sw.S = S; sw.M = M;
   sw.D = D; sw.E = E; sw.Dh = Dh_small; sw.Eh = Dh_small ? (const T *)h->Eh : nullptr; sw.psi0 = (const T *)h->psi0; sw.ckpt = (T *)h->ckpt;
@@ -974,8 +1007,18 @@ qoc_status run_any(qoc_handle *h, const double *u_dev, double *out_dev, double *
   return run<float>(h, u_dev, out_dev, grad_dev, st, want_grad);
 }
 
+// The unitarity word of the last call: (epoch << 32 | FP32 bits); -1 when
+// the call ran no check.
+double unitarity_of(const qoc_handle *h, unsigned long long word) {
+  if (h->unit_epoch == 0 || (unsigned)(word >> 32) != h->unit_epoch) return -1.0;
+  const unsigned bitsf = (unsigned)(word & 0xffffffffu);
+  float f;
+  std::memcpy(&f, &bitsf, sizeof(f));
+  return (double)f;
+}
+
 qoc_status finish_diag(qoc_handle *h, hipStream_t st, int *flags) {
-  unsigned long long b[2] = {0, 0};
+  unsigned long long b[4] = {0, 0, 0, 0};
   int pn[3] = {0, 0, 0};
   HIP_TRY(hipMemcpyAsync(b, h->bits, sizeof(b), hipMemcpyDeviceToHost, st));
   const bool small_path = h->prec == QOC_FP64
@@ -995,9 +1038,11 @@ qoc_status finish_diag(qoc_handle *h, hipStream_t st, int *flags) {
   std::memcpy(&dr, &b[1], 8);
   h->last_theta = th;
   h->last_drift = dr;
+  h->last_unitarity = unitarity_of(h, b[3]);
   h->last_flags = ((dr > h->drift_warn) ? QOC_WARN_DRIFT : 0) |
                   ((dev_pn && pn[2] == 2) ? QOC_WARN_TAYLOR : 0) |
-                  (h->bf3_fallback ? QOC_WARN_PRECISION : 0);
+                  (h->bf3_fallback ? QOC_WARN_PRECISION : 0) |
+                  ((h->last_unitarity > h->drift_warn) ? QOC_WARN_UNITARITY : 0);
   if (flags) *flags = h->last_flags;
   if (h->prof) return drain_pending(h);
   return QOC_OK;
@@ -1044,8 +1089,17 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n) {
   if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
   if (!(p == 0 || (p >= 2 && p <= 64 && n >= 0 && n <= 60)))
     return fail(QOC_ERR_ARG, "p must be 0 (automatic) or in [2, 64] with n in [0, 60]");
+  const qoc_status s = check_fixed_pair(h, p, n);
+  if (s) return s;
   h->fixed_p = p;
   h->fixed_n = p ? n : 0;
+  return QOC_OK;
+}
+
+qoc_status qoc_set_unitarity_check(qoc_handle *h, int stride) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  if (stride < 0) return fail(QOC_ERR_ARG, "stride must be >= 0");
+  h->unit_stride = stride;
   return QOC_OK;
 }
 
@@ -1144,6 +1198,11 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
   h->drift_warn = D.drift_warn > 0 ? D.drift_warn : 1e-4;
   h->fixed_p = D.taylor_p;
   h->fixed_n = D.taylor_n;
+  if (check_fixed_pair(h, h->fixed_p, h->fixed_n) != QOC_OK) {
+    const std::string msg = g_err;
+    delete h;
+    return fail(QOC_ERR_UNSUPPORTED, msg);
+  }
   h->device = D.device;
   if (D.checkpoint_every > 0) {
     h->L = pow2_at_least(D.checkpoint_every);
@@ -1348,10 +1407,11 @@ qoc_status qoc_get_info(const qoc_handle *hc, qoc_info *info) {
     DeviceGuard g(h->device);
     if (!g.ok) return fail(QOC_ERR_DEVICE, "hipSetDevice failed");
     HIP_TRY(hipDeviceSynchronize());
-    unsigned long long b[2] = {0, 0};
+    unsigned long long b[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpy(b, h->bits, sizeof(b), hipMemcpyDeviceToHost));
     std::memcpy(&h->last_theta, &b[0], 8);
     std::memcpy(&h->last_drift, &b[1], 8);
+    h->last_unitarity = unitarity_of(h, b[3]);
     int pn[3] = {0, 0, 0};
     HIP_TRY(hipMemcpy(pn, h->pn_dev, sizeof(pn), hipMemcpyDeviceToHost));
     if (pn[0] >= 2 && h->fixed_p == 0 && h->last_p == 0) {
@@ -1368,7 +1428,9 @@ qoc_status qoc_get_info(const qoc_handle *hc, qoc_info *info) {
     }
     h->last_flags = ((h->last_drift > h->drift_warn) ? QOC_WARN_DRIFT : 0) |
                     (((small_path || h->fixed_p >= 2) && pn[2] == 2) ? QOC_WARN_TAYLOR : 0) |
-                    (h->bf3_fallback ? QOC_WARN_PRECISION : 0);
+                    (((small_path || h->fixed_p >= 2) && pn[2] == 1) ? QOC_WARN_NO_PAIR : 0) |
+                    (h->bf3_fallback ? QOC_WARN_PRECISION : 0) |
+                    ((h->last_unitarity > h->drift_warn) ? QOC_WARN_UNITARITY : 0);
   }
   info->flags = h->last_flags;
   info->p = h->last_p;
@@ -1380,6 +1442,7 @@ qoc_status qoc_get_info(const qoc_handle *hc, qoc_info *info) {
   info->d_pad = h->dp;
   info->device_bytes = h->bytes;
   info->bf16x3_classes = h->bf3_used;
+  info->unitarity_drift = h->last_unitarity;
   return QOC_OK;
 }
 

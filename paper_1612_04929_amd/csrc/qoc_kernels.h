@@ -171,6 +171,14 @@ template <typename T> struct ExtArgs {
 };
 template <typename T>
 hipError_t launch_ext(const SweepArgs<T> &a, const ExtArgs<T> &e, hipStream_t st);
+
+// FP64 unitarity drift max |(D + D^H + D^H D)_{rc}| of the final step
+// propagators U_j = I + D_j (true d x d block) over the steps N-1,
+// N-1-stride, ..., folded into *acc as (epoch << 32 | FP32 bits) by atomic
+// maximum (kernels_ext.hip).
+template <typename T>
+hipError_t launch_unitarity(const T *D, int dp, int d, int N, int stride, unsigned epoch,
+                            unsigned long long *acc, hipStream_t st);
 template <typename T> hipError_t launch_fwd_blocks(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_bwd_blocks(const SweepArgs<T> &a, hipStream_t st);

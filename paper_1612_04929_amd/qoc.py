@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libqoc.so")
 QOC_FP64, QOC_FP32, QOC_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": QOC_FP64, "fp32": QOC_FP32, "bf16x3": QOC_BF16X3}
 QOC_FID_COHERENT, QOC_FID_INCOHERENT = 0, 1
-QOC_WARN_DRIFT, QOC_WARN_TAYLOR, QOC_WARN_PRECISION = 1, 2, 4
+QOC_WARN_DRIFT, QOC_WARN_TAYLOR, QOC_WARN_PRECISION, QOC_WARN_UNITARITY = 1, 2, 4, 8
+QOC_WARN_NO_PAIR = 16
 QOC_BF3_TAYLOR, QOC_BF3_SQUARING, QOC_BF3_BLOCKPROD, QOC_BF3_ADJOINT = 1, 2, 4, 8
 QOC_BF3_ALL = 15
 PHASES = ["norm", "assemble", "taylor", "blockprod", "fwd_blocks", "fwd_replay", "cost",
@@ -31,7 +32,7 @@ EXPORTS = ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
            "qoc_cost_grad_device_noalloc",
            "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
            "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
-           "qoc_set_bf16x3", "qoc_destroy",
+           "qoc_set_bf16x3", "qoc_set_unitarity_check", "qoc_destroy",
            "qoc_status_string",
            "qoc_last_error", "qoc_version"]
 
@@ -53,7 +54,7 @@ class Info(C.Structure):
     _fields_ = [("p", C.c_int), ("n", C.c_int), ("theta_max", C.c_double),
                 ("norm_drift", C.c_double), ("block_len", C.c_int), ("n_blocks", C.c_int),
                 ("d_pad", C.c_int), ("flags", C.c_int), ("device_bytes", C.c_size_t),
-                ("bf16x3_classes", C.c_int)]
+                ("bf16x3_classes", C.c_int), ("unitarity_drift", C.c_double)]
 
 
 class QocError(RuntimeError):
@@ -100,6 +101,7 @@ def load(path: str = LIB_PATH):
     lib.qoc_set_taylor.argtypes = [vp, C.c_int, C.c_int]
     lib.qoc_set_sweep.argtypes = [vp, C.c_int, C.c_int]
     lib.qoc_set_bf16x3.argtypes = [vp, C.c_int]
+    lib.qoc_set_unitarity_check.argtypes = [vp, C.c_int]
     lib.qoc_destroy.argtypes = [vp]
     lib.qoc_destroy.restype = None
     for f in ["qoc_status_string", "qoc_last_error", "qoc_version"]:
@@ -109,7 +111,7 @@ def load(path: str = LIB_PATH):
               "qoc_cost_grad_device_noalloc",
               "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
               "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
-              "qoc_set_bf16x3"]:
+              "qoc_set_bf16x3", "qoc_set_unitarity_check"]:
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -232,13 +234,27 @@ class Problem:
         a bf16x3 handle; -1 restores the automatic choice."""
         _check(load().qoc_set_bf16x3(self._h, int(classes)))
 
+    def check_last(self):
+        """Raise QocError if the last device-pointer call ran with a clamped
+        (p, n) (QOC_WARN_NO_PAIR: no pair met the tolerance within the
+        path's capacity, or theta_max was not finite).  Synchronises."""
+        inf = self.info()
+        if inf["flags"] & QOC_WARN_NO_PAIR:
+            raise QocError(-7, f"no (p, n) met the tolerance at theta_max = {inf['theta_max']}; "
+                               "the last call's results are not accurate")
+        return inf
+
+    def set_unitarity_check(self, stride: int):
+        """FP64 check of max |(U^H U - I)_{rc}| on every stride-th step (0: off)."""
+        _check(load().qoc_set_unitarity_check(self._h, int(stride)))
+
     def info(self):
         inf = Info()
         _check(load().qoc_get_info(self._h, C.byref(inf)))
         return dict(p=inf.p, n=inf.n, theta_max=inf.theta_max, norm_drift=inf.norm_drift,
                     block_len=inf.block_len, n_blocks=inf.n_blocks, d_pad=inf.d_pad,
                     flags=inf.flags, device_bytes=inf.device_bytes,
-                    bf16x3_classes=inf.bf16x3_classes)
+                    bf16x3_classes=inf.bf16x3_classes, unitarity_drift=inf.unitarity_drift)
 
     def profile_enable(self, on=True):
         _check(load().qoc_profile_enable(self._h, 1 if on else 0))
