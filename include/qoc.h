@@ -158,6 +158,8 @@ typedef struct {
                                |(U_j^H U_j - I)_{rc}|, evaluated in FP64 (kept
                                to FP32 precision); -1 when the last call ran
                                no check (qoc_set_unitarity_check)           */
+  int structured;           /* 1 when the last call ran the structured
+                               (sparse) norm and gradient contraction       */
 } qoc_info;
 
 /* Create a handle: validates and copies the problem to device memory.
@@ -285,6 +287,20 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n);
  * Returns QOC_ERR_ARG for a mask outside -1..QOC_BF3_ALL.  Sec. III
  * (truncated Taylor series with scaling and squaring), Sec. II.B. */
 qoc_status qoc_set_bf16x3(qoc_handle *h, int classes);
+
+/* Structured Hamiltonians (Sec. IV and the Conclusion: sparse matrices,
+ * e.g. a diagonal drift and permutation-like controls).  On the batched
+ * path (padded d >= 64) qoc_create records the union of the nonzero
+ * patterns of H_0 .. H_M when it has at most d^2 / 4 entries; then the FP64
+ * step norms sum each column over the union only, and (for M <= 32 and a
+ * derivative panel width p R <= 512) the gradient contraction g_{k,j} =
+ * 2 s Im tr(Xbar_j^H H_k) forms Xbar_j at the nonzeros of the controls
+ * alone instead of storing the dense d x d Xbar_j.  The Taylor,
+ * squaring and block products stay dense (the step propagators are dense).
+ * mode -1 (default): structured when the union has at most d^2 / 16
+ * entries; 0: dense; 1: structured (QOC_ERR_UNSUPPORTED when no pattern was
+ * recorded).  Results agree with the dense kernels up to summation order. */
+qoc_status qoc_set_structure(qoc_handle *h, int mode);
 
 /* FP64 unitarity check of later calls: every stride-th step propagator
  * (steps N-1, N-1-stride, ...; stride 1 checks every step) is tested for

@@ -406,6 +406,102 @@ template <typename T> __global__ __launch_bounds__(256) void k_gcontract(GContra
   }
 }
 
+// Structured control Hamiltonians: g_{k,j} partials over the nonzeros of
+// the controls only.  Xbar_j is formed at each entry (r, c) of the union of
+// the controls' patterns from the derivative's panels,
+//   Xbar_j[r][c] = sum_{kb < p} sum_{i < rr} P[r][(2 kb + 1) rr + i]
+//                  conj(P[c][(2 (p - 1 - kb)) rr + i])
+// (At_{kb+1} V_{kb+2}^H, the product k_xstore would store), and contracted
+// with every control that has a nonzero there: g += Im(conj(Xbar) h), which
+// is linear in Xbar, so each lane contracts its own share of the inner
+// index and keeps per-control sums of its own (FP64, in LDS), summed over
+// lanes and wavefronts in a fixed order at the end.  Workgroup (g, j) takes
+// the rows r = g, g + SG_GROUPS, ... of step j, one row per wavefront at a
+// time: the row's panel entries are loaded once (consecutive lanes read
+// consecutive entries) and serve every union entry of the row; the entries
+// of a row go in batches of SG_BATCH with all their loads in flight.
+constexpr int SG_GROUPS = 4, SG_AREG = 8, SG_BATCH = 4;
+// per-lane sums of one control: 4 wavefronts x 64 lanes FP64
+constexpr int SG_LDS_PER_CONTROL = 4 * 64 * 8;
+template <typename T> struct SContract {
+  const T *panel;  // step 0's panel (real plane; imaginary at + big)
+  long per, big;
+  int ld, rr, p;
+  const int *rptr, *rcol;  // union of the controls' patterns, by rows
+  const int *eptr, *ek;    // controls with a nonzero at each union entry
+  const T *eval;           // their values, [2][nev]
+  long nev;
+  double *part;
+  int N, M, d;
+};
+
+template <typename T> __global__ __launch_bounds__(256) void k_sgcontract(SContract<T> a) {
+  extern __shared__ double gsh[];  // [4 waves][M][64 lanes]
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = blockIdx.x;
+  const long j = blockIdx.y;
+  double *acc = gsh + (long)w * a.M * 64 + lane;
+  for (int k = 0; k < a.M; ++k) acc[k * 64] = 0.0;
+  const T *Pr = a.panel + j * a.per, *Pi = Pr + a.big;
+  const int K = a.p * a.rr;
+  // this lane's inner indices i = lane + 64 q and their panel columns
+  long ca[SG_AREG], cb[SG_AREG];
+  bool iv[SG_AREG];
+#pragma unroll
+  for (int q = 0; q < SG_AREG; ++q) {
+    const int i = lane + 64 * q;
+    iv[q] = i < K;
+    const int kb = iv[q] ? i / a.rr : 0, ii = iv[q] ? i - kb * a.rr : 0;
+    ca[q] = (long)(2 * kb + 1) * a.rr + ii;
+    cb[q] = (long)(2 * (a.p - 1 - kb)) * a.rr + ii;
+  }
+  for (int r = g + SG_GROUPS * w; r < a.d; r += 4 * SG_GROUPS) {
+    const int e0 = a.rptr[r], e1 = a.rptr[r + 1];
+    if (e0 == e1) continue;  // wavefront-uniform
+    const long ro = (long)r * a.ld;
+    T ar[SG_AREG], ai[SG_AREG];
+#pragma unroll
+    for (int q = 0; q < SG_AREG; ++q) {
+      ar[q] = iv[q] ? Pr[ro + ca[q]] : (T)0;
+      ai[q] = iv[q] ? Pi[ro + ca[q]] : (T)0;
+    }
+    for (int e = e0; e < e1; e += SG_BATCH) {
+      T br[SG_BATCH][SG_AREG], bi[SG_BATCH][SG_AREG];
+#pragma unroll
+      for (int u = 0; u < SG_BATCH; ++u) {
+        const long co = (long)a.rcol[e + u < e1 ? e + u : e] * a.ld;
+#pragma unroll
+        for (int q = 0; q < SG_AREG; ++q) {
+          br[u][q] = iv[q] ? Pr[co + cb[q]] : (T)0;
+          bi[u][q] = iv[q] ? Pi[co + cb[q]] : (T)0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SG_BATCH; ++u) {
+        if (e + u < e1) {  // wavefront-uniform
+          T xr = 0, xi = 0;
+#pragma unroll
+          for (int q = 0; q < SG_AREG; ++q) {
+            xr += ar[q] * br[u][q] + ai[q] * bi[u][q];  // a conj(b)
+            xi += ai[q] * br[u][q] - ar[q] * bi[u][q];
+          }
+          for (int q = a.eptr[e + u]; q < a.eptr[e + u + 1]; ++q) {
+            const double hr = (double)a.eval[q], hi = (double)a.eval[a.nev + q];
+            acc[a.ek[q] * 64] += (double)xr * hi - (double)xi * hr;  // Im(conj(Xbar) h)
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < a.M; k += 256) {
+    double s = 0.0;
+    for (int ww = 0; ww < 4; ++ww)
+      for (int l = 0; l < 64; ++l) s += gsh[((long)ww * a.M + k) * 64 + l];
+    a.part[(j * SG_GROUPS + g) * a.M + k] = s;
+  }
+}
+
 template <typename T> struct AdjPrep {
   const T *lam_buf, *psi_buf;
   T *scratch;
@@ -668,6 +764,20 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
     tb.split[0] = rr;
     tb.nhalf = 1; tb.N = N; tb.dp = dp; tb.W = 2 * rr;
     if ((e = launch_thin(tb)) != hipSuccess) return e;
+  }
+  // ---- structured control Hamiltonians: Xbar only at their nonzeros
+  if (a.rptr && (long)M * SG_LDS_PER_CONTROL <= 64 * 1024 && (long)p * rr <= 64 * SG_AREG) {
+    if (M > 0) {
+      SContract<T> sc2{sc + 8 * thin, per, big, (int)KK2, rr, p, a.rptr, a.rcol, a.eptr, a.ek,
+                       a.eval, a.nev, a.part, N, M, a.d};
+      hipLaunchKernelGGL(k_sgcontract<T>, dim3(SG_GROUPS, N), dim3(256),
+                         (size_t)M * SG_LDS_PER_CONTROL, st, sc2);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    AdjFinish<T> f{a.part, a.u, a.grad, 2.0 * a.s_scale, a.alpha_amp, a.alpha_var, nullptr, N, M,
+                   SG_GROUPS};
+    hipLaunchKernelGGL(k_adj_finish<T>, dim3(grid_for((long)N * M)), dim3(256), 0, st, f);
+    return hipGetLastError();
   }
   // ---- Xbar = sum_k At_k V_{k+1}^H, stored, then contracted with every H_k
   {

@@ -29,7 +29,7 @@ template <int COLS>
 __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
                                               const double *__restrict__ u, int d, int M, int N,
                                               double dt, unsigned long long *theta_bits,
-                                              SelectArgs sel, int hs_lds) {
+                                              SelectArgs sel, int hs_lds, SparseU sp) {
   constexpr int NRM_SW = NrmSw<COLS>::value;
   constexpr int LANES = 256 / COLS, STEPS = LANES * NRM_SW;
   extern __shared__ __align__(16) double coef[];  // [STEPS][M] amplitudes, then (hs) the
@@ -68,7 +68,30 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
   double nrm[NRM_SW];
 #pragma unroll
   for (int s = 0; s < NRM_SW; ++s) nrm[s] = 0.0;
-  if (col < d) {
+  if (col < d && sp.colptr) {
+    // structured Hamiltonians: the union entries of this column only
+    const int e0 = sp.colptr[col], e1 = sp.colptr[col + 1];
+    for (int e = e0; e < e1; ++e) {
+      const double *v = sp.vals + (long)e * (M + 1) * 2;
+      double hr[NRM_SW], hi[NRM_SW];
+#pragma unroll
+      for (int s = 0; s < NRM_SW; ++s) {
+        hr[s] = v[0];
+        hi[s] = v[1];
+      }
+      for (int k = 0; k < M; ++k) {
+        const double vr = v[2 * (k + 1)], vi = v[2 * (k + 1) + 1];
+#pragma unroll
+        for (int s = 0; s < NRM_SW; ++s) {
+          const double c = cw[s * M + k];
+          hr[s] += c * vr;
+          hi[s] += c * vi;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < NRM_SW; ++s) nrm[s] += sqrt(hr[s] * hr[s] + hi[s] * hi[s]);
+    }
+  } else if (col < d) {
     const long dd = (long)d * d;
 #pragma unroll 4
     for (int r = 0; r < d; ++r) {
@@ -154,16 +177,18 @@ __global__ __launch_bounds__(256) void k_norm(const double *__restrict__ H64,
 }
 
 hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, double dt,
-                       unsigned long long *theta_bits, const SelectArgs &sel, hipStream_t st) {
+                       unsigned long long *theta_bits, const SelectArgs &sel, hipStream_t st,
+                       const SparseU *sp) {
+  const SparseU spv = sp ? *sp : SparseU{nullptr, nullptr, nullptr};
   auto go = [&](auto cols) {
     constexpr int COLS = decltype(cols)::value, STEPS = 256 / COLS * NrmSw<COLS>::value;
     dim3 grid((N + STEPS - 1) / STEPS, (d + COLS - 1) / COLS);
     const size_t shc = sizeof(double) * STEPS * M;
     const size_t shh = sizeof(double) * (size_t)(M + 1) * d * d * 2;
-    const int hs_lds = (COLS < 64 && shc + shh <= 48 * 1024) ? 1 : 0;
+    const int hs_lds = (COLS < 64 && shc + shh <= 48 * 1024 && !spv.colptr) ? 1 : 0;
     const size_t shm = shc + (hs_lds ? shh : 0);
     hipLaunchKernelGGL(k_norm<COLS>, grid, dim3(256), shm, st, H64, u, d, M, N, dt, theta_bits,
-                       sel, hs_lds);
+                       sel, hs_lds, spv);
   };
   if (d > 32)
     go(std::integral_constant<int, 64>());

@@ -196,6 +196,18 @@ struct qoc_handle {
   void *src = nullptr;        // (N + 1) state sets of costate sources
   double *ext_part = nullptr; // 2 x next
   int next = 1;
+  // structured (sparse) Hamiltonians on the batched path: the union pattern
+  // in compressed columns for the norm, and per-control nonzero lists for
+  // the gradient contraction; built when the union has at most d^2 / 4
+  // entries, used by default at most d^2 / 16 (qoc_set_structure)
+  bool sp_built = false, sp_auto = false;
+  int sp_mode = -1;  // -1 automatic, 0 dense, 1 structured
+  bool sp_used = false;
+  long nnz_union = 0, nev = 0;
+  int *sp_colptr = nullptr, *sp_rowidx = nullptr;
+  double *sp_vals = nullptr;
+  int *sp_rptr = nullptr, *sp_rcol = nullptr, *sp_eptr = nullptr, *sp_ek = nullptr;
+  void *sp_eval = nullptr;
   int fixed_p = 0, fixed_n = 0;
   int L = 1, nb = 1, device = 0;
   size_t esize = 4;  // sizeof(T) of the chain precision
@@ -294,6 +306,9 @@ void release(qoc_handle *h) {
                    (void **)&h->grad_dev, &h->psi0, (void **)&h->psiT64, (void **)&h->w64,
                    &h->pw, &h->X, &h->Qa, &h->Qb, &h->Eh, &h->Es, &h->Ehs, &h->nu, &h->Dlev,
                    (void **)&h->forb64, &h->src, (void **)&h->ext_part,
+                   (void **)&h->sp_colptr, (void **)&h->sp_rowidx, (void **)&h->sp_vals,
+                   (void **)&h->sp_rptr, (void **)&h->sp_rcol, (void **)&h->sp_eptr,
+                   (void **)&h->sp_ek, &h->sp_eval,
                    &h->ckpt, &h->lam_ckpt, &h->mu,
                    &h->psi_buf, &h->lam_buf, (void **)&h->bits,
                    (void **)&h->zinfo, (void **)&h->part, (void **)&h->pn_dev,
@@ -455,6 +470,88 @@ template <typename T> bool split_sweeps(const qoc_handle *h) {
          h->L % qoc::SUB16 == 0 && h->L <= 8 * qoc::SUB16;
 }
 
+// Union pattern and per-control nonzero lists of the (Hermitian parts of
+// the) Hamiltonians, for the structured kernels of the batched path.
+template <typename T>
+qoc_status build_structure(qoc_handle *h, const std::vector<double> &h64) {
+  const int d = h->d, M = h->M;
+  if (h->dp < 64) return QOC_OK;  // the small-d path keeps dense tiles
+  const size_t dd = (size_t)d * d;
+  auto nz = [&](int k, size_t rc) { return h64[(k * dd + rc) * 2] != 0.0 || h64[(k * dd + rc) * 2 + 1] != 0.0; };
+  std::vector<int> colptr(d + 1, 0), rowidx;
+  for (int c = 0; c < d; ++c) {
+    for (int r = 0; r < d; ++r) {
+      bool any = false;
+      for (int k = 0; k <= M && !any; ++k) any = nz(k, (size_t)r * d + c);
+      if (any) rowidx.push_back(r);
+    }
+    colptr[c + 1] = (int)rowidx.size();
+  }
+  h->nnz_union = (long)rowidx.size();
+  if (h->nnz_union * 4 > (long)dd) return QOC_OK;  // dense enough for the dense kernels
+  std::vector<double> vals((size_t)h->nnz_union * (M + 1) * 2);
+  for (int c = 0; c < d; ++c)
+    for (int e = colptr[c]; e < colptr[c + 1]; ++e)
+      for (int k = 0; k <= M; ++k) {
+        const size_t rc = (size_t)rowidx[e] * d + c;
+        vals[((size_t)e * (M + 1) + k) * 2] = h64[(k * dd + rc) * 2];
+        vals[((size_t)e * (M + 1) + k) * 2 + 1] = h64[(k * dd + rc) * 2 + 1];
+      }
+  // union of the controls' patterns by rows, with the controls at each entry
+  std::vector<int> rptr(d + 1, 0), rcol, eptr(1, 0), ek;
+  std::vector<double> ev;
+  for (int r = 0; r < d; ++r) {
+    for (int c = 0; c < d; ++c) {
+      const size_t rc = (size_t)r * d + c;
+      bool any = false;
+      for (int k = 1; k <= M; ++k)
+        if (nz(k, rc)) {
+          any = true;
+          ek.push_back(k - 1);
+          ev.push_back(h64[(k * dd + rc) * 2]);
+          ev.push_back(h64[(k * dd + rc) * 2 + 1]);
+        }
+      if (any) {
+        rcol.push_back(c);
+        eptr.push_back((int)ek.size());
+      }
+    }
+    rptr[r + 1] = (int)rcol.size();
+  }
+  h->nev = (long)ek.size();
+  std::vector<T> eval(2 * std::max<long>(1, h->nev), (T)0);
+  for (long q = 0; q < h->nev; ++q) {
+    eval[q] = (T)ev[2 * q];
+    eval[h->nev + q] = (T)ev[2 * q + 1];
+  }
+  qoc_status s;
+#define ALLOC(ptr, bytes)                                        \
+  if ((s = dalloc(h, (void **)&(ptr), (bytes))) != QOC_OK) return s;
+  ALLOC(h->sp_colptr, (d + 1) * sizeof(int));
+  ALLOC(h->sp_rowidx, std::max<long>(1, h->nnz_union) * sizeof(int));
+  ALLOC(h->sp_vals, vals.size() * sizeof(double) + 16);
+  ALLOC(h->sp_rptr, (d + 1) * sizeof(int));
+  ALLOC(h->sp_rcol, std::max<size_t>(1, rcol.size()) * sizeof(int));
+  ALLOC(h->sp_eptr, eptr.size() * sizeof(int));
+  ALLOC(h->sp_ek, std::max<long>(1, h->nev) * sizeof(int));
+  ALLOC(h->sp_eval, eval.size() * sizeof(T));
+#undef ALLOC
+  HIP_TRY(hipMemcpy(h->sp_colptr, colptr.data(), (d + 1) * sizeof(int), hipMemcpyHostToDevice));
+  if (h->nnz_union) {
+    HIP_TRY(hipMemcpy(h->sp_rowidx, rowidx.data(), rowidx.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->sp_vals, vals.data(), vals.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipMemcpy(h->sp_rptr, rptr.data(), (d + 1) * sizeof(int), hipMemcpyHostToDevice));
+  if (!rcol.empty())
+    HIP_TRY(hipMemcpy(h->sp_rcol, rcol.data(), rcol.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->sp_eptr, eptr.data(), eptr.size() * sizeof(int), hipMemcpyHostToDevice));
+  if (h->nev) HIP_TRY(hipMemcpy(h->sp_ek, ek.data(), ek.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->sp_eval, eval.data(), eval.size() * sizeof(T), hipMemcpyHostToDevice));
+  h->sp_built = true;
+  h->sp_auto = h->nnz_union * 16 <= (long)dd;
+  return QOC_OK;
+}
+
 template <typename T>
 qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   const int d = h->d, dp = h->dp, M = h->M, N = h->N, S = h->S;
@@ -544,6 +641,7 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   }
   HIP_TRY(hipMemcpy(h->Hf, hf.data(), hf.size() * sizeof(T), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->H64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice));
+  if ((s = build_structure<T>(h, h64)) != QOC_OK) return s;
   std::vector<T> ps(set, (T)0);
   for (int s2 = 0; s2 < S; ++s2)
     for (int m = 0; m < d; ++m) {
@@ -694,6 +792,11 @@ template <typename T>
 qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad_dev,
                hipStream_t st, bool want_grad) {
   const int dp = h->dp, N = h->N, M = h->M, S = h->S;
+  // structured Hamiltonians (batched path): norm and gradient contraction
+  // over their nonzeros
+  const bool sp_on = h->sp_built && (h->sp_mode == 1 || (h->sp_mode < 0 && h->sp_auto));
+  h->sp_used = sp_on;
+  const qoc::SparseU spu{h->sp_colptr, h->sp_rowidx, h->sp_vals};
   const long mat = 2L * dp * dp;
   const long lev = (long)N * mat;
   const bool small_path = qoc::small_expm_ok<T>(dp) && qoc::small_sweep_ok<T>(dp, S);
@@ -756,7 +859,8 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
       if (h->fixed_p >= 2)
         sel = qoc::SelectArgs{h->pn_dev, h->sc_dev, (unsigned *)(h->bits + 2), h->tol, 60, 30,
                               h->fixed_p, h->fixed_n, h->bits + 4};
-      HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, sel, st));
+      HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, sel, st,
+                               sp_on ? &spu : nullptr));
     }
     if (h->fixed_p >= 2) {
       p = h->fixed_p;
@@ -991,6 +1095,10 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     ad.bf3 = (h->bf3_used & QOC_BF3_ADJOINT) ? 1 : 0;
     ad.with_total = total_in_adjoint ? 1 : 0;
     ad.total = qoc::total_args(sw);
+    if (sp_on && big) {
+      ad.rptr = h->sp_rptr; ad.rcol = h->sp_rcol; ad.eptr = h->sp_eptr; ad.ek = h->sp_ek;
+      ad.eval = (const T *)h->sp_eval; ad.nev = h->nev; ad.d = h->d;
+    }
     if (!big && qoc::adjoint16_ok<T>(dp, ad.p))
       HIP_TRY(qoc::launch_adjoint16<T>(ad, st));
     else if (big)
@@ -1093,6 +1201,17 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n) {
   if (s) return s;
   h->fixed_p = p;
   h->fixed_n = p ? n : 0;
+  return QOC_OK;
+}
+
+qoc_status qoc_set_structure(qoc_handle *h, int mode) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  if (mode < -1 || mode > 1) return fail(QOC_ERR_ARG, "mode must be -1, 0 or 1");
+  if (mode == 1 && !h->sp_built)
+    return fail(QOC_ERR_UNSUPPORTED,
+                "structured kernels need padded d >= 64 and a union of nonzero patterns of at "
+                "most d^2 / 4 entries");
+  h->sp_mode = mode;
   return QOC_OK;
 }
 
@@ -1443,6 +1562,7 @@ qoc_status qoc_get_info(const qoc_handle *hc, qoc_info *info) {
   info->device_bytes = h->bytes;
   info->bf16x3_classes = h->bf3_used;
   info->unitarity_drift = h->last_unitarity;
+  info->structured = h->sp_used ? 1 : 0;
   return QOC_OK;
 }
 

@@ -54,9 +54,19 @@ struct SelectArgs {
   int n_cap, p_cap, fixed_p, fixed_n;
   unsigned long long *acc;
 };
-// theta_max = max_j ||dt H_j||_1 in FP64 (maximum on the bit pattern).
+// Structured (sparse) Hamiltonians: the union of the nonzero patterns of
+// H_0 .. H_M in compressed columns, with the M + 1 FP64 values of every
+// union entry (zero where a Hamiltonian has no entry there).
+struct SparseU {
+  const int *colptr;   // d + 1
+  const int *rowidx;   // nnz_union
+  const double *vals;  // nnz_union x (M + 1) x 2 (re, im), H_0 first
+};
+// theta_max = max_j ||dt H_j||_1 in FP64 (maximum on the bit pattern);
+// with sp (not null) each column sums over its union entries only.
 hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, double dt,
-                       unsigned long long *theta_bits, const SelectArgs &sel, hipStream_t st);
+                       unsigned long long *theta_bits, const SelectArgs &sel, hipStream_t st,
+                       const SparseU *sp = nullptr);
 
 template <typename T> hipError_t launch_fill(T *p, long n, T v, hipStream_t st);
 // dst[0:n] = src[0:n] (a kernel, so that captured graphs hold no copy nodes)
@@ -227,6 +237,17 @@ template <typename T> struct AdjointArgs {
   int bf3;             // batched variant: bf16x3 split products
   int with_total;      // padded d 16: one extra workgroup reduces the cost (total)
   TotalArgs total;
+  // batched variant with structured control Hamiltonians (rptr null:
+  // dense): the union of the controls' nonzero patterns by rows (rptr: d + 1
+  // offsets, rcol: columns) and, per union entry e, the controls with a
+  // nonzero there (ek[eptr[e] .. eptr[e+1]]) and their values (eval: re
+  // plane, then im plane, nev each); the gradient contracts Xbar_j only at
+  // these entries, formed from the derivative's panels instead of storing
+  // Xbar_j.  d: true dimension.
+  const int *rptr, *rcol, *eptr, *ek;
+  const T *eval;
+  long nev;
+  int d;
 };
 template <typename T> long adjoint_scratch_elems(int dp, int p, int Rcap);
 // Time steps processed concurrently per workgroup (one per wave for small d).

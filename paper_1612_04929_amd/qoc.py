@@ -32,7 +32,7 @@ EXPORTS = ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
            "qoc_cost_grad_device_noalloc",
            "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
            "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
-           "qoc_set_bf16x3", "qoc_set_unitarity_check", "qoc_destroy",
+           "qoc_set_bf16x3", "qoc_set_unitarity_check", "qoc_set_structure", "qoc_destroy",
            "qoc_status_string",
            "qoc_last_error", "qoc_version"]
 
@@ -54,7 +54,8 @@ class Info(C.Structure):
     _fields_ = [("p", C.c_int), ("n", C.c_int), ("theta_max", C.c_double),
                 ("norm_drift", C.c_double), ("block_len", C.c_int), ("n_blocks", C.c_int),
                 ("d_pad", C.c_int), ("flags", C.c_int), ("device_bytes", C.c_size_t),
-                ("bf16x3_classes", C.c_int), ("unitarity_drift", C.c_double)]
+                ("bf16x3_classes", C.c_int), ("unitarity_drift", C.c_double),
+                ("structured", C.c_int)]
 
 
 class QocError(RuntimeError):
@@ -102,6 +103,7 @@ def load(path: str = LIB_PATH):
     lib.qoc_set_sweep.argtypes = [vp, C.c_int, C.c_int]
     lib.qoc_set_bf16x3.argtypes = [vp, C.c_int]
     lib.qoc_set_unitarity_check.argtypes = [vp, C.c_int]
+    lib.qoc_set_structure.argtypes = [vp, C.c_int]
     lib.qoc_destroy.argtypes = [vp]
     lib.qoc_destroy.restype = None
     for f in ["qoc_status_string", "qoc_last_error", "qoc_version"]:
@@ -111,7 +113,7 @@ def load(path: str = LIB_PATH):
               "qoc_cost_grad_device_noalloc",
               "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
               "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
-              "qoc_set_bf16x3", "qoc_set_unitarity_check"]:
+              "qoc_set_bf16x3", "qoc_set_unitarity_check", "qoc_set_structure"]:
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -146,7 +148,7 @@ class Problem:
     """
 
     def __init__(self, prob, precision="fp32", checkpoint_every=0, taylor_tol=0.0,
-                 taylor_pn=None, drift_warn=0.0, device=0):
+                 taylor_pn=None, drift_warn=0.0, device=0, structure=-1):
         lib = load()
         self.d, self.M, self.N, self.S = int(prob.d), int(prob.M), int(prob.N), int(prob.S)
         keep = []
@@ -179,6 +181,8 @@ class Problem:
         self._h = C.c_void_p()
         _check(lib.qoc_create(C.byref(desc), C.byref(self._h)))
         self.precision = precision
+        if structure != -1:
+            self.set_structure(structure)
 
     # -- host-array calls -------------------------------------------------
     def _u(self, u):
@@ -244,6 +248,11 @@ class Problem:
                                "the last call's results are not accurate")
         return inf
 
+    def set_structure(self, mode: int):
+        """Structured (sparse) norm and gradient contraction: -1 automatic,
+        0 dense, 1 structured."""
+        _check(load().qoc_set_structure(self._h, int(mode)))
+
     def set_unitarity_check(self, stride: int):
         """FP64 check of max |(U^H U - I)_{rc}| on every stride-th step (0: off)."""
         _check(load().qoc_set_unitarity_check(self._h, int(stride)))
@@ -254,7 +263,8 @@ class Problem:
         return dict(p=inf.p, n=inf.n, theta_max=inf.theta_max, norm_drift=inf.norm_drift,
                     block_len=inf.block_len, n_blocks=inf.n_blocks, d_pad=inf.d_pad,
                     flags=inf.flags, device_bytes=inf.device_bytes,
-                    bf16x3_classes=inf.bf16x3_classes, unitarity_drift=inf.unitarity_drift)
+                    bf16x3_classes=inf.bf16x3_classes, unitarity_drift=inf.unitarity_drift,
+                    structured=inf.structured)
 
     def profile_enable(self, on=True):
         _check(load().qoc_profile_enable(self._h, 1 if on else 0))
