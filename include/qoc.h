@@ -288,6 +288,19 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n);
  * (truncated Taylor series with scaling and squaring), Sec. II.B. */
 qoc_status qoc_set_bf16x3(qoc_handle *h, int classes);
 
+/* Gradient of later cost + gradient calls: QOC_GRAD_EXACT (default), the
+ * exact derivative of the evaluated Taylor / squaring approximant, or
+ * QOC_GRAD_FIRST_ORDER, the paper's approximate gradient (Sec. III, eq. 7;
+ * App. A, Algorithms 1-3), which replaces dU_j/du_{k,j} by (-i dt H_k) U_j:
+ *   g_{k,j} = 2 dt Im sum_s <lambda_{j+1}^s| H_k |psi_{j+1}^s>  (+ C3 / C4)
+ * from the same costates, without the derivative of the step exponential
+ * (a rank-S outer product per step contracted with every H_k).  It equals
+ * the exact gradient only when the step Hamiltonians commute; its error
+ * grows with dt ||[H_j, H_k]||.  The cost is unaffected.  Returns
+ * QOC_ERR_ARG for another mode. */
+enum { QOC_GRAD_EXACT = 0, QOC_GRAD_FIRST_ORDER = 1 };
+qoc_status qoc_set_gradient(qoc_handle *h, int mode);
+
 /* Structured Hamiltonians (Sec. IV and the Conclusion: sparse matrices,
  * e.g. a diagonal drift and permutation-like controls).  On the batched
  * path (padded d >= 64) qoc_create records the union of the nonzero

@@ -10,6 +10,8 @@
 // of the 4 wavefronts owns 16 rows and TN/16 MFMA tiles.  op is identity or
 // conjugate transpose on either operand.  Rows beyond the matrix are
 // skipped, so any padded d (multiple of 16) works.
+#include <algorithm>
+
 #include "qoc_device.h"
 #include "qoc_kernels.h"
 #include "qoc_tile.h"
@@ -806,6 +808,64 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
   hipLaunchKernelGGL(k_adj_finish<T>, dim3(grid_for((long)N * M)), dim3(256), 0, st, f);
   return hipGetLastError();
 }
+
+// The paper's first-order gradient (Sec. III, eq. 7; App. A, Algorithms
+// 1-3), offered as a cheap approximate mode: dU_j/du_{k,j} is replaced by
+// (-i dt H_k) U_j, so g_{k,j} = 2 dt Im sum_s <lambda_{j+1}^s|H_k|psi_{j+1}^s>
+// = 2 dt Im tr(Y_j^H H_k) with the rank-S matrix Y_j = sum_s lambda_{j+1}^s
+// psi_{j+1}^{s H}, formed here into the work space of Xbar and contracted
+// by k_gcontract.  Exact only when the step Hamiltonians commute.
+template <typename T> struct OuterArgs {
+  const T *lam_buf, *psi_buf;  // lambda_{j+1} of step j at set j; psi_j at set j
+  T *out;                      // N x 2 dp^2
+  int N, dp, S;
+};
+
+template <typename T> __global__ __launch_bounds__(256) void k_outer(OuterArgs<T> a) {
+  const long plane = (long)a.dp * a.dp, set = 2L * a.S * a.dp;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= plane) return;
+  const int r = (int)(e / a.dp), c = (int)(e - (long)r * a.dp);
+  for (long j = blockIdx.y; j < a.N; j += gridDim.y) {
+    const T *lam = a.lam_buf + j * set, *psi = a.psi_buf + (j + 1) * set;
+    T yr = 0, yi = 0;
+    for (int s = 0; s < a.S; ++s) {
+      const T lr = lam[(long)s * a.dp + r], li = lam[(long)(a.S + s) * a.dp + r];
+      const T pr = psi[(long)s * a.dp + c], pi = psi[(long)(a.S + s) * a.dp + c];
+      yr += lr * pr + li * pi;  // lambda conj(psi)
+      yi += li * pr - lr * pi;
+    }
+    T *o = a.out + j * 2 * plane;
+    o[e] = yr;
+    o[plane + e] = yi;
+  }
+}
+
+template <typename T> hipError_t launch_grad_first(const AdjointArgs<T> &a, double dt,
+                                                   hipStream_t st) {
+  const int dp = a.dp, N = a.N, M = a.M;
+  const long plane = (long)dp * dp, mat = 2 * plane;
+  hipError_t e;
+  if (M > 0) {
+    OuterArgs<T> oa{a.lam_buf, a.psi_buf, a.xbar, N, dp, a.S};
+    dim3 grid((unsigned)((plane + 255) / 256), (unsigned)std::min(N, 1024));
+    hipLaunchKernelGGL(k_outer<T>, grid, dim3(256), 0, st, oa);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const long nsl = adjoint_big_slices(dp);
+  if (M > 0) {
+    GContract<T> gc{a.xbar, mat, plane, a.Hf, a.part, N, M, (int)nsl,
+                    (int)std::min<long>(1024, plane)};
+    dim3 grid((unsigned)nsl, (unsigned)((N + 63) / 64));
+    hipLaunchKernelGGL(k_gcontract<T>, grid, dim3(256), 0, st, gc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  AdjFinish<T> f{a.part, a.u, a.grad, 2.0 * dt, a.alpha_amp, a.alpha_var, nullptr, N, M, (int)nsl};
+  hipLaunchKernelGGL(k_adj_finish<T>, dim3(grid_for((long)N * M)), dim3(256), 0, st, f);
+  return hipGetLastError();
+}
+template hipError_t launch_grad_first<float>(const AdjointArgs<float> &, double, hipStream_t);
+template hipError_t launch_grad_first<double>(const AdjointArgs<double> &, double, hipStream_t);
 
 template <typename T> bool adjoint_big_ok(int dp) { return dp >= 64; }
 

@@ -176,6 +176,7 @@ struct qoc_handle {
   // FP64 unitarity check of the step propagators: every `unit_stride`-th
   // step (0: off); its result word carries the call's epoch
   int unit_stride = 0;
+  int grad_mode = QOC_GRAD_EXACT;
   unsigned epoch = 0, unit_epoch = 0;
   double last_unitarity = -1.0;
   // per-call work space carved from the static device scratch instead of
@@ -459,6 +460,19 @@ template <typename T> qoc_status ensure_adjoint(qoc_handle *h, int p, int Rcap, 
   qoc_status s = dalloc(h, &h->adj, (size_t)total * sizeof(T));
   if (s) return s;
   h->adj_elems_alloc = total;
+  return QOC_OK;
+}
+
+// Partial sums of the first-order gradient contraction: N x slices x M.
+qoc_status ensure_part(qoc_handle *h) {
+  const long parts = (long)h->N * qoc::adjoint_big_slices(h->dp) * std::max(h->M, 1);
+  if (h->ws_base) return carve(h, (void **)&h->adj_part, (size_t)parts * sizeof(double));
+  if (parts <= h->adj_part_alloc) return QOC_OK;
+  dfree(h, (void **)&h->adj_part, (size_t)h->adj_part_alloc * sizeof(double));
+  h->adj_part_alloc = 0;
+  qoc_status s = dalloc(h, (void **)&h->adj_part, (size_t)parts * sizeof(double));
+  if (s) return s;
+  h->adj_part_alloc = parts;
   return QOC_OK;
 }
 
@@ -996,7 +1010,8 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   // the derivative kernel instead of a launch of its own, and (single-
   // wavefront block sweep) lambda_N, the fidelity and the penalty pass run
   // inside the backward block sweep's launch instead of the cost launch
-  const bool total_in_adjoint = !ext && want_grad && M > 0 && small_path &&
+  const bool first_order = h->grad_mode == QOC_GRAD_FIRST_ORDER;
+  const bool total_in_adjoint = !ext && !first_order && want_grad && M > 0 && small_path &&
                                 !small_big_adjoint<T>(h) && qoc::adjoint16_ok<T>(dp, kSmallPCap);
   sw.fuse_cost = (total_in_adjoint && wave && h->sweep_mode[2] != 3) ? 1 : 0;
   const bool small = !ext && !wave && qoc::small_sweep_ok<T>(dp, S);
@@ -1071,7 +1086,18 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     PhaseTimer tm(h, QOC_PHASE_BWD_PAIRS, st);
     HIP_TRY(sweep(3));
   }
-  if (M > 0) {
+  if (M > 0 && first_order) {
+    // the paper's first-order gradient from the pairs (lambda_{j+1}, psi_{j+1})
+    PhaseTimer tm(h, QOC_PHASE_ADJOINT, st);
+    qoc_status s = ensure_part(h);
+    if (s) return s;
+    qoc::AdjointArgs<T> ad{};
+    ad.N = N; ad.dp = dp; ad.M = M; ad.S = S;
+    ad.lam_buf = (const T *)h->lam_buf; ad.psi_buf = (const T *)h->psi_buf;
+    ad.Hf = (const T *)h->Hf; ad.u = u_dev; ad.alpha_amp = h->a_amp; ad.alpha_var = h->a_var;
+    ad.grad = grad_dev; ad.part = h->adj_part; ad.xbar = Qa;
+    HIP_TRY(qoc::launch_grad_first<T>(ad, h->dt, st));
+  } else if (M > 0) {
     PhaseTimer tm(h, QOC_PHASE_ADJOINT, st);
     qoc::AdjointArgs<T> ad{};
     // batched per-step derivative for padded d >= 64, and for d >= 32 on the
@@ -1201,6 +1227,14 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n) {
   if (s) return s;
   h->fixed_p = p;
   h->fixed_n = p ? n : 0;
+  return QOC_OK;
+}
+
+qoc_status qoc_set_gradient(qoc_handle *h, int mode) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  if (mode != QOC_GRAD_EXACT && mode != QOC_GRAD_FIRST_ORDER)
+    return fail(QOC_ERR_ARG, "mode must be QOC_GRAD_EXACT or QOC_GRAD_FIRST_ORDER");
+  h->grad_mode = mode;
   return QOC_OK;
 }
 

@@ -268,5 +268,11 @@ template <typename T> long adjoint_big_scratch_per_step(int dp, int p, int Rcap)
 long adjoint_big_slices(int dp);
 template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_adjoint16(const AdjointArgs<T> &a, hipStream_t st);
+// The paper's first-order gradient (eq. 7) for any padded d: Y_j = sum_s
+// lambda_{j+1}^s psi_{j+1}^{s H} into a.xbar, contracted with every H_k
+// (partial sums in a.part: N x adjoint_big_slices(dp) x M), times 2 dt, plus
+// the C3 / C4 gradients.
+template <typename T> hipError_t launch_grad_first(const AdjointArgs<T> &a, double dt,
+                                                   hipStream_t st);
 
 }  // namespace qoc

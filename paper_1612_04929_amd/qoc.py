@@ -21,6 +21,7 @@ PRECISIONS = {"fp64": QOC_FP64, "fp32": QOC_FP32, "bf16x3": QOC_BF16X3}
 QOC_FID_COHERENT, QOC_FID_INCOHERENT = 0, 1
 QOC_WARN_DRIFT, QOC_WARN_TAYLOR, QOC_WARN_PRECISION, QOC_WARN_UNITARITY = 1, 2, 4, 8
 QOC_WARN_NO_PAIR = 16
+QOC_GRAD_EXACT, QOC_GRAD_FIRST_ORDER = 0, 1
 QOC_BF3_TAYLOR, QOC_BF3_SQUARING, QOC_BF3_BLOCKPROD, QOC_BF3_ADJOINT = 1, 2, 4, 8
 QOC_BF3_ALL = 15
 PHASES = ["norm", "assemble", "taylor", "blockprod", "fwd_blocks", "fwd_replay", "cost",
@@ -32,7 +33,8 @@ EXPORTS = ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
            "qoc_cost_grad_device_noalloc",
            "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
            "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
-           "qoc_set_bf16x3", "qoc_set_unitarity_check", "qoc_set_structure", "qoc_destroy",
+           "qoc_set_bf16x3", "qoc_set_unitarity_check", "qoc_set_structure", "qoc_set_gradient",
+           "qoc_destroy",
            "qoc_status_string",
            "qoc_last_error", "qoc_version"]
 
@@ -104,6 +106,7 @@ def load(path: str = LIB_PATH):
     lib.qoc_set_bf16x3.argtypes = [vp, C.c_int]
     lib.qoc_set_unitarity_check.argtypes = [vp, C.c_int]
     lib.qoc_set_structure.argtypes = [vp, C.c_int]
+    lib.qoc_set_gradient.argtypes = [vp, C.c_int]
     lib.qoc_destroy.argtypes = [vp]
     lib.qoc_destroy.restype = None
     for f in ["qoc_status_string", "qoc_last_error", "qoc_version"]:
@@ -113,7 +116,8 @@ def load(path: str = LIB_PATH):
               "qoc_cost_grad_device_noalloc",
               "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
               "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
-              "qoc_set_bf16x3", "qoc_set_unitarity_check", "qoc_set_structure"]:
+              "qoc_set_bf16x3", "qoc_set_unitarity_check", "qoc_set_structure",
+              "qoc_set_gradient"]:
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -247,6 +251,10 @@ class Problem:
             raise QocError(-7, f"no (p, n) met the tolerance at theta_max = {inf['theta_max']}; "
                                "the last call's results are not accurate")
         return inf
+
+    def set_gradient(self, mode: int):
+        """QOC_GRAD_EXACT (default) or QOC_GRAD_FIRST_ORDER (the paper's eq. 7)."""
+        _check(load().qoc_set_gradient(self._h, int(mode)))
 
     def set_structure(self, mode: int):
         """Structured (sparse) norm and gradient contraction: -1 automatic,
