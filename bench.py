@@ -349,7 +349,7 @@ def bench_batch(args):
                config=dict(workload="c5_batched_uneven", instances=len(probs),
                            sum_N=b.total_steps, d_range=[min(p.d for p in probs),
                                                          max(p.d for p in probs)],
-                           optimizer="Adam lr=1e-2 (torch, capturable)", streams=len(b.streams),
+                           optimizer="Adam lr=1e-2 (qoc_adam_step kernel)", streams=len(b.streams),
                            precision=args.precision),
                roofline=dict(kernel="whole iteration (graph)", bound="mfma",
                              achieved=flops / t / 1e12, peak=peak / 1e12, unit="TFLOP/s",

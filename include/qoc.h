@@ -228,6 +228,21 @@ qoc_status qoc_cost_grad_batched(int B, qoc_handle *const *hs,
                                  double *const *out_dev,
                                  double *const *grad_dev, void *stream);
 
+/* One Adam step (the optimiser of the paper's examples, Sec. IV) over n
+ * FP64 amplitudes on the device, e.g. the controls of many instances packed
+ * back to back:
+ *   m <- beta1 m + (1 - beta1) g,  v <- beta2 v + (1 - beta2) g^2,
+ *   t <- t + 1,  u <- u - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+ * u_dev, m_dev, v_dev (updated in place), grad_dev: n doubles each; t_dev:
+ * one double on the device holding the step count (0 before the first
+ * step), advanced by the call, so replays of a captured iteration keep
+ * counting.  Enqueued on `stream`, no host synchronisation; two kernel
+ * launches, no allocation.  QOC_ERR_ARG for n < 0, NULL arrays, lr < 0,
+ * betas outside [0, 1) or eps <= 0. */
+qoc_status qoc_adam_step(long n, double *u_dev, const double *grad_dev, double *m_dev,
+                         double *v_dev, double *t_dev, double lr, double beta1, double beta2,
+                         double eps, void *stream);
+
 /* Diagnostics of the last call (see qoc_info).  Synchronises the handle's
  * device to read the on-device diagnostics back. */
 qoc_status qoc_get_info(const qoc_handle *h, qoc_info *info);

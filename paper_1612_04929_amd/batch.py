@@ -1,12 +1,13 @@
 """Many independent control problems per optimizer iteration.
 
 A :class:`Batch` holds one libqoc handle per instance (uneven d, N, M), the
-instances' amplitudes, outputs and gradients as device tensors, and
-torch's capturable Adam over the amplitudes (the optimizer of the
-workload, not part of the cost + gradient path).  One iteration enqueues
+instances' amplitudes and gradients packed back to back in flat device
+buffers (each instance's M x N block a contiguous slice), the Adam moments
+and step count beside them, and the outputs.  One iteration enqueues
 ``qoc_cost_grad_batched`` for every instance, split over a few streams
 (default priority) forked from and joined back into the current stream,
-then the Adam update.  Handles whose padded d is 32 or more get a fixed
+then one ``qoc_adam_step`` over all amplitudes (the library's Adam kernel;
+torch only allocates the buffers).  Handles whose padded d is 32 or more get a fixed
 (p, n) chosen from their initial theta_max times a margin: from 64 on no
 call then needs a host round trip, and from 32 on the per-step derivative
 runs as batched tile products (padded d 16 choose (p, n) on the device);
@@ -41,13 +42,22 @@ class Batch:
         self.problems = list(problems)
         self.handles = [qoc.Problem(p, precision=precision, device=device) for p in self.problems]
         f64 = torch.float64
-        self.u = [torch.tensor(np.asarray(p.u, dtype=np.float64).reshape(p.M, p.N), dtype=f64,
-                               device=self.dev).requires_grad_(True) for p in self.problems]
+        sizes = [max(1, p.M * p.N) for p in self.problems]
+        offs = np.concatenate([[0], np.cumsum(sizes)]).astype(int)
+        self.n_amp = int(offs[-1])
+        u0 = np.zeros(self.n_amp)
+        for p, o in zip(self.problems, offs):
+            u0[o: o + p.M * p.N] = np.asarray(p.u, dtype=np.float64).ravel()
+        self.u_flat = torch.tensor(u0, dtype=f64, device=self.dev)
+        self.g_flat = torch.zeros(self.n_amp, dtype=f64, device=self.dev)
+        self.m_flat = torch.zeros(self.n_amp, dtype=f64, device=self.dev)
+        self.v_flat = torch.zeros(self.n_amp, dtype=f64, device=self.dev)
+        self.t_step = torch.zeros(1, dtype=f64, device=self.dev)
+        self.lr, self.betas, self.eps = float(lr), (float(betas[0]), float(betas[1])), float(eps)
+        self.u = [self.u_flat[o: o + p.M * p.N].view(p.M, p.N)
+                  for p, o in zip(self.problems, offs)]
+        self.grad = [self.g_flat[o: o + s] for o, s in zip(offs, sizes)]
         self.out = [torch.zeros(2 + p.N, dtype=f64, device=self.dev) for p in self.problems]
-        self.grad = [torch.zeros(max(1, p.M * p.N), dtype=f64, device=self.dev)
-                     for p in self.problems]
-        for u, g, p in zip(self.u, self.grad, self.problems):
-            u.grad = g[: p.M * p.N].view(p.M, p.N)
         self.total_steps = int(sum(p.N for p in self.problems))
         # initial (p, n): one call per instance, then fix the pair of the
         # instances that would otherwise read theta_max back on the host
@@ -86,8 +96,6 @@ class Batch:
                                  arr([self.u[i].data_ptr() for i in g]),
                                  arr([self.out[i].data_ptr() for i in g]),
                                  arr([self.grad[i].data_ptr() for i in g])))
-        self.opt = torch.optim.Adam(self.u, lr=lr, betas=betas, eps=eps, capturable=True,
-                                    foreach=True)
         self.graph = None
 
     # ------------------------------------------------------------------
@@ -110,9 +118,16 @@ class Batch:
         for h, u, o, g in zip(self.handles, self.u, self.out, self.grad):
             h.cost_grad_device(u.data_ptr(), o.data_ptr(), g.data_ptr(), st)
 
+    def adam(self):
+        """One Adam step over every instance's amplitudes (qoc_adam_step)."""
+        qoc.adam_step(self.n_amp, self.u_flat.data_ptr(), self.g_flat.data_ptr(),
+                      self.m_flat.data_ptr(), self.v_flat.data_ptr(), self.t_step.data_ptr(),
+                      self.lr, self.betas, self.eps,
+                      torch.cuda.current_stream(self.dev).cuda_stream)
+
     def iteration(self, serial=False):
         (self.cost_grad_serial if serial else self.cost_grad)()
-        self.opt.step()
+        self.adam()
 
     def capture(self, warmup=3):
         """Capture one iteration (all cost + gradient calls and the Adam

@@ -13,6 +13,8 @@
 //              <T_s|psi_j^s> / S (incoherent),
 // and lambda_j = U_j^H lambda_{j+1} + (level penalty) + src_j for j >= 1,
 // lambda_N picking up src_N.  One wavefront per step, all overlaps in FP64.
+#include <algorithm>
+
 #include "qoc_device.h"
 #include "qoc_kernels.h"
 
@@ -223,5 +225,48 @@ template hipError_t launch_unitarity<float>(const float *, int, int, int, int, u
                                             unsigned long long *, hipStream_t);
 template hipError_t launch_unitarity<double>(const double *, int, int, int, int, unsigned,
                                              unsigned long long *, hipStream_t);
+
+
+// ---------------------------------------------------------------------------
+// Adam update of the control amplitudes (the optimiser of the paper's
+// examples, Sec. IV), flat over any number of instances' amplitudes, in FP64:
+//   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,  t' = t + 1,
+//   u <- u - lr (m / (1 - b1^t')) / (sqrt(v / (1 - b2^t')) + eps).
+// The step count lives on the device (graph replays advance it): k_adam
+// reads t, and k_adam_count increments it afterwards.
+namespace {
+__global__ __launch_bounds__(256) void k_adam(long n, double *__restrict__ u,
+                                              const double *__restrict__ g, double *__restrict__ m,
+                                              double *__restrict__ v, const double *__restrict__ t,
+                                              double lr, double b1, double b2, double eps) {
+  const double tn = t[0] + 1.0;
+  const double bc1 = 1.0 - pow(b1, tn), bc2 = 1.0 - pow(b2, tn);
+  const double step = lr / bc1, rbc2 = 1.0 / sqrt(bc2);
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const double gi = g[i];
+    const double mi = b1 * m[i] + (1.0 - b1) * gi;
+    const double vi = b2 * v[i] + (1.0 - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    u[i] -= step * mi / (sqrt(vi) * rbc2 + eps);
+  }
+}
+__global__ void k_adam_count(double *t) {
+  if (threadIdx.x == 0) t[0] += 1.0;
+}
+}  // namespace
+
+hipError_t launch_adam(long n, double *u, const double *g, double *m, double *v, double *t,
+                       double lr, double b1, double b2, double eps, hipStream_t st) {
+  if (n > 0) {
+    const long blocks = std::min<long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, n, u, g, m, v, t, lr, b1,
+                       b2, eps);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_adam_count, dim3(1), dim3(64), 0, st, t);
+  return hipGetLastError();
+}
 
 }  // namespace qoc

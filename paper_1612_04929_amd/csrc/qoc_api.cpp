@@ -1536,6 +1536,19 @@ qoc_status qoc_cost_grad_device_noalloc(qoc_handle *h, const double *u_dev, doub
   return s;
 }
 
+qoc_status qoc_adam_step(long n, double *u_dev, const double *grad_dev, double *m_dev,
+                         double *v_dev, double *t_dev, double lr, double beta1, double beta2,
+                         double eps, void *stream) {
+  if (n < 0 || (n > 0 && (!u_dev || !grad_dev || !m_dev || !v_dev)) || !t_dev)
+    return fail(QOC_ERR_ARG, "n must be >= 0 and the device arrays non-NULL");
+  if (!(lr >= 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+      !(eps > 0.0) || !std::isfinite(lr) || !std::isfinite(eps))
+    return fail(QOC_ERR_ARG, "need lr >= 0, 0 <= beta1, beta2 < 1 and eps > 0");
+  HIP_TRY(qoc::launch_adam(n, u_dev, grad_dev, m_dev, v_dev, t_dev, lr, beta1, beta2, eps,
+                           (hipStream_t)stream));
+  return QOC_OK;
+}
+
 qoc_status qoc_cost_grad_batched(int B, qoc_handle *const *hs, const double *const *u_dev,
                                  double *const *out_dev, double *const *grad_dev, void *stream) {
   if (B < 0 || (B > 0 && (!hs || !u_dev || !out_dev || !grad_dev)))

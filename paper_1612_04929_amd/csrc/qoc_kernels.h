@@ -186,6 +186,10 @@ hipError_t launch_ext(const SweepArgs<T> &a, const ExtArgs<T> &e, hipStream_t st
 // propagators U_j = I + D_j (true d x d block) over the steps N-1,
 // N-1-stride, ..., folded into *acc as (epoch << 32 | FP32 bits) by atomic
 // maximum (kernels_ext.hip).
+// Adam over n FP64 amplitudes with a device-side step count t (kernels_ext.hip).
+hipError_t launch_adam(long n, double *u, const double *g, double *m, double *v, double *t,
+                       double lr, double b1, double b2, double eps, hipStream_t st);
+
 template <typename T>
 hipError_t launch_unitarity(const T *D, int dp, int d, int N, int stride, unsigned epoch,
                             unsigned long long *acc, hipStream_t st);

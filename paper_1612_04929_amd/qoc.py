@@ -34,7 +34,7 @@ EXPORTS = ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
            "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
            "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
            "qoc_set_bf16x3", "qoc_set_unitarity_check", "qoc_set_structure", "qoc_set_gradient",
-           "qoc_destroy",
+           "qoc_adam_step", "qoc_destroy",
            "qoc_status_string",
            "qoc_last_error", "qoc_version"]
 
@@ -107,6 +107,8 @@ def load(path: str = LIB_PATH):
     lib.qoc_set_unitarity_check.argtypes = [vp, C.c_int]
     lib.qoc_set_structure.argtypes = [vp, C.c_int]
     lib.qoc_set_gradient.argtypes = [vp, C.c_int]
+    lib.qoc_adam_step.argtypes = [C.c_long, vp, vp, vp, vp, vp, C.c_double, C.c_double,
+                                  C.c_double, C.c_double, vp]
     lib.qoc_destroy.argtypes = [vp]
     lib.qoc_destroy.restype = None
     for f in ["qoc_status_string", "qoc_last_error", "qoc_version"]:
@@ -117,7 +119,7 @@ def load(path: str = LIB_PATH):
               "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
               "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
               "qoc_set_bf16x3", "qoc_set_unitarity_check", "qoc_set_structure",
-              "qoc_set_gradient"]:
+              "qoc_set_gradient", "qoc_adam_step"]:
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -293,6 +295,15 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def adam_step(n: int, u_ptr: int, grad_ptr: int, m_ptr: int, v_ptr: int, t_ptr: int,
+              lr: float, betas=(0.9, 0.999), eps: float = 1e-8, stream: int = 0):
+    """One Adam step over n FP64 device amplitudes (qoc_adam_step)."""
+    _check(load().qoc_adam_step(int(n), C.c_void_p(u_ptr), C.c_void_p(grad_ptr),
+                                C.c_void_p(m_ptr), C.c_void_p(v_ptr), C.c_void_p(t_ptr),
+                                float(lr), float(betas[0]), float(betas[1]), float(eps),
+                                C.c_void_p(stream)))
 
 
 def cost_grad_batched(problems, u_ptrs, out_ptrs, grad_ptrs, stream: int = 0):

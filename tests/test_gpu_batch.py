@@ -102,3 +102,36 @@ def test_full_length_instances_match_stored_oracle(precision):
         assert err <= tG * nrm + 1e-9
         assert np.max(np.abs(c - ref["c"])) <= 2e-6
     b.close()
+
+
+def test_adam_kernel_matches_reference():
+    """qoc_adam_step against Adam written out in FP64 on the host (the
+    update of Kingma and Ba with bias corrections), three steps in a row,
+    the step count kept on the device."""
+    from paper_1612_04929_amd import qoc
+    rng = np.random.default_rng(1200)
+    n = 10007
+    u0 = rng.normal(size=n)
+    grads = [rng.normal(size=n) * s for s in (1.0, 0.3, 2.0)]
+    dev = torch.device("cuda:0")
+    u = torch.tensor(u0, dtype=torch.float64, device=dev)
+    m = torch.zeros_like(u)
+    v = torch.zeros_like(u)
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    ru, rm, rv = u0.copy(), np.zeros(n), np.zeros(n)
+    st = torch.cuda.current_stream(dev).cuda_stream
+    for k, gk in enumerate(grads, start=1):
+        g = torch.tensor(gk, dtype=torch.float64, device=dev)
+        qoc.adam_step(n, u.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), t.data_ptr(),
+                      lr, (b1, b2), eps, st)
+        torch.cuda.synchronize()
+        rm = b1 * rm + (1 - b1) * gk
+        rv = b2 * rv + (1 - b2) * gk * gk
+        mh, vh = rm / (1 - b1 ** k), rv / (1 - b2 ** k)
+        ru = ru - lr * mh / (np.sqrt(vh) + eps)
+        assert float(t.item()) == k
+        assert np.max(np.abs(u.cpu().numpy() - ru)) <= 1e-13
+    with pytest.raises(qoc.QocError):
+        qoc.adam_step(n, u.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), t.data_ptr(),
+                      lr, (1.0, b2), eps, st)
