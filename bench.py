@@ -276,7 +276,12 @@ def bench_batch(args):
     probs = workloads.config5()
     log(f"[bench] c5: {len(probs)} instances, d {min(p.d for p in probs)}..{max(p.d for p in probs)}, "
         f"sum N = {sum(p.N for p in probs)}, precision={args.precision}")
-    b = Batch(probs, precision=args.precision, streams=args.streams)
+    t_tune = time.perf_counter()
+    b = Batch(probs, precision=args.precision, streams=args.streams,
+              tune_tiles=not args.no_tune)
+    t_tune = time.perf_counter() - t_tune
+    log(f"[bench] c5 tiles: {sum(1 for x in b.pads if x == 64)} of {len(probs)} instances on "
+        f"64 x 64 tiles (set-up and tuning {t_tune:.1f} s)")
     res_acc = {}
     if not args.no_cpu_baseline:
         import oracle
@@ -355,6 +360,8 @@ def bench_batch(args):
                              achieved=flops / t / 1e12, peak=peak / 1e12, unit="TFLOP/s",
                              frac=flops / t / peak, traffic=None),
                graph=graph, eager_multistream=eager, per_instance_calls=serial,
+               tiles=dict(pad64=sum(1 for x in b.pads if x == 64), instances=len(probs),
+                          tuned=not args.no_tune, setup_s=t_tune),
                speedup_graph_vs_per_instance=serial["p50_ms"] / graph["p50_ms"],
                taylor_pair_refreshes=refreshes, taylor_warnings_last_chunk=len(warn))
     if res_acc:

@@ -138,6 +138,12 @@ typedef struct {
   const double *forbidden;  /* n_forbidden*d complex, state-major (state f at
                                [f*d + m]), or NULL when n_forbidden == 0    */
   double alpha_time;        /* weight of the time-optimal term C_time        */
+  int pad_multiple;         /* d is padded with zeros (exact: exp of a zero
+                               block is the identity) to a multiple of 16
+                               (0 or 16: the default), 32 or 64; a multiple
+                               of 64 runs every product on 64 x 64 MFMA
+                               tiles (a tile-shape choice for measuring
+                               tuners); anything else is QOC_ERR_ARG       */
 } qoc_problem_desc;
 
 /* Diagnostics of the most recent forward / cost_grad call on a handle. */

@@ -37,10 +37,21 @@ def taylor_ok(p, n, theta, tol):
 
 class Batch:
     def __init__(self, problems, precision="fp32", streams=4, device=0, margin=1.1,
-                 lr=1e-2, betas=(0.9, 0.999), eps=1e-8):
+                 lr=1e-2, betas=(0.9, 0.999), eps=1e-8, tune_tiles=False):
         self.dev = torch.device(f"cuda:{device}")
         self.problems = list(problems)
-        self.handles = [qoc.Problem(p, precision=precision, device=device) for p in self.problems]
+        # tile shape per instance (padding multiple of d), measured and cached
+        # by (architecture, d, S, M, precision) when tune_tiles is set
+        self.pads = [16] * len(self.problems)
+        self.tile_tuning = {}
+        if tune_tiles:
+            from . import tune
+            for i, p in enumerate(self.problems):
+                r = tune.tune_tiles(p, precision=precision, device=device)
+                self.pads[i] = r["pad_multiple"]
+                self.tile_tuning[tune.tile_key(p, precision, device)] = r
+        self.handles = [qoc.Problem(p, precision=precision, device=device, pad_multiple=pm)
+                        for p, pm in zip(self.problems, self.pads)]
         f64 = torch.float64
         sizes = [max(1, p.M * p.N) for p in self.problems]
         offs = np.concatenate([[0], np.cumsum(sizes)]).astype(int)

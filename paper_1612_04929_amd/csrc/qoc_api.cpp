@@ -1290,6 +1290,9 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
   if (D.precision != QOC_FP32 && D.precision != QOC_FP64 && D.precision != QOC_BF16X3)
     return fail(QOC_ERR_ARG, "precision must be QOC_FP32, QOC_FP64 or QOC_BF16X3");
   if (D.checkpoint_every < 0) return fail(QOC_ERR_ARG, "checkpoint_every must be >= 0");
+  if (!(D.pad_multiple == 0 || D.pad_multiple == 16 || D.pad_multiple == 32 ||
+        D.pad_multiple == 64))
+    return fail(QOC_ERR_ARG, "pad_multiple must be 0, 16, 32 or 64");
   if (!(D.taylor_tol >= 0.0) || !std::isfinite(D.taylor_tol))
     return fail(QOC_ERR_ARG, "taylor_tol must be finite and >= 0");
   if (!(D.taylor_p == 0 || (D.taylor_p >= 2 && D.taylor_p <= 64 && D.taylor_n >= 0 &&
@@ -1330,7 +1333,14 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
   qoc_handle *h = new (std::nothrow) qoc_handle();
   if (!h) return fail(QOC_ERR_NOMEM, "host allocation failed");
   h->d = D.d;
-  h->dp = (D.d + 15) / 16 * 16;
+  {
+    // padding of d: a multiple of 16 by default (16 / 32-wide tiles and the
+    // small-d chains for d <= 48), or of 32 / 64 on request (64 x 64 tiles
+    // for every product at the price of more zero padding; a tile-shape
+    // choice that bench and Batch leave to the measuring tuner)
+    const int pm = D.pad_multiple > 0 ? D.pad_multiple : 16;
+    h->dp = (D.d + pm - 1) / pm * pm;
+  }
   h->M = D.M;
   h->N = D.N;
   h->S = D.S;

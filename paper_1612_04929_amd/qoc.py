@@ -49,7 +49,7 @@ class Desc(C.Structure):
                 ("precision", C.c_int), ("checkpoint_every", C.c_int),
                 ("taylor_tol", C.c_double), ("taylor_p", C.c_int), ("taylor_n", C.c_int),
                 ("drift_warn", C.c_double), ("device", C.c_int), ("n_forbidden", C.c_int),
-                ("forbidden", _dp), ("alpha_time", C.c_double)]
+                ("forbidden", _dp), ("alpha_time", C.c_double), ("pad_multiple", C.c_int)]
 
 
 class Info(C.Structure):
@@ -154,7 +154,7 @@ class Problem:
     """
 
     def __init__(self, prob, precision="fp32", checkpoint_every=0, taylor_tol=0.0,
-                 taylor_pn=None, drift_warn=0.0, device=0, structure=-1):
+                 taylor_pn=None, drift_warn=0.0, device=0, structure=-1, pad_multiple=0):
         lib = load()
         self.d, self.M, self.N, self.S = int(prob.d), int(prob.M), int(prob.N), int(prob.S)
         keep = []
@@ -183,7 +183,7 @@ class Problem:
                     float(prob.alpha_amp), float(prob.alpha_var), float(prob.alpha_pen),
                     int(fid), PRECISIONS.get(precision, precision), int(checkpoint_every),
                     float(taylor_tol), tp, tn, float(drift_warn), int(device), nf, pf,
-                    float(getattr(prob, "alpha_time", 0.0)))
+                    float(getattr(prob, "alpha_time", 0.0)), int(pad_multiple))
         self._h = C.c_void_p()
         _check(lib.qoc_create(C.byref(desc), C.byref(self._h)))
         self.precision = precision

@@ -44,3 +44,30 @@ def test_tuned_configuration_matches_oracle():
     assert cfg["checkpoint_every"] in [r["L"] for r in cfg["table"]]
     out, ref, e = compare("tuned", p, checkpoint_every=cfg["checkpoint_every"])
     check(p, e)
+
+
+@pytest.mark.parametrize("d,pm", [(100, 64), (40, 64), (70, 32), (20, 64)])
+def test_padding_multiple_matches_oracle(d, pm):
+    # zero padding to a multiple of 32 / 64 (64 x 64 tiles) is exact
+    rng = np.random.default_rng(31 + d)
+    p = workloads.random_problem(rng, d=d, M=3, N=40, S=2, dt=0.2, scale=1.5)
+    out, ref, e = compare(f"pad{pm}_d{d}", p, pad_multiple=pm)
+    check(p, e)
+    assert out["d_pad"] == (d + pm - 1) // pm * pm
+
+
+def test_tile_tuner_picks_a_candidate_and_caches(tmp_path, monkeypatch):
+    from paper_1612_04929_amd import tune
+    monkeypatch.setenv("QOC_TUNE_CACHE", str(tmp_path / "tiles.json"))
+    monkeypatch.setattr(tune, "_TILE_CACHE", None)
+    rng = np.random.default_rng(37)
+    p = workloads.random_problem(rng, d=100, M=2, N=300, S=2, dt=0.2)
+    say("[tune] tiles d=100")
+    r = tune.tune_tiles(p, steps=128)
+    say(f"[tune] tiles: {r}")
+    assert r["pad_multiple"] in tune.pad_candidates(100) and not r["cached"]
+    assert set(r["ms"]) == {"16", "64"}
+    r2 = tune.tune_tiles(p, steps=128)
+    assert r2["cached"] and r2["pad_multiple"] == r["pad_multiple"]
+    assert (tmp_path / "tiles.json").exists()
+    assert tune.pad_candidates(64) == [16] and tune.pad_candidates(20) == [16]
