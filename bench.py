@@ -384,7 +384,7 @@ def single_kernel_phases(info, sweep, precision="fp32"):
         ph.add("blockprod")
     if dp == 16:
         ph.add("adjoint")
-    chain = precision != "fp64" and 64 <= dp <= 128  # variant 4, the default from 80
+    chain = precision != "fp64" and 64 <= dp <= 128  # variant 4, the default from 64
     for name, v in zip(["fwd_blocks", "fwd_replay", "bwd_blocks", "bwd_pairs"], sweep):
         blocks = name in ("fwd_blocks", "bwd_blocks")
         auto_wide = v == 0 and not chain and (blocks or dp >= 256)

@@ -1028,8 +1028,10 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     }
     if (wave && !(mode == 3 && qoc::small_sweep_ok<T>(dp, S)))
       return qoc::launch_wave_sweep<T>(which, sw, st);
-    // chain workgroups: by default for FP32 padded d 80 .. 128
-    if (qoc::chain_sweep_ok<T>(dp, S) && (mode == 4 || (mode == 0 && dp >= 80)))
+    // chain workgroups: by default for FP32 padded d 64 .. 128 (measured at
+    // padded d 64, S = 2, N ~ 2900: 1.8 ms per call against 3.7 ms with the
+    // four-wavefront LDS sweeps)
+    if (qoc::chain_sweep_ok<T>(dp, S) && (mode == 4 || (mode == 0 && dp >= 64)))
       return qoc::launch_chain_sweep<T>(which, sw, st);
     if (wave || small) return qoc::launch_small_sweep<T>(which, sw, st);
     // per-step launches: the block sweeps (F2, B2) from padded d 80, the
