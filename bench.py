@@ -592,6 +592,11 @@ def main():
             q = workloads.make_config(name)
             tq = None if args.no_tune else qtune.tune(q, precision=args.precision)
             res.setdefault("other_workloads", {})[name] = quick_measure(q, args.precision, args, tq)
+            if name == "c3":
+                # the transmon-cavity workload's stated checkpoint interval, 71
+                t71 = dict(checkpoint_every=71, sweep=tq["sweep"] if tq else [0, 0, 0, 0])
+                res["other_workloads"]["c3_checkpoint_71"] = quick_measure(q, args.precision,
+                                                                            args, t71)
     if not args.no_torch_baseline:
         tb = fp64_torch_path(prob, dev)
         g64 = tb.pop("grad")

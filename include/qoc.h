@@ -123,8 +123,8 @@ typedef struct {
   int fid_mode;             /* QOC_FID_COHERENT or QOC_FID_INCOHERENT       */
   int precision;            /* QOC_FP32 (default), QOC_FP64 or QOC_BF16X3   */
   int checkpoint_every;     /* state checkpoint interval L of the blocked
-                               sweeps; 0 = power of two nearest sqrt(N);
-                               otherwise rounded up to a power of two       */
+                               sweeps (any L >= 1, used as given); 0 = the
+                               power of two nearest sqrt(N)                 */
   double taylor_tol;        /* truncation tolerance tau of the (p, n) rule;
                                0 = 1e-10 (FP32, BF16X3) or 1e-15 (FP64)     */
   int taylor_p, taylor_n;   /* taylor_p >= 2 and taylor_n >= 0: fixed global

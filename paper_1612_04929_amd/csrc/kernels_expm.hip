@@ -13,6 +13,16 @@
 
 namespace qoc {
 
+// Offset of matrix j of a stage operand: j * stride, or with segments of
+// a.seg matrices (the per-block trees of the block products) the segment's
+// own stride between segments: (j / seg) * segstride + (j % seg) * stride.
+template <typename T>
+__device__ __forceinline__ long moff(const StageArgs<T> &a, long j, long stride, long segstride) {
+  if (a.seg <= 0) return j * stride;
+  const long b = j / a.seg;
+  return b * segstride + (j - b * a.seg) * stride;
+}
+
 // Block: 256 consecutive matrix entries (one per thread, coalesced) x
 // AS_STEPS steps; each Hamiltonian entry loaded feeds AS_STEPS steps, and
 // the control amplitudes are wave-uniform LDS broadcasts.
@@ -94,12 +104,12 @@ __device__ __forceinline__ void stage_store(const StageArgs<T> &a, long j, int r
   const bool needA = a.betaA != (T)0 || (a.C2 && a.c2A != (T)0);
   const bool needB = a.betaB != (T)0 || (a.C2 && a.c2B != (T)0);
   if (needA) {
-    const T *Aj = a.A + j * a.strideA;
+    const T *Aj = a.A + moff(a, j, a.strideA, a.segA);
     ar = Aj[o];
     ai = Aj[plane + o];
   }
   if (needB) {
-    const T *Bj = a.B + j * a.strideB;
+    const T *Bj = a.B + moff(a, j, a.strideB, a.segB);
     br = Bj[o];
     bi = Bj[plane + o];
   }
@@ -108,13 +118,13 @@ __device__ __forceinline__ void stage_store(const StageArgs<T> &a, long j, int r
   if (row == col) vr += a.gamma;
   T xr[3] = {0, 0, 0}, xi[3] = {0, 0, 0};
   for (int q = 0; q < a.nx; ++q) {
-    const T *Xq = a.xadd[q] + j * a.strideC;
+    const T *Xq = a.xadd[q] + moff(a, j, a.strideC, a.segC);
     xr[q] = Xq[o];
     xi[q] = Xq[plane + o];
     vr += a.xc[q] * xr[q];
     vi += a.xc[q] * xi[q];
   }
-  T *Cj = a.C + j * a.strideC;
+  T *Cj = a.C + moff(a, j, a.strideC, a.segC);
   Cj[o] = vr;
   Cj[plane + o] = vi;
   if (a.C2) {
@@ -125,7 +135,7 @@ __device__ __forceinline__ void stage_store(const StageArgs<T> &a, long j, int r
       wr += a.xc2[q] * xr[q];
       wi += a.xc2[q] * xi[q];
     }
-    T *C2j = a.C2 + j * a.strideC;
+    T *C2j = a.C2 + moff(a, j, a.strideC, a.segC);
     C2j[o] = wr;
     C2j[plane + o] = wi;
   }
@@ -142,7 +152,7 @@ __device__ __forceinline__ void stage_store_n(const StageArgs<T> &a, long j, con
   const long plane = (long)a.dp * a.dp;
   const bool needA = a.betaA != (T)0 || (a.C2 && a.c2A != (T)0);
   const bool needB = a.betaB != (T)0 || (a.C2 && a.c2B != (T)0);
-  const T *Aj = a.A + j * a.strideA, *Bj = a.B + j * a.strideB;
+  const T *Aj = a.A + moff(a, j, a.strideA, a.segA), *Bj = a.B + moff(a, j, a.strideB, a.segB);
   T ar[NV], ai[NV], br[NV], bi[NV], xr[3][NV], xi[3][NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -153,13 +163,13 @@ __device__ __forceinline__ void stage_store_n(const StageArgs<T> &a, long j, con
     bi[v] = needB ? Bj[plane + o] : (T)0;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      const T *Xq = a.xadd[q] + j * a.strideC;
+      const T *Xq = a.xadd[q] + moff(a, j, a.strideC, a.segC);
       xr[q][v] = q < a.nx ? Xq[o] : (T)0;
       xi[q][v] = q < a.nx ? Xq[plane + o] : (T)0;
     }
   }
-  T *Cj = a.C + j * a.strideC;
-  T *C2j = a.C2 ? a.C2 + j * a.strideC : nullptr;
+  T *Cj = a.C + moff(a, j, a.strideC, a.segC);
+  T *C2j = a.C2 ? a.C2 + moff(a, j, a.strideC, a.segC) : nullptr;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const long o = (long)row[v] * a.dp + col[v];
@@ -201,8 +211,8 @@ __global__ __launch_bounds__(256) void k_stage16(StageArgs<T> a) {
   const int t = (int)(gt - j * tiles);
   const int r0 = (t / t1) * 16, c0 = (t % t1) * 16;
   const long plane = (long)a.dp * a.dp;
-  CView<const T> A = cview<const T>(a.A + j * a.strideA, plane, a.dp);
-  CView<const T> B = cview<const T>(a.B + j * a.strideB, plane, a.dp);
+  CView<const T> A = cview<const T>(a.A + moff(a, j, a.strideA, a.segA), plane, a.dp);
+  CView<const T> B = cview<const T>(a.B + moff(a, j, a.strideB, a.segB), plane, a.dp);
   v4<T> cr = vzero<T>(), ci = vzero<T>();
   wave_cgemm16<T, OPA, 0>(A, B, r0, c0, a.dp, cr, ci);
 #pragma unroll
@@ -223,8 +233,8 @@ __global__ __launch_bounds__(256) void k_stage64(StageArgs<T> a, long padded) {
   const int t = (int)(logical - j * tiles);
   const int r0 = (t / t1) * 64, c0 = (t % t1) * 64;
   const long plane = (long)a.dp * a.dp;
-  CView<const T> A = cview<const T>(a.A + j * a.strideA, plane, a.dp);
-  CView<const T> B = cview<const T>(a.B + j * a.strideB, plane, a.dp);
+  CView<const T> A = cview<const T>(a.A + moff(a, j, a.strideA, a.segA), plane, a.dp);
+  CView<const T> B = cview<const T>(a.B + moff(a, j, a.strideB, a.segB), plane, a.dp);
   v4<T> acc[2][2][2];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
@@ -286,7 +296,7 @@ __global__ __launch_bounds__(256) void k_stage32(StageArgs<T> a, long padded) {
   const int r0 = (tt / t1) * 32, c0 = (tt % t1) * 32;
   const int dp = a.dp;
   const long plane = (long)dp * dp;
-  const T *Aj = a.A + j * a.strideA, *Bj = a.B + j * a.strideB;
+  const T *Aj = a.A + moff(a, j, a.strideA, a.segA), *Bj = a.B + moff(a, j, a.strideB, a.segB);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int i = lane & 15, kk = lane >> 4;
   const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
@@ -357,8 +367,8 @@ __global__ __launch_bounds__(256) void k_stage64_bf3(StageArgs<float> a, long pa
   const int t = (int)(logical - j * tiles);
   const int r0 = (t / t1) * 64, c0 = (t % t1) * 64;
   const long plane = (long)a.dp * a.dp;
-  const TOp<float> A = make_top<float>(a.A + j * a.strideA, plane, a.dp, a.dp);
-  const TOp<float> B = make_top<float>(a.B + j * a.strideB, plane, a.dp, a.dp);
+  const TOp<float> A = make_top<float>(a.A + moff(a, j, a.strideA, a.segA), plane, a.dp, a.dp);
+  const TOp<float> B = make_top<float>(a.B + moff(a, j, a.strideB, a.segB), plane, a.dp, a.dp);
   f32x4 acc[2][2][2];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
@@ -504,6 +514,33 @@ template <typename T> hipError_t launch_copy(T *dst, const T *src, long n, hipSt
 
 template hipError_t launch_copy<float>(float *, const float *, long, hipStream_t);
 template hipError_t launch_copy<double>(double *, const double *, long, hipStream_t);
+
+// count segments of n elements: dst + b dstride <- src + b sstride
+template <typename T>
+__global__ void k_copy_strided(T *dst, long dstride, const T *src, long sstride, long n, long count) {
+  const long b = blockIdx.y;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    dst[b * dstride + i] = src[b * sstride + i];
+}
+
+template <typename T>
+hipError_t launch_copy_strided(T *dst, long dstride, const T *src, long sstride, long n,
+                               long count, hipStream_t st) {
+  if (n <= 0 || count <= 0) return hipSuccess;
+  long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  for (long b0 = 0; b0 < count; b0 += 65535) {
+    const long cnt = count - b0 < 65535 ? count - b0 : 65535;
+    hipLaunchKernelGGL(k_copy_strided<T>, dim3((unsigned)blocks, (unsigned)cnt), dim3(256), 0, st,
+                       dst + b0 * dstride, dstride, src + b0 * sstride, sstride, n, cnt);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_copy_strided<float>(float *, long, const float *, long, long, long,
+                                               hipStream_t);
+template hipError_t launch_copy_strided<double>(double *, long, const double *, long, long, long,
+                                                hipStream_t);
 template hipError_t launch_assemble<float>(const float *, const double *, int, int, int, float,
                                            float, float *, float *, hipStream_t);
 template hipError_t launch_assemble<double>(const double *, const double *, int, int, int, double,

@@ -802,6 +802,68 @@ template <typename T> bool small_big_adjoint(const qoc_handle *h) {
   return h->fixed_p >= 2 && h->dp >= 32 && !qoc::adjoint16_ok<T>(h->dp, kSmallPCap);
 }
 
+// Block products for a checkpoint interval L that is not a power of two:
+// a pairwise tree inside every block (the blocks' trees side by side),
+// E_b = U_{bL+L-1} ... U_{bL} - I in D-form (C = A + B + A B).  At each
+// level the c elements of a full block pair up as (2i, 2i + 1) -> i, one
+// stage launch over all full blocks (segments of c / 2 products), an odd
+// last element carried by a strided copy; the shorter last block runs its
+// own launches into the slot after the full blocks, so every level's
+// results are contiguous per block and the final E_b are contiguous.
+template <typename T>
+hipError_t block_tree_any(qoc_handle *h, const T *D, T *Qa, T *Qb, long mat, int bf3,
+                          hipStream_t st, const T **E_out) {
+  const long N = h->N, L = h->L, nb = h->nb;
+  const long nfull = N / L, clast = N - nfull * L;  // clast: steps of a short last block
+  long c = L, cl = clast;  // elements per full block and in the short block at this level
+  const T *in = D;
+  long in_stride = L * mat;  // between full blocks at this level
+  long in_last = nfull * L * mat;  // offset of the short block's elements
+  T *out = Qa;
+  while (c > 1 || cl > 1) {
+    const long c2 = (c + 1) / 2, cl2 = (cl + 1) / 2;
+    const long out_stride = c2 * mat, out_last = nfull * c2 * mat;
+    if (c > 1 && nfull > 0) {
+      qoc::StageArgs<T> a{in + mat, 2 * mat, in, 2 * mat, out, mat, (int)(nfull * (c / 2)),
+                          h->dp, (T)1, (T)1, (T)1, (T)0, bf3};
+      a.seg = (int)(c / 2);
+      a.segA = a.segB = in_stride;
+      a.segC = out_stride;
+      PhaseTimer tm(h, QOC_PHASE_BLOCKPROD, st);
+      hipError_t e = qoc::launch_stage<T>(0, a, st);
+      if (e != hipSuccess) return e;
+    }
+    if (nfull > 0 && (c & 1)) {
+      // the odd element of every full block, carried (c == 1: the block's
+      // product is already complete and moves to this level's buffer)
+      hipError_t e = qoc::launch_copy_strided<T>(out + (c2 - 1) * mat, out_stride,
+                                                 in + (c - 1) * mat, in_stride, mat, nfull, st);
+      if (e != hipSuccess) return e;
+    }
+    if (cl > 1) {
+      qoc::StageArgs<T> a{in + in_last + mat, 2 * mat, in + in_last, 2 * mat, out + out_last,
+                          mat, (int)(cl / 2), h->dp, (T)1, (T)1, (T)1, (T)0, bf3};
+      PhaseTimer tm(h, QOC_PHASE_BLOCKPROD, st);
+      hipError_t e = qoc::launch_stage<T>(0, a, st);
+      if (e != hipSuccess) return e;
+    }
+    if (cl > 0 && (cl & 1)) {
+      hipError_t e = qoc::launch_copy<T>(out + out_last + (cl2 - 1) * mat,
+                                         in + in_last + (cl - 1) * mat, mat, st);
+      if (e != hipSuccess) return e;
+    }
+    c = c2;
+    cl = cl2;
+    in = out;
+    in_stride = out_stride;
+    in_last = out_last;
+    out = (out == Qa) ? Qb : Qa;
+  }
+  (void)nb;
+  *E_out = in;
+  return hipSuccess;
+}
+
 template <typename T>
 qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad_dev,
                hipStream_t st, bool want_grad) {
@@ -957,6 +1019,9 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     }
     D = Dl + (long)n * lev;
     // ---- block products E_b (pairwise tree, D-form: C = A + B + A B)
+    if (h->L & (h->L - 1)) {
+      HIP_TRY(block_tree_any<T>(h, D, Qa, Qb, mat, bB, st, &E));
+    } else {
     long cnt = N;
     const T *in = D;
     T *outb = Qa;
@@ -974,6 +1039,7 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
       outb = (outb == Qa) ? Qb : Qa;
     }
     E = in;
+    }
   }
   // FP64 unitarity drift of the final propagators (a diagnostic; at padded
   // d 16 after the block products, which may recompute D with the chosen pair)
@@ -1370,7 +1436,7 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
   }
   h->device = D.device;
   if (D.checkpoint_every > 0) {
-    h->L = pow2_at_least(D.checkpoint_every);
+    h->L = D.checkpoint_every;
   } else {
     const double r = std::sqrt((double)D.N);
     int l = 1;

@@ -29,6 +29,11 @@ template <typename T> struct StageArgs {
   T *C2;                  // optional second output (null: none)
   T c2P, c2A, c2B, g2;
   T xc2[3];
+  // segments (seg > 0): matrix j = b seg + i of a stack sits at
+  // base + b * seg{A,B,C} + i * stride (the per-block trees of the block
+  // products); seg = 0: base + j * stride
+  int seg;
+  long segA, segB, segC;
 };
 
 // X_j = -i s (H_0 + sum_k u_{k,j} H_k) for all steps and, when Q is not
@@ -71,6 +76,10 @@ hipError_t launch_norm(const double *H64, const double *u, int d, int M, int N, 
 template <typename T> hipError_t launch_fill(T *p, long n, T v, hipStream_t st);
 // dst[0:n] = src[0:n] (a kernel, so that captured graphs hold no copy nodes)
 template <typename T> hipError_t launch_copy(T *dst, const T *src, long n, hipStream_t st);
+// count segments of n elements: dst + b * dstride <- src + b * sstride
+template <typename T>
+hipError_t launch_copy_strided(T *dst, long dstride, const T *src, long sstride, long n,
+                               long count, hipStream_t st);
 
 // Small padded d (16, 32; 48 in FP32): the whole Taylor + squaring chain of
 // a step in LDS, (p, n, dt/2^n) read from device memory (pn, sc).  Level

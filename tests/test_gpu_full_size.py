@@ -25,7 +25,8 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 # (workload, checkpoint interval, sweep variants F2, F3, B2, B3)
-CASES = [("c3", 64, (4, 4, 4, 4)), ("c4", 32, (2, 2, 2, 2))]
+CASES = [("c3", 64, (4, 4, 4, 4)), ("c4", 32, (2, 2, 2, 2)),
+         ("c3", 71, (4, 4, 4, 4))]  # the transmon-cavity workload's stated interval
 # accuracy targets per precision: |dF|, gradient rel-l2, max |dc_j|
 TARGETS = {"fp32": (1e-6, 1e-4, 2e-6), "bf16x3": (1e-5, 1e-3, 2e-5)}
 

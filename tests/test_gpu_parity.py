@@ -130,7 +130,7 @@ def test_random_problems(d, S, N, mode):
     check(p, e)
 
 
-@pytest.mark.parametrize("L", [1, 2, 8, 64])
+@pytest.mark.parametrize("L", [1, 2, 8, 64, 3, 7, 71])
 def test_checkpoint_interval_does_not_change_results(L):
     rng = np.random.default_rng(7)
     p = workloads.random_problem(rng, d=12, M=2, N=50, S=2, dt=0.3, scale=1.5)
@@ -162,7 +162,7 @@ def test_split_in_block_passes(d, S, N, L, pen, mode, prec):
     assert e["L"] == L
 
 
-@pytest.mark.parametrize("L", [1, 4, 64])
+@pytest.mark.parametrize("L", [1, 4, 64, 3, 12, 71])
 def test_wide_sweeps_checkpoint_intervals(L):
     # padded d 96: per-step launches of the sweeps, ragged last block, penalty
     rng = np.random.default_rng(17)
@@ -173,7 +173,7 @@ def test_wide_sweeps_checkpoint_intervals(L):
 
 
 @pytest.mark.parametrize("d,S,N,L", [(64, 2, 45, 8), (70, 3, 50, 16), (120, 1, 70, 32),
-                                     (100, 2, 33, 1)])
+                                     (100, 2, 33, 1), (128, 1, 300, 71), (64, 2, 100, 9)])
 def test_chain_workgroup_sweeps(d, S, N, L):
     # sweep variant 4 on padded d 64 / 80 / 128 / 112: every sweep as one
     # 8 d_pad-thread workgroup per block, ragged last block, penalty
