@@ -192,3 +192,32 @@ def test_capture_of_a_synchronising_call_is_rejected():
         torch.cuda.synchronize()
         assert torch.equal(out, ref[0]) and torch.equal(g, ref[1])
     h.close()
+
+
+@pytest.mark.parametrize("case", ["d16", "d40", "d100", "c4_structured", "ext"])
+def test_results_are_bitwise_deterministic(case):
+    """Every reduction runs in a fixed order (no floating-point atomics): two
+    calls on one handle and a call on a fresh handle give the same bits."""
+    rng = np.random.default_rng(1300)
+    if case == "d16":
+        p = workloads.config2().with_steps(300)
+    elif case == "d40":
+        p = workloads.random_problem(rng, d=40, M=3, N=90, S=3, dt=0.2, scale=1.5)
+    elif case == "d100":
+        p = workloads.random_problem(rng, d=100, M=3, N=70, S=2, dt=0.2, scale=1.5)
+    elif case == "c4_structured":
+        p = workloads.config4().with_steps(30)
+    else:
+        p = workloads.random_problem(rng, d=24, M=2, N=80, S=2, dt=0.2, scale=1.5,
+                                     n_forbidden=2, alpha_time=0.3)
+    say(f"[diag] determinism {case}")
+    h1 = qoc.Problem(p)
+    a = h1.cost_grad(p.u)
+    b = h1.cost_grad(p.u)
+    h1.close()
+    h2 = qoc.Problem(p)
+    c = h2.cost_grad(p.u)
+    h2.close()
+    for x in (b, c):
+        assert x["C"] == a["C"] and x["C_fid"] == a["C_fid"]
+        assert np.array_equal(x["c"], a["c"]) and np.array_equal(x["grad"], a["grad"])
