@@ -39,14 +39,14 @@ HBM_PEAK = 8.0e12
 # HBM bytes per launch (read, written) of the kernel behind a timed phase,
 # from two rocprofv3 PMC runs (FETCH_SIZE, WRITE_SIZE) scaled by the same
 # counters on a 256 MiB device copy (x2.0 and x1.0 to four digits); the table, commands
-# and calibration are in profiles/hbm_traffic_pmc.md.  FP32 chains.
+# and calibration are in profiles/hbm_traffic_pmc.md.  FP32 chains; kernels
+# changed since their counters were taken have no entry (traffic null).
 TRAFFIC = {
     ("c2_transmon_cnot", "adjoint"): ("k_adjoint16", 15221088, 64064),
     ("c2_transmon_cnot", "taylor"): ("k_expm16", 615810, 18857632),
     ("c2_transmon_cnot", "bwd_blocks"): ("k_wB2", 2872874, 160384),
     ("c2_transmon_cnot", "fwd_replay"): ("k_wF3s", 36083954, 1184768),
-    ("c3_transmon_cavity", "taylor"): ("k_stage64", 1296167514, 734440794),
-    ("c4_spin_chain", "taylor"): ("k_stage64", 6248850207, 3050028777),
+    ("c4_spin_chain", "taylor"): ("k_stage64", 6328181985, 3122350848),
 }
 
 

@@ -437,11 +437,16 @@ template <typename T> struct SContract {
   int N, M, d;
 };
 
-template <typename T> __global__ __launch_bounds__(256) void k_sgcontract(SContract<T> a) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_sgcontract(SContract<T> a, long padded) {
   extern __shared__ double gsh[];  // [4 waves][M][64 lanes]
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = blockIdx.x;
-  const long j = blockIdx.y;
+  // the SG_GROUPS workgroups of one step on one XCD, so that they share the
+  // step's panel in its L2 (read from HBM about once)
+  const long logical = xcd_logical_block(blockIdx.x, padded);
+  if (logical >= (long)a.N * SG_GROUPS) return;  // block-uniform
+  const int g = (int)(logical % SG_GROUPS);
+  const long j = logical / SG_GROUPS;
   double *acc = gsh + (long)w * a.M * 64 + lane;
   for (int k = 0; k < a.M; ++k) acc[k * 64] = 0.0;
   const T *Pr = a.panel + j * a.per, *Pi = Pr + a.big;
@@ -772,8 +777,9 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
     if (M > 0) {
       SContract<T> sc2{sc + 8 * thin, per, big, (int)KK2, rr, p, a.rptr, a.rcol, a.eptr, a.ek,
                        a.eval, a.nev, a.part, N, M, a.d};
-      hipLaunchKernelGGL(k_sgcontract<T>, dim3(SG_GROUPS, N), dim3(256),
-                         (size_t)M * SG_LDS_PER_CONTROL, st, sc2);
+      const long total = (long)SG_GROUPS * N, padded = (total + 7) / 8 * 8;
+      hipLaunchKernelGGL(k_sgcontract<T>, dim3((unsigned)padded), dim3(256),
+                         (size_t)M * SG_LDS_PER_CONTROL, st, sc2, padded);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     AdjFinish<T> f{a.part, a.u, a.grad, 2.0 * a.s_scale, a.alpha_amp, a.alpha_var, nullptr, N, M,
