@@ -144,6 +144,20 @@ typedef struct {
                                of 64 runs every product on 64 x 64 MFMA
                                tiles (a tile-shape choice for measuring
                                tuners); anything else is QOC_ERR_ARG       */
+  int segment_steps;        /* memory-lean mode (batched path, padded
+                               d >= 64): 0 = one
+                               segment; otherwise the horizon is cut into
+                               time segments of this many steps (rounded up
+                               to a multiple of the checkpoint interval L)
+                               and every per-step stack (propagators, Taylor
+                               and squaring levels, derivative work space)
+                               holds one segment: the backward pass
+                               recomputes each segment's exponentials from
+                               the controls (Sec. 5.2 and App. A trade
+                               memory for recomputation the same way).  The
+                               states, checkpoints and costates stay whole
+                               (O(N S d)).  Negative: QOC_ERR_ARG; a handle
+                               on the small-d path: QOC_ERR_UNSUPPORTED    */
 } qoc_problem_desc;
 
 /* Diagnostics of the most recent forward / cost_grad call on a handle. */
@@ -166,6 +180,8 @@ typedef struct {
                                no check (qoc_set_unitarity_check)           */
   int structured;           /* 1 when the last call ran the structured
                                (sparse) norm and gradient contraction       */
+  int segments;             /* time segments of the memory-lean mode (1: the
+                               whole horizon at once)                       */
 } qoc_info;
 
 /* Create a handle: validates and copies the problem to device memory.

@@ -614,6 +614,10 @@ template <typename T> __global__ void k_adj_horn_init(AdjHorn<T> a) {
   }
 }
 
+// Gradient entries of the N steps j0 .. j0 + N - 1 of a horizon of Nf steps
+// (u and grad: M x Nf; j0 = 0, Nf = N unless a time segment is processed):
+// the contraction's partial sums (local step index) plus the regularisers,
+// whose control variations reach the neighbouring steps across segment ends.
 template <typename T> struct AdjFinish {
   const double *part;
   const double *u;
@@ -621,6 +625,8 @@ template <typename T> struct AdjFinish {
   double two_s, alpha_amp, alpha_var;
   const double *sc;  // device dt/2^n (or null: use two_s)
   int N, M, tiles;
+  long j0;
+  int Nf;
 };
 
 template <typename T> __global__ void k_adj_finish(AdjFinish<T> a) {
@@ -631,12 +637,13 @@ template <typename T> __global__ void k_adj_finish(AdjFinish<T> a) {
     const long j = e - (long)k * a.N;
     double g = 0.0;
     for (int t = 0; t < a.tiles; ++t) g += a.part[(j * a.tiles + t) * a.M + k];
-    const double *uk = a.u + (long)k * a.N;
-    double reg = 2.0 * a.alpha_amp * uk[j];
-    if (j >= 1) reg += 2.0 * a.alpha_var * (uk[j] - uk[j - 1]);
-    if (j <= a.N - 2) reg -= 2.0 * a.alpha_var * (uk[j + 1] - uk[j]);
+    const double *uk = a.u + (long)k * a.Nf;
+    const long jg = a.j0 + j;
+    double reg = 2.0 * a.alpha_amp * uk[jg];
+    if (jg >= 1) reg += 2.0 * a.alpha_var * (uk[jg] - uk[jg - 1]);
+    if (jg <= a.Nf - 2) reg -= 2.0 * a.alpha_var * (uk[jg + 1] - uk[jg]);
     const double two_s = a.sc ? 2.0 * a.sc[0] : a.two_s;
-    a.grad[e] = two_s * g + reg;
+    a.grad[(long)k * a.Nf + jg] = two_s * g + reg;
   }
 }
 
@@ -783,7 +790,7 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     AdjFinish<T> f{a.part, a.u, a.grad, 2.0 * a.s_scale, a.alpha_amp, a.alpha_var, nullptr, N, M,
-                   SG_GROUPS};
+                   SG_GROUPS, a.j0, a.ldN > 0 ? a.ldN : N};
     hipLaunchKernelGGL(k_adj_finish<T>, dim3(grid_for((long)N * M)), dim3(256), 0, st, f);
     return hipGetLastError();
   }
@@ -810,7 +817,7 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
     }
   }
   AdjFinish<T> f{a.part, a.u, a.grad, 2.0 * a.s_scale, a.alpha_amp, a.alpha_var, nullptr, N, M,
-                 (int)nsl};
+                 (int)nsl, a.j0, a.ldN > 0 ? a.ldN : N};
   hipLaunchKernelGGL(k_adj_finish<T>, dim3(grid_for((long)N * M)), dim3(256), 0, st, f);
   return hipGetLastError();
 }
@@ -866,7 +873,8 @@ template <typename T> hipError_t launch_grad_first(const AdjointArgs<T> &a, doub
     hipLaunchKernelGGL(k_gcontract<T>, grid, dim3(256), 0, st, gc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  AdjFinish<T> f{a.part, a.u, a.grad, 2.0 * dt, a.alpha_amp, a.alpha_var, nullptr, N, M, (int)nsl};
+  AdjFinish<T> f{a.part, a.u, a.grad, 2.0 * dt, a.alpha_amp, a.alpha_var, nullptr, N, M, (int)nsl,
+                 a.j0, a.ldN > 0 ? a.ldN : N};
   hipLaunchKernelGGL(k_adj_finish<T>, dim3(grid_for((long)N * M)), dim3(256), 0, st, f);
   return hipGetLastError();
 }

@@ -473,6 +473,44 @@ template <typename T> __global__ __launch_bounds__(256) void k_bwd_pairs(SweepAr
   }
 }
 
+// ------------------------------------------------------------------ segment start
+// Time segments (memory-lean mode): the costate at a segment's first step
+// j0 >= 1, lambda_j0 = lambda_{j0+1} + D_j0^H lambda_{j0+1} + pw o psi_j0 +
+// src_j0, written to the segment's first checkpoint lam_ckpt[0].  The
+// arguments are the segment's own (lam_buf[0] = lambda_{j0+1}, D[0],
+// psi_buf[0], src[0]); the preceding segment's block sweep starts from it.
+template <typename T> __global__ __launch_bounds__(256) void k_seg_lambda(SweepArgs<T> a) {
+  extern __shared__ unsigned char shraw[];
+  T *buf = (T *)shraw;
+  const int dp = a.dp, S = a.S, s = blockIdx.x;
+  T *xr = buf, *xi = buf + dp, *yr = buf + 2 * dp, *yi = buf + 3 * dp;
+  T *pr = buf + 4 * dp, *pi = buf + 5 * dp;
+  for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+    xr[m] = set_re(a.lam_buf, S, dp, s)[m];
+    xi[m] = set_im(a.lam_buf, S, dp, s)[m];
+    const T wgt = a.pw ? a.pw[m] : (T)0;
+    T vr = wgt * set_re(a.psi_buf, S, dp, s)[m], vi = wgt * set_im(a.psi_buf, S, dp, s)[m];
+    if (a.src) {
+      vr += set_re(a.src, S, dp, s)[m];
+      vi += set_im(a.src, S, dp, s)[m];
+    }
+    pr[m] = vr;
+    pi[m] = vi;
+  }
+  __syncthreads();
+  mv_plus_adj(a.D, a.D + (long)dp * dp, dp, xr, xi, yr, yi, pr, pi, buf + 6 * dp);
+  __syncthreads();
+  for (int m = threadIdx.x; m < dp; m += blockDim.x) {
+    set_rew(a.lam_ckpt, S, dp, s)[m] = yr[m];
+    set_imw(a.lam_ckpt, S, dp, s)[m] = yi[m];
+  }
+}
+
+template <typename T> hipError_t launch_seg_lambda(const SweepArgs<T> &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_lambda<T>, dim3(a.S), dim3(256), 6 * a.dp * sizeof(T) + 8192, st, a);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ wide
 // Large d: one launch per step of a sequential chain, the step's matrix
 // spread over many workgroups (the chains above keep one workgroup per
@@ -828,6 +866,7 @@ template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStre
   template bool wide_sweep_ok<T>(int, int);                                           \
   template hipError_t launch_wide_sweep<T>(int, const SweepArgs<T> &, hipStream_t);   \
   template hipError_t launch_fwd_blocks<T>(const SweepArgs<T> &, hipStream_t);       \
+  template hipError_t launch_seg_lambda<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_fwd_replay<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_cost<T>(const SweepArgs<T> &, hipStream_t);             \
   template hipError_t launch_total<T>(const SweepArgs<T> &, hipStream_t);            \

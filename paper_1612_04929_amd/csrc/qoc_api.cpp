@@ -223,12 +223,16 @@ struct qoc_handle {
   double *psiT64 = nullptr;   // S x d complex interleaved
   double *w64 = nullptr;      // dp
   void *pw = nullptr;         // dp, a_pen / S * w
-  void *X = nullptr, *Qa = nullptr, *Qb = nullptr;  // N x 2 dp^2 each
+  // memory-lean mode: time segments of Ns steps (a multiple of L; Ns = N
+  // and nseg = 1 when off); every per-step stack holds Ns steps
+  int Ns = 0, nseg = 1;
+  double *u_seg = nullptr;    // M x Ns: the controls of one segment
+  void *X = nullptr, *Qa = nullptr, *Qb = nullptr;  // Ns x 2 dp^2 each
   void *Eh = nullptr;  // nb x 2 dp^2: E_b^H for the single-wavefront sweeps
   // padded d 16, L a multiple of SUB16 above it: sub-block products, their
   // ^H (ceil(N / SUB16) x 2 dp^2 each) and partial penalty costates
   void *Es = nullptr, *Ehs = nullptr, *nu = nullptr;
-  void *Dlev = nullptr;       // levels x N x 2 dp^2
+  void *Dlev = nullptr;       // levels x Ns x 2 dp^2
   int levels_alloc = 0;
   void *ckpt = nullptr, *lam_ckpt = nullptr, *mu = nullptr;  // (nb+1) sets
   void *psi_buf = nullptr, *lam_buf = nullptr;                // N+1, N sets
@@ -306,7 +310,7 @@ void release(qoc_handle *h) {
   void **ptrs[] = {&h->Hf, (void **)&h->H64, (void **)&h->u_dev, (void **)&h->out_dev,
                    (void **)&h->grad_dev, &h->psi0, (void **)&h->psiT64, (void **)&h->w64,
                    &h->pw, &h->X, &h->Qa, &h->Qb, &h->Eh, &h->Es, &h->Ehs, &h->nu, &h->Dlev,
-                   (void **)&h->forb64, &h->src, (void **)&h->ext_part,
+                   (void **)&h->forb64, &h->src, (void **)&h->ext_part, (void **)&h->u_seg,
                    (void **)&h->sp_colptr, (void **)&h->sp_rowidx, (void **)&h->sp_vals,
                    (void **)&h->sp_rptr, (void **)&h->sp_rcol, (void **)&h->sp_eptr,
                    (void **)&h->sp_ek, &h->sp_eval,
@@ -422,11 +426,11 @@ qoc_status carve(qoc_handle *h, void **p, size_t bytes) {
 
 template <typename T> qoc_status ensure_levels(qoc_handle *h, int levels) {
   const size_t mat = 2 * (size_t)h->dp * h->dp;
-  if (h->ws_base) return carve(h, &h->Dlev, (size_t)levels * h->N * mat * sizeof(T));
+  if (h->ws_base) return carve(h, &h->Dlev, (size_t)levels * h->Ns * mat * sizeof(T));
   if (levels <= h->levels_alloc) return QOC_OK;
-  dfree(h, &h->Dlev, (size_t)h->levels_alloc * h->N * mat * sizeof(T));
+  dfree(h, &h->Dlev, (size_t)h->levels_alloc * h->Ns * mat * sizeof(T));
   h->levels_alloc = 0;
-  qoc_status s = dalloc(h, &h->Dlev, (size_t)levels * h->N * mat * sizeof(T));
+  qoc_status s = dalloc(h, &h->Dlev, (size_t)levels * h->Ns * mat * sizeof(T));
   if (s) return s;
   h->levels_alloc = levels;
   return QOC_OK;
@@ -436,8 +440,8 @@ template <typename T> qoc_status ensure_adjoint(qoc_handle *h, int p, int Rcap, 
   long total;
   if (big) {
     // batched large-d adjoint: scratch per step, partial sums per tile
-    total = qoc::adjoint_big_scratch_per_step<T>(h->dp, p, Rcap) * (long)h->N;
-    const long parts = (long)h->N * qoc::adjoint_big_slices(h->dp) * std::max(h->M, 1);
+    total = qoc::adjoint_big_scratch_per_step<T>(h->dp, p, Rcap) * (long)h->Ns;
+    const long parts = (long)h->Ns * qoc::adjoint_big_slices(h->dp) * std::max(h->M, 1);
     if (h->ws_base) {
       qoc_status s = carve(h, (void **)&h->adj_part, (size_t)parts * sizeof(double));
       if (s) return s;
@@ -463,9 +467,9 @@ template <typename T> qoc_status ensure_adjoint(qoc_handle *h, int p, int Rcap, 
   return QOC_OK;
 }
 
-// Partial sums of the first-order gradient contraction: N x slices x M.
+// Partial sums of the first-order gradient contraction: Ns x slices x M.
 qoc_status ensure_part(qoc_handle *h) {
-  const long parts = (long)h->N * qoc::adjoint_big_slices(h->dp) * std::max(h->M, 1);
+  const long parts = (long)h->Ns * qoc::adjoint_big_slices(h->dp) * std::max(h->M, 1);
   if (h->ws_base) return carve(h, (void **)&h->adj_part, (size_t)parts * sizeof(double));
   if (parts <= h->adj_part_alloc) return QOC_OK;
   dfree(h, (void **)&h->adj_part, (size_t)h->adj_part_alloc * sizeof(double));
@@ -584,9 +588,11 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
     ALLOC(h->w64, (size_t)dp * sizeof(double));
     ALLOC(h->pw, (size_t)dp * sizeof(T));
   }
-  ALLOC(h->X, (size_t)N * mat * sizeof(T));
-  ALLOC(h->Qa, (size_t)N * mat * sizeof(T));
-  ALLOC(h->Qb, (size_t)N * mat * sizeof(T));
+  const size_t Ns = (size_t)h->Ns;
+  ALLOC(h->X, Ns * mat * sizeof(T));
+  ALLOC(h->Qa, Ns * mat * sizeof(T));
+  ALLOC(h->Qb, Ns * mat * sizeof(T));
+  if (h->nseg > 1) ALLOC(h->u_seg, (size_t)std::max(1, M) * Ns * sizeof(double));
   if (qoc::wave_sweep_ok<T>(dp, S)) ALLOC(h->Eh, (size_t)h->nb * mat * sizeof(T));
   // state buffers carry kRingSlack elements of padding: the small-d sweeps
   // load fixed-size ring slots that may run past the last state set
@@ -811,9 +817,9 @@ template <typename T> bool small_big_adjoint(const qoc_handle *h) {
 // own launches into the slot after the full blocks, so every level's
 // results are contiguous per block and the final E_b are contiguous.
 template <typename T>
-hipError_t block_tree_any(qoc_handle *h, const T *D, T *Qa, T *Qb, long mat, int bf3,
+hipError_t block_tree_any(qoc_handle *h, const T *D, long N, T *Qa, T *Qb, long mat, int bf3,
                           hipStream_t st, const T **E_out) {
-  const long N = h->N, L = h->L, nb = h->nb;
+  const long L = h->L, nb = (N + L - 1) / L;
   const long nfull = N / L, clast = N - nfull * L;  // clast: steps of a short last block
   long c = L, cl = clast;  // elements per full block and in the short block at this level
   const T *in = D;
@@ -862,6 +868,234 @@ hipError_t block_tree_any(qoc_handle *h, const T *D, T *Qa, T *Qb, long mat, int
   (void)nb;
   *E_out = in;
   return hipSuccess;
+}
+
+// Batched path: the FP64 norms of all N steps and the global (p, n) (fixed,
+// or chosen on the host from theta_max read back).
+template <typename T>
+qoc_status choose_pn_large(qoc_handle *h, const double *u_dev, hipStream_t st,
+                           const qoc::SparseU *spu, int *p, int *n) {
+  {
+    PhaseTimer tm(h, QOC_PHASE_NORM, st);
+    // a fixed (p, n) is checked against the tolerance on the device
+    // (status 2 in pn_dev), so the call needs no host round trip
+    qoc::SelectArgs sel{nullptr, nullptr, (unsigned *)(h->bits + 2), h->tol, 60, 30, 0, 0,
+                        h->bits + 4};
+    if (h->fixed_p >= 2)
+      sel = qoc::SelectArgs{h->pn_dev, h->sc_dev, (unsigned *)(h->bits + 2), h->tol, 60, 30,
+                            h->fixed_p, h->fixed_n, h->bits + 4};
+    HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, h->M, h->N, h->dt, h->bits, sel, st, spu));
+  }
+  if (h->fixed_p >= 2) {
+    *p = h->fixed_p;
+    *n = h->fixed_n;
+    return QOC_OK;
+  }
+  if (h->capturing)
+    return fail(QOC_ERR_UNSUPPORTED,
+                "choosing (p, n) per call reads theta_max back to the host, which a stream "
+                "that captures a HIP graph cannot do: fix the pair with qoc_set_taylor "
+                "before capturing");
+  unsigned long long tb = 0;
+  HIP_TRY(hipMemcpyAsync(&tb, h->bits, sizeof(tb), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double theta;
+  std::memcpy(&theta, &tb, sizeof(theta));
+  h->last_theta = theta;
+  if (!std::isfinite(theta)) return fail(QOC_ERR_NONFINITE, "non-finite step norm");
+  if (!taylor_select(theta, h->tol, p, n))
+    return fail(QOC_ERR_UNSUPPORTED, "no (p, n) meets the tolerance for theta_max = " +
+                                         std::to_string(theta));
+  return QOC_OK;
+}
+
+// Paterson-Stockmeyer temporaries beyond the levels 1..n: the two ping-pong
+// panels and, for s = 4, the fourth power.
+int ps_extra_levels(int p, int n) {
+  const PsPlan ps = ps_plan(p);
+  const bool use_ps = ps.cost < p - 1;
+  const int need = use_ps ? 2 + (ps.s == 4 ? 1 : 0) : 0;
+  return std::max(0, need - n);
+}
+
+// Batched path, once (p, n) is known: the work space of this call and the
+// product classes that run as bf16x3 split products.
+template <typename T>
+qoc_status prepare_large(qoc_handle *h, int p, int n, bool want_grad, int Rcap) {
+  qoc_status s = ensure_levels<T>(h, n + 1 + ps_extra_levels(p, n));
+  if (s) return s;
+  if (want_grad && (s = ensure_adjoint<T>(h, p, Rcap, qoc::adjoint_big_ok<T>(h->dp))) != QOC_OK)
+    return s;
+  h->last_p = p;
+  h->last_n = n;
+  int cls = 0;
+  h->bf3_fallback = 0;
+  if (h->bf3) {
+    if (h->bf3_req >= 0) {
+      cls = h->bf3_req;
+    } else {
+      const double th = h->fixed_p >= 2 ? theta_admitted(p, n, h->tol) : h->last_theta;
+      cls = bf3_auto_classes(th, n, h->N, h->L);
+      h->bf3_fallback = cls != QOC_BF3_ALL;
+    }
+  }
+  h->bf3_used = cls;
+  return QOC_OK;
+}
+
+// Batched path: the step exponentials D_j = U_j - I of Nloc consecutive
+// steps with controls u_loc (M x Nloc) -- assembly, Taylor (Horner or
+// Paterson-Stockmeyer) in D-form, n squarings -- and their block products
+// E_b (blocks of L).  Stacks of Nloc matrices, levels at stride Nloc.
+template <typename T>
+hipError_t exps_large(qoc_handle *h, const double *u_loc, int Nloc, int p, int n, hipStream_t st,
+                      const T **D_out, const T **E_out) {
+  const int dp = h->dp, M = h->M;
+  const long mat = 2L * dp * dp, lev = (long)Nloc * mat;
+  T *X = (T *)h->X, *Qa = (T *)h->Qa, *Qb = (T *)h->Qb, *Dl = (T *)h->Dlev;
+  const int cls = h->bf3_used;
+  const int bT = (cls & QOC_BF3_TAYLOR) ? 1 : 0, bS = (cls & QOC_BF3_SQUARING) ? 1 : 0,
+            bB = (cls & QOC_BF3_BLOCKPROD) ? 1 : 0;
+  const PsPlan ps = ps_plan(p);
+  const bool use_ps = ps.cost < p - 1;
+  const int ps_extra = ps_extra_levels(p, n);
+  hipError_t e;
+  const double sc = std::ldexp(h->dt, -n);
+  {
+    PhaseTimer tm(h, QOC_PHASE_ASSEMBLE, st);
+    if ((e = qoc::launch_assemble<T>((const T *)h->Hf, u_loc, dp, M, Nloc, (T)sc, (T)(1.0 / p), X,
+                                     use_ps ? nullptr : Qa, st)) != hipSuccess)
+      return e;
+  }
+  if (use_ps) {
+    if ((e = taylor_ps<T>(h, ps, p, n + 1 + ps_extra, X, Qa, Qb, Dl, lev, mat, Nloc, dp, bT, st)) !=
+        hipSuccess)
+      return e;
+  } else {
+    T *cur = Qa, *nxt = Qb;
+    for (int k = p - 1; k >= 2; --k) {
+      qoc::StageArgs<T> a{X, mat, cur, mat, nxt, mat, Nloc, dp, (T)(1.0 / k), (T)0, (T)0, (T)1,
+                          bT};
+      PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
+      if ((e = qoc::launch_stage<T>(0, a, st)) != hipSuccess) return e;
+      std::swap(cur, nxt);
+    }
+    qoc::StageArgs<T> a{X, mat, cur, mat, Dl, mat, Nloc, dp, (T)1, (T)0, (T)0, (T)0, bT};
+    PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
+    if ((e = qoc::launch_stage<T>(0, a, st)) != hipSuccess) return e;
+  }
+  for (int i = 0; i < n; ++i) {
+    qoc::StageArgs<T> a{Dl + i * lev, mat, Dl + i * lev, mat, Dl + (i + 1) * lev, mat, Nloc, dp,
+                        (T)1, (T)0, (T)2, (T)0, bS};
+    PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
+    if ((e = qoc::launch_stage<T>(0, a, st)) != hipSuccess) return e;
+  }
+  const T *D = Dl + (long)n * lev;
+  *D_out = D;
+  // ---- block products E_b (pairwise tree, D-form: C = A + B + A B)
+  if (h->L & (h->L - 1)) return block_tree_any<T>(h, D, Nloc, Qa, Qb, mat, bB, st, E_out);
+  long cnt = Nloc;
+  const T *in = D;
+  T *outb = Qa;
+  for (int span = 2; span <= h->L; span <<= 1) {
+    const long pairs = cnt / 2;
+    qoc::StageArgs<T> a{in + mat, 2 * mat, in, 2 * mat, outb, mat, (int)pairs, dp,
+                        (T)1, (T)1, (T)1, (T)0, bB};
+    PhaseTimer tm(h, QOC_PHASE_BLOCKPROD, st);
+    if ((e = qoc::launch_stage<T>(0, a, st)) != hipSuccess) return e;
+    tm.done();
+    if (cnt & 1)
+      if ((e = qoc::launch_copy<T>(outb + pairs * mat, in + (cnt - 1) * mat, mat, st)) !=
+          hipSuccess)
+        return e;
+    cnt = (cnt + 1) / 2;
+    in = outb;
+    outb = (outb == Qa) ? Qb : Qa;
+  }
+  *E_out = in;
+  return hipSuccess;
+}
+
+// Sweep and cost arguments over the whole horizon.
+template <typename T>
+qoc::SweepArgs<T> sweep_args(const qoc_handle *h, const T *D, const T *E, const double *u_dev,
+                             double *out_dev) {
+  qoc::SweepArgs<T> sw{};
+  sw.N = h->N; sw.L = h->L; sw.nb = h->nb; sw.dp = h->dp; sw.d = h->d; sw.S = h->S; sw.M = h->M;
+  sw.D = D; sw.E = E; sw.psi0 = (const T *)h->psi0; sw.ckpt = (T *)h->ckpt;
+  sw.psi_buf = (T *)h->psi_buf; sw.lam_ckpt = (T *)h->lam_ckpt; sw.mu = (T *)h->mu;
+  sw.lam_buf = (T *)h->lam_buf; sw.w64 = h->w64; sw.pw = (const T *)h->pw;
+  sw.drift_bits = h->bits + 1; sw.psiT64 = h->psiT64; sw.u = u_dev;
+  sw.alpha_fid = h->a_fid; sw.alpha_pen = h->a_pen; sw.alpha_amp = h->a_amp;
+  sw.alpha_var = h->a_var; sw.fid_mode = h->fid_mode; sw.out = out_dev; sw.zinfo = h->zinfo;
+  sw.part = h->part; sw.npart = h->npart;
+  if (h->has_ext) {
+    sw.src = (const T *)h->src;
+    sw.ext_part = h->ext_part;
+    sw.next = h->next;
+    sw.alpha_time = h->a_time;
+  }
+  return sw;
+}
+
+// The cost from the states of the whole horizon: fidelity and lambda_N
+// beside the penalties in one launch, then (with source terms) the
+// forbidden-state occupancies, time-optimal fidelities and costate sources,
+// then the total.
+template <typename T>
+hipError_t launch_cost_all(qoc_handle *h, const qoc::SweepArgs<T> &sw, bool total, hipStream_t st) {
+  PhaseTimer tm(h, QOC_PHASE_COST, st);
+  hipError_t e = qoc::launch_cost<T>(sw, st);
+  if (e != hipSuccess) return e;
+  if (h->has_ext) {
+    const long set = 2L * h->S * h->dp;
+    const qoc::ExtArgs<T> ea{h->forb64, h->nf, h->a_time, (T *)h->src,
+                             (T *)h->lam_ckpt + (long)h->nb * set, h->ext_part, h->next};
+    if ((e = qoc::launch_ext<T>(sw, ea, st)) != hipSuccess) return e;
+  }
+  return total ? qoc::launch_total<T>(sw, st) : hipSuccess;
+}
+
+// The sweep kernels of a call: one wavefront (S d_pad <= 64), one workgroup
+// with a prefetch ring (d_pad <= 64), chain workgroups, per-step launches of
+// many workgroups, or the generic per-block kernels, which alone carry the
+// per-step source terms (forbidden states, time-optimal term).
+struct SweepPick {
+  bool ext, wave, small, wide_ok;
+};
+
+template <typename T>
+hipError_t launch_sweep(const qoc_handle *h, const SweepPick &k, int which,
+                        const qoc::SweepArgs<T> &sw, hipStream_t st) {
+  const int dp = h->dp, S = h->S;
+  const int mode = h->sweep_mode[which];
+  if (k.ext) {
+    switch (which) {
+      case 0: return qoc::launch_fwd_blocks<T>(sw, st);
+      case 1: return qoc::launch_fwd_replay<T>(sw, st);
+      case 2: return qoc::launch_bwd_blocks<T>(sw, st);
+      default: return qoc::launch_bwd_pairs<T>(sw, st);
+    }
+  }
+  if (k.wave && !(mode == 3 && qoc::small_sweep_ok<T>(dp, S)))
+    return qoc::launch_wave_sweep<T>(which, sw, st);
+  // chain workgroups: by default for FP32 padded d 64 .. 128 (measured at
+  // padded d 64, S = 2, N ~ 2900: 1.8 ms per call against 3.7 ms with the
+  // four-wavefront LDS sweeps)
+  if (qoc::chain_sweep_ok<T>(dp, S) && (mode == 4 || (mode == 0 && dp >= 64)))
+    return qoc::launch_chain_sweep<T>(which, sw, st);
+  if (k.wave || k.small) return qoc::launch_small_sweep<T>(which, sw, st);
+  // per-step launches: the block sweeps (F2, B2) from padded d 80, the
+  // in-block passes (F3, B3) from 256, unless set per handle
+  const bool wide =
+      k.wide_ok && (mode == 2 || (mode == 0 && (which == 0 || which == 2 || dp >= 256)));
+  if (wide) return qoc::launch_wide_sweep<T>(which, sw, st);
+  switch (which) {
+    case 0: return qoc::launch_fwd_blocks<T>(sw, st);
+    case 1: return qoc::launch_fwd_replay<T>(sw, st);
+    case 2: return qoc::launch_bwd_blocks<T>(sw, st);
+    default: return qoc::launch_bwd_pairs<T>(sw, st);
+  }
 }
 
 template <typename T>
@@ -926,120 +1160,12 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     E = Qa;
   } else {
     // ---- (p, n): fixed, or from theta_max (FP64 norms on the device)
-    {
-      PhaseTimer tm(h, QOC_PHASE_NORM, st);
-      // a fixed (p, n) is checked against the tolerance on the device
-      // (status 2 in pn_dev), so the call needs no host round trip
-      qoc::SelectArgs sel{nullptr, nullptr, (unsigned *)(h->bits + 2), h->tol, 60, 30, 0, 0,
-                          h->bits + 4};
-      if (h->fixed_p >= 2)
-        sel = qoc::SelectArgs{h->pn_dev, h->sc_dev, (unsigned *)(h->bits + 2), h->tol, 60, 30,
-                              h->fixed_p, h->fixed_n, h->bits + 4};
-      HIP_TRY(qoc::launch_norm(h->H64, u_dev, h->d, M, N, h->dt, h->bits, sel, st,
-                               sp_on ? &spu : nullptr));
-    }
-    if (h->fixed_p >= 2) {
-      p = h->fixed_p;
-      n = h->fixed_n;
-    } else {
-      if (h->capturing)
-        return fail(QOC_ERR_UNSUPPORTED,
-                    "choosing (p, n) per call reads theta_max back to the host, which a stream "
-                    "that captures a HIP graph cannot do: fix the pair with qoc_set_taylor "
-                    "before capturing");
-      unsigned long long tb = 0;
-      HIP_TRY(hipMemcpyAsync(&tb, h->bits, sizeof(tb), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      double theta;
-      std::memcpy(&theta, &tb, sizeof(theta));
-      h->last_theta = theta;
-      if (!std::isfinite(theta)) return fail(QOC_ERR_NONFINITE, "non-finite step norm");
-      if (!taylor_select(theta, h->tol, &p, &n))
-        return fail(QOC_ERR_UNSUPPORTED, "no (p, n) meets the tolerance for theta_max = " +
-                                             std::to_string(theta));
-    }
+    qoc_status s = choose_pn_large<T>(h, u_dev, st, sp_on ? &spu : nullptr, &p, &n);
+    if (s) return s;
     const int Rraw = (long)S << std::min(n, 30) > dp ? dp : (S << n);
     Rcap_used = std::min((Rraw + 15) & ~15, dp);
-    const PsPlan ps = ps_plan(p);
-    const bool use_ps = ps.cost < p - 1;
-    // PS temporaries beyond the levels 1..n: the two ping-pong panels and,
-    // for s = 4, the fourth power
-    const int ps_need = use_ps ? 2 + (ps.s == 4 ? 1 : 0) : 0;
-    const int ps_extra = std::max(0, ps_need - n);
-    qoc_status s = ensure_levels<T>(h, n + 1 + ps_extra);
-    if (s) return s;
-    if (want_grad &&
-        (s = ensure_adjoint<T>(h, p, Rcap_used, qoc::adjoint_big_ok<T>(dp))) != QOC_OK)
-      return s;
-    h->last_p = p;
-    h->last_n = n;
-    // product classes that run as bf16x3 split products this call
-    int cls = 0;
-    h->bf3_fallback = 0;
-    if (h->bf3) {
-      if (h->bf3_req >= 0) {
-        cls = h->bf3_req;
-      } else {
-        const double th = h->fixed_p >= 2 ? theta_admitted(p, n, h->tol) : h->last_theta;
-        cls = bf3_auto_classes(th, n, N, h->L);
-        h->bf3_fallback = cls != QOC_BF3_ALL;
-      }
-    }
-    h->bf3_used = cls;
-    const int bT = (cls & QOC_BF3_TAYLOR) ? 1 : 0, bS = (cls & QOC_BF3_SQUARING) ? 1 : 0,
-              bB = (cls & QOC_BF3_BLOCKPROD) ? 1 : 0;
-    T *Dl = (T *)h->Dlev;
-    // ---- step exponentials: Horner in D-form, then squarings
-    const double sc = std::ldexp(h->dt, -n);
-    {
-      PhaseTimer tm(h, QOC_PHASE_ASSEMBLE, st);
-      HIP_TRY(qoc::launch_assemble<T>((const T *)h->Hf, u_dev, dp, M, N, (T)sc, (T)(1.0 / p), X,
-                                      use_ps ? nullptr : Qa, st));
-    }
-    if (use_ps) {
-      HIP_TRY(taylor_ps<T>(h, ps, p, n + 1 + ps_extra, X, Qa, Qb, Dl, lev, mat, N, dp, bT, st));
-    } else {
-      T *cur = Qa, *nxt = Qb;
-      for (int k = p - 1; k >= 2; --k) {
-        qoc::StageArgs<T> a{X, mat, cur, mat, nxt, mat, N, dp, (T)(1.0 / k), (T)0, (T)0, (T)1,
-                            bT};
-        PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
-        HIP_TRY(qoc::launch_stage<T>(0, a, st));
-        std::swap(cur, nxt);
-      }
-      qoc::StageArgs<T> a{X, mat, cur, mat, Dl, mat, N, dp, (T)1, (T)0, (T)0, (T)0, bT};
-      PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
-      HIP_TRY(qoc::launch_stage<T>(0, a, st));
-    }
-    for (int i = 0; i < n; ++i) {
-      qoc::StageArgs<T> a{Dl + i * lev, mat, Dl + i * lev, mat, Dl + (i + 1) * lev, mat, N, dp,
-                          (T)1, (T)0, (T)2, (T)0, bS};
-      PhaseTimer tm(h, QOC_PHASE_TAYLOR, st);
-      HIP_TRY(qoc::launch_stage<T>(0, a, st));
-    }
-    D = Dl + (long)n * lev;
-    // ---- block products E_b (pairwise tree, D-form: C = A + B + A B)
-    if (h->L & (h->L - 1)) {
-      HIP_TRY(block_tree_any<T>(h, D, Qa, Qb, mat, bB, st, &E));
-    } else {
-    long cnt = N;
-    const T *in = D;
-    T *outb = Qa;
-    for (int span = 2; span <= h->L; span <<= 1) {
-      const long pairs = cnt / 2;
-      qoc::StageArgs<T> a{in + mat, 2 * mat, in, 2 * mat, outb, mat, (int)pairs, dp,
-                          (T)1, (T)1, (T)1, (T)0, bB};
-      PhaseTimer tm(h, QOC_PHASE_BLOCKPROD, st);
-      HIP_TRY(qoc::launch_stage<T>(0, a, st));
-      tm.done();
-      if (cnt & 1)
-        HIP_TRY(qoc::launch_copy<T>(outb + pairs * mat, in + (cnt - 1) * mat, mat, st));
-      cnt = (cnt + 1) / 2;
-      in = outb;
-      outb = (outb == Qa) ? Qb : Qa;
-    }
-    E = in;
-    }
+    if ((s = prepare_large<T>(h, p, n, want_grad, Rcap_used)) != QOC_OK) return s;
+    HIP_TRY(exps_large<T>(h, u_dev, N, p, n, st, &D, &E));
   }
   // FP64 unitarity drift of the final propagators (a diagnostic; at padded
   // d 16 after the block products, which may recompute D with the chosen pair)
@@ -1048,23 +1174,11 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     h->unit_epoch = ++h->epoch;
     HIP_TRY(qoc::launch_unitarity<T>(D, dp, h->d, N, h->unit_stride, h->unit_epoch, h->bits + 3, st));
   }
-  qoc::SweepArgs<T> sw{};
-  sw.N = N; sw.L = h->L; sw.nb = h->nb; sw.dp = dp; sw.d = h->d; sw.S = S; sw.M = M;
-  sw.D = D; sw.E = E; sw.Dh = Dh_small; sw.Eh = Dh_small ? (const T *)h->Eh : nullptr; sw.psi0 = (const T *)h->psi0; sw.ckpt = (T *)h->ckpt;
-  sw.psi_buf = (T *)h->psi_buf; sw.lam_ckpt = (T *)h->lam_ckpt; sw.mu = (T *)h->mu;
+  qoc::SweepArgs<T> sw = sweep_args<T>(h, D, E, u_dev, out_dev);
+  sw.Dh = Dh_small;
+  sw.Eh = Dh_small ? (const T *)h->Eh : nullptr;
   if (h->Es && Dh_small) {  // sub-block products written by the block-product kernel
     sw.Es = (const T *)h->Es; sw.Ehs = (const T *)h->Ehs; sw.nu = (T *)h->nu;
-  }
-  sw.lam_buf = (T *)h->lam_buf; sw.w64 = h->w64; sw.pw = (const T *)h->pw;
-  sw.drift_bits = h->bits + 1; sw.psiT64 = h->psiT64; sw.u = u_dev;
-  sw.alpha_fid = h->a_fid; sw.alpha_pen = h->a_pen; sw.alpha_amp = h->a_amp;
-  sw.alpha_var = h->a_var; sw.fid_mode = h->fid_mode; sw.out = out_dev; sw.zinfo = h->zinfo;
-  sw.part = h->part; sw.npart = h->npart;
-  if (h->has_ext) {
-    sw.src = (const T *)h->src;
-    sw.ext_part = h->ext_part;
-    sw.next = h->next;
-    sw.alpha_time = h->a_time;
   }
   // sweep kernels: one wavefront (S d_pad <= 64), one workgroup with a
   // prefetch ring (d_pad <= 64), or the generic streaming kernels; the
@@ -1082,35 +1196,8 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   sw.fuse_cost = (total_in_adjoint && wave && h->sweep_mode[2] != 3) ? 1 : 0;
   const bool small = !ext && !wave && qoc::small_sweep_ok<T>(dp, S);
   const bool wide_ok = !ext && !wave && !small && qoc::wide_sweep_ok<T>(dp, S);
-  auto sweep = [&](int which) -> hipError_t {
-    const int mode = h->sweep_mode[which];
-    if (ext) {
-      switch (which) {
-        case 0: return qoc::launch_fwd_blocks<T>(sw, st);
-        case 1: return qoc::launch_fwd_replay<T>(sw, st);
-        case 2: return qoc::launch_bwd_blocks<T>(sw, st);
-        default: return qoc::launch_bwd_pairs<T>(sw, st);
-      }
-    }
-    if (wave && !(mode == 3 && qoc::small_sweep_ok<T>(dp, S)))
-      return qoc::launch_wave_sweep<T>(which, sw, st);
-    // chain workgroups: by default for FP32 padded d 64 .. 128 (measured at
-    // padded d 64, S = 2, N ~ 2900: 1.8 ms per call against 3.7 ms with the
-    // four-wavefront LDS sweeps)
-    if (qoc::chain_sweep_ok<T>(dp, S) && (mode == 4 || (mode == 0 && dp >= 64)))
-      return qoc::launch_chain_sweep<T>(which, sw, st);
-    if (wave || small) return qoc::launch_small_sweep<T>(which, sw, st);
-    // per-step launches: the block sweeps (F2, B2) from padded d 80, the
-    // in-block passes (F3, B3) from 256, unless set per handle
-    const bool wide = wide_ok && (mode == 2 || (mode == 0 && (which == 0 || which == 2 || dp >= 256)));
-    if (wide) return qoc::launch_wide_sweep<T>(which, sw, st);
-    switch (which) {
-      case 0: return qoc::launch_fwd_blocks<T>(sw, st);
-      case 1: return qoc::launch_fwd_replay<T>(sw, st);
-      case 2: return qoc::launch_bwd_blocks<T>(sw, st);
-      default: return qoc::launch_bwd_pairs<T>(sw, st);
-    }
-  };
+  const SweepPick pick{ext, wave, small, wide_ok};
+  auto sweep = [&](int which) { return launch_sweep<T>(h, pick, which, sw, st); };
   {
     PhaseTimer tm(h, QOC_PHASE_FWD_BLOCKS, st);
     HIP_TRY(sweep(0));
@@ -1125,19 +1212,7 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   // penalties beside fidelity / lambda_N in one launch, then the total cost
   // and drift (a side stream for the penalties measured slower here, its
   // events costing more than the overlap gained)
-  if (!sw.fuse_cost) {
-    PhaseTimer tm(h, QOC_PHASE_COST, st);
-    HIP_TRY(qoc::launch_cost<T>(sw, st));
-    if (ext) {
-      // forbidden-state occupancies into c_j, the time-optimal fidelities,
-      // the costate sources src_j and src_N into lambda_N
-      const long set = 2L * S * dp;
-      const qoc::ExtArgs<T> ea{h->forb64, h->nf, h->a_time, (T *)h->src,
-                               (T *)h->lam_ckpt + (long)h->nb * set, h->ext_part, h->next};
-      HIP_TRY(qoc::launch_ext<T>(sw, ea, st));
-    }
-    if (!total_in_adjoint) HIP_TRY(qoc::launch_total<T>(sw, st));
-  }
+  if (!sw.fuse_cost) HIP_TRY(launch_cost_all<T>(h, sw, !total_in_adjoint, st));
   if (!want_grad) return QOC_OK;
   if (ext) {
     // the block-local penalty costates mu_b with the sources
@@ -1203,8 +1278,135 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
   return QOC_OK;
 }
 
+// Memory-lean mode (App. A: the propagators formed again in the backward
+// pass instead of stored): the horizon in time segments of Ns steps, whole
+// checkpoint blocks each, and every per-step stack one segment long.  The
+// forward pass forms each segment's exponentials and sweeps its states; the
+// cost runs over the whole horizon; the backward pass visits the segments
+// last to first, forms each segment's exponentials again (the same kernels
+// on the same controls: the same values), sweeps its costates from the
+// costate at the following segment's first step, writes the costate at its
+// own first step, and contracts its derivative.  The states, checkpoints and
+// costates stay whole (O(N S d), against the O(N d^2) stacks).
+template <typename T>
+qoc_status run_segmented(qoc_handle *h, const double *u_dev, double *out_dev, double *grad_dev,
+                         hipStream_t st, bool want_grad) {
+  const int dp = h->dp, N = h->N, M = h->M, S = h->S, L = h->L, Ns = h->Ns;
+  const long set = 2L * S * dp;
+  const bool sp_on = h->sp_built && (h->sp_mode == 1 || (h->sp_mode < 0 && h->sp_auto));
+  h->sp_used = sp_on;
+  const qoc::SparseU spu{h->sp_colptr, h->sp_rowidx, h->sp_vals};
+  int p = 0, n = 0;
+  qoc_status s = choose_pn_large<T>(h, u_dev, st, sp_on ? &spu : nullptr, &p, &n);
+  if (s) return s;
+  const int Rraw = (long)S << std::min(n, 30) > dp ? dp : (S << n);
+  const int Rcap = std::min((Rraw + 15) & ~15, dp);
+  if ((s = prepare_large<T>(h, p, n, want_grad, Rcap)) != QOC_OK) return s;
+  h->unit_epoch = h->unit_stride > 0 ? ++h->epoch : 0;
+  const bool ext = h->has_ext;
+  const bool small = !ext && qoc::small_sweep_ok<T>(dp, S);
+  const SweepPick pick{ext, false, small, !ext && !small && qoc::wide_sweep_ok<T>(dp, S)};
+  const qoc::SweepArgs<T> all = sweep_args<T>(h, nullptr, nullptr, u_dev, out_dev);
+  auto seg_len = [&](int g) { return (int)std::min<long>(Ns, N - (long)g * Ns); };
+  // the segment's exponentials D_j and block products E_b, from its controls
+  auto exps = [&](int g, const T **D, const T **E) -> hipError_t {
+    const int Nloc = seg_len(g);
+    hipError_t e = qoc::launch_copy_strided<double>(h->u_seg, Nloc, u_dev + (long)g * Ns, N,
+                                                     Nloc, M, st);
+    if (e != hipSuccess) return e;
+    return exps_large<T>(h, h->u_seg, Nloc, p, n, st, D, E);
+  };
+  // sweep arguments of segment g: its steps and blocks, the global buffers
+  // at its offsets (its first state: psi_0, or the previous segment's last)
+  auto segment = [&](int g, const T *D, const T *E) {
+    qoc::SweepArgs<T> sw = all;
+    const long s0 = (long)g * Ns, b0 = s0 / L;
+    sw.N = seg_len(g);
+    sw.nb = (sw.N + L - 1) / L;
+    sw.D = D;
+    sw.E = E;
+    sw.psi0 = g == 0 ? all.psi0 : all.psi_buf + s0 * set;
+    sw.ckpt = all.ckpt + b0 * set;
+    sw.psi_buf = all.psi_buf + s0 * set;
+    sw.lam_ckpt = all.lam_ckpt + b0 * set;
+    sw.mu = all.mu ? all.mu + b0 * set : nullptr;
+    sw.lam_buf = all.lam_buf + s0 * set;
+    sw.src = all.src ? all.src + s0 * set : nullptr;
+    return sw;
+  };
+  const T *D = nullptr, *E = nullptr;
+  for (int g = 0; g < h->nseg; ++g) {
+    HIP_TRY(exps(g, &D, &E));
+    if (h->unit_stride > 0)
+      HIP_TRY(qoc::launch_unitarity<T>(D, dp, h->d, seg_len(g), h->unit_stride, h->unit_epoch,
+                                       h->bits + 3, st));
+    qoc::SweepArgs<T> sw = segment(g, D, E);
+    {
+      PhaseTimer tm(h, QOC_PHASE_FWD_BLOCKS, st);
+      HIP_TRY(launch_sweep<T>(h, pick, 0, sw, st));
+    }
+    PhaseTimer tm(h, QOC_PHASE_FWD_REPLAY, st);
+    sw.replay_mode = ext ? 1 : 0;  // with source terms the block costates wait for them
+    HIP_TRY(launch_sweep<T>(h, pick, 1, sw, st));
+  }
+  HIP_TRY(launch_cost_all<T>(h, all, true, st));
+  if (!want_grad) return QOC_OK;
+  const bool first_order = h->grad_mode == QOC_GRAD_FIRST_ORDER;
+  if (M > 0 && first_order && (s = ensure_part(h)) != QOC_OK) return s;
+  for (int g = h->nseg - 1; g >= 0; --g) {
+    HIP_TRY(exps(g, &D, &E));
+    qoc::SweepArgs<T> sw = segment(g, D, E);
+    if (ext) {
+      PhaseTimer tm(h, QOC_PHASE_FWD_REPLAY, st);
+      sw.replay_mode = 2;
+      HIP_TRY(qoc::launch_fwd_replay<T>(sw, st));
+      sw.replay_mode = 0;
+    }
+    {
+      PhaseTimer tm(h, QOC_PHASE_BWD_BLOCKS, st);
+      HIP_TRY(launch_sweep<T>(h, pick, 2, sw, st));
+    }
+    {
+      PhaseTimer tm(h, QOC_PHASE_BWD_PAIRS, st);
+      HIP_TRY(launch_sweep<T>(h, pick, 3, sw, st));
+      if (g > 0) HIP_TRY(qoc::launch_seg_lambda<T>(sw, st));
+    }
+    if (M == 0) continue;
+    PhaseTimer tm(h, QOC_PHASE_ADJOINT, st);
+    qoc::AdjointArgs<T> ad{};
+    ad.N = sw.N; ad.dp = dp; ad.M = M; ad.S = S; ad.p = p; ad.n = n; ad.Rcap = Rcap;
+    ad.nblocks = h->adj_blocks;
+    ad.X = (const T *)h->X; ad.Dlev = (const T *)h->Dlev;
+    ad.lam_buf = sw.lam_buf; ad.psi_buf = sw.psi_buf;
+    ad.Hf = (const T *)h->Hf; ad.u = u_dev; ad.s_scale = std::ldexp(h->dt, -n);
+    ad.alpha_amp = h->a_amp; ad.alpha_var = h->a_var; ad.scratch = (T *)h->adj;
+    ad.scratch_elems = qoc::adjoint_scratch_elems<T>(dp, p, Rcap);
+    ad.grad = grad_dev; ad.part = h->adj_part;
+    ad.xbar = (T *)h->Qa;  // the Taylor work space is free once the sweeps are done
+    ad.bf3 = (h->bf3_used & QOC_BF3_ADJOINT) ? 1 : 0;
+    ad.total = qoc::total_args(all);
+    ad.j0 = (long)g * Ns;
+    ad.ldN = N;
+    if (first_order) {
+      HIP_TRY(qoc::launch_grad_first<T>(ad, h->dt, st));
+      continue;
+    }
+    if (sp_on) {
+      ad.rptr = h->sp_rptr; ad.rcol = h->sp_rcol; ad.eptr = h->sp_eptr; ad.ek = h->sp_ek;
+      ad.eval = (const T *)h->sp_eval; ad.nev = h->nev; ad.d = h->d;
+    }
+    HIP_TRY(qoc::launch_adjoint_big<T>(ad, st));
+  }
+  return QOC_OK;
+}
+
 qoc_status run_any(qoc_handle *h, const double *u_dev, double *out_dev, double *grad_dev,
                    hipStream_t st, bool want_grad) {
+  if (h->nseg > 1) {
+    if (h->prec == QOC_FP64)
+      return run_segmented<double>(h, u_dev, out_dev, grad_dev, st, want_grad);
+    return run_segmented<float>(h, u_dev, out_dev, grad_dev, st, want_grad);
+  }
   if (h->prec == QOC_FP64) return run<double>(h, u_dev, out_dev, grad_dev, st, want_grad);
   return run<float>(h, u_dev, out_dev, grad_dev, st, want_grad);
 }
@@ -1361,6 +1563,7 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
   if (!(D.pad_multiple == 0 || D.pad_multiple == 16 || D.pad_multiple == 32 ||
         D.pad_multiple == 64))
     return fail(QOC_ERR_ARG, "pad_multiple must be 0, 16, 32 or 64");
+  if (D.segment_steps < 0) return fail(QOC_ERR_ARG, "segment_steps must be >= 0");
   if (!(D.taylor_tol >= 0.0) || !std::isfinite(D.taylor_tol))
     return fail(QOC_ERR_ARG, "taylor_tol must be finite and >= 0");
   if (!(D.taylor_p == 0 || (D.taylor_p >= 2 && D.taylor_p <= 64 && D.taylor_n >= 0 &&
@@ -1445,6 +1648,21 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
   }
   h->nb = (int)((D.N + h->L - 1) / h->L);
   h->adj_blocks = std::min(D.N, 1024);
+  // memory-lean mode: segments of whole checkpoint blocks
+  h->Ns = D.N;
+  if (D.segment_steps > 0) {
+    const long len = ((long)D.segment_steps + h->L - 1) / h->L * h->L;
+    if (len < D.N) {
+      h->Ns = (int)len;
+      h->nseg = (int)((D.N + len - 1) / len);
+    }
+  }
+  if (h->nseg > 1 && (on_small_path(h) || h->dp < 64)) {
+    delete h;
+    return fail(QOC_ERR_UNSUPPORTED,
+                "time segments apply to the batched path with its batched derivative (padded "
+                "d >= 64); smaller problems keep their stacks whole");
+  }
   DeviceGuard g(h->device);
   if (!g.ok) {
     delete h;
@@ -1688,6 +1906,7 @@ qoc_status qoc_get_info(const qoc_handle *hc, qoc_info *info) {
   info->bf16x3_classes = h->bf3_used;
   info->unitarity_drift = h->last_unitarity;
   info->structured = h->sp_used ? 1 : 0;
+  info->segments = h->nseg;
   return QOC_OK;
 }
 

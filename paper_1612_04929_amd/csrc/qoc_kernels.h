@@ -206,6 +206,9 @@ template <typename T> hipError_t launch_fwd_blocks(const SweepArgs<T> &a, hipStr
 template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_bwd_blocks(const SweepArgs<T> &a, hipStream_t st);
 template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStream_t st);
+// Time segments: the costate at a segment's first step (>= 1) into the
+// segment's first checkpoint (arguments offset to the segment).
+template <typename T> hipError_t launch_seg_lambda(const SweepArgs<T> &a, hipStream_t st);
 // Small padded d (<= 64): all columns per workgroup, prefetched step matrices.
 // which: 0 = F2, 1 = F3, 2 = B2, 3 = B3.
 template <typename T> bool small_sweep_ok(int dp, int S);
@@ -261,6 +264,10 @@ template <typename T> struct AdjointArgs {
   const T *eval;
   long nev;
   int d;
+  // batched variant, one time segment of a longer horizon: the N steps are
+  // global steps j0 .. j0 + N - 1 of ldN (u and grad are M x ldN; ldN 0: N)
+  long j0;
+  int ldN;
 };
 template <typename T> long adjoint_scratch_elems(int dp, int p, int Rcap);
 // Time steps processed concurrently per workgroup (one per wave for small d).

@@ -49,7 +49,8 @@ class Desc(C.Structure):
                 ("precision", C.c_int), ("checkpoint_every", C.c_int),
                 ("taylor_tol", C.c_double), ("taylor_p", C.c_int), ("taylor_n", C.c_int),
                 ("drift_warn", C.c_double), ("device", C.c_int), ("n_forbidden", C.c_int),
-                ("forbidden", _dp), ("alpha_time", C.c_double), ("pad_multiple", C.c_int)]
+                ("forbidden", _dp), ("alpha_time", C.c_double), ("pad_multiple", C.c_int),
+                ("segment_steps", C.c_int)]
 
 
 class Info(C.Structure):
@@ -57,7 +58,7 @@ class Info(C.Structure):
                 ("norm_drift", C.c_double), ("block_len", C.c_int), ("n_blocks", C.c_int),
                 ("d_pad", C.c_int), ("flags", C.c_int), ("device_bytes", C.c_size_t),
                 ("bf16x3_classes", C.c_int), ("unitarity_drift", C.c_double),
-                ("structured", C.c_int)]
+                ("structured", C.c_int), ("segments", C.c_int)]
 
 
 class QocError(RuntimeError):
@@ -154,7 +155,8 @@ class Problem:
     """
 
     def __init__(self, prob, precision="fp32", checkpoint_every=0, taylor_tol=0.0,
-                 taylor_pn=None, drift_warn=0.0, device=0, structure=-1, pad_multiple=0):
+                 taylor_pn=None, drift_warn=0.0, device=0, structure=-1, pad_multiple=0,
+                 segment_steps=0):
         lib = load()
         self.d, self.M, self.N, self.S = int(prob.d), int(prob.M), int(prob.N), int(prob.S)
         keep = []
@@ -183,7 +185,8 @@ class Problem:
                     float(prob.alpha_amp), float(prob.alpha_var), float(prob.alpha_pen),
                     int(fid), PRECISIONS.get(precision, precision), int(checkpoint_every),
                     float(taylor_tol), tp, tn, float(drift_warn), int(device), nf, pf,
-                    float(getattr(prob, "alpha_time", 0.0)), int(pad_multiple))
+                    float(getattr(prob, "alpha_time", 0.0)), int(pad_multiple),
+                    int(segment_steps))
         self._h = C.c_void_p()
         _check(lib.qoc_create(C.byref(desc), C.byref(self._h)))
         self.precision = precision
@@ -274,7 +277,7 @@ class Problem:
                     block_len=inf.block_len, n_blocks=inf.n_blocks, d_pad=inf.d_pad,
                     flags=inf.flags, device_bytes=inf.device_bytes,
                     bf16x3_classes=inf.bf16x3_classes, unitarity_drift=inf.unitarity_drift,
-                    structured=inf.structured)
+                    structured=inf.structured, segments=inf.segments)
 
     def profile_enable(self, on=True):
         _check(load().qoc_profile_enable(self._h, 1 if on else 0))
