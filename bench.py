@@ -173,17 +173,19 @@ def fp64_torch_path(prob, dev, reps=2):
                 F=F, grad=g)
 
 
-def quick_measure(prob, precision, args, tuned=None):
+def quick_measure(prob, precision, args, tuned=None, segment_steps=0):
     """ms per cost + gradient call of one workload and precision (device-
     resident inputs, args.steps timed calls after args.warmup), with its
-    accuracy against the stored oracle outputs where they exist."""
+    accuracy against the stored oracle outputs where they exist; with
+    segment_steps, in the memory-lean mode (time segments)."""
     import numpy as np
     import torch
     from paper_1612_04929_amd import qoc
     from paper_1612_04929_amd import tune as qtune
     dev = torch.device("cuda:0")
     h = qoc.Problem(prob, precision=precision, device=0,
-                    checkpoint_every=tuned["checkpoint_every"] if tuned else 0)
+                    checkpoint_every=tuned["checkpoint_every"] if tuned else 0,
+                    segment_steps=segment_steps)
     if tuned:
         qtune.apply(h, tuned)
     u = torch.from_numpy(np.ascontiguousarray(prob.u)).to(dev)
@@ -204,7 +206,7 @@ def quick_measure(prob, precision, args, tuned=None):
     r = dict(workload=prob.name, precision=precision, ms_per_step=ms, value=prob.N / (ms / 1e3),
              unit="time-steps/s", taylor_p=info["p"], taylor_n=info["n"],
              checkpoint_every=info["block_len"], bf16x3_classes=info["bf16x3_classes"],
-             flags=info["flags"])
+             flags=info["flags"], segments=info["segments"], device_bytes=info["device_bytes"])
     golden = os.path.join(ROOT, "tests", "golden", f"{prob.name[:2]}_full_oracle.npz")
     if os.path.exists(golden):
         with np.load(golden) as z:
@@ -588,6 +590,14 @@ def main():
         # the metric's range (tuned the same way), as extra keys
         if args.precision == "fp32":
             res["bf16x3"] = quick_measure(prob, "bf16x3", args, tuned)
+        if info["d_pad"] >= 64:
+            # memory-lean mode: four time segments, every stack a quarter
+            # as long, the exponentials formed twice
+            torch.cuda.empty_cache()
+            r = quick_measure(prob, args.precision, args, tuned, segment_steps=-(-prob.N // 4))
+            r["whole_horizon_device_bytes"] = info["device_bytes"]
+            r["whole_horizon_ms_per_step"] = ms
+            res["memory_lean_4_segments"] = r
         for name in [c for c in ("c2", "c3") if c != args.config]:
             q = workloads.make_config(name)
             tq = None if args.no_tune else qtune.tune(q, precision=args.precision)
