@@ -36,4 +36,6 @@ from .grape import (  # noqa: F401
     taylor_select,
     taylor_bound,
     taylor_squaring_expm,
+    action_select,
+    taylor_action,
 )

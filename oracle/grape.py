@@ -107,6 +107,51 @@ def taylor_squaring_expm(A: np.ndarray, p: int, n: int) -> np.ndarray:
     return T
 
 
+# --------------------------------------------------------------------- f2
+def action_select(theta: float, tau: float = 1e-10, p_max: int = 30,
+                  n_max: int = 60) -> tuple:
+    """Global (p, n) for the state-mode action form (Sec. IV: U_j|psi> as a
+    series of matrix-vector products, no U_j formed).
+
+    The approximant is the one of Sec. III, T_p(A/2^n)^(2^n), applied to the
+    columns, which costs p 2^n matrix-vector products per step.  Reading
+    (the paper gives no rule for this form): the pair with the fewest
+    products p 2^n subject to ``taylor_bound(theta, p, n) <= tau`` and
+    theta / 2^n <= 1 (the series terms do not grow, so no large terms
+    cancel), ties toward fewer squarings, p >= 2.
+    """
+    best = None
+    for n in range(n_max):
+        if theta / 2.0 ** n > 1.0:
+            continue
+        for p in range(2, p_max + 1):
+            if taylor_bound(theta, p, n) <= tau:
+                products = p * 2 ** n
+                if best is None or products < best[0]:
+                    best = (products, p, n)
+                break
+    if best is None:
+        raise ValueError(f"no (p, n) meets tau={tau} for theta={theta}")
+    return best[1], best[2]
+
+
+def taylor_action(A: np.ndarray, psi: np.ndarray, p: int, n: int) -> np.ndarray:
+    """T_p(A/2^n)^(2^n) applied to the states (rows of psi) without forming
+    the matrix: 2^n times the truncated series sum_{k=0}^p (A/2^n)^k v / k!,
+    its terms by repeated matrix-vector products (Sec. IV, the series for
+    U_j|Psi>), in FP64."""
+    X = A / 2.0 ** n
+    v = psi.T.astype(np.complex128)  # columns
+    for _ in range(2 ** n):
+        term = v
+        acc = v.copy()
+        for k in range(1, p + 1):
+            term = X @ term / k
+            acc = acc + term
+        v = acc
+    return v.T
+
+
 # --------------------------------------------------------------------- a3/a4
 def propagators(prob, u: Optional[np.ndarray] = None):
     """Exact step propagators U_j = exp(-i H_j dt) (eq. (3)).

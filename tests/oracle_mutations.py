@@ -16,6 +16,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 GRAPE = os.path.join(os.path.dirname(HERE), "oracle", "grape.py")
 
 MUTATIONS = {
+    # action form: series term without its 1/k, (p, n) rule on matrix
+    # products instead of matrix-vector products, no term-growth limit
+    "action_term_factorial": ("            term = X @ term / k\n", "            term = X @ term\n"),
+    "action_rule_products": ("                products = p * 2 ** n\n",
+                             "                products = p - 1 + n\n"),
+    "action_rule_growth": ("        if theta / 2.0 ** n > 1.0:\n            continue\n", ""),
     # exponential: sign of the phase, transposed propagator
     "expm_sign": ("phase = np.exp(-1j * prob.dt * lam)", "phase = np.exp(1j * prob.dt * lam)"),
     "expm_transpose": ("U = (V * phase[:, None, :]) @ np.conj(np.swapaxes(V, 1, 2))",

@@ -423,3 +423,70 @@ def test_forbidden_and_time_optimal_gradient_matches_fd(mode):
     p = random_problem(rng, d=3, M=2, N=5, S=2, dt=0.35, scale=1.3, fid_mode=mode,
                        alphas=(1.0, 0.3, 0.05, 0.02), n_forbidden=2, alpha_time=0.6)
     assert rel(oracle.cost_grad(p)["grad"], fd_grad(p)) < 1e-7
+
+
+# ------------------------------------------------------------ action form
+def test_taylor_action_equals_matrix_approximant_and_expm():
+    """The series applied to the columns is the same polynomial as the
+    matrix approximant (exactly, up to rounding), and within the Taylor
+    bound of the exact exponential."""
+    rng = np.random.default_rng(30)
+    d = 7
+    A0 = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+    H = (A0 + A0.conj().T) / 2
+    H = H * 1.7 / np.abs(H).sum(axis=0).max()      # ||H||_1 = 1.7
+    psi = np.stack([haar_state(rng, d) for _ in range(3)])
+    for p, n in [(2, 0), (5, 1), (9, 3), (12, 0)]:
+        got = oracle.taylor_action(-1j * H, psi, p, n)
+        mat = psi @ oracle.taylor_squaring_expm(-1j * H, p, n).T
+        assert np.max(np.abs(got - mat)) < 1e-13
+        exact = psi @ sla.expm(-1j * H).T
+        assert np.max(np.abs(got - exact)) <= oracle.taylor_bound(1.7, p, n) * (1 + 1e-9) + 1e-14
+
+
+def test_taylor_action_diagonal_and_pauli_closed_forms():
+    # diagonal generator: each component is the scalar truncated series,
+    # applied 2^n times
+    lam = np.array([0.3, -0.8, 1.1])
+    psi = np.array([[1.0, 2.0, -1.0j]])
+    p, n = 4, 2
+    x = -1j * lam / 4
+    scal = sum(x ** k / math.factorial(k) for k in range(p + 1)) ** 4
+    got = oracle.taylor_action(np.diag(-1j * lam), psi, p, n)
+    assert np.max(np.abs(got[0] - scal * psi[0])) < 1e-15
+    # Pauli rotation exp(-i theta sigma_x / 2) |0> = (cos, -i sin), long series
+    theta = 1.3
+    got = oracle.taylor_action(-1j * theta / 2 * SIGMA_X, np.array([[1.0, 0.0]]), 30, 2)
+    assert np.max(np.abs(got[0] - [math.cos(theta / 2), -1j * math.sin(theta / 2)])) < 1e-15
+
+
+def test_action_rule_hand_values_and_brute_force():
+    """theta = 0.81: order 11 leaves 3.7e-10 > 1e-10, order 12 2.3e-11, and
+    n = 1 needs order 9 (18 products): (12, 0).  theta = 3: n >= 2 for
+    theta / 2^n <= 1; n = 2 needs order 12 (48 products), n = 3 order 10
+    (80): (12, 2).  Every choice meets the bound and no pair with fewer
+    products (and theta / 2^n <= 1) does."""
+    assert oracle.action_select(0.81, 1e-10) == (12, 0)
+    assert oracle.action_select(3.0, 1e-10) == (12, 2)
+    assert oracle.action_select(0.0, 1e-10) == (2, 0)
+    for theta in (1e-3, 0.37, 0.81, 1.0, 3.0, 12.0, 70.0):
+        for tau in (1e-10, 1e-15):
+            p, n = oracle.action_select(theta, tau)
+            assert oracle.taylor_bound(theta, p, n) <= tau and theta / 2 ** n <= 1.0
+            for nn in range(0, 12):
+                for pp in range(2, 31):
+                    if pp * 2 ** nn < p * 2 ** n and theta / 2 ** nn <= 1.0:
+                        assert oracle.taylor_bound(theta, pp, nn) > tau
+
+
+def test_action_rule_meets_tolerance_on_a_generator():
+    rng = np.random.default_rng(31)
+    d = 6
+    A0 = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+    H = (A0 + A0.conj().T) / 2
+    psi = np.stack([haar_state(rng, d) for _ in range(2)])
+    for theta in (0.2, 2.5, 9.0):
+        Hs = H * theta / np.abs(H).sum(axis=0).max()
+        p, n = oracle.action_select(theta, 1e-12)
+        err = np.max(np.abs(oracle.taylor_action(-1j * Hs, psi, p, n) - psi @ sla.expm(-1j * Hs).T))
+        assert err <= 1e-12
