@@ -173,7 +173,7 @@ def fp64_torch_path(prob, dev, reps=2):
                 F=F, grad=g)
 
 
-def quick_measure(prob, precision, args, tuned=None, segment_steps=0):
+def quick_measure(prob, precision, args, tuned=None, segment_steps=0, propagation="matrix"):
     """ms per cost + gradient call of one workload and precision (device-
     resident inputs, args.steps timed calls after args.warmup), with its
     accuracy against the stored oracle outputs where they exist; with
@@ -185,7 +185,7 @@ def quick_measure(prob, precision, args, tuned=None, segment_steps=0):
     dev = torch.device("cuda:0")
     h = qoc.Problem(prob, precision=precision, device=0,
                     checkpoint_every=tuned["checkpoint_every"] if tuned else 0,
-                    segment_steps=segment_steps)
+                    segment_steps=segment_steps, propagation=propagation)
     if tuned:
         qtune.apply(h, tuned)
     u = torch.from_numpy(np.ascontiguousarray(prob.u)).to(dev)
@@ -206,7 +206,8 @@ def quick_measure(prob, precision, args, tuned=None, segment_steps=0):
     r = dict(workload=prob.name, precision=precision, ms_per_step=ms, value=prob.N / (ms / 1e3),
              unit="time-steps/s", taylor_p=info["p"], taylor_n=info["n"],
              checkpoint_every=info["block_len"], bf16x3_classes=info["bf16x3_classes"],
-             flags=info["flags"], segments=info["segments"], device_bytes=info["device_bytes"])
+             flags=info["flags"], segments=info["segments"], device_bytes=info["device_bytes"],
+             propagation=propagation)
     golden = os.path.join(ROOT, "tests", "golden", f"{prob.name[:2]}_full_oracle.npz")
     if os.path.exists(golden):
         with np.load(golden) as z:
@@ -598,6 +599,16 @@ def main():
             r["whole_horizon_device_bytes"] = info["device_bytes"]
             r["whole_horizon_ms_per_step"] = ms
             res["memory_lean_4_segments"] = r
+        if args.precision != "bf16x3" and prob.S * 8 <= prob.d:
+            # the state-mode action form (matrix-vector products, no U_j) on
+            # the same workload: it pays where S << d and H_j is sparse
+            torch.cuda.empty_cache()
+            try:
+                r = quick_measure(prob, args.precision, args, None, propagation="action")
+                r["matrix_path_ms_per_step"] = ms
+                res["action_form"] = r
+            except qoc.QocError as e:
+                res["action_form"] = dict(unsupported=str(e))
         for name in [c for c in ("c2", "c3") if c != args.config]:
             q = workloads.make_config(name)
             tq = None if args.no_tune else qtune.tune(q, precision=args.precision)

@@ -97,6 +97,8 @@ enum {
  * accumulation) or as FP32 products.  Sec. III: the Taylor series of
  * eq. 6 on the scaled generator, the squarings that undo the scaling; Sec.
  * II.B: the reverse pass. */
+enum { QOC_PROP_MATRIX = 0, QOC_PROP_ACTION = 1 };
+
 enum {
   QOC_BF3_TAYLOR = 1,     /* Taylor (Horner / Paterson-Stockmeyer) products   */
   QOC_BF3_SQUARING = 2,   /* the n squarings D <- 2D + D^2                    */
@@ -158,6 +160,20 @@ typedef struct {
                                states, checkpoints and costates stay whole
                                (O(N S d)).  Negative: QOC_ERR_ARG; a handle
                                on the small-d path: QOC_ERR_UNSUPPORTED    */
+  int propagation;          /* QOC_PROP_MATRIX (0, default): every step
+                               exponential formed as a matrix (batched
+                               Taylor + squaring products); QOC_PROP_ACTION:
+                               the state-mode action form of Sec. IV, the
+                               approximant applied to the S columns by
+                               p 2^n matrix-vector products per step with
+                               H_j in a sparse (ELL) layout over the union
+                               pattern of H_0 .. H_M, no U_j formed and no
+                               per-step matrix stack held; (p, n) by the
+                               fewest products within the same bound (and
+                               theta / 2^n <= 1).  FP32 or FP64; the union
+                               pattern may hold at most 32 nonzeros per row
+                               (FP32, padded d <= 512; 16 in FP64 or above
+                               512), else QOC_ERR_UNSUPPORTED at create    */
 } qoc_problem_desc;
 
 /* Diagnostics of the most recent forward / cost_grad call on a handle. */
@@ -182,6 +198,7 @@ typedef struct {
                                (sparse) norm and gradient contraction       */
   int segments;             /* time segments of the memory-lean mode (1: the
                                whole horizon at once)                       */
+  int propagation;          /* QOC_PROP_* of the handle                      */
 } qoc_info;
 
 /* Create a handle: validates and copies the problem to device memory.

@@ -16,7 +16,7 @@ SOURCES = ["kernels_expm.hip", "kernels_norm.hip", "kernels_sweep.hip", "kernels
            "kernels_expm_small.hip",
            "kernels_sweep_wave.hip", "kernels_sweep_chain.hip",
            "kernels_adjoint.hip", "kernels_adjoint16.hip",
-           "kernels_adjoint_big.hip", "kernels_ext.hip", "qoc_api.cpp"]
+           "kernels_adjoint_big.hip", "kernels_ext.hip", "kernels_action.hip", "qoc_api.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # packed FP32 VALU instructions stay disabled in all device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -647,6 +647,17 @@ template <typename T> __global__ void k_adj_finish(AdjFinish<T> a) {
   }
 }
 
+hipError_t launch_grad_finish(const double *part, const double *u, double *grad, double two_s,
+                              double alpha_amp, double alpha_var, int N, int M, int tiles, long j0,
+                              int Nf, hipStream_t st) {
+  if ((long)N * M <= 0) return hipSuccess;
+  AdjFinish<float> f{part, u, grad, two_s, alpha_amp, alpha_var, nullptr, N, M, tiles, j0, Nf};
+  const long b = ((long)N * M + 255) / 256;
+  hipLaunchKernelGGL(k_adj_finish<float>, dim3((unsigned)(b > 65536 ? 65536 : b)), dim3(256), 0,
+                     st, f);
+  return hipGetLastError();
+}
+
 // (elements of one step / 256) x (steps, at most 65535: the kernels loop)
 static dim3 grid2d(long per_step, long N) {
   const long bx = (per_step + 255) / 256;

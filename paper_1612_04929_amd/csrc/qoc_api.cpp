@@ -62,6 +62,34 @@ bool taylor_select(double theta, double tol, int *p_out, int *n_out) {
   return true;
 }
 
+// The action form's pair (U_j psi by p 2^n products with H_j): the fewest
+// products within the same bound, with theta / 2^n <= 1 so that the series
+// terms do not grow (no cancellation between large terms in FP32); ties
+// toward fewer squarings.
+bool action_select(double theta, double tol, int *p_out, int *n_out) {
+  long best = -1;
+  int bp = 0, bn = 0;
+  for (int n = 0; n < 60; ++n) {
+    if (std::ldexp(theta, -n) > 1.0) continue;
+    if (best >= 0 && (2L << n) >= best) break;  // p >= 2: no later n does better
+    for (int p = 2; p <= 30; ++p) {
+      if (taylor_bound(theta, p, n) <= tol) {
+        const long c = (long)p << n;
+        if (best < 0 || c < best) {
+          best = c;
+          bp = p;
+          bn = n;
+        }
+        break;
+      }
+    }
+  }
+  if (best < 0) return false;
+  *p_out = bp;
+  *n_out = bn;
+  return true;
+}
+
 // Largest theta whose truncation bound a fixed (p, n) still meets (the
 // bound grows with theta): what a fixed pair admits without a warning.
 double theta_admitted(int p, int n, double tol) {
@@ -223,6 +251,20 @@ struct qoc_handle {
   double *psiT64 = nullptr;   // S x d complex interleaved
   double *w64 = nullptr;      // dp
   void *pw = nullptr;         // dp, a_pen / S * w
+  // action form (QOC_PROP_ACTION): H_j in an ELL layout (actK slots per
+  // row), every matrix's slot values, per-step values, product inputs and
+  // cotangents of gradient calls, and the controls' entries
+  int prop = QOC_PROP_MATRIX, actK = 0;
+  int *act_ecol = nullptr;       // actK x dp
+  double *act_hm = nullptr;      // (M+1) x actK x 2 x dp
+  void *act_hv = nullptr;        // N x actK x 2 x dp
+  void *act_A = nullptr, *act_Y = nullptr;  // N x S x P x 2 x dp each
+  long act_P = 0;                // P of act_A / act_Y
+  double *act_part = nullptr;    // N x S x M
+  int act_nent = 0;
+  int *act_erow = nullptr, *act_ecol2 = nullptr, *act_cptr = nullptr, *act_cent = nullptr;
+  void *act_cval = nullptr;
+  long act_npairs = 0;
   // memory-lean mode: time segments of Ns steps (a multiple of L; Ns = N
   // and nseg = 1 when off); every per-step stack holds Ns steps
   int Ns = 0, nseg = 1;
@@ -311,6 +353,9 @@ void release(qoc_handle *h) {
                    (void **)&h->grad_dev, &h->psi0, (void **)&h->psiT64, (void **)&h->w64,
                    &h->pw, &h->X, &h->Qa, &h->Qb, &h->Eh, &h->Es, &h->Ehs, &h->nu, &h->Dlev,
                    (void **)&h->forb64, &h->src, (void **)&h->ext_part, (void **)&h->u_seg,
+                   (void **)&h->act_ecol, (void **)&h->act_hm, &h->act_hv, &h->act_A, &h->act_Y,
+                   (void **)&h->act_part, (void **)&h->act_erow, (void **)&h->act_ecol2,
+                   (void **)&h->act_cptr, (void **)&h->act_cent, &h->act_cval,
                    (void **)&h->sp_colptr, (void **)&h->sp_rowidx, (void **)&h->sp_vals,
                    (void **)&h->sp_rptr, (void **)&h->sp_rcol, (void **)&h->sp_eptr,
                    (void **)&h->sp_ek, &h->sp_eval,
@@ -570,6 +615,113 @@ qoc_status build_structure(qoc_handle *h, const std::vector<double> &h64) {
   return QOC_OK;
 }
 
+// Action form: the ELL layout of the union pattern of H_0 .. H_M over the
+// padded rows (K slots per row, zero-valued padding slots at the row's own
+// column), every matrix's slot values in FP64, the per-step value and
+// partial-sum buffers, and for the gradient the union of the controls'
+// patterns (rows, columns) with each control's entries and values.
+template <typename T>
+qoc_status build_action(qoc_handle *h, const std::vector<double> &h64) {
+  const int d = h->d, dp = h->dp, M = h->M, N = h->N, S = h->S;
+  const size_t dd = (size_t)d * d * 2;
+  auto at = [&](int k, int r, int c) { return h64.data() + k * dd + 2 * ((size_t)r * d + c); };
+  auto nz = [&](int k, int r, int c) {
+    const double *x = at(k, r, c);
+    return x[0] != 0.0 || x[1] != 0.0;
+  };
+  std::vector<std::vector<int>> rows(dp);
+  size_t width = 1;
+  for (int r = 0; r < d; ++r) {
+    for (int c = 0; c < d; ++c)
+      for (int k = 0; k <= M; ++k)
+        if (nz(k, r, c)) {
+          rows[r].push_back(c);
+          break;
+        }
+    width = std::max(width, rows[r].size());
+  }
+  int K = 4;  // slot counts the chains are built for: 4, 8, 12, 16, 24, 32
+  while ((size_t)K < width) K = K < 8 ? 8 : (K < 16 ? K + 4 : K + 8);
+  if (!qoc::act_shape_ok<T>(dp, K))
+    return fail(QOC_ERR_UNSUPPORTED,
+                "the action form keeps each row's nonzeros in registers: the union pattern of "
+                "H_0 .. H_M has " + std::to_string(width) + " per row (at most 32 in FP32 and 16 "
+                "in FP64 for padded d <= 512, half that up to 1024)");
+  h->actK = K;
+  std::vector<int> ecol((size_t)K * dp);
+  std::vector<double> hm((size_t)(M + 1) * K * 2 * dp, 0.0);
+  for (int r = 0; r < dp; ++r)
+    for (int kk = 0; kk < K; ++kk) {
+      const bool real = kk < (int)rows[r].size();
+      const int c = real ? rows[r][kk] : r;
+      ecol[(size_t)kk * dp + r] = c;
+      if (!real) continue;
+      for (int k = 0; k <= M; ++k) {
+        const double *x = at(k, r, c);
+        double *o = hm.data() + (((size_t)k * K + kk) * 2) * dp;
+        o[r] = x[0];
+        o[dp + r] = x[1];
+      }
+    }
+  // the controls' entries and each control's (entry, value) pairs
+  std::vector<int> erow, ecol2, cptr(M + 1, 0), cent;
+  std::vector<std::vector<std::pair<int, int>>> per(M);  // (entry, (r, c) index)
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c < d; ++c) {
+      int e = -1;
+      for (int k = 1; k <= M; ++k)
+        if (nz(k, r, c)) {
+          if (e < 0) {
+            e = (int)erow.size();
+            erow.push_back(r);
+            ecol2.push_back(c);
+          }
+          per[k - 1].push_back({e, r * d + c});
+        }
+    }
+  h->act_nent = (int)erow.size();
+  for (int k = 0; k < M; ++k) cptr[k + 1] = cptr[k] + (int)per[k].size();
+  h->act_npairs = cptr[M];
+  std::vector<T> cval(2 * std::max<long>(1, h->act_npairs));
+  for (int k = 0; k < M; ++k)
+    for (size_t i = 0; i < per[k].size(); ++i) {
+      const long pi = cptr[k] + (long)i;
+      const int rc = per[k][i].second;
+      const double *x = at(k + 1, rc / d, rc % d);
+      cent.push_back(per[k][i].first);
+      cval[pi] = (T)x[0];
+      cval[h->act_npairs + pi] = (T)x[1];
+    }
+  if (M > 0 && qoc::act_grad_lds<T>(dp, h->act_nent) > 64 * 1024)
+    return fail(QOC_ERR_UNSUPPORTED,
+                "the action form's gradient keeps the controls' " +
+                    std::to_string(h->act_nent) +
+                    " pattern entries in LDS: too many for 64 KB at this d");
+  qoc_status s;
+#define ALLOC(ptr, bytes)                                        \
+  if ((s = dalloc(h, (void **)&(ptr), (bytes))) != QOC_OK) return s;
+  ALLOC(h->act_ecol, ecol.size() * sizeof(int));
+  ALLOC(h->act_hm, hm.size() * sizeof(double));
+  ALLOC(h->act_hv, (size_t)N * K * 2 * dp * sizeof(T));
+  ALLOC(h->act_part, (size_t)N * S * std::max(1, M) * sizeof(double));
+  ALLOC(h->act_erow, std::max<size_t>(1, erow.size()) * sizeof(int));
+  ALLOC(h->act_ecol2, std::max<size_t>(1, ecol2.size()) * sizeof(int));
+  ALLOC(h->act_cptr, cptr.size() * sizeof(int));
+  ALLOC(h->act_cent, std::max<size_t>(1, cent.size()) * sizeof(int));
+  ALLOC(h->act_cval, cval.size() * sizeof(T));
+#undef ALLOC
+  HIP_TRY(hipMemcpy(h->act_ecol, ecol.data(), ecol.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->act_hm, hm.data(), hm.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (!erow.empty()) {
+    HIP_TRY(hipMemcpy(h->act_erow, erow.data(), erow.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->act_ecol2, ecol2.data(), ecol2.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->act_cent, cent.data(), cent.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipMemcpy(h->act_cptr, cptr.data(), cptr.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->act_cval, cval.data(), cval.size() * sizeof(T), hipMemcpyHostToDevice));
+  return QOC_OK;
+}
+
 template <typename T>
 qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   const int d = h->d, dp = h->dp, M = h->M, N = h->N, S = h->S;
@@ -588,7 +740,8 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
     ALLOC(h->w64, (size_t)dp * sizeof(double));
     ALLOC(h->pw, (size_t)dp * sizeof(T));
   }
-  const size_t Ns = (size_t)h->Ns;
+  // the action form forms no step propagator: no per-step matrix stacks
+  const size_t Ns = h->prop == QOC_PROP_ACTION ? 0 : (size_t)h->Ns;
   ALLOC(h->X, Ns * mat * sizeof(T));
   ALLOC(h->Qa, Ns * mat * sizeof(T));
   ALLOC(h->Qb, Ns * mat * sizeof(T));
@@ -662,6 +815,7 @@ qoc_status alloc_all(qoc_handle *h, const qoc_problem_desc *desc) {
   HIP_TRY(hipMemcpy(h->Hf, hf.data(), hf.size() * sizeof(T), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->H64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice));
   if ((s = build_structure<T>(h, h64)) != QOC_OK) return s;
+  if (h->prop == QOC_PROP_ACTION && (s = build_action<T>(h, h64)) != QOC_OK) return s;
   std::vector<T> ps(set, (T)0);
   for (int s2 = 0; s2 < S; ++s2)
     for (int m = 0; m < d; ++m) {
@@ -874,7 +1028,7 @@ hipError_t block_tree_any(qoc_handle *h, const T *D, long N, T *Qa, T *Qb, long 
 // or chosen on the host from theta_max read back).
 template <typename T>
 qoc_status choose_pn_large(qoc_handle *h, const double *u_dev, hipStream_t st,
-                           const qoc::SparseU *spu, int *p, int *n) {
+                           const qoc::SparseU *spu, int *p, int *n, bool action = false) {
   {
     PhaseTimer tm(h, QOC_PHASE_NORM, st);
     // a fixed (p, n) is checked against the tolerance on the device
@@ -903,7 +1057,7 @@ qoc_status choose_pn_large(qoc_handle *h, const double *u_dev, hipStream_t st,
   std::memcpy(&theta, &tb, sizeof(theta));
   h->last_theta = theta;
   if (!std::isfinite(theta)) return fail(QOC_ERR_NONFINITE, "non-finite step norm");
-  if (!taylor_select(theta, h->tol, p, n))
+  if (!(action ? action_select(theta, h->tol, p, n) : taylor_select(theta, h->tol, p, n)))
     return fail(QOC_ERR_UNSUPPORTED, "no (p, n) meets the tolerance for theta_max = " +
                                          std::to_string(theta));
   return QOC_OK;
@@ -1400,8 +1554,115 @@ qoc_status run_segmented(qoc_handle *h, const double *u_dev, double *out_dev, do
   return QOC_OK;
 }
 
+// Product inputs and cotangents of the action form's gradient for P
+// products per step and column.
+template <typename T> qoc_status ensure_action_work(qoc_handle *h, long P) {
+  const size_t bytes = (size_t)h->N * h->S * P * 2 * h->dp * sizeof(T);
+  if (h->ws_base) {
+    qoc_status s = carve(h, &h->act_A, bytes);
+    return s ? s : carve(h, &h->act_Y, bytes);
+  }
+  if (P <= h->act_P) return QOC_OK;
+  const size_t old = (size_t)h->N * h->S * h->act_P * 2 * h->dp * sizeof(T);
+  dfree(h, &h->act_A, old);
+  dfree(h, &h->act_Y, old);
+  h->act_P = 0;
+  qoc_status s = dalloc(h, &h->act_A, bytes);
+  if (s || (s = dalloc(h, &h->act_Y, bytes)) != QOC_OK) return s;
+  h->act_P = P;
+  return QOC_OK;
+}
+
+// State-mode action form (Sec. IV): no step propagator is formed.  The
+// per-step values of H_j (parallel over steps), the forward chain of
+// matrix-vector products (one workgroup per column; it keeps every
+// product's input for the gradient), the cost over the whole horizon, the
+// backward chain (the reverse pass of the same products: the costates, and
+// every product's output cotangent), then the derivative for all controls
+// at once, parallel over (step, column).  The first-order mode contracts
+// (lambda_{j+1}, psi_{j+1}) instead.
+template <typename T>
+qoc_status run_action(qoc_handle *h, const double *u_dev, double *out_dev, double *grad_dev,
+                      hipStream_t st, bool want_grad) {
+  const int dp = h->dp, N = h->N, M = h->M, S = h->S;
+  const long set = 2L * S * dp;
+  const bool sp_on = h->sp_built && (h->sp_mode == 1 || (h->sp_mode < 0 && h->sp_auto));
+  h->sp_used = sp_on;
+  const qoc::SparseU spu{h->sp_colptr, h->sp_rowidx, h->sp_vals};
+  int p = 0, n = 0;
+  qoc_status s = choose_pn_large<T>(h, u_dev, st, sp_on ? &spu : nullptr, &p, &n, true);
+  if (s) return s;
+  if (p > 32 || n > 16 || ((long)p << n) > 4096)
+    return fail(QOC_ERR_UNSUPPORTED, "the action form runs at most 4096 products per step (p 2^n "
+                                     "with n <= 16); theta_max or the fixed pair asks for more");
+  const long P = (long)p << n;
+  h->last_p = p;
+  h->last_n = n;
+  h->bf3_used = 0;
+  h->bf3_fallback = 0;
+  h->unit_epoch = 0;  // no step propagator to check
+  const bool first_order = h->grad_mode == QOC_GRAD_FIRST_ORDER;
+  const bool keep = want_grad && M > 0 && !first_order;
+  if (keep && (s = ensure_action_work<T>(h, P)) != QOC_OK) return s;
+  {
+    PhaseTimer tm(h, QOC_PHASE_ASSEMBLE, st);
+    const qoc::ActValArgs<T> va{h->act_hm, u_dev, M, N, h->actK, dp, (T *)h->act_hv};
+    HIP_TRY(qoc::launch_act_values<T>(va, st));
+  }
+  qoc::ActionArgs<T> a{};
+  a.N = N; a.dp = dp; a.S = S; a.K = h->actK; a.p = p; a.n = n; a.P = (int)P;
+  a.s = (T)std::ldexp(h->dt, -n);
+  for (int k = 1; k <= p; ++k) {
+    a.coef[k] = (T)(std::ldexp(h->dt, -n) / k);
+    a.inv[k] = (T)(1.0 / k);
+  }
+  a.ecol = h->act_ecol; a.hv = (const T *)h->act_hv; a.psi0 = (const T *)h->psi0;
+  a.psi_buf = (T *)h->psi_buf; a.A = keep ? (T *)h->act_A : nullptr;
+  a.lamN = (const T *)h->lam_ckpt + (long)h->nb * set; a.lam_buf = (T *)h->lam_buf;
+  a.pw = (const T *)h->pw; a.src = h->has_ext ? (const T *)h->src : nullptr;
+  a.Ybar = keep ? (T *)h->act_Y : nullptr;
+  {
+    PhaseTimer tm(h, QOC_PHASE_FWD_REPLAY, st);
+    HIP_TRY(qoc::launch_act_chain<T>(0, a, st));
+  }
+  const qoc::SweepArgs<T> all = sweep_args<T>(h, nullptr, nullptr, u_dev, out_dev);
+  HIP_TRY(launch_cost_all<T>(h, all, true, st));
+  if (!want_grad) return QOC_OK;
+  {
+    PhaseTimer tm(h, QOC_PHASE_BWD_PAIRS, st);
+    HIP_TRY(qoc::launch_act_chain<T>(1, a, st));
+  }
+  if (M == 0) return QOC_OK;
+  PhaseTimer tm(h, QOC_PHASE_ADJOINT, st);
+  qoc::ActGradArgs<T> g{};
+  if (first_order) {
+    // eq. (7): one product per step, (lambda_{j+1}, psi_{j+1}) in set layout
+    g.A = (const T *)h->psi_buf + set; g.aj = set; g.as = dp; g.aq = 0; g.aplane = (long)S * dp;
+    g.Y = (const T *)h->lam_buf; g.yj = set; g.ys = dp; g.yq = 0; g.yplane = (long)S * dp;
+    g.P = 1;
+  } else {
+    const long vec = 2L * dp;
+    g.A = (const T *)h->act_A; g.aj = S * P * vec; g.as = P * vec; g.aq = vec; g.aplane = dp;
+    g.Y = (const T *)h->act_Y; g.yj = S * P * vec; g.ys = P * vec; g.yq = vec; g.yplane = dp;
+    g.P = (int)P;
+  }
+  g.N = N; g.S = S; g.dp = dp; g.M = M;
+  g.nent = h->act_nent; g.erow = h->act_erow; g.ecol = h->act_ecol2;
+  g.cptr = h->act_cptr; g.cent = h->act_cent; g.cval = (const T *)h->act_cval;
+  g.npairs = h->act_npairs; g.part = h->act_part;
+  HIP_TRY(qoc::launch_act_grad<T>(g, st));
+  const double two_s = 2.0 * (first_order ? h->dt : std::ldexp(h->dt, -n));
+  HIP_TRY(qoc::launch_grad_finish(h->act_part, u_dev, grad_dev, two_s, h->a_amp, h->a_var, N, M,
+                                  S, 0, N, st));
+  return QOC_OK;
+}
+
 qoc_status run_any(qoc_handle *h, const double *u_dev, double *out_dev, double *grad_dev,
                    hipStream_t st, bool want_grad) {
+  if (h->prop == QOC_PROP_ACTION) {
+    if (h->prec == QOC_FP64) return run_action<double>(h, u_dev, out_dev, grad_dev, st, want_grad);
+    return run_action<float>(h, u_dev, out_dev, grad_dev, st, want_grad);
+  }
   if (h->nseg > 1) {
     if (h->prec == QOC_FP64)
       return run_segmented<double>(h, u_dev, out_dev, grad_dev, st, want_grad);
@@ -1425,9 +1686,7 @@ qoc_status finish_diag(qoc_handle *h, hipStream_t st, int *flags) {
   unsigned long long b[4] = {0, 0, 0, 0};
   int pn[3] = {0, 0, 0};
   HIP_TRY(hipMemcpyAsync(b, h->bits, sizeof(b), hipMemcpyDeviceToHost, st));
-  const bool small_path = h->prec == QOC_FP64
-                              ? (qoc::small_expm_ok<double>(h->dp) && qoc::small_sweep_ok<double>(h->dp, h->S))
-                              : (qoc::small_expm_ok<float>(h->dp) && qoc::small_sweep_ok<float>(h->dp, h->S));
+  const bool small_path = h->prop != QOC_PROP_ACTION && on_small_path(h);
   const bool dev_pn = small_path || h->fixed_p >= 2;
   if (dev_pn) HIP_TRY(hipMemcpyAsync(pn, h->pn_dev, sizeof(pn), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -1564,6 +1823,13 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
         D.pad_multiple == 64))
     return fail(QOC_ERR_ARG, "pad_multiple must be 0, 16, 32 or 64");
   if (D.segment_steps < 0) return fail(QOC_ERR_ARG, "segment_steps must be >= 0");
+  if (!(D.propagation == QOC_PROP_MATRIX || D.propagation == QOC_PROP_ACTION))
+    return fail(QOC_ERR_ARG, "propagation must be QOC_PROP_MATRIX or QOC_PROP_ACTION");
+  if (D.propagation == QOC_PROP_ACTION && D.precision == QOC_BF16X3)
+    return fail(QOC_ERR_UNSUPPORTED, "the action form runs no matrix products: FP32 or FP64");
+  if (D.propagation == QOC_PROP_ACTION && D.segment_steps > 0)
+    return fail(QOC_ERR_UNSUPPORTED, "the action form keeps no per-step matrix stacks to "
+                                     "segment");
   if (!(D.taylor_tol >= 0.0) || !std::isfinite(D.taylor_tol))
     return fail(QOC_ERR_ARG, "taylor_tol must be finite and >= 0");
   if (!(D.taylor_p == 0 || (D.taylor_p >= 2 && D.taylor_p <= 64 && D.taylor_n >= 0 &&
@@ -1615,6 +1881,7 @@ qoc_status qoc_create(const qoc_problem_desc *desc, qoc_handle **out) {
   h->M = D.M;
   h->N = D.N;
   h->S = D.S;
+  h->prop = D.propagation;
   h->dt = D.dt;
   h->prec = D.precision;
   h->bf3 = D.precision == QOC_BF16X3 ? 1 : 0;
@@ -1907,6 +2174,7 @@ qoc_status qoc_get_info(const qoc_handle *hc, qoc_info *info) {
   info->unitarity_drift = h->last_unitarity;
   info->structured = h->sp_used ? 1 : 0;
   info->segments = h->nseg;
+  info->propagation = h->prop;
   return QOC_OK;
 }
 

@@ -294,5 +294,57 @@ template <typename T> hipError_t launch_adjoint16(const AdjointArgs<T> &a, hipSt
 // the C3 / C4 gradients.
 template <typename T> hipError_t launch_grad_first(const AdjointArgs<T> &a, double dt,
                                                    hipStream_t st);
+// grad[k, j0 + j] = two_s sum_t part[(j tiles + t) M + k] + the C3 / C4
+// gradients, for the N steps j0 .. j0 + N - 1 of a horizon of Nf steps.
+hipError_t launch_grad_finish(const double *part, const double *u, double *grad, double two_s,
+                              double alpha_amp, double alpha_var, int N, int M, int tiles, long j0,
+                              int Nf, hipStream_t st);
+
+// ---------------------------------------------------------------- action form
+// State-mode action form (kernels_action.hip): H_j in an ELL layout over the
+// union pattern of H_0 .. H_M, K slots per row.
+template <typename T> struct ActValArgs {
+  const double *hm;  // (M+1) x K x 2 x dp: each matrix's slot values (re plane, im plane)
+  const double *u;   // M x N
+  int M, N, K, dp;
+  T *hv;             // N x K x 2 x dp: H_j's slot values
+};
+template <typename T> struct ActionArgs {
+  int N, dp, S, K, p, n, P;  // P = p 2^n products per step and column
+  T s;                       // dt / 2^n
+  T coef[33], inv[33];       // s / k and 1 / k, k = 1 .. p (p <= 32)
+  const int *ecol;           // K x dp: column of slot (kk, r)
+  const T *hv;               // N x K x 2 x dp
+  const T *psi0;             // state set
+  T *psi_buf;                // (N+1) state sets
+  T *A;                      // N x S x P x 2 x dp: product inputs (null: not kept)
+  const T *lamN;             // state set: lambda_N
+  T *lam_buf;                // N state sets: lambda_{j+1} at set j
+  const T *pw, *src;         // per-step costate sources (null: none)
+  T *Ybar;                   // N x S x P x 2 x dp: product output cotangents (null: not kept)
+};
+template <typename T> struct ActGradArgs {
+  // product inputs a_q and output cotangents ybar_q of step j, column s:
+  // base + j * (a|y)j + s * (a|y)s + q * (a|y)q, imaginary plane at +(a|y)plane
+  const T *A, *Y;
+  long aj, as, aq, aplane, yj, ys, yq, yplane;
+  int N, S, P, dp, M;
+  int nent;                   // entries of the union of the controls' patterns
+  const int *erow, *ecol;     // their rows and columns
+  const int *cptr, *cent;     // per control k: entries cent[cptr[k] .. cptr[k+1])
+  const T *cval;              // ... and values (re plane, then im plane at +npairs)
+  long npairs;
+  double *part;               // N x S x M partial sums
+};
+template <typename T> hipError_t launch_act_values(const ActValArgs<T> &a, hipStream_t st);
+// which 0: forward chain (psi, product inputs); 1: backward chain (lambda,
+// product cotangents).  One workgroup per column.
+template <typename T> hipError_t launch_act_chain(int which, const ActionArgs<T> &a,
+                                                  hipStream_t st);
+template <typename T> hipError_t launch_act_grad(const ActGradArgs<T> &a, hipStream_t st);
+// Shapes the chains handle: padded d <= 1024 and K slots (4, 8, 16, 32) per
+// row within the register budget; LDS bytes of the gradient kernel.
+template <typename T> bool act_shape_ok(int dp, int K);
+template <typename T> long act_grad_lds(int dp, long nent);
 
 }  // namespace qoc

@@ -22,6 +22,8 @@ QOC_FID_COHERENT, QOC_FID_INCOHERENT = 0, 1
 QOC_WARN_DRIFT, QOC_WARN_TAYLOR, QOC_WARN_PRECISION, QOC_WARN_UNITARITY = 1, 2, 4, 8
 QOC_WARN_NO_PAIR = 16
 QOC_GRAD_EXACT, QOC_GRAD_FIRST_ORDER = 0, 1
+QOC_PROP_MATRIX, QOC_PROP_ACTION = 0, 1
+PROPAGATIONS = {"matrix": QOC_PROP_MATRIX, "action": QOC_PROP_ACTION}
 QOC_BF3_TAYLOR, QOC_BF3_SQUARING, QOC_BF3_BLOCKPROD, QOC_BF3_ADJOINT = 1, 2, 4, 8
 QOC_BF3_ALL = 15
 PHASES = ["norm", "assemble", "taylor", "blockprod", "fwd_blocks", "fwd_replay", "cost",
@@ -50,7 +52,7 @@ class Desc(C.Structure):
                 ("taylor_tol", C.c_double), ("taylor_p", C.c_int), ("taylor_n", C.c_int),
                 ("drift_warn", C.c_double), ("device", C.c_int), ("n_forbidden", C.c_int),
                 ("forbidden", _dp), ("alpha_time", C.c_double), ("pad_multiple", C.c_int),
-                ("segment_steps", C.c_int)]
+                ("segment_steps", C.c_int), ("propagation", C.c_int)]
 
 
 class Info(C.Structure):
@@ -58,7 +60,7 @@ class Info(C.Structure):
                 ("norm_drift", C.c_double), ("block_len", C.c_int), ("n_blocks", C.c_int),
                 ("d_pad", C.c_int), ("flags", C.c_int), ("device_bytes", C.c_size_t),
                 ("bf16x3_classes", C.c_int), ("unitarity_drift", C.c_double),
-                ("structured", C.c_int), ("segments", C.c_int)]
+                ("structured", C.c_int), ("segments", C.c_int), ("propagation", C.c_int)]
 
 
 class QocError(RuntimeError):
@@ -156,7 +158,7 @@ class Problem:
 
     def __init__(self, prob, precision="fp32", checkpoint_every=0, taylor_tol=0.0,
                  taylor_pn=None, drift_warn=0.0, device=0, structure=-1, pad_multiple=0,
-                 segment_steps=0):
+                 segment_steps=0, propagation="matrix"):
         lib = load()
         self.d, self.M, self.N, self.S = int(prob.d), int(prob.M), int(prob.N), int(prob.S)
         keep = []
@@ -186,7 +188,7 @@ class Problem:
                     int(fid), PRECISIONS.get(precision, precision), int(checkpoint_every),
                     float(taylor_tol), tp, tn, float(drift_warn), int(device), nf, pf,
                     float(getattr(prob, "alpha_time", 0.0)), int(pad_multiple),
-                    int(segment_steps))
+                    int(segment_steps), PROPAGATIONS.get(propagation, propagation))
         self._h = C.c_void_p()
         _check(lib.qoc_create(C.byref(desc), C.byref(self._h)))
         self.precision = precision
@@ -277,7 +279,8 @@ class Problem:
                     block_len=inf.block_len, n_blocks=inf.n_blocks, d_pad=inf.d_pad,
                     flags=inf.flags, device_bytes=inf.device_bytes,
                     bf16x3_classes=inf.bf16x3_classes, unitarity_drift=inf.unitarity_drift,
-                    structured=inf.structured, segments=inf.segments)
+                    structured=inf.structured, segments=inf.segments,
+                    propagation=inf.propagation)
 
     def profile_enable(self, on=True):
         _check(load().qoc_profile_enable(self._h, 1 if on else 0))

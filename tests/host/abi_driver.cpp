@@ -76,6 +76,9 @@ int main() {
   { auto X = D; X.taylor_p = 1; expect_create(X, QOC_ERR_ARG); }
   { auto X = D; X.pad_multiple = 48; expect_create(X, QOC_ERR_ARG); }
   { auto X = D; X.segment_steps = -1; expect_create(X, QOC_ERR_ARG); }
+  { auto X = D; X.propagation = 2; expect_create(X, QOC_ERR_ARG); }
+  { auto X = D; X.propagation = QOC_PROP_ACTION; X.precision = QOC_BF16X3;
+    expect_create(X, QOC_ERR_UNSUPPORTED); }
   { auto X = D; X.n_forbidden = 17; expect_create(X, QOC_ERR_SHAPE); }
   { auto X = D; X.forbidden = nullptr; expect_create(X, QOC_ERR_ARG); }
   { auto X = D; X.alpha_time = INFINITY; expect_create(X, QOC_ERR_NONFINITE); }

@@ -320,3 +320,39 @@ def random_problem(rng: np.random.Generator, d: int, M: int, N: int, S: int,
                    alpha_pen=ap if (with_penalty or n_forbidden > 0) else 0.0,
                    alpha_amp=aa, alpha_var=av, fid_mode=fid_mode, forbidden=forb,
                    alpha_time=float(alpha_time))
+
+
+def sparse_problem(rng: np.random.Generator, d: int, M: int, N: int, S: int,
+                   dt: float = 0.1, couplings: int = 2, u_scale: float = 0.5,
+                   with_penalty: bool = True, fid_mode: str = "coherent",
+                   alphas=(1.0, 0.3, 0.05, 0.02), n_forbidden: int = 0,
+                   alpha_time: float = 0.0) -> Problem:
+    """Random sparse Hermitian drift and controls: H_0 a random diagonal plus
+    ``couplings`` random pairings of the basis states (one off-diagonal
+    entry per row and pairing, Hermitian), each H_k one such pairing, so
+    that a row of H_j holds at most 1 + couplings + M nonzeros."""
+    def pairing():
+        A = np.zeros((d, d), np.complex128)
+        perm = rng.permutation(d)
+        for i in range(0, d - 1, 2):
+            a, b = perm[i], perm[i + 1]
+            v = (rng.standard_normal() + 1j * rng.standard_normal()) / math.sqrt(2.0)
+            A[a, b] = v
+            A[b, a] = np.conj(v)
+        return A
+    H0 = np.diag(rng.standard_normal(d)).astype(np.complex128)
+    for _ in range(couplings):
+        H0 = H0 + pairing()
+    Hk = np.stack([pairing() for _ in range(M)]) if M else np.zeros((0, d, d), np.complex128)
+    u = rng.uniform(-u_scale, u_scale, size=(M, N))
+    psi0 = np.stack([haar_state(rng, d) for _ in range(S)])
+    psiT = np.stack([haar_state(rng, d) for _ in range(S)])
+    w = rng.uniform(0.0, 1.0, size=d) if with_penalty else None
+    forb = (np.stack([haar_state(rng, d) for _ in range(n_forbidden)])
+            if n_forbidden > 0 else None)
+    af, ap, aa, av = alphas
+    return Problem(f"sparse_d{d}_M{M}_N{N}_S{S}", d, M, N, S, dt, H0, Hk, u, psi0,
+                   psiT, w=w, alpha_fid=af,
+                   alpha_pen=ap if (with_penalty or n_forbidden > 0) else 0.0,
+                   alpha_amp=aa, alpha_var=av, fid_mode=fid_mode, forbidden=forb,
+                   alpha_time=float(alpha_time))
