@@ -38,4 +38,6 @@ from .grape import (  # noqa: F401
     taylor_squaring_expm,
     action_select,
     taylor_action,
+    ps_products,
+    taylor_select_ps,
 )

@@ -94,6 +94,43 @@ def taylor_select(theta: float, tau: float = 1e-10, p_max: int = 30,
     return best[1], best[2]
 
 
+def ps_products(p: int) -> int:
+    """Matrix products that evaluate T_p(X) (p >= 1) in Paterson-Stockmeyer
+    form, or by Horner's rule when that takes fewer: the powers X^2 .. X^s
+    (s - 1 products, 2 <= s <= min(p, 4)), then Horner's rule in Y = X^s
+    over the floor(p/s) + 1 blocks of s coefficients (one product per block
+    below the top one, which is a scalar multiple of the identity when s
+    divides p, so that its product falls away)."""
+    best = p - 1  # Horner's rule
+    for s in range(2, min(p, 4) + 1):
+        q, rem = divmod(p, s)
+        best = min(best, (s - 1) + q - (1 if rem == 0 else 0))
+    return best
+
+
+def taylor_select_ps(theta: float, tau: float = 1e-10, p_max: int = 30,
+                     n_max: int = 60) -> tuple:
+    """Global (p, n) for steps evaluated as batched matrix products with
+    Paterson-Stockmeyer Taylor polynomials (Sec. III, the conservative
+    global choice).  Reading: the pair with the fewest evaluated products
+    ps_products(p) + n subject to ``taylor_bound(theta, p, n) <= tau`` and
+    theta / 2^n <= 1 (the series terms do not grow), ties toward fewer
+    squarings, p >= 2."""
+    best = None
+    for n in range(n_max):
+        if theta / 2.0 ** n > 1.0:
+            continue
+        for p in range(2, p_max + 1):
+            if taylor_bound(theta, p, n) <= tau:
+                cost = ps_products(p) + n
+                if best is None or cost < best[0]:
+                    best = (cost, p, n)
+                break
+    if best is None:
+        raise ValueError(f"no (p, n) meets tau={tau} for theta={theta}")
+    return best[1], best[2]
+
+
 def taylor_squaring_expm(A: np.ndarray, p: int, n: int) -> np.ndarray:
     """[sum_{k=0}^p (A/2^n)^k / k!]^(2^n)  (Sec. III, eq. (6)), in FP64."""
     X = A / 2.0 ** n

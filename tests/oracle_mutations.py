@@ -16,6 +16,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 GRAPE = os.path.join(os.path.dirname(HERE), "oracle", "grape.py")
 
 MUTATIONS = {
+    # Paterson-Stockmeyer count: the scalar top block multiplied anyway;
+    # the batched rule on the Horner count
+    "ps_top_block": ("        best = min(best, (s - 1) + q - (1 if rem == 0 else 0))\n",
+                     "        best = min(best, (s - 1) + q)\n"),
+    "ps_rule_horner": ("                cost = ps_products(p) + n\n", "                cost = p - 1 + n\n"),
     # action form: series term without its 1/k, (p, n) rule on matrix
     # products instead of matrix-vector products, no term-growth limit
     "action_term_factorial": ("            term = X @ term / k\n", "            term = X @ term\n"),

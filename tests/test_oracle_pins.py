@@ -490,3 +490,65 @@ def test_action_rule_meets_tolerance_on_a_generator():
         p, n = oracle.action_select(theta, 1e-12)
         err = np.max(np.abs(oracle.taylor_action(-1j * Hs, psi, p, n) - psi @ sla.expm(-1j * Hs).T))
         assert err <= 1e-12
+
+
+# ------------------------------------------------------------ PS product count
+def _ps_counted(X, p, s):
+    """T_p(X) by Paterson-Stockmeyer with block size s, counting the matrix
+    products actually performed (a scalar-identity top block is scaled, not
+    multiplied)."""
+    count = [0]
+
+    def mul(A, B):
+        count[0] += 1
+        return A @ B
+
+    I = np.eye(X.shape[0], dtype=complex)
+    pw = [I, X]
+    for _ in range(2, s + 1):
+        pw.append(mul(pw[-1], X))
+    c = [1.0 / math.factorial(k) for k in range(p + 1)]
+    Q = p // s
+
+    def block(q):
+        return sum(c[q * s + r] * pw[r] for r in range(s) if q * s + r <= p)
+
+    if p % s == 0:  # top block c_p I: its Horner step is a scaling
+        W = block(Q - 1) + c[p] * pw[s]
+        top = Q - 2
+    else:
+        W = block(Q)
+        top = Q - 1
+    for q in range(top, -1, -1):
+        W = block(q) + mul(pw[s], W)
+    return W, count[0]
+
+
+def test_ps_products_counted():
+    rng = np.random.default_rng(40)
+    X = (rng.normal(size=(5, 5)) + 1j * rng.normal(size=(5, 5))) * 0.3
+    for p in range(2, 21):
+        ref = oracle.taylor_squaring_expm(X, p, 0)
+        counts = [p - 1]  # Horner
+        for s in range(2, min(p, 4) + 1):
+            W, k = _ps_counted(X, p, s)
+            assert np.max(np.abs(W - ref)) < 1e-13
+            counts.append(k)
+        assert oracle.ps_products(p) == min(counts), (p, counts)
+
+
+def test_ps_rule_hand_values_and_brute_force():
+    """theta = 0.81: (12, 0) takes 5 products, (9, 1) 4 + 1 (tie: fewer
+    squarings), (8, 2) 4 + 2.  theta = 3: n >= 2; (12, 2) takes 5 + 2,
+    n = 3 needs order 10 (5 + 3)."""
+    assert oracle.taylor_select_ps(0.81, 1e-10) == (12, 0)
+    assert oracle.taylor_select_ps(3.0, 1e-10) == (12, 2)
+    for theta in (1e-3, 0.37, 0.81, 1.0, 3.0, 4.83, 12.0, 70.0):
+        for tau in (1e-10, 1e-15):
+            p, n = oracle.taylor_select_ps(theta, tau)
+            assert oracle.taylor_bound(theta, p, n) <= tau and theta / 2 ** n <= 1.0
+            cost = oracle.ps_products(p) + n
+            for nn in range(0, 12):
+                for pp in range(2, 31):
+                    if oracle.ps_products(pp) + nn < cost and theta / 2 ** nn <= 1.0:
+                        assert oracle.taylor_bound(theta, pp, nn) > tau
