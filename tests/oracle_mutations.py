@@ -26,7 +26,20 @@ MUTATIONS = {
     "action_term_factorial": ("            term = X @ term / k\n", "            term = X @ term\n"),
     "action_rule_products": ("                products = p * 2 ** n\n",
                              "                products = p - 1 + n\n"),
-    "action_rule_growth": ("        if theta / 2.0 ** n > 1.0:\n            continue\n", ""),
+    "action_rule_growth": ("        if theta / 2.0 ** n > 1.0:\n            continue\n"
+                           "        for p in range(2, p_max + 1):\n"
+                           "            if taylor_bound(theta, p, n) <= tau:\n"
+                           "                products = p * 2 ** n\n",
+                           "        for p in range(2, p_max + 1):\n"
+                           "            if taylor_bound(theta, p, n) <= tau:\n"
+                           "                products = p * 2 ** n\n"),
+    "ps_rule_growth": ("        if theta / 2.0 ** n > 1.0:\n            continue\n"
+                       "        for p in range(2, p_max + 1):\n"
+                       "            if taylor_bound(theta, p, n) <= tau:\n"
+                       "                cost = ps_products(p) + n\n",
+                       "        for p in range(2, p_max + 1):\n"
+                       "            if taylor_bound(theta, p, n) <= tau:\n"
+                       "                cost = ps_products(p) + n\n"),
     # exponential: sign of the phase, transposed propagator
     "expm_sign": ("phase = np.exp(-1j * prob.dt * lam)", "phase = np.exp(1j * prob.dt * lam)"),
     "expm_transpose": ("U = (V * phase[:, None, :]) @ np.conj(np.swapaxes(V, 1, 2))",
