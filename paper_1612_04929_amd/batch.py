@@ -81,7 +81,7 @@ class Batch:
         for h in self.handles:
             inf = h.info()
             if inf["d_pad"] >= 32:
-                p, n = qoc.taylor_select(inf["theta_max"] * margin, self.tol)
+                p, n = h.pair_for(inf["theta_max"] * margin)
                 h.set_taylor(p, n)
                 self.pn.append((p, n))
             else:
@@ -179,7 +179,7 @@ class Batch:
             p, n = self.pn[i]
             if (inf["flags"] & qoc.QOC_WARN_TAYLOR) or not taylor_ok(p, n, inf["theta_max"] * ahead,
                                                                     tol):
-                pn = qoc.taylor_select(inf["theta_max"] * margin, tol)
+                pn = h.pair_for(inf["theta_max"] * margin)
                 if pn != (p, n):
                     h.set_taylor(*pn)
                     self.pn[i] = pn

@@ -861,6 +861,69 @@ PsPlan ps_plan(int p) {
   return best;
 }
 
+// Products that evaluate T_p(X) on the batched path: Paterson-Stockmeyer
+// when it takes fewer than Horner's p - 1.
+int batched_products(int p) { return std::min(p - 1, ps_plan(p).cost); }
+
+// The batched path's pair: the fewest evaluated products
+// batched_products(p) + n within the bound, with theta / 2^n <= 1 (the
+// series terms do not grow), ties toward fewer squarings.
+bool taylor_select_ps(double theta, double tol, int *p_out, int *n_out) {
+  int best = -1, bp = 0, bn = 0;
+  for (int n = 0; n < 60; ++n) {
+    if (std::ldexp(theta, -n) > 1.0) continue;
+    if (best >= 0 && n >= best) break;  // n alone already costs as much
+    for (int p = 2; p <= 30; ++p) {
+      if (taylor_bound(theta, p, n) <= tol) {
+        const int c = batched_products(p) + n;
+        if (best < 0 || c < best) {
+          best = c;
+          bp = p;
+          bn = n;
+        }
+        break;
+      }
+    }
+  }
+  if (best < 0) return false;
+  *p_out = bp;
+  *n_out = bn;
+  return true;
+}
+
+// bf16x3 handles under the automatic class policy: the pair whose Taylor
+// products and squarings take the least modelled time, a split product
+// counting kBf3ProductCost of an FP32 one (full-grid products at d = 512:
+// 4.36 ms split against 8.39 ms in FP32), with the classes the policy
+// allows at that pair (fewer squarings raise theta / 2^n and with it the
+// split's error index, so the cheapest pair in products may run unsplit).
+constexpr double kBf3ProductCost = 0.52;
+bool taylor_select_bf3(double theta, double tol, int N, int L, int *p_out, int *n_out) {
+  double best = -1.0;
+  int bp = 0, bn = 0;
+  for (int n = 0; n < 60; ++n) {
+    if (std::ldexp(theta, -n) > 1.0) continue;
+    if (best >= 0.0 && n * kBf3ProductCost >= best) break;
+    for (int p = 2; p <= 30; ++p) {
+      if (taylor_bound(theta, p, n) <= tol) {
+        const int cls = bf3_auto_classes(theta, n, N, L);
+        const double t = batched_products(p) * ((cls & QOC_BF3_TAYLOR) ? kBf3ProductCost : 1.0) +
+                         n * ((cls & QOC_BF3_SQUARING) ? kBf3ProductCost : 1.0);
+        if (best < 0.0 || t < best - 1e-9) {
+          best = t;
+          bp = p;
+          bn = n;
+        }
+        break;
+      }
+    }
+  }
+  if (best < 0.0) return false;
+  *p_out = bp;
+  *n_out = bn;
+  return true;
+}
+
 template <typename T>
 hipError_t taylor_ps(qoc_handle *h, const PsPlan &ps, int p, int nslots, T *X, T *Qa, T *Qb,
                      T *Dl, long lev, long mat, int N, int dp, int bf3, hipStream_t st) {
@@ -1057,7 +1120,11 @@ qoc_status choose_pn_large(qoc_handle *h, const double *u_dev, hipStream_t st,
   std::memcpy(&theta, &tb, sizeof(theta));
   h->last_theta = theta;
   if (!std::isfinite(theta)) return fail(QOC_ERR_NONFINITE, "non-finite step norm");
-  if (!(action ? action_select(theta, h->tol, p, n) : taylor_select(theta, h->tol, p, n)))
+  const bool ok = action ? action_select(theta, h->tol, p, n)
+                  : (h->bf3 && h->bf3_req < 0)
+                      ? taylor_select_bf3(theta, h->tol, h->N, h->L, p, n)
+                      : taylor_select_ps(theta, h->tol, p, n);
+  if (!ok)
     return fail(QOC_ERR_UNSUPPORTED, "no (p, n) meets the tolerance for theta_max = " +
                                          std::to_string(theta));
   return QOC_OK;
@@ -1748,6 +1815,37 @@ qoc_status qoc_taylor_select(double theta, double tol, int *p, int *n) {
   return QOC_OK;
 }
 
+qoc_status qoc_select_pair(double theta, double tol, int form, int *p, int *n) {
+  if (!p || !n) return fail(QOC_ERR_ARG, "null output pointer");
+  if (!(theta >= 0.0) || !std::isfinite(theta) || !(tol > 0.0))
+    return fail(QOC_ERR_ARG, "theta must be finite and >= 0, tol > 0");
+  bool ok;
+  switch (form) {
+    case QOC_FORM_HORNER: ok = taylor_select(theta, tol, p, n); break;
+    case QOC_FORM_BATCHED: ok = taylor_select_ps(theta, tol, p, n); break;
+    case QOC_FORM_ACTION: ok = action_select(theta, tol, p, n); break;
+    default: return fail(QOC_ERR_ARG, "form must be QOC_FORM_HORNER, _BATCHED or _ACTION");
+  }
+  if (!ok) return fail(QOC_ERR_UNSUPPORTED, "no (p, n) meets tol");
+  return QOC_OK;
+}
+
+qoc_status qoc_pair_for(const qoc_handle *h, double theta, int *p, int *n) {
+  if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
+  if (h->prop != QOC_PROP_ACTION && !on_small_path(h) && h->bf3 && h->bf3_req < 0) {
+    if (!p || !n) return fail(QOC_ERR_ARG, "null output pointer");
+    if (!(theta >= 0.0) || !std::isfinite(theta))
+      return fail(QOC_ERR_ARG, "theta must be finite and >= 0");
+    if (!taylor_select_bf3(theta, h->tol, h->N, h->L, p, n))
+      return fail(QOC_ERR_UNSUPPORTED, "no (p, n) meets tol");
+    return QOC_OK;
+  }
+  const int form = h->prop == QOC_PROP_ACTION ? QOC_FORM_ACTION
+                   : on_small_path(h)         ? QOC_FORM_HORNER
+                                              : QOC_FORM_BATCHED;
+  return qoc_select_pair(theta, h->tol, form, p, n);
+}
+
 qoc_status qoc_set_taylor(qoc_handle *h, int p, int n) {
   if (!h) return fail(QOC_ERR_ARG, "handle is NULL");
   if (!(p == 0 || (p >= 2 && p <= 64 && n >= 0 && n <= 60)))
@@ -2147,10 +2245,7 @@ qoc_status qoc_get_info(const qoc_handle *hc, qoc_info *info) {
       h->last_p = pn[0];
       h->last_n = pn[1];
     }
-    const bool small_path =
-        h->prec == QOC_FP64
-            ? (qoc::small_expm_ok<double>(h->dp) && qoc::small_sweep_ok<double>(h->dp, h->S))
-            : (qoc::small_expm_ok<float>(h->dp) && qoc::small_sweep_ok<float>(h->dp, h->S));
+    const bool small_path = h->prop != QOC_PROP_ACTION && on_small_path(h);
     if (small_path && pn[0] >= 2) {
       h->last_p = pn[0];
       h->last_n = pn[1];

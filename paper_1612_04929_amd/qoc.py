@@ -23,6 +23,7 @@ QOC_WARN_DRIFT, QOC_WARN_TAYLOR, QOC_WARN_PRECISION, QOC_WARN_UNITARITY = 1, 2, 
 QOC_WARN_NO_PAIR = 16
 QOC_GRAD_EXACT, QOC_GRAD_FIRST_ORDER = 0, 1
 QOC_PROP_MATRIX, QOC_PROP_ACTION = 0, 1
+QOC_FORM_HORNER, QOC_FORM_BATCHED, QOC_FORM_ACTION = 0, 1, 2
 PROPAGATIONS = {"matrix": QOC_PROP_MATRIX, "action": QOC_PROP_ACTION}
 QOC_BF3_TAYLOR, QOC_BF3_SQUARING, QOC_BF3_BLOCKPROD, QOC_BF3_ADJOINT = 1, 2, 4, 8
 QOC_BF3_ALL = 15
@@ -36,7 +37,7 @@ EXPORTS = ["qoc_create", "qoc_forward", "qoc_cost_grad", "qoc_cost_grad_device",
            "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
            "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
            "qoc_set_bf16x3", "qoc_set_unitarity_check", "qoc_set_structure", "qoc_set_gradient",
-           "qoc_adam_step", "qoc_destroy",
+           "qoc_adam_step", "qoc_select_pair", "qoc_pair_for", "qoc_destroy",
            "qoc_status_string",
            "qoc_last_error", "qoc_version"]
 
@@ -104,6 +105,9 @@ def load(path: str = LIB_PATH):
     lib.qoc_profile_read.argtypes = [vp, _dp, C.POINTER(C.c_longlong), C.c_int]
     lib.qoc_taylor_select.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]
+    lib.qoc_select_pair.argtypes = [C.c_double, C.c_double, C.c_int, C.POINTER(C.c_int),
+                                    C.POINTER(C.c_int)]
+    lib.qoc_pair_for.argtypes = [vp, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.qoc_set_taylor.argtypes = [vp, C.c_int, C.c_int]
     lib.qoc_set_sweep.argtypes = [vp, C.c_int, C.c_int]
     lib.qoc_set_bf16x3.argtypes = [vp, C.c_int]
@@ -122,7 +126,7 @@ def load(path: str = LIB_PATH):
               "qoc_cost_grad_batched", "qoc_get_info", "qoc_profile_enable",
               "qoc_profile_read", "qoc_taylor_select", "qoc_set_taylor", "qoc_set_sweep",
               "qoc_set_bf16x3", "qoc_set_unitarity_check", "qoc_set_structure",
-              "qoc_set_gradient", "qoc_adam_step"]:
+              "qoc_set_gradient", "qoc_adam_step", "qoc_select_pair", "qoc_pair_for"]:
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -141,6 +145,14 @@ def _cplx(a, shape):
 def taylor_select(theta: float, tol: float):
     p, n = C.c_int(), C.c_int()
     _check(load().qoc_taylor_select(float(theta), float(tol), C.byref(p), C.byref(n)))
+    return p.value, n.value
+
+
+def select_pair(theta: float, tol: float, form: int = 0):
+    """(p, n) by the rule of an evaluation form (QOC_FORM_HORNER, _BATCHED,
+    _ACTION)."""
+    p, n = C.c_int(), C.c_int()
+    _check(load().qoc_select_pair(float(theta), float(tol), int(form), C.byref(p), C.byref(n)))
     return p.value, n.value
 
 
@@ -233,6 +245,12 @@ class Problem:
         _check(load().qoc_cost_grad_device_noalloc(self._h, C.c_void_p(u_ptr),
                                                    C.c_void_p(out_ptr), C.c_void_p(grad_ptr),
                                                    C.c_void_p(stream)))
+
+    def pair_for(self, theta: float):
+        """The (p, n) this handle would choose per call at theta_max = theta."""
+        p, n = C.c_int(), C.c_int()
+        _check(load().qoc_pair_for(self._h, float(theta), C.byref(p), C.byref(n)))
+        return p.value, n.value
 
     def set_taylor(self, p: int, n: int = 0):
         """Fix (p, n) for later calls (p = 0: choose per call)."""

@@ -53,6 +53,13 @@ int main() {
   EXPECT(qoc_taylor_select(NAN, 1e-10, &p, &n) == QOC_ERR_ARG);
   EXPECT(qoc_taylor_select(1.0, 0.0, &p, &n) == QOC_ERR_ARG);
   EXPECT(qoc_taylor_select(1.0, 1e-10, nullptr, &n) == QOC_ERR_ARG);
+  for (int form = 0; form < 3; ++form) {
+    EXPECT(qoc_select_pair(0.81, 1e-10, form, &p, &n) == QOC_OK && p >= 2 && n >= 0);
+    EXPECT(qoc_select_pair(-1.0, 1e-10, form, &p, &n) == QOC_ERR_ARG);
+  }
+  EXPECT(qoc_select_pair(0.81, 1e-10, QOC_FORM_BATCHED, &p, &n) == QOC_OK && p == 12 && n == 0);
+  EXPECT(qoc_select_pair(1.0, 1e-10, 7, &p, &n) == QOC_ERR_ARG);
+  EXPECT(qoc_pair_for(nullptr, 1.0, &p, &n) == QOC_ERR_ARG);
   // invalid descriptors
   EXPECT(qoc_create(nullptr, &h) == QOC_ERR_ARG);
   EXPECT(qoc_create(&D, nullptr) == QOC_ERR_ARG);

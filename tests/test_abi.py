@@ -56,6 +56,9 @@ def test_struct_layouts_match_header(tmp_path):
 @pytest.mark.parametrize("tol", [1e-10, 1e-15])
 def test_host_taylor_rule_agrees_with_oracle_reading(theta, tol):
     assert qoc.taylor_select(theta, tol) == oracle.taylor_select(theta, tol)
+    assert qoc.select_pair(theta, tol, qoc.QOC_FORM_HORNER) == oracle.taylor_select(theta, tol)
+    assert qoc.select_pair(theta, tol, qoc.QOC_FORM_BATCHED) == oracle.taylor_select_ps(theta, tol)
+    assert qoc.select_pair(theta, tol, qoc.QOC_FORM_ACTION) == oracle.action_select(theta, tol)
 
 
 def test_taylor_select_rejects_bad_arguments():
@@ -64,6 +67,9 @@ def test_taylor_select_rejects_bad_arguments():
     assert e.value.status == -1
     with pytest.raises(qoc.QocError):
         qoc.taylor_select(1.0, 0.0)
+    with pytest.raises(qoc.QocError) as e:
+        qoc.select_pair(1.0, 1e-10, 3)
+    assert e.value.status == -1
 
 
 def _expect(status, prob, **kw):
