@@ -114,8 +114,8 @@ def taylor_select_ps(theta: float, tau: float = 1e-10, p_max: int = 30,
     Paterson-Stockmeyer Taylor polynomials (Sec. III, the conservative
     global choice).  Reading: the pair with the fewest evaluated products
     ps_products(p) + n subject to ``taylor_bound(theta, p, n) <= tau`` and
-    theta / 2^n <= 1 (the series terms do not grow), ties toward fewer
-    squarings, p >= 2."""
+    theta / 2^n <= 1 (the series terms do not grow), ties toward the lower
+    order p (the exact derivative runs p - 1 reverse Horner stages), p >= 2."""
     best = None
     for n in range(n_max):
         if theta / 2.0 ** n > 1.0:
@@ -123,7 +123,7 @@ def taylor_select_ps(theta: float, tau: float = 1e-10, p_max: int = 30,
         for p in range(2, p_max + 1):
             if taylor_bound(theta, p, n) <= tau:
                 cost = ps_products(p) + n
-                if best is None or cost < best[0]:
+                if best is None or cost < best[0] or (cost == best[0] and p < best[1]):
                     best = (cost, p, n)
                 break
     if best is None:

@@ -21,6 +21,7 @@ MUTATIONS = {
     "ps_top_block": ("        best = min(best, (s - 1) + q - (1 if rem == 0 else 0))\n",
                      "        best = min(best, (s - 1) + q)\n"),
     "ps_rule_horner": ("                cost = ps_products(p) + n\n", "                cost = p - 1 + n\n"),
+    "ps_rule_ties": ("cost < best[0] or (cost == best[0] and p < best[1])", "cost < best[0]"),
     # action form: series term without its 1/k, (p, n) rule on matrix
     # products instead of matrix-vector products, no term-growth limit
     "action_term_factorial": ("            term = X @ term / k\n", "            term = X @ term\n"),

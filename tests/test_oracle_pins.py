@@ -538,10 +538,10 @@ def test_ps_products_counted():
 
 
 def test_ps_rule_hand_values_and_brute_force():
-    """theta = 0.81: (12, 0) takes 5 products, (9, 1) 4 + 1 (tie: fewer
-    squarings), (8, 2) 4 + 2.  theta = 3: n >= 2; (12, 2) takes 5 + 2,
-    n = 3 needs order 10 (5 + 3)."""
-    assert oracle.taylor_select_ps(0.81, 1e-10) == (12, 0)
+    """theta = 0.81: (12, 0) takes 5 products, (9, 1) 4 + 1 (tie: the lower
+    order), (8, 2) 4 + 2.  theta = 3: n >= 2; (12, 2) takes 5 + 2, n = 3
+    needs order 10 (5 + 3)."""
+    assert oracle.taylor_select_ps(0.81, 1e-10) == (9, 1)
     assert oracle.taylor_select_ps(3.0, 1e-10) == (12, 2)
     for theta in (1e-3, 0.37, 0.81, 1.0, 3.0, 4.83, 12.0, 70.0):
         for tau in (1e-10, 1e-15):
@@ -550,5 +550,7 @@ def test_ps_rule_hand_values_and_brute_force():
             cost = oracle.ps_products(p) + n
             for nn in range(0, 12):
                 for pp in range(2, 31):
-                    if oracle.ps_products(pp) + nn < cost and theta / 2 ** nn <= 1.0:
+                    cheaper = oracle.ps_products(pp) + nn < cost
+                    tie_lower = oracle.ps_products(pp) + nn == cost and pp < p
+                    if (cheaper or tie_lower) and theta / 2 ** nn <= 1.0:
                         assert oracle.taylor_bound(theta, pp, nn) > tau
