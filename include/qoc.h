@@ -317,15 +317,16 @@ qoc_status qoc_profile_read(qoc_handle *h, double *ms, long long *calls,
 qoc_status qoc_taylor_select(double theta, double tol, int *p, int *n);
 
 /* The (p, n) rule of each evaluation form (Sec. III's conservative global
- * choice; the bound above throughout, ties to smaller n, p >= 2):
- *   QOC_FORM_HORNER   fewest Horner products p-1+n (the small-d chains;
- *                     the same as qoc_taylor_select)
+ * choice; the bound above throughout, p >= 2):
+ *   QOC_FORM_HORNER   fewest Horner products p-1+n, ties to smaller n (the
+ *                     small-d chains; the same as qoc_taylor_select)
  *   QOC_FORM_BATCHED  fewest evaluated products P(p)+n, P(p) the
  *                     Paterson-Stockmeyer count min over s = 2..4 of
  *                     (s-1) + floor(p/s) - [s divides p], or p-1 when
- *                     smaller, with theta/2^n <= 1 (the batched path)
- *   QOC_FORM_ACTION   fewest matrix-vector products p 2^n, theta/2^n <= 1
- *                     (the action form, Sec. IV)
+ *                     smaller, with theta/2^n <= 1, ties to smaller p (the
+ *                     batched path; the derivative runs p-1 reverse stages)
+ *   QOC_FORM_ACTION   fewest matrix-vector products p 2^n, theta/2^n <= 1,
+ *                     ties to smaller n (the action form, Sec. IV)
  * QOC_ERR_ARG for theta < 0 or not finite, tol <= 0, another form;
  * QOC_ERR_UNSUPPORTED when no pair with p <= 30, n < 60 meets tol. */
 enum { QOC_FORM_HORNER = 0, QOC_FORM_BATCHED = 1, QOC_FORM_ACTION = 2 };
@@ -336,7 +337,8 @@ qoc_status qoc_select_pair(double theta, double tol, int form, int *p, int *n);
  * a graph.  A bf16x3 handle on the batched path under the automatic class
  * policy picks, among the pairs within the bound (theta/2^n <= 1), the one
  * with the least modelled product time, a bf16x3 product counting 0.52 of
- * an FP32 one, with the classes the policy allows at that pair. */
+ * an FP32 one, with the classes the policy allows at that pair (ties to
+ * smaller p). */
 qoc_status qoc_pair_for(const qoc_handle *h, double theta, int *p, int *n);
 
 /* Fix the global (p, n) of later calls on h (p in [2, 64], n in [0, 60]),

@@ -301,8 +301,12 @@ __global__ __launch_bounds__(256) void k_stage32(StageArgs<T> a, long padded) {
   const int i = lane & 15, kk = lane >> 4;
   const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
   v4<T> cr = vzero<T>(), ci = vzero<T>();
-  for (int k0 = 0; k0 < dp; k0 += T32_BK) {
-    // op(A)[r0 .. r0+31][k0 .. k0+15] as As[k][r]; two elements per thread
+  // one chunk's operands, two complex elements of op(A) and of B per
+  // thread: op(A)[r0 .. r0+31][k0 .. k0+15] as As[k][r], B[k0 ..][c0 ..] as
+  // Bs[k][c].  The next chunk is loaded into registers while the current
+  // one is multiplied; the barriers order LDS only.
+  T par[2], pai[2], pbr[2], pbi[2];
+  auto load = [&](int k0) {
     if (OPA == 0) {
       const int r = t >> 3, kq = (t & 7) * 2;
       const bool ok = r0 + r < dp;
@@ -310,8 +314,8 @@ __global__ __launch_bounds__(256) void k_stage32(StageArgs<T> a, long padded) {
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const T vr = Aj[o + q], vi = Aj[plane + o + q];
-        Asr[(kq + q) * T32_LD + r] = ok ? vr : (T)0;
-        Asi[(kq + q) * T32_LD + r] = ok ? vi : (T)0;
+        par[q] = ok ? vr : (T)0;
+        pai[q] = ok ? vi : (T)0;
       }
     } else {
       const int k = t >> 4, rq = (t & 15) * 2;
@@ -320,22 +324,48 @@ __global__ __launch_bounds__(256) void k_stage32(StageArgs<T> a, long padded) {
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const T vr = Aj[o + q], vi = Aj[plane + o + q];
-        Asr[k * T32_LD + rq + q] = ok ? vr : (T)0;
-        Asi[k * T32_LD + rq + q] = ok ? -vi : (T)0;
+        par[q] = ok ? vr : (T)0;
+        pai[q] = ok ? -vi : (T)0;
       }
     }
-    {
-      const int k = t >> 4, cq = (t & 15) * 2;
-      const bool ok = c0 + cq < dp;
-      const long o = ok ? (long)(k0 + k) * dp + c0 + cq : 0;
+    const int k = t >> 4, cq = (t & 15) * 2;
+    const bool ok = c0 + cq < dp;
+    const long o = ok ? (long)(k0 + k) * dp + c0 + cq : 0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const T vr = Bj[o + q], vi = Bj[plane + o + q];
+      pbr[q] = ok ? vr : (T)0;
+      pbi[q] = ok ? vi : (T)0;
+    }
+  };
+  auto store = [&]() {
+    if (OPA == 0) {
+      const int r = t >> 3, kq = (t & 7) * 2;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const T vr = Bj[o + q], vi = Bj[plane + o + q];
-        Bsr[k * T32_LD + cq + q] = ok ? vr : (T)0;
-        Bsi[k * T32_LD + cq + q] = ok ? vi : (T)0;
+        Asr[(kq + q) * T32_LD + r] = par[q];
+        Asi[(kq + q) * T32_LD + r] = pai[q];
+      }
+    } else {
+      const int k = t >> 4, rq = (t & 15) * 2;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        Asr[k * T32_LD + rq + q] = par[q];
+        Asi[k * T32_LD + rq + q] = pai[q];
       }
     }
-    __syncthreads();
+    const int k = t >> 4, cq = (t & 15) * 2;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      Bsr[k * T32_LD + cq + q] = pbr[q];
+      Bsi[k * T32_LD + cq + q] = pbi[q];
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < dp; k0 += T32_BK) {
+    store();
+    lds_barrier();
+    if (k0 + T32_BK < dp) load(k0 + T32_BK);  // block-uniform
 #pragma unroll
     for (int k4 = 0; k4 < T32_BK; k4 += 4) {
       const T ar = Asr[(k4 + kk) * T32_LD + wr + i], ai = Asi[(k4 + kk) * T32_LD + wr + i];
@@ -345,7 +375,7 @@ __global__ __launch_bounds__(256) void k_stage32(StageArgs<T> a, long padded) {
       ci = mfma4(ar, bi, ci);
       ci = mfma4(ai, br, ci);
     }
-    __syncthreads();
+    lds_barrier();
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {

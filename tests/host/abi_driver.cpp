@@ -57,7 +57,7 @@ int main() {
     EXPECT(qoc_select_pair(0.81, 1e-10, form, &p, &n) == QOC_OK && p >= 2 && n >= 0);
     EXPECT(qoc_select_pair(-1.0, 1e-10, form, &p, &n) == QOC_ERR_ARG);
   }
-  EXPECT(qoc_select_pair(0.81, 1e-10, QOC_FORM_BATCHED, &p, &n) == QOC_OK && p == 12 && n == 0);
+  EXPECT(qoc_select_pair(0.81, 1e-10, QOC_FORM_BATCHED, &p, &n) == QOC_OK && p == 9 && n == 1);
   EXPECT(qoc_select_pair(1.0, 1e-10, 7, &p, &n) == QOC_ERR_ARG);
   EXPECT(qoc_pair_for(nullptr, 1.0, &p, &n) == QOC_ERR_ARG);
   // invalid descriptors
