@@ -66,27 +66,42 @@ template <typename T> hipError_t launch_act_values(const ActValArgs<T> &a, hipSt
 template <typename T> struct Cplx;
 template <> struct Cplx<float> { typedef float2 type; };
 template <> struct Cplx<double> { typedef double2 type; };
-template <typename T, int K, int RPT> struct ActRows {
-  int col[RPT][K];
-  T hr[RPT][K], hi[RPT][K];   // values of the current step
-  T nr[RPT][K], ni[RPT][K];   // prefetched values of the next step
-  __device__ __forceinline__ void load_cols(const ActionArgs<T> &a, int t, int nt) {
+template <typename T, int K, int RPT, int TPR> struct ActRows {
+  // TPR consecutive lanes share a row, each holding K / TPR of its slots;
+  // thread t's rows are t / TPR + i nt / TPR
+  static constexpr int KT = K / TPR;
+  int col[RPT][KT];
+  T hr[RPT][KT], hi[RPT][KT];   // values of the current step
+  T nr[RPT][KT], ni[RPT][KT];   // prefetched values of the next step
+  int h, rb, rs;
+  __device__ __forceinline__ void init(int t, int nt) {
+    h = t % TPR;
+    rb = t / TPR;
+    rs = nt / TPR;
+  }
+  __device__ __forceinline__ int row(int i) const { return rb + i * rs; }
+  __device__ __forceinline__ bool lead() const { return h == 0; }
+  __device__ __forceinline__ void load_cols(const ActionArgs<T> &a) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int r = t + i * nt;
+      const int r = row(i);
 #pragma unroll
-      for (int kk = 0; kk < K; ++kk) col[i][kk] = r < a.dp ? a.ecol[kk * a.dp + r] : 0;
+      for (int m = 0; m < KT; ++m) {
+        const int kk = h + TPR * m;
+        col[i][m] = r < a.dp ? a.ecol[kk * a.dp + r] : 0;
+      }
     }
   }
-  __device__ __forceinline__ void prefetch(const ActionArgs<T> &a, long j, int t, int nt) {
+  __device__ __forceinline__ void prefetch(const ActionArgs<T> &a, long j) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int r = t + i * nt;
+      const int r = row(i);
 #pragma unroll
-      for (int kk = 0; kk < K; ++kk) {
-        const T *h = a.hv + (j * K + kk) * 2 * a.dp;
-        nr[i][kk] = r < a.dp ? h[r] : (T)0;
-        ni[i][kk] = r < a.dp ? h[a.dp + r] : (T)0;
+      for (int m = 0; m < KT; ++m) {
+        const int kk = h + TPR * m;
+        const T *hp = a.hv + (j * K + kk) * 2 * a.dp;
+        nr[i][m] = r < a.dp ? hp[r] : (T)0;
+        ni[i][m] = r < a.dp ? hp[a.dp + r] : (T)0;
       }
     }
   }
@@ -94,31 +109,38 @@ template <typename T, int K, int RPT> struct ActRows {
 #pragma unroll
     for (int i = 0; i < RPT; ++i)
 #pragma unroll
-      for (int kk = 0; kk < K; ++kk) {
-        hr[i][kk] = nr[i][kk];
-        hi[i][kk] = ni[i][kk];
+      for (int m = 0; m < KT; ++m) {
+        hr[i][m] = nr[i][m];
+        hi[i][m] = ni[i][m];
       }
   }
-  // (H_j x)_r for the thread's rows, x interleaved complex in LDS
+  // (H_j x)_r for the thread's rows, x interleaved complex in LDS; the
+  // TPR lanes of a row add their partial sums (both hold the result)
   __device__ __forceinline__ void mv(const typename Cplx<T>::type *x, T (&ar)[RPT],
                                      T (&ai)[RPT]) const {
-    typename Cplx<T>::type v[RPT][K];
+    typename Cplx<T>::type v[RPT][KT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i)
 #pragma unroll
-      for (int kk = 0; kk < K; ++kk) v[i][kk] = x[col[i][kk]];
+      for (int m = 0; m < KT; ++m) v[i][m] = x[col[i][m]];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       // two partial sums per component (even / odd slots): half the
       // dependent chain of a row's multiply-adds
       T sr[2] = {0, 0}, si[2] = {0, 0};
 #pragma unroll
-      for (int kk = 0; kk < K; ++kk) {
-        sr[kk & 1] += hr[i][kk] * v[i][kk].x - hi[i][kk] * v[i][kk].y;
-        si[kk & 1] += hr[i][kk] * v[i][kk].y + hi[i][kk] * v[i][kk].x;
+      for (int m = 0; m < KT; ++m) {
+        sr[m & 1] += hr[i][m] * v[i][m].x - hi[i][m] * v[i][m].y;
+        si[m & 1] += hr[i][m] * v[i][m].y + hi[i][m] * v[i][m].x;
       }
-      ar[i] = sr[0] + sr[1];
-      ai[i] = si[0] + si[1];
+      T r0 = sr[0] + sr[1], i0 = si[0] + si[1];
+#pragma unroll
+      for (int o = 1; o < TPR; o <<= 1) {
+        r0 += __shfl_xor(r0, o, 64);
+        i0 += __shfl_xor(i0, o, 64);
+      }
+      ar[i] = r0;
+      ai[i] = i0;
     }
   }
 };
@@ -128,23 +150,24 @@ __device__ __forceinline__ long act_off(const ActionArgs<T> &a, long j, int s, i
   return ((j * a.S + s) * (long)a.P + q) * 2 * a.dp;
 }
 
-template <typename T, int K, int RPT>
-__global__ __launch_bounds__(512) void k_act_fwd(ActionArgs<T> a) {
+template <typename T, int K, int RPT, int TPR>
+__global__ __launch_bounds__(512 * TPR) void k_act_fwd(ActionArgs<T> a) {
   typedef typename Cplx<T>::type C2;
   extern __shared__ unsigned char shraw[];
   C2 *buf = (C2 *)shraw;  // [2 buffers][dp]
   const int s = blockIdx.x, t = threadIdx.x, nt = blockDim.x, dp = a.dp, S = a.S;
   const long set = 2L * S * dp;
-  ActRows<T, K, RPT> R;
-  R.load_cols(a, t, nt);
-  R.prefetch(a, 0, t, nt);
+  ActRows<T, K, RPT, TPR> R;
+  R.init(t, nt);
+  R.load_cols(a);
+  R.prefetch(a, 0);
   T vr[RPT], vi[RPT], wr[RPT], wi[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int r = t + i * nt;
+    const int r = R.row(i);
     vr[i] = r < dp ? a.psi0[(long)s * dp + r] : (T)0;
     vi[i] = r < dp ? a.psi0[(long)(S + s) * dp + r] : (T)0;
-    if (r < dp) {
+    if (r < dp && R.lead()) {
       a.psi_buf[(long)s * dp + r] = vr[i];
       a.psi_buf[(long)(S + s) * dp + r] = vi[i];
     }
@@ -153,7 +176,7 @@ __global__ __launch_bounds__(512) void k_act_fwd(ActionArgs<T> a) {
   const int subs = 1 << a.n;
   for (long j = 0; j < a.N; ++j) {
     R.advance();
-    if (j + 1 < a.N) R.prefetch(a, j + 1, t, nt);
+    if (j + 1 < a.N) R.prefetch(a, j + 1);
     for (int sub = 0; sub < subs; ++sub) {
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
@@ -165,8 +188,8 @@ __global__ __launch_bounds__(512) void k_act_fwd(ActionArgs<T> a) {
         const long off = a.A ? act_off(a, j, s, sub * a.p + (a.p - k)) : 0;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-          const int r = t + i * nt;
-          if (r < dp) {
+          const int r = R.row(i);
+          if (r < dp && R.lead()) {
             C2 v;
             v.x = wr[i];
             v.y = wi[i];
@@ -197,8 +220,8 @@ __global__ __launch_bounds__(512) void k_act_fwd(ActionArgs<T> a) {
     T *o = a.psi_buf + (j + 1) * set;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int r = t + i * nt;
-      if (r < dp) {
+      const int r = R.row(i);
+      if (r < dp && R.lead()) {
         o[(long)s * dp + r] = vr[i];
         o[(long)(S + s) * dp + r] = vi[i];
       }
@@ -206,20 +229,21 @@ __global__ __launch_bounds__(512) void k_act_fwd(ActionArgs<T> a) {
   }
 }
 
-template <typename T, int K, int RPT>
-__global__ __launch_bounds__(512) void k_act_bwd(ActionArgs<T> a) {
+template <typename T, int K, int RPT, int TPR>
+__global__ __launch_bounds__(512 * TPR) void k_act_bwd(ActionArgs<T> a) {
   typedef typename Cplx<T>::type C2;
   extern __shared__ unsigned char shraw[];
   C2 *buf = (C2 *)shraw;
   const int s = blockIdx.x, t = threadIdx.x, nt = blockDim.x, dp = a.dp, S = a.S;
   const long set = 2L * S * dp;
-  ActRows<T, K, RPT> R;
-  R.load_cols(a, t, nt);
-  R.prefetch(a, a.N - 1, t, nt);
+  ActRows<T, K, RPT, TPR> R;
+  R.init(t, nt);
+  R.load_cols(a);
+  R.prefetch(a, a.N - 1);
   T lr[RPT], li[RPT], br[RPT], bi[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int r = t + i * nt;
+    const int r = R.row(i);
     lr[i] = r < dp ? a.lamN[(long)s * dp + r] : (T)0;
     li[i] = r < dp ? a.lamN[(long)(S + s) * dp + r] : (T)0;
   }
@@ -227,12 +251,12 @@ __global__ __launch_bounds__(512) void k_act_bwd(ActionArgs<T> a) {
   const int subs = 1 << a.n;
   for (long j = a.N - 1; j >= 0; --j) {
     R.advance();
-    if (j >= 1) R.prefetch(a, j - 1, t, nt);
+    if (j >= 1) R.prefetch(a, j - 1);
     // the step's own costate source (pw o psi_j + src_j), loaded ahead of use
     T qr[RPT], qi[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int r = t + i * nt;
+      const int r = R.row(i);
       qr[i] = 0;
       qi[i] = 0;
       if (j >= 1 && r < dp) {
@@ -251,8 +275,8 @@ __global__ __launch_bounds__(512) void k_act_bwd(ActionArgs<T> a) {
     T *lb = a.lam_buf + j * set;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int r = t + i * nt;
-      if (r < dp) {
+      const int r = R.row(i);
+      if (r < dp && R.lead()) {
         lb[(long)s * dp + r] = lr[i];
         lb[(long)(S + s) * dp + r] = li[i];
       }
@@ -270,11 +294,11 @@ __global__ __launch_bounds__(512) void k_act_bwd(ActionArgs<T> a) {
         const long off = a.Ybar ? act_off(a, j, s, sub * a.p + (a.p - k)) : 0;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-          const int r = t + i * nt;
+          const int r = R.row(i);
           br[i] += lr[i];
           bi[i] += li[i];
           const T yr = lr[i] * ik, yi = li[i] * ik;
-          if (r < dp) {
+          if (r < dp && R.lead()) {
             C2 v;
             v.x = yr;
             v.y = yi;
@@ -309,14 +333,15 @@ __global__ __launch_bounds__(512) void k_act_bwd(ActionArgs<T> a) {
   }
 }
 
-template <typename T, int K, int RPT>
+template <typename T, int K, int RPT, int TPR = 1>
 hipError_t act_chain(int which, const ActionArgs<T> &a, hipStream_t st) {
-  const int nt = a.dp <= 512 ? std::max(64, (a.dp + 63) / 64 * 64) : 512;
+  const int rows = (a.dp + RPT - 1) / RPT;
+  const int nt = std::max(64, (TPR * rows + 63) / 64 * 64);
   const size_t sh = 4 * (size_t)a.dp * sizeof(T);  // two buffers of dp complex
   if (which == 0)
-    hipLaunchKernelGGL((k_act_fwd<T, K, RPT>), dim3(a.S), dim3(nt), sh, st, a);
+    hipLaunchKernelGGL((k_act_fwd<T, K, RPT, TPR>), dim3(a.S), dim3(nt), sh, st, a);
   else
-    hipLaunchKernelGGL((k_act_bwd<T, K, RPT>), dim3(a.S), dim3(nt), sh, st, a);
+    hipLaunchKernelGGL((k_act_bwd<T, K, RPT, TPR>), dim3(a.S), dim3(nt), sh, st, a);
   return hipGetLastError();
 }
 
@@ -331,13 +356,33 @@ template <typename T> hipError_t launch_act_chain(int which, const ActionArgs<T>
   if (!act_shape_ok<T>(a.dp, a.K)) return hipErrorInvalidValue;
   const bool two = a.dp > 512;
   if constexpr (std::is_same<T, float>::value) {
+    // lanes per row: the most that keep a padded d <= 32 within one
+    // wavefront (more lanes per row shorten each product's dependent chain;
+    // beyond one wavefront the wider barrier costs more, measured at
+    // padded d 512: 16.2 against 14.0 ms per call with two lanes)
+    const int tpr = (a.dp <= 16 && a.K >= 8) ? 4 : (a.dp <= 32 ? 2 : 1);
     switch (a.K) {
-      case 4: return two ? act_chain<T, 4, 2>(which, a, st) : act_chain<T, 4, 1>(which, a, st);
-      case 8: return two ? act_chain<T, 8, 2>(which, a, st) : act_chain<T, 8, 1>(which, a, st);
-      case 12: return two ? act_chain<T, 12, 2>(which, a, st) : act_chain<T, 12, 1>(which, a, st);
-      case 16: return two ? act_chain<T, 16, 2>(which, a, st) : act_chain<T, 16, 1>(which, a, st);
-      case 24: return act_chain<T, 24, 1>(which, a, st);
-      case 32: return act_chain<T, 32, 1>(which, a, st);
+      case 4:
+        if (tpr >= 2) return act_chain<T, 4, 1, 2>(which, a, st);
+        return two ? act_chain<T, 4, 2>(which, a, st) : act_chain<T, 4, 1>(which, a, st);
+      case 8:
+        if (tpr == 4) return act_chain<T, 8, 1, 4>(which, a, st);
+        if (tpr == 2) return act_chain<T, 8, 1, 2>(which, a, st);
+        return two ? act_chain<T, 8, 2>(which, a, st) : act_chain<T, 8, 1>(which, a, st);
+      case 12:
+        if (tpr == 4) return act_chain<T, 12, 1, 4>(which, a, st);
+        if (tpr == 2) return act_chain<T, 12, 1, 2>(which, a, st);
+        return two ? act_chain<T, 12, 2>(which, a, st) : act_chain<T, 12, 1>(which, a, st);
+      case 16:
+        if (tpr == 4) return act_chain<T, 16, 1, 4>(which, a, st);
+        if (tpr == 2) return act_chain<T, 16, 1, 2>(which, a, st);
+        return two ? act_chain<T, 16, 2>(which, a, st) : act_chain<T, 16, 1>(which, a, st);
+      case 24:
+        if (tpr >= 2) return act_chain<T, 24, 1, 2>(which, a, st);
+        return act_chain<T, 24, 1>(which, a, st);
+      case 32:
+        if (tpr >= 2) return act_chain<T, 32, 1, 2>(which, a, st);
+        return act_chain<T, 32, 1>(which, a, st);
     }
   } else {
     switch (a.K) {
