@@ -3,7 +3,8 @@ qoc_cost_grad_device through the C ABI: the same cost, penalties and
 gradient, bit for bit (the same kernels on the same inputs; only where the
 per-call work space lives differs), on two calls in a row of which the
 second has a smaller input, and for several paths (padded d 16, a small
-chain at padded d 48, a batched large-d chain with a fixed pair); a call
+chain at padded d 48, a batched large-d chain with a fixed pair, the
+memory-lean mode's time segments, the action form); a call
 whose work space exceeds the static scratch is rejected with
 QOC_ERR_UNSUPPORTED."""
 import sys
@@ -23,13 +24,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-def run_both(prob, precision="fp32", taylor_pn=None):
+def run_both(prob, precision="fp32", **kw):
     dev = torch.device("cuda:0")
     st = torch.cuda.current_stream(dev).cuda_stream
     u = torch.from_numpy(np.ascontiguousarray(prob.u)).to(dev)
     res = []
     for noalloc in (False, True):
-        h = qoc.Problem(prob, precision=precision, taylor_pn=taylor_pn)
+        h = qoc.Problem(prob, precision=precision, **kw)
         out = torch.full((2 + prob.N,), float("nan"), dtype=torch.float64, device=dev)
         grad = torch.full((max(1, prob.M * prob.N),), float("nan"), dtype=torch.float64,
                           device=dev)
@@ -41,7 +42,7 @@ def run_both(prob, precision="fp32", taylor_pn=None):
     return res
 
 
-@pytest.mark.parametrize("case", ["d16", "d40", "d64_fixed"])
+@pytest.mark.parametrize("case", ["d16", "d40", "d64_fixed", "d70_segments", "action"])
 def test_noalloc_matches_device_entry_point_twice(case):
     rng = np.random.default_rng(900)
     if case == "d16":
@@ -51,10 +52,20 @@ def test_noalloc_matches_device_entry_point_twice(case):
         big = workloads.random_problem(rng, d=40, M=3, N=120, S=3, dt=0.2, scale=1.5)
         small = workloads.random_problem(rng, d=20, M=2, N=33, S=2, dt=0.2, scale=1.5)
         kw = {}
-    else:
+    elif case == "d64_fixed":
         big = workloads.random_problem(rng, d=64, M=3, N=90, S=2, dt=0.2, scale=1.5)
         small = workloads.random_problem(rng, d=64, M=2, N=40, S=2, dt=0.2, scale=1.5)
         kw = dict(taylor_pn=(9, 2))
+    elif case == "d70_segments":
+        # memory-lean mode: the segment's stacks carved from the scratch
+        big = workloads.random_problem(rng, d=70, M=3, N=96, S=2, dt=0.2, scale=1.5)
+        small = workloads.random_problem(rng, d=70, M=2, N=41, S=1, dt=0.2, scale=1.5)
+        kw = dict(taylor_pn=(9, 2), checkpoint_every=8, segment_steps=24)
+    else:
+        # action form: the kept product inputs and cotangents in the scratch
+        big = workloads.sparse_problem(rng, 90, 3, 80, 2, dt=0.15)
+        small = workloads.sparse_problem(rng, 90, 2, 30, 1, dt=0.15)
+        kw = dict(propagation="action")
     for prob in (big, small):
         say(f"[noalloc] {case}: d={prob.d} M={prob.M} N={prob.N} S={prob.S}")
         (o1, g1), (o2, g2) = run_both(prob, **kw)
