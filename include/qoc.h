@@ -415,7 +415,9 @@ qoc_status qoc_set_unitarity_check(qoc_handle *h, int stride);
  * 2 one launch per step spread over many workgroups (padded d >= 80),
  * 3 a four-wavefront workgroup per block with the step matrices staged in
  * LDS (padded d <= 64), 4 one workgroup of 8 d_pad threads per block with
- * a register prefetch ring of matrix slices (FP32, padded d 64 .. 128).  A
+ * a register prefetch ring of matrix slices (FP32, padded d 64 .. 128), 5
+ * one launch per step with the products on the MFMA (16-row x 16-state
+ * tiles; padded d >= 80).  A
  * variant that does not apply falls back to the automatic choice.  Sec. II,
  * eqs. 2-4 (the sequential product of propagators). */
 qoc_status qoc_set_sweep(qoc_handle *h, int which, int variant);

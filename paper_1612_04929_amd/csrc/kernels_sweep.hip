@@ -762,6 +762,113 @@ template <typename T> __global__ __launch_bounds__(256) void k_wide_adj(SweepArg
   }
 }
 
+// ------------------------------------------------------------------ wide, MFMA
+// The same per-step products as thin matrix products on the MFMA (sweep
+// variant 5): Y = X + op(M) X (+ addend) with the state set X (S x d_pad,
+// state-major) taken as the d_pad x S panel X^T.  A workgroup owns 16
+// output rows and 16 states; its 4 wavefronts split the inner dimension in
+// quarters and multiply straight from global memory (no LDS staging: each
+// lane reads 16-byte vectors of 4 consecutive inner indices, and the inner
+// index of MFMA step q at lane group kk is 4 kk + q so that both operands
+// come from those vectors), then meet in LDS.  Small tiles put the
+// sequential chain's per-step matrix read on many compute units.
+template <typename T>
+__device__ __forceinline__ void wm_vec4(const T *p, T (&v)[4]) {
+  typedef typename Vec16<T>::type V;
+  if constexpr (Vec16<T>::n == 4) {
+    const V x = *reinterpret_cast<const V *>(p);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = vget<T>(x, e);
+  } else {
+    const V x0 = *reinterpret_cast<const V *>(p), x1 = *reinterpret_cast<const V *>(p + 2);
+    v[0] = vget<T>(x0, 0);
+    v[1] = vget<T>(x0, 1);
+    v[2] = vget<T>(x1, 0);
+    v[3] = vget<T>(x1, 1);
+  }
+}
+
+template <typename T, int OPA>
+__global__ __launch_bounds__(256) void k_wide_mm(SweepArgs<T> a, WideStep<T> w) {
+  __shared__ T red[4][2][4][64];  // [wave][re, im][acc element][lane]
+  const T *D, *X, *add;
+  T *Y;
+  bool addw;
+  if (!wide_job(a, w, blockIdx.y, D, X, Y, add, addw)) return;  // block-uniform
+  const int dp = a.dp, S = a.S;
+  const long plane = (long)dp * dp;
+  const int rt = dp / 16;
+  const int r0 = (blockIdx.x % rt) * 16, s0 = (blockIdx.x / rt) * 16;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  const int kq = dp / 4, kb = wv * kq, ke = kb + kq;  // this wavefront's inner range
+  const bool sok = s0 + i < S;
+  const long xo = sok ? (long)(s0 + i) * dp : 0;  // state row (index 0 if none)
+  v4<T> cr = vzero<T>(), ci = vzero<T>();
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    // this lane's 4 inner indices k .. k+3 (a quarter of dp is a multiple of
+    // 4, not always of 16: lanes past the range read at its start, add zero)
+    const bool kok = k0 + 4 * kk < ke;
+    const int k = kok ? k0 + 4 * kk : kb;
+    T ar[4], ai[4], br[4], bi[4];
+    if (OPA == 0) {  // M[r0 + i][k .. k+3]
+      wm_vec4<T>(D + (long)(r0 + i) * dp + k, ar);
+      wm_vec4<T>(D + plane + (long)(r0 + i) * dp + k, ai);
+    } else {  // conj(M[k .. k+3][r0 + i])
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ar[q] = D[(long)(k + q) * dp + r0 + i];
+        ai[q] = -D[plane + (long)(k + q) * dp + r0 + i];
+      }
+    }
+    wm_vec4<T>(X + xo + k, br);
+    wm_vec4<T>(X + (long)S * dp + xo + k, bi);
+    if (!sok || !kok) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        br[q] = 0;
+        bi[q] = 0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cr = mfma4(ar[q], br[q], cr);
+      cr = mfma4(-ai[q], bi[q], cr);
+      ci = mfma4(ar[q], bi[q], ci);
+      ci = mfma4(ai[q], br[q], ci);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    red[wv][0][v][lane] = cr[v];
+    red[wv][1][v][lane] = ci[v];
+  }
+  __syncthreads();
+  if (wv != 0) return;
+  // y[s][m] = x[s][m] + (op(M) x^s)[m] (+ mu, or pw o psi, by mode)
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int m = r0 + acc_row<T>(lane, v), sidx = s0 + (lane & 15);
+    if (sidx >= S) continue;
+    const T sr = red[0][0][v][lane] + red[1][0][v][lane] + red[2][0][v][lane] + red[3][0][v][lane];
+    const T si = red[0][1][v][lane] + red[1][1][v][lane] + red[2][1][v][lane] + red[3][1][v][lane];
+    const long o = (long)sidx * dp + m, oi = (long)S * dp + o;
+    T vr = X[o] + sr, vi = X[oi] + si;
+    if (add) {
+      if (w.mode == 3) {
+        vr += add[o];
+        vi += add[oi];
+      } else if (addw) {
+        const T wg = a.pw[m];
+        vr += wg * add[o];
+        vi += wg * add[oi];
+      }
+    }
+    Y[o] = vr;
+    Y[oi] = vi;
+  }
+}
+
 template <typename T> bool wide_sweep_ok(int dp, int S) {
   (void)S;
   return dp >= 80;
@@ -770,13 +877,27 @@ template <typename T> bool wide_sweep_ok(int dp, int S) {
 // The four sweeps of the blocked scan as per-step launches.  Scratch: the
 // F3mu ping-pong partner of mu uses lam_buf (free until B3).
 template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T> &a,
-                                                   hipStream_t st) {
+                                                   hipStream_t st, bool mm) {
   const int SW = wide_sw<T>(a.dp);
+  // MFMA variant: 16-row x 16-state tiles
+  const unsigned mmg = (unsigned)((a.dp / 16) * ((a.S + 15) / 16));
+  auto fwd = [&](const WideStep<T> &w, unsigned gy) -> hipError_t {
+    if (mm)
+      hipLaunchKernelGGL((k_wide_mm<T, 0>), dim3(mmg, gy), dim3(256), 0, st, a, w);
+    else
+      hipLaunchKernelGGL(k_wide_fwd<T>, dim3((unsigned)((a.dp + 4 * WR_ROWS - 1) / (4 * WR_ROWS)), gy),
+                         dim3(256), 2 * SW * a.dp * sizeof(T), st, a, w);
+    return hipGetLastError();
+  };
+  auto adj = [&](const WideStep<T> &w, unsigned gy) -> hipError_t {
+    if (mm)
+      hipLaunchKernelGGL((k_wide_mm<T, 1>), dim3(mmg, gy), dim3(256), 0, st, a, w);
+    else
+      hipLaunchKernelGGL(k_wide_adj<T>, dim3((unsigned)((a.dp + 63) / 64), gy), dim3(256),
+                         2 * SW * a.dp * sizeof(T) + 4 * 2 * SW * 64 * sizeof(T), st, a, w);
+    return hipGetLastError();
+  };
   const long set = 2L * a.S * a.dp;
-  const size_t shf = 2 * SW * a.dp * sizeof(T);
-  const size_t sha = shf + 4 * 2 * SW * 64 * sizeof(T);
-  const unsigned rowg = (unsigned)((a.dp + 4 * WR_ROWS - 1) / (4 * WR_ROWS));
-  const unsigned colg = (unsigned)((a.dp + 63) / 64);
   const int Lmax = a.nb > 1 ? a.L : a.N;  // longest block
   hipError_t e;
   WideStep<T> w{};
@@ -787,8 +908,7 @@ template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T>
       for (int b = 0; b < a.nb; ++b) {
         w.mode = 0;
         w.t = b;
-        hipLaunchKernelGGL(k_wide_fwd<T>, dim3(rowg, 1), dim3(256), shf, st, a, w);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = fwd(w, 1)) != hipSuccess) return e;
       }
       return hipSuccess;
     case 1: {  // F3: block starts from the checkpoints, then every offset
@@ -799,8 +919,7 @@ template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T>
       for (int t = 0; t < Lmax; ++t) {
         w.mode = 1;
         w.t = t;
-        hipLaunchKernelGGL(k_wide_fwd<T>, dim3(rowg, a.nb), dim3(256), shf, st, a, w);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = fwd(w, a.nb)) != hipSuccess) return e;
       }
       if (!a.pw) return hipSuccess;
       // block-local penalty costates, from zero at each block end
@@ -813,8 +932,7 @@ template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T>
         w.t = t;
         w.mu_out = bufs[t & 1];
         w.mu_in = bufs[(t + 1) & 1];
-        hipLaunchKernelGGL(k_wide_adj<T>, dim3(colg, a.nb), dim3(256), sha, st, a, w);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = adj(w, a.nb)) != hipSuccess) return e;
       }
       return hipSuccess;
     }
@@ -822,8 +940,7 @@ template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T>
       for (int b = a.nb - 1; b >= 1; --b) {
         w.mode = 3;
         w.t = b;
-        hipLaunchKernelGGL(k_wide_adj<T>, dim3(colg, 1), dim3(256), sha, st, a, w);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = adj(w, 1)) != hipSuccess) return e;
       }
       return hipSuccess;
     default: {  // B3: lam_buf[end-1] = lambda_end, then every offset downwards
@@ -836,8 +953,7 @@ template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T>
       for (int t = Lmax - 1; t >= 1; --t) {
         w.mode = 4;
         w.t = t;
-        hipLaunchKernelGGL(k_wide_adj<T>, dim3(colg, a.nb), dim3(256), sha, st, a, w);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = adj(w, a.nb)) != hipSuccess) return e;
       }
       return hipSuccess;
     }
@@ -864,7 +980,7 @@ template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStre
 
 #define QOC_INST(T)                                                                   \
   template bool wide_sweep_ok<T>(int, int);                                           \
-  template hipError_t launch_wide_sweep<T>(int, const SweepArgs<T> &, hipStream_t);   \
+  template hipError_t launch_wide_sweep<T>(int, const SweepArgs<T> &, hipStream_t, bool); \
   template hipError_t launch_fwd_blocks<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_seg_lambda<T>(const SweepArgs<T> &, hipStream_t);       \
   template hipError_t launch_fwd_replay<T>(const SweepArgs<T> &, hipStream_t);       \

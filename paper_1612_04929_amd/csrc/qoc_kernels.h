@@ -223,7 +223,9 @@ template <typename T> hipError_t launch_chain_sweep(int which, const SweepArgs<T
 // Large padded d (>= 80): the sweeps as per-step launches spread over many
 // workgroups.  which: 0 = F2, 1 = F3, 2 = B2, 3 = B3.
 template <typename T> bool wide_sweep_ok(int dp, int S);
-template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T> &a, hipStream_t st);
+// mm: the products on the MFMA (16-row x 16-state tiles), else on the VALU.
+template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T> &a, hipStream_t st,
+                                                   bool mm = false);
 // One launch: per-step penalties c_j (FP64) and norm drift partials,
 // parallel over steps, beside the fidelity, C_fid and lambda_N (one
 // workgroup; needs the final states only).  npart + 1 workgroups.

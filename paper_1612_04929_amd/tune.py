@@ -17,7 +17,8 @@ on the number of columns in ways that launch overheads, occupancy and
 cache reuse decide, so the interval and the kernel variant of each sweep
 are chosen by timing them on the problem itself: for every candidate L a
 handle is built, each sweep is timed in the applicable variants (padded
-d >= 80: per-block workgroups or per-step launches; smaller d: one
+d >= 80: per-block workgroups or per-step launches with the products on
+the VALU or on the MFMA; smaller d: one
 wavefront or a four-wavefront LDS-staged workgroup; FP32 padded d 64 ..
 128 also one 8 d_pad-thread chain workgroup per block; padded d 16 also
 longer blocks, whose in-block passes run over sub-blocks) with the library's
@@ -143,7 +144,7 @@ def tune(prob, precision="fp32", intervals=None, reps=3, device=0, **kw):
         h = Problem(prob, precision=precision, checkpoint_every=L, device=device, **kw)
         times = {}
         dp = h.info()["d_pad"]
-        variants = (1, 2) if dp >= 80 else (1, 3)
+        variants = (1, 2, 5) if dp >= 80 else (1, 3)
         if precision != "fp64" and 64 <= dp <= 128:
             variants += (4,)  # chain workgroups (FP32 chains)
         for variant in variants:

@@ -17,7 +17,8 @@ def say(*a):
 
 
 @pytest.mark.parametrize("d,S,variant", [(100, 2, 1), (100, 2, 2), (12, 4, 1), (12, 4, 3),
-                                         (40, 3, 3)])
+                                         (40, 3, 3), (100, 2, 5),
+                                         (260, 18, 5)])  # ragged row tile, two state tiles
 def test_sweep_variants_match_oracle(d, S, variant):
     rng = np.random.default_rng(23 + d)
     p = workloads.random_problem(rng, d=d, M=2, N=70, S=S, dt=0.25, scale=1.5)
@@ -33,6 +34,25 @@ def test_sweep_variants_match_oracle(d, S, variant):
     rel = np.linalg.norm(out["grad"] - ref["grad"]) / np.linalg.norm(ref["grad"])
     say(f"[tune] variant {variant}: dF={dF:.2e} grad_rel={rel:.2e}")
     assert dF <= 1e-6 and rel <= 1e-4
+
+
+def test_mfma_sweeps_fp64_match_oracle():
+    """Sweep variant 5 (per-step launches, products on the FP64 MFMA) in
+    FP64 chains, with the level penalty (block-local penalty costates)."""
+    rng = np.random.default_rng(31)
+    p = workloads.random_problem(rng, d=100, M=2, N=60, S=3, dt=0.25, scale=1.5)
+    from paper_1612_04929_amd import qoc
+    import oracle
+    ref = oracle.cost_grad(p)
+    h = qoc.Problem(p, precision="fp64", checkpoint_every=8)
+    h.set_sweep(-1, 5)
+    out = h.cost_grad(p.u)
+    h.close()
+    dF = abs((1 - out["C_fid"]) - ref["F"])
+    rel = np.linalg.norm(out["grad"] - ref["grad"]) / np.linalg.norm(ref["grad"])
+    say(f"[tune] fp64 variant 5: dF={dF:.2e} grad_rel={rel:.2e}")
+    assert dF <= 1e-11 and rel <= 1e-9
+    assert np.max(np.abs(out["c"] - ref["c"])) <= 1e-11
 
 
 def test_tuned_configuration_matches_oracle():
