@@ -911,11 +911,10 @@ template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T>
         if ((e = fwd(w, 1)) != hipSuccess) return e;
       }
       return hipSuccess;
-    case 1: {  // F3: block starts from the checkpoints, then every offset
-      for (int b = 0; b < a.nb; ++b)
-        if ((e = launch_copy<T>(a.psi_buf + (long)b * a.L * set, a.ckpt + (long)b * set, set,
-                                st)) != hipSuccess)
-          return e;
+    case 1: {  // F3: block starts from the checkpoints (one strided copy), then every offset
+      if ((e = launch_copy_strided<T>(a.psi_buf, (long)a.L * set, a.ckpt, set, set, a.nb, st)) !=
+          hipSuccess)
+        return e;
       for (int t = 0; t < Lmax; ++t) {
         w.mode = 1;
         w.t = t;
@@ -943,13 +942,16 @@ template <typename T> hipError_t launch_wide_sweep(int which, const SweepArgs<T>
         if ((e = adj(w, 1)) != hipSuccess) return e;
       }
       return hipSuccess;
-    default: {  // B3: lam_buf[end-1] = lambda_end, then every offset downwards
-      for (int b = 0; b < a.nb; ++b) {
-        const int end = std::min(a.N, (b + 1) * a.L);
-        if ((e = launch_copy<T>(a.lam_buf + (long)(end - 1) * set,
-                                a.lam_ckpt + (long)(b + 1) * set, set, st)) != hipSuccess)
-          return e;
-      }
+    default: {  // B3: lam_buf[end-1] = lambda_end (the full blocks in one strided copy), then every offset downwards
+      const int full = a.N / a.L;  // blocks of length L; a ragged last one apart
+      if (full > 0 &&
+          (e = launch_copy_strided<T>(a.lam_buf + (long)(a.L - 1) * set, (long)a.L * set,
+                                      a.lam_ckpt + set, set, set, full, st)) != hipSuccess)
+        return e;
+      if (full < a.nb &&
+          (e = launch_copy<T>(a.lam_buf + (long)(a.N - 1) * set, a.lam_ckpt + (long)a.nb * set,
+                              set, st)) != hipSuccess)
+        return e;
       for (int t = Lmax - 1; t >= 1; --t) {
         w.mode = 4;
         w.t = t;
