@@ -37,9 +37,14 @@ __device__ __forceinline__ void wg_tile(CView<const T> A, CView<const T> B, int 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int i = lane & 15, kk = lane >> 4;
   const bool wave_on = r0 + 16 * w < rows;
-  for (int k0 = 0; k0 < K; k0 += BG_BK) {
-    // ---- stage op(A)[r0 .. r0+63][k0 .. k0+15] as As[k][r]; rows of op(A)
-    // beyond `rows` read index 0 (a valid address) and store zero
+  // one chunk's operands in registers (4 elements of op(A), TN / 16 of
+  // op(B) per thread): the next chunk is loaded while the current one is
+  // multiplied, and the barriers order LDS only
+  constexpr int NB = TN / 16;
+  T par[4], pai[4], pbr[NB], pbi[NB];
+  auto load = [&](int k0) {
+    // op(A)[r0 .. r0+63][k0 .. k0+15]; rows of op(A) beyond `rows` read
+    // index 0 (a valid address) and hold zero
     if (OPA == 0) {
       const int r = t >> 2, kq = (t & 3) * 4;
       const bool ok = r0 + r < rows;
@@ -47,8 +52,8 @@ __device__ __forceinline__ void wg_tile(CView<const T> A, CView<const T> B, int 
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const T vr = A.re[o + q], vi = A.im[o + q];
-        L.ar[(kq + q) * BG_LDA + r] = ok ? vr : (T)0;
-        L.ai[(kq + q) * BG_LDA + r] = ok ? vi : (T)0;
+        par[q] = ok ? vr : (T)0;
+        pai[q] = ok ? vi : (T)0;
       }
     } else {
       const int k = t >> 4, rq = (t & 15) * 4;
@@ -57,28 +62,66 @@ __device__ __forceinline__ void wg_tile(CView<const T> A, CView<const T> B, int 
         const bool ok = r0 + rq + q < rows;
         const long o = ok ? (long)(k0 + k) * A.ld + r0 + rq + q : 0;
         const T vr = A.re[o], vi = A.im[o];
-        L.ar[k * BG_LDA + rq + q] = ok ? vr : (T)0;
-        L.ai[k * BG_LDA + rq + q] = ok ? -vi : (T)0;
+        par[q] = ok ? vr : (T)0;
+        pai[q] = ok ? -vi : (T)0;
       }
     }
-    // ---- stage op(B)[k0 .. k0+15][c0 .. c0+TN-1] as Bs[k][c]; for op = ^H the
-    // rows of B beyond `rows` read index 0 and store zero
-    for (int e = t; e < BG_BK * TN; e += 256) {
+    // op(B)[k0 .. k0+15][c0 .. c0+TN-1]; for op = ^H the rows of B beyond
+    // `rows` read index 0 and hold zero
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = t + 256 * q;
       if (OPB == 0) {
         const int k = e / TN, c = e - (e / TN) * TN;
         const long o = (long)(k0 + k) * B.ld + c0 + c;
-        L.br[k * BG_LDB + c] = B.re[o];
-        L.bi[k * BG_LDB + c] = B.im[o];
+        pbr[q] = B.re[o];
+        pbi[q] = B.im[o];
       } else {
         const int c = e / BG_BK, k = e - (e / BG_BK) * BG_BK;
         const bool ok = c0 + c < rows;
         const long o = ok ? (long)(c0 + c) * B.ld + k0 + k : 0;
         const T vr = B.re[o], vi = B.im[o];
-        L.br[k * BG_LDB + c] = ok ? vr : (T)0;
-        L.bi[k * BG_LDB + c] = ok ? -vi : (T)0;
+        pbr[q] = ok ? vr : (T)0;
+        pbi[q] = ok ? -vi : (T)0;
       }
     }
-    __syncthreads();
+  };
+  auto store = [&]() {  // op(A) as As[k][r], op(B) as Bs[k][c]
+    if (OPA == 0) {
+      const int r = t >> 2, kq = (t & 3) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        L.ar[(kq + q) * BG_LDA + r] = par[q];
+        L.ai[(kq + q) * BG_LDA + r] = pai[q];
+      }
+    } else {
+      const int k = t >> 4, rq = (t & 15) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        L.ar[k * BG_LDA + rq + q] = par[q];
+        L.ai[k * BG_LDA + rq + q] = pai[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = t + 256 * q;
+      int k, c;
+      if (OPB == 0) {
+        k = e / TN;
+        c = e - k * TN;
+      } else {
+        c = e / BG_BK;
+        k = e - c * BG_BK;
+      }
+      L.br[k * BG_LDB + c] = pbr[q];
+      L.bi[k * BG_LDB + c] = pbi[q];
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += BG_BK) {
+    store();
+    lds_barrier();
+    if (k0 + BG_BK < K) load(k0 + BG_BK);  // block-uniform
     if (wave_on) {
 #pragma unroll
       for (int k4 = 0; k4 < BG_BK; k4 += 4) {
@@ -95,7 +138,7 @@ __device__ __forceinline__ void wg_tile(CView<const T> A, CView<const T> B, int 
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
