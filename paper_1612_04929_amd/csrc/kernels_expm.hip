@@ -198,6 +198,88 @@ __device__ __forceinline__ void stage_store_n(const StageArgs<T> &a, long j, con
   }
 }
 
+// The epilogue of a 64 x 64 output tile through LDS: each plane of the
+// accumulators is written to LDS in the MFMA layout (wave w holds rows
+// 32 (w >> 1) + 16 m + acc_row, columns 32 (w & 1) + 16 n + lane % 16), then
+// every thread takes four rows of four consecutive columns, so the addends
+// are read and the outputs written as 16-byte vectors, 256 bytes per row
+// segment, and all addend loads of a row are issued before its stores.  The
+// coefficients are real, so the planes are independent.  sm must hold
+// 64 x 68 elements; all 256 threads must call.
+constexpr int EP_LD = 64 + 4;  // row stride: conflict-free writes in the MFMA layout
+
+template <typename T>
+__device__ __forceinline__ void st4(T *p, const T (&v)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+    *(double2 *)p = make_double2(v[0], v[1]);
+    *(double2 *)(p + 2) = make_double2(v[2], v[3]);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_epilogue64(const StageArgs<T> &a, long j, int r0, int c0,
+                                                 T *sm, const v4<T> (&acc)[2][2][2]) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const long plane = (long)a.dp * a.dp;
+  const bool needA = a.betaA != (T)0 || (a.C2 && a.c2A != (T)0);
+  const bool needB = a.betaB != (T)0 || (a.C2 && a.c2B != (T)0);
+  const T *Aj = a.A + moff(a, j, a.strideA, a.segA), *Bj = a.B + moff(a, j, a.strideB, a.segB);
+  const long oc = moff(a, j, a.strideC, a.segC);
+  T *Cj = a.C + oc;
+  T *C2j = a.C2 ? a.C2 + oc : nullptr;
+  const int rr = t >> 4, cc = 4 * (t & 15);  // rows rr + 16 q, columns cc .. cc + 3
+#pragma unroll
+  for (int pl = 0; pl < 2; ++pl) {
+    __syncthreads();  // the previous use of sm is done
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          sm[(wr + 16 * m + acc_row<T>(lane, v)) * EP_LD + wc + 16 * n + (lane & 15)] =
+              acc[m][n][pl][v];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = rr + 16 * q;
+      const long o = pl * plane + (long)(r0 + row) * a.dp + c0 + cc;
+      T p[4], va[4] = {0, 0, 0, 0}, vb[4] = {0, 0, 0, 0}, x[3][4];
+      ld4(sm + row * EP_LD + cc, p);
+      if (needA) ld4(Aj + o, va);
+      if (needB) ld4(Bj + o, vb);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (k < a.nx) {
+          ld4(a.xadd[k] + oc + o, x[k]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x[k][e] = 0;
+        }
+      }
+      T c[4], c2[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool diag = pl == 0 && r0 + row == c0 + cc + e;
+        c[e] = a.alpha * p[e] + a.betaA * va[e] + a.betaB * vb[e] + (diag ? a.gamma : (T)0);
+        c2[e] = a.c2P * p[e] + a.c2A * va[e] + a.c2B * vb[e] + (diag ? a.g2 : (T)0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if (k < a.nx) {
+            c[e] += a.xc[k] * x[k][e];
+            c2[e] += a.xc2[k] * x[k][e];
+          }
+        }
+      }
+      st4(Cj + o, c);
+      if (C2j) st4(C2j + o, c2);
+    }
+  }
+}
+
 // dp a multiple of 16: one wavefront per 16x16 output tile, operands read
 // straight from L1/L2 (small matrices: the whole matrix is a few tiles).
 template <typename T, int OPA>
@@ -244,36 +326,7 @@ __global__ __launch_bounds__(256) void k_stage64(StageArgs<T> a, long padded) {
       acc[m][n][1] = vzero<T>();
     }
   wg_cgemm64<T, OPA, PF>(A, B, r0, c0, a.dp, lds, acc);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  if constexpr (!PF) {
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int n = 0; n < 2; ++n)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        stage_store(a, j, r0 + wr + 16 * m + acc_row<T>(lane, v), c0 + wc + 16 * n + (lane & 15),
-                    acc[m][n][0][v], acc[m][n][1][v]);
-  } else {
-  constexpr int NV = 8, NPG = NV / 4;  // outputs and 16x16 tiles per batch
-#pragma unroll
-  for (int g = 0; g < 4 / NPG; ++g) {
-    int row[NV], col[NV];
-    T pr[NV], pi[NV];
-#pragma unroll
-    for (int u = 0; u < NPG; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int tn = g * NPG + u, m = tn >> 1, n = tn & 1;
-        row[4 * u + v] = r0 + wr + 16 * m + acc_row<T>(lane, v);
-        col[4 * u + v] = c0 + wc + 16 * n + (lane & 15);
-        pr[4 * u + v] = acc[m][n][0][v];
-        pi[4 * u + v] = acc[m][n][1][v];
-      }
-    stage_store_n<T, NV>(a, j, row, col, pr, pi);
-  }
-  }
+  stage_epilogue64<T>(a, j, r0, c0, lds, acc);
 }
 
 // dp a multiple of 16 but not of 64 (80, 96, 112, ...): one workgroup per
@@ -385,8 +438,11 @@ __global__ __launch_bounds__(256) void k_stage32(StageArgs<T> a, long padded) {
 }
 
 // bf16x3 variant of k_stage64 (FP32 storage; the split-product tile of
-// qoc_tile.h), same tiling, epilogue and block order.
-template <int OPA, bool EB>
+// qoc_tile.h): one workgroup per 64 x 64 output tile, 4 waves of 32 x 32,
+// the same LDS epilogue and XCD-aware block order.  (Tiles of 128 x 64 and
+// 64 x 128, and a second chunk of operands in registers, were slower: they
+// cost occupancy, and the split products need the latency hiding.)
+template <int OPA>
 __global__ __launch_bounds__(256) void k_stage64_bf3(StageArgs<float> a, long padded) {
   __shared__ BfLds L;
   const int t1 = a.dp >> 6;
@@ -408,38 +464,11 @@ __global__ __launch_bounds__(256) void k_stage64_bf3(StageArgs<float> a, long pa
       acc[m][n][1] = vzero<float>();
     }
   // op(A) = A: inner index along rows of A; op(A) = A^H: along columns,
-  // conjugated; B as stored: inner index along columns of B
-  ctile64_bf3<OPA == 0, OPA == 1, false, false>(A, B, r0, c0, a.dp, L, acc);
-  if constexpr (EB) {  // batched epilogue (d_pad <= 128)
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      int row[8], col[8];
-      float pr[8], pi[8];
-#pragma unroll
-      for (int n = 0; n < 2; ++n)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          int r, c;
-          tile64_pos<float>(m, n, v, r, c);
-          row[4 * n + v] = r0 + r;
-          col[4 * n + v] = c0 + c;
-          pr[4 * n + v] = acc[m][n][0][v];
-          pi[4 * n + v] = acc[m][n][1][v];
-        }
-      stage_store_n<float, 8>(a, j, row, col, pr, pi);
-    }
-  } else {
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int n = 0; n < 2; ++n)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          int r, c;
-          tile64_pos<float>(m, n, v, r, c);
-          stage_store(a, j, r0 + r, c0 + c, acc[m][n][0][v], acc[m][n][1][v]);
-        }
-  }
+  // conjugated; B as stored: inner index along columns of B.  The tiles lie
+  // inside the matrices (dp a multiple of 64, d <= 1024: both planes of a
+  // matrix within 2^31 bytes).
+  ctile_bf3<2, 2, OPA == 0, OPA == 1, false, false, true>(A, B, r0, c0, a.dp, L, acc);
+  stage_epilogue64<float>(a, j, r0, c0, (float *)&L, acc);
 }
 
 template <typename T>
@@ -459,19 +488,12 @@ template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hi
       const long t1 = a.dp / 64;
       const long total = (long)a.nmat * t1 * t1;
       const long padded = (total + 7) / 8 * 8;
-      const bool eb = a.dp <= 128;
-      if (opa && eb)
-        hipLaunchKernelGGL((k_stage64_bf3<1, true>), dim3((unsigned)padded), dim3(256), 0, st, a,
-                           padded);
-      else if (opa)
-        hipLaunchKernelGGL((k_stage64_bf3<1, false>), dim3((unsigned)padded), dim3(256), 0, st, a,
-                           padded);
-      else if (eb)
-        hipLaunchKernelGGL((k_stage64_bf3<0, true>), dim3((unsigned)padded), dim3(256), 0, st, a,
+      if (opa)
+        hipLaunchKernelGGL((k_stage64_bf3<1>), dim3((unsigned)padded), dim3(256), 0, st, a,
                            padded);
       else
-        hipLaunchKernelGGL((k_stage64_bf3<0, false>), dim3((unsigned)padded), dim3(256), 0, st,
-                           a, padded);
+        hipLaunchKernelGGL((k_stage64_bf3<0>), dim3((unsigned)padded), dim3(256), 0, st, a,
+                           padded);
       return hipGetLastError();
     }
   }
@@ -479,8 +501,8 @@ template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hi
     const long t1 = a.dp / 64;
     const long total = (long)a.nmat * t1 * t1;
     const long padded = (total + 7) / 8 * 8;
-    // short inner dimension (d_pad <= 128): register prefetch and batched
-    // epilogue; longer ones: the occupancy-friendly loop
+    // short inner dimension (d_pad <= 128): register prefetch; longer ones:
+    // the occupancy-friendly loop
     const bool pf = a.dp <= 128;
     if (opa && pf)
       hipLaunchKernelGGL((k_stage64<T, 1, true>), dim3((unsigned)padded), dim3(256), 0, st, a,

@@ -198,42 +198,53 @@ __device__ __forceinline__ f32x4 mfma_bf(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ bf16x8 bf_neg(bf16x8 v) {
-  u32x4 u = __builtin_bit_cast(u32x4, v);
-  u ^= 0x80008000u;
-  return __builtin_bit_cast(bf16x8, u);
-}
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
+// Pairs of values through the packed FP32 -> bf16 conversion (RNE).
 __device__ __forceinline__ void bf_split8(const float (&x)[8], bf16x8 &hi, bf16x8 &lo) {
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const __bf16 h = (__bf16)x[q];
-    hi[q] = h;
-    lo[q] = (__bf16)(x[q] - (float)h);
+  for (int q = 0; q < 8; q += 2) {
+    const f32x2v v = {x[q], x[q + 1]};
+    const bf16x2v h = __builtin_convertvector(v, bf16x2v);
+    const f32x2v hf = __builtin_convertvector(h, f32x2v);
+    const f32x2v r = {v[0] - hf[0], v[1] - hf[1]};
+    const bf16x2v l = __builtin_convertvector(r, bf16x2v);
+    hi[q] = h[0];
+    hi[q + 1] = h[1];
+    lo[q] = l[0];
+    lo[q + 1] = l[1];
   }
 }
 
-struct alignas(16) BfLds {
-  __bf16 a[4][64][BF_LDK];
-  __bf16 b[4][64][BF_LDK];
+// LDS of one TM x 32 chunk of op(A) and 32 x TN chunk of op(B), both as
+// [plane][outer][k].
+template <int TM, int TN> struct alignas(16) BfLdsT {
+  __bf16 a[4][TM][BF_LDK];
+  __bf16 b[4][TN][BF_LDK];
 };
+typedef BfLdsT<64, 64> BfLds;
 
-// Thread -> (outer index, group of 8 inner indices) of a 64 x 32 chunk.
-template <bool KC> __device__ __forceinline__ void bf_slot(int t, int &i, int &kq) {
+// Slot s (0 <= s < 4 TM) of a TM x 32 chunk -> (outer index, group of 8
+// inner indices).  Slots s and s + 256 belong to one thread.
+// KC: each wavefront covers 16 whole rows (lane l: row l % 16, group l / 16),
+// so a wave's loads touch 16 full 128-byte row segments and the 8 (or 16)
+// lanes of one LDS write cycle hit 8 (16) different rows: no bank conflicts.
+template <bool KC, int TM> __device__ __forceinline__ void bf_slot(int s, int &i, int &kq) {
   if (KC) {
-    i = t >> 2;
-    kq = t & 3;
+    i = s >> 2;
+    kq = s & 3;
   } else {
-    i = t & 63;
-    kq = t >> 6;
+    i = s % TM;
+    kq = s / TM;
   }
 }
 
-template <bool KC, bool CJ>
-__device__ __forceinline__ void bf_load_op(const TOp<float> &X, int i0, int k0, int K,
+template <bool KC, bool CJ, int TM>
+__device__ __forceinline__ void bf_load_op(const TOp<float> &X, int s, int i0, int k0, int K,
                                            float (&vr)[8], float (&vi)[8]) {
   int i, kq;
-  bf_slot<KC>(threadIdx.x, i, kq);
+  bf_slot<KC, TM>(s, i, kq);
   const int kk = k0 + 8 * kq;
   const bool ok = (i0 + i < X.rows) && (kk < K);
   if (KC) {
@@ -260,11 +271,58 @@ __device__ __forceinline__ void bf_load_op(const TOp<float> &X, int i0, int k0, 
   }
 }
 
-template <bool KC>
-__device__ __forceinline__ void bf_store_op(const float (&vr)[8], const float (&vi)[8],
-                                            __bf16 (&S)[4][64][BF_LDK]) {
+// The same chunk load for tiles that lie inside the operand (outer indices
+// below rows, K a multiple of 32, no column blocks, both planes within 2^31
+// bytes of re): no guards, and the per-lane part of each address is one
+// 32-bit byte offset.  Inner index along memory rows: 16-byte global loads
+// from the uniform plane pointers; across rows: dword buffer loads whose
+// row and plane offsets are wave-uniform (scalar offsets), so no lane
+// computes a 64-bit address.  The buffer's range covers both planes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t bf_rsrc(const TOp<float> &X) {
+  const long bytes = ((long)(X.im - X.re) + (long)X.rows * X.ld) * 4;
+  return __builtin_amdgcn_make_buffer_rsrc((void *)X.re, 0,
+                                           (int)(bytes < 0x7fffffffL ? bytes : 0x7fffffffL),
+                                           0x00020000);
+}
+
+template <bool KC, bool CJ, int TM>
+__device__ __forceinline__ void bf_load_full(const TOp<float> &X, __amdgpu_buffer_rsrc_t rs,
+                                             int s, int i0, int k0, float (&vr)[8],
+                                             float (&vi)[8]) {
   int i, kq;
-  bf_slot<KC>(threadIdx.x, i, kq);
+  bf_slot<KC, TM>(s, i, kq);
+  if (KC) {
+    const unsigned o = (unsigned)(((i0 + i) * X.ld + k0 + 8 * kq) * 4);
+    const char *re = (const char *)X.re, *im = (const char *)X.im;
+    const float4 r0 = *(const float4 *)(re + o), r1 = *(const float4 *)(re + o + 16);
+    const float4 q0 = *(const float4 *)(im + o), q1 = *(const float4 *)(im + o + 16);
+    vr[0] = r0.x; vr[1] = r0.y; vr[2] = r0.z; vr[3] = r0.w;
+    vr[4] = r1.x; vr[5] = r1.y; vr[6] = r1.z; vr[7] = r1.w;
+    vi[0] = q0.x; vi[1] = q0.y; vi[2] = q0.z; vi[3] = q0.w;
+    vi[4] = q1.x; vi[5] = q1.y; vi[6] = q1.z; vi[7] = q1.w;
+  } else {
+    // kq = s / TM is the same on every lane of a wave (TM a multiple of 64)
+    const int kw = __builtin_amdgcn_readfirstlane(kq);
+    const int im = (int)(X.im - X.re) * 4;
+    const int o = (i0 + i) * 4;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int row = (k0 + 8 * kw + q) * X.ld * 4;
+      vr[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o, row, 0));
+      vi[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o, row + im, 0));
+    }
+  }
+  if (CJ) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) vi[q] = -vi[q];
+  }
+}
+
+template <bool KC, int TM>
+__device__ __forceinline__ void bf_store_op(int s, const float (&vr)[8], const float (&vi)[8],
+                                            __bf16 (&S)[4][TM][BF_LDK]) {
+  int i, kq;
+  bf_slot<KC, TM>(s, i, kq);
   bf16x8 h, l;
   bf_split8(vr, h, l);
   *(bf16x8 *)&S[0][i][8 * kq] = h;
@@ -274,57 +332,112 @@ __device__ __forceinline__ void bf_store_op(const float (&vr)[8], const float (&
   *(bf16x8 *)&S[3][i][8 * kq] = l;
 }
 
+// acc[m][n][0/1] (re / im) += the (16 MT) x (16 NT) sub-tile of wave w at
+// rows 16 MT (w >> 1), columns 16 NT (w & 1) of the (32 MT) x (32 NT) tile
+// at (i0, j0).  All 256 threads must call.  Every accumulator receives its
+// terms in the same order whatever MT and NT, so tiles of any shape give
+// the same sums.
+template <int MT, int NT, bool AKC, bool ACJ, bool BKC, bool BCJ, bool FULL = false>
+__device__ __forceinline__ void ctile_bf3(const TOp<float> &A, const TOp<float> &B, int i0,
+                                          int j0, int K, BfLdsT<32 * MT, 32 * NT> &L,
+                                          f32x4 (&acc)[MT][NT][2]) {
+  constexpr int TM = 32 * MT, TN = 32 * NT, UA = TM / 64, UB = TN / 64;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int i = lane & 15, g8 = 8 * (lane >> 4);
+  const int wr = (w >> 1) * 16 * MT, wc = (w & 1) * 16 * NT;
+  float ar[UA][8], ai[UA][8], br[UB][8], bi[UB][8];
+  __amdgpu_buffer_rsrc_t rsa, rsb;
+  if constexpr (FULL) {
+    rsa = bf_rsrc(A);
+    rsb = bf_rsrc(B);
+  }
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      if constexpr (FULL)
+        bf_load_full<AKC, ACJ, TM>(A, rsa, t + 256 * u, i0, k0, ar[u], ai[u]);
+      else
+        bf_load_op<AKC, ACJ, TM>(A, t + 256 * u, i0, k0, K, ar[u], ai[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      if constexpr (FULL)
+        bf_load_full<BKC, BCJ, TN>(B, rsb, t + 256 * u, j0, k0, br[u], bi[u]);
+      else
+        bf_load_op<BKC, BCJ, TN>(B, t + 256 * u, j0, k0, K, br[u], bi[u]);
+    }
+  };
+  // Ai Bi accumulates on its own (added with a minus sign at the end), so
+  // no fragment needs a negation
+  f32x4 accn[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) accn[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += BF_BK) {
+#pragma unroll
+    for (int u = 0; u < UA; ++u) bf_store_op<AKC, TM>(t + 256 * u, ar[u], ai[u], L.a);
+#pragma unroll
+    for (int u = 0; u < UB; ++u) bf_store_op<BKC, TN>(t + 256 * u, br[u], bi[u], L.b);
+    __syncthreads();
+    if (k0 + BF_BK < K) load(k0 + BF_BK);  // block-uniform
+    bf16x8 fb[NT][4];
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) fb[n][p] = *(const bf16x8 *)&L.b[p][wc + 16 * n + i][g8];
+    // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br, each real product as
+    // hi*hi + hi*lo + lo*hi; consecutive MFMAs go to different accumulators.
+    // MT <= 2: every fragment of op(A) up front, term by term over all
+    // tiles; above, one row block of fragments at a time (register budget).
+    constexpr int FA = MT <= 2 ? MT : 1;
+#define QOC_BF3_TERMS(MLO, MHI, FA_)                                           \
+  QOC_BF3_TERM(MLO, MHI, acc[m][n][0], FA_[0], fb[n][0])                       \
+  QOC_BF3_TERM(MLO, MHI, acc[m][n][1], FA_[0], fb[n][2])                       \
+  QOC_BF3_TERM(MLO, MHI, accn[m][n], FA_[2], fb[n][2])                         \
+  QOC_BF3_TERM(MLO, MHI, acc[m][n][0], FA_[0], fb[n][1])                       \
+  QOC_BF3_TERM(MLO, MHI, acc[m][n][1], FA_[0], fb[n][3])                       \
+  QOC_BF3_TERM(MLO, MHI, accn[m][n], FA_[2], fb[n][3])                         \
+  QOC_BF3_TERM(MLO, MHI, acc[m][n][0], FA_[1], fb[n][0])                       \
+  QOC_BF3_TERM(MLO, MHI, acc[m][n][1], FA_[1], fb[n][2])                       \
+  QOC_BF3_TERM(MLO, MHI, accn[m][n], FA_[3], fb[n][2])                         \
+  QOC_BF3_TERM(MLO, MHI, acc[m][n][1], FA_[2], fb[n][0])                       \
+  QOC_BF3_TERM(MLO, MHI, acc[m][n][1], FA_[2], fb[n][1])                       \
+  QOC_BF3_TERM(MLO, MHI, acc[m][n][1], FA_[3], fb[n][0])
+#define QOC_BF3_TERM(MLO, MHI, D, X, Y)                                        \
+  _Pragma("unroll") for (int m = MLO; m < MHI; ++m)                            \
+  _Pragma("unroll") for (int n = 0; n < NT; ++n) D = mfma_bf(X, Y, D);
+    if constexpr (MT <= 2) {
+      bf16x8 fa[FA][4];
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) fa[m][p] = *(const bf16x8 *)&L.a[p][wr + 16 * m + i][g8];
+      QOC_BF3_TERMS(0, MT, fa[m])
+    } else {
+#pragma unroll
+      for (int mb = 0; mb < MT; ++mb) {
+        bf16x8 fa[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) fa[p] = *(const bf16x8 *)&L.a[p][wr + 16 * mb + i][g8];
+        QOC_BF3_TERMS(mb, mb + 1, fa)
+      }
+    }
+#undef QOC_BF3_TERM
+#undef QOC_BF3_TERMS
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[m][n][0] -= accn[m][n];
+}
+
 template <bool AKC, bool ACJ, bool BKC, bool BCJ>
 __device__ __forceinline__ void ctile64_bf3(const TOp<float> &A, const TOp<float> &B, int i0,
                                             int j0, int K, BfLds &L, f32x4 (&acc)[2][2][2]) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = lane & 15, g8 = 8 * (lane >> 4);
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  float ar[8], ai[8], br[8], bi[8];
-  bf_load_op<AKC, ACJ>(A, i0, 0, K, ar, ai);
-  bf_load_op<BKC, BCJ>(B, j0, 0, K, br, bi);
-  for (int k0 = 0; k0 < K; k0 += BF_BK) {
-    bf_store_op<AKC>(ar, ai, L.a);
-    bf_store_op<BKC>(br, bi, L.b);
-    __syncthreads();
-    if (k0 + BF_BK < K) {
-      bf_load_op<AKC, ACJ>(A, i0, k0 + BF_BK, K, ar, ai);
-      bf_load_op<BKC, BCJ>(B, j0, k0 + BF_BK, K, br, bi);
-    }
-    bf16x8 fa[2][4], fb[2][4], na[2][2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        fa[m][p] = *(const bf16x8 *)&L.a[p][wr + 16 * m + i][g8];
-        fb[m][p] = *(const bf16x8 *)&L.b[p][wc + 16 * m + i][g8];
-      }
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      na[m][0] = bf_neg(fa[m][2]);
-      na[m][1] = bf_neg(fa[m][3]);
-    }
-    // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br, each real product as
-    // hi*hi + hi*lo + lo*hi; consecutive MFMAs go to different accumulators
-#define QOC_BF3_TERM(dst, X, Y)                                                \
-  _Pragma("unroll") for (int m = 0; m < 2; ++m)                                \
-  _Pragma("unroll") for (int n = 0; n < 2; ++n)                                \
-    acc[m][n][dst] = mfma_bf(X, Y, acc[m][n][dst]);
-    QOC_BF3_TERM(0, fa[m][0], fb[n][0])
-    QOC_BF3_TERM(1, fa[m][0], fb[n][2])
-    QOC_BF3_TERM(0, fa[m][0], fb[n][1])
-    QOC_BF3_TERM(1, fa[m][0], fb[n][3])
-    QOC_BF3_TERM(0, fa[m][1], fb[n][0])
-    QOC_BF3_TERM(1, fa[m][1], fb[n][2])
-    QOC_BF3_TERM(0, na[m][0], fb[n][2])
-    QOC_BF3_TERM(1, fa[m][2], fb[n][0])
-    QOC_BF3_TERM(0, na[m][0], fb[n][3])
-    QOC_BF3_TERM(1, fa[m][2], fb[n][1])
-    QOC_BF3_TERM(0, na[m][1], fb[n][2])
-    QOC_BF3_TERM(1, fa[m][3], fb[n][0])
-#undef QOC_BF3_TERM
-    __syncthreads();
-  }
+  ctile_bf3<2, 2, AKC, ACJ, BKC, BCJ>(A, B, i0, j0, K, L, acc);
 }
 
 // Dispatch: one 64x64 tile in the chain precision or as bf16x3 (float only).
