@@ -198,15 +198,15 @@ __device__ __forceinline__ void stage_store_n(const StageArgs<T> &a, long j, con
   }
 }
 
-// The epilogue of a 64 x 64 output tile through LDS: each plane of the
-// accumulators is written to LDS in the MFMA layout (wave w holds rows
-// 32 (w >> 1) + 16 m + acc_row, columns 32 (w & 1) + 16 n + lane % 16), then
-// every thread takes four rows of four consecutive columns, so the addends
-// are read and the outputs written as 16-byte vectors, 256 bytes per row
-// segment, and all addend loads of a row are issued before its stores.  The
-// coefficients are real, so the planes are independent.  sm must hold
-// 64 x 68 elements; all 256 threads must call.
-constexpr int EP_LD = 64 + 4;  // row stride: conflict-free writes in the MFMA layout
+// Stage epilogues through LDS.  Each plane of a TD x TD output tile is
+// written to LDS in the kernel's MFMA layout, then emitted by every thread
+// as runs of four consecutive columns of a row (TD / 4 threads per row), so
+// the addends are read and the outputs written as 16-byte vectors, whole
+// row segments per wavefront, all loads of a run before its stores.  The
+// coefficients are real, so the planes are independent.  Rows and columns
+// at or beyond dp (a multiple of 16: a run is inside or outside) are
+// skipped.  All 256 threads must call.
+constexpr int EP_PAD = 4;  // LDS row padding: conflict-free writes in the MFMA layout
 
 template <typename T>
 __device__ __forceinline__ void st4(T *p, const T (&v)[4]) {
@@ -218,11 +218,11 @@ __device__ __forceinline__ void st4(T *p, const T (&v)[4]) {
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void stage_epilogue64(const StageArgs<T> &a, long j, int r0, int c0,
-                                                 T *sm, const v4<T> (&acc)[2][2][2]) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+template <typename T, int TD>
+__device__ __forceinline__ void stage_emit_plane(const StageArgs<T> &a, long j, int r0, int c0,
+                                                 const T *sm, int pl) {
+  constexpr int LD = TD + EP_PAD, TPR = TD / 4, RPP = 256 / TPR;
+  const int t = threadIdx.x;
   const long plane = (long)a.dp * a.dp;
   const bool needA = a.betaA != (T)0 || (a.C2 && a.c2A != (T)0);
   const bool needB = a.betaB != (T)0 || (a.C2 && a.c2B != (T)0);
@@ -230,7 +230,52 @@ __device__ __forceinline__ void stage_epilogue64(const StageArgs<T> &a, long j, 
   const long oc = moff(a, j, a.strideC, a.segC);
   T *Cj = a.C + oc;
   T *C2j = a.C2 ? a.C2 + oc : nullptr;
-  const int rr = t >> 4, cc = 4 * (t & 15);  // rows rr + 16 q, columns cc .. cc + 3
+  const int rr = t / TPR, cc = 4 * (t % TPR);
+#pragma unroll
+  for (int q = 0; q < TD / RPP; ++q) {
+    const int row = rr + RPP * q;
+    if (r0 + row >= a.dp || c0 + cc >= a.dp) continue;
+    const long o = pl * plane + (long)(r0 + row) * a.dp + c0 + cc;
+    T p[4], va[4] = {0, 0, 0, 0}, vb[4] = {0, 0, 0, 0}, x[3][4];
+    ld4(sm + row * LD + cc, p);
+    if (needA) ld4(Aj + o, va);
+    if (needB) ld4(Bj + o, vb);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k < a.nx) {
+        ld4(a.xadd[k] + oc + o, x[k]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[k][e] = 0;
+      }
+    }
+    T c[4], c2[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool diag = pl == 0 && r0 + row == c0 + cc + e;
+      c[e] = a.alpha * p[e] + a.betaA * va[e] + a.betaB * vb[e] + (diag ? a.gamma : (T)0);
+      c2[e] = a.c2P * p[e] + a.c2A * va[e] + a.c2B * vb[e] + (diag ? a.g2 : (T)0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (k < a.nx) {
+          c[e] += a.xc[k] * x[k][e];
+          c2[e] += a.xc2[k] * x[k][e];
+        }
+      }
+    }
+    st4(Cj + o, c);
+    if (C2j) st4(C2j + o, c2);
+  }
+}
+
+// 64 x 64 tiles: wave w holds rows 32 (w >> 1) + 16 m + acc_row, columns
+// 32 (w & 1) + 16 n + lane % 16.  sm holds 64 x 68 elements.
+template <typename T>
+__device__ __forceinline__ void stage_epilogue64(const StageArgs<T> &a, long j, int r0, int c0,
+                                                 T *sm, const v4<T> (&acc)[2][2][2]) {
+  constexpr int LD = 64 + EP_PAD;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
 #pragma unroll
   for (int pl = 0; pl < 2; ++pl) {
     __syncthreads();  // the previous use of sm is done
@@ -240,43 +285,10 @@ __device__ __forceinline__ void stage_epilogue64(const StageArgs<T> &a, long j, 
       for (int n = 0; n < 2; ++n)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          sm[(wr + 16 * m + acc_row<T>(lane, v)) * EP_LD + wc + 16 * n + (lane & 15)] =
+          sm[(wr + 16 * m + acc_row<T>(lane, v)) * LD + wc + 16 * n + (lane & 15)] =
               acc[m][n][pl][v];
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = rr + 16 * q;
-      const long o = pl * plane + (long)(r0 + row) * a.dp + c0 + cc;
-      T p[4], va[4] = {0, 0, 0, 0}, vb[4] = {0, 0, 0, 0}, x[3][4];
-      ld4(sm + row * EP_LD + cc, p);
-      if (needA) ld4(Aj + o, va);
-      if (needB) ld4(Bj + o, vb);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        if (k < a.nx) {
-          ld4(a.xadd[k] + oc + o, x[k]);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) x[k][e] = 0;
-        }
-      }
-      T c[4], c2[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const bool diag = pl == 0 && r0 + row == c0 + cc + e;
-        c[e] = a.alpha * p[e] + a.betaA * va[e] + a.betaB * vb[e] + (diag ? a.gamma : (T)0);
-        c2[e] = a.c2P * p[e] + a.c2A * va[e] + a.c2B * vb[e] + (diag ? a.g2 : (T)0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          if (k < a.nx) {
-            c[e] += a.xc[k] * x[k][e];
-            c2[e] += a.xc2[k] * x[k][e];
-          }
-        }
-      }
-      st4(Cj + o, c);
-      if (C2j) st4(C2j + o, c2);
-    }
+    stage_emit_plane<T, 64>(a, j, r0, c0, sm, pl);
   }
 }
 
@@ -338,8 +350,9 @@ constexpr int T32_BK = 16, T32_LD = 32 + 16;
 
 template <typename T, int OPA>
 __global__ __launch_bounds__(256) void k_stage32(StageArgs<T> a, long padded) {
-  __shared__ T Asr[T32_BK * T32_LD], Asi[T32_BK * T32_LD];
-  __shared__ T Bsr[T32_BK * T32_LD], Bsi[T32_BK * T32_LD];
+  __shared__ T lds[4 * T32_BK * T32_LD];
+  T *Asr = lds, *Asi = Asr + T32_BK * T32_LD;
+  T *Bsr = Asi + T32_BK * T32_LD, *Bsi = Bsr + T32_BK * T32_LD;
   const int t1 = (a.dp + 31) >> 5;
   const long tiles = (long)t1 * t1;
   const long logical = xcd_logical_block(blockIdx.x, padded);
@@ -430,10 +443,18 @@ __global__ __launch_bounds__(256) void k_stage32(StageArgs<T> a, long padded) {
     }
     lds_barrier();
   }
+  // epilogue through LDS (32 x 36 elements per plane, over the operand
+  // chunks: the product's last LDS reads are behind the barrier above)
+  T *sm = lds;
+  static_assert(4 * T32_BK * T32_LD >= 32 * (32 + EP_PAD), "LDS tile too small");
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int row = r0 + wr + acc_row<T>(lane, v), col = c0 + wc + (lane & 15);
-    if (row < dp && col < dp) stage_store(a, j, row, col, cr[v], ci[v]);
+  for (int pl = 0; pl < 2; ++pl) {
+    if (pl) __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      sm[(wr + acc_row<T>(lane, v)) * (32 + EP_PAD) + wc + (lane & 15)] = pl ? ci[v] : cr[v];
+    __syncthreads();
+    stage_emit_plane<T, 32>(a, j, r0, c0, sm, pl);
   }
 }
 
