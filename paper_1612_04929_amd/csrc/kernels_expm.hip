@@ -316,8 +316,12 @@ __global__ __launch_bounds__(256) void k_stage16(StageArgs<T> a) {
 
 // dp a multiple of 64: one workgroup per 64x64 output tile, LDS-staged,
 // XCD-aware block order (all tiles of one step on one XCD's L2).
+// FP64: at most 168 registers (three wavefronts per SIMD; the epilogue
+// would otherwise take the kernel just past it)
 template <typename T, int OPA, bool PF>
-__global__ __launch_bounds__(256) void k_stage64(StageArgs<T> a, long padded) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, 256),
+                          amdgpu_waves_per_eu(sizeof(T) == 8 && !PF ? 3 : 1)))
+void k_stage64(StageArgs<T> a, long padded) {
   __shared__ T lds[T64_LDS_ELEMS];
   const int t1 = a.dp >> 6;
   const long tiles = (long)t1 * t1;
