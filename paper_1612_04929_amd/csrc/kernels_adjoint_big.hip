@@ -459,15 +459,16 @@ template <typename T> __global__ __launch_bounds__(256) void k_gcontract(GContra
 // (At_{kb+1} V_{kb+2}^H, the product k_xstore would store), and contracted
 // with every control that has a nonzero there: g += Im(conj(Xbar) h), which
 // is linear in Xbar, so each lane contracts its own share of the inner
-// index and keeps per-control sums of its own (FP64, in LDS), summed over
-// lanes and wavefronts in a fixed order at the end.  Workgroup (g, j) takes
+// index and keeps per-control sums of its own (in the chain precision, in
+// LDS: a lane adds a few dozen terms), summed over lanes and wavefronts in
+// FP64 in a fixed order at the end.  Workgroup (g, j) takes
 // the rows r = g, g + SG_GROUPS, ... of step j, one row per wavefront at a
 // time: the row's panel entries are loaded once (consecutive lanes read
 // consecutive entries) and serve every union entry of the row; the entries
 // of a row go in batches of SG_BATCH with all their loads in flight.
 constexpr int SG_GROUPS = 4, SG_AREG = 8, SG_BATCH = 4;
-// per-lane sums of one control: 4 wavefronts x 64 lanes FP64
-constexpr int SG_LDS_PER_CONTROL = 4 * 64 * 8;
+// per-lane sums of one control: 4 wavefronts x 64 lanes of T
+template <typename T> constexpr int sg_lds_per_control() { return 4 * 64 * (int)sizeof(T); }
 template <typename T> struct SContract {
   const T *panel;  // step 0's panel (real plane; imaginary at + big)
   long per, big;
@@ -480,9 +481,10 @@ template <typename T> struct SContract {
   int N, M, d;
 };
 
-template <typename T>
+template <typename T, int AREG>
 __global__ __launch_bounds__(256) void k_sgcontract(SContract<T> a, long padded) {
-  extern __shared__ double gsh[];  // [4 waves][M][64 lanes]
+  extern __shared__ __align__(16) char gsh_raw[];
+  T *gsh = (T *)gsh_raw;  // [4 waves][M][64 lanes]
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // the SG_GROUPS workgroups of one step on one XCD, so that they share the
   // step's panel in its L2 (read from HBM about once)
@@ -490,15 +492,15 @@ __global__ __launch_bounds__(256) void k_sgcontract(SContract<T> a, long padded)
   if (logical >= (long)a.N * SG_GROUPS) return;  // block-uniform
   const int g = (int)(logical % SG_GROUPS);
   const long j = logical / SG_GROUPS;
-  double *acc = gsh + (long)w * a.M * 64 + lane;
-  for (int k = 0; k < a.M; ++k) acc[k * 64] = 0.0;
+  T *acc = gsh + (long)w * a.M * 64 + lane;
+  for (int k = 0; k < a.M; ++k) acc[k * 64] = (T)0;
   const T *Pr = a.panel + j * a.per, *Pi = Pr + a.big;
   const int K = a.p * a.rr;
   // this lane's inner indices i = lane + 64 q and their panel columns
-  long ca[SG_AREG], cb[SG_AREG];
-  bool iv[SG_AREG];
+  long ca[AREG], cb[AREG];
+  bool iv[AREG];
 #pragma unroll
-  for (int q = 0; q < SG_AREG; ++q) {
+  for (int q = 0; q < AREG; ++q) {
     const int i = lane + 64 * q;
     iv[q] = i < K;
     const int kb = iv[q] ? i / a.rr : 0, ii = iv[q] ? i - kb * a.rr : 0;
@@ -509,19 +511,19 @@ __global__ __launch_bounds__(256) void k_sgcontract(SContract<T> a, long padded)
     const int e0 = a.rptr[r], e1 = a.rptr[r + 1];
     if (e0 == e1) continue;  // wavefront-uniform
     const long ro = (long)r * a.ld;
-    T ar[SG_AREG], ai[SG_AREG];
+    T ar[AREG], ai[AREG];
 #pragma unroll
-    for (int q = 0; q < SG_AREG; ++q) {
+    for (int q = 0; q < AREG; ++q) {
       ar[q] = iv[q] ? Pr[ro + ca[q]] : (T)0;
       ai[q] = iv[q] ? Pi[ro + ca[q]] : (T)0;
     }
     for (int e = e0; e < e1; e += SG_BATCH) {
-      T br[SG_BATCH][SG_AREG], bi[SG_BATCH][SG_AREG];
+      T br[SG_BATCH][AREG], bi[SG_BATCH][AREG];
 #pragma unroll
       for (int u = 0; u < SG_BATCH; ++u) {
         const long co = (long)a.rcol[e + u < e1 ? e + u : e] * a.ld;
 #pragma unroll
-        for (int q = 0; q < SG_AREG; ++q) {
+        for (int q = 0; q < AREG; ++q) {
           br[u][q] = iv[q] ? Pr[co + cb[q]] : (T)0;
           bi[u][q] = iv[q] ? Pi[co + cb[q]] : (T)0;
         }
@@ -531,13 +533,13 @@ __global__ __launch_bounds__(256) void k_sgcontract(SContract<T> a, long padded)
         if (e + u < e1) {  // wavefront-uniform
           T xr = 0, xi = 0;
 #pragma unroll
-          for (int q = 0; q < SG_AREG; ++q) {
+          for (int q = 0; q < AREG; ++q) {
             xr += ar[q] * br[u][q] + ai[q] * bi[u][q];  // a conj(b)
             xi += ai[q] * br[u][q] - ar[q] * bi[u][q];
           }
           for (int q = a.eptr[e + u]; q < a.eptr[e + u + 1]; ++q) {
-            const double hr = (double)a.eval[q], hi = (double)a.eval[a.nev + q];
-            acc[a.ek[q] * 64] += (double)xr * hi - (double)xi * hr;  // Im(conj(Xbar) h)
+            const T hr = a.eval[q], hi = a.eval[a.nev + q];
+            acc[a.ek[q] * 64] += xr * hi - xi * hr;  // Im(conj(Xbar) h)
           }
         }
       }
@@ -547,7 +549,7 @@ __global__ __launch_bounds__(256) void k_sgcontract(SContract<T> a, long padded)
   for (int k = threadIdx.x; k < a.M; k += 256) {
     double s = 0.0;
     for (int ww = 0; ww < 4; ++ww)
-      for (int l = 0; l < 64; ++l) s += gsh[((long)ww * a.M + k) * 64 + l];
+      for (int l = 0; l < 64; ++l) s += (double)gsh[((long)ww * a.M + k) * 64 + l];
     a.part[(j * SG_GROUPS + g) * a.M + k] = s;
   }
 }
@@ -834,13 +836,23 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
     if ((e = launch_thin(tb)) != hipSuccess) return e;
   }
   // ---- structured control Hamiltonians: Xbar only at their nonzeros
-  if (a.rptr && (long)M * SG_LDS_PER_CONTROL <= 64 * 1024 && (long)p * rr <= 64 * SG_AREG) {
+  if (a.rptr && (long)M * sg_lds_per_control<T>() <= 64 * 1024 && (long)p * rr <= 64 * SG_AREG) {
     if (M > 0) {
       SContract<T> sc2{sc + 8 * thin, per, big, (int)KK2, rr, p, a.rptr, a.rcol, a.eptr, a.ek,
                        a.eval, a.nev, a.part, N, M, a.d};
       const long total = (long)SG_GROUPS * N, padded = (total + 7) / 8 * 8;
-      hipLaunchKernelGGL(k_sgcontract<T>, dim3((unsigned)padded), dim3(256),
-                         (size_t)M * SG_LDS_PER_CONTROL, st, sc2, padded);
+      // registers for the lane's share of the inner length p rr (<= 64 AREG)
+      const long K = (long)p * rr;
+      const size_t shm = (size_t)M * sg_lds_per_control<T>();
+      if (K <= 128)
+        hipLaunchKernelGGL((k_sgcontract<T, 2>), dim3((unsigned)padded), dim3(256), shm, st,
+                           sc2, padded);
+      else if (K <= 256)
+        hipLaunchKernelGGL((k_sgcontract<T, 4>), dim3((unsigned)padded), dim3(256), shm, st,
+                           sc2, padded);
+      else
+        hipLaunchKernelGGL((k_sgcontract<T, SG_AREG>), dim3((unsigned)padded), dim3(256), shm,
+                           st, sc2, padded);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     AdjFinish<T> f{a.part, a.u, a.grad, 2.0 * a.s_scale, a.alpha_amp, a.alpha_var, nullptr, N, M,
