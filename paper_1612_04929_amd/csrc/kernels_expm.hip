@@ -141,63 +141,6 @@ __device__ __forceinline__ void stage_store(const StageArgs<T> &a, long j, int r
   }
 }
 
-// The epilogue for NV outputs of one thread at once: every addend of the NV
-// outputs is loaded before the first store.  The stage launches never let
-// C or C2 overlap A, B or an extra addend (outputs go to buffers of their
-// own), so the loads need not wait behind the stores.
-template <typename T, int NV>
-__device__ __forceinline__ void stage_store_n(const StageArgs<T> &a, long j, const int (&row)[NV],
-                                              const int (&col)[NV], const T (&accr)[NV],
-                                              const T (&acci)[NV]) {
-  const long plane = (long)a.dp * a.dp;
-  const bool needA = a.betaA != (T)0 || (a.C2 && a.c2A != (T)0);
-  const bool needB = a.betaB != (T)0 || (a.C2 && a.c2B != (T)0);
-  const T *Aj = a.A + moff(a, j, a.strideA, a.segA), *Bj = a.B + moff(a, j, a.strideB, a.segB);
-  T ar[NV], ai[NV], br[NV], bi[NV], xr[3][NV], xi[3][NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const long o = (long)row[v] * a.dp + col[v];
-    ar[v] = needA ? Aj[o] : (T)0;
-    ai[v] = needA ? Aj[plane + o] : (T)0;
-    br[v] = needB ? Bj[o] : (T)0;
-    bi[v] = needB ? Bj[plane + o] : (T)0;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const T *Xq = a.xadd[q] + moff(a, j, a.strideC, a.segC);
-      xr[q][v] = q < a.nx ? Xq[o] : (T)0;
-      xi[q][v] = q < a.nx ? Xq[plane + o] : (T)0;
-    }
-  }
-  T *Cj = a.C + moff(a, j, a.strideC, a.segC);
-  T *C2j = a.C2 ? a.C2 + moff(a, j, a.strideC, a.segC) : nullptr;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const long o = (long)row[v] * a.dp + col[v];
-    T vr = a.alpha * accr[v] + a.betaA * ar[v] + a.betaB * br[v];
-    T vi = a.alpha * acci[v] + a.betaA * ai[v] + a.betaB * bi[v];
-    if (row[v] == col[v]) vr += a.gamma;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      vr += a.xc[q] * xr[q][v];
-      vi += a.xc[q] * xi[q][v];
-    }
-    Cj[o] = vr;
-    Cj[plane + o] = vi;
-    if (C2j) {
-      T wr = a.c2P * accr[v] + a.c2A * ar[v] + a.c2B * br[v];
-      T wi = a.c2P * acci[v] + a.c2A * ai[v] + a.c2B * bi[v];
-      if (row[v] == col[v]) wr += a.g2;
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        wr += a.xc2[q] * xr[q][v];
-        wi += a.xc2[q] * xi[q][v];
-      }
-      C2j[o] = wr;
-      C2j[plane + o] = wi;
-    }
-  }
-}
-
 // Stage epilogues through LDS.  Each plane of a TD x TD output tile is
 // written to LDS in the kernel's MFMA layout, then emitted by every thread
 // as runs of four consecutive columns of a row (TD / 4 threads per row), so
