@@ -189,7 +189,6 @@ __device__ __forceinline__ void ctile64(const TOp<T> &A, const TOp<T> &B, int i0
 // loaded into registers while the current chunk is multiplied.
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BF_BK = 32;
 constexpr int BF_LDK = BF_BK + 8;
@@ -227,9 +226,11 @@ typedef BfLdsT<64, 64> BfLds;
 
 // Slot s (0 <= s < 4 TM) of a TM x 32 chunk -> (outer index, group of 8
 // inner indices).  Slots s and s + 256 belong to one thread.
-// KC: each wavefront covers 16 whole rows (lane l: row l % 16, group l / 16),
-// so a wave's loads touch 16 full 128-byte row segments and the 8 (or 16)
-// lanes of one LDS write cycle hit 8 (16) different rows: no bank conflicts.
+// KC: four consecutive lanes cover one row's 32 inner indices (one 128-byte
+// segment per plane); otherwise consecutive lanes take consecutive outer
+// indices of one group.  (Lanes of one row group spread over 16 rows would
+// avoid the two-way LDS bank conflict of the KC stores, but cost registers
+// and measured slower.)
 template <bool KC, int TM> __device__ __forceinline__ void bf_slot(int s, int &i, int &kq) {
   if (KC) {
     i = s >> 2;
