@@ -46,8 +46,8 @@ TRAFFIC = {
     ("c2_transmon_cnot", "taylor"): ("k_expm16", 615810, 18857632),
     ("c2_transmon_cnot", "bwd_blocks"): ("k_wB2", 2872874, 160384),
     ("c2_transmon_cnot", "fwd_replay"): ("k_wF3s", 36083954, 1184768),
-    ("c4_spin_chain", "taylor"): ("k_stage64", 8680494522, 2516582400),
-    ("c3_transmon_cavity", "taylor"): ("k_stage64", 1939557073, 737280000),
+    ("c4_spin_chain", "taylor"): ("k_stage64", 8655107148, 2516582400),
+    ("c3_transmon_cavity", "taylor"): ("k_stage64", 1933738424, 737280000),
 }
 
 
