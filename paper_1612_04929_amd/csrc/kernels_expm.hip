@@ -141,9 +141,9 @@ __device__ __forceinline__ void stage_store(const StageArgs<T> &a, long j, int r
   }
 }
 
-// Stage epilogues through LDS.  Each plane of a TD x TD output tile is
+// Stage epilogues through LDS.  Each plane of a TR x TC output tile is
 // written to LDS in the kernel's MFMA layout, then emitted by every thread
-// as runs of four consecutive columns of a row (TD / 4 threads per row), so
+// as runs of four consecutive columns of a row (TC / 4 threads per row), so
 // the addends are read and the outputs written as 16-byte vectors, whole
 // row segments per wavefront, all loads of a run before its stores.  The
 // coefficients are real, so the planes are independent.  Rows and columns
@@ -161,10 +161,10 @@ __device__ __forceinline__ void st4(T *p, const T (&v)[4]) {
   }
 }
 
-template <typename T, int TD>
+template <typename T, int TR, int TC = TR>
 __device__ __forceinline__ void stage_emit_plane(const StageArgs<T> &a, long j, int r0, int c0,
                                                  const T *sm, int pl) {
-  constexpr int LD = TD + EP_PAD, TPR = TD / 4, RPP = 256 / TPR;
+  constexpr int LD = TC + EP_PAD, TPR = TC / 4, RPP = 256 / TPR;
   const int t = threadIdx.x;
   const long plane = (long)a.dp * a.dp;
   const bool needA = a.betaA != (T)0 || (a.C2 && a.c2A != (T)0);
@@ -175,7 +175,7 @@ __device__ __forceinline__ void stage_emit_plane(const StageArgs<T> &a, long j, 
   T *C2j = a.C2 ? a.C2 + oc : nullptr;
   const int rr = t / TPR, cc = 4 * (t % TPR);
 #pragma unroll
-  for (int q = 0; q < TD / RPP; ++q) {
+  for (int q = 0; q < TR / RPP; ++q) {
     const int row = rr + RPP * q;
     if (r0 + row >= a.dp || c0 + cc >= a.dp) continue;
     const long o = pl * plane + (long)(r0 + row) * a.dp + c0 + cc;
@@ -208,6 +208,31 @@ __device__ __forceinline__ void stage_emit_plane(const StageArgs<T> &a, long j, 
     }
     st4(Cj + o, c);
     if (C2j) st4(C2j + o, c2);
+  }
+}
+
+// (32 MT) x (32 NT) tiles: wave w holds rows 16 MT (w >> 1) + 16 m + acc_row,
+// columns 16 NT (w & 1) + 16 n + lane % 16.  sm holds 32 MT x (32 NT + 4)
+// elements.
+template <typename T, int MT, int NT>
+__device__ __forceinline__ void stage_epilogue_t(const StageArgs<T> &a, long j, int r0, int c0,
+                                                 T *sm, const v4<T> (&acc)[MT][NT][2]) {
+  constexpr int LD = 32 * NT + EP_PAD;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = (w >> 1) * 16 * MT, wc = (w & 1) * 16 * NT;
+#pragma unroll
+  for (int pl = 0; pl < 2; ++pl) {
+    __syncthreads();  // the previous use of sm is done
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int n = 0; n < NT; ++n)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          sm[(wr + 16 * m + acc_row<T>(lane, v)) * LD + wc + 16 * n + (lane & 15)] =
+              acc[m][n][pl][v];
+    __syncthreads();
+    stage_emit_plane<T, 32 * MT, 32 * NT>(a, j, r0, c0, sm, pl);
   }
 }
 
@@ -265,7 +290,7 @@ template <typename T, int OPA, bool PF>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, 256),
                           amdgpu_waves_per_eu(sizeof(T) == 8 && !PF ? 3 : 1)))
 void k_stage64(StageArgs<T> a, long padded) {
-  __shared__ T lds[T64_LDS_ELEMS];
+  __shared__ __align__(16) T lds[T64_LDS_ELEMS];
   const int t1 = a.dp >> 6;
   const long tiles = (long)t1 * t1;
   const long logical = xcd_logical_block(blockIdx.x, padded);
@@ -288,6 +313,35 @@ void k_stage64(StageArgs<T> a, long padded) {
   stage_epilogue64<T>(a, j, r0, c0, lds, acc);
 }
 
+// dp a multiple of 32 MT and of 32 NT: one workgroup per (32 MT) x (32 NT)
+// output tile (wg_cgemm), the same LDS epilogue and XCD-aware block order.
+template <typename T, int OPA, int MT, int NT>
+__global__ __launch_bounds__(256) void k_stage_t(StageArgs<T> a, long padded) {
+  constexpr int TM = 32 * MT, TN = 32 * NT;
+  constexpr int LE = tcg_lds_elems<TM, TN>(), LP = TM * (TN + EP_PAD);
+  __shared__ __align__(16) T lds[LE > LP ? LE : LP];
+  const int tr = a.dp / TM, tc = a.dp / TN;
+  const long tiles = (long)tr * tc;
+  const long logical = xcd_logical_block(blockIdx.x, padded);
+  if (logical >= (long)a.nmat * tiles) return;  // block-uniform
+  const long j = logical / tiles;
+  const int t = (int)(logical - j * tiles);
+  const int r0 = (t / tc) * TM, c0 = (t % tc) * TN;
+  const long plane = (long)a.dp * a.dp;
+  CView<const T> A = cview<const T>(a.A + moff(a, j, a.strideA, a.segA), plane, a.dp);
+  CView<const T> B = cview<const T>(a.B + moff(a, j, a.strideB, a.segB), plane, a.dp);
+  v4<T> acc[MT][NT][2];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      acc[m][n][0] = vzero<T>();
+      acc[m][n][1] = vzero<T>();
+    }
+  wg_cgemm<T, OPA, MT, NT>(A, B, r0, c0, a.dp, lds, acc);
+  stage_epilogue_t<T, MT, NT>(a, j, r0, c0, lds, acc);
+}
+
 // dp a multiple of 16 but not of 64 (80, 96, 112, ...): one workgroup per
 // 32x32 output tile (4 waves, one 16x16 MFMA tile each), operand chunks of
 // 16 inner indices staged in LDS; rows / columns beyond dp read as zero and
@@ -297,7 +351,7 @@ constexpr int T32_BK = 16, T32_LD = 32 + 16;
 
 template <typename T, int OPA>
 __global__ __launch_bounds__(256) void k_stage32(StageArgs<T> a, long padded) {
-  __shared__ T lds[4 * T32_BK * T32_LD];
+  __shared__ __align__(16) T lds[4 * T32_BK * T32_LD];
   T *Asr = lds, *Asi = Asr + T32_BK * T32_LD;
   T *Bsr = Asi + T32_BK * T32_LD, *Bsi = Bsr + T32_BK * T32_LD;
   const int t1 = (a.dp + 31) >> 5;
@@ -461,6 +515,23 @@ template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hi
                            padded);
       else
         hipLaunchKernelGGL((k_stage64_bf3<0>), dim3((unsigned)padded), dim3(256), 0, st, a,
+                           padded);
+      return hipGetLastError();
+    }
+  }
+  // FP32, padded d a multiple of 128 and at least 256: 64 x 128 tiles (each
+  // wave 32 x 64), the same sums as the 64 x 64 tiles; the wider tile
+  // halves the A-operand traffic per flop (spin chain: 8.13 -> 8.02 ms per
+  // product; at d_pad 128 the 64 x 64 tiles keep more workgroups busy)
+  if constexpr (sizeof(T) == 4) {
+    if (a.dp % 128 == 0 && a.dp >= 256) {
+      const long total = (long)a.nmat * (a.dp / 64) * (a.dp / 128);
+      const long padded = (total + 7) / 8 * 8;
+      if (opa)
+        hipLaunchKernelGGL((k_stage_t<T, 1, 2, 4>), dim3((unsigned)padded), dim3(256), 0, st, a,
+                           padded);
+      else
+        hipLaunchKernelGGL((k_stage_t<T, 0, 2, 4>), dim3((unsigned)padded), dim3(256), 0, st, a,
                            padded);
       return hipGetLastError();
     }

@@ -206,6 +206,97 @@ __device__ __forceinline__ void wg_cgemm64(CView<const T> A, CView<const T> B, i
   }
 }
 
+// The same product on a (32 MT) x (32 NT) tile: wave w owns the
+// (16 MT) x (16 NT) sub-tile (16 MT (w >> 1), 16 NT (w & 1)) as MT x NT
+// MFMA tiles; chunks of 16 inner indices, LDS row stride tile + 16.  lds
+// holds 2 T64_BK (TM + TN + 32) elements.
+template <int TM, int TN> constexpr int tcg_lds_elems() { return 2 * T64_BK * (TM + TN + 32); }
+
+template <typename T, int OPA, int MT, int NT>
+__device__ __forceinline__ void wg_cgemm(CView<const T> A, CView<const T> B, int r0, int c0,
+                                         int K, T *lds, v4<T> (&acc)[MT][NT][2]) {
+  constexpr int TM = 32 * MT, TN = 32 * NT, LDA = TM + 16, LDB = TN + 16;
+  constexpr int UA = TM / 64, UB = TN / 64;  // 4-element groups per thread and plane
+  T *Asr = lds;
+  T *Asi = Asr + T64_BK * LDA;
+  T *Bsr = Asi + T64_BK * LDA;
+  T *Bsi = Bsr + T64_BK * LDB;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  const int wr = (w >> 1) * 16 * MT, wc = (w & 1) * 16 * NT;
+  const int ar_ = t >> 2, akq = (t & 3) * 4;   // OPA = 0: row (+ 64 u), inner offset
+  const int ak = t >> 4, arq = (t & 15) * 4;   // OPA = 1: inner, row offset (+ 64 u)
+  const int bk = t >> 4, bcq = (t & 15) * 4;   // inner, column offset (+ 64 u)
+  T va[UA][2][4], vb[UB][2][4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      const long oa = OPA == 0 ? (long)(r0 + ar_ + 64 * u) * A.ld + k0 + akq
+                               : (long)(k0 + ak) * A.ld + r0 + arq + 64 * u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        va[u][0][q] = A.re[oa + q];
+        va[u][1][q] = A.im[oa + q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const long ob = (long)(k0 + bk) * B.ld + c0 + bcq + 64 * u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        vb[u][0][q] = B.re[ob + q];
+        vb[u][1][q] = B.im[ob + q];
+      }
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += T64_BK) {
+#pragma unroll
+    for (int u = 0; u < UA; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (OPA == 0) {
+          Asr[(akq + q) * LDA + ar_ + 64 * u] = va[u][0][q];
+          Asi[(akq + q) * LDA + ar_ + 64 * u] = va[u][1][q];
+        } else {
+          Asr[ak * LDA + arq + 64 * u + q] = va[u][0][q];
+          Asi[ak * LDA + arq + 64 * u + q] = -va[u][1][q];
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < UB; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Bsr[bk * LDB + bcq + 64 * u + q] = vb[u][0][q];
+        Bsi[bk * LDB + bcq + 64 * u + q] = vb[u][1][q];
+      }
+    lds_barrier();
+    if (k0 + T64_BK < K) load(k0 + T64_BK);  // uniform
+#pragma unroll
+    for (int k4 = 0; k4 < T64_BK; k4 += 4) {
+      T br[NT], bi[NT];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        br[n] = Bsr[(k4 + kk) * LDB + wc + 16 * n + i];
+        bi[n] = Bsi[(k4 + kk) * LDB + wc + 16 * n + i];
+      }
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const T ar = Asr[(k4 + kk) * LDA + wr + 16 * m + i];
+        const T ai = Asi[(k4 + kk) * LDA + wr + 16 * m + i];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          acc[m][n][0] = mfma4(ar, br[n], acc[m][n][0]);
+          acc[m][n][0] = mfma4(-ai, bi[n], acc[m][n][0]);
+          acc[m][n][1] = mfma4(ar, bi[n], acc[m][n][1]);
+          acc[m][n][1] = mfma4(ai, br[n], acc[m][n][1]);
+        }
+      }
+    }
+    lds_barrier();  // the chunk's LDS reads are done; the prefetch stays in flight
+  }
+}
+
 // Blocks of a 1-D launch are dispatched round-robin over the 8 XCDs of an
 // MI355X.  Re-map the block index so that consecutive logical blocks (the
 // tiles of one matrix, which share operand panels) land on the same XCD
