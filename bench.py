@@ -587,6 +587,14 @@ def main():
         h64.close()
         res["fp64_own_kernels"] = dict(value=prob.N / t64, unit="time-steps/s",
                                        ms_per_step=t64 * 1e3, reps=reps)
+        golden64 = os.path.join(ROOT, "tests", "golden", f"{args.config}_full_oracle.npz")
+        if os.path.exists(golden64):
+            with np.load(golden64) as z:
+                g = g64[: prob.M * prob.N].cpu().numpy().reshape(prob.M, prob.N)
+                res["fp64_own_kernels"]["accuracy_vs_oracle"] = dict(
+                    dF=abs((1 - float(o64[1])) - float(z["F"])),
+                    grad_rel=float(np.linalg.norm(g - z["grad"]) / np.linalg.norm(z["grad"])),
+                    max_dc=float(np.max(np.abs(o64[2:].cpu().numpy() - z["c"]))))
     if not args.no_extras:
         # the same call in the other precision and on the other workloads of
         # the metric's range (tuned the same way), as extra keys
@@ -619,6 +627,11 @@ def main():
                 t71 = dict(checkpoint_every=71, sweep=tq["sweep"] if tq else [0, 0, 0, 0])
                 res["other_workloads"]["c3_checkpoint_71"] = quick_measure(q, args.precision,
                                                                             args, t71)
+                if args.precision == "fp32":
+                    # the transmon-cavity workload in the other two precisions,
+                    # each with its error against the stored oracle outputs
+                    for prec in ("bf16x3", "fp64"):
+                        res["other_workloads"][f"c3_{prec}"] = quick_measure(q, prec, args, tq)
     if not args.no_torch_baseline:
         tb = fp64_torch_path(prob, dev)
         g64 = tb.pop("grad")

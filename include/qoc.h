@@ -188,7 +188,12 @@ typedef struct {
   int d_pad;                /* device padding of d (multiple of 16)          */
   int flags;                /* warning bits (QOC_WARN_*) of the last call    */
   size_t device_bytes;      /* device memory held by the handle              */
-  int bf16x3_classes;       /* QOC_BF3_* classes that ran bf16x3 products     */
+  int bf16x3_classes;       /* QOC_BF3_* classes that ran bf16x3 products in
+                               the last call: the chain classes need padded
+                               d a multiple of 64, and the derivative's class
+                               counts only if one of its products was wide
+                               enough (64 columns) or dense enough to have a
+                               split kernel                                  */
   double unitarity_drift;   /* max over the checked steps of
                                max_{r,c} |(D_j + D_j^H + D_j^H D_j)_{rc}| =
                                |(U_j^H U_j - I)_{rc}|, evaluated in FP64 (kept
@@ -362,7 +367,11 @@ qoc_status qoc_set_taylor(qoc_handle *h, int p, int n);
  * by the later squarings (norms from theta_max, n and the squaring levels),
  * and grows as sqrt(N) over the steps.  Any class left in FP32 by the
  * automatic choice sets QOC_WARN_PRECISION.  With a fixed (p, n) the index
- * uses the largest theta the pair admits.  No effect on other precisions.
+ * uses the largest theta the pair admits.  Products without a split kernel
+ * at the handle's shapes (chain products at padded d not a multiple of 64;
+ * thin derivative products narrower than 64 columns; the sparse gradient
+ * contraction) run in FP32 and are left out of qoc_info.bf16x3_classes
+ * (without QOC_WARN_PRECISION).  No effect on other precisions.
  * Returns QOC_ERR_ARG for a mask outside -1..QOC_BF3_ALL.  Sec. III
  * (truncated Taylor series with scaling and squaring), Sec. II.B. */
 qoc_status qoc_set_bf16x3(qoc_handle *h, int classes);

@@ -757,10 +757,11 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
     if (tb.W >= 64) {
       const long total = (long)tb.nhalf * N * ((dp + 63) / 64) * ((tb.W + 63) / 64);
       const long padded = (total + 7) / 8 * 8;
-      if (bf3)
+      if (bf3) {
         hipLaunchKernelGGL((k_thin64<T, true>), dim3((unsigned)padded), dim3(256), 0, st, tb,
                            padded);
-      else
+        if (a.bf3_launched) *a.bf3_launched = 1;
+      } else
         hipLaunchKernelGGL((k_thin64<T, false>), dim3((unsigned)padded), dim3(256), 0, st, tb,
                            padded);
       return hipGetLastError();
@@ -776,10 +777,12 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
   };
   auto launch_xstore = [&](XStore<T> &xs) -> hipError_t {
     const long rp = (dp + 63) / 64, total = (long)N * rp * rp, padded = (total + 7) / 8 * 8;
-    if (bf3)
+    if (bf3) {
       hipLaunchKernelGGL((k_xstore<T, true>), dim3((unsigned)padded), dim3(256), 0, st, xs, padded);
-    else
+      if (a.bf3_launched) *a.bf3_launched = 1;
+    } else {
       hipLaunchKernelGGL((k_xstore<T, false>), dim3((unsigned)padded), dim3(256), 0, st, xs, padded);
+    }
     return hipGetLastError();
   };
   const BOp<T> Ablk = blk(0, R, thin), Bblk = blk(2 * thin, R, thin);

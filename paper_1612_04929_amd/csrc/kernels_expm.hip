@@ -503,10 +503,12 @@ hipError_t launch_assemble(const T *Hf, const double *u, int dp, int M, int N, T
   return hipGetLastError();
 }
 
+bool stage_bf3_ok(int dp) { return dp % 64 == 0; }
+
 template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hipStream_t st) {
   if (a.nmat <= 0) return hipSuccess;
   if constexpr (sizeof(T) == 4) {
-    if (a.bf3 && a.dp % 64 == 0) {
+    if (a.bf3 && stage_bf3_ok(a.dp)) {
       const long t1 = a.dp / 64;
       const long total = (long)a.nmat * t1 * t1;
       const long padded = (total + 7) / 8 * 8;

@@ -198,7 +198,8 @@ struct qoc_handle {
   int d = 0, dp = 0, M = 0, N = 0, S = 0, prec = QOC_FP32, fid_mode = 0;
   int bf3 = 0;  // bf16x3 split products in the batched chains (padded d >= 64)
   int bf3_req = -1;  // classes allowed bf16x3 products (QOC_BF3_* bits), -1 automatic
-  int bf3_used = 0;  // classes that ran bf16x3 products in the last call
+  int bf3_used = 0;  // classes the last call asked to run as bf16x3 products
+  int bf3_adj_ran = 0;  // the last call launched split products in the derivative
   int bf3_fallback = 0;  // the automatic choice moved some classes to FP32
   bool capturing = false;  // the current call's stream is capturing a HIP graph
   // FP64 unitarity check of the step propagators: every `unit_stride`-th
@@ -1163,7 +1164,10 @@ qoc_status prepare_large(qoc_handle *h, int p, int n, bool want_grad, int Rcap) 
       h->bf3_fallback = cls != QOC_BF3_ALL;
     }
   }
+  // the chain classes have split kernels only for padded d a multiple of 64
+  if (!qoc::stage_bf3_ok(h->dp)) cls &= QOC_BF3_ADJOINT;
   h->bf3_used = cls;
+  h->bf3_adj_ran = 0;
   return QOC_OK;
 }
 
@@ -1490,6 +1494,7 @@ qoc_status run(qoc_handle *h, const double *u_dev, double *out_dev, double *grad
     ad.part = h->adj_part;
     ad.xbar = Qa;  // the Taylor work space is free once the sweeps are done
     ad.bf3 = (h->bf3_used & QOC_BF3_ADJOINT) ? 1 : 0;
+    ad.bf3_launched = &h->bf3_adj_ran;
     ad.with_total = total_in_adjoint ? 1 : 0;
     ad.total = qoc::total_args(sw);
     if (sp_on && big) {
@@ -1612,6 +1617,7 @@ qoc_status run_segmented(qoc_handle *h, const double *u_dev, double *out_dev, do
     ad.grad = grad_dev; ad.part = h->adj_part;
     ad.xbar = (T *)h->Qa;  // the Taylor work space is free once the sweeps are done
     ad.bf3 = (h->bf3_used & QOC_BF3_ADJOINT) ? 1 : 0;
+    ad.bf3_launched = &h->bf3_adj_ran;
     ad.total = qoc::total_args(all);
     ad.j0 = (long)g * Ns;
     ad.ldN = N;
@@ -1673,6 +1679,7 @@ qoc_status run_action(qoc_handle *h, const double *u_dev, double *out_dev, doubl
   h->last_p = p;
   h->last_n = n;
   h->bf3_used = 0;
+  h->bf3_adj_ran = 0;
   h->bf3_fallback = 0;
   h->unit_epoch = 0;  // no step propagator to check
   const bool first_order = h->grad_mode == QOC_GRAD_FIRST_ORDER;
@@ -2272,7 +2279,10 @@ qoc_status qoc_get_info(const qoc_handle *hc, qoc_info *info) {
   info->n_blocks = h->nb;
   info->d_pad = h->dp;
   info->device_bytes = h->bytes;
-  info->bf16x3_classes = h->bf3_used;
+  // classes that ran split products: the derivative's only where a split
+  // product was launched (narrow thin products and the sparse contraction
+  // have FP32 kernels only)
+  info->bf16x3_classes = h->bf3_adj_ran ? h->bf3_used : (h->bf3_used & ~QOC_BF3_ADJOINT);
   info->unitarity_drift = h->last_unitarity;
   info->structured = h->sp_used ? 1 : 0;
   info->segments = h->nseg;

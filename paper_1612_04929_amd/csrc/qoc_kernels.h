@@ -44,6 +44,10 @@ hipError_t launch_assemble(const T *Hf, const double *u, int dp, int M, int N, T
 
 template <typename T> hipError_t launch_stage(int opa, const StageArgs<T> &a, hipStream_t st);
 
+// Whether launch_stage runs bf16x3 split products for padded d dp (when
+// StageArgs.bf3 asks for them); otherwise the chain precision's kernels run.
+bool stage_bf3_ok(int dp);
+
 // Each workgroup of the norm kernel folds its maximum into `acc` (atomic
 // max on the FP64 bit pattern) and takes a number from `ticket`; the last
 // one (both words zero at the first launch and cleared by that workgroup)
@@ -253,6 +257,7 @@ template <typename T> struct AdjointArgs {
   double *part;        // batched variant: N x slices x M partial sums
   T *xbar;             // batched variant: N x 2 dp^2 work space for Xbar_j
   int bf3;             // batched variant: bf16x3 split products
+  int *bf3_launched;   // host flag, may be null: set to 1 when a split product is launched
   int with_total;      // padded d 16: one extra workgroup reduces the cost (total)
   TotalArgs total;
   // batched variant with structured control Hamiltonians (rptr null:

@@ -43,19 +43,28 @@ def test_bf16x3_random(name, d, S, N, mode, seed):
 
 
 def test_bf16x3_forced_classes_and_flag():
-    """qoc_set_bf16x3 forces a class mask; the automatic choice reports the
-    classes it ran and flags the ones it moved to FP32."""
+    """qoc_set_bf16x3 forces a class mask; the automatic choice flags the
+    classes it moved to FP32; the reported classes are the ones that ran
+    split products.  The transmon-cavity derivative (rank 16, sparse
+    contraction) has no product wide enough for a split kernel: its class
+    runs in FP32 unless the dense contraction (a d x d product) is used."""
     from paper_1612_04929_amd import qoc
+    chain = qoc.QOC_BF3_TAYLOR | qoc.QOC_BF3_SQUARING | qoc.QOC_BF3_BLOCKPROD
     p = workloads.config3().with_steps(400)
     h = qoc.Problem(p, precision="bf16x3", checkpoint_every=16)
     say("[bf3] c3 N=400 class masks")
     out = h.cost_grad(p.u)
-    assert out["bf16x3_classes"] == qoc.QOC_BF3_ADJOINT
+    assert out["structured"] == 1
+    assert out["bf16x3_classes"] == 0  # the policy's choice (derivative) ran in FP32
     assert out["flags"] & qoc.QOC_WARN_PRECISION
     h.set_bf16x3(qoc.QOC_BF3_ALL)
     out = h.cost_grad(p.u)
-    assert out["bf16x3_classes"] == qoc.QOC_BF3_ALL
+    assert out["bf16x3_classes"] == chain
     assert not out["flags"] & qoc.QOC_WARN_PRECISION
+    h.set_structure(0)  # dense contraction: the stored Xbar product runs split
+    out = h.cost_grad(p.u)
+    assert out["bf16x3_classes"] == qoc.QOC_BF3_ALL
+    h.set_structure(-1)
     h.set_bf16x3(0)
     r0 = h.cost_grad(p.u)
     h.close()
