@@ -122,6 +122,8 @@ def test_config2_transmon_cnot_full():
     (3, 2, 1, "coherent"),         # a single step
     (64, 48, 20, "coherent"),      # batched adjoint: rank compression at the first level
     (100, 3, 25, "incoherent"),    # batched adjoint on pad 112 (partial 64-tiles)
+    (256, 2, 8, "coherent"),       # 64 x 128 stage tiles (4 x 2 per matrix)
+    (384, 3, 5, "incoherent"),     # 64 x 128 stage tiles (6 x 3 per matrix)
 ])
 def test_random_problems(d, S, N, mode):
     rng = np.random.default_rng(100 + d + N)
@@ -190,6 +192,17 @@ def test_batched_taylor_orders(pn):
     rng = np.random.default_rng(41)
     p = workloads.random_problem(rng, d=70, M=2, N=30, S=2, dt=0.15, scale=1.5)
     out, ref, e = compare(f"orders_p{pn[0]}_n{pn[1]}", p, taylor_pn=pn)
+    check(p, e)
+    assert (e["p"], e["n"]) == pn
+
+
+@pytest.mark.parametrize("pn", [(9, 2), (12, 1), (10, 0)])
+def test_wide_tile_taylor_orders(pn):
+    # padded d 256 (64 x 128 stage tiles): Paterson-Stockmeyer blocks with
+    # a second output, extra addends and both endings, then squarings
+    rng = np.random.default_rng(43)
+    p = workloads.random_problem(rng, d=256, M=2, N=6, S=2, dt=0.1, scale=1.5)
+    out, ref, e = compare(f"wide_orders_p{pn[0]}_n{pn[1]}", p, taylor_pn=pn)
     check(p, e)
     assert (e["p"], e["n"]) == pn
 
