@@ -897,11 +897,11 @@ bool taylor_select_ps(double theta, double tol, int *p_out, int *n_out) {
 // bf16x3 handles under the automatic class policy: the pair whose Taylor
 // products and squarings take the least modelled time, a split product
 // counting kBf3ProductCost of an FP32 one (full-grid products at d = 512:
-// 4.36 ms split against 8.39 ms in FP32), with the classes the policy
+// 3.23 ms split against 7.99 ms in FP32), with the classes the policy
 // allows at that pair (fewer squarings raise theta / 2^n and with it the
 // split's error index, so the cheapest pair in products may run unsplit);
 // ties toward the lower order p.
-constexpr double kBf3ProductCost = 0.52;
+constexpr double kBf3ProductCost = 0.40;
 bool taylor_select_bf3(double theta, double tol, int N, int L, int *p_out, int *n_out) {
   double best = -1.0;
   int bp = 0, bn = 0;
