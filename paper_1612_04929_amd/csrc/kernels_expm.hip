@@ -461,11 +461,14 @@ __global__ __launch_bounds__(256) void k_stage32(StageArgs<T> a, long padded) {
 
 // bf16x3 variant of k_stage64 (FP32 storage; the split-product tile of
 // qoc_tile.h): one workgroup per 64 x 64 output tile, 4 waves of 32 x 32,
-// the same LDS epilogue and XCD-aware block order.  (Tiles of 128 x 64 and
-// 64 x 128, and a second chunk of operands in registers, were slower: they
-// cost occupancy, and the split products need the latency hiding.)
+// the same LDS epilogue and XCD-aware block order, four wavefronts per SIMD
+// (each chunk loaded just before its stores: the registers of a register
+// prefetch would leave three).  Tiles of 128 x 64 and 64 x 128, and a
+// second chunk of operands in registers, were slower: they cost occupancy,
+// and the split products need the latency hiding.
 template <int OPA>
-__global__ __launch_bounds__(256) void k_stage64_bf3(StageArgs<float> a, long padded) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, 256), amdgpu_waves_per_eu(4, 4)))
+void k_stage64_bf3(StageArgs<float> a, long padded) {
   __shared__ BfLds L;
   const int t1 = a.dp >> 6;
   const long tiles = (long)t1 * t1;
@@ -489,7 +492,7 @@ __global__ __launch_bounds__(256) void k_stage64_bf3(StageArgs<float> a, long pa
   // conjugated; B as stored: inner index along columns of B.  The tiles lie
   // inside the matrices (dp a multiple of 64, d <= 1024: both planes of a
   // matrix within 2^31 bytes).
-  ctile_bf3<2, 2, OPA == 0, OPA == 1, false, false, true>(A, B, r0, c0, a.dp, L, acc);
+  ctile_bf3<2, 2, OPA == 0, OPA == 1, false, false, true, false>(A, B, r0, c0, a.dp, L, acc);
   stage_epilogue64<float>(a, j, r0, c0, (float *)&L, acc);
 }
 

@@ -186,7 +186,8 @@ __device__ __forceinline__ void ctile64(const TOp<T> &A, const TOp<T> &B, int i0
 // LDS holds each operand chunk as [plane][outer][k] (k contiguous, row
 // stride 40 halves), planes re_hi, re_lo, im_hi, im_lo, so each lane's
 // MFMA operand is one 16-byte LDS read.  The next chunk's FP32 values are
-// loaded into registers while the current chunk is multiplied.
+// loaded into registers while the current chunk is multiplied (or, for the
+// stage products, just before its stores, at one more wavefront per SIMD).
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -338,7 +339,8 @@ __device__ __forceinline__ void bf_store_op(int s, const float (&vr)[8], const f
 // at (i0, j0).  All 256 threads must call.  Every accumulator receives its
 // terms in the same order whatever MT and NT, so tiles of any shape give
 // the same sums.
-template <int MT, int NT, bool AKC, bool ACJ, bool BKC, bool BCJ, bool FULL = false>
+template <int MT, int NT, bool AKC, bool ACJ, bool BKC, bool BCJ, bool FULL = false,
+          bool PF = true>
 __device__ __forceinline__ void ctile_bf3(const TOp<float> &A, const TOp<float> &B, int i0,
                                           int j0, int K, BfLdsT<32 * MT, 32 * NT> &L,
                                           f32x4 (&acc)[MT][NT][2]) {
@@ -375,14 +377,18 @@ __device__ __forceinline__ void ctile_bf3(const TOp<float> &A, const TOp<float> 
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int n = 0; n < NT; ++n) accn[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  load(0);
+  // PF: the next chunk is loaded into registers while the current one is
+  // multiplied; without it each chunk is loaded just before its stores
+  // (fewer registers: one more wavefront per SIMD hides the latency)
+  if (PF) load(0);
   for (int k0 = 0; k0 < K; k0 += BF_BK) {
+    if (!PF) load(k0);
 #pragma unroll
     for (int u = 0; u < UA; ++u) bf_store_op<AKC, TM>(t + 256 * u, ar[u], ai[u], L.a);
 #pragma unroll
     for (int u = 0; u < UB; ++u) bf_store_op<BKC, TN>(t + 256 * u, br[u], bi[u], L.b);
     __syncthreads();
-    if (k0 + BF_BK < K) load(k0 + BF_BK);  // block-uniform
+    if (PF && k0 + BF_BK < K) load(k0 + BF_BK);  // block-uniform
     bf16x8 fb[NT][4];
 #pragma unroll
     for (int n = 0; n < NT; ++n)
