@@ -315,8 +315,12 @@ void k_stage64(StageArgs<T> a, long padded) {
 
 // dp a multiple of 32 MT and of 32 NT: one workgroup per (32 MT) x (32 NT)
 // output tile (wg_cgemm), the same LDS epilogue and XCD-aware block order.
+// FP32: four wavefronts per SIMD (the compiler fits the register prefetch
+// in 128 registers when asked; left alone it takes three)
 template <typename T, int OPA, int MT, int NT>
-__global__ __launch_bounds__(256) void k_stage_t(StageArgs<T> a, long padded) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, 256),
+                          amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+void k_stage_t(StageArgs<T> a, long padded) {
   constexpr int TM = 32 * MT, TN = 32 * NT;
   constexpr int LE = tcg_lds_elems<TM, TN>(), LP = TM * (TN + EP_PAD);
   __shared__ __align__(16) T lds[LE > LP ? LE : LP];
