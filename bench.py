@@ -46,7 +46,7 @@ TRAFFIC = {
     ("c2_transmon_cnot", "taylor"): ("k_expm16", 615810, 18857632),
     ("c2_transmon_cnot", "bwd_blocks"): ("k_wB2", 2872874, 160384),
     ("c2_transmon_cnot", "fwd_replay"): ("k_wF3s", 36083954, 1184768),
-    ("c4_spin_chain", "taylor"): ("k_stage_t", 7272536014, 2516582400),
+    ("c4_spin_chain", "taylor"): ("k_stage_t", 7380331861, 2516582400),
     ("c3_transmon_cavity", "taylor"): ("k_stage64", 1933738424, 737280000),
 }
 
