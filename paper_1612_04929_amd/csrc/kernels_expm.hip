@@ -236,30 +236,6 @@ __device__ __forceinline__ void stage_epilogue_t(const StageArgs<T> &a, long j, 
   }
 }
 
-// 64 x 64 tiles: wave w holds rows 32 (w >> 1) + 16 m + acc_row, columns
-// 32 (w & 1) + 16 n + lane % 16.  sm holds 64 x 68 elements.
-template <typename T>
-__device__ __forceinline__ void stage_epilogue64(const StageArgs<T> &a, long j, int r0, int c0,
-                                                 T *sm, const v4<T> (&acc)[2][2][2]) {
-  constexpr int LD = 64 + EP_PAD;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-#pragma unroll
-  for (int pl = 0; pl < 2; ++pl) {
-    __syncthreads();  // the previous use of sm is done
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int n = 0; n < 2; ++n)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          sm[(wr + 16 * m + acc_row<T>(lane, v)) * LD + wc + 16 * n + (lane & 15)] =
-              acc[m][n][pl][v];
-    __syncthreads();
-    stage_emit_plane<T, 64>(a, j, r0, c0, sm, pl);
-  }
-}
-
 // dp a multiple of 16: one wavefront per 16x16 output tile, operands read
 // straight from L1/L2 (small matrices: the whole matrix is a few tiles).
 template <typename T, int OPA>
@@ -310,7 +286,7 @@ void k_stage64(StageArgs<T> a, long padded) {
       acc[m][n][1] = vzero<T>();
     }
   wg_cgemm64<T, OPA, PF>(A, B, r0, c0, a.dp, lds, acc);
-  stage_epilogue64<T>(a, j, r0, c0, lds, acc);
+  stage_epilogue_t<T, 2, 2>(a, j, r0, c0, lds, acc);
 }
 
 // dp a multiple of 32 MT and of 32 NT: one workgroup per (32 MT) x (32 NT)
@@ -497,7 +473,7 @@ void k_stage64_bf3(StageArgs<float> a, long padded) {
   // inside the matrices (dp a multiple of 64, d <= 1024: both planes of a
   // matrix within 2^31 bytes).
   ctile_bf3<2, 2, OPA == 0, OPA == 1, false, false, true, false>(A, B, r0, c0, a.dp, L, acc);
-  stage_epilogue64<float>(a, j, r0, c0, (float *)&L, acc);
+  stage_epilogue_t<float, 2, 2>(a, j, r0, c0, (float *)&L, acc);
 }
 
 template <typename T>
