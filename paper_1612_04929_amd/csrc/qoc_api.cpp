@@ -896,23 +896,28 @@ bool taylor_select_ps(double theta, double tol, int *p_out, int *n_out) {
 
 // bf16x3 handles under the automatic class policy: the pair whose Taylor
 // products and squarings take the least modelled time, a split product
-// counting kBf3ProductCost of an FP32 one (full-grid products at d = 512:
-// 3.23 ms split against 7.99 ms in FP32), with the classes the policy
-// allows at that pair (fewer squarings raise theta / 2^n and with it the
-// split's error index, so the cheapest pair in products may run unsplit);
-// ties toward the lower order p.
-constexpr double kBf3ProductCost = 0.40;
-bool taylor_select_bf3(double theta, double tol, int N, int L, int *p_out, int *n_out) {
+// counting bf3_product_cost(d_pad) of an FP32 one (the measured ratio of the
+// stage kernels, every class split, pair (8, 2): d_pad 64 0.81, 128 0.56,
+// 256 0.50, 512 0.44; 1 where the chain has no split kernel), with the
+// classes the policy allows at that pair (fewer squarings raise
+// theta / 2^n and with it the split's error index, so the cheapest pair in
+// products may run unsplit); ties toward the lower order p.
+double bf3_product_cost(int dp) {
+  if (!qoc::stage_bf3_ok(dp)) return 1.0;
+  return dp <= 64 ? 0.81 : dp <= 128 ? 0.56 : dp <= 256 ? 0.50 : 0.44;
+}
+bool taylor_select_bf3(double theta, double tol, int N, int L, int dp, int *p_out, int *n_out) {
+  const double cost = bf3_product_cost(dp);
   double best = -1.0;
   int bp = 0, bn = 0;
   for (int n = 0; n < 60; ++n) {
     if (std::ldexp(theta, -n) > 1.0) continue;
-    if (best >= 0.0 && n * kBf3ProductCost >= best) break;
+    if (best >= 0.0 && n * cost >= best) break;
     for (int p = 2; p <= 30; ++p) {
       if (taylor_bound(theta, p, n) <= tol) {
         const int cls = bf3_auto_classes(theta, n, N, L);
-        const double t = batched_products(p) * ((cls & QOC_BF3_TAYLOR) ? kBf3ProductCost : 1.0) +
-                         n * ((cls & QOC_BF3_SQUARING) ? kBf3ProductCost : 1.0);
+        const double t = batched_products(p) * ((cls & QOC_BF3_TAYLOR) ? cost : 1.0) +
+                         n * ((cls & QOC_BF3_SQUARING) ? cost : 1.0);
         if (best < 0.0 || t < best - 1e-9 || (t <= best + 1e-9 && p < bp)) {
           best = t;
           bp = p;
@@ -1126,7 +1131,7 @@ qoc_status choose_pn_large(qoc_handle *h, const double *u_dev, hipStream_t st,
   if (!std::isfinite(theta)) return fail(QOC_ERR_NONFINITE, "non-finite step norm");
   const bool ok = action ? action_select(theta, h->tol, p, n)
                   : (h->bf3 && h->bf3_req < 0)
-                      ? taylor_select_bf3(theta, h->tol, h->N, h->L, p, n)
+                      ? taylor_select_bf3(theta, h->tol, h->N, h->L, h->dp, p, n)
                       : taylor_select_ps(theta, h->tol, p, n);
   if (!ok)
     return fail(QOC_ERR_UNSUPPORTED, "no (p, n) meets the tolerance for theta_max = " +
@@ -1850,7 +1855,7 @@ qoc_status qoc_pair_for(const qoc_handle *h, double theta, int *p, int *n) {
     if (!p || !n) return fail(QOC_ERR_ARG, "null output pointer");
     if (!(theta >= 0.0) || !std::isfinite(theta))
       return fail(QOC_ERR_ARG, "theta must be finite and >= 0");
-    if (!taylor_select_bf3(theta, h->tol, h->N, h->L, p, n))
+    if (!taylor_select_bf3(theta, h->tol, h->N, h->L, h->dp, p, n))
       return fail(QOC_ERR_UNSUPPORTED, "no (p, n) meets tol");
     return QOC_OK;
   }
