@@ -109,3 +109,18 @@ def test_bf16x3_equals_fp32_below_64():
     a.close()
     b.close()
     assert ra["C"] == rb["C"] and np.array_equal(ra["grad"], rb["grad"])
+
+
+def test_pair_rule_prices_split_products_by_padded_d():
+    """The bf16x3 pair rule weighs a split product by its measured cost at
+    the handle's padded d; where padded d has no split kernel (not a
+    multiple of 64) every product counts as an FP32 one, so the handle picks
+    the batched FP32 rule's pair."""
+    from paper_1612_04929_amd import qoc
+    rng = np.random.default_rng(77)
+    p = workloads.random_problem(rng, d=70, M=2, N=40, S=2, dt=0.2)
+    h = qoc.Problem(p, precision="bf16x3", pad_multiple=16)
+    assert h.info()["d_pad"] == 80
+    for theta in (0.3, 0.81, 1.7, 3.0, 5.5):
+        assert h.pair_for(theta) == qoc.select_pair(theta, 1e-10, qoc.QOC_FORM_BATCHED), theta
+    h.close()
