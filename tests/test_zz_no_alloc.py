@@ -3,7 +3,8 @@ qoc_cost_grad_device through the C ABI: the same cost, penalties and
 gradient, bit for bit (the same kernels on the same inputs; only where the
 per-call work space lives differs), on two calls in a row of which the
 second has a smaller input, and for several paths (padded d 16, a small
-chain at padded d 48, a batched large-d chain with a fixed pair, the
+chain at padded d 48, batched large-d chains with a fixed pair at padded
+d 64 and 256, the
 memory-lean mode's time segments, the action form); a call
 whose work space exceeds the static scratch is rejected with
 QOC_ERR_UNSUPPORTED."""
@@ -42,7 +43,8 @@ def run_both(prob, precision="fp32", **kw):
     return res
 
 
-@pytest.mark.parametrize("case", ["d16", "d40", "d64_fixed", "d70_segments", "action"])
+@pytest.mark.parametrize("case", ["d16", "d40", "d64_fixed", "d256_fixed", "d70_segments",
+                                  "action"])
 def test_noalloc_matches_device_entry_point_twice(case):
     rng = np.random.default_rng(900)
     if case == "d16":
@@ -55,6 +57,11 @@ def test_noalloc_matches_device_entry_point_twice(case):
     elif case == "d64_fixed":
         big = workloads.random_problem(rng, d=64, M=3, N=90, S=2, dt=0.2, scale=1.5)
         small = workloads.random_problem(rng, d=64, M=2, N=40, S=2, dt=0.2, scale=1.5)
+        kw = dict(taylor_pn=(9, 2))
+    elif case == "d256_fixed":
+        # 64 x 128 stage tiles
+        big = workloads.random_problem(rng, d=256, M=2, N=24, S=2, dt=0.1, scale=1.5)
+        small = workloads.random_problem(rng, d=256, M=2, N=10, S=1, dt=0.1, scale=1.5)
         kw = dict(taylor_pn=(9, 2))
     elif case == "d70_segments":
         # memory-lean mode: the segment's stacks carved from the scratch
