@@ -897,14 +897,14 @@ bool taylor_select_ps(double theta, double tol, int *p_out, int *n_out) {
 // bf16x3 handles under the automatic class policy: the pair whose Taylor
 // products and squarings take the least modelled time, a split product
 // counting bf3_product_cost(d_pad) of an FP32 one (the measured ratio of the
-// stage kernels, every class split, pair (8, 2): d_pad 64 0.81, 128 0.56,
-// 256 0.50, 512 0.44; 1 where the chain has no split kernel), with the
+// stage kernels, every class split, pair (8, 2): d_pad 64 0.79, 128 0.56,
+// 256 0.48, 512 0.42; 1 where the chain has no split kernel), with the
 // classes the policy allows at that pair (fewer squarings raise
 // theta / 2^n and with it the split's error index, so the cheapest pair in
 // products may run unsplit); ties toward the lower order p.
 double bf3_product_cost(int dp) {
   if (!qoc::stage_bf3_ok(dp)) return 1.0;
-  return dp <= 64 ? 0.81 : dp <= 128 ? 0.56 : dp <= 256 ? 0.50 : 0.44;
+  return dp <= 64 ? 0.79 : dp <= 128 ? 0.56 : dp <= 256 ? 0.48 : 0.42;
 }
 bool taylor_select_bf3(double theta, double tol, int N, int L, int dp, int *p_out, int *n_out) {
   const double cost = bf3_product_cost(dp);

@@ -183,16 +183,26 @@ __device__ __forceinline__ void ctile64(const TOp<T> &A, const TOp<T> &B, int i0
 // accumulation; the dropped lo*lo term and the two roundings leave a
 // relative error of a few 2^-18 per product.  The inner dimension runs in
 // chunks of 32 (one MFMA K; a ragged last chunk of 16 is zero-filled).
-// LDS holds each operand chunk as [plane][outer][k] (k contiguous, row
-// stride 40 halves), planes re_hi, re_lo, im_hi, im_lo, so each lane's
-// MFMA operand is one 16-byte LDS read.  The next chunk's FP32 values are
+// LDS holds each operand chunk as [plane][outer][k] (k contiguous, 64-byte
+// rows of four 16-byte groups, the group index XOR-ed with bits 1-2 of the
+// row), planes re_hi, re_lo, im_hi, im_lo, so each lane's MFMA operand is
+// one 16-byte LDS read.  The next chunk's FP32 values are
 // loaded into registers while the current chunk is multiplied (or, for the
 // stage products, just before its stores, at one more wavefront per SIMD).
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int BF_BK = 32;
-constexpr int BF_LDK = BF_BK + 8;
+constexpr int BF_LDK = BF_BK;
+
+// Position (in halves) of 16-byte group q of row r.  Against a padded row
+// stride of 40 halves, the swizzle keeps all three access patterns of the
+// tile free of LDS bank conflicts (by the hardware's conflict counters): the
+// fragment reads (16 consecutive rows, one group), the row-contiguous
+// stores (four lanes per row) and the across-row stores (one group of 64
+// consecutive rows); the padded stride has two-way conflicts on the first
+// two.  It also takes a quarter less LDS.
+__device__ __forceinline__ int bf_grp(int r, int q) { return 8 * (q ^ ((r >> 1) & 3)); }
 
 __device__ __forceinline__ f32x4 mfma_bf(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -326,12 +336,13 @@ __device__ __forceinline__ void bf_store_op(int s, const float (&vr)[8], const f
   int i, kq;
   bf_slot<KC, TM>(s, i, kq);
   bf16x8 h, l;
+  const int g = bf_grp(i, kq);
   bf_split8(vr, h, l);
-  *(bf16x8 *)&S[0][i][8 * kq] = h;
-  *(bf16x8 *)&S[1][i][8 * kq] = l;
+  *(bf16x8 *)&S[0][i][g] = h;
+  *(bf16x8 *)&S[1][i][g] = l;
   bf_split8(vi, h, l);
-  *(bf16x8 *)&S[2][i][8 * kq] = h;
-  *(bf16x8 *)&S[3][i][8 * kq] = l;
+  *(bf16x8 *)&S[2][i][g] = h;
+  *(bf16x8 *)&S[3][i][g] = l;
 }
 
 // acc[m][n][0/1] (re / im) += the (16 MT) x (16 NT) sub-tile of wave w at
@@ -346,7 +357,7 @@ __device__ __forceinline__ void ctile_bf3(const TOp<float> &A, const TOp<float> 
                                           f32x4 (&acc)[MT][NT][2]) {
   constexpr int TM = 32 * MT, TN = 32 * NT, UA = TM / 64, UB = TN / 64;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int i = lane & 15, g8 = 8 * (lane >> 4);
+  const int i = lane & 15, q = lane >> 4;
   const int wr = (w >> 1) * 16 * MT, wc = (w & 1) * 16 * NT;
   float ar[UA][8], ai[UA][8], br[UB][8], bi[UB][8];
   __amdgpu_buffer_rsrc_t rsa, rsb;
@@ -393,7 +404,8 @@ __device__ __forceinline__ void ctile_bf3(const TOp<float> &A, const TOp<float> 
 #pragma unroll
     for (int n = 0; n < NT; ++n)
 #pragma unroll
-      for (int p = 0; p < 4; ++p) fb[n][p] = *(const bf16x8 *)&L.b[p][wc + 16 * n + i][g8];
+      for (int p = 0; p < 4; ++p)
+        fb[n][p] = *(const bf16x8 *)&L.b[p][wc + 16 * n + i][bf_grp(wc + 16 * n + i, q)];
     // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br, each real product as
     // hi*hi + hi*lo + lo*hi; consecutive MFMAs go to different accumulators.
     // MT <= 2: every fragment of op(A) up front, term by term over all
@@ -420,14 +432,16 @@ __device__ __forceinline__ void ctile_bf3(const TOp<float> &A, const TOp<float> 
 #pragma unroll
       for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int p = 0; p < 4; ++p) fa[m][p] = *(const bf16x8 *)&L.a[p][wr + 16 * m + i][g8];
+        for (int p = 0; p < 4; ++p)
+          fa[m][p] = *(const bf16x8 *)&L.a[p][wr + 16 * m + i][bf_grp(wr + 16 * m + i, q)];
       QOC_BF3_TERMS(0, MT, fa[m])
     } else {
 #pragma unroll
       for (int mb = 0; mb < MT; ++mb) {
         bf16x8 fa[4];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) fa[p] = *(const bf16x8 *)&L.a[p][wr + 16 * mb + i][g8];
+        for (int p = 0; p < 4; ++p)
+          fa[p] = *(const bf16x8 *)&L.a[p][wr + 16 * mb + i][bf_grp(wr + 16 * mb + i, q)];
         QOC_BF3_TERMS(mb, mb + 1, fa)
       }
     }
