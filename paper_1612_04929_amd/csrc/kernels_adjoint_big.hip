@@ -6,7 +6,7 @@
 // product is LDS-staged; thousands of workgroups per launch hide latency.
 //
 // wg_tile computes a 64-row x TN-column strip of op(A) op(B) with the inner
-// dimension staged through LDS in chunks of 16 (k-major, padded rows); each
+// dimension staged through LDS in chunks of 16 (k-major, swizzled rows); each
 // of the 4 wavefronts owns 16 rows and TN/16 MFMA tiles.  op is identity or
 // conjugate transpose on either operand.  Rows beyond the matrix are
 // skipped, so any padded d (multiple of 16) works.
@@ -19,12 +19,24 @@
 namespace qoc {
 
 constexpr int BG_BK = 16;
-constexpr int BG_LDA = 64 + 4;  // LDS row stride of the A chunk (k-major)
-constexpr int BG_LDB = 64 + 4;  // LDS row stride of the B chunk (k-major)
+constexpr int BG_LDA = 64;  // LDS row stride of the A chunk (k-major); B's is TN
 
-template <typename T> struct BigLds {
+// LDS chunks without padding: the column c of inner row k is stored at
+// bg_col(k, c), an XOR of c with a multiple of 16 that depends on k.  With
+// 4-byte elements this keeps the fragment reads (16 consecutive columns of
+// four consecutive rows), the transposing stores of op(A) (four rows of 16
+// columns per wavefront) and the row stores of B (one, two or four rows per
+// wavefront) on distinct LDS banks; a padded stride of 68 elements had two-
+// to four-way conflicts on the fragment reads and the stores of B.
+template <int W> __device__ __forceinline__ int bg_col(int k, int c) {
+  if constexpr (W == 16) return c;
+  if constexpr (W == 32) return c ^ (16 * ((k >> 1) & 1));
+  return c ^ (16 * ((k + (k >> 2)) & 3));  // W a multiple of 64
+}
+
+template <typename T, int TN> struct BigLds {
   T ar[BG_BK * BG_LDA], ai[BG_BK * BG_LDA];
-  T br[BG_BK * BG_LDB], bi[BG_BK * BG_LDB];
+  T br[BG_BK * TN], bi[BG_BK * TN];
 };
 
 // acc[q] += op(A)[r0 + 16 w + (0..15)][:] op(B)[:][c0 + 16 q + (0..15)]
@@ -32,7 +44,7 @@ template <typename T> struct BigLds {
 // op(A) (padded d).  Must be called by all 256 threads.
 template <typename T, int OPA, int OPB, int TN>
 __device__ __forceinline__ void wg_tile(CView<const T> A, CView<const T> B, int r0, int c0,
-                                        int K, int rows, BigLds<T> &L,
+                                        int K, int rows, BigLds<T, TN> &L,
                                         v4<T> (&cr)[TN / 16], v4<T> (&ci)[TN / 16]) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int i = lane & 15, kk = lane >> 4;
@@ -91,15 +103,15 @@ __device__ __forceinline__ void wg_tile(CView<const T> A, CView<const T> B, int 
       const int r = t >> 2, kq = (t & 3) * 4;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        L.ar[(kq + q) * BG_LDA + r] = par[q];
-        L.ai[(kq + q) * BG_LDA + r] = pai[q];
+        L.ar[(kq + q) * BG_LDA + bg_col<64>(kq + q, r)] = par[q];
+        L.ai[(kq + q) * BG_LDA + bg_col<64>(kq + q, r)] = pai[q];
       }
     } else {
       const int k = t >> 4, rq = (t & 15) * 4;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        L.ar[k * BG_LDA + rq + q] = par[q];
-        L.ai[k * BG_LDA + rq + q] = pai[q];
+        L.ar[k * BG_LDA + bg_col<64>(k, rq + q)] = par[q];
+        L.ai[k * BG_LDA + bg_col<64>(k, rq + q)] = pai[q];
       }
     }
 #pragma unroll
@@ -113,8 +125,8 @@ __device__ __forceinline__ void wg_tile(CView<const T> A, CView<const T> B, int 
         c = e / BG_BK;
         k = e - c * BG_BK;
       }
-      L.br[k * BG_LDB + c] = pbr[q];
-      L.bi[k * BG_LDB + c] = pbi[q];
+      L.br[k * TN + bg_col<TN>(k, c)] = pbr[q];
+      L.bi[k * TN + bg_col<TN>(k, c)] = pbi[q];
     }
   };
   load(0);
@@ -125,12 +137,14 @@ __device__ __forceinline__ void wg_tile(CView<const T> A, CView<const T> B, int 
     if (wave_on) {
 #pragma unroll
       for (int k4 = 0; k4 < BG_BK; k4 += 4) {
-        const T a_r = L.ar[(k4 + kk) * BG_LDA + 16 * w + i];
-        const T a_i = L.ai[(k4 + kk) * BG_LDA + 16 * w + i];
+        const int ca = (k4 + kk) * BG_LDA + bg_col<64>(k4 + kk, 16 * w + i);
+        const T a_r = L.ar[ca];
+        const T a_i = L.ai[ca];
 #pragma unroll
         for (int q = 0; q < TN / 16; ++q) {
-          const T b_r = L.br[(k4 + kk) * BG_LDB + 16 * q + i];
-          const T b_i = L.bi[(k4 + kk) * BG_LDB + 16 * q + i];
+          const int cb = (k4 + kk) * TN + bg_col<TN>(k4 + kk, 16 * q + i);
+          const T b_r = L.br[cb];
+          const T b_i = L.bi[cb];
           cr[q] = mfma4(a_r, b_r, cr[q]);
           cr[q] = mfma4(-a_i, b_i, cr[q]);
           ci[q] = mfma4(a_r, b_i, ci[q]);
@@ -184,7 +198,7 @@ template <typename T> struct ThinBatch {
 // a step run on one XCD at about the same time and the second reads the
 // step's matrix from L2.
 template <typename T, int TN> __global__ __launch_bounds__(256) void k_thin_batch(ThinBatch<T> a, long padded) {
-  __shared__ BigLds<T> L;
+  __shared__ BigLds<T, TN> L;
   const int rp = (a.dp + 63) / 64, cp = a.W / TN;
   const long per_step = (long)rp * cp, per_j = per_step * a.nhalf;
   const long logical = xcd_logical_block(blockIdx.x, padded);
