@@ -378,7 +378,9 @@ __device__ __forceinline__ void ws_load(WSlices<T, DP> &S, const WLane &L, const
   __shared__ __align__(16) T xs[WSPLIT_MAX][2][2 * DP];              \
   __shared__ __align__(16) T xb[WSPLIT_MAX][2 * DP];                 \
   const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;           \
-  const int ws = blockIdx.y, b = blockIdx.x;                         \
+  const long lg_ = xcd_logical_block(blockIdx.x, gridDim.x);         \
+  if (lg_ >= (long)a.nb * a.S) return; /* padding of the 1-D grid */ \
+  const int ws = (int)(lg_ % a.S), b = (int)(lg_ / a.S);             \
   WLane L;                                                           \
   L.m = lane / KQ;                                                   \
   L.kq = lane - L.m * KQ;                                            \
@@ -554,6 +556,16 @@ template <typename T> bool wave_sweep_ok(int dp, int S) {
   return (dp == 16 && S * dp <= 64) || (dp == 32 && S * dp <= 64);
 }
 
+// Grid of the split in-block passes: one workgroup per (block, state) on a
+// 1-D launch padded to a multiple of 8 S, with the S states of a block at
+// consecutive logical indices of one XCD (xcd_logical_block), so that the
+// block's step matrices come from HBM once into that XCD's L2 and are read
+// there by all S state workgroups.
+template <typename T> unsigned ws_grid(const SweepArgs<T> &a) {
+  const long n = (long)a.nb * a.S, m = 8L * a.S;
+  return (unsigned)((n + m - 1) / m * m);
+}
+
 template <typename T, int DP> hipError_t w_launch(int which, const SweepArgs<T> &a, hipStream_t st) {
   const unsigned S = (unsigned)a.S;
   switch (which) {
@@ -561,7 +573,7 @@ template <typename T, int DP> hipError_t w_launch(int which, const SweepArgs<T> 
     case 1:
       if constexpr (DP == 16 && sizeof(T) == 4) {
         if (a.Es) {
-          hipLaunchKernelGGL((k_wF3s<T, DP>), dim3(a.nb, S), dim3(64 * (a.L / SUB16)), 0, st, a);
+          hipLaunchKernelGGL((k_wF3s<T, DP>), dim3(ws_grid(a)), dim3(64 * (a.L / SUB16)), 0, st, a);
           break;
         }
       }
@@ -576,7 +588,7 @@ template <typename T, int DP> hipError_t w_launch(int which, const SweepArgs<T> 
     default:
       if constexpr (DP == 16 && sizeof(T) == 4) {
         if (a.Es) {
-          hipLaunchKernelGGL((k_wB3s<T, DP>), dim3(a.nb, S), dim3(64 * (a.L / SUB16)), 0, st, a);
+          hipLaunchKernelGGL((k_wB3s<T, DP>), dim3(ws_grid(a)), dim3(64 * (a.L / SUB16)), 0, st, a);
           break;
         }
       }
