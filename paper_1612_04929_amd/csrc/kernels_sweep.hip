@@ -221,7 +221,10 @@ template <typename T> __global__ __launch_bounds__(256) void k_fwd_replay(SweepA
   extern __shared__ unsigned char shraw[];
   T *buf = (T *)shraw;
   const int dp = a.dp, S = a.S;
-  const int b = blockIdx.x / S, s = blockIdx.x - (blockIdx.x / S) * S;
+  // (block, state) from the XCD-grouped 1-D grid (xcd_grid in the launch)
+  const long lg_ = xcd_logical_block(blockIdx.x, gridDim.x);
+  if (lg_ >= (long)a.nb * S) return;  // padding of the grid
+  const int b = (int)(lg_ / S), s = (int)(lg_ - lg_ / S * S);
   const long set = 2L * S * dp, mat = 2L * dp * dp;
   const int start = b * a.L, end = min(a.N, start + a.L);
   T *xr = buf, *xi = buf + dp, *yr = buf + 2 * dp, *yi = buf + 3 * dp;
@@ -437,7 +440,10 @@ template <typename T> __global__ __launch_bounds__(256) void k_bwd_pairs(SweepAr
   extern __shared__ unsigned char shraw[];
   T *buf = (T *)shraw;
   const int dp = a.dp, S = a.S;
-  const int b = blockIdx.x / S, s = blockIdx.x - (blockIdx.x / S) * S;
+  // (block, state) from the XCD-grouped 1-D grid (xcd_grid in the launch)
+  const long lg_ = xcd_logical_block(blockIdx.x, gridDim.x);
+  if (lg_ >= (long)a.nb * S) return;  // padding of the grid
+  const int b = (int)(lg_ / S), s = (int)(lg_ - lg_ / S * S);
   const long set = 2L * S * dp, mat = 2L * dp * dp;
   const int start = b * a.L, end = min(a.N, start + a.L);
   T *xr = buf, *xi = buf + dp, *yr = buf + 2 * dp, *yi = buf + 3 * dp;
@@ -967,7 +973,7 @@ template <typename T> hipError_t launch_fwd_blocks(const SweepArgs<T> &a, hipStr
   return hipGetLastError();
 }
 template <typename T> hipError_t launch_fwd_replay(const SweepArgs<T> &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_fwd_replay<T>, dim3(a.nb * a.S), dim3(256), 6 * a.dp * sizeof(T) + 8192, st, a);
+  hipLaunchKernelGGL(k_fwd_replay<T>, dim3(xcd_grid((long)a.nb * a.S, a.S)), dim3(256), 6 * a.dp * sizeof(T) + 8192, st, a);
   return hipGetLastError();
 }
 
@@ -976,7 +982,7 @@ template <typename T> hipError_t launch_bwd_blocks(const SweepArgs<T> &a, hipStr
   return hipGetLastError();
 }
 template <typename T> hipError_t launch_bwd_pairs(const SweepArgs<T> &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_bwd_pairs<T>, dim3(a.nb * a.S), dim3(256), 6 * a.dp * sizeof(T) + 8192, st, a);
+  hipLaunchKernelGGL(k_bwd_pairs<T>, dim3(xcd_grid((long)a.nb * a.S, a.S)), dim3(256), 6 * a.dp * sizeof(T) + 8192, st, a);
   return hipGetLastError();
 }
 

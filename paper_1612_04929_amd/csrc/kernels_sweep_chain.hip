@@ -278,7 +278,10 @@ template <typename T, int DP> __global__ __launch_bounds__(8 * DP) void k_cF2(Sw
 // ------------------------------------------------------------------ F3
 template <typename T, int DP> __global__ __launch_bounds__(8 * DP) void k_cF3(SweepArgs<T> a) {
   C_SETUP
-  const int b = blockIdx.x / S, s = blockIdx.x - (blockIdx.x / S) * S;
+  // (block, state) from the XCD-grouped 1-D grid (xcd_grid in the launch)
+  const long lg_ = xcd_logical_block(blockIdx.x, gridDim.x);
+  if (lg_ >= (long)a.nb * S) return;  // padding of the grid
+  const int b = (int)(lg_ / S), s = (int)(lg_ - lg_ / S * S);
   const int start = b * a.L, end = min(a.N, start + a.L), cnt = end - start;
   if (t < DP) {
     const T *c = a.ckpt + (long)b * set;
@@ -359,7 +362,10 @@ template <typename T, int DP> __global__ __launch_bounds__(8 * DP) void k_cB2(Sw
 // ------------------------------------------------------------------ B3
 template <typename T, int DP> __global__ __launch_bounds__(8 * DP) void k_cB3(SweepArgs<T> a) {
   C_SETUP
-  const int b = blockIdx.x / S, s = blockIdx.x - (blockIdx.x / S) * S;
+  // (block, state) from the XCD-grouped 1-D grid (xcd_grid in the launch)
+  const long lg_ = xcd_logical_block(blockIdx.x, gridDim.x);
+  if (lg_ >= (long)a.nb * S) return;  // padding of the grid
+  const int b = (int)(lg_ / S), s = (int)(lg_ - lg_ / S * S);
   const int start = b * a.L, end = min(a.N, start + a.L);
   if (t < DP) {
     const T *c = a.lam_ckpt + (long)(b + 1) * set;
@@ -400,9 +406,9 @@ template <typename T, int DP> hipError_t c_launch(int which, const SweepArgs<T> 
   const dim3 blk(8 * DP);
   switch (which) {
     case 0: hipLaunchKernelGGL((k_cF2<T, DP>), dim3(a.S), blk, 0, st, a); break;
-    case 1: hipLaunchKernelGGL((k_cF3<T, DP>), dim3(a.nb * a.S), blk, 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_cF3<T, DP>), dim3(xcd_grid((long)a.nb * a.S, a.S)), blk, 0, st, a); break;
     case 2: hipLaunchKernelGGL((k_cB2<T, DP>), dim3(a.S), blk, 0, st, a); break;
-    default: hipLaunchKernelGGL((k_cB3<T, DP>), dim3(a.nb * a.S), blk, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_cB3<T, DP>), dim3(xcd_grid((long)a.nb * a.S, a.S)), blk, 0, st, a); break;
   }
   return hipGetLastError();
 }

@@ -562,8 +562,7 @@ template <typename T> bool wave_sweep_ok(int dp, int S) {
 // block's step matrices come from HBM once into that XCD's L2 and are read
 // there by all S state workgroups.
 template <typename T> unsigned ws_grid(const SweepArgs<T> &a) {
-  const long n = (long)a.nb * a.S, m = 8L * a.S;
-  return (unsigned)((n + m - 1) / m * m);
+  return xcd_grid((long)a.nb * a.S, a.S);
 }
 
 template <typename T, int DP> hipError_t w_launch(int which, const SweepArgs<T> &a, hipStream_t st) {

@@ -306,6 +306,15 @@ __device__ __forceinline__ long xcd_logical_block(long b, long padded) {
   return (b & 7) * per + (b >> 3);
 }
 
+// Launch size for n workgroups whose groups of `group` consecutive logical
+// indices (e.g. the states of one time block, which read the same step
+// matrices) must share an XCD under xcd_logical_block: n rounded up to a
+// multiple of 8 group, the extra workgroups returning at once.
+inline unsigned xcd_grid(long n, int group) {
+  const long m = 8L * group;
+  return (unsigned)((n + m - 1) / m * m);
+}
+
 
 // Wave-wide sum (64 lanes) with cross-lane shuffles.
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
