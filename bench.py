@@ -45,7 +45,8 @@ TRAFFIC = {
     ("c2_transmon_cnot", "adjoint"): ("k_adjoint16", 15221088, 64064),
     ("c2_transmon_cnot", "taylor"): ("k_expm16", 615810, 18857632),
     ("c2_transmon_cnot", "bwd_blocks"): ("k_wB2", 2872874, 160384),
-    ("c2_transmon_cnot", "fwd_replay"): ("k_wF3s", 36083954, 1184768),
+    ("c2_transmon_cnot", "fwd_replay"): ("k_wF3s", 9192707, 1184768),
+    ("c2_transmon_cnot", "bwd_pairs"): ("k_wB3s", 5295042, 1024000),
     ("c4_spin_chain", "taylor"): ("k_stage_t", 7380331861, 2516582400),
     ("c3_transmon_cavity", "taylor"): ("k_stage64", 1933738424, 737280000),
 }
