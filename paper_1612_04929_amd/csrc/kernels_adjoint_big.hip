@@ -476,11 +476,14 @@ template <typename T> __global__ __launch_bounds__(256) void k_gcontract(GContra
 // index and keeps per-control sums of its own (in the chain precision, in
 // LDS: a lane adds a few dozen terms), summed over lanes and wavefronts in
 // FP64 in a fixed order at the end.  Workgroup (g, j) takes
-// the rows r = g, g + SG_GROUPS, ... of step j, one row per wavefront at a
-// time: the row's panel entries are loaded once (consecutive lanes read
-// consecutive entries) and serve every union entry of the row; the entries
-// of a row go in batches of SG_BATCH with all their loads in flight.
-constexpr int SG_GROUPS = 4, SG_AREG = 8, SG_BATCH = 4;
+// the rows r = g, g + G, ... of step j (G workgroups per step), one row per
+// wavefront at a time: the row's panel entries are loaded once (consecutive
+// lanes read consecutive entries) and serve every union entry of the row;
+// the entries of a row go in batches of SG_BATCH with all their loads in
+// flight.  The G workgroups of a step run on one XCD, and G up to
+// SG_GROUPS_MAX keeps few steps in flight per XCD, so that the panels of the
+// steps in flight stay in its L2 while their rows are read once per entry.
+constexpr int SG_GROUPS_MAX = 64, SG_AREG = 8, SG_BATCH = 4;
 // per-lane sums of one control: 4 wavefronts x 64 lanes of T
 template <typename T> constexpr int sg_lds_per_control() { return 4 * 64 * (int)sizeof(T); }
 template <typename T> struct SContract {
@@ -493,6 +496,7 @@ template <typename T> struct SContract {
   long nev;
   double *part;
   int N, M, d;
+  int groups;  // workgroups per step (at most the partial-sum slices per step)
 };
 
 template <typename T, int AREG>
@@ -500,12 +504,13 @@ __global__ __launch_bounds__(256) void k_sgcontract(SContract<T> a, long padded)
   extern __shared__ __align__(16) char gsh_raw[];
   T *gsh = (T *)gsh_raw;  // [4 waves][M][64 lanes]
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // the SG_GROUPS workgroups of one step on one XCD, so that they share the
-  // step's panel in its L2 (read from HBM about once)
+  // the G workgroups of one step on one XCD, so that they share the step's
+  // panel in its L2 (read from HBM about once)
+  const int G = a.groups;
   const long logical = xcd_logical_block(blockIdx.x, padded);
-  if (logical >= (long)a.N * SG_GROUPS) return;  // block-uniform
-  const int g = (int)(logical % SG_GROUPS);
-  const long j = logical / SG_GROUPS;
+  if (logical >= (long)a.N * G) return;  // block-uniform
+  const int g = (int)(logical % G);
+  const long j = logical / G;
   T *acc = gsh + (long)w * a.M * 64 + lane;
   for (int k = 0; k < a.M; ++k) acc[k * 64] = (T)0;
   const T *Pr = a.panel + j * a.per, *Pi = Pr + a.big;
@@ -521,7 +526,7 @@ __global__ __launch_bounds__(256) void k_sgcontract(SContract<T> a, long padded)
     ca[q] = (long)(2 * kb + 1) * a.rr + ii;
     cb[q] = (long)(2 * (a.p - 1 - kb)) * a.rr + ii;
   }
-  for (int r = g + SG_GROUPS * w; r < a.d; r += 4 * SG_GROUPS) {
+  for (int r = g + G * w; r < a.d; r += 4 * G) {
     const int e0 = a.rptr[r], e1 = a.rptr[r + 1];
     if (e0 == e1) continue;  // wavefront-uniform
     const long ro = (long)r * a.ld;
@@ -564,7 +569,7 @@ __global__ __launch_bounds__(256) void k_sgcontract(SContract<T> a, long padded)
     double s = 0.0;
     for (int ww = 0; ww < 4; ++ww)
       for (int l = 0; l < 64; ++l) s += (double)gsh[((long)ww * a.M + k) * 64 + l];
-    a.part[(j * SG_GROUPS + g) * a.M + k] = s;
+    a.part[(j * G + g) * a.M + k] = s;
   }
 }
 
@@ -854,10 +859,12 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
   }
   // ---- structured control Hamiltonians: Xbar only at their nonzeros
   if (a.rptr && (long)M * sg_lds_per_control<T>() <= 64 * 1024 && (long)p * rr <= 64 * SG_AREG) {
+    // workgroups per step: at most the partial-sum slices the handle holds
+    const int sg_groups = (int)std::min<long>(SG_GROUPS_MAX, adjoint_big_slices(dp));
     if (M > 0) {
       SContract<T> sc2{sc + 8 * thin, per, big, (int)KK2, rr, p, a.rptr, a.rcol, a.eptr, a.ek,
-                       a.eval, a.nev, a.part, N, M, a.d};
-      const long total = (long)SG_GROUPS * N, padded = (total + 7) / 8 * 8;
+                       a.eval, a.nev, a.part, N, M, a.d, sg_groups};
+      const long total = (long)sg_groups * N, padded = (total + 7) / 8 * 8;
       // registers for the lane's share of the inner length p rr (<= 64 AREG)
       const long K = (long)p * rr;
       const size_t shm = (size_t)M * sg_lds_per_control<T>();
@@ -873,7 +880,7 @@ template <typename T> hipError_t launch_adjoint_big(const AdjointArgs<T> &a, hip
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     AdjFinish<T> f{a.part, a.u, a.grad, 2.0 * a.s_scale, a.alpha_amp, a.alpha_var, nullptr, N, M,
-                   SG_GROUPS, a.j0, a.ldN > 0 ? a.ldN : N};
+                   sg_groups, a.j0, a.ldN > 0 ? a.ldN : N};
     hipLaunchKernelGGL(k_adj_finish<T>, dim3(grid_for((long)N * M)), dim3(256), 0, st, f);
     return hipGetLastError();
   }
