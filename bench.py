@@ -47,7 +47,7 @@ TRAFFIC = {
     ("c2_transmon_cnot", "bwd_blocks"): ("k_wB2", 2872874, 160384),
     ("c2_transmon_cnot", "fwd_replay"): ("k_wF3s", 9192707, 1184768),
     ("c2_transmon_cnot", "bwd_pairs"): ("k_wB3s", 5295042, 1024000),
-    ("c4_spin_chain", "taylor"): ("k_stage_t", 7380331861, 2516582400),
+    ("c4_spin_chain", "taylor"): ("k_stage_t", 7382338232, 2516582400),
     ("c3_transmon_cavity", "taylor"): ("k_stage64", 1933738424, 737280000),
 }
 
