@@ -398,8 +398,8 @@ qoc_status qoc_set_gradient(qoc_handle *h, int mode);
  * 2 s Im tr(Xbar_j^H H_k) forms Xbar_j at the nonzeros of the controls
  * alone instead of storing the dense d x d Xbar_j.  The Taylor,
  * squaring and block products stay dense (the step propagators are dense).
- * mode -1 (default): structured when the union has at most d^2 / 16
- * entries; 0: dense; 1: structured (QOC_ERR_UNSUPPORTED when no pattern was
+ * mode -1 (default): structured whenever the pattern was recorded (a
+ * union of at most d^2 / 4 entries); 0: dense; 1: structured (QOC_ERR_UNSUPPORTED when no pattern was
  * recorded).  Results agree with the dense kernels up to summation order. */
 qoc_status qoc_set_structure(qoc_handle *h, int mode);
 

@@ -62,20 +62,20 @@ def test_random_sparse_structured(d, S, N, per_row, prec):
         check(p, e, precision=prec)
 
 
-def test_forced_structure_on_a_denser_pattern():
-    # union of d^2 / 8 .. d^2 / 4 entries: recorded, dense by default, forced
+def test_default_structure_on_a_denser_pattern():
+    # union of d^2 / 8 .. d^2 / 4 entries: recorded and used by default;
+    # dense on request
     rng = np.random.default_rng(950)
     p = sparse_problem(rng, 64, 2, 30, 2, per_row=6)
     h = qoc.Problem(p)
-    dense = h.cost_grad(p.u)
-    try:
-        h.set_structure(1)
-    except qoc.QocError:
-        pytest.skip("pattern denser than d^2 / 4 for this seed")
     st = h.cost_grad(p.u)
-    say(f"[struct] forced: dense={dense['structured']} structured={st['structured']} "
+    if not st["structured"]:
+        pytest.skip("pattern denser than d^2 / 4 for this seed")
+    h.set_structure(0)
+    dense = h.cost_grad(p.u)
+    say(f"[struct] default: structured={st['structured']} dense={dense['structured']} "
         f"grad rel {rel(st['grad'], dense['grad']):.2e}")
-    assert st["structured"] == 1
+    assert dense["structured"] == 0
     assert rel(st["grad"], dense["grad"]) <= 1e-5
     h.close()
     q = workloads.random_problem(np.random.default_rng(951), d=64, M=2, N=10, S=2)
